@@ -1,0 +1,159 @@
+#!/usr/bin/env python
+"""Benchmark of the rounded-polytope DEM step on one MI355X.
+
+Workload: 4096 rounded cubes (edge 1, rounding radius 0.15, so sigma 0.3) at
+volume fraction 0.4 in a periodic cube, 16^3 simple-cubic start with
+rotations up to 10 degrees, Nose-Hoover NVT at kT = 1, dt = 5e-4; FP32 pair
+geometry with FP64 positions, integration and reductions.  One step is the
+whole path: thermostat, kick-drift, displacement-triggered cell and
+neighbour lists, pair forces (Eq. 1 with WCA), closing kick.
+
+Prints one JSON line: particle-timesteps/s of the FP32 path (the value), the
+plain FP64 single-system path on the same inputs, the force kernel's ALU
+roofline (work counters x per-problem flop weights / mean launch time from
+HIP events on the launch stream) and the CPU oracle timed on this host.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "particle-timesteps/s (3D cubes) FP32-batched vs plain; p50/p99 replica latency"
+
+# FP32 flop weights of the force kernel's formulas (add/mul/sub 1, FMA 2,
+# divide or reciprocal 1), per unit of work the counters report.
+FLOPS = {
+    "pair": 110,       # FP64 relative rotation and offset, bound test (once per particle pair)
+    "vf": 24,          # vertex into the face owner's frame + plane distance (every vertex-face problem)
+    "vf_near": 80,     # inside test, projection or boundary edges, back-transform (plane distance < r_cut)
+    "ee": 110,         # edge into i's frame + segment-segment closest points + distance
+    "wca": 50,         # WCA energy/force and accumulation of F, tau, U, W (inside the cutoff)
+}
+PEAK_FP32 = 157.3e12   # MI355X FP32 vector, published
+PEAK_HBM = 8.0e12
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def run_path(system, precision, steps, warmup, counting=False):
+    import torch
+    from paper_1607_02427_amd import dem
+    g = dem.DemSystem(system, precision)
+    stream = g.stream
+    if counting:
+        g.set_counting(True)
+    g.step(warmup)
+    g.sync()
+    if counting:
+        g.force_stats(reset=True)
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    e0.record(stream)
+    g.step(steps)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    gpu_ms = e0.elapsed_time(e1)
+    en = g.energy()
+    return g, dict(wall_s=wall, gpu_ms=gpu_ms, energy=en)
+
+
+def force_roofline(g, system, reps=200):
+    """Work counters of one force launch on the current state, and the mean
+    launch duration of the force kernel alone (HIP events on its stream)."""
+    g.force_stats(reset=True)
+    g.compute_forces()
+    st = g.force_stats(reset=True)
+    mean_ms = g.time_forces(reps)
+    shp = system.shapes[0]
+    per_pair_vf = 2 * shp.nv * shp.nf
+    per_pair_ee = shp.ne * shp.ne
+    n_vf = st["pairs"] * per_pair_vf
+    n_ee = st["pairs"] * per_pair_ee
+    assert n_vf + n_ee == st["features"], (st, per_pair_vf, per_pair_ee)
+    flops = (st["pairs"] * FLOPS["pair"] + n_vf * FLOPS["vf"] + st["vf_near"] * FLOPS["vf_near"]
+             + n_ee * FLOPS["ee"] + st["in_cutoff"] * FLOPS["wca"])
+    achieved = flops / (mean_ms * 1e-3)
+    return dict(bound="alu", achieved=achieved / 1e12, peak=PEAK_FP32 / 1e12, unit="TFLOP/s",
+                frac=achieved / PEAK_FP32, traffic=None, kernel="k_forces<float,3>",
+                mean_launch_ms=mean_ms, flops_per_launch=flops, counters=st)
+
+
+def cpu_baseline(system, target_s):
+    import oracle as O
+    threads = len(os.sched_getaffinity(0))
+    O.set_threads(threads)
+    s = system.copy()
+    t0 = time.perf_counter()
+    O.run(s, 1, log=False)
+    one = time.perf_counter() - t0
+    steps = max(1, min(500, int(target_s / max(one, 1e-6))))
+    t0 = time.perf_counter()
+    O.run(s, steps, log=False)
+    dt = time.perf_counter() - t0
+    return dict(value=system.n * steps / dt, unit="particle-timesteps/s", cores=O.get_threads(), kind="oracle",
+                sample=f"{steps} NVT steps of the same 4096-cube workload from its seeded start "
+                       f"(FP64 brute force over every feature pair, own cell list), {dt:.1f} s")
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=4000)
+    ap.add_argument("--warmup", type=int, default=400)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-plain", action="store_true", help="skip the plain FP64 path")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU layout is design-only.",
+              file=sys.stderr)
+        sys.exit(2)
+    import torch
+    from paper_1607_02427_amd import inputs as I
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    system = I.cubes_3d()
+    n = system.n
+    log(f"[bench] fp32 path: {n} cubes, warmup {args.warmup}, steps {args.steps}")
+    g, r32 = run_path(system, "fp32", args.steps, args.warmup)
+    ptps = n * args.steps / (r32["gpu_ms"] * 1e-3)
+    log(f"[bench] fp32 {r32['gpu_ms'] / args.steps * 1e3:.2f} us/step, {ptps:.3e} PTPS, rebuilds "
+        f"{r32['energy']['n_rebuilds']}")
+    roof = force_roofline(g, system)
+    log(f"[bench] force kernel {roof['mean_launch_ms'] * 1e3:.2f} us, {roof['achieved']:.2f} TFLOP/s")
+    line = {
+        "metric": METRIC, "value": ptps, "unit": "particle-timesteps/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": r32["gpu_ms"] / args.steps, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "4096 rounded cubes, edge 1, r 0.15, volume fraction 0.4, NVT kT 1, dt 5e-4, "
+                               "FP32 pair geometry / FP64 integration, single system",
+                   "n": n, "box": float(system.box[0]), "dt": system.dt, "ensemble": "nvt",
+                   "precision": "fp32 geometry, fp64 state"},
+        "wall_s": r32["wall_s"],
+        "rebuilds": r32["energy"]["n_rebuilds"],
+        "roofline": roof,
+    }
+    g.close()
+    if not args.no_plain:
+        log("[bench] plain fp64 path")
+        g64, r64 = run_path(system, "fp64", args.steps, args.warmup)
+        line["plain_fp64"] = {"value": n * args.steps / (r64["gpu_ms"] * 1e-3), "ms_per_step": r64["gpu_ms"] / args.steps}
+        line["fp32_over_plain"] = ptps / line["plain_fp64"]["value"]
+        g64.close()
+    if not args.no_cpu:
+        log("[bench] cpu oracle baseline")
+        line["cpu_baseline"] = cpu_baseline(system, args.cpu_seconds)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

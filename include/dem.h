@@ -1,0 +1,207 @@
+/*
+ * dem.h -- C ABI of libdem, an MI355X (gfx950) implementation of the
+ * rounded-polytope Discrete Element Method for molecular dynamics of
+ * Spellings, Marson, Anderson & Glotzer (arXiv:1607.02427).
+ *
+ * One handle is one periodic system of N rigid rounded polygons (2D) or
+ * polyhedra (3D).  Per time step the library computes, on the GPU:
+ *   - a cell list and a full neighbour list, rebuilt when a particle has
+ *     moved more than rebuild_frac * skin since the last build;
+ *   - pair forces, torques, energies and virials by Eq. 1 (3D: every
+ *     edge-edge and vertex-face feature pair, Sec. II) or Eq. 2 (2D: every
+ *     vertex-edge pair), each evaluated at the features' nearest points under
+ *     the WCA potential of Eq. 3-4 with sigma_ij = r_i + r_j;
+ *   - a second-order rigid-body integrator (Sec. IV.A) with an optional
+ *     Nose-Hoover thermostat on translation and rotation (Sec. IV.C).
+ *
+ * Conventions
+ *   - Units are reduced (m, epsilon, tau; Sec. IV.A).
+ *   - All device pointers are HIP device addresses on the current device.
+ *   - Every call is asynchronous on the stream given at creation, except
+ *     dem_energy, dem_sync, dem_copy_lists and dem_force_stats, which
+ *     synchronise that stream.
+ *   - Errors: every call returns a dem_status.  Device-side conditions
+ *     (neighbour-row overflow, non-finite state) are latched on the device
+ *     and reported by the next synchronising call; dem_last_error gives text.
+ *   - Ownership: state and output arrays belong to the caller, which keeps
+ *     them alive and unmoved for the handle's lifetime.  Shape and parameter
+ *     structs are copied at creation.  Lists, cells and reduction scratch
+ *     belong to the library and are freed by dem_destroy_system.
+ */
+#ifndef DEM_H
+#define DEM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct dem_system *dem_handle;
+
+typedef enum {
+    DEM_OK = 0,
+    DEM_E_ARG = 1,       /* invalid argument or inconsistent parameters */
+    DEM_E_SHAPE = 2,     /* shape tables fail validation or exceed limits */
+    DEM_E_OOM = 3,       /* device allocation failed */
+    DEM_E_HIP = 4,       /* a HIP runtime call failed */
+    DEM_E_CAPACITY = 5,  /* a neighbour row overflowed nbr_capacity */
+    DEM_E_NONFINITE = 6, /* a position or velocity became non-finite */
+    DEM_E_STATE = 7      /* handle in an unusable state */
+} dem_status;
+
+enum { DEM_FP64 = 0, DEM_FP32 = 1 };  /* pair-geometry precision */
+enum { DEM_NVE = 0, DEM_NVT = 1 };
+
+/* Limits of one shape (vertices, edges, faces, face-loop entries) and of the
+ * number of shapes per system. */
+enum { DEM_MAX_VERTS = 16, DEM_MAX_EDGES = 32, DEM_MAX_FACES = 20, DEM_MAX_LOOP = 64, DEM_MAX_SHAPES = 4 };
+
+/* One rigid shape (Sec. II, Fig. 1): body-frame feature tables.  The body
+ * frame is the principal frame with its origin at the centre of mass.
+ * 2D: vertices counter-clockwise with z = 0; edge k = (k, k+1 mod n) (Sec.
+ * III: the edge beginning at a vertex, travelling counter-clockwise).
+ * 3D: faces are planar vertex loops, counter-clockwise seen from outside,
+ * convex or concave (Fig. 1a); every edge must appear in the edge table. */
+typedef struct {
+    int32_t dim;                  /* 2 or 3, equal to the system's */
+    int32_t n_vertices;
+    const double *vertices;       /* [n_vertices][3] */
+    int32_t n_edges;
+    const int32_t *edges;         /* [n_edges][2] vertex indices */
+    int32_t n_faces;              /* 0 in 2D */
+    const int32_t *face_offsets;  /* [n_faces+1] into face_vertices */
+    const int32_t *face_vertices; /* loop vertex indices */
+    double rounding_radius;       /* r: surface at r from the features; sigma_ij = r_i + r_j */
+    double mass;
+    double inertia[3];            /* principal moments; 2D uses inertia[2] */
+} dem_shape_desc;
+
+typedef struct {
+    int32_t dim;                  /* 2 or 3 */
+    int64_t n;                    /* particles, >= 0 */
+    double box[3];                /* periodic orthorhombic box; 2D ignores box[2] */
+    int32_t n_shapes;             /* 1..DEM_MAX_SHAPES */
+    const dem_shape_desc *shapes;
+    double epsilon;               /* WCA energy scale (Eq. 3) */
+    double skin;                  /* neighbour-list skin */
+    double rebuild_frac;          /* rebuild when max displacement > rebuild_frac * skin */
+    double dt;
+    int32_t ensemble;             /* DEM_NVE or DEM_NVT */
+    double kT;                    /* thermostat temperature (NVT) */
+    double tau_T;                 /* thermostat time constant: Q = g kT tau_T^2 */
+    int32_t precision;            /* DEM_FP64 or DEM_FP32 */
+    double parallel_sin2;         /* edges with |u x v|^2 < parallel_sin2 |u|^2 |v|^2
+                                     use the overlap-midpoint rule (Sec. II) */
+    int32_t nbr_capacity;         /* neighbour-row capacity; 0 = automatic */
+} dem_params;
+
+/* Caller-owned device arrays, FP64 structure-of-arrays, length n, borrowed
+ * for the handle's lifetime.  q is the unit quaternion (w, x, y, z) mapping
+ * body to space; L is the angular momentum in the body frame; image holds
+ * periodic image counters [n][3].  Positions must lie in [0, box). */
+typedef struct {
+    double *x, *y, *z;
+    double *qw, *qx, *qy, *qz;
+    double *vx, *vy, *vz;
+    double *Lx, *Ly, *Lz;
+    int32_t *shape_id;
+    int32_t *image;
+} dem_state_ptrs;
+
+/* Caller-owned device outputs, FP64, written by dem_compute_forces and every
+ * step: force, torque about the centre (space frame; 2D uses Tz), per-particle
+ * energy U_i = 1/2 sum_j U_ij and virial W_i = 1/2 sum_j (x_i - x_j) (x) F_ij
+ * stored component-major: W[(3a + b) * n + i]. */
+typedef struct {
+    double *Fx, *Fy, *Fz;
+    double *Tx, *Ty, *Tz;
+    double *U;
+    double *W;                    /* [9][n] */
+} dem_output_ptrs;
+
+typedef struct {
+    double U, K_trans, K_rot;
+    double H;                     /* K + U (NVE) or K + U + Q xi^2/2 + g kT eta (NVT) */
+    double T;                     /* 2K / g */
+    double P;                     /* (2 K_trans + tr W) / (d V) */
+    double W[9];                  /* sum_i W_i */
+    double xi, eta;               /* thermostat variables */
+    int64_t step;
+    int64_t n_rebuilds;
+} dem_energy_out;
+
+/* Creates a system on the current device and stream, validates and uploads
+ * the shape tables, allocates lists, builds them and computes the forces of
+ * the initial state.  On error *out is NULL. */
+dem_status dem_create_system(const dem_params *params, const dem_state_ptrs *state, const dem_output_ptrs *outputs,
+                             void *hip_stream, dem_handle *out);
+
+/* Frees library-owned device memory and the handle (synchronises). */
+dem_status dem_destroy_system(dem_handle h);
+
+/* Rebuilds the cell list and the neighbour list from the current positions
+ * (cell size L / floor(L / r_list), r_list = 2 R_max + 2^(1/6) sigma_max +
+ * skin).  Synchronises; grows the row capacity and rebuilds if a row
+ * overflowed and the capacity is automatic. */
+dem_status dem_build_celllist(dem_handle h);
+
+/* Computes F, tau, U_i and W_i for the current positions and orientations
+ * over the current neighbour list (Eq. 1 / Eq. 2 with Eq. 4). */
+dem_status dem_compute_forces(dem_handle h);
+
+/* Advances n_steps time steps (lists rebuilt on the displacement trigger). */
+dem_status dem_step(dem_handle h, int64_t n_steps);
+
+/* Reduces energies, kinetic terms, virial and thermostat state in FP64 and
+ * reports latched device errors.  Synchronises. */
+dem_status dem_energy(dem_handle h, dem_energy_out *out);
+
+/* Synchronises and reports latched device errors. */
+dem_status dem_sync(dem_handle h);
+
+/* Sets the Nose-Hoover variables (for checkpoint/restore). */
+dem_status dem_set_thermostat(dem_handle h, double xi, double eta);
+
+/* Copies the lists to host buffers (synchronises): cell_start[n_cells+1],
+ * cell_particles[n], nbr[capacity * n] column-major (row i of particle i is
+ * nbr[k * n + i], k < n_nbr[i], ascending in j) and n_nbr[n].  Any pointer
+ * may be NULL.  dims receives {cells_x, cells_y, cells_z, capacity}. */
+dem_status dem_copy_lists(dem_handle h, int32_t *cell_start, int32_t *cell_particles, int32_t *nbr, int32_t *n_nbr,
+                          int32_t *dims);
+
+/* Neighbour-list radius and number of cells. */
+dem_status dem_list_info(dem_handle h, double *r_list, int32_t *n_cells, int32_t *capacity);
+
+/* Work counters accumulated by counted force evaluations since the last
+ * reset: out[0] particle pairs within R_i + R_j + r_cut, out[1] feature
+ * pairs evaluated, out[2] feature pairs inside the cutoff, out[3] counted
+ * launches, out[4] vertex-face (3D) problems whose plane distance is below
+ * the cutoff (the rest are settled by the plane test alone).  reset != 0
+ * clears them after reading.  Synchronises. */
+dem_status dem_force_stats(dem_handle h, int64_t *out, int32_t reset);
+
+/* Enables (on != 0) or disables the work counters inside dem_step's
+ * captured step (dem_compute_forces always counts).  Counting adds a few
+ * atomics per wave; the arithmetic and results are unchanged. */
+dem_status dem_set_counting(dem_handle h, int32_t on);
+
+/* Launches the force kernel alone `reps` times on the current state (no
+ * list work, no counters), bracketed by HIP events recorded on the system's
+ * stream, and returns the mean duration of one launch in milliseconds.
+ * Outputs are overwritten with the same values.  Synchronises. */
+dem_status dem_time_forces(dem_handle h, int32_t reps, double *mean_ms);
+
+/* Bytes of device memory the library would allocate for these parameters
+ * (lists, cells, scratch), excluding caller-owned state and outputs. */
+size_t dem_footprint_bytes(const dem_params *params);
+
+const char *dem_status_string(dem_status s);
+const char *dem_last_error(dem_handle h);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* DEM_H */

@@ -1,0 +1,372 @@
+// Rigid-body integrator and reductions, FP64.
+//
+// Sec. IV.A: a second-order integrator; Sec. IV.C: a Nose-Hoover thermostat
+// on translational and rotational degrees of freedom.  One step is
+//   [NVT half step] kick (v, L by dt/2) - drift x by dt - free rotation -
+//   forces - kick (dt/2) - [NVT half step],
+// where the free rotation is the symmetric split about the body principal
+// axes z(dt/2) y(dt/2) x(dt) y(dt/2) z(dt/2) (one rotation about z in 2D):
+// a turn about body axis k by phi = h L_k / I_k right-multiplies q by the
+// axis-angle quaternion and turns the body-frame L by -phi about that axis.
+// The Nose-Hoover half step of length h on the single variable xi is
+//   xi += h/2 (2K - g kT)/Q;  (v, L) *= exp(-xi h);  eta += xi h;
+//   xi += h/2 (2K - g kT)/Q,
+// with g = d N + d_rot N - d and Q = g kT tau_T^2.  The half step that ends
+// a step is applied lazily by the next step's first kernel (and by an
+// explicit finishing kernel after the last step of a call), so a captured
+// step needs no extra pass over the particles.
+#include "dem_internal.h"
+
+namespace dem {
+namespace {
+
+__device__ inline void quat_mul(double &w, double &x, double &y, double &z, double bw, double bx, double by,
+                                double bz)
+{
+    double nw = w * bw - x * bx - y * by - z * bz;
+    double nx = w * bx + x * bw + y * bz - z * by;
+    double ny = w * by - x * bz + y * bw + z * bx;
+    double nz = w * bz + x * by - y * bx + z * bw;
+    w = nw;
+    x = nx;
+    y = ny;
+    z = nz;
+}
+
+// Free rotation about body axis k for time h.
+__device__ inline void turn(double q[4], double L[3], const double I[3], int k, double h)
+{
+    if (I[k] <= 0.0) return;
+    const double phi = h * L[k] / I[k];
+    double sn, cs;
+    sincos(0.5 * phi, &sn, &cs);
+    double b[3] = {0.0, 0.0, 0.0};
+    b[k] = sn;
+    quat_mul(q[0], q[1], q[2], q[3], cs, b[0], b[1], b[2]);
+    double s1, c1;
+    sincos(phi, &s1, &c1);
+    const int a = (k + 1) % 3, c = (k + 2) % 3;
+    const double La = L[a], Lc = L[c];
+    L[a] = c1 * La + s1 * Lc;
+    L[c] = -s1 * La + c1 * Lc;
+}
+
+// Body-frame torque R(q)^T tau.
+__device__ inline void body_torque(const double q[4], double tx, double ty, double tz, double out[3])
+{
+    const double w = q[0], x = q[1], y = q[2], z = q[3];
+    const double r00 = 1 - 2 * (y * y + z * z), r01 = 2 * (x * y - w * z), r02 = 2 * (x * z + w * y);
+    const double r10 = 2 * (x * y + w * z), r11 = 1 - 2 * (x * x + z * z), r12 = 2 * (y * z - w * x);
+    const double r20 = 2 * (x * z - w * y), r21 = 2 * (y * z + w * x), r22 = 1 - 2 * (x * x + y * y);
+    out[0] = r00 * tx + r10 * ty + r20 * tz;
+    out[1] = r01 * tx + r11 * ty + r21 * tz;
+    out[2] = r02 * tx + r12 * ty + r22 * tz;
+}
+
+__device__ inline double min_image(double d, double L) { return d - L * rint(d / L); }
+
+template <int NT>
+__device__ inline double block_sum(double v, double *sh)
+{
+    const int t = threadIdx.x;
+    sh[t] = v;
+    __syncthreads();
+    for (int off = NT / 2; off > 0; off >>= 1) {
+        if (t < off) sh[t] += sh[t + off];
+        __syncthreads();
+    }
+    double r = sh[0];
+    __syncthreads();
+    return r;
+}
+
+// Nose-Hoover half step on xi, eta; returns the velocity scale, updates K.
+__device__ inline double nh_half(const SysParams &p, double &xi, double &eta, double &K)
+{
+    const double h = 0.5 * p.dt;
+    xi += 0.5 * h * (2.0 * K - p.g * p.kT) / p.Qm;
+    const double sc = exp(-xi * h);
+    K *= sc * sc;
+    eta += xi * h;
+    xi += 0.5 * h * (2.0 * K - p.g * p.kT) / p.Qm;
+    return sc;
+}
+
+__device__ inline double sum_partials(const double *part, int nblk, double *sh)
+{
+    double acc = 0.0;
+    for (int b = threadIdx.x; b < nblk; b += blockDim.x) acc += part[2 * b] + part[2 * b + 1];
+    return block_sum<kBlock>(acc, sh);
+}
+
+// Start of a step: the pending end-of-step half step (if any), then this
+// step's opening half step.  One block.
+__global__ void __launch_bounds__(kBlock) k_nh_begin(SysParams p, const double *ke_part, int nblk, double *th)
+{
+    __shared__ double sh[kBlock];
+    double K = sum_partials(ke_part, nblk, sh);
+    if (threadIdx.x != 0) return;
+    double xi = th[TH_XI], eta = th[TH_ETA], sc = 1.0;
+    if (th[TH_PENDING] != 0.0) sc *= nh_half(p, xi, eta, K);
+    sc *= nh_half(p, xi, eta, K);
+    th[TH_XI] = xi;
+    th[TH_ETA] = eta;
+    th[TH_SCALE] = sc;
+    th[TH_PENDING] = 0.0;
+}
+
+// After the last step of a call: apply the pending closing half step.
+__global__ void __launch_bounds__(kBlock) k_nh_end(SysParams p, const double *ke_part, int nblk, double *th)
+{
+    __shared__ double sh[kBlock];
+    double K = sum_partials(ke_part, nblk, sh);
+    if (threadIdx.x != 0) return;
+    double xi = th[TH_XI], eta = th[TH_ETA], sc = 1.0;
+    if (th[TH_PENDING] != 0.0) sc = nh_half(p, xi, eta, K);
+    th[TH_XI] = xi;
+    th[TH_ETA] = eta;
+    th[TH_SCALE] = sc;
+    th[TH_PENDING] = 0.0;
+}
+
+__global__ void k_scale(SysParams p, StatePtrs s, const double *th)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= p.n) return;
+    const double sc = th[TH_SCALE];
+    s.vx[i] *= sc;
+    s.vy[i] *= sc;
+    s.vz[i] *= sc;
+    s.Lx[i] *= sc;
+    s.Ly[i] *= sc;
+    s.Lz[i] *= sc;
+}
+
+template <int DIM, bool NVT>
+__global__ void __launch_bounds__(kBlock) k_kick_drift(SysParams p, StatePtrs s, OutPtrs o, ListPtrs l,
+                                                          const double *th)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= p.n) return;
+    const double sc = NVT ? th[TH_SCALE] : 1.0;
+    const int sid = s.sid[i];
+    const double hm = 0.5 * p.dt / p.mass[sid];
+    const double I[3] = {p.inertia[sid][0], p.inertia[sid][1], p.inertia[sid][2]};
+    double q[4] = {s.qw[i], s.qx[i], s.qy[i], s.qz[i]};
+    double v[3] = {sc * s.vx[i] + hm * o.Fx[i], sc * s.vy[i] + hm * o.Fy[i], 0.0};
+    double L[3];
+    if (DIM == 3) {
+        v[2] = sc * s.vz[i] + hm * o.Fz[i];
+        double tb[3];
+        body_torque(q, o.Tx[i], o.Ty[i], o.Tz[i], tb);
+        L[0] = sc * s.Lx[i] + 0.5 * p.dt * tb[0];
+        L[1] = sc * s.Ly[i] + 0.5 * p.dt * tb[1];
+        L[2] = sc * s.Lz[i] + 0.5 * p.dt * tb[2];
+    } else {
+        L[0] = 0.0;
+        L[1] = 0.0;
+        L[2] = sc * s.Lz[i] + 0.5 * p.dt * o.Tz[i];
+    }
+    double x[3] = {s.x[i], s.y[i], (DIM == 3) ? s.z[i] : 0.0};
+    int img[3] = {s.image[3 * i], s.image[3 * i + 1], s.image[3 * i + 2]};
+    for (int a = 0; a < DIM; ++a) {
+        double xa = x[a] + p.dt * v[a];
+        if (xa >= p.box[a]) {
+            xa -= p.box[a];
+            img[a] += 1;
+        } else if (xa < 0.0) {
+            xa += p.box[a];
+            img[a] -= 1;
+        }
+        x[a] = xa;
+    }
+    if (DIM == 3) {
+        turn(q, L, I, 2, 0.5 * p.dt);
+        turn(q, L, I, 1, 0.5 * p.dt);
+        turn(q, L, I, 0, p.dt);
+        turn(q, L, I, 1, 0.5 * p.dt);
+        turn(q, L, I, 2, 0.5 * p.dt);
+    } else {
+        turn(q, L, I, 2, p.dt);
+    }
+    const double qn = 1.0 / sqrt(q[0] * q[0] + q[1] * q[1] + q[2] * q[2] + q[3] * q[3]);
+    s.qw[i] = q[0] * qn;
+    s.qx[i] = q[1] * qn;
+    s.qy[i] = q[2] * qn;
+    s.qz[i] = q[3] * qn;
+    s.x[i] = x[0];
+    s.y[i] = x[1];
+    s.vx[i] = v[0];
+    s.vy[i] = v[1];
+    if (DIM == 3) {
+        s.z[i] = x[2];
+        s.vz[i] = v[2];
+        s.Lx[i] = L[0];
+        s.Ly[i] = L[1];
+    }
+    s.Lz[i] = L[2];
+    s.image[3 * i] = img[0];
+    s.image[3 * i + 1] = img[1];
+    s.image[3 * i + 2] = img[2];
+    // displacement since the last list build triggers a rebuild
+    double d2 = 0.0;
+    for (int a = 0; a < DIM; ++a) {
+        const double d = min_image(x[a] - l.xlast[(size_t)a * p.n + i], p.box[a]);
+        d2 += d * d;
+    }
+    if (d2 > p.disp2) atomicOr(&l.flags[FLAG_REBUILD], 1);
+    if (!(isfinite(x[0]) && isfinite(x[1]) && isfinite(x[2]) && isfinite(v[0]) && isfinite(v[1]) && isfinite(v[2])))
+        atomicOr(&l.flags[FLAG_NONFINITE], 1);
+}
+
+// Closing kick; per-block kinetic partials (NVT) and the pending flag.
+template <int DIM, bool NVT>
+__global__ void __launch_bounds__(kBlock) k_kick(SysParams p, StatePtrs s, OutPtrs o, double *ke_part, double *th)
+{
+    __shared__ double sh[kBlock];
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    double kt = 0.0, kr = 0.0;
+    if (i < p.n) {
+        const int sid = s.sid[i];
+        const double m = p.mass[sid];
+        const double hm = 0.5 * p.dt / m;
+        const double I[3] = {p.inertia[sid][0], p.inertia[sid][1], p.inertia[sid][2]};
+        double v[3] = {s.vx[i] + hm * o.Fx[i], s.vy[i] + hm * o.Fy[i], 0.0};
+        s.vx[i] = v[0];
+        s.vy[i] = v[1];
+        double L[3] = {0.0, 0.0, 0.0};
+        if (DIM == 3) {
+            v[2] = s.vz[i] + hm * o.Fz[i];
+            s.vz[i] = v[2];
+            const double q[4] = {s.qw[i], s.qx[i], s.qy[i], s.qz[i]};
+            double tb[3];
+            body_torque(q, o.Tx[i], o.Ty[i], o.Tz[i], tb);
+            L[0] = s.Lx[i] + 0.5 * p.dt * tb[0];
+            L[1] = s.Ly[i] + 0.5 * p.dt * tb[1];
+            L[2] = s.Lz[i] + 0.5 * p.dt * tb[2];
+            s.Lx[i] = L[0];
+            s.Ly[i] = L[1];
+            s.Lz[i] = L[2];
+        } else {
+            L[2] = s.Lz[i] + 0.5 * p.dt * o.Tz[i];
+            s.Lz[i] = L[2];
+        }
+        if (NVT) {
+            kt = 0.5 * m * (v[0] * v[0] + v[1] * v[1] + v[2] * v[2]);
+            for (int a = 0; a < 3; ++a)
+                if (I[a] > 0.0) kr += 0.5 * L[a] * L[a] / I[a];
+        }
+    }
+    if (NVT) {
+        kt = block_sum<kBlock>(kt, sh);
+        kr = block_sum<kBlock>(kr, sh);
+        if (threadIdx.x == 0) {
+            ke_part[2 * blockIdx.x] = kt;
+            ke_part[2 * blockIdx.x + 1] = kr;
+            if (blockIdx.x == 0) th[TH_PENDING] = 1.0;
+        }
+    }
+}
+
+// Per-block kinetic partials of the current state.
+__global__ void __launch_bounds__(kBlock) k_kinetic(SysParams p, StatePtrs s, double *ke_part)
+{
+    __shared__ double sh[kBlock];
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    double kt = 0.0, kr = 0.0;
+    if (i < p.n) {
+        const int sid = s.sid[i];
+        const double m = p.mass[sid];
+        kt = 0.5 * m * (s.vx[i] * s.vx[i] + s.vy[i] * s.vy[i] + s.vz[i] * s.vz[i]);
+        const double L[3] = {s.Lx[i], s.Ly[i], s.Lz[i]};
+        for (int a = 0; a < 3; ++a)
+            if (p.inertia[sid][a] > 0.0) kr += 0.5 * L[a] * L[a] / p.inertia[sid][a];
+    }
+    kt = block_sum<kBlock>(kt, sh);
+    kr = block_sum<kBlock>(kr, sh);
+    if (threadIdx.x == 0) {
+        ke_part[2 * blockIdx.x] = kt;
+        ke_part[2 * blockIdx.x + 1] = kr;
+    }
+}
+
+// Per-block partials of U, K_trans, K_rot and W (9): part[blk * 12 + c].
+__global__ void __launch_bounds__(kBlock) k_energy_partials(SysParams p, StatePtrs s, OutPtrs o, double *part)
+{
+    __shared__ double sh[kBlock];
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    double val[12];
+    for (int c = 0; c < 12; ++c) val[c] = 0.0;
+    if (i < p.n) {
+        const int sid = s.sid[i];
+        val[0] = o.U[i];
+        val[1] = 0.5 * p.mass[sid] * (s.vx[i] * s.vx[i] + s.vy[i] * s.vy[i] + s.vz[i] * s.vz[i]);
+        const double L[3] = {s.Lx[i], s.Ly[i], s.Lz[i]};
+        for (int a = 0; a < 3; ++a)
+            if (p.inertia[sid][a] > 0.0) val[2] += 0.5 * L[a] * L[a] / p.inertia[sid][a];
+        for (int c = 0; c < 9; ++c) val[3 + c] = o.W[(size_t)c * p.n + i];
+    }
+    for (int c = 0; c < 12; ++c) {
+        const double r = block_sum<kBlock>(val[c], sh);
+        if (threadIdx.x == 0) part[12 * blockIdx.x + c] = r;
+    }
+}
+
+}  // namespace
+
+void launch_nh_begin(const SysParams &p, const double *ke_part, int nblk, double *thermo, hipStream_t stream)
+{
+    k_nh_begin<<<1, kBlock, 0, stream>>>(p, ke_part, nblk, thermo);
+}
+
+void launch_nh_end(const SysParams &p, const StatePtrs &s, const double *ke_part, int nblk, double *thermo,
+                   hipStream_t stream)
+{
+    k_nh_end<<<1, kBlock, 0, stream>>>(p, ke_part, nblk, thermo);
+    if (p.n > 0) k_scale<<<blocks_for(p.n), kBlock, 0, stream>>>(p, s, thermo);
+}
+
+void launch_kick_drift(const SysParams &p, const StatePtrs &s, const OutPtrs &o, const ListPtrs &l,
+                       const double *thermo, hipStream_t stream)
+{
+    if (p.n == 0) return;
+    const int nb = blocks_for(p.n);
+    const bool nvt = p.ensemble == DEM_NVT;
+    if (p.dim == 3) {
+        if (nvt) k_kick_drift<3, true><<<nb, kBlock, 0, stream>>>(p, s, o, l, thermo);
+        else k_kick_drift<3, false><<<nb, kBlock, 0, stream>>>(p, s, o, l, thermo);
+    } else {
+        if (nvt) k_kick_drift<2, true><<<nb, kBlock, 0, stream>>>(p, s, o, l, thermo);
+        else k_kick_drift<2, false><<<nb, kBlock, 0, stream>>>(p, s, o, l, thermo);
+    }
+}
+
+void launch_kick(const SysParams &p, const StatePtrs &s, const OutPtrs &o, double *ke_part, double *thermo,
+                 hipStream_t stream)
+{
+    if (p.n == 0) return;
+    const int nb = blocks_for(p.n);
+    const bool nvt = p.ensemble == DEM_NVT;
+    if (p.dim == 3) {
+        if (nvt) k_kick<3, true><<<nb, kBlock, 0, stream>>>(p, s, o, ke_part, thermo);
+        else k_kick<3, false><<<nb, kBlock, 0, stream>>>(p, s, o, ke_part, thermo);
+    } else {
+        if (nvt) k_kick<2, true><<<nb, kBlock, 0, stream>>>(p, s, o, ke_part, thermo);
+        else k_kick<2, false><<<nb, kBlock, 0, stream>>>(p, s, o, ke_part, thermo);
+    }
+}
+
+void launch_kinetic(const SysParams &p, const StatePtrs &s, double *ke_part, hipStream_t stream)
+{
+    if (p.n == 0) return;
+    k_kinetic<<<blocks_for(p.n), kBlock, 0, stream>>>(p, s, ke_part);
+}
+
+void launch_energy_partials(const SysParams &p, const StatePtrs &s, const OutPtrs &o, double *part,
+                            hipStream_t stream)
+{
+    if (p.n == 0) return;
+    k_energy_partials<<<blocks_for(p.n), kBlock, 0, stream>>>(p, s, o, part);
+}
+
+}  // namespace dem

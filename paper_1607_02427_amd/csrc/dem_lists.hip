@@ -1,0 +1,178 @@
+// Cell list and full neighbour list.
+//
+// The lists are an integer contract: the cell of a particle is
+// min(n_c - 1, floor(x / (L / n_c))) per axis, cells are CSR with particles
+// ascending inside a cell, and the neighbours of i are every j != i with
+// |minimum image (x_j - x_i)|^2 < r_list^2, evaluated in FP64 as written
+// (no contraction into fused multiply-adds), stored ascending in j.
+// Rows live column-major (nbr[k * n + i]) so the force kernel's per-row
+// loads are contiguous across particles.
+#include "dem_internal.h"
+
+#pragma clang fp contract(off)
+
+namespace dem {
+namespace {
+
+__device__ inline int cell_coord(double x, double w, int nc)
+{
+    int c = (int)floor(x / w);
+    c = c < 0 ? 0 : c;
+    return c > nc - 1 ? nc - 1 : c;
+}
+
+__device__ inline double min_image(double d, double L) { return d - L * rint(d / L); }
+
+__global__ void k_cell_assign(SysParams p, StatePtrs s, ListPtrs l)
+{
+    if (l.flags[FLAG_REBUILD] == 0) return;
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= p.n) return;
+    int cx = cell_coord(s.x[i], p.cellw[0], p.nc[0]);
+    int cy = cell_coord(s.y[i], p.cellw[1], p.nc[1]);
+    int cz = (p.dim == 3) ? cell_coord(s.z[i], p.cellw[2], p.nc[2]) : 0;
+    int c = cx + p.nc[0] * (cy + p.nc[1] * cz);
+    l.pcell[i] = c;
+    atomicAdd(&l.cell_count[c], 1);
+}
+
+// Exclusive scan of cell counts into cell_start (one block).
+__global__ void __launch_bounds__(1024) k_cell_scan(SysParams p, ListPtrs l)
+{
+    if (l.flags[FLAG_REBUILD] == 0) return;
+    __shared__ int part[1024];
+    int t = threadIdx.x;
+    int per = (p.ncell + 1023) / 1024;
+    int lo = t * per, hi = min(lo + per, p.ncell);
+    int sum = 0;
+    for (int c = lo; c < hi; ++c) sum += l.cell_count[c];
+    part[t] = sum;
+    __syncthreads();
+    for (int off = 1; off < 1024; off <<= 1) {
+        int v = (t >= off) ? part[t - off] : 0;
+        __syncthreads();
+        part[t] += v;
+        __syncthreads();
+    }
+    int run = part[t] - sum;
+    for (int c = lo; c < hi; ++c) {
+        l.cell_start[c] = run;
+        run += l.cell_count[c];
+    }
+    if (t == 1023) l.cell_start[p.ncell] = part[1023];
+}
+
+// Scatter; counting each cell back down leaves cell_count zeroed for the next build.
+__global__ void k_cell_fill(SysParams p, ListPtrs l)
+{
+    if (l.flags[FLAG_REBUILD] == 0) return;
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= p.n) return;
+    int c = l.pcell[i];
+    int slot = atomicSub(&l.cell_count[c], 1) - 1;
+    l.cell_particles[l.cell_start[c] + slot] = i;
+}
+
+// The scatter order is arbitrary: sort every cell ascending (cells hold a few particles).
+__global__ void k_cell_sort(SysParams p, ListPtrs l)
+{
+    if (l.flags[FLAG_REBUILD] == 0) return;
+    int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= p.ncell) return;
+    int lo = l.cell_start[c], hi = l.cell_start[c + 1];
+    for (int a = lo + 1; a < hi; ++a) {
+        int key = l.cell_particles[a];
+        int b = a - 1;
+        while (b >= lo && l.cell_particles[b] > key) {
+            l.cell_particles[b + 1] = l.cell_particles[b];
+            --b;
+        }
+        l.cell_particles[b + 1] = key;
+    }
+}
+
+__device__ inline bool within(const SysParams &p, const StatePtrs &s, double xi, double yi, double zi, int j)
+{
+    double dx = min_image(s.x[j] - xi, p.box[0]);
+    double dy = min_image(s.y[j] - yi, p.box[1]);
+    double r2 = dx * dx + dy * dy;
+    if (p.dim == 3) {
+        double dz = min_image(s.z[j] - zi, p.box[2]);
+        r2 = r2 + dz * dz;
+    }
+    return r2 < p.rl2;
+}
+
+__global__ void k_nbr_build(SysParams p, StatePtrs s, ListPtrs l)
+{
+    if (l.flags[FLAG_REBUILD] == 0) return;
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= p.n) return;
+    const int n = p.n;
+    double xi = s.x[i], yi = s.y[i], zi = (p.dim == 3) ? s.z[i] : 0.0;
+    int count = 0;
+    if (p.use_cells) {
+        int c = l.pcell[i];
+        int cx = c % p.nc[0];
+        int cy = (c / p.nc[0]) % p.nc[1];
+        int cz = c / (p.nc[0] * p.nc[1]);
+        int zlo = (p.dim == 3) ? -1 : 0, zhi = (p.dim == 3) ? 1 : 0;
+        for (int dz = zlo; dz <= zhi; ++dz)
+            for (int dy = -1; dy <= 1; ++dy)
+                for (int dx = -1; dx <= 1; ++dx) {
+                    int ax = cx + dx, ay = cy + dy, az = cz + dz;
+                    ax += (ax < 0) ? p.nc[0] : 0;
+                    ax -= (ax >= p.nc[0]) ? p.nc[0] : 0;
+                    ay += (ay < 0) ? p.nc[1] : 0;
+                    ay -= (ay >= p.nc[1]) ? p.nc[1] : 0;
+                    az += (az < 0) ? p.nc[2] : 0;
+                    az -= (az >= p.nc[2]) ? p.nc[2] : 0;
+                    int cc = ax + p.nc[0] * (ay + p.nc[1] * az);
+                    for (int t = l.cell_start[cc]; t < l.cell_start[cc + 1]; ++t) {
+                        int j = l.cell_particles[t];
+                        if (j != i && within(p, s, xi, yi, zi, j)) {
+                            if (count < p.cap) l.nbr[(size_t)count * n + i] = j;
+                            ++count;
+                        }
+                    }
+                }
+    } else {
+        for (int j = 0; j < n; ++j)
+            if (j != i && within(p, s, xi, yi, zi, j)) {
+                if (count < p.cap) l.nbr[(size_t)count * n + i] = j;
+                ++count;
+            }
+    }
+    int m = count < p.cap ? count : p.cap;
+    for (int a = 1; a < m; ++a) {  // ascending row
+        int key = l.nbr[(size_t)a * n + i];
+        int b = a - 1;
+        while (b >= 0 && l.nbr[(size_t)b * n + i] > key) {
+            l.nbr[(size_t)(b + 1) * n + i] = l.nbr[(size_t)b * n + i];
+            --b;
+        }
+        l.nbr[(size_t)(b + 1) * n + i] = key;
+    }
+    l.n_nbr[i] = m;
+    if (count > p.cap) atomicMax(&l.flags[FLAG_MAXROW], count);
+    l.xlast[i] = xi;
+    l.xlast[n + i] = yi;
+    l.xlast[2 * n + i] = zi;
+}
+
+}  // namespace
+
+void launch_build_lists(const SysParams &p, const StatePtrs &s, const ListPtrs &l, hipStream_t stream)
+{
+    if (p.n == 0) return;
+    const int nb = blocks_for(p.n);
+    // The cell list is always built (it is part of the output contract); the
+    // neighbour search falls back to all pairs when an axis has < 3 cells.
+    k_cell_assign<<<nb, kBlock, 0, stream>>>(p, s, l);
+    k_cell_scan<<<1, 1024, 0, stream>>>(p, l);
+    k_cell_fill<<<nb, kBlock, 0, stream>>>(p, l);
+    k_cell_sort<<<blocks_for(p.ncell), kBlock, 0, stream>>>(p, l);
+    k_nbr_build<<<nb, kBlock, 0, stream>>>(p, s, l);
+}
+
+}  // namespace dem

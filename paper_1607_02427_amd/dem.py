@@ -1,0 +1,300 @@
+"""Python binding of libdem (include/dem.h): argument marshalling only.
+
+PyTorch supplies device memory (the caller-owned state and output arrays)
+and the stream; every step of the method runs in libdem's HIP kernels.  If
+libdem.so is missing this module raises; there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import re
+from typing import Dict, Optional
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libdem.so")
+HEADER = os.path.join(os.path.dirname(HERE), "include", "dem.h")
+
+DEM_FP64, DEM_FP32 = 0, 1
+DEM_NVE, DEM_NVT = 0, 1
+STATUS = {0: "DEM_OK", 1: "DEM_E_ARG", 2: "DEM_E_SHAPE", 3: "DEM_E_OOM", 4: "DEM_E_HIP", 5: "DEM_E_CAPACITY",
+          6: "DEM_E_NONFINITE", 7: "DEM_E_STATE"}
+
+_dp = C.POINTER(C.c_double)
+_ip = C.POINTER(C.c_int32)
+
+
+class ShapeDesc(C.Structure):
+    _fields_ = [("dim", C.c_int32), ("n_vertices", C.c_int32), ("vertices", _dp), ("n_edges", C.c_int32),
+                ("edges", _ip), ("n_faces", C.c_int32), ("face_offsets", _ip), ("face_vertices", _ip),
+                ("rounding_radius", C.c_double), ("mass", C.c_double), ("inertia", C.c_double * 3)]
+
+
+class Params(C.Structure):
+    _fields_ = [("dim", C.c_int32), ("n", C.c_int64), ("box", C.c_double * 3), ("n_shapes", C.c_int32),
+                ("shapes", C.POINTER(ShapeDesc)), ("epsilon", C.c_double), ("skin", C.c_double),
+                ("rebuild_frac", C.c_double), ("dt", C.c_double), ("ensemble", C.c_int32), ("kT", C.c_double),
+                ("tau_T", C.c_double), ("precision", C.c_int32), ("parallel_sin2", C.c_double),
+                ("nbr_capacity", C.c_int32)]
+
+
+class StatePtrs(C.Structure):
+    _fields_ = [(k, C.c_void_p) for k in ("x", "y", "z", "qw", "qx", "qy", "qz", "vx", "vy", "vz", "Lx", "Ly", "Lz",
+                                          "shape_id", "image")]
+
+
+class OutPtrs(C.Structure):
+    _fields_ = [(k, C.c_void_p) for k in ("Fx", "Fy", "Fz", "Tx", "Ty", "Tz", "U", "W")]
+
+
+class EnergyOut(C.Structure):
+    _fields_ = [("U", C.c_double), ("K_trans", C.c_double), ("K_rot", C.c_double), ("H", C.c_double),
+                ("T", C.c_double), ("P", C.c_double), ("W", C.c_double * 9), ("xi", C.c_double),
+                ("eta", C.c_double), ("step", C.c_int64), ("n_rebuilds", C.c_int64)]
+
+
+class DemError(RuntimeError):
+    def __init__(self, status: int, where: str, msg: str):
+        super().__init__(f"{where}: {STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+_lib = None
+
+
+def declared_functions():
+    """Names of the functions dem.h declares."""
+    text = open(HEADER).read()
+    return sorted(set(re.findall(r"^\s*(?:const\s+)?[a-z_0-9]+\s*\*?\s*(dem_[a-z_0-9]+)\s*\(", text, re.M)))
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"libdem.so is not built at {LIB_PATH}; run __graft_entry__.build() "
+                               f"or python -m paper_1607_02427_amd.build")
+        L = C.CDLL(LIB_PATH)
+        st = C.c_int
+        L.dem_create_system.argtypes = [C.POINTER(Params), C.POINTER(StatePtrs), C.POINTER(OutPtrs), C.c_void_p,
+                                        C.POINTER(C.c_void_p)]
+        L.dem_create_system.restype = st
+        for name in ("dem_destroy_system", "dem_build_celllist", "dem_compute_forces", "dem_sync"):
+            getattr(L, name).argtypes = [C.c_void_p]
+            getattr(L, name).restype = st
+        L.dem_step.argtypes = [C.c_void_p, C.c_int64]
+        L.dem_step.restype = st
+        L.dem_energy.argtypes = [C.c_void_p, C.POINTER(EnergyOut)]
+        L.dem_energy.restype = st
+        L.dem_set_thermostat.argtypes = [C.c_void_p, C.c_double, C.c_double]
+        L.dem_set_thermostat.restype = st
+        L.dem_copy_lists.argtypes = [C.c_void_p, _ip, _ip, _ip, _ip, _ip]
+        L.dem_copy_lists.restype = st
+        L.dem_list_info.argtypes = [C.c_void_p, _dp, _ip, _ip]
+        L.dem_list_info.restype = st
+        L.dem_force_stats.argtypes = [C.c_void_p, C.POINTER(C.c_int64), C.c_int32]
+        L.dem_force_stats.restype = st
+        L.dem_set_counting.argtypes = [C.c_void_p, C.c_int32]
+        L.dem_set_counting.restype = st
+        L.dem_time_forces.argtypes = [C.c_void_p, C.c_int32, _dp]
+        L.dem_time_forces.restype = st
+        L.dem_footprint_bytes.argtypes = [C.POINTER(Params)]
+        L.dem_footprint_bytes.restype = C.c_size_t
+        L.dem_status_string.argtypes = [C.c_int]
+        L.dem_status_string.restype = C.c_char_p
+        L.dem_last_error.argtypes = [C.c_void_p]
+        L.dem_last_error.restype = C.c_char_p
+        _lib = L
+    return _lib
+
+
+def _shape_desc(shape, keep):
+    v = np.ascontiguousarray(shape.vertices, dtype=np.float64)
+    e = np.ascontiguousarray(shape.edges, dtype=np.int32)
+    fo = np.ascontiguousarray(shape.face_offsets(), dtype=np.int32)
+    fv = np.ascontiguousarray(shape.face_vertices() if shape.faces else np.zeros(1, np.int32), dtype=np.int32)
+    keep += [v, e, fo, fv]
+    d = ShapeDesc()
+    d.dim = shape.dim
+    d.n_vertices = v.shape[0]
+    d.vertices = v.ctypes.data_as(_dp)
+    d.n_edges = e.shape[0]
+    d.edges = e.ctypes.data_as(_ip)
+    d.n_faces = len(shape.faces)
+    d.face_offsets = fo.ctypes.data_as(_ip)
+    d.face_vertices = fv.ctypes.data_as(_ip)
+    d.rounding_radius = shape.r
+    d.mass = shape.mass
+    for a in range(3):
+        d.inertia[a] = float(shape.inertia[a])
+    return d
+
+
+def make_params(system, precision: str = "fp64", nbr_capacity: int = 0):
+    keep = []
+    descs = (ShapeDesc * len(system.shapes))(*[_shape_desc(s, keep) for s in system.shapes])
+    keep.append(descs)
+    p = Params()
+    p.dim = system.dim
+    p.n = system.n
+    for a in range(3):
+        p.box[a] = float(system.box[a])
+    p.n_shapes = len(system.shapes)
+    p.shapes = C.cast(descs, C.POINTER(ShapeDesc))
+    p.epsilon = system.epsilon
+    p.skin = system.skin
+    p.rebuild_frac = system.rebuild_frac
+    p.dt = system.dt
+    p.ensemble = DEM_NVT if system.ensemble == "nvt" else DEM_NVE
+    p.kT = system.kT
+    p.tau_T = system.tau_T
+    p.precision = DEM_FP32 if precision == "fp32" else DEM_FP64
+    p.parallel_sin2 = system.parallel_sin2
+    p.nbr_capacity = nbr_capacity
+    return p, keep
+
+
+def footprint_bytes(system, precision="fp64", nbr_capacity=0) -> int:
+    p, keep = make_params(system, precision, nbr_capacity)
+    return int(lib().dem_footprint_bytes(C.byref(p)))
+
+
+class DemSystem:
+    """One libdem system whose state and outputs are torch tensors on `device`."""
+
+    STATE = ("x", "y", "z", "qw", "qx", "qy", "qz", "vx", "vy", "vz", "Lx", "Ly", "Lz")
+    OUT = ("Fx", "Fy", "Fz", "Tx", "Ty", "Tz", "U")
+
+    def __init__(self, system, precision: str = "fp64", nbr_capacity: int = 0, device: str = "cuda:0",
+                 stream=None):
+        import torch
+        self.torch = torch
+        self.system = system
+        self.precision = precision
+        self.device = torch.device(device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        n = system.n
+        cols = {"x": system.x[:, 0], "y": system.x[:, 1], "z": system.x[:, 2], "qw": system.q[:, 0],
+                "qx": system.q[:, 1], "qy": system.q[:, 2], "qz": system.q[:, 3], "vx": system.v[:, 0],
+                "vy": system.v[:, 1], "vz": system.v[:, 2], "Lx": system.L[:, 0], "Ly": system.L[:, 1],
+                "Lz": system.L[:, 2]}
+        with torch.cuda.device(self.device):
+            self.t = {k: torch.tensor(np.ascontiguousarray(cols[k]), dtype=torch.float64, device=self.device)
+                      for k in self.STATE}
+            self.t["shape_id"] = torch.tensor(np.ascontiguousarray(system.shape_id, dtype=np.int32), device=self.device)
+            self.t["image"] = torch.tensor(np.ascontiguousarray(system.image, dtype=np.int32).reshape(-1),
+                                           device=self.device)
+            self.o = {k: torch.zeros(n, dtype=torch.float64, device=self.device) for k in self.OUT}
+            self.o["W"] = torch.zeros(9 * n, dtype=torch.float64, device=self.device)
+        sp = StatePtrs(**{k: self.t[k].data_ptr() for k in self.STATE + ("shape_id", "image")})
+        op = OutPtrs(**{k: self.o[k].data_ptr() for k in self.OUT + ("W",)})
+        self._params, self._keep = make_params(system, precision, nbr_capacity)
+        h = C.c_void_p()
+        torch.cuda.synchronize(self.device)
+        with torch.cuda.device(self.device):
+            st = lib().dem_create_system(C.byref(self._params), C.byref(sp), C.byref(op),
+                                         C.c_void_p(self.stream.cuda_stream), C.byref(h))
+        if st != 0:
+            raise DemError(st, "dem_create_system", lib().dem_last_error(None).decode())
+        self.h = h
+
+    # ---------------------------------------------------------------- calls
+    def _check(self, st, where):
+        if st != 0:
+            raise DemError(st, where, lib().dem_last_error(self.h).decode())
+
+    def build_lists(self):
+        self._check(lib().dem_build_celllist(self.h), "dem_build_celllist")
+
+    def compute_forces(self):
+        self._check(lib().dem_compute_forces(self.h), "dem_compute_forces")
+
+    def step(self, n: int):
+        self._check(lib().dem_step(self.h, int(n)), "dem_step")
+
+    def sync(self):
+        self._check(lib().dem_sync(self.h), "dem_sync")
+
+    def set_thermostat(self, xi: float, eta: float):
+        self._check(lib().dem_set_thermostat(self.h, float(xi), float(eta)), "dem_set_thermostat")
+
+    def set_counting(self, on: bool):
+        self._check(lib().dem_set_counting(self.h, 1 if on else 0), "dem_set_counting")
+
+    def energy(self) -> Dict[str, float]:
+        e = EnergyOut()
+        self._check(lib().dem_energy(self.h, C.byref(e)), "dem_energy")
+        return dict(U=e.U, K_trans=e.K_trans, K_rot=e.K_rot, H=e.H, T=e.T, P=e.P, W=np.array(e.W[:]), xi=e.xi,
+                    eta=e.eta, step=e.step, n_rebuilds=e.n_rebuilds)
+
+    def list_info(self):
+        rl = C.c_double()
+        nc = C.c_int32()
+        cap = C.c_int32()
+        self._check(lib().dem_list_info(self.h, C.byref(rl), C.byref(nc), C.byref(cap)), "dem_list_info")
+        return rl.value, nc.value, cap.value
+
+    def lists(self):
+        rl, ncell, cap = self.list_info()
+        n = self.system.n
+        cs = np.zeros(ncell + 1, np.int32)
+        cp = np.zeros(max(n, 1), np.int32)
+        nb = np.zeros(max(cap * n, 1), np.int32)
+        nn = np.zeros(max(n, 1), np.int32)
+        dims = np.zeros(4, np.int32)
+        self._check(lib().dem_copy_lists(self.h, cs.ctypes.data_as(_ip), cp.ctypes.data_as(_ip),
+                                         nb.ctypes.data_as(_ip), nn.ctypes.data_as(_ip), dims.ctypes.data_as(_ip)),
+                    "dem_copy_lists")
+        return dict(r_list=rl, dims=dims[:3].copy(), capacity=int(dims[3]), cell_start=cs,
+                    cell_particles=cp[:n], nbr=nb[: cap * n].reshape(cap, n) if n else nb[:0].reshape(cap, 0),
+                    n_nbr=nn[:n])
+
+    def force_stats(self, reset: bool = False):
+        out = (C.c_int64 * 5)()
+        self._check(lib().dem_force_stats(self.h, out, 1 if reset else 0), "dem_force_stats")
+        return dict(pairs=out[0], features=out[1], in_cutoff=out[2], launches=out[3], vf_near=out[4])
+
+    def time_forces(self, reps: int = 100) -> float:
+        """Mean duration (ms) of one force-kernel launch, HIP events on the system's stream."""
+        ms = C.c_double()
+        self._check(lib().dem_time_forces(self.h, int(reps), C.byref(ms)), "dem_time_forces")
+        return ms.value
+
+    def outputs(self) -> Dict[str, np.ndarray]:
+        """Synchronises and returns F (n,3), T (n,3), U (n,), W (n,9)."""
+        self.sync()
+        o = {k: v.cpu().numpy() for k, v in self.o.items()}
+        n = self.system.n
+        return dict(F=np.stack([o["Fx"], o["Fy"], o["Fz"]], axis=1), T=np.stack([o["Tx"], o["Ty"], o["Tz"]], axis=1),
+                    U=o["U"], W=o["W"].reshape(9, n).T.copy())
+
+    def state(self):
+        """Synchronises and returns a numpy copy of the system at its current state."""
+        self.sync()
+        t = {k: v.cpu().numpy() for k, v in self.t.items()}
+        s = self.system.copy()
+        s.x = np.stack([t["x"], t["y"], t["z"]], axis=1)
+        s.q = np.stack([t["qw"], t["qx"], t["qy"], t["qz"]], axis=1)
+        s.v = np.stack([t["vx"], t["vy"], t["vz"]], axis=1)
+        s.L = np.stack([t["Lx"], t["Ly"], t["Lz"]], axis=1)
+        s.image = t["image"].reshape(-1, 3).copy()
+        return s
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().dem_destroy_system(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()

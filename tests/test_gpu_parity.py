@@ -1,0 +1,199 @@
+"""GPU parity: the HIP path through the C ABI against the FP64 oracle on the
+same seeded inputs.
+
+Lists are compared bit for bit; forces, torques, per-particle energies and
+virials within 1e-5 (FP64 path) or 2e-4 (FP32 path) by the metric of
+parity_metrics.py; short FP64 trajectories against the oracle's integrator.
+"""
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_1607_02427_amd import inputs as I
+from parity_metrics import TOL, compare
+
+pytestmark = pytest.mark.gpu
+
+
+def _dem():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    from paper_1607_02427_amd import dem
+    return dem
+
+
+def _cases():
+    return {
+        "squares_2d_256": lambda: I.squares_2d(),
+        "squares_2d_contact_256": lambda: I.squares_2d_contact(),
+        "cubes_contact_512": lambda: I.cubes_3d_contact(n_side=8),
+        "cubes_3d_1000": lambda: I.cubes_3d(n_side=10),
+        "dimers_cube_256": lambda: I.dimer_gas("cube", 128),
+        "dimers_octa_256": lambda: I.dimer_gas("octahedron", 128),
+        "dimers_tetra_256": lambda: I.dimer_gas("tetrahedron", 128),
+        "dimers_lprism_128": lambda: I.dimer_gas("lprism", 64, quad_h=0.05),
+        "dimers_pentagon_256": lambda: I.dimer_gas("pentagon", 128, dim=2),
+        "ragged_cubes_37": lambda: _drop_last(I.dimer_gas("cube", 19, seed=5)),
+    }
+
+
+def _drop_last(s):
+    s = s.copy()
+    s.x, s.q, s.v, s.L = s.x[:-1], s.q[:-1], s.v[:-1], s.L[:-1]
+    s.shape_id, s.image = s.shape_id[:-1], s.image[:-1]
+    return s
+
+
+CASES = _cases()
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_lists_bit_exact(name):
+    dem = _dem()
+    s = CASES[name]()
+    print(f"[lists] {name} n={s.n}", flush=True)
+    with dem.DemSystem(s, "fp64") as g:
+        L = g.lists()
+        rl_oracle = O.OracleSystem.of(s).r_list(s.skin)
+        assert L["r_list"] == rl_oracle  # same FP64 bits
+        nc, cs, cp = O.cell_list(s, rl_oracle)
+        assert np.array_equal(L["dims"], nc)
+        assert np.array_equal(L["cell_start"], cs)
+        assert np.array_equal(L["cell_particles"], cp)
+        nb, nn, maxrow = O.nbr_list(s, rl_oracle, cap=L["capacity"], mode=1)
+        assert maxrow <= L["capacity"]
+        assert np.array_equal(L["n_nbr"], nn)
+        for i in range(s.n):
+            assert np.array_equal(L["nbr"][: nn[i], i], nb[: nn[i], i])
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("name", list(CASES))
+def test_forces_match_oracle(name, prec):
+    dem = _dem()
+    s = CASES[name]()
+    print(f"[forces] {name} n={s.n} {prec}", flush=True)
+    ref = O.forces(s)
+    assert ref["stats"]["near_par"] == 0
+    with dem.DemSystem(s, prec) as g:
+        out = g.outputs()
+        st = g.force_stats()
+    err = compare(out, ref)
+    print(name, prec, err, ref["stats"], st, flush=True)
+    for k, e in err.items():
+        assert e <= TOL[prec], (k, e)
+    # particles the oracle leaves untouched stay (essentially) untouched
+    zero = np.all(ref["F"] == 0.0, axis=1)
+    scale = np.abs(ref["F"]).max() + 1.0
+    assert np.abs(out["F"][zero]).max(initial=0.0) <= (0.0 if prec == "fp64" else 1e-6 * scale)
+    assert st["pairs"] == ref["stats"]["pairs"]
+
+
+def test_cubes_4096_full_size_fp32():
+    """The benchmark's particle count and launch configuration (4096 cubes,
+    FP32 geometry) on a contact-rich lattice: every particle against the
+    oracle."""
+    dem = _dem()
+    s = I.cubes_3d_contact(n_side=16)
+    print(f"[full] cubes_contact_4096 n={s.n}", flush=True)
+    ref = O.forces(s)
+    with dem.DemSystem(s, "fp32") as g:
+        out = g.outputs()
+    err = compare(out, ref)
+    print("full", err, ref["stats"], flush=True)
+    for k, e in err.items():
+        assert e <= TOL["fp32"], (k, e)
+
+
+@pytest.mark.parametrize("which", ["2d", "3d_nvt"])
+def test_short_trajectory_fp64(which):
+    dem = _dem()
+    if which == "2d":
+        s = I.squares_2d_contact()
+        n = 100
+    else:
+        s = I.cubes_3d_contact(n_side=6)
+        s.ensemble = "nvt"
+        s.kT = 1.5
+        n = 60
+    print(f"[traj] {which} n={s.n} steps={n}", flush=True)
+    ref, th, lg, rf = O.run(s, n)
+    with dem.DemSystem(s, "fp64") as g:
+        g.step(n)
+        e = g.energy()
+        out = g.outputs()
+        st = g.state()
+    ux = st.x + st.image * s.box
+    rx = ref.x + ref.image * s.box
+    assert np.abs(ux - rx).max() < 1e-9
+    assert np.abs(st.v - ref.v).max() < 1e-7 * (1 + np.abs(ref.v).max())
+    sgn = np.sign(np.sum(st.q * ref.q, axis=1))[:, None]
+    assert np.abs(st.q * sgn - ref.q).max() < 1e-9
+    assert e["U"] == pytest.approx(lg[-1, 0], rel=1e-8, abs=1e-10)
+    assert e["K_trans"] == pytest.approx(lg[-1, 1], rel=1e-9)
+    assert e["K_rot"] == pytest.approx(lg[-1, 2], rel=1e-9)
+    assert e["xi"] == pytest.approx(th[0], rel=1e-7, abs=1e-12)
+    assert e["H"] == pytest.approx(lg[-1, 5], rel=1e-9)
+    assert compare(out, rf)["F"] < 1e-6
+
+
+def test_energy_and_virial_totals():
+    dem = _dem()
+    s = I.cubes_3d_contact(n_side=8)
+    ref = O.forces(s)
+    with dem.DemSystem(s, "fp64") as g:
+        e = g.energy()
+    assert e["U"] == pytest.approx(ref["U"].sum(), rel=1e-10)
+    Kt, Kr = O.kinetic(s)
+    assert e["K_trans"] == pytest.approx(Kt, rel=1e-12)
+    assert e["K_rot"] == pytest.approx(Kr, rel=1e-12)
+    W = ref["W"].sum(axis=0)
+    assert np.allclose(e["W"], W, rtol=1e-9, atol=1e-9 * np.abs(W).max())
+    P = (2 * Kt + W[0] + W[4] + W[8]) / (3 * np.prod(s.box))
+    assert e["P"] == pytest.approx(P, rel=1e-9)
+
+
+def test_nve_energy_conservation_fp32_steps():
+    """Mixed precision (FP32 geometry, FP64 state): a 3D contact-rich NVE
+    run keeps the total energy within a small band."""
+    dem = _dem()
+    s = I.cubes_3d_contact(n_side=8)
+    s.ensemble = "nve"
+    with dem.DemSystem(s, "fp32") as g:
+        e0 = g.energy()
+        Hs = []
+        for _ in range(10):
+            g.step(50)
+            Hs.append(g.energy()["H"])
+    drift = (max(Hs) - min(min(Hs), e0["H"])) / s.n
+    print("nve fp32 H band per particle", drift, flush=True)
+    assert drift < 5e-3
+
+
+def test_capacity_overflow_is_reported():
+    dem = _dem()
+    s = I.cubes_3d_contact(n_side=6)
+    with pytest.raises(dem.DemError) as ei:
+        dem.DemSystem(s, "fp64", nbr_capacity=4)
+    assert ei.value.status == 5
+
+
+def test_auto_capacity_grows():
+    dem = _dem()
+    s = I.cubes_3d_contact(n_side=6)
+    with dem.DemSystem(s, "fp64") as g:
+        g.build_lists()
+        rl, ncell, cap = g.list_info()
+        L = g.lists()
+        assert L["n_nbr"].max() <= cap
+
+
+def test_empty_system():
+    dem = _dem()
+    s = I.cubes_3d_contact(n_side=4)
+    s.x, s.q, s.v, s.L = s.x[:0], s.q[:0], s.v[:0], s.L[:0]
+    s.shape_id, s.image = s.shape_id[:0], s.image[:0]
+    with dem.DemSystem(s, "fp32") as g:
+        g.step(5)
+        e = g.energy()
+        assert e["U"] == 0.0 and e["step"] == 5
