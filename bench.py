@@ -25,14 +25,16 @@ if ROOT not in sys.path:
 
 METRIC = "particle-timesteps/s (3D cubes) FP32-batched vs plain; p50/p99 replica latency"
 
-# FP32 flop weights of the force kernel's formulas (add/mul/sub 1, FMA 2,
-# divide or reciprocal 1), per unit of work the counters report.
+# FP32 flop weights of the pair kernel's formulas (add/mul/sub 1, FMA 2,
+# divide or reciprocal 1), per unit of work its counters report.
 FLOPS = {
-    "pair": 110,       # FP64 relative rotation and offset, bound test (once per particle pair)
-    "vf": 24,          # vertex into the face owner's frame + plane distance (every vertex-face problem)
-    "vf_near": 80,     # inside test, projection or boundary edges, back-transform (plane distance < r_cut)
-    "ee": 110,         # edge into i's frame + segment-segment closest points + distance
-    "wca": 50,         # WCA energy/force and accumulation of F, tau, U, W (inside the cutoff)
+    "pair": 60,        # relative rotation R_i^T R_j and offset R_i^T d (once per particle pair)
+    "vertex": 18,      # one vertex carried into the other body's frame (nv_i + nv_j per pair)
+    "vf_cull": 16,     # plane distance + bounding circle (every vertex-face problem)
+    "ee_cull": 17,     # bounding spheres of the two segments (every edge-edge problem)
+    "vf_solve": 100,   # inside test, projection or boundary edges, offset back to i's frame
+    "ee_solve": 65,    # segment-segment closest points and offset
+    "wca": 56,         # WCA energy/force, accumulation of F, both torques and U
 }
 PEAK_FP32 = 157.3e12   # MI355X FP32 vector, published
 PEAK_HBM = 8.0e12
@@ -80,11 +82,12 @@ def force_roofline(g, system, reps=200):
     n_vf = st["pairs"] * per_pair_vf
     n_ee = st["pairs"] * per_pair_ee
     assert n_vf + n_ee == st["features"], (st, per_pair_vf, per_pair_ee)
-    flops = (st["pairs"] * FLOPS["pair"] + n_vf * FLOPS["vf"] + st["vf_near"] * FLOPS["vf_near"]
-             + n_ee * FLOPS["ee"] + st["in_cutoff"] * FLOPS["wca"])
+    flops = (st["pairs"] * (FLOPS["pair"] + 2 * shp.nv * FLOPS["vertex"]) + n_vf * FLOPS["vf_cull"]
+             + n_ee * FLOPS["ee_cull"] + st["vf_near"] * FLOPS["vf_solve"] + st["ee_near"] * FLOPS["ee_solve"]
+             + st["in_cutoff"] * FLOPS["wca"])
     achieved = flops / (mean_ms * 1e-3)
     return dict(bound="alu", achieved=achieved / 1e12, peak=PEAK_FP32 / 1e12, unit="TFLOP/s",
-                frac=achieved / PEAK_FP32, traffic=None, kernel="k_forces<float,3>",
+                frac=achieved / PEAK_FP32, traffic=None, kernel="k_pairs<float,3>",
                 mean_launch_ms=mean_ms, flops_per_launch=flops, counters=st)
 
 

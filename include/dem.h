@@ -175,11 +175,13 @@ dem_status dem_copy_lists(dem_handle h, int32_t *cell_start, int32_t *cell_parti
 dem_status dem_list_info(dem_handle h, double *r_list, int32_t *n_cells, int32_t *capacity);
 
 /* Work counters accumulated by counted force evaluations since the last
- * reset: out[0] particle pairs within R_i + R_j + r_cut, out[1] feature
- * pairs evaluated, out[2] feature pairs inside the cutoff, out[3] counted
- * launches, out[4] vertex-face (3D) problems whose plane distance is below
- * the cutoff (the rest are settled by the plane test alone).  reset != 0
- * clears them after reading.  Synchronises. */
+ * reset (out must hold 7 entries): out[0] unordered particle pairs within
+ * R_i + R_j + r_cut, out[1] feature-pair problems of Eq. 1/2 they contain,
+ * out[2] feature pairs inside the cutoff, out[3] counted launches, out[4]
+ * vertex-face (2D: vertex-edge) problems that pass the conservative cull
+ * and are solved exactly, out[5] FP32 edge pairs redone in FP64, out[6]
+ * edge-edge problems that pass the cull.  reset != 0 clears them after
+ * reading.  Synchronises. */
 dem_status dem_force_stats(dem_handle h, int64_t *out, int32_t reset);
 
 /* Enables (on != 0) or disables the work counters inside dem_step's

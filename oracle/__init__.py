@@ -35,7 +35,8 @@ class _OrSys(C.Structure):
 
 class PairOut(C.Structure):
     _fields_ = [("U", C.c_double), ("Fi", C.c_double * 3), ("Ti", C.c_double * 3), ("Tj", C.c_double * 3),
-                ("W", C.c_double * 9), ("n_in", C.c_int), ("n_par", C.c_int), ("n_near_par", C.c_int)]
+                ("W", C.c_double * 9), ("Fabs", C.c_double), ("Tabs_i", C.c_double), ("Wabs", C.c_double),
+                ("n_in", C.c_int), ("n_par", C.c_int), ("n_near_par", C.c_int)]
 
 
 class Stats(C.Structure):
@@ -68,7 +69,7 @@ def lib():
         L.or_nbr_list.argtypes = [C.POINTER(_OrSys), C.c_int, _dp, C.c_double, C.c_int, C.c_int, _ip, _ip]
         L.or_nbr_list.restype = C.c_int
         L.or_forces.argtypes = [C.POINTER(_OrSys), C.c_int, _dp, _dp, _ip, C.c_int, _dp, _dp, _dp, _dp,
-                                C.POINTER(Stats)]
+                                C.POINTER(Stats), _dp]
         L.or_run.argtypes = [C.POINTER(_OrSys), C.c_int, _dp, _dp, _dp, _dp, _ip, _ip, C.c_int, C.c_double,
                              C.c_int, C.c_double, C.c_double, _dp, C.c_int, _dp, _dp, _dp, _dp, _dp]
         L.or_set_threads.argtypes = [C.c_int]
@@ -205,7 +206,10 @@ def nbr_list(sysobj, r_list, cap, mode=1):
 
 
 def forces(sysobj, mode=1, threads: Optional[int] = None):
-    """Per-particle F (n,3), torque (n,3), U_i (n,), W_i (n,9) and stats."""
+    """Per-particle F (n,3), torque (n,3), U_i (n,), W_i (n,9), stats, and the
+    per-particle magnitude scales of the sums: scale[:,0] = sum |f|,
+    scale[:,1] = sum |(P - x_i) x f|, scale[:,2] = 1/2 sum |r_ij||f| over the
+    feature pairs that contribute to particle i."""
     if threads:
         lib().or_set_threads(int(threads))
     osys = OracleSystem.of(sysobj)
@@ -218,10 +222,11 @@ def forces(sysobj, mode=1, threads: Optional[int] = None):
     U = np.zeros(n)
     W = np.zeros((n, 9))
     st = Stats()
+    sc = np.zeros((n, 3))
     lib().or_forces(C.byref(osys.c), int(n), _d(x), _d(q), _i(sid), int(mode), _d(F), _d(T), _d(U), _d(W),
-                    C.byref(st))
-    return dict(F=F, T=T, U=U, W=W, stats=dict(pairs=st.n_pairs_bound, feature_in=st.n_feature_in,
-                                                 par=st.n_par, near_par=st.n_near_par))
+                    C.byref(st), _d(sc))
+    return dict(F=F, T=T, U=U, W=W, scale=sc, stats=dict(pairs=st.n_pairs_bound, feature_in=st.n_feature_in,
+                                                           par=st.n_par, near_par=st.n_near_par))
 
 
 def run(sysobj, n_steps, *, mode=1, thermo=None, log=True, threads: Optional[int] = None):

@@ -72,6 +72,7 @@ typedef struct {
     double Ti[3];      /* torque on i about x_i */
     double Tj[3];      /* torque on j about its image x_j' */
     double W[9];       /* (x_i - x_j') (x) F_i, row-major */
+    double Fabs, Tabs_i, Wabs; /* sums of |f|, |(P - x_i) x f|, |r_ij (x) f| over feature pairs */
     int n_in;          /* feature pairs inside the cutoff */
     int n_par;         /* of those, evaluated with the parallel rule */
     int n_near_par;    /* of those, within +-1% of the parallel threshold */
@@ -292,6 +293,9 @@ static void accumulate(or_pair_out *o, const double *P, const double *Q, const d
     v_cross(aj, f, tj); /* torque on j is aj x (-f) */
     v_sub(xi, xj, rij);
     o->U += U;
+    o->Fabs += sqrt(v_dot(f, f));
+    o->Tabs_i += sqrt(v_dot(ti, ti));
+    o->Wabs += sqrt(v_dot(rij, rij)) * sqrt(v_dot(f, f));
     for (int k = 0; k < 3; ++k) {
         o->Fi[k] += f[k];
         o->Ti[k] += ti[k];
@@ -525,7 +529,7 @@ typedef struct {
  * neighbours (mode 1); particle pairs farther apart than R_i + R_j + r_cut
  * are skipped because no feature pair can then reach the cutoff. */
 void or_forces(const or_sys *S, int n, const double *x, const double *q, const int *sid, int mode,
-               double *F, double *T, double *U, double *W, or_stats *st)
+               double *F, double *T, double *U, double *W, or_stats *st, double *scale)
 {
     double R[64];
     for (int s = 0; s < S->n_shapes && s < 64; ++s) R[s] = shape_R(S, s);
@@ -548,7 +552,7 @@ void or_forces(const or_sys *S, int n, const double *x, const double *q, const i
     long c_pairs = 0, c_in = 0, c_par = 0, c_near = 0;
 #pragma omp parallel for schedule(dynamic, 16) reduction(+ : c_pairs, c_in, c_par, c_near)
     for (int i = 0; i < n; ++i) {
-        double Fi[3] = {0, 0, 0}, Ti[3] = {0, 0, 0}, Ui = 0.0, Wi[9] = {0};
+        double Fi[3] = {0, 0, 0}, Ti[3] = {0, 0, 0}, Ui = 0.0, Wi[9] = {0}, sF = 0.0, sT = 0.0, sW = 0.0;
         int m = (mode == 1) ? n_nbr[i] : n;
         for (int k = 0; k < m; ++k) {
             int j = (mode == 1) ? nbr[(size_t)k * n + i] : k;
@@ -568,6 +572,14 @@ void or_forces(const or_sys *S, int n, const double *x, const double *q, const i
             for (int a = 0; a < 3; ++a) { Fi[a] += o.Fi[a]; Ti[a] += o.Ti[a]; }
             Ui += 0.5 * o.U;
             for (int a = 0; a < 9; ++a) Wi[a] += 0.5 * o.W[a];
+            sF += o.Fabs;
+            sT += o.Tabs_i;
+            sW += 0.5 * o.Wabs;
+        }
+        if (scale) {
+            scale[3 * i] = sF;
+            scale[3 * i + 1] = sT;
+            scale[3 * i + 2] = sW;
         }
         for (int a = 0; a < 3; ++a) { F[3 * i + a] = Fi[a]; T[3 * i + a] = Ti[a]; }
         U[i] = Ui;
@@ -652,7 +664,7 @@ void or_run(const or_sys *S, int n, double *x, double *q, double *v, double *L, 
     double g = (double)(d * n + drot * n - d);
     double Qm = g * kT * tau_T * tau_T;
     double xi = thermo[0], eta = thermo[1];
-    or_forces(S, n, x, q, sid, mode, F, T, Ui, W, NULL);
+    or_forces(S, n, x, q, sid, mode, F, T, Ui, W, NULL, NULL);
     for (int step = 0; step < n_steps; ++step) {
         if (ensemble == 1) nh_half(S, n, v, L, sid, 0.5 * dt, g, kT, Qm, &xi, &eta);
         for (int i = 0; i < n; ++i) {
@@ -684,7 +696,7 @@ void or_run(const or_sys *S, int n, double *x, double *q, double *v, double *L, 
             double qn = sqrt(qi[0] * qi[0] + qi[1] * qi[1] + qi[2] * qi[2] + qi[3] * qi[3]);
             for (int a = 0; a < 4; ++a) qi[a] /= qn;
         }
-        or_forces(S, n, x, q, sid, mode, F, T, Ui, W, NULL);
+        or_forces(S, n, x, q, sid, mode, F, T, Ui, W, NULL, NULL);
         for (int i = 0; i < n; ++i) {
             double m = S->mass[sid[i]];
             double Rm[9], tb[3];

@@ -1,4 +1,5 @@
-// Rigid-body integrator and reductions, FP64.
+// Rigid-body integrator and reductions, FP64 (the closing kick is fused
+// into the force gather, see dem_force.hip).
 //
 // Sec. IV.A: a second-order integrator; Sec. IV.C: a Nose-Hoover thermostat
 // on translational and rotational degrees of freedom.  One step is
@@ -54,13 +55,11 @@ __device__ inline void turn(double q[4], double L[3], const double I[3], int k, 
 // Body-frame torque R(q)^T tau.
 __device__ inline void body_torque(const double q[4], double tx, double ty, double tz, double out[3])
 {
-    const double w = q[0], x = q[1], y = q[2], z = q[3];
-    const double r00 = 1 - 2 * (y * y + z * z), r01 = 2 * (x * y - w * z), r02 = 2 * (x * z + w * y);
-    const double r10 = 2 * (x * y + w * z), r11 = 1 - 2 * (x * x + z * z), r12 = 2 * (y * z - w * x);
-    const double r20 = 2 * (x * z - w * y), r21 = 2 * (y * z + w * x), r22 = 1 - 2 * (x * x + y * y);
-    out[0] = r00 * tx + r10 * ty + r20 * tz;
-    out[1] = r01 * tx + r11 * ty + r21 * tz;
-    out[2] = r02 * tx + r12 * ty + r22 * tz;
+    double R[9];
+    quat_to_rot(q[0], q[1], q[2], q[3], R);
+    out[0] = R[0] * tx + R[3] * ty + R[6] * tz;
+    out[1] = R[1] * tx + R[4] * ty + R[7] * tz;
+    out[2] = R[2] * tx + R[5] * ty + R[8] * tz;
 }
 
 __device__ inline double min_image(double d, double L) { return d - L * rint(d / L); }
@@ -142,9 +141,9 @@ __global__ void k_scale(SysParams p, StatePtrs s, const double *th)
     s.Lz[i] *= sc;
 }
 
-template <int DIM, bool NVT>
+template <typename T, int DIM, bool NVT>
 __global__ void __launch_bounds__(kBlock) k_kick_drift(SysParams p, StatePtrs s, OutPtrs o, ListPtrs l,
-                                                          const double *th)
+                                                          const double *th, T *rot)
 {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= p.n) return;
@@ -190,10 +189,16 @@ __global__ void __launch_bounds__(kBlock) k_kick_drift(SysParams p, StatePtrs s,
         turn(q, L, I, 2, p.dt);
     }
     const double qn = 1.0 / sqrt(q[0] * q[0] + q[1] * q[1] + q[2] * q[2] + q[3] * q[3]);
-    s.qw[i] = q[0] * qn;
-    s.qx[i] = q[1] * qn;
-    s.qy[i] = q[2] * qn;
-    s.qz[i] = q[3] * qn;
+    for (int a = 0; a < 4; ++a) q[a] *= qn;
+    s.qw[i] = q[0];
+    s.qx[i] = q[1];
+    s.qy[i] = q[2];
+    s.qz[i] = q[3];
+    {  // rotation matrix of the new orientation, for the force pass
+        double R[9];
+        quat_to_rot(q[0], q[1], q[2], q[3], R);
+        for (int k = 0; k < 9; ++k) rot[(size_t)k * p.n + i] = (T)R[k];
+    }
     s.x[i] = x[0];
     s.y[i] = x[1];
     s.vx[i] = v[0];
@@ -217,55 +222,6 @@ __global__ void __launch_bounds__(kBlock) k_kick_drift(SysParams p, StatePtrs s,
     if (d2 > p.disp2) atomicOr(&l.flags[FLAG_REBUILD], 1);
     if (!(isfinite(x[0]) && isfinite(x[1]) && isfinite(x[2]) && isfinite(v[0]) && isfinite(v[1]) && isfinite(v[2])))
         atomicOr(&l.flags[FLAG_NONFINITE], 1);
-}
-
-// Closing kick; per-block kinetic partials (NVT) and the pending flag.
-template <int DIM, bool NVT>
-__global__ void __launch_bounds__(kBlock) k_kick(SysParams p, StatePtrs s, OutPtrs o, double *ke_part, double *th)
-{
-    __shared__ double sh[kBlock];
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    double kt = 0.0, kr = 0.0;
-    if (i < p.n) {
-        const int sid = s.sid[i];
-        const double m = p.mass[sid];
-        const double hm = 0.5 * p.dt / m;
-        const double I[3] = {p.inertia[sid][0], p.inertia[sid][1], p.inertia[sid][2]};
-        double v[3] = {s.vx[i] + hm * o.Fx[i], s.vy[i] + hm * o.Fy[i], 0.0};
-        s.vx[i] = v[0];
-        s.vy[i] = v[1];
-        double L[3] = {0.0, 0.0, 0.0};
-        if (DIM == 3) {
-            v[2] = s.vz[i] + hm * o.Fz[i];
-            s.vz[i] = v[2];
-            const double q[4] = {s.qw[i], s.qx[i], s.qy[i], s.qz[i]};
-            double tb[3];
-            body_torque(q, o.Tx[i], o.Ty[i], o.Tz[i], tb);
-            L[0] = s.Lx[i] + 0.5 * p.dt * tb[0];
-            L[1] = s.Ly[i] + 0.5 * p.dt * tb[1];
-            L[2] = s.Lz[i] + 0.5 * p.dt * tb[2];
-            s.Lx[i] = L[0];
-            s.Ly[i] = L[1];
-            s.Lz[i] = L[2];
-        } else {
-            L[2] = s.Lz[i] + 0.5 * p.dt * o.Tz[i];
-            s.Lz[i] = L[2];
-        }
-        if (NVT) {
-            kt = 0.5 * m * (v[0] * v[0] + v[1] * v[1] + v[2] * v[2]);
-            for (int a = 0; a < 3; ++a)
-                if (I[a] > 0.0) kr += 0.5 * L[a] * L[a] / I[a];
-        }
-    }
-    if (NVT) {
-        kt = block_sum<kBlock>(kt, sh);
-        kr = block_sum<kBlock>(kr, sh);
-        if (threadIdx.x == 0) {
-            ke_part[2 * blockIdx.x] = kt;
-            ke_part[2 * blockIdx.x + 1] = kr;
-            if (blockIdx.x == 0) th[TH_PENDING] = 1.0;
-        }
-    }
 }
 
 // Per-block kinetic partials of the current state.
@@ -326,34 +282,27 @@ void launch_nh_end(const SysParams &p, const StatePtrs &s, const double *ke_part
     if (p.n > 0) k_scale<<<blocks_for(p.n), kBlock, 0, stream>>>(p, s, thermo);
 }
 
-void launch_kick_drift(const SysParams &p, const StatePtrs &s, const OutPtrs &o, const ListPtrs &l,
-                       const double *thermo, hipStream_t stream)
+template <typename T>
+void kick_drift_t(const SysParams &p, const StatePtrs &s, const OutPtrs &o, const ListPtrs &l, const double *thermo,
+                  T *rot, hipStream_t stream)
 {
-    if (p.n == 0) return;
     const int nb = blocks_for(p.n);
     const bool nvt = p.ensemble == DEM_NVT;
     if (p.dim == 3) {
-        if (nvt) k_kick_drift<3, true><<<nb, kBlock, 0, stream>>>(p, s, o, l, thermo);
-        else k_kick_drift<3, false><<<nb, kBlock, 0, stream>>>(p, s, o, l, thermo);
+        if (nvt) k_kick_drift<T, 3, true><<<nb, kBlock, 0, stream>>>(p, s, o, l, thermo, rot);
+        else k_kick_drift<T, 3, false><<<nb, kBlock, 0, stream>>>(p, s, o, l, thermo, rot);
     } else {
-        if (nvt) k_kick_drift<2, true><<<nb, kBlock, 0, stream>>>(p, s, o, l, thermo);
-        else k_kick_drift<2, false><<<nb, kBlock, 0, stream>>>(p, s, o, l, thermo);
+        if (nvt) k_kick_drift<T, 2, true><<<nb, kBlock, 0, stream>>>(p, s, o, l, thermo, rot);
+        else k_kick_drift<T, 2, false><<<nb, kBlock, 0, stream>>>(p, s, o, l, thermo, rot);
     }
 }
 
-void launch_kick(const SysParams &p, const StatePtrs &s, const OutPtrs &o, double *ke_part, double *thermo,
-                 hipStream_t stream)
+void launch_kick_drift(const SysParams &p, const StatePtrs &s, const OutPtrs &o, const ListPtrs &l,
+                       const double *thermo, void *rot, int precision, hipStream_t stream)
 {
     if (p.n == 0) return;
-    const int nb = blocks_for(p.n);
-    const bool nvt = p.ensemble == DEM_NVT;
-    if (p.dim == 3) {
-        if (nvt) k_kick<3, true><<<nb, kBlock, 0, stream>>>(p, s, o, ke_part, thermo);
-        else k_kick<3, false><<<nb, kBlock, 0, stream>>>(p, s, o, ke_part, thermo);
-    } else {
-        if (nvt) k_kick<2, true><<<nb, kBlock, 0, stream>>>(p, s, o, ke_part, thermo);
-        else k_kick<2, false><<<nb, kBlock, 0, stream>>>(p, s, o, ke_part, thermo);
-    }
+    if (precision == DEM_FP32) kick_drift_t(p, s, o, l, thermo, reinterpret_cast<float *>(rot), stream);
+    else kick_drift_t(p, s, o, l, thermo, reinterpret_cast<double *>(rot), stream);
 }
 
 void launch_kinetic(const SysParams &p, const StatePtrs &s, double *ke_part, hipStream_t stream)

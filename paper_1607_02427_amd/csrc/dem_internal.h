@@ -14,17 +14,24 @@ namespace dem {
 constexpr double kWcaCut = 1.122462048309373;
 
 // Device flag words.
-enum Flag { FLAG_REBUILD = 0, FLAG_NBUILDS = 1, FLAG_MAXROW = 2, FLAG_NONFINITE = 3, FLAG_COUNT = 8 };
+enum Flag { FLAG_REBUILD = 0, FLAG_NBUILDS = 1, FLAG_MAXROW = 2, FLAG_NONFINITE = 3, FLAG_NPAIRS = 4, FLAG_COUNT = 8 };
 // Thermostat words (double): xi, eta, velocity scale, B-half-step pending.
 enum Thermo { TH_XI = 0, TH_ETA = 1, TH_SCALE = 2, TH_PENDING = 3, TH_COUNT = 8 };
 // Force work counters (unsigned long long).
-enum Stat { ST_PAIRS = 0, ST_FEATURES = 1, ST_INCUT = 2, ST_LAUNCHES = 3, ST_NEAR = 4, ST_COUNT = 5 };
+enum Stat {
+    ST_PAIRS = 0, ST_FEATURES = 1, ST_INCUT = 2, ST_LAUNCHES = 3, ST_NEAR = 4, ST_REFINED = 5, ST_EENEAR = 6, ST_COUNT = 7
+};
 
-// Body-frame feature tables of one shape in precision T, laid out for LDS.
-// Faces carry their outward unit normal n and offset o (n.x = o on the
-// plane), the in-plane inward normal and offset of each loop edge (convex
-// inside test), 2D face coordinates of each loop vertex (crossing-number
-// test for concave faces) and 1/|edge|^2 for every segment projection.
+// Words of one pair record: force on i (space frame), torque on i, torque
+// on j (both about their own centres, space frame), pair energy U_ij.
+constexpr int kRec = 10;
+
+// Body-frame feature tables of one shape in precision T, staged in LDS.
+// Edges carry their vector, midpoint, half length and 1/|edge|^2; faces
+// their outward unit normal n and offset o (n.x = o on the plane), a
+// bounding circle (centroid, radius), the in-plane inward normal and offset
+// of each loop edge (convex inside test), face coordinates of each loop
+// vertex (crossing-number test for concave faces) and 1/|loop edge|^2.
 template <typename T>
 struct ShapeTab {
     int nv, ne, nf, pad0;
@@ -32,12 +39,16 @@ struct ShapeTab {
     T v[DEM_MAX_VERTS][3];
     int e[DEM_MAX_EDGES][2];
     T ed[DEM_MAX_EDGES][3];      // edge vector b - a
+    T em[DEM_MAX_EDGES][3];      // edge midpoint
+    T eh[DEM_MAX_EDGES];         // half length
     T einv[DEM_MAX_EDGES];       // 1 / |b - a|^2
     int foff[DEM_MAX_FACES + 1];
     int floop[DEM_MAX_LOOP];
     int fconvex[DEM_MAX_FACES];
     T fn[DEM_MAX_FACES][3];
     T fo[DEM_MAX_FACES];
+    T fc[DEM_MAX_FACES][3];      // centroid of the loop vertices
+    T frad[DEM_MAX_FACES];       // max distance from fc to a loop vertex
     T fe1[DEM_MAX_FACES][3];     // face axis 1; axis 2 = n x axis 1; origin = first loop vertex
     T lnrm[DEM_MAX_LOOP][3];     // inward in-plane normal of loop edge k -> k+1
     T loff[DEM_MAX_LOOP];        // lnrm . b_k
@@ -51,6 +62,8 @@ struct SysParams {
     int nc[3], ncell;
     int use_cells;               // 1 if every periodic axis has >= 3 cells
     int ensemble;
+    int max_pairs;               // capacity of the pair arrays
+    int pair_blocks;             // grid of the pair kernel (grid-stride over pairs)
     double box[3];
     double cellw[3];             // box / nc
     double rl2;                  // r_list^2
@@ -76,23 +89,43 @@ struct ListPtrs {
     int32_t *cell_count, *cell_start, *cell_particles, *pcell, *nbr, *n_nbr;
     double *xlast;               // [3][n]
     int32_t *flags;
+    // half list of unordered pairs (i < j), rebuilt with the neighbour list
+    int32_t *klo;                // [n] first row slot of i holding a j > i
+    int32_t *pstart;             // [n] first pair index of i
+    int32_t *pi, *pj;            // [max_pairs]
+    int32_t *pidx;               // [cap][n] pair index of row slot (k, i)
+};
+
+struct ForcePtrs {
+    void *rot;                   // [9][n] body-to-space rotation, precision T
+    void *rec;                   // [max_pairs][kRec] pair records, precision T
+    const void *tab;             // shape tables, precision T
+    const void *tab64;           // shape tables, FP64 (refinement of ill-conditioned FP32 problems)
 };
 
 // ---- launchers (all asynchronous on `stream`) ----
-// Cell list + neighbour list; `gated` kernels exit at once unless the
-// rebuild flag is set (so a captured step can contain them unconditionally).
+// Cell list, neighbour list and half pair list.  The kernels exit at once
+// unless the rebuild flag is set, so a captured step contains them
+// unconditionally.
 void launch_build_lists(const SysParams &p, const StatePtrs &s, const ListPtrs &l, hipStream_t stream);
 
-// Pair forces over the neighbour list; stats may be null.
-void launch_forces(const SysParams &p, const StatePtrs &s, const OutPtrs &o, const ListPtrs &l, const void *tabs,
-                   int precision, unsigned long long *stats, hipStream_t stream);
+// Per-particle rotation matrices from the quaternions.
+void launch_rotations(const SysParams &p, const StatePtrs &s, void *rot, int precision, hipStream_t stream);
+
+// Pair records over the half list; stats may be null.
+void launch_pairs(const SysParams &p, const StatePtrs &s, const ListPtrs &l, const ForcePtrs &f, int precision,
+                  unsigned long long *stats, hipStream_t stream);
+
+// Per-particle sums of pair records in row order (fixed, atomic-free):
+// F, tau, U_i, W_i; with kick != 0 also the closing velocity/angular
+// momentum kick and (NVT) per-block kinetic partials.
+void launch_gather(const SysParams &p, const StatePtrs &s, const OutPtrs &o, const ListPtrs &l, const ForcePtrs &f,
+                   int precision, bool kick, double *ke_part, double *thermo, hipStream_t stream);
 
 // Integrator pieces.
 void launch_nh_begin(const SysParams &p, const double *ke_part, int nblk, double *thermo, hipStream_t stream);
 void launch_kick_drift(const SysParams &p, const StatePtrs &s, const OutPtrs &o, const ListPtrs &l,
-                       const double *thermo, hipStream_t stream);
-void launch_kick(const SysParams &p, const StatePtrs &s, const OutPtrs &o, double *ke_part, double *thermo,
-                 hipStream_t stream);
+                       const double *thermo, void *rot, int precision, hipStream_t stream);
 void launch_kinetic(const SysParams &p, const StatePtrs &s, double *ke_part, hipStream_t stream);
 void launch_nh_end(const SysParams &p, const StatePtrs &s, const double *ke_part, int nblk, double *thermo,
                    hipStream_t stream);
@@ -101,5 +134,19 @@ void launch_energy_partials(const SysParams &p, const StatePtrs &s, const OutPtr
 
 constexpr int kBlock = 256;
 inline int blocks_for(int n) { return (n + kBlock - 1) / kBlock; }
+
+// Rotation matrix (row-major, body to space) of a unit quaternion (w, x, y, z).
+__host__ __device__ inline void quat_to_rot(double w, double x, double y, double z, double *R)
+{
+    R[0] = 1.0 - 2.0 * (y * y + z * z);
+    R[1] = 2.0 * (x * y - w * z);
+    R[2] = 2.0 * (x * z + w * y);
+    R[3] = 2.0 * (x * y + w * z);
+    R[4] = 1.0 - 2.0 * (x * x + z * z);
+    R[5] = 2.0 * (y * z - w * x);
+    R[6] = 2.0 * (x * z - w * y);
+    R[7] = 2.0 * (y * z + w * x);
+    R[8] = 1.0 - 2.0 * (x * x + y * y);
+}
 
 }  // namespace dem

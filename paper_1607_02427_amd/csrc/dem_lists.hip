@@ -1,12 +1,14 @@
-// Cell list and full neighbour list.
+// Cell list, full neighbour list and half pair list.
 //
 // The lists are an integer contract: the cell of a particle is
 // min(n_c - 1, floor(x / (L / n_c))) per axis, cells are CSR with particles
 // ascending inside a cell, and the neighbours of i are every j != i with
 // |minimum image (x_j - x_i)|^2 < r_list^2, evaluated in FP64 as written
 // (no contraction into fused multiply-adds), stored ascending in j.
-// Rows live column-major (nbr[k * n + i]) so the force kernel's per-row
-// loads are contiguous across particles.
+// Rows live column-major (nbr[k * n + i]) so per-row loads are contiguous
+// across particles.  The half list enumerates each unordered pair once
+// (owner i < j), and pidx maps every row slot to its pair, so the force
+// pass evaluates a pair once and each particle sums its own row.
 #include "dem_internal.h"
 
 #pragma clang fp contract(off)
@@ -36,16 +38,16 @@ __global__ void k_cell_assign(SysParams p, StatePtrs s, ListPtrs l)
     atomicAdd(&l.cell_count[c], 1);
 }
 
-// Exclusive scan of cell counts into cell_start (one block).
-__global__ void __launch_bounds__(1024) k_cell_scan(SysParams p, ListPtrs l)
+// Exclusive scan of count[0..m) into start[0..m], start[m] = total (one block).
+__global__ void __launch_bounds__(1024) k_scan(const int32_t *count, int32_t *start, int m, const int32_t *flags)
 {
-    if (l.flags[FLAG_REBUILD] == 0) return;
+    if (flags[FLAG_REBUILD] == 0) return;
     __shared__ int part[1024];
     int t = threadIdx.x;
-    int per = (p.ncell + 1023) / 1024;
-    int lo = t * per, hi = min(lo + per, p.ncell);
+    int per = (m + 1023) / 1024;
+    int lo = t * per, hi = min(lo + per, m);
     int sum = 0;
-    for (int c = lo; c < hi; ++c) sum += l.cell_count[c];
+    for (int c = lo; c < hi; ++c) sum += count[c];
     part[t] = sum;
     __syncthreads();
     for (int off = 1; off < 1024; off <<= 1) {
@@ -56,10 +58,10 @@ __global__ void __launch_bounds__(1024) k_cell_scan(SysParams p, ListPtrs l)
     }
     int run = part[t] - sum;
     for (int c = lo; c < hi; ++c) {
-        l.cell_start[c] = run;
-        run += l.cell_count[c];
+        start[c] = run;
+        run += count[c];
     }
-    if (t == 1023) l.cell_start[p.ncell] = part[1023];
+    if (t == 1023) start[m] = part[1023];
 }
 
 // Scatter; counting each cell back down leaves cell_count zeroed for the next build.
@@ -160,6 +162,58 @@ __global__ void k_nbr_build(SysParams p, StatePtrs s, ListPtrs l)
     l.xlast[2 * n + i] = zi;
 }
 
+// First slot of row i holding a neighbour j > i (rows ascend), and the
+// number of such slots: i owns the pairs (i, j > i) of the half list.
+__global__ void k_pair_count(SysParams p, ListPtrs l, int32_t *upper)
+{
+    if (l.flags[FLAG_REBUILD] == 0) return;
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= p.n) return;
+    const int n = p.n, m = l.n_nbr[i];
+    int lo = 0, hi = m;
+    while (lo < hi) {
+        int mid = (lo + hi) >> 1;
+        if (l.nbr[(size_t)mid * n + i] > i) hi = mid;
+        else lo = mid + 1;
+    }
+    l.klo[i] = lo;
+    upper[i] = m - lo;
+}
+
+// Pair arrays and the slot -> pair map; a slot (k, i) with j < i maps to
+// the pair owned by j, found by bisection in j's row.
+__global__ void k_pair_fill(SysParams p, ListPtrs l)
+{
+    if (l.flags[FLAG_REBUILD] == 0) return;
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i == 0) l.flags[FLAG_NPAIRS] = min(l.pstart[p.n], p.max_pairs);
+    if (i >= p.n) return;
+    const int n = p.n, m = l.n_nbr[i], k0 = l.klo[i];
+    for (int k = 0; k < m; ++k) {
+        const int j = l.nbr[(size_t)k * n + i];
+        int q = -1;
+        if (k >= k0) {
+            q = l.pstart[i] + (k - k0);
+            if (q < p.max_pairs) {
+                l.pi[q] = i;
+                l.pj[q] = j;
+            } else {
+                q = -1;  // only after a row overflow, which is reported
+            }
+        } else {
+            int lo = l.klo[j], hi = l.n_nbr[j];
+            while (lo < hi) {
+                int mid = (lo + hi) >> 1;
+                if (l.nbr[(size_t)mid * n + j] < i) lo = mid + 1;
+                else hi = mid;
+            }
+            if (lo < l.n_nbr[j] && l.nbr[(size_t)lo * n + j] == i) q = l.pstart[j] + (lo - l.klo[j]);
+            if (q >= p.max_pairs) q = -1;
+        }
+        l.pidx[(size_t)k * n + i] = q;
+    }
+}
+
 }  // namespace
 
 void launch_build_lists(const SysParams &p, const StatePtrs &s, const ListPtrs &l, hipStream_t stream)
@@ -169,10 +223,14 @@ void launch_build_lists(const SysParams &p, const StatePtrs &s, const ListPtrs &
     // The cell list is always built (it is part of the output contract); the
     // neighbour search falls back to all pairs when an axis has < 3 cells.
     k_cell_assign<<<nb, kBlock, 0, stream>>>(p, s, l);
-    k_cell_scan<<<1, 1024, 0, stream>>>(p, l);
+    k_scan<<<1, 1024, 0, stream>>>(l.cell_count, l.cell_start, p.ncell, l.flags);
     k_cell_fill<<<nb, kBlock, 0, stream>>>(p, l);
     k_cell_sort<<<blocks_for(p.ncell), kBlock, 0, stream>>>(p, l);
     k_nbr_build<<<nb, kBlock, 0, stream>>>(p, s, l);
+    // half pair list: pcell is free after the neighbour build and holds the per-particle pair counts
+    k_pair_count<<<nb, kBlock, 0, stream>>>(p, l, l.pcell);
+    k_scan<<<1, 1024, 0, stream>>>(l.pcell, l.pstart, p.n, l.flags);
+    k_pair_fill<<<nb, kBlock, 0, stream>>>(p, l);
 }
 
 }  // namespace dem

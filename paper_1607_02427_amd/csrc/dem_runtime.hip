@@ -29,6 +29,8 @@ struct dem_system {
     hipStream_t stream = nullptr;
     hipStream_t cap_stream = nullptr;
     void *tab64 = nullptr, *tab32 = nullptr;
+    void *rot = nullptr;          // [9][n] in the force precision
+    void *rec = nullptr;          // [max_pairs][kRec] in the force precision
     double *ke_part = nullptr;    // [2 * nblk]
     double *e_part = nullptr;     // [12 * nblk]
     double *thermo = nullptr;     // [TH_COUNT]
@@ -66,6 +68,11 @@ dem_status fail(dem_system *h, dem_status s, const char *fmt, ...)
     } while (0)
 
 __global__ void k_set_int(int32_t *p, int32_t v) { *p = v; }
+__global__ void k_end_build(int32_t *flags)
+{
+    if (flags[FLAG_REBUILD] != 0) flags[FLAG_NBUILDS] += 1;
+    flags[FLAG_REBUILD] = 0;
+}
 __global__ void k_set_thermo(double *th, double xi, double eta)
 {
     th[TH_XI] = xi;
@@ -124,6 +131,8 @@ dem_status build_table(dem_system *h, int idx, const dem_shape_desc &d, int dim,
         }
         if (!(l2 > 0.0)) return fail(h, DEM_E_SHAPE, "shape %d: edge %d has zero length", idx, k);
         T.einv[k] = 1.0 / l2;
+        T.eh[k] = 0.5 * std::sqrt(l2);
+        for (int c = 0; c < 3; ++c) T.em[k][c] = 0.5 * (T.v[a][c] + T.v[b][c]);
     }
     if (dim == 3) {
         if (d.face_offsets[0] != 0) return fail(h, DEM_E_SHAPE, "shape %d: face_offsets[0] != 0", idx);
@@ -190,6 +199,23 @@ dem_status build_table(dem_system *h, int idx, const dem_shape_desc &d, int dim,
                 if (hdot(hcross(hsub(a, c), ed), n) < -1e-12) convex = false;
             }
             T.fconvex[f] = convex ? 1 : 0;
+            HostVec c{0, 0, 0};
+            for (int k = k0; k < k1; ++k) {
+                c.x += T.v[T.floop[k]][0];
+                c.y += T.v[T.floop[k]][1];
+                c.z += T.v[T.floop[k]][2];
+            }
+            const double inv = 1.0 / (k1 - k0);
+            c = {c.x * inv, c.y * inv, c.z * inv};
+            double rad = 0.0;
+            for (int k = k0; k < k1; ++k) {
+                HostVec dv = hsub(HostVec{T.v[T.floop[k]][0], T.v[T.floop[k]][1], T.v[T.floop[k]][2]}, c);
+                rad = std::max(rad, std::sqrt(hdot(dv, dv)));
+            }
+            T.fc[f][0] = c.x;
+            T.fc[f][1] = c.y;
+            T.fc[f][2] = c.z;
+            T.frad[f] = rad * (1.0 + 1e-6) + 1e-9;  // conservative bounding circle
         }
         if (!(vol6 > 0.0))
             return fail(h, DEM_E_SHAPE, "shape %d: face loops are not counter-clockwise seen from outside", idx);
@@ -210,16 +236,22 @@ void to_float(const ShapeTab<double> &D, ShapeTab<float> &F)
     for (int k = 0; k < DEM_MAX_EDGES; ++k) {
         F.e[k][0] = D.e[k][0];
         F.e[k][1] = D.e[k][1];
-        for (int a = 0; a < 3; ++a) F.ed[k][a] = (float)D.ed[k][a];
+        for (int a = 0; a < 3; ++a) {
+            F.ed[k][a] = (float)D.ed[k][a];
+            F.em[k][a] = (float)D.em[k][a];
+        }
+        F.eh[k] = (float)(D.eh[k] * (1.0 + 1e-6));  // keep the FP32 bounds conservative
         F.einv[k] = (float)D.einv[k];
     }
     for (int f = 0; f <= DEM_MAX_FACES; ++f) F.foff[f] = D.foff[f];
     for (int f = 0; f < DEM_MAX_FACES; ++f) {
         F.fconvex[f] = D.fconvex[f];
         F.fo[f] = (float)D.fo[f];
+        F.frad[f] = (float)(D.frad[f] * (1.0 + 1e-6));
         for (int a = 0; a < 3; ++a) {
             F.fn[f][a] = (float)D.fn[f][a];
             F.fe1[f][a] = (float)D.fe1[f][a];
+            F.fc[f][a] = (float)D.fc[f][a];
         }
     }
     for (int k = 0; k < DEM_MAX_LOOP; ++k) {
@@ -251,8 +283,15 @@ void free_lists(dem_system *h)
     (void)hipFree(h->lst.nbr);
     (void)hipFree(h->lst.n_nbr);
     (void)hipFree(h->lst.xlast);
-    h->lst.cell_count = h->lst.cell_start = h->lst.cell_particles = h->lst.pcell = h->lst.nbr = h->lst.n_nbr = nullptr;
-    h->lst.xlast = nullptr;
+    (void)hipFree(h->lst.klo);
+    (void)hipFree(h->lst.pstart);
+    (void)hipFree(h->lst.pi);
+    (void)hipFree(h->lst.pj);
+    (void)hipFree(h->lst.pidx);
+    (void)hipFree(h->rec);
+    (void)hipFree(h->rot);
+    h->lst = ListPtrs{};
+    h->rec = h->rot = nullptr;
 }
 
 void drop_graph(dem_system *h)
@@ -263,16 +302,45 @@ void drop_graph(dem_system *h)
     h->graph = nullptr;
 }
 
+size_t force_word(const dem_system *h) { return h->prm.precision == DEM_FP32 ? sizeof(float) : sizeof(double); }
+
+// Row storage and everything sized by the row capacity: slot -> pair map,
+// pair arrays and pair records.
 dem_status alloc_nbr(dem_system *h, int cap)
 {
     (void)hipFree(h->lst.nbr);
-    h->lst.nbr = nullptr;
-    size_t n = (size_t)std::max(h->sp.n, 1);
-    if (hipMalloc(&h->lst.nbr, sizeof(int32_t) * (size_t)cap * n) != hipSuccess)
+    (void)hipFree(h->lst.pidx);
+    (void)hipFree(h->lst.pi);
+    (void)hipFree(h->lst.pj);
+    (void)hipFree(h->rec);
+    h->lst.nbr = h->lst.pidx = h->lst.pi = h->lst.pj = nullptr;
+    h->rec = nullptr;
+    const size_t n = (size_t)std::max(h->sp.n, 1);
+    const size_t maxp = n * (size_t)cap / 2 + 64;
+    if (maxp > (size_t)INT32_MAX) return fail(h, DEM_E_ARG, "pair capacity overflows int32");
+    if (hipMalloc(&h->lst.nbr, sizeof(int32_t) * (size_t)cap * n) != hipSuccess ||
+        hipMalloc(&h->lst.pidx, sizeof(int32_t) * (size_t)cap * n) != hipSuccess ||
+        hipMalloc(&h->lst.pi, sizeof(int32_t) * maxp) != hipSuccess ||
+        hipMalloc(&h->lst.pj, sizeof(int32_t) * maxp) != hipSuccess ||
+        hipMalloc(&h->rec, force_word(h) * kRec * maxp) != hipSuccess)
         return fail(h, DEM_E_OOM, "neighbour list of %d x %zu entries", cap, n);
     h->sp.cap = cap;
+    h->sp.max_pairs = (int)maxp;
+    // grid-stride pair kernel: enough waves to fill the chip, no more than the pairs need
+    const size_t want = (maxp + 3) / 4;
+    h->sp.pair_blocks = (int)std::max<size_t>(1, std::min<size_t>(want, 2048));
     drop_graph(h);
     return DEM_OK;
+}
+
+ForcePtrs force_ptrs(const dem_system *h)
+{
+    ForcePtrs f;
+    f.rot = h->rot;
+    f.rec = h->rec;
+    f.tab = h->prm.precision == DEM_FP32 ? h->tab32 : h->tab64;
+    f.tab64 = h->tab64;
+    return f;
 }
 
 dem_status latched(dem_system *h)
@@ -288,12 +356,12 @@ dem_status latched(dem_system *h)
 
 void enqueue_step(dem_system *h, hipStream_t s)
 {
+    const ForcePtrs f = force_ptrs(h);
     if (h->sp.ensemble == DEM_NVT) launch_nh_begin(h->sp, h->ke_part, h->nblk, h->thermo, s);
-    launch_kick_drift(h->sp, h->st, h->out, h->lst, h->thermo, s);
+    launch_kick_drift(h->sp, h->st, h->out, h->lst, h->thermo, h->rot, h->prm.precision, s);
     launch_build_lists(h->sp, h->st, h->lst, s);
-    launch_forces(h->sp, h->st, h->out, h->lst, h->prm.precision == DEM_FP32 ? h->tab32 : h->tab64,
-                  h->prm.precision, h->counting ? h->stats : nullptr, s);
-    launch_kick(h->sp, h->st, h->out, h->ke_part, h->thermo, s);
+    launch_pairs(h->sp, h->st, h->lst, f, h->prm.precision, h->counting ? h->stats : nullptr, s);
+    launch_gather(h->sp, h->st, h->out, h->lst, f, h->prm.precision, true, h->ke_part, h->thermo, s);
 }
 
 dem_status ensure_graph(dem_system *h)
@@ -367,7 +435,10 @@ size_t dem_footprint_bytes(const dem_params *p)
     size_t ncell = 1;
     for (int a = 0; a < p->dim && a < 3; ++a) ncell *= (size_t)std::max(1.0, std::floor(p->box[a] / rl));
     size_t nblk = (n + kBlock - 1) / kBlock;
-    return sizeof(int32_t) * (n * (size_t)cap + 3 * n + 2 * ncell + 1) + sizeof(double) * (3 * n + 14 * nblk + TH_COUNT) +
+    const size_t w = p->precision == DEM_FP32 ? sizeof(float) : sizeof(double);
+    const size_t maxp = n * (size_t)cap / 2 + 64;
+    return sizeof(int32_t) * (2 * n * (size_t)cap + 6 * n + 2 * ncell + 2 + 2 * maxp) +
+           sizeof(double) * (3 * n + 14 * nblk + TH_COUNT) + w * (9 * n + kRec * maxp) +
            2 * DEM_MAX_SHAPES * sizeof(ShapeTab<double>) + 256;
 }
 
@@ -480,7 +551,10 @@ dem_status dem_create_system(const dem_params *params, const dem_state_ptrs *sta
               hipMalloc(&h->lst.cell_particles, sizeof(int32_t) * n) == hipSuccess &&
               hipMalloc(&h->lst.pcell, sizeof(int32_t) * n) == hipSuccess &&
               hipMalloc(&h->lst.n_nbr, sizeof(int32_t) * n) == hipSuccess &&
-              hipMalloc(&h->lst.xlast, sizeof(double) * 3 * n) == hipSuccess;
+              hipMalloc(&h->lst.xlast, sizeof(double) * 3 * n) == hipSuccess &&
+              hipMalloc(&h->lst.klo, sizeof(int32_t) * n) == hipSuccess &&
+              hipMalloc(&h->lst.pstart, sizeof(int32_t) * (n + 1)) == hipSuccess &&
+              hipMalloc(&h->rot, (p.precision == DEM_FP32 ? sizeof(float) : sizeof(double)) * 9 * n) == hipSuccess;
     if (!ok) return bail(fail(h, DEM_E_OOM, "device allocation failed"));
     if (sp.n > 0) {  // shape ids index the LDS tables: validate before any kernel reads them
         std::vector<int32_t> sid((size_t)sp.n);
@@ -537,7 +611,7 @@ dem_status dem_build_celllist(dem_handle h)
     if (!h) return fail(nullptr, DEM_E_ARG, "null handle");
     dem_status st = build_lists_sync(h);
     if (st != DEM_OK) return st;
-    k_set_int<<<1, 1, 0, h->stream>>>(h->lst.flags + FLAG_REBUILD, 0);
+    k_end_build<<<1, 1, 0, h->stream>>>(h->lst.flags);
     HIPCHK(h, hipGetLastError());
     return DEM_OK;
 }
@@ -545,9 +619,11 @@ dem_status dem_build_celllist(dem_handle h)
 dem_status dem_compute_forces(dem_handle h)
 {
     if (!h) return fail(nullptr, DEM_E_ARG, "null handle");
+    const ForcePtrs f = force_ptrs(h);
+    launch_rotations(h->sp, h->st, h->rot, h->prm.precision, h->stream);
     launch_build_lists(h->sp, h->st, h->lst, h->stream);  // gated: only if a rebuild is due
-    launch_forces(h->sp, h->st, h->out, h->lst, h->prm.precision == DEM_FP32 ? h->tab32 : h->tab64, h->prm.precision,
-                  h->stats, h->stream);
+    launch_pairs(h->sp, h->st, h->lst, f, h->prm.precision, h->stats, h->stream);
+    launch_gather(h->sp, h->st, h->out, h->lst, f, h->prm.precision, false, h->ke_part, h->thermo, h->stream);
     HIPCHK(h, hipGetLastError());
     return DEM_OK;
 }
@@ -686,10 +762,10 @@ dem_status dem_time_forces(dem_handle h, int32_t reps, double *mean_ms)
     hipEvent_t e0, e1;
     HIPCHK(h, hipEventCreate(&e0));
     HIPCHK(h, hipEventCreate(&e1));
-    const void *tab = h->prm.precision == DEM_FP32 ? h->tab32 : h->tab64;
-    launch_forces(h->sp, h->st, h->out, h->lst, tab, h->prm.precision, nullptr, h->stream);  // warm
+    const ForcePtrs f = force_ptrs(h);
+    launch_pairs(h->sp, h->st, h->lst, f, h->prm.precision, nullptr, h->stream);  // warm
     HIPCHK(h, hipEventRecord(e0, h->stream));
-    for (int r = 0; r < reps; ++r) launch_forces(h->sp, h->st, h->out, h->lst, tab, h->prm.precision, nullptr, h->stream);
+    for (int r = 0; r < reps; ++r) launch_pairs(h->sp, h->st, h->lst, f, h->prm.precision, nullptr, h->stream);
     HIPCHK(h, hipEventRecord(e1, h->stream));
     HIPCHK(h, hipEventSynchronize(e1));
     float ms = 0.0f;

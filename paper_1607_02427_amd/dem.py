@@ -252,9 +252,10 @@ class DemSystem:
                     n_nbr=nn[:n])
 
     def force_stats(self, reset: bool = False):
-        out = (C.c_int64 * 5)()
+        out = (C.c_int64 * 7)()
         self._check(lib().dem_force_stats(self.h, out, 1 if reset else 0), "dem_force_stats")
-        return dict(pairs=out[0], features=out[1], in_cutoff=out[2], launches=out[3], vf_near=out[4])
+        return dict(pairs=out[0], features=out[1], in_cutoff=out[2], launches=out[3], vf_near=out[4],
+                    refined=out[5], ee_near=out[6])
 
     def time_forces(self, reps: int = 100) -> float:
         """Mean duration (ms) of one force-kernel launch, HIP events on the system's stream."""

@@ -329,11 +329,9 @@ def _finish_3d(name, verts, faces, r, V, M1, S, mass=1.0):
     if np.max(np.abs(I - np.diag(np.diag(I)))) < 1e-12 * np.max(np.abs(I)):
         U = np.eye(3)
         w = np.diag(I).copy()
-    verts_b = (verts - com) @ U
-    # keep right-handed principal frame
     if np.linalg.det(U) < 0:
-        verts_b[:, 2] *= -1.0
-        faces = [list(reversed(f)) for f in faces]
+        U[:, 2] *= -1.0  # proper rotation, so face loops keep their orientation
+    verts_b = (verts - com) @ U
     edges = _edges_from_faces(faces)
     return Shape(dim=3, vertices=np.ascontiguousarray(verts_b), edges=edges, faces=faces, r=float(r),
                  mass=float(mass), inertia=np.asarray(w, dtype=np.float64), name=name, volume=float(V))
