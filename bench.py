@@ -29,9 +29,10 @@ METRIC = "particle-timesteps/s (3D cubes) FP32-batched vs plain; p50/p99 replica
 # divide or reciprocal 1), per unit of work its counters report.
 FLOPS = {
     "pair": 60,        # relative rotation R_i^T R_j and offset R_i^T d (once per particle pair)
-    "vertex": 18,      # one vertex carried into the other body's frame (nv_i + nv_j per pair)
-    "vf_cull": 16,     # plane distance + bounding circle (every vertex-face problem)
-    "ee_cull": 17,     # bounding spheres of the two segments (every edge-edge problem)
+    "vertex": 23,      # vertex carried into the other body's frame + reach test (nv_i + nv_j per pair)
+    "edge": 12,        # edge reach test (ne_i + ne_j per pair)
+    "face": 12,        # face reach test (nf_i + nf_j per pair)
+    "cull": 17,        # per-problem test: plane + bounding circle, or segment bounding spheres
     "vf_solve": 100,   # inside test, projection or boundary edges, offset back to i's frame
     "ee_solve": 65,    # segment-segment closest points and offset
     "wca": 56,         # WCA energy/force, accumulation of F, both torques and U
@@ -77,14 +78,9 @@ def force_roofline(g, system, reps=200):
     st = g.force_stats(reset=True)
     mean_ms = g.time_forces(reps)
     shp = system.shapes[0]
-    per_pair_vf = 2 * shp.nv * shp.nf
-    per_pair_ee = shp.ne * shp.ne
-    n_vf = st["pairs"] * per_pair_vf
-    n_ee = st["pairs"] * per_pair_ee
-    assert n_vf + n_ee == st["features"], (st, per_pair_vf, per_pair_ee)
-    flops = (st["pairs"] * (FLOPS["pair"] + 2 * shp.nv * FLOPS["vertex"]) + n_vf * FLOPS["vf_cull"]
-             + n_ee * FLOPS["ee_cull"] + st["vf_near"] * FLOPS["vf_solve"] + st["ee_near"] * FLOPS["ee_solve"]
-             + st["in_cutoff"] * FLOPS["wca"])
+    per_pair = FLOPS["pair"] + 2 * (shp.nv * FLOPS["vertex"] + shp.ne * FLOPS["edge"] + shp.nf * FLOPS["face"])
+    flops = (st["pairs"] * per_pair + st["features"] * FLOPS["cull"] + st["vf_near"] * FLOPS["vf_solve"]
+             + st["ee_near"] * FLOPS["ee_solve"] + st["in_cutoff"] * FLOPS["wca"])
     achieved = flops / (mean_ms * 1e-3)
     return dict(bound="alu", achieved=achieved / 1e12, peak=PEAK_FP32 / 1e12, unit="TFLOP/s",
                 frac=achieved / PEAK_FP32, traffic=None, kernel="k_pairs<float,3>",

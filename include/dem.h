@@ -53,6 +53,9 @@ typedef enum {
 
 enum { DEM_FP64 = 0, DEM_FP32 = 1 };  /* pair-geometry precision */
 enum { DEM_NVE = 0, DEM_NVT = 1 };
+/* List build: automatic (one workgroup for small systems, one kernel per
+ * phase for large ones) or always one kernel per phase.  Same lists. */
+enum { DEM_LISTS_AUTO = 0, DEM_LISTS_MULTI = 1 };
 
 /* Limits of one shape (vertices, edges, faces, face-loop entries) and of the
  * number of shapes per system. */
@@ -95,6 +98,7 @@ typedef struct {
     double parallel_sin2;         /* edges with |u x v|^2 < parallel_sin2 |u|^2 |v|^2
                                      use the overlap-midpoint rule (Sec. II) */
     int32_t nbr_capacity;         /* neighbour-row capacity; 0 = automatic */
+    int32_t list_mode;            /* DEM_LISTS_AUTO or DEM_LISTS_MULTI */
 } dem_params;
 
 /* Caller-owned device arrays, FP64 structure-of-arrays, length n, borrowed
@@ -176,12 +180,12 @@ dem_status dem_list_info(dem_handle h, double *r_list, int32_t *n_cells, int32_t
 
 /* Work counters accumulated by counted force evaluations since the last
  * reset (out must hold 7 entries): out[0] unordered particle pairs within
- * R_i + R_j + r_cut, out[1] feature-pair problems of Eq. 1/2 they contain,
- * out[2] feature pairs inside the cutoff, out[3] counted launches, out[4]
- * vertex-face (2D: vertex-edge) problems that pass the conservative cull
- * and are solved exactly, out[5] FP32 edge pairs redone in FP64, out[6]
- * edge-edge problems that pass the cull.  reset != 0 clears them after
- * reading.  Synchronises. */
+ * R_i + R_j + r_cut, out[1] feature-pair problems of Eq. 1/2 left after the
+ * per-pair feature prefilter, out[2] feature pairs inside the cutoff,
+ * out[3] counted launches, out[4] vertex-face (2D: vertex-edge) problems
+ * that pass the per-problem cull and are solved exactly, out[5] FP32 edge
+ * pairs redone in FP64, out[6] edge-edge problems solved exactly.
+ * reset != 0 clears them after reading.  Synchronises. */
 dem_status dem_force_stats(dem_handle h, int64_t *out, int32_t reset);
 
 /* Enables (on != 0) or disables the work counters inside dem_step's

@@ -10,18 +10,25 @@
 // their overlap (Sec. II, paragraph on parallel edges).
 //
 // Mapping to gfx950 (two kernels):
-//  1. k_pairs: one wave64 per unordered pair of the half list (grid-stride).
-//     The wave builds j's frame relative to i's once, transforms both
+//  1. k_pairs: 16 lanes per unordered pair of the half list, so one wave64
+//     works on four pairs at once and shares every latency stage among them
+//     (grid-stride over the list).  A group builds j's frame relative to
+//     i's once, transforms both
 //     vertex sets across (one lane per vertex, kept in LDS), then runs the
-//     contact search: every feature pair of Eq. 1/2 gets a cheap
-//     conservative test (plane distance and bounding circle for
-//     vertex-face, bounding spheres for edge-edge and vertex-edge), and the
-//     survivors are compacted into a per-wave LDS queue with ballot/popcount
-//     so the exact nearest-point and WCA work runs on dense lanes.  The wave
-//     reduces force and both torques in FP64 and writes one record per pair.
-//  2. k_gather: one thread per particle sums its row of pair records in row
+//     contact search in three levels, all conservative: a feature prefilter
+//     keeps only vertices, edges and faces within reach of the other body
+//     (one lane per feature, ballot-compacted index lists); every remaining
+//     feature pair of Eq. 1/2 gets a cheap test (plane distance and
+//     bounding circle for vertex-face, bounding spheres for edge-edge and
+//     vertex-edge); and the survivors are compacted into a per-wave LDS
+//     queue so the exact nearest-point and WCA work runs on dense lanes.  The
+//     group reduces force, both torques and energy across its 16 lanes and
+//     writes one record per pair (FP32 pair records in FP32 mode; every sum
+//     over pairs is FP64).
+//  2. k_gather: 8 lanes per particle sum its row of pair records in a fixed
 //     order (no atomics, deterministic) into F, tau, U_i and W_i, optionally
-//     fused with the closing kick of the integrator.
+//     fused with the closing kick of the integrator and, with NVT, the
+//     thermostat half steps between two steps.
 // FP32 mode does the geometry in FP32 from FP64 pair offsets rounded once;
 // segment pairs that are nearly parallel (sin^2 < 1e-2) and near the cutoff
 // are redone in FP64, because their closest points are ill-conditioned in
@@ -132,51 +139,6 @@ __device__ inline V3<T> face_point(const ShapeTab<T> &S, int f, V3<T> p)
     return q;
 }
 
-// Closest points of segments p1 + s d1 and p2 + t d2 (s, t in [0,1]).
-// Non-parallel: the clamped line solution (Ericson, Real-Time Collision
-// Detection, 2005, Sec. 5.1.9) with the cross-product form of its
-// denominator.  Nearly parallel (|d1 x d2|^2 < par_s2 a e): each point is
-// the midpoint of its segment's overlap with the other segment's
-// projection, or the facing endpoint.  Returns |d1 x d2|^2.
-template <typename T>
-__device__ inline T seg_seg(V3<T> p1, V3<T> d1, T a, V3<T> p2, V3<T> d2, T e, T par_s2, V3<T> &P, V3<T> &Q)
-{
-    const V3<T> r = p1 - p2;
-    const T b = dot(d1, d2), c = dot(d1, r), f = dot(d2, r);
-    const V3<T> cr = cross(d1, d2);
-    const T den = dot(cr, cr);
-    T s, t;
-    if (den < par_s2 * a * e) {
-        const T ia = T(1) / a, ie = T(1) / e;
-        const T t0 = -c * ia, t1 = (b - c) * ia;
-        T lo = fmax(T(0), fmin(t0, t1)), hi = fmin(T(1), fmax(t0, t1));
-        s = (lo <= hi) ? T(0.5) * (lo + hi) : (fmax(t0, t1) < T(0) ? T(0) : T(1));
-        const T u0 = f * ie, u1 = (f + b) * ie;
-        lo = fmax(T(0), fmin(u0, u1));
-        hi = fmin(T(1), fmax(u0, u1));
-        t = (lo <= hi) ? T(0.5) * (lo + hi) : (fmax(u0, u1) < T(0) ? T(0) : T(1));
-    } else {
-        s = clamp01((b * f - c * e) / den);
-        t = (b * s + f) / e;
-        if (t < T(0)) {
-            t = T(0);
-            s = clamp01(-c / a);
-        } else if (t > T(1)) {
-            t = T(1);
-            s = clamp01((b - c) / a);
-        }
-    }
-    P = p1 + s * d1;
-    Q = p2 + t * d2;
-    return den;
-}
-
-__device__ inline double wave_sum(double v)
-{
-    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-    return v;
-}
-
 __device__ inline double min_image(double d, double L) { return d - L * rint(d / L); }
 
 __device__ inline unsigned long long lanes_below()
@@ -185,110 +147,157 @@ __device__ inline unsigned long long lanes_below()
     return lane == 0 ? 0ull : (~0ull >> (64 - lane));
 }
 
-constexpr int kWaves = 4;     // waves per block
-constexpr int kQueue = 512;   // survivor queue entries per wave
+constexpr int kWaves = 4;          // waves per block
+constexpr int kGL = 16;            // lanes per particle pair
+constexpr int kGroups = 64 / kGL;  // pairs per wave
+constexpr int kQueue = 128;        // survivor queue entries per pair
+
+// Reciprocal: the hardware FP32 estimate (1 ulp), exact division in FP64.
+__device__ inline float rcp(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ inline double rcp(double x) { return 1.0 / x; }
 
 template <typename T>
-struct WaveLds {
+struct PairLds {
     T vj[DEM_MAX_VERTS][3];   // j's vertices in i's frame
     T vi[DEM_MAX_VERTS][3];   // i's vertices in j's frame
-    int queue[kQueue];
+    // features that can reach the other body (conservative prefilter), by index
+    unsigned char vi_near[DEM_MAX_VERTS], vj_near[DEM_MAX_VERTS];
+    unsigned char ei_near[DEM_MAX_EDGES], ej_near[DEM_MAX_EDGES];
+    unsigned char fi_near[DEM_MAX_FACES], fj_near[DEM_MAX_FACES];
+    unsigned short queue[kQueue];
 };
 
-// One feature-pair problem: nearest points P on i and Q on j, in i's frame,
-// returned as P and rho = P - Q.
+// Closest points of segments p1 + s d1 and p2 + t d2 (s, t in [0,1]) with
+// a = |d1|^2, e = |d2|^2 and their reciprocals ia, ie given.
+// Non-parallel: the clamped line solution (Ericson, Real-Time Collision
+// Detection, 2005, Sec. 5.1.9) with the cross-product form of its
+// denominator.  Nearly parallel (|d1 x d2|^2 < par_s2 a e): each point is
+// the midpoint of its segment's overlap with the other segment's
+// projection, or the facing endpoint.  Returns |d1 x d2|^2.
+template <typename T>
+__device__ inline T seg_seg(V3<T> p1, V3<T> d1, T a, T ia, V3<T> p2, V3<T> d2, T e, T ie, T par_s2, V3<T> &P,
+                            V3<T> &Q)
+{
+    const V3<T> r = p1 - p2;
+    const T b = dot(d1, d2), c = dot(d1, r), f = dot(d2, r);
+    const V3<T> cr = cross(d1, d2);
+    const T den = dot(cr, cr);
+    T s, t;
+    if (den < par_s2 * a * e) {
+        const T t0 = -c * ia, t1 = (b - c) * ia;
+        T lo = fmax(T(0), fmin(t0, t1)), hi = fmin(T(1), fmax(t0, t1));
+        s = (lo <= hi) ? T(0.5) * (lo + hi) : (fmax(t0, t1) < T(0) ? T(0) : T(1));
+        const T u0 = f * ie, u1 = (f + b) * ie;
+        lo = fmax(T(0), fmin(u0, u1));
+        hi = fmin(T(1), fmax(u0, u1));
+        t = (lo <= hi) ? T(0.5) * (lo + hi) : (fmax(u0, u1) < T(0) ? T(0) : T(1));
+    } else {
+        s = clamp01((b * f - c * e) * rcp(den));
+        t = (b * s + f) * ie;
+        if (t < T(0)) {
+            t = T(0);
+            s = clamp01(-c * ia);
+        } else if (t > T(1)) {
+            t = T(1);
+            s = clamp01((b - c) * ia);
+        }
+    }
+    P = p1 + s * d1;
+    Q = p2 + t * d2;
+    return den;
+}
+
+// The feature-pair problems of one particle pair, restricted to the
+// features that passed the prefilter: family A pairs near vertices of i
+// with near faces (2D: edges) of j, family B near vertices of j with near
+// faces (edges) of i, family C near edges of i with near edges of j (3D).
+// Problem q decodes to list positions by an exact small division.
 template <typename T, int DIM>
 struct Problem {
     const ShapeTab<T> &Si, &Sj;
-    const WaveLds<T> &W;
+    const PairLds<T> &W;
     const M3<T> &Rr;
     V3<T> t;
     int nA, nB;
-    float inv_nfj, inv_nfi, inv_nej;
+    int nfj, nfi, nej;            // list lengths used as divisors
+    float inv_fj, inv_fi, inv_ej;
+
+    __device__ void decode(int q, int &fam, int &x, int &y) const
+    {
+        if (q < nA) {
+            const int ax = qdiv(q, inv_fj);
+            fam = 0;
+            x = W.vi_near[ax];
+            y = (DIM == 3) ? W.fj_near[q - ax * nfj] : W.ej_near[q - ax * nfj];
+        } else if (q < nA + nB) {
+            const int qq = q - nA, bx = qdiv(qq, inv_fi);
+            fam = 1;
+            x = W.vj_near[bx];
+            y = (DIM == 3) ? W.fi_near[qq - bx * nfi] : W.ei_near[qq - bx * nfi];
+        } else {
+            const int qq = q - nA - nB, ex = qdiv(qq, inv_ej);
+            fam = 2;
+            x = W.ei_near[ex];
+            y = W.ej_near[qq - ex * nej];
+        }
+    }
 
     // conservative cull: false if no point of the two features can be within rc
     __device__ bool candidate(int q, T rc) const
     {
+        int fam, x, y;
+        decode(q, fam, x, y);
         if (DIM == 3) {
-            if (q < nA) {  // vertex a of i against face f of j, in j's frame
-                const int a = qdiv(q, inv_nfj), f = q - a * Sj.nf;
-                const V3<T> p = ld3(W.vi[a]);
-                const T sd = dot(ld3(Sj.fn[f]), p) - Sj.fo[f];
-                const V3<T> dc = p - ld3(Sj.fc[f]);
-                const T lim = Sj.frad[f] + rc;
+            if (fam < 2) {  // vertex against face, in the face owner's frame
+                const ShapeTab<T> &S = fam == 0 ? Sj : Si;
+                const V3<T> pt = fam == 0 ? ld3(W.vi[x]) : ld3(W.vj[x]);
+                const T sd = dot(ld3(S.fn[y]), pt) - S.fo[y];
+                const V3<T> dc = pt - ld3(S.fc[y]);
+                const T lim = S.frad[y] + rc;
                 return fabs(sd) < rc && dot(dc, dc) < lim * lim;
-            } else if (q < nA + nB) {  // vertex b of j against face f of i, in i's frame
-                const int qq = q - nA, b = qdiv(qq, inv_nfi), f = qq - b * Si.nf;
-                const V3<T> p = ld3(W.vj[b]);
-                const T sd = dot(ld3(Si.fn[f]), p) - Si.fo[f];
-                const V3<T> dc = p - ld3(Si.fc[f]);
-                const T lim = Si.frad[f] + rc;
-                return fabs(sd) < rc && dot(dc, dc) < lim * lim;
-            } else {  // edge e of i against edge g of j: bounding spheres of the two segments
-                const int qq = q - nA - nB, e = qdiv(qq, inv_nej), g = qq - e * Sj.ne;
-                const V3<T> mj = T(0.5) * (ld3(W.vj[Sj.e[g][0]]) + ld3(W.vj[Sj.e[g][1]]));
-                const V3<T> dm = ld3(Si.em[e]) - mj;
-                const T lim = Si.eh[e] + Sj.eh[g] + rc;
-                return dot(dm, dm) < lim * lim;
             }
-        } else {
-            if (q < nA) {  // vertex a of i against edge e of j, in j's frame
-                const int a = qdiv(q, inv_nej), e = q - a * Sj.ne;
-                const V3<T> dm = ld3(W.vi[a]) - ld3(Sj.em[e]);
-                const T lim = Sj.eh[e] + rc;
-                return dot(dm, dm) < lim * lim;
-            } else {  // vertex b of j against edge e of i, in i's frame
-                const int qq = q - nA, b = qdiv(qq, inv_nfi), e = qq - b * Si.ne;
-                const V3<T> dm = ld3(W.vj[b]) - ld3(Si.em[e]);
-                const T lim = Si.eh[e] + rc;
-                return dot(dm, dm) < lim * lim;
-            }
+            // edge against edge: bounding spheres of the two segments
+            const V3<T> mj = T(0.5) * (ld3(W.vj[Sj.e[y][0]]) + ld3(W.vj[Sj.e[y][1]]));
+            const V3<T> dm = ld3(Si.em[x]) - mj;
+            const T lim = Si.eh[x] + Sj.eh[y] + rc;
+            return dot(dm, dm) < lim * lim;
+        } else {  // vertex against edge, in the edge owner's frame
+            const ShapeTab<T> &S = fam == 0 ? Sj : Si;
+            const V3<T> dm = (fam == 0 ? ld3(W.vi[x]) : ld3(W.vj[x])) - ld3(S.em[y]);
+            const T lim = S.eh[y] + rc;
+            return dot(dm, dm) < lim * lim;
         }
     }
 
-    // exact nearest points; returns the family (0: V_i-F_j / V_i-E_j, 1: V_j-F_i / V_j-E_i, 2: E_i-E_j)
-    __device__ int solve(int q, T par_s2, V3<T> &P, V3<T> &rho, T &den) const
+    // exact nearest points: P on i and rho = P - Q, in i's frame; for edge
+    // pairs also sin^2 of their angle (1 otherwise)
+    __device__ int solve(int q, T par_s2, V3<T> &P, V3<T> &rho, T &sin2, int &ex, int &ey) const
     {
-        den = T(1);
-        if (DIM == 3) {
-            if (q < nA) {
-                const int a = qdiv(q, inv_nfj), f = q - a * Sj.nf;
-                const V3<T> p = ld3(W.vi[a]);
-                P = ld3(Si.v[a]);
-                rho = mul(Rr, p - face_point(Sj, f, p));  // offset formed in j's frame, then rotated
-                return 0;
-            } else if (q < nA + nB) {
-                const int qq = q - nA, b = qdiv(qq, inv_nfi), f = qq - b * Si.nf;
-                const V3<T> p = ld3(W.vj[b]);
-                P = face_point(Si, f, p);
-                rho = P - p;
-                return 1;
-            } else {
-                const int qq = q - nA - nB, e = qdiv(qq, inv_nej), g = qq - e * Sj.ne;
-                const V3<T> b0 = ld3(W.vj[Sj.e[g][0]]);
-                const V3<T> d2 = ld3(W.vj[Sj.e[g][1]]) - b0;
-                const T ee = T(1) / Sj.einv[g];
-                V3<T> Q;
-                den = seg_seg(ld3(Si.v[Si.e[e][0]]), ld3(Si.ed[e]), T(1) / Si.einv[e], b0, d2, ee, par_s2, P, Q) /
-                      ((T(1) / Si.einv[e]) * ee);
-                rho = P - Q;
-                return 2;
-            }
+        int fam, x, y;
+        decode(q, fam, x, y);
+        ex = x;
+        ey = y;
+        sin2 = T(1);
+        if (fam == 0) {
+            const V3<T> pt = ld3(W.vi[x]);
+            P = ld3(Si.v[x]);
+            const V3<T> qj = (DIM == 3) ? face_point(Sj, y, pt)
+                                        : seg_point(pt, ld3(Sj.v[Sj.e[y][0]]), ld3(Sj.ed[y]), Sj.einv[y]);
+            rho = mul(Rr, pt - qj);  // offset formed in j's frame, then rotated
+        } else if (fam == 1) {
+            const V3<T> pt = ld3(W.vj[x]);
+            P = (DIM == 3) ? face_point(Si, y, pt) : seg_point(pt, ld3(Si.v[Si.e[y][0]]), ld3(Si.ed[y]), Si.einv[y]);
+            rho = P - pt;
         } else {
-            if (q < nA) {
-                const int a = qdiv(q, inv_nej), e = q - a * Sj.ne;
-                const V3<T> p = ld3(W.vi[a]);
-                P = ld3(Si.v[a]);
-                rho = mul(Rr, p - seg_point(p, ld3(Sj.v[Sj.e[e][0]]), ld3(Sj.ed[e]), Sj.einv[e]));
-                return 0;
-            } else {
-                const int qq = q - nA, b = qdiv(qq, inv_nfi), e = qq - b * Si.ne;
-                const V3<T> p = ld3(W.vj[b]);
-                P = seg_point(p, ld3(Si.v[Si.e[e][0]]), ld3(Si.ed[e]), Si.einv[e]);
-                rho = P - p;
-                return 1;
-            }
+            const V3<T> b0 = ld3(W.vj[Sj.e[y][0]]);
+            const V3<T> d2 = ld3(W.vj[Sj.e[y][1]]) - b0;
+            V3<T> Q;
+            const T den = seg_seg(ld3(Si.v[Si.e[x][0]]), ld3(Si.ed[x]), Si.el2[x], Si.einv[x], b0, d2, Sj.el2[y],
+                                  Sj.einv[y], par_s2, P, Q);
+            sin2 = den * Si.einv[x] * Sj.einv[y];
+            rho = P - Q;
         }
+        return fam;
     }
 };
 
@@ -304,7 +313,7 @@ __device__ inline int add_wca(Acc<T> &A, V3<T> P, V3<T> rho, V3<T> t, T sig2, T 
 {
     const T r2 = dot(rho, rho);
     if (!(r2 < rc2)) return 0;
-    const T ir2 = T(1) / r2;
+    const T ir2 = rcp(r2);
     const T s2 = sig2 * ir2;
     const T s6 = s2 * s2 * s2;
     const T h = T(2) * s6 - T(1);
@@ -324,6 +333,56 @@ __device__ inline void load_rot(const T *rot, int n, int i, M3<T> &R)
     for (int k = 0; k < 9; ++k) R.m[k] = rot[(size_t)k * n + i];
 }
 
+template <typename T>
+__device__ inline T group_sum(T v)
+{
+    for (int off = kGL / 2; off > 0; off >>= 1) v += __shfl_xor(v, off, kGL);
+    return v;
+}
+
+__device__ inline void wave_sync_lds()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Appends this lane's item to its group's list when keep is set; returns
+// the group's new length.  All 64 lanes must call it together.
+__device__ inline int group_append(bool keep, unsigned char *list, int len, int item, unsigned long long gmask,
+                                   unsigned long long below)
+{
+    const unsigned long long m = __ballot(keep);
+    if (keep) list[len + __popcll(m & below & gmask)] = (unsigned char)item;
+    return len + __popcll(m & gmask);
+}
+
+// FP64 redo of an FP32 edge-edge problem whose closest points are
+// ill-conditioned (nearly parallel edges near the cutoff).
+template <typename T>
+__device__ void refine_edges(const SysParams &p, const StatePtrs &s, int i, int j, const ShapeTab<double> &Di,
+                             const ShapeTab<double> &Dj, int e, int g, V3<T> &Pt, V3<T> &rho)
+{
+    double Rd[9], Rjd[9];
+    quat_to_rot(s.qw[i], s.qx[i], s.qy[i], s.qz[i], Rd);
+    quat_to_rot(s.qw[j], s.qx[j], s.qy[j], s.qz[j], Rjd);
+    M3<double> Rrd, Rid;
+    for (int a = 0; a < 3; ++a)
+        for (int b = 0; b < 3; ++b)
+            Rrd.m[3 * a + b] = Rd[a] * Rjd[b] + Rd[3 + a] * Rjd[3 + b] + Rd[6 + a] * Rjd[6 + b];
+    for (int k = 0; k < 9; ++k) Rid.m[k] = Rd[k];
+    const V3<double> dd = v3<double>(min_image(s.x[j] - s.x[i], p.box[0]), min_image(s.y[j] - s.y[i], p.box[1]),
+                                     min_image(s.z[j] - s.z[i], p.box[2]));
+    const V3<double> td = mulT(Rid, dd);
+    const V3<double> b0 = td + mul(Rrd, ld3(Dj.v[Dj.e[g][0]]));
+    const V3<double> d2 = mul(Rrd, ld3(Dj.ed[g]));
+    V3<double> Pd, Qd;
+    seg_seg(ld3(Di.v[Di.e[e][0]]), ld3(Di.ed[e]), Di.el2[e], Di.einv[e], b0, d2, Dj.el2[g], Dj.einv[g], p.par_s2,
+            Pd, Qd);
+    Pt = cvt<T>(Pd);
+    rho = cvt<T>(Pd - Qd);
+}
+
 template <typename T, int DIM>
 __global__ void __launch_bounds__(64 * kWaves) k_pairs(SysParams p, StatePtrs s, ListPtrs l, const T *__restrict__ rot,
                                                           T *__restrict__ rec, const ShapeTab<T> *__restrict__ gtab,
@@ -332,7 +391,7 @@ __global__ void __launch_bounds__(64 * kWaves) k_pairs(SysParams p, StatePtrs s,
 {
     extern __shared__ __align__(16) unsigned char smem[];
     ShapeTab<T> *tab = reinterpret_cast<ShapeTab<T> *>(smem);
-    WaveLds<T> *wl = reinterpret_cast<WaveLds<T> *>(smem + p.n_shapes * sizeof(ShapeTab<T>));
+    PairLds<T> *pls = reinterpret_cast<PairLds<T> *>(smem + p.n_shapes * sizeof(ShapeTab<T>));
     {
         const int words = p.n_shapes * (int)(sizeof(ShapeTab<T>) / 4);
         const uint32_t *src = reinterpret_cast<const uint32_t *>(gtab);
@@ -343,7 +402,10 @@ __global__ void __launch_bounds__(64 * kWaves) k_pairs(SysParams p, StatePtrs s,
 
     const int lane = __lane_id();
     const int wid = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    WaveLds<T> &W = wl[wid];
+    const int grp = lane / kGL, sub = lane % kGL;
+    PairLds<T> &W = pls[wid * kGroups + grp];
+    const unsigned long long gmask = 0xffffull << (kGL * grp);
+    const unsigned long long below = lanes_below();
     const int n = p.n;
     const int npairs = l.flags[FLAG_NPAIRS];
     // XCD-aware order: blocks are dealt round-robin to the 8 XCDs, so give
@@ -351,32 +413,40 @@ __global__ void __launch_bounds__(64 * kWaves) k_pairs(SysParams p, StatePtrs s,
     // share one L2).
     const int G = gridDim.x;
     const int xcd = blockIdx.x & 7, slot = blockIdx.x >> 3;
-    const int per_xcd = (G + 7 - xcd) >> 3;  // blocks on this XCD
     int first_xcd_block = 0;
     for (int x = 0; x < xcd; ++x) first_xcd_block += (G + 7 - x) >> 3;
     const int vblock = first_xcd_block + slot;  // virtual block index, contiguous per XCD
-    (void)per_xcd;
     const T par_s2 = (T)p.par_s2;
     const T eps = (T)p.eps;
+    const T grow = T(1.00001);
     unsigned long long c_pairs = 0, c_feat = 0, c_in = 0, c_near = 0, c_ee = 0, c_ref = 0;
 
-    for (int pr = vblock * kWaves + wid; pr < npairs; pr += G * kWaves) {
-        const int i = l.pi[pr], j = l.pj[pr];
-        T *out = rec + (size_t)pr * kRec;
-        const double dx = min_image(s.x[j] - s.x[i], p.box[0]);
-        const double dy = min_image(s.y[j] - s.y[i], p.box[1]);
-        const double dz = (DIM == 3) ? min_image(s.z[j] - s.z[i], p.box[2]) : 0.0;
-        const int si = s.sid[i], sj = s.sid[j];
-        const double bound = p.R[si] + p.R[sj] + kWcaCut * (p.rad[si] + p.rad[sj]);
-        if (dx * dx + dy * dy + dz * dz >= bound * bound) {
-            if (lane < kRec) out[lane] = T(0);
-            continue;
+    for (int base = (vblock * kWaves + wid) * kGroups; base < npairs; base += G * kWaves * kGroups) {
+        const int pr = base + grp;
+        const bool active = pr < npairs;
+        int i = 0, j = 0, si = 0, sj = 0;
+        double dx = 0.0, dy = 0.0, dz = 0.0;
+        bool live = false;
+        if (active) {
+            i = l.pi[pr];
+            j = l.pj[pr];
+            dx = min_image(s.x[j] - s.x[i], p.box[0]);
+            dy = min_image(s.y[j] - s.y[i], p.box[1]);
+            dz = (DIM == 3) ? min_image(s.z[j] - s.z[i], p.box[2]) : 0.0;
+            si = s.sid[i];
+            sj = s.sid[j];
+            const double bound = p.R[si] + p.R[sj] + kWcaCut * (p.rad[si] + p.rad[sj]);
+            live = dx * dx + dy * dy + dz * dz < bound * bound;
+            if (!live && sub < kRec) rec[(size_t)pr * kRec + sub] = T(0);
         }
+        if (__ballot(live) == 0) continue;
         const ShapeTab<T> &Si = tab[si];
         const ShapeTab<T> &Sj = tab[sj];
         M3<T> Rr;
-        V3<T> t;
-        {
+        V3<T> t = v3<T>(0, 0, 0);
+        T sig2 = T(0), rc = T(0), Bi = T(0), Bj = T(0);
+        for (int k = 0; k < 9; ++k) Rr.m[k] = T(0);
+        if (live) {
             M3<T> Ri, Rj;
             load_rot(rot, n, i, Ri);
             load_rot(rot, n, j, Rj);
@@ -384,128 +454,171 @@ __global__ void __launch_bounds__(64 * kWaves) k_pairs(SysParams p, StatePtrs s,
                 for (int b = 0; b < 3; ++b)
                     Rr.m[3 * a + b] = Ri.m[a] * Rj.m[b] + Ri.m[3 + a] * Rj.m[3 + b] + Ri.m[6 + a] * Rj.m[6 + b];
             t = mulT(Ri, v3<T>((T)dx, (T)dy, (T)dz));
+            const double sigd = p.rad[si] + p.rad[sj];
+            sig2 = (T)(sigd * sigd);
+            rc = (T)(kWcaCut * sigd);
+            Bi = (T)p.R[si] + rc;
+            Bj = (T)p.R[sj] + rc;
         }
-        const double sigd = p.rad[si] + p.rad[sj];
-        const T sig2 = (T)(sigd * sigd);
-        const T rc = (T)(kWcaCut * sigd);
         const T rc2 = rc * rc;
 
-        // vertex sets across frames, one lane per vertex
-        if (lane < Sj.nv) {
-            const V3<T> v = t + mul(Rr, ld3(Sj.v[lane]));
-            W.vj[lane][0] = v.x;
-            W.vj[lane][1] = v.y;
-            W.vj[lane][2] = v.z;
-        } else if (lane >= 32 && lane - 32 < Si.nv) {
-            const V3<T> v = mulT(Rr, ld3(Si.v[lane - 32]) - t);
-            W.vi[lane - 32][0] = v.x;
-            W.vi[lane - 32][1] = v.y;
-            W.vi[lane - 32][2] = v.z;
+        // Feature prefilter (conservative): a vertex, edge or face can touch
+        // the other body only if it lies within R_other + r_cut of that body's
+        // centre, widened by the edge half length or the face's bounding
+        // radius.  One lane per feature; survivors are listed by index.
+        bool nj = false, ni = false;
+        if (live && sub < Sj.nv) {
+            const V3<T> v = t + mul(Rr, ld3(Sj.v[sub]));
+            W.vj[sub][0] = v.x;
+            W.vj[sub][1] = v.y;
+            W.vj[sub][2] = v.z;
+            nj = dot(v, v) < grow * Bi * Bi;
         }
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        if (live && sub < Si.nv) {
+            const V3<T> v = mulT(Rr, ld3(Si.v[sub]) - t);
+            W.vi[sub][0] = v.x;
+            W.vi[sub][1] = v.y;
+            W.vi[sub][2] = v.z;
+            ni = dot(v, v) < grow * Bj * Bj;
+        }
+        const int cvj = group_append(nj, W.vj_near, 0, sub, gmask, below);
+        const int cvi = group_append(ni, W.vi_near, 0, sub, gmask, below);
+        wave_sync_lds();
+        int cei = 0, cej = 0;
+        for (int e0 = 0; e0 < DEM_MAX_EDGES; e0 += kGL) {
+            const int e = e0 + sub;
+            bool ne = false, me = false;
+            if (live && e < Si.ne) {
+                const V3<T> d = ld3(Si.em[e]) - t;
+                const T lim = Bj + Si.eh[e];
+                ne = dot(d, d) < grow * lim * lim;
+            }
+            if (live && e < Sj.ne) {
+                const V3<T> m = T(0.5) * (ld3(W.vj[Sj.e[e][0]]) + ld3(W.vj[Sj.e[e][1]]));
+                const T lim = Bi + Sj.eh[e];
+                me = dot(m, m) < grow * lim * lim;
+            }
+            cei = group_append(ne, W.ei_near, cei, e, gmask, below);
+            cej = group_append(me, W.ej_near, cej, e, gmask, below);
+            if (__ballot(live && (e0 + kGL < Si.ne || e0 + kGL < Sj.ne)) == 0) break;
+        }
+        int cfi = 0, cfj = 0;
+        if (DIM == 3) {
+            const V3<T> ti = -(T)1 * mulT(Rr, t);  // i's centre in j's frame
+            for (int f0 = 0; f0 < DEM_MAX_FACES; f0 += kGL) {
+                const int f = f0 + sub;
+                bool nf = false, mf = false;
+                if (live && f < Si.nf) {
+                    const V3<T> d = ld3(Si.fc[f]) - t;
+                    const T lim = Bj + Si.frad[f];
+                    nf = dot(d, d) < grow * lim * lim;
+                }
+                if (live && f < Sj.nf) {
+                    const V3<T> d = ld3(Sj.fc[f]) - ti;
+                    const T lim = Bi + Sj.frad[f];
+                    mf = dot(d, d) < grow * lim * lim;
+                }
+                cfi = group_append(nf, W.fi_near, cfi, f, gmask, below);
+                cfj = group_append(mf, W.fj_near, cfj, f, gmask, below);
+                if (__ballot(live && (f0 + kGL < Si.nf || f0 + kGL < Sj.nf)) == 0) break;
+            }
+        }
+        wave_sync_lds();
 
-        Problem<T, DIM> P{Si, Sj, W, Rr, t, 0, 0, 0.f, 0.f, 0.f};
+        Problem<T, DIM> P{Si, Sj, W, Rr, t, 0, 0, 1, 1, 1, 1.f, 1.f, 1.f};
         int total;
         if (DIM == 3) {
-            P.nA = Si.nv * Sj.nf;
-            P.nB = Sj.nv * Si.nf;
-            total = P.nA + P.nB + Si.ne * Sj.ne;
-            P.inv_nfj = 1.0f / (float)Sj.nf;
-            P.inv_nfi = 1.0f / (float)Si.nf;
+            P.nA = cvi * cfj;
+            P.nB = cvj * cfi;
+            total = P.nA + P.nB + cei * cej;
+            P.nfj = cfj;
+            P.nfi = cfi;
         } else {
-            P.nA = Si.nv * Sj.ne;
-            P.nB = Sj.nv * Si.ne;
+            P.nA = cvi * cej;
+            P.nB = cvj * cei;
             total = P.nA + P.nB;
-            P.inv_nfi = 1.0f / (float)Si.ne;
+            P.nfj = cej;
+            P.nfi = cei;
         }
-        P.inv_nej = 1.0f / (float)Sj.ne;
-        c_pairs += 1;
-        c_feat += total;
+        P.nej = cej;
+        P.inv_fj = 1.0f / (float)(P.nfj > 0 ? P.nfj : 1);
+        P.inv_fi = 1.0f / (float)(P.nfi > 0 ? P.nfi : 1);
+        P.inv_ej = 1.0f / (float)(P.nej > 0 ? P.nej : 1);
+        if (!live) total = 0;
+        if (sub == 0 && live) {
+            c_pairs += 1;
+            c_feat += total;
+        }
 
         Acc<T> A;
         A.F = A.Ti = A.Tj = v3<T>(0, 0, 0);
         A.U = T(0);
         int count = 0;
-        for (int base = 0; base < total; base += 64) {
-            const int q = base + lane;
-            const bool keep = q < total && P.candidate(q, rc);
-            const unsigned long long m = __ballot(keep);
-            if (keep) W.queue[count + __popcll(m & lanes_below())] = q;
-            count += __popcll(m);
-            if (count > kQueue - 64 || base + 64 >= total) {
-                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-                __builtin_amdgcn_wave_barrier();
-                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-                for (int k = lane; k < count; k += 64) {
-                    const int qq = W.queue[k];
-                    V3<T> Pt, rho;
-                    T den;
-                    const int fam = P.solve(qq, par_s2, Pt, rho, den);
-                    c_near += fam < 2 ? 1 : 0;
-                    c_ee += fam == 2 ? 1 : 0;
-                    if (sizeof(T) == 4 && DIM == 3 && fam == 2 && den < T(1e-2) &&
-                        dot(rho, rho) < T(1.0001) * rc2 + T(1e-3) * rc) {
-                        // ill-conditioned in FP32: redo this edge pair in FP64 from FP64 geometry
-                        const int q3 = qq - P.nA - P.nB, e = qdiv(q3, P.inv_nej), g = q3 - e * Sj.ne;
-                        double Rd[9], Rjd[9];
-                        quat_to_rot(s.qw[i], s.qx[i], s.qy[i], s.qz[i], Rd);
-                        quat_to_rot(s.qw[j], s.qx[j], s.qy[j], s.qz[j], Rjd);
-                        M3<double> Rrd;
-                        for (int a = 0; a < 3; ++a)
-                            for (int b = 0; b < 3; ++b)
-                                Rrd.m[3 * a + b] = Rd[a] * Rjd[b] + Rd[3 + a] * Rjd[3 + b] + Rd[6 + a] * Rjd[6 + b];
-                        M3<double> Rid;
-                        for (int k9 = 0; k9 < 9; ++k9) Rid.m[k9] = Rd[k9];
-                        const V3<double> dd = v3<double>(min_image(s.x[j] - s.x[i], p.box[0]),
-                                                         min_image(s.y[j] - s.y[i], p.box[1]),
-                                                         min_image(s.z[j] - s.z[i], p.box[2]));
-                        const V3<double> td = mulT(Rid, dd);
-                        const ShapeTab<double> &Di = gtab64[si];
-                        const ShapeTab<double> &Dj = gtab64[sj];
-                        const V3<double> b0 = td + mul(Rrd, ld3(Dj.v[Dj.e[g][0]]));
-                        const V3<double> d2 = mul(Rrd, ld3(Dj.ed[g]));
-                        V3<double> Pd, Qd;
-                        seg_seg(ld3(Di.v[Di.e[e][0]]), ld3(Di.ed[e]), 1.0 / Di.einv[e], b0, d2, 1.0 / Dj.einv[g],
-                                p.par_s2, Pd, Qd);
-                        Pt = cvt<T>(Pd);
-                        rho = cvt<T>(Pd - Qd);
-                        c_ref += 1;
+        for (int qb = 0;; qb += kGL) {
+            const int q = qb + sub;
+            const bool has = q < total;
+            const bool last = __ballot(has) == 0;
+            if (!last) {
+                const bool keep = has && P.candidate(q, rc);
+                const unsigned long long m = __ballot(keep);
+                if (keep) W.queue[count + __popcll(m & below & gmask)] = (unsigned short)q;
+                count += __popcll(m & gmask);
+            }
+            if (last || __ballot(count > kQueue - kGL) != 0) {
+                wave_sync_lds();
+                for (int k = sub;; k += kGL) {
+                    const bool w = k < count;
+                    if (__ballot(w) == 0) break;
+                    if (w) {
+                        V3<T> Pt, rho;
+                        T sin2;
+                        int e, g;
+                        const int fam = P.solve(W.queue[k], par_s2, Pt, rho, sin2, e, g);
+                        c_near += fam < 2 ? 1 : 0;
+                        c_ee += fam == 2 ? 1 : 0;
+                        if (sizeof(T) == 4 && DIM == 3 && fam == 2 && sin2 < T(1e-2) &&
+                            dot(rho, rho) < T(1.0001) * rc2 + T(1e-3) * rc) {
+                            refine_edges(p, s, i, j, gtab64[si], gtab64[sj], e, g, Pt, rho);
+                            c_ref += 1;
+                        }
+                        c_in += add_wca(A, Pt, rho, t, sig2, rc2, eps);
                     }
-                    c_in += add_wca(A, Pt, rho, t, sig2, rc2, eps);
                 }
                 count = 0;
-                __builtin_amdgcn_wave_barrier();
+                wave_sync_lds();
             }
+            if (last) break;
         }
-        // reduce in FP64; lane 0 rotates to the space frame and writes the record
-        double F[3] = {wave_sum((double)A.F.x), wave_sum((double)A.F.y), wave_sum((double)A.F.z)};
-        double Ti[3] = {wave_sum((double)A.Ti.x), wave_sum((double)A.Ti.y), wave_sum((double)A.Ti.z)};
-        double Tj[3] = {wave_sum((double)A.Tj.x), wave_sum((double)A.Tj.y), wave_sum((double)A.Tj.z)};
-        const double U = wave_sum((double)A.U);
-        if (lane == 0) {
+        // group reduction; the group's first lane rotates to the space frame and writes the record
+        const T F0 = group_sum(A.F.x), F1 = group_sum(A.F.y), F2 = group_sum(A.F.z);
+        const T I0 = group_sum(A.Ti.x), I1 = group_sum(A.Ti.y), I2 = group_sum(A.Ti.z);
+        const T J0 = group_sum(A.Tj.x), J1 = group_sum(A.Tj.y), J2 = group_sum(A.Tj.z);
+        const T U = group_sum(A.U);
+        if (live && sub == 0) {
             M3<T> Ri;
             load_rot(rot, n, i, Ri);
+            T *out = rec + (size_t)pr * kRec;
             for (int a = 0; a < 3; ++a) {
-                out[a] = (T)(Ri.m[3 * a] * F[0] + Ri.m[3 * a + 1] * F[1] + Ri.m[3 * a + 2] * F[2]);
-                out[3 + a] = (T)(Ri.m[3 * a] * Ti[0] + Ri.m[3 * a + 1] * Ti[1] + Ri.m[3 * a + 2] * Ti[2]);
-                out[6 + a] = (T)(Ri.m[3 * a] * Tj[0] + Ri.m[3 * a + 1] * Tj[1] + Ri.m[3 * a + 2] * Tj[2]);
+                out[a] = Ri.m[3 * a] * F0 + Ri.m[3 * a + 1] * F1 + Ri.m[3 * a + 2] * F2;
+                out[3 + a] = Ri.m[3 * a] * I0 + Ri.m[3 * a + 1] * I1 + Ri.m[3 * a + 2] * I2;
+                out[6 + a] = Ri.m[3 * a] * J0 + Ri.m[3 * a + 1] * J1 + Ri.m[3 * a + 2] * J2;
             }
-            out[9] = (T)U;
+            out[9] = U;
         }
     }
     if (stats) {
-        unsigned long long in_w = c_in, near_w = c_near, ee_w = c_ee, ref_w = c_ref;
+        unsigned long long in_w = c_in, near_w = c_near, ee_w = c_ee, ref_w = c_ref, pr_w = c_pairs, ft_w = c_feat;
         for (int off = 32; off > 0; off >>= 1) {
             in_w += __shfl_xor(in_w, off, 64);
             near_w += __shfl_xor(near_w, off, 64);
             ee_w += __shfl_xor(ee_w, off, 64);
             ref_w += __shfl_xor(ref_w, off, 64);
+            pr_w += __shfl_xor(pr_w, off, 64);
+            ft_w += __shfl_xor(ft_w, off, 64);
         }
         if (lane == 0) {
-            atomicAdd(&stats[ST_PAIRS], c_pairs);
-            atomicAdd(&stats[ST_FEATURES], c_feat);
+            atomicAdd(&stats[ST_PAIRS], pr_w);
+            atomicAdd(&stats[ST_FEATURES], ft_w);
             atomicAdd(&stats[ST_INCUT], in_w);
             atomicAdd(&stats[ST_NEAR], near_w);
             atomicAdd(&stats[ST_REFINED], ref_w);
@@ -539,25 +652,46 @@ __device__ inline double block_sum(double v, double *sh)
     return r;
 }
 
-// Per-particle sums of the pair records in row order; optional closing kick.
+// Nose-Hoover half step of length dt/2 on xi and eta (one variable for
+// translation and rotation); returns the velocity scale and updates K.
+__device__ inline double nh_half(const SysParams &p, double &xi, double &eta, double &K)
+{
+    const double h = 0.5 * p.dt;
+    xi += 0.5 * h * (2.0 * K - p.g * p.kT) / p.Qm;
+    const double sc = exp(-xi * h);
+    K *= sc * sc;
+    eta += xi * h;
+    xi += 0.5 * h * (2.0 * K - p.g * p.kT) / p.Qm;
+    return sc;
+}
+
+// Per-particle sums of the pair records, optionally fused with the closing
+// kick.  Each particle gets kGatherLanes lanes: lane l sums row slots
+// k = l, l + 8, ... in order, then a butterfly over the 8 lanes combines
+// them, so the result does not depend on scheduling.  With NVT the block's
+// kinetic partial is published and the last block to finish (ticket
+// counter, no waiting) applies the step's closing Nose-Hoover half step and
+// the next step's opening one.
 template <typename T, int DIM, bool KICK, bool NVT>
 __global__ void __launch_bounds__(kBlock) k_gather(SysParams p, StatePtrs s, OutPtrs o, ListPtrs l,
                                                       const T *__restrict__ rec, double *ke_part, double *th)
 {
     __shared__ double sh[kBlock];
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i == 0 && l.flags[FLAG_REBUILD] != 0) {
+    __shared__ int last;
+    const int sub = threadIdx.x % kGatherLanes;
+    const int i = blockIdx.x * kGatherPer + threadIdx.x / kGatherLanes;
+    if (blockIdx.x == 0 && threadIdx.x == 0 && l.flags[FLAG_REBUILD] != 0) {
         // the lists consumed by this step are fresh: count the build and clear the trigger
         l.flags[FLAG_REBUILD] = 0;
         l.flags[FLAG_NBUILDS] += 1;
     }
-    double kt = 0.0, kr = 0.0;
-    if (i < p.n) {
-        const int n = p.n;
-        double F[3] = {0, 0, 0}, Tq[3] = {0, 0, 0}, U = 0.0, Wm[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+    const int n = p.n;
+    double acc[16];
+    for (int c = 0; c < 16; ++c) acc[c] = 0.0;  // F[3], T[3], U, W[9]
+    if (i < n) {
         const double xi = s.x[i], yi = s.y[i], zi = (DIM == 3) ? s.z[i] : 0.0;
         const int m = l.n_nbr[i];
-        for (int k = 0; k < m; ++k) {
+        for (int k = sub; k < m; k += kGatherLanes) {
             const int j = l.nbr[(size_t)k * n + i];
             const int q = l.pidx[(size_t)k * n + i];
             if (q < 0) continue;
@@ -566,17 +700,23 @@ __global__ void __launch_bounds__(kBlock) k_gather(SysParams p, StatePtrs s, Out
             const double f[3] = {sg * (double)r[0], sg * (double)r[1], sg * (double)r[2]};
             const int to = (j > i) ? 3 : 6;
             for (int a = 0; a < 3; ++a) {
-                F[a] += f[a];
-                Tq[a] += (double)r[to + a];
+                acc[a] += f[a];
+                acc[3 + a] += (double)r[to + a];
             }
-            U += 0.5 * (double)r[9];
+            acc[6] += 0.5 * (double)r[9];
             if (f[0] != 0.0 || f[1] != 0.0 || f[2] != 0.0) {
                 const double d[3] = {min_image(s.x[j] - xi, p.box[0]), min_image(s.y[j] - yi, p.box[1]),
                                      (DIM == 3) ? min_image(s.z[j] - zi, p.box[2]) : 0.0};
                 for (int a = 0; a < 3; ++a)
-                    for (int b = 0; b < 3; ++b) Wm[3 * a + b] -= 0.5 * d[a] * f[b];
+                    for (int b = 0; b < 3; ++b) acc[7 + 3 * a + b] -= 0.5 * d[a] * f[b];
             }
         }
+    }
+    for (int off = 1; off < kGatherLanes; off <<= 1)
+        for (int c = 0; c < 16; ++c) acc[c] += __shfl_xor(acc[c], off, kGatherLanes);
+    double kt = 0.0, kr = 0.0;
+    if (i < n && sub == 0) {
+        double *F = acc, *Tq = acc + 3;
         if (DIM == 2) {
             F[2] = 0.0;
             Tq[0] = Tq[1] = 0.0;
@@ -587,8 +727,8 @@ __global__ void __launch_bounds__(kBlock) k_gather(SysParams p, StatePtrs s, Out
         o.Tx[i] = Tq[0];
         o.Ty[i] = Tq[1];
         o.Tz[i] = Tq[2];
-        o.U[i] = U;
-        for (int c = 0; c < 9; ++c) o.W[(size_t)c * n + i] = Wm[c];
+        o.U[i] = acc[6];
+        for (int c = 0; c < 9; ++c) o.W[(size_t)c * n + i] = acc[7 + c];
         if (KICK) {
             const int sid = s.sid[i];
             const double hm = 0.5 * p.dt / p.mass[sid];
@@ -625,7 +765,31 @@ __global__ void __launch_bounds__(kBlock) k_gather(SysParams p, StatePtrs s, Out
         if (threadIdx.x == 0) {
             ke_part[2 * blockIdx.x] = kt;
             ke_part[2 * blockIdx.x + 1] = kr;
-            if (blockIdx.x == 0) th[TH_PENDING] = 1.0;
+            __threadfence();
+            const int ticket = atomicAdd(&l.flags[FLAG_TICKET], 1);
+            last = (ticket == (int)gridDim.x - 1);
+        }
+        __syncthreads();
+        if (last) {
+            __threadfence();
+            double acc2 = 0.0;
+            for (int b = threadIdx.x; b < (int)gridDim.x; b += blockDim.x) {
+                const volatile double *vp = ke_part;
+                acc2 += vp[2 * b] + vp[2 * b + 1];
+            }
+            double K = block_sum<kBlock>(acc2, sh);
+            if (threadIdx.x == 0) {
+                double xi = th[TH_XI], eta = th[TH_ETA];
+                const double sb = nh_half(p, xi, eta, K);  // closes this step
+                th[TH_XI_B] = xi;
+                th[TH_ETA_B] = eta;
+                th[TH_SCALE_B] = sb;
+                const double sa = nh_half(p, xi, eta, K);  // opens the next step
+                th[TH_XI] = xi;
+                th[TH_ETA] = eta;
+                th[TH_SCALE] = sb * sa;
+                l.flags[FLAG_TICKET] = 0;
+            }
         }
     }
 }
@@ -644,7 +808,7 @@ template <typename T, int DIM>
 void pairs_t(const SysParams &p, const StatePtrs &s, const ListPtrs &l, const ForcePtrs &f,
              unsigned long long *stats, hipStream_t stream)
 {
-    const size_t sh = (size_t)p.n_shapes * sizeof(ShapeTab<T>) + kWaves * sizeof(WaveLds<T>);
+    const size_t sh = (size_t)p.n_shapes * sizeof(ShapeTab<T>) + kWaves * kGroups * sizeof(PairLds<T>);
     k_pairs<T, DIM><<<p.pair_blocks, 64 * kWaves, sh, stream>>>(
         p, s, l, reinterpret_cast<const T *>(f.rot), reinterpret_cast<T *>(f.rec),
         reinterpret_cast<const ShapeTab<T> *>(f.tab), reinterpret_cast<const ShapeTab<double> *>(f.tab64), stats);
@@ -655,7 +819,7 @@ void gather_t(const SysParams &p, const StatePtrs &s, const OutPtrs &o, const Li
               double *ke_part, double *th, hipStream_t stream)
 {
     const T *rec = reinterpret_cast<const T *>(f.rec);
-    const int nb = blocks_for(p.n);
+    const int nb = gather_blocks(p.n);
     const bool nvt = p.ensemble == DEM_NVT;
     if (!kick)
         k_gather<T, DIM, false, false><<<nb, kBlock, 0, stream>>>(p, s, o, l, rec, ke_part, th);

@@ -12,10 +12,12 @@
 // The Nose-Hoover half step of length h on the single variable xi is
 //   xi += h/2 (2K - g kT)/Q;  (v, L) *= exp(-xi h);  eta += xi h;
 //   xi += h/2 (2K - g kT)/Q,
-// with g = d N + d_rot N - d and Q = g kT tau_T^2.  The half step that ends
-// a step is applied lazily by the next step's first kernel (and by an
-// explicit finishing kernel after the last step of a call), so a captured
-// step needs no extra pass over the particles.
+// with g = d N + d_rot N - d and Q = g kT tau_T^2.  The closing half step
+// of a step and the opening half step of the next are computed together by
+// the last workgroup of the force gather (dem_force.hip); their velocity
+// scale is applied by the next kick-drift, and after the last step of a call
+// k_nh_end and k_scale apply the closing half step alone, so a captured step
+// needs no extra pass over the particles.
 #include "dem_internal.h"
 
 namespace dem {
@@ -98,34 +100,25 @@ __device__ inline double sum_partials(const double *part, int nblk, double *sh)
     return block_sum<kBlock>(acc, sh);
 }
 
-// Start of a step: the pending end-of-step half step (if any), then this
-// step's opening half step.  One block.
+// Opening half step of the first step of a call, from the kinetic partials.
 __global__ void __launch_bounds__(kBlock) k_nh_begin(SysParams p, const double *ke_part, int nblk, double *th)
 {
     __shared__ double sh[kBlock];
     double K = sum_partials(ke_part, nblk, sh);
     if (threadIdx.x != 0) return;
-    double xi = th[TH_XI], eta = th[TH_ETA], sc = 1.0;
-    if (th[TH_PENDING] != 0.0) sc *= nh_half(p, xi, eta, K);
-    sc *= nh_half(p, xi, eta, K);
+    double xi = th[TH_XI], eta = th[TH_ETA];
+    const double sc = nh_half(p, xi, eta, K);
     th[TH_XI] = xi;
     th[TH_ETA] = eta;
     th[TH_SCALE] = sc;
-    th[TH_PENDING] = 0.0;
 }
 
-// After the last step of a call: apply the pending closing half step.
-__global__ void __launch_bounds__(kBlock) k_nh_end(SysParams p, const double *ke_part, int nblk, double *th)
+// After the last step of a call: back to the state after its closing half step.
+__global__ void k_nh_end(double *th)
 {
-    __shared__ double sh[kBlock];
-    double K = sum_partials(ke_part, nblk, sh);
-    if (threadIdx.x != 0) return;
-    double xi = th[TH_XI], eta = th[TH_ETA], sc = 1.0;
-    if (th[TH_PENDING] != 0.0) sc = nh_half(p, xi, eta, K);
-    th[TH_XI] = xi;
-    th[TH_ETA] = eta;
-    th[TH_SCALE] = sc;
-    th[TH_PENDING] = 0.0;
+    th[TH_XI] = th[TH_XI_B];
+    th[TH_ETA] = th[TH_ETA_B];
+    th[TH_SCALE] = th[TH_SCALE_B];
 }
 
 __global__ void k_scale(SysParams p, StatePtrs s, const double *th)
@@ -224,13 +217,14 @@ __global__ void __launch_bounds__(kBlock) k_kick_drift(SysParams p, StatePtrs s,
         atomicOr(&l.flags[FLAG_NONFINITE], 1);
 }
 
-// Per-block kinetic partials of the current state.
+// Per-block kinetic partials of the current state, with the particle-to-
+// block mapping of the gather (kGatherPer particles per block).
 __global__ void __launch_bounds__(kBlock) k_kinetic(SysParams p, StatePtrs s, double *ke_part)
 {
     __shared__ double sh[kBlock];
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int i = blockIdx.x * kGatherPer + threadIdx.x / kGatherLanes;
     double kt = 0.0, kr = 0.0;
-    if (i < p.n) {
+    if (i < p.n && (threadIdx.x % kGatherLanes) == 0) {
         const int sid = s.sid[i];
         const double m = p.mass[sid];
         kt = 0.5 * m * (s.vx[i] * s.vx[i] + s.vy[i] * s.vy[i] + s.vz[i] * s.vz[i]);
@@ -278,7 +272,9 @@ void launch_nh_begin(const SysParams &p, const double *ke_part, int nblk, double
 void launch_nh_end(const SysParams &p, const StatePtrs &s, const double *ke_part, int nblk, double *thermo,
                    hipStream_t stream)
 {
-    k_nh_end<<<1, kBlock, 0, stream>>>(p, ke_part, nblk, thermo);
+    (void)ke_part;
+    (void)nblk;
+    k_nh_end<<<1, 1, 0, stream>>>(thermo);
     if (p.n > 0) k_scale<<<blocks_for(p.n), kBlock, 0, stream>>>(p, s, thermo);
 }
 
@@ -308,7 +304,7 @@ void launch_kick_drift(const SysParams &p, const StatePtrs &s, const OutPtrs &o,
 void launch_kinetic(const SysParams &p, const StatePtrs &s, double *ke_part, hipStream_t stream)
 {
     if (p.n == 0) return;
-    k_kinetic<<<blocks_for(p.n), kBlock, 0, stream>>>(p, s, ke_part);
+    k_kinetic<<<gather_blocks(p.n), kBlock, 0, stream>>>(p, s, ke_part);
 }
 
 void launch_energy_partials(const SysParams &p, const StatePtrs &s, const OutPtrs &o, double *part,

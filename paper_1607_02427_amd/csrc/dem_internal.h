@@ -14,9 +14,13 @@ namespace dem {
 constexpr double kWcaCut = 1.122462048309373;
 
 // Device flag words.
-enum Flag { FLAG_REBUILD = 0, FLAG_NBUILDS = 1, FLAG_MAXROW = 2, FLAG_NONFINITE = 3, FLAG_NPAIRS = 4, FLAG_COUNT = 8 };
-// Thermostat words (double): xi, eta, velocity scale, B-half-step pending.
-enum Thermo { TH_XI = 0, TH_ETA = 1, TH_SCALE = 2, TH_PENDING = 3, TH_COUNT = 8 };
+enum Flag {
+    FLAG_REBUILD = 0, FLAG_NBUILDS = 1, FLAG_MAXROW = 2, FLAG_NONFINITE = 3, FLAG_NPAIRS = 4, FLAG_TICKET = 5, FLAG_COUNT = 8
+};
+// Thermostat words (double): running xi and eta, the velocity scale the next
+// kick-drift applies, and the state right after the closing half step of the
+// last completed step (xi, eta and its velocity scale).
+enum Thermo { TH_XI = 0, TH_ETA = 1, TH_SCALE = 2, TH_XI_B = 3, TH_ETA_B = 4, TH_SCALE_B = 5, TH_COUNT = 8 };
 // Force work counters (unsigned long long).
 enum Stat {
     ST_PAIRS = 0, ST_FEATURES = 1, ST_INCUT = 2, ST_LAUNCHES = 3, ST_NEAR = 4, ST_REFINED = 5, ST_EENEAR = 6, ST_COUNT = 7
@@ -41,6 +45,7 @@ struct ShapeTab {
     T ed[DEM_MAX_EDGES][3];      // edge vector b - a
     T em[DEM_MAX_EDGES][3];      // edge midpoint
     T eh[DEM_MAX_EDGES];         // half length
+    T el2[DEM_MAX_EDGES];        // |b - a|^2
     T einv[DEM_MAX_EDGES];       // 1 / |b - a|^2
     int foff[DEM_MAX_FACES + 1];
     int floop[DEM_MAX_LOOP];
@@ -63,6 +68,7 @@ struct SysParams {
     int use_cells;               // 1 if every periodic axis has >= 3 cells
     int ensemble;
     int max_pairs;               // capacity of the pair arrays
+    int force_multi_kernel_lists;  // build lists with one kernel per phase even when small
     int pair_blocks;             // grid of the pair kernel (grid-stride over pairs)
     double box[3];
     double cellw[3];             // box / nc
@@ -122,7 +128,10 @@ void launch_pairs(const SysParams &p, const StatePtrs &s, const ListPtrs &l, con
 void launch_gather(const SysParams &p, const StatePtrs &s, const OutPtrs &o, const ListPtrs &l, const ForcePtrs &f,
                    int precision, bool kick, double *ke_part, double *thermo, hipStream_t stream);
 
-// Integrator pieces.
+// Integrator pieces.  With NVT the gather's last workgroup applies the
+// closing half step of the step and the opening half step of the next one;
+// launch_nh_begin opens the first step of a call, launch_nh_end restores
+// the state after the last closing half step and rescales the velocities.
 void launch_nh_begin(const SysParams &p, const double *ke_part, int nblk, double *thermo, hipStream_t stream);
 void launch_kick_drift(const SysParams &p, const StatePtrs &s, const OutPtrs &o, const ListPtrs &l,
                        const double *thermo, void *rot, int precision, hipStream_t stream);
@@ -134,6 +143,11 @@ void launch_energy_partials(const SysParams &p, const StatePtrs &s, const OutPtr
 
 constexpr int kBlock = 256;
 inline int blocks_for(int n) { return (n + kBlock - 1) / kBlock; }
+// The gather and the kinetic reduction give each particle 8 lanes, so a
+// 256-thread block covers 32 particles and writes one kinetic partial.
+constexpr int kGatherLanes = 8;
+constexpr int kGatherPer = kBlock / kGatherLanes;
+inline int gather_blocks(int n) { return (n + kGatherPer - 1) / kGatherPer; }
 
 // Rotation matrix (row-major, body to space) of a unit quaternion (w, x, y, z).
 __host__ __device__ inline void quat_to_rot(double w, double x, double y, double z, double *R)

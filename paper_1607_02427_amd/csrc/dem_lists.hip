@@ -9,12 +9,20 @@
 // across particles.  The half list enumerates each unordered pair once
 // (owner i < j), and pidx maps every row slot to its pair, so the force
 // pass evaluates a pair once and each particle sums its own row.
+//
+// Every list kernel returns at once unless the rebuild flag is set, so a
+// captured step contains the build unconditionally.  Systems of up to
+// kFusedMaxN particles build everything in one workgroup (one launch per
+// step, the phases separated by workgroup barriers); larger systems use one
+// grid-wide kernel per phase.  Both run the same per-item code.
 #include "dem_internal.h"
 
 #pragma clang fp contract(off)
 
 namespace dem {
 namespace {
+
+constexpr int kFusedMaxN = 65536;
 
 __device__ inline int cell_coord(double x, double w, int nc)
 {
@@ -25,65 +33,31 @@ __device__ inline int cell_coord(double x, double w, int nc)
 
 __device__ inline double min_image(double d, double L) { return d - L * rint(d / L); }
 
-__global__ void k_cell_assign(SysParams p, StatePtrs s, ListPtrs l)
+// ---- per-item steps --------------------------------------------------------
+__device__ inline void cell_assign(const SysParams &p, const StatePtrs &s, const ListPtrs &l, int i)
 {
-    if (l.flags[FLAG_REBUILD] == 0) return;
-    int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= p.n) return;
-    int cx = cell_coord(s.x[i], p.cellw[0], p.nc[0]);
-    int cy = cell_coord(s.y[i], p.cellw[1], p.nc[1]);
-    int cz = (p.dim == 3) ? cell_coord(s.z[i], p.cellw[2], p.nc[2]) : 0;
-    int c = cx + p.nc[0] * (cy + p.nc[1] * cz);
+    const int cx = cell_coord(s.x[i], p.cellw[0], p.nc[0]);
+    const int cy = cell_coord(s.y[i], p.cellw[1], p.nc[1]);
+    const int cz = (p.dim == 3) ? cell_coord(s.z[i], p.cellw[2], p.nc[2]) : 0;
+    const int c = cx + p.nc[0] * (cy + p.nc[1] * cz);
     l.pcell[i] = c;
     atomicAdd(&l.cell_count[c], 1);
 }
 
-// Exclusive scan of count[0..m) into start[0..m], start[m] = total (one block).
-__global__ void __launch_bounds__(1024) k_scan(const int32_t *count, int32_t *start, int m, const int32_t *flags)
-{
-    if (flags[FLAG_REBUILD] == 0) return;
-    __shared__ int part[1024];
-    int t = threadIdx.x;
-    int per = (m + 1023) / 1024;
-    int lo = t * per, hi = min(lo + per, m);
-    int sum = 0;
-    for (int c = lo; c < hi; ++c) sum += count[c];
-    part[t] = sum;
-    __syncthreads();
-    for (int off = 1; off < 1024; off <<= 1) {
-        int v = (t >= off) ? part[t - off] : 0;
-        __syncthreads();
-        part[t] += v;
-        __syncthreads();
-    }
-    int run = part[t] - sum;
-    for (int c = lo; c < hi; ++c) {
-        start[c] = run;
-        run += count[c];
-    }
-    if (t == 1023) start[m] = part[1023];
-}
-
 // Scatter; counting each cell back down leaves cell_count zeroed for the next build.
-__global__ void k_cell_fill(SysParams p, ListPtrs l)
+__device__ inline void cell_fill(const ListPtrs &l, int i)
 {
-    if (l.flags[FLAG_REBUILD] == 0) return;
-    int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= p.n) return;
-    int c = l.pcell[i];
-    int slot = atomicSub(&l.cell_count[c], 1) - 1;
+    const int c = l.pcell[i];
+    const int slot = atomicSub(&l.cell_count[c], 1) - 1;
     l.cell_particles[l.cell_start[c] + slot] = i;
 }
 
 // The scatter order is arbitrary: sort every cell ascending (cells hold a few particles).
-__global__ void k_cell_sort(SysParams p, ListPtrs l)
+__device__ inline void cell_sort(const ListPtrs &l, int c)
 {
-    if (l.flags[FLAG_REBUILD] == 0) return;
-    int c = blockIdx.x * blockDim.x + threadIdx.x;
-    if (c >= p.ncell) return;
-    int lo = l.cell_start[c], hi = l.cell_start[c + 1];
+    const int lo = l.cell_start[c], hi = l.cell_start[c + 1];
     for (int a = lo + 1; a < hi; ++a) {
-        int key = l.cell_particles[a];
+        const int key = l.cell_particles[a];
         int b = a - 1;
         while (b >= lo && l.cell_particles[b] > key) {
             l.cell_particles[b + 1] = l.cell_particles[b];
@@ -95,30 +69,27 @@ __global__ void k_cell_sort(SysParams p, ListPtrs l)
 
 __device__ inline bool within(const SysParams &p, const StatePtrs &s, double xi, double yi, double zi, int j)
 {
-    double dx = min_image(s.x[j] - xi, p.box[0]);
-    double dy = min_image(s.y[j] - yi, p.box[1]);
+    const double dx = min_image(s.x[j] - xi, p.box[0]);
+    const double dy = min_image(s.y[j] - yi, p.box[1]);
     double r2 = dx * dx + dy * dy;
     if (p.dim == 3) {
-        double dz = min_image(s.z[j] - zi, p.box[2]);
+        const double dz = min_image(s.z[j] - zi, p.box[2]);
         r2 = r2 + dz * dz;
     }
     return r2 < p.rl2;
 }
 
-__global__ void k_nbr_build(SysParams p, StatePtrs s, ListPtrs l)
+__device__ inline void nbr_build(const SysParams &p, const StatePtrs &s, const ListPtrs &l, int i)
 {
-    if (l.flags[FLAG_REBUILD] == 0) return;
-    int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= p.n) return;
     const int n = p.n;
-    double xi = s.x[i], yi = s.y[i], zi = (p.dim == 3) ? s.z[i] : 0.0;
+    const double xi = s.x[i], yi = s.y[i], zi = (p.dim == 3) ? s.z[i] : 0.0;
     int count = 0;
     if (p.use_cells) {
-        int c = l.pcell[i];
-        int cx = c % p.nc[0];
-        int cy = (c / p.nc[0]) % p.nc[1];
-        int cz = c / (p.nc[0] * p.nc[1]);
-        int zlo = (p.dim == 3) ? -1 : 0, zhi = (p.dim == 3) ? 1 : 0;
+        const int c = l.pcell[i];
+        const int cx = c % p.nc[0];
+        const int cy = (c / p.nc[0]) % p.nc[1];
+        const int cz = c / (p.nc[0] * p.nc[1]);
+        const int zlo = (p.dim == 3) ? -1 : 0, zhi = (p.dim == 3) ? 1 : 0;
         for (int dz = zlo; dz <= zhi; ++dz)
             for (int dy = -1; dy <= 1; ++dy)
                 for (int dx = -1; dx <= 1; ++dx) {
@@ -129,9 +100,9 @@ __global__ void k_nbr_build(SysParams p, StatePtrs s, ListPtrs l)
                     ay -= (ay >= p.nc[1]) ? p.nc[1] : 0;
                     az += (az < 0) ? p.nc[2] : 0;
                     az -= (az >= p.nc[2]) ? p.nc[2] : 0;
-                    int cc = ax + p.nc[0] * (ay + p.nc[1] * az);
+                    const int cc = ax + p.nc[0] * (ay + p.nc[1] * az);
                     for (int t = l.cell_start[cc]; t < l.cell_start[cc + 1]; ++t) {
-                        int j = l.cell_particles[t];
+                        const int j = l.cell_particles[t];
                         if (j != i && within(p, s, xi, yi, zi, j)) {
                             if (count < p.cap) l.nbr[(size_t)count * n + i] = j;
                             ++count;
@@ -145,9 +116,9 @@ __global__ void k_nbr_build(SysParams p, StatePtrs s, ListPtrs l)
                 ++count;
             }
     }
-    int m = count < p.cap ? count : p.cap;
+    const int m = count < p.cap ? count : p.cap;
     for (int a = 1; a < m; ++a) {  // ascending row
-        int key = l.nbr[(size_t)a * n + i];
+        const int key = l.nbr[(size_t)a * n + i];
         int b = a - 1;
         while (b >= 0 && l.nbr[(size_t)b * n + i] > key) {
             l.nbr[(size_t)(b + 1) * n + i] = l.nbr[(size_t)b * n + i];
@@ -164,15 +135,12 @@ __global__ void k_nbr_build(SysParams p, StatePtrs s, ListPtrs l)
 
 // First slot of row i holding a neighbour j > i (rows ascend), and the
 // number of such slots: i owns the pairs (i, j > i) of the half list.
-__global__ void k_pair_count(SysParams p, ListPtrs l, int32_t *upper)
+__device__ inline void pair_count(const SysParams &p, const ListPtrs &l, int32_t *upper, int i)
 {
-    if (l.flags[FLAG_REBUILD] == 0) return;
-    int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= p.n) return;
     const int n = p.n, m = l.n_nbr[i];
     int lo = 0, hi = m;
     while (lo < hi) {
-        int mid = (lo + hi) >> 1;
+        const int mid = (lo + hi) >> 1;
         if (l.nbr[(size_t)mid * n + i] > i) hi = mid;
         else lo = mid + 1;
     }
@@ -182,12 +150,8 @@ __global__ void k_pair_count(SysParams p, ListPtrs l, int32_t *upper)
 
 // Pair arrays and the slot -> pair map; a slot (k, i) with j < i maps to
 // the pair owned by j, found by bisection in j's row.
-__global__ void k_pair_fill(SysParams p, ListPtrs l)
+__device__ inline void pair_fill(const SysParams &p, const ListPtrs &l, int i)
 {
-    if (l.flags[FLAG_REBUILD] == 0) return;
-    int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i == 0) l.flags[FLAG_NPAIRS] = min(l.pstart[p.n], p.max_pairs);
-    if (i >= p.n) return;
     const int n = p.n, m = l.n_nbr[i], k0 = l.klo[i];
     for (int k = 0; k < m; ++k) {
         const int j = l.nbr[(size_t)k * n + i];
@@ -203,7 +167,7 @@ __global__ void k_pair_fill(SysParams p, ListPtrs l)
         } else {
             int lo = l.klo[j], hi = l.n_nbr[j];
             while (lo < hi) {
-                int mid = (lo + hi) >> 1;
+                const int mid = (lo + hi) >> 1;
                 if (l.nbr[(size_t)mid * n + j] < i) lo = mid + 1;
                 else hi = mid;
             }
@@ -214,21 +178,121 @@ __global__ void k_pair_fill(SysParams p, ListPtrs l)
     }
 }
 
+// Exclusive scan of count[0..m) into start[0..m], start[m] = total, by one
+// workgroup of 1024 threads.
+__device__ inline void block_scan(const int32_t *count, int32_t *start, int m, int *part)
+{
+    const int t = threadIdx.x;
+    const int per = (m + 1023) / 1024;
+    const int lo = t * per, hi = min(lo + per, m);
+    int sum = 0;
+    for (int c = lo; c < hi; ++c) sum += count[c];
+    part[t] = sum;
+    __syncthreads();
+    for (int off = 1; off < 1024; off <<= 1) {
+        const int v = (t >= off) ? part[t - off] : 0;
+        __syncthreads();
+        part[t] += v;
+        __syncthreads();
+    }
+    int run = part[t] - sum;
+    for (int c = lo; c < hi; ++c) {
+        start[c] = run;
+        run += count[c];
+    }
+    if (t == 1023) start[m] = part[1023];
+    __syncthreads();
+}
+
+// ---- grid-wide kernels (one per phase) -------------------------------------
+__global__ void k_cell_assign(SysParams p, StatePtrs s, ListPtrs l)
+{
+    if (l.flags[FLAG_REBUILD] == 0) return;
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < p.n) cell_assign(p, s, l, i);
+}
+
+__global__ void __launch_bounds__(1024) k_scan(const int32_t *count, int32_t *start, int m, const int32_t *flags)
+{
+    if (flags[FLAG_REBUILD] == 0) return;
+    __shared__ int part[1024];
+    block_scan(count, start, m, part);
+}
+
+__global__ void k_cell_fill(SysParams p, ListPtrs l)
+{
+    if (l.flags[FLAG_REBUILD] == 0) return;
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < p.n) cell_fill(l, i);
+}
+
+__global__ void k_cell_sort(SysParams p, ListPtrs l)
+{
+    if (l.flags[FLAG_REBUILD] == 0) return;
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c < p.ncell) cell_sort(l, c);
+}
+
+__global__ void k_nbr_build(SysParams p, StatePtrs s, ListPtrs l)
+{
+    if (l.flags[FLAG_REBUILD] == 0) return;
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < p.n) nbr_build(p, s, l, i);
+}
+
+__global__ void k_pair_count(SysParams p, ListPtrs l)
+{
+    if (l.flags[FLAG_REBUILD] == 0) return;
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < p.n) pair_count(p, l, l.pcell, i);  // pcell is free after the neighbour build
+}
+
+__global__ void k_pair_fill(SysParams p, ListPtrs l)
+{
+    if (l.flags[FLAG_REBUILD] == 0) return;
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i == 0) l.flags[FLAG_NPAIRS] = min(l.pstart[p.n], p.max_pairs);
+    if (i < p.n) pair_fill(p, l, i);
+}
+
+// ---- the whole build in one workgroup ---------------------------------------
+__global__ void __launch_bounds__(1024) k_lists_fused(SysParams p, StatePtrs s, ListPtrs l)
+{
+    if (l.flags[FLAG_REBUILD] == 0) return;
+    __shared__ int part[1024];
+    const int t = threadIdx.x, n = p.n;
+    for (int i = t; i < n; i += 1024) cell_assign(p, s, l, i);
+    __syncthreads();
+    block_scan(l.cell_count, l.cell_start, p.ncell, part);
+    for (int i = t; i < n; i += 1024) cell_fill(l, i);
+    __syncthreads();
+    for (int c = t; c < p.ncell; c += 1024) cell_sort(l, c);
+    __syncthreads();
+    for (int i = t; i < n; i += 1024) nbr_build(p, s, l, i);
+    __syncthreads();
+    for (int i = t; i < n; i += 1024) pair_count(p, l, l.pcell, i);
+    __syncthreads();
+    block_scan(l.pcell, l.pstart, n, part);
+    if (t == 0) l.flags[FLAG_NPAIRS] = min(l.pstart[n], p.max_pairs);
+    for (int i = t; i < n; i += 1024) pair_fill(p, l, i);
+}
+
 }  // namespace
 
 void launch_build_lists(const SysParams &p, const StatePtrs &s, const ListPtrs &l, hipStream_t stream)
 {
     if (p.n == 0) return;
+    if (p.n <= kFusedMaxN && !p.force_multi_kernel_lists) {
+        k_lists_fused<<<1, 1024, 0, stream>>>(p, s, l);
+        return;
+    }
     const int nb = blocks_for(p.n);
-    // The cell list is always built (it is part of the output contract); the
-    // neighbour search falls back to all pairs when an axis has < 3 cells.
     k_cell_assign<<<nb, kBlock, 0, stream>>>(p, s, l);
     k_scan<<<1, 1024, 0, stream>>>(l.cell_count, l.cell_start, p.ncell, l.flags);
     k_cell_fill<<<nb, kBlock, 0, stream>>>(p, l);
     k_cell_sort<<<blocks_for(p.ncell), kBlock, 0, stream>>>(p, l);
     k_nbr_build<<<nb, kBlock, 0, stream>>>(p, s, l);
-    // half pair list: pcell is free after the neighbour build and holds the per-particle pair counts
-    k_pair_count<<<nb, kBlock, 0, stream>>>(p, l, l.pcell);
+    k_pair_count<<<nb, kBlock, 0, stream>>>(p, l);
     k_scan<<<1, 1024, 0, stream>>>(l.pcell, l.pstart, p.n, l.flags);
     k_pair_fill<<<nb, kBlock, 0, stream>>>(p, l);
 }

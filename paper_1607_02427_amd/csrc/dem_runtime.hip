@@ -75,10 +75,9 @@ __global__ void k_end_build(int32_t *flags)
 }
 __global__ void k_set_thermo(double *th, double xi, double eta)
 {
-    th[TH_XI] = xi;
-    th[TH_ETA] = eta;
-    th[TH_SCALE] = 1.0;
-    th[TH_PENDING] = 0.0;
+    th[TH_XI] = th[TH_XI_B] = xi;
+    th[TH_ETA] = th[TH_ETA_B] = eta;
+    th[TH_SCALE] = th[TH_SCALE_B] = 1.0;
 }
 
 struct HostVec {
@@ -130,6 +129,7 @@ dem_status build_table(dem_system *h, int idx, const dem_shape_desc &d, int dim,
             l2 += T.ed[k][c] * T.ed[k][c];
         }
         if (!(l2 > 0.0)) return fail(h, DEM_E_SHAPE, "shape %d: edge %d has zero length", idx, k);
+        T.el2[k] = l2;
         T.einv[k] = 1.0 / l2;
         T.eh[k] = 0.5 * std::sqrt(l2);
         for (int c = 0; c < 3; ++c) T.em[k][c] = 0.5 * (T.v[a][c] + T.v[b][c]);
@@ -241,6 +241,7 @@ void to_float(const ShapeTab<double> &D, ShapeTab<float> &F)
             F.em[k][a] = (float)D.em[k][a];
         }
         F.eh[k] = (float)(D.eh[k] * (1.0 + 1e-6));  // keep the FP32 bounds conservative
+        F.el2[k] = (float)D.el2[k];
         F.einv[k] = (float)D.einv[k];
     }
     for (int f = 0; f <= DEM_MAX_FACES; ++f) F.foff[f] = D.foff[f];
@@ -327,7 +328,7 @@ dem_status alloc_nbr(dem_system *h, int cap)
     h->sp.cap = cap;
     h->sp.max_pairs = (int)maxp;
     // grid-stride pair kernel: enough waves to fill the chip, no more than the pairs need
-    const size_t want = (maxp + 3) / 4;
+    const size_t want = (maxp + 15) / 16;  // four waves per block, four pairs per wave
     h->sp.pair_blocks = (int)std::max<size_t>(1, std::min<size_t>(want, 2048));
     drop_graph(h);
     return DEM_OK;
@@ -357,7 +358,6 @@ dem_status latched(dem_system *h)
 void enqueue_step(dem_system *h, hipStream_t s)
 {
     const ForcePtrs f = force_ptrs(h);
-    if (h->sp.ensemble == DEM_NVT) launch_nh_begin(h->sp, h->ke_part, h->nblk, h->thermo, s);
     launch_kick_drift(h->sp, h->st, h->out, h->lst, h->thermo, h->rot, h->prm.precision, s);
     launch_build_lists(h->sp, h->st, h->lst, s);
     launch_pairs(h->sp, h->st, h->lst, f, h->prm.precision, h->counting ? h->stats : nullptr, s);
@@ -454,6 +454,7 @@ dem_status dem_create_system(const dem_params *params, const dem_state_ptrs *sta
         return fail(nullptr, DEM_E_ARG, "n_shapes must be 1..%d", DEM_MAX_SHAPES);
     if (p.ensemble != DEM_NVE && p.ensemble != DEM_NVT) return fail(nullptr, DEM_E_ARG, "bad ensemble");
     if (p.precision != DEM_FP64 && p.precision != DEM_FP32) return fail(nullptr, DEM_E_ARG, "bad precision");
+    if (p.list_mode != DEM_LISTS_AUTO && p.list_mode != DEM_LISTS_MULTI) return fail(nullptr, DEM_E_ARG, "bad list_mode");
     if (!(p.dt > 0.0) || !(p.skin >= 0.0) || !(p.rebuild_frac > 0.0) || !(p.epsilon > 0.0) || !(p.parallel_sin2 >= 0.0))
         return fail(nullptr, DEM_E_ARG, "dt, epsilon, rebuild_frac must be > 0; skin, parallel_sin2 >= 0");
     if (p.ensemble == DEM_NVT && (!(p.kT > 0.0) || !(p.tau_T > 0.0)))
@@ -507,6 +508,7 @@ dem_status dem_create_system(const dem_params *params, const dem_state_ptrs *sta
     sp.n_shapes = p.n_shapes;
     sp.ensemble = p.ensemble;
     sp.use_cells = 1;
+    sp.force_multi_kernel_lists = p.list_mode == DEM_LISTS_MULTI ? 1 : 0;
     for (int a = 0; a < 3; ++a) {
         sp.box[a] = (a < p.dim) ? p.box[a] : 1.0;
         if (a < p.dim) {
@@ -537,11 +539,12 @@ dem_status dem_create_system(const dem_params *params, const dem_state_ptrs *sta
 
     const size_t n = (size_t)std::max(sp.n, 1);
     h->nblk = (int)((n + kBlock - 1) / kBlock);
+    const int kblk = gather_blocks((int)n);
     if (hipStreamCreateWithFlags(&h->cap_stream, hipStreamNonBlocking) != hipSuccess)
         return bail(fail(h, DEM_E_HIP, "stream creation failed"));
     bool ok = hipMalloc(&h->tab64, sizeof(ShapeTab<double>) * p.n_shapes) == hipSuccess &&
               hipMalloc(&h->tab32, sizeof(ShapeTab<float>) * p.n_shapes) == hipSuccess &&
-              hipMalloc(&h->ke_part, sizeof(double) * 2 * h->nblk) == hipSuccess &&
+              hipMalloc(&h->ke_part, sizeof(double) * 2 * kblk) == hipSuccess &&
               hipMalloc(&h->e_part, sizeof(double) * 12 * h->nblk) == hipSuccess &&
               hipMalloc(&h->thermo, sizeof(double) * TH_COUNT) == hipSuccess &&
               hipMalloc(&h->stats, sizeof(unsigned long long) * ST_COUNT) == hipSuccess &&
@@ -578,7 +581,7 @@ dem_status dem_create_system(const dem_params *params, const dem_state_ptrs *sta
         hipMemsetAsync(h->lst.cell_count, 0, sizeof(int32_t) * sp.ncell, h->stream) != hipSuccess ||
         hipMemsetAsync(h->lst.n_nbr, 0, sizeof(int32_t) * n, h->stream) != hipSuccess ||
         hipMemsetAsync(h->stats, 0, sizeof(unsigned long long) * ST_COUNT, h->stream) != hipSuccess ||
-        hipMemsetAsync(h->ke_part, 0, sizeof(double) * 2 * h->nblk, h->stream) != hipSuccess)
+        hipMemsetAsync(h->ke_part, 0, sizeof(double) * 2 * kblk, h->stream) != hipSuccess)
         return bail(fail(h, DEM_E_HIP, "initial upload failed"));
     k_set_thermo<<<1, 1, 0, h->stream>>>(h->thermo, 0.0, 0.0);
     if ((st = build_lists_sync(h)) != DEM_OK) return bail(st);
@@ -639,7 +642,10 @@ dem_status dem_step(dem_handle h, int64_t n_steps)
     dem_status st = ensure_graph(h);
     if (st != DEM_OK) return st;
     const bool nvt = h->sp.ensemble == DEM_NVT;
-    if (nvt) launch_kinetic(h->sp, h->st, h->ke_part, h->stream);
+    if (nvt) {  // opening half step of the first step, from the current kinetic energy
+        launch_kinetic(h->sp, h->st, h->ke_part, h->stream);
+        launch_nh_begin(h->sp, h->ke_part, gather_blocks(h->sp.n), h->thermo, h->stream);
+    }
     for (int64_t k = 0; k < n_steps; ++k) HIPCHK(h, hipGraphLaunch(h->gexec, h->stream));
     if (nvt) launch_nh_end(h->sp, h->st, h->ke_part, h->nblk, h->thermo, h->stream);
     HIPCHK(h, hipGetLastError());

@@ -37,7 +37,7 @@ class Params(C.Structure):
                 ("shapes", C.POINTER(ShapeDesc)), ("epsilon", C.c_double), ("skin", C.c_double),
                 ("rebuild_frac", C.c_double), ("dt", C.c_double), ("ensemble", C.c_int32), ("kT", C.c_double),
                 ("tau_T", C.c_double), ("precision", C.c_int32), ("parallel_sin2", C.c_double),
-                ("nbr_capacity", C.c_int32)]
+                ("nbr_capacity", C.c_int32), ("list_mode", C.c_int32)]
 
 
 class StatePtrs(C.Structure):
@@ -132,7 +132,7 @@ def _shape_desc(shape, keep):
     return d
 
 
-def make_params(system, precision: str = "fp64", nbr_capacity: int = 0):
+def make_params(system, precision: str = "fp64", nbr_capacity: int = 0, list_mode: str = "auto"):
     keep = []
     descs = (ShapeDesc * len(system.shapes))(*[_shape_desc(s, keep) for s in system.shapes])
     keep.append(descs)
@@ -153,6 +153,7 @@ def make_params(system, precision: str = "fp64", nbr_capacity: int = 0):
     p.precision = DEM_FP32 if precision == "fp32" else DEM_FP64
     p.parallel_sin2 = system.parallel_sin2
     p.nbr_capacity = nbr_capacity
+    p.list_mode = 1 if list_mode == "multi" else 0
     return p, keep
 
 
@@ -168,7 +169,7 @@ class DemSystem:
     OUT = ("Fx", "Fy", "Fz", "Tx", "Ty", "Tz", "U")
 
     def __init__(self, system, precision: str = "fp64", nbr_capacity: int = 0, device: str = "cuda:0",
-                 stream=None):
+                 stream=None, list_mode: str = "auto"):
         import torch
         self.torch = torch
         self.system = system
@@ -190,7 +191,7 @@ class DemSystem:
             self.o["W"] = torch.zeros(9 * n, dtype=torch.float64, device=self.device)
         sp = StatePtrs(**{k: self.t[k].data_ptr() for k in self.STATE + ("shape_id", "image")})
         op = OutPtrs(**{k: self.o[k].data_ptr() for k in self.OUT + ("W",)})
-        self._params, self._keep = make_params(system, precision, nbr_capacity)
+        self._params, self._keep = make_params(system, precision, nbr_capacity, list_mode)
         h = C.c_void_p()
         torch.cuda.synchronize(self.device)
         with torch.cuda.device(self.device):

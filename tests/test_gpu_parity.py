@@ -47,12 +47,26 @@ def _drop_last(s):
 CASES = _cases()
 
 
+@pytest.mark.parametrize("mode", ["auto", "multi"])
 @pytest.mark.parametrize("name", list(CASES))
-def test_lists_bit_exact(name):
+def test_lists_bit_exact(name, mode):
     dem = _dem()
     s = CASES[name]()
-    print(f"[lists] {name} n={s.n}", flush=True)
-    with dem.DemSystem(s, "fp64") as g:
+    print(f"[lists] {name} n={s.n} {mode}", flush=True)
+    _check_lists(dem, s, mode)
+
+
+def test_lists_bit_exact_large():
+    """74,088 cubes: above the single-workgroup limit, so the automatic mode
+    takes the one-kernel-per-phase build."""
+    dem = _dem()
+    s = I.cubes_3d(n_side=42)
+    print(f"[lists] cubes_74088 n={s.n}", flush=True)
+    _check_lists(dem, s, "auto")
+
+
+def _check_lists(dem, s, mode):
+    with dem.DemSystem(s, "fp64", list_mode=mode) as g:
         L = g.lists()
         rl_oracle = O.OracleSystem.of(s).r_list(s.skin)
         assert L["r_list"] == rl_oracle  # same FP64 bits
