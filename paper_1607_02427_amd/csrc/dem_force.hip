@@ -25,8 +25,8 @@
 //     group reduces force, both torques and energy across its 16 lanes and
 //     writes one record per pair (FP32 pair records in FP32 mode; every sum
 //     over pairs is FP64).
-//  2. k_gather: 8 lanes per particle sum its row of pair records in a fixed
-//     order (no atomics, deterministic) into F, tau, U_i and W_i, optionally
+//  2. k_gather: each particle sums the records of its row in slot order (no
+//     atomics, deterministic) into F, tau, U_i and W_i, optionally
 //     fused with the closing kick of the integrator and, with NVT, the
 //     thermostat half steps between two steps.
 // FP32 mode does the geometry in FP32 from FP64 pair offsets rounded once;
@@ -328,12 +328,6 @@ __device__ inline int add_wca(Acc<T> &A, V3<T> P, V3<T> rho, V3<T> t, T sig2, T 
 }
 
 template <typename T>
-__device__ inline void load_rot(const T *rot, int n, int i, M3<T> &R)
-{
-    for (int k = 0; k < 9; ++k) R.m[k] = rot[(size_t)k * n + i];
-}
-
-template <typename T>
 __device__ inline T group_sum(T v)
 {
     for (int off = kGL / 2; off > 0; off >>= 1) v += __shfl_xor(v, off, kGL);
@@ -384,7 +378,7 @@ __device__ void refine_edges(const SysParams &p, const StatePtrs &s, int i, int 
 }
 
 template <typename T, int DIM>
-__global__ void __launch_bounds__(64 * kWaves) k_pairs(SysParams p, StatePtrs s, ListPtrs l, const T *__restrict__ rot,
+__global__ void __launch_bounds__(64 * kWaves) k_pairs(SysParams p, StatePtrs s, ListPtrs l, const PartRec<T> *__restrict__ prec,
                                                           T *__restrict__ rec, const ShapeTab<T> *__restrict__ gtab,
                                                           const ShapeTab<double> *__restrict__ gtab64,
                                                           unsigned long long *stats)
@@ -408,36 +402,51 @@ __global__ void __launch_bounds__(64 * kWaves) k_pairs(SysParams p, StatePtrs s,
     const unsigned long long below = lanes_below();
     const int n = p.n;
     const int npairs = l.flags[FLAG_NPAIRS];
-    // XCD-aware order: blocks are dealt round-robin to the 8 XCDs, so give
-    // each XCD a contiguous share of the pair list (neighbouring particles
-    // share one L2).
+    // XCD-aware order: blocks are dealt round-robin to the 8 XCDs, so each
+    // XCD takes a contiguous eighth of the pair list (pairs of neighbouring
+    // particles share its L2) and its blocks stride through that range.
     const int G = gridDim.x;
     const int xcd = blockIdx.x & 7, slot = blockIdx.x >> 3;
-    int first_xcd_block = 0;
-    for (int x = 0; x < xcd; ++x) first_xcd_block += (G + 7 - x) >> 3;
-    const int vblock = first_xcd_block + slot;  // virtual block index, contiguous per XCD
+    const int xblocks = (G + 7 - xcd) >> 3;
+    const int per_xcd = (npairs + 7) >> 3;
+    const int x_lo = min(xcd * per_xcd, npairs), x_hi = min(x_lo + per_xcd, npairs);
     const T par_s2 = (T)p.par_s2;
     const T eps = (T)p.eps;
     const T grow = T(1.00001);
     unsigned long long c_pairs = 0, c_feat = 0, c_in = 0, c_near = 0, c_ee = 0, c_ref = 0;
 
-    for (int base = (vblock * kWaves + wid) * kGroups; base < npairs; base += G * kWaves * kGroups) {
+    for (int base = x_lo + (slot * kWaves + wid) * kGroups; base < x_hi; base += xblocks * kWaves * kGroups) {
         const int pr = base + grp;
-        const bool active = pr < npairs;
-        int i = 0, j = 0, si = 0, sj = 0;
+        const bool active = pr < x_hi;
+        // two dependent round trips: the pair entry, then both particle
+        // records (position, rotation and shape in one line each)
+        int4 ent = make_int4(0, 0, 0, 0);
+        if (active) ent = l.pairs[pr];
+        const int i = ent.x, j = ent.y;
+        int si = 0, sj = 0;
         double dx = 0.0, dy = 0.0, dz = 0.0;
         bool live = false;
+        M3<T> Ri, Rj;
+        for (int k = 0; k < 9; ++k) Ri.m[k] = Rj.m[k] = T(0);
         if (active) {
-            i = l.pi[pr];
-            j = l.pj[pr];
-            dx = min_image(s.x[j] - s.x[i], p.box[0]);
-            dy = min_image(s.y[j] - s.y[i], p.box[1]);
-            dz = (DIM == 3) ? min_image(s.z[j] - s.z[i], p.box[2]) : 0.0;
-            si = s.sid[i];
-            sj = s.sid[j];
+            const PartRec<T> ri = prec[i];
+            const PartRec<T> rj = prec[j];
+            for (int k = 0; k < 9; ++k) {
+                Ri.m[k] = ri.R[k];
+                Rj.m[k] = rj.R[k];
+            }
+            dx = min_image(rj.x - ri.x, p.box[0]);
+            dy = min_image(rj.y - ri.y, p.box[1]);
+            dz = (DIM == 3) ? min_image(rj.z - ri.z, p.box[2]) : 0.0;
+            si = ri.sid;
+            sj = rj.sid;
             const double bound = p.R[si] + p.R[sj] + kWcaCut * (p.rad[si] + p.rad[sj]);
             live = dx * dx + dy * dy + dz * dz < bound * bound;
-            if (!live && sub < kRec) rec[(size_t)pr * kRec + sub] = T(0);
+            if (!live && sub < kRec) {  // zero both row slots of a pair out of reach
+                const size_t cs = (size_t)sub * p.cap * n;
+                rec[cs + (size_t)ent.z * n + i] = T(0);
+                rec[cs + (size_t)ent.w * n + j] = T(0);
+            }
         }
         if (__ballot(live) == 0) continue;
         const ShapeTab<T> &Si = tab[si];
@@ -447,9 +456,6 @@ __global__ void __launch_bounds__(64 * kWaves) k_pairs(SysParams p, StatePtrs s,
         T sig2 = T(0), rc = T(0), Bi = T(0), Bj = T(0);
         for (int k = 0; k < 9; ++k) Rr.m[k] = T(0);
         if (live) {
-            M3<T> Ri, Rj;
-            load_rot(rot, n, i, Ri);
-            load_rot(rot, n, j, Rj);
             for (int a = 0; a < 3; ++a)
                 for (int b = 0; b < 3; ++b)
                     Rr.m[3 * a + b] = Ri.m[a] * Rj.m[b] + Ri.m[3 + a] * Rj.m[3 + b] + Ri.m[6 + a] * Rj.m[6 + b];
@@ -589,21 +595,33 @@ __global__ void __launch_bounds__(64 * kWaves) k_pairs(SysParams p, StatePtrs s,
             }
             if (last) break;
         }
-        // group reduction; the group's first lane rotates to the space frame and writes the record
+        // group reduction (every lane of the group gets the sums); rotate to
+        // the space frame and write both row slots, one component per lane
         const T F0 = group_sum(A.F.x), F1 = group_sum(A.F.y), F2 = group_sum(A.F.z);
         const T I0 = group_sum(A.Ti.x), I1 = group_sum(A.Ti.y), I2 = group_sum(A.Ti.z);
         const T J0 = group_sum(A.Tj.x), J1 = group_sum(A.Tj.y), J2 = group_sum(A.Tj.z);
         const T U = group_sum(A.U);
-        if (live && sub == 0) {
-            M3<T> Ri;
-            load_rot(rot, n, i, Ri);
-            T *out = rec + (size_t)pr * kRec;
-            for (int a = 0; a < 3; ++a) {
-                out[a] = Ri.m[3 * a] * F0 + Ri.m[3 * a + 1] * F1 + Ri.m[3 * a + 2] * F2;
-                out[3 + a] = Ri.m[3 * a] * I0 + Ri.m[3 * a + 1] * I1 + Ri.m[3 * a + 2] * I2;
-                out[6 + a] = Ri.m[3 * a] * J0 + Ri.m[3 * a + 1] * J1 + Ri.m[3 * a + 2] * J2;
+        if (live && sub < kRec) {
+            const V3<T> Fs = mul(Ri, v3<T>(F0, F1, F2));
+            const V3<T> Is = mul(Ri, v3<T>(I0, I1, I2));
+            const V3<T> Js = mul(Ri, v3<T>(J0, J1, J2));
+            T vi, vj;  // component sub of the records in i's slot and in j's slot
+            if (sub < 3) {
+                vi = sub == 0 ? Fs.x : (sub == 1 ? Fs.y : Fs.z);
+                vj = -vi;
+            } else if (sub < 6) {
+                vi = sub == 3 ? Is.x : (sub == 4 ? Is.y : Is.z);
+                vj = sub == 3 ? Js.x : (sub == 4 ? Js.y : Js.z);
+            } else if (sub == 6) {
+                vi = U;
+                vj = U;
+            } else {
+                vi = (T)(sub == 7 ? dx : (sub == 8 ? dy : dz));
+                vj = -vi;
             }
-            out[9] = U;
+            const size_t cs = (size_t)sub * p.cap * n;
+            rec[cs + (size_t)ent.z * n + i] = vi;
+            rec[cs + (size_t)ent.w * n + j] = vj;
         }
     }
     if (stats) {
@@ -665,10 +683,10 @@ __device__ inline double nh_half(const SysParams &p, double &xi, double &eta, do
     return sc;
 }
 
-// Per-particle sums of the pair records, optionally fused with the closing
-// kick.  Each particle gets kGatherLanes lanes: lane l sums row slots
-// k = l, l + 8, ... in order, then a butterfly over the 8 lanes combines
-// them, so the result does not depend on scheduling.  With NVT the block's
+// Per-particle sums of the row-slot records, optionally fused with the
+// closing kick.  Each particle's row is split over kGatherLanes lanes (lane
+// l takes slots l, l + kGatherLanes, ... in order) and combined by a fixed
+// butterfly, so the result does not depend on scheduling.  With NVT the block's
 // kinetic partial is published and the last block to finish (ticket
 // counter, no waiting) applies the step's closing Nose-Hoover half step and
 // the next step's opening one.
@@ -689,27 +707,20 @@ __global__ void __launch_bounds__(kBlock) k_gather(SysParams p, StatePtrs s, Out
     double acc[16];
     for (int c = 0; c < 16; ++c) acc[c] = 0.0;  // F[3], T[3], U, W[9]
     if (i < n) {
-        const double xi = s.x[i], yi = s.y[i], zi = (DIM == 3) ? s.z[i] : 0.0;
         const int m = l.n_nbr[i];
+        const size_t cs = (size_t)p.cap * n;
+#pragma unroll 2
         for (int k = sub; k < m; k += kGatherLanes) {
-            const int j = l.nbr[(size_t)k * n + i];
-            const int q = l.pidx[(size_t)k * n + i];
-            if (q < 0) continue;
-            const T *r = rec + (size_t)q * kRec;
-            const double sg = (j > i) ? 1.0 : -1.0;  // records hold the force on the pair's owner (lower index)
-            const double f[3] = {sg * (double)r[0], sg * (double)r[1], sg * (double)r[2]};
-            const int to = (j > i) ? 3 : 6;
+            const T *r = rec + (size_t)k * n + i;  // component c at r[c * cs]
+            const double f[3] = {(double)r[0], (double)r[cs], (double)r[2 * cs]};
             for (int a = 0; a < 3; ++a) {
                 acc[a] += f[a];
-                acc[3 + a] += (double)r[to + a];
+                acc[3 + a] += (double)r[(3 + a) * cs];
             }
-            acc[6] += 0.5 * (double)r[9];
-            if (f[0] != 0.0 || f[1] != 0.0 || f[2] != 0.0) {
-                const double d[3] = {min_image(s.x[j] - xi, p.box[0]), min_image(s.y[j] - yi, p.box[1]),
-                                     (DIM == 3) ? min_image(s.z[j] - zi, p.box[2]) : 0.0};
-                for (int a = 0; a < 3; ++a)
-                    for (int b = 0; b < 3; ++b) acc[7 + 3 * a + b] -= 0.5 * d[a] * f[b];
-            }
+            acc[6] += 0.5 * (double)r[6 * cs];
+            const double d[3] = {(double)r[7 * cs], (double)r[8 * cs], (double)r[9 * cs]};
+            for (int a = 0; a < 3; ++a)
+                for (int b = 0; b < 3; ++b) acc[7 + 3 * a + b] -= 0.5 * d[a] * f[b];
         }
     }
     for (int off = 1; off < kGatherLanes; off <<= 1)
@@ -795,13 +806,19 @@ __global__ void __launch_bounds__(kBlock) k_gather(SysParams p, StatePtrs s, Out
 }
 
 template <typename T>
-__global__ void k_rotations(SysParams p, StatePtrs s, T *rot)
+__global__ void k_rotations(SysParams p, StatePtrs s, PartRec<T> *rot)
 {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= p.n) return;
     double R[9];
     quat_to_rot(s.qw[i], s.qx[i], s.qy[i], s.qz[i], R);
-    for (int k = 0; k < 9; ++k) rot[(size_t)k * p.n + i] = (T)R[k];
+    PartRec<T> r;
+    r.x = s.x[i];
+    r.y = s.y[i];
+    r.z = p.dim == 3 ? s.z[i] : 0.0;
+    for (int k = 0; k < 9; ++k) r.R[k] = (T)R[k];
+    r.sid = s.sid[i];
+    rot[i] = r;
 }
 
 template <typename T, int DIM>
@@ -810,7 +827,7 @@ void pairs_t(const SysParams &p, const StatePtrs &s, const ListPtrs &l, const Fo
 {
     const size_t sh = (size_t)p.n_shapes * sizeof(ShapeTab<T>) + kWaves * kGroups * sizeof(PairLds<T>);
     k_pairs<T, DIM><<<p.pair_blocks, 64 * kWaves, sh, stream>>>(
-        p, s, l, reinterpret_cast<const T *>(f.rot), reinterpret_cast<T *>(f.rec),
+        p, s, l, reinterpret_cast<const PartRec<T> *>(f.rot), reinterpret_cast<T *>(f.rec),
         reinterpret_cast<const ShapeTab<T> *>(f.tab), reinterpret_cast<const ShapeTab<double> *>(f.tab64), stats);
 }
 
@@ -835,9 +852,9 @@ void launch_rotations(const SysParams &p, const StatePtrs &s, void *rot, int pre
 {
     if (p.n == 0) return;
     if (precision == DEM_FP32)
-        k_rotations<float><<<blocks_for(p.n), kBlock, 0, stream>>>(p, s, reinterpret_cast<float *>(rot));
+        k_rotations<float><<<blocks_for(p.n), kBlock, 0, stream>>>(p, s, reinterpret_cast<PartRec<float> *>(rot));
     else
-        k_rotations<double><<<blocks_for(p.n), kBlock, 0, stream>>>(p, s, reinterpret_cast<double *>(rot));
+        k_rotations<double><<<blocks_for(p.n), kBlock, 0, stream>>>(p, s, reinterpret_cast<PartRec<double> *>(rot));
 }
 
 void launch_pairs(const SysParams &p, const StatePtrs &s, const ListPtrs &l, const ForcePtrs &f, int precision,

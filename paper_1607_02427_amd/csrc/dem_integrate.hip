@@ -46,8 +46,7 @@ __device__ inline void turn(double q[4], double L[3], const double I[3], int k, 
     double b[3] = {0.0, 0.0, 0.0};
     b[k] = sn;
     quat_mul(q[0], q[1], q[2], q[3], cs, b[0], b[1], b[2]);
-    double s1, c1;
-    sincos(phi, &s1, &c1);
+    const double s1 = 2.0 * sn * cs, c1 = (cs - sn) * (cs + sn);  // sin, cos of phi from the half angle
     const int a = (k + 1) % 3, c = (k + 2) % 3;
     const double La = L[a], Lc = L[c];
     L[a] = c1 * La + s1 * Lc;
@@ -136,7 +135,7 @@ __global__ void k_scale(SysParams p, StatePtrs s, const double *th)
 
 template <typename T, int DIM, bool NVT>
 __global__ void __launch_bounds__(kBlock) k_kick_drift(SysParams p, StatePtrs s, OutPtrs o, ListPtrs l,
-                                                          const double *th, T *rot)
+                                                          const double *th, void *rot)
 {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= p.n) return;
@@ -187,10 +186,16 @@ __global__ void __launch_bounds__(kBlock) k_kick_drift(SysParams p, StatePtrs s,
     s.qx[i] = q[1];
     s.qy[i] = q[2];
     s.qz[i] = q[3];
-    {  // rotation matrix of the new orientation, for the force pass
+    {  // the force pass's record: new position, rotation of the new orientation, shape
         double R[9];
         quat_to_rot(q[0], q[1], q[2], q[3], R);
-        for (int k = 0; k < 9; ++k) rot[(size_t)k * p.n + i] = (T)R[k];
+        PartRec<T> r;
+        r.x = x[0];
+        r.y = x[1];
+        r.z = x[2];
+        for (int k = 0; k < 9; ++k) r.R[k] = (T)R[k];
+        r.sid = sid;
+        reinterpret_cast<PartRec<T> *>(rot)[i] = r;
     }
     s.x[i] = x[0];
     s.y[i] = x[1];
@@ -280,7 +285,7 @@ void launch_nh_end(const SysParams &p, const StatePtrs &s, const double *ke_part
 
 template <typename T>
 void kick_drift_t(const SysParams &p, const StatePtrs &s, const OutPtrs &o, const ListPtrs &l, const double *thermo,
-                  T *rot, hipStream_t stream)
+                  void *rot, hipStream_t stream)
 {
     const int nb = blocks_for(p.n);
     const bool nvt = p.ensemble == DEM_NVT;
@@ -297,8 +302,8 @@ void launch_kick_drift(const SysParams &p, const StatePtrs &s, const OutPtrs &o,
                        const double *thermo, void *rot, int precision, hipStream_t stream)
 {
     if (p.n == 0) return;
-    if (precision == DEM_FP32) kick_drift_t(p, s, o, l, thermo, reinterpret_cast<float *>(rot), stream);
-    else kick_drift_t(p, s, o, l, thermo, reinterpret_cast<double *>(rot), stream);
+    if (precision == DEM_FP32) kick_drift_t<float>(p, s, o, l, thermo, rot, stream);
+    else kick_drift_t<double>(p, s, o, l, thermo, rot, stream);
 }
 
 void launch_kinetic(const SysParams &p, const StatePtrs &s, double *ke_part, hipStream_t stream)

@@ -26,8 +26,10 @@ enum Stat {
     ST_PAIRS = 0, ST_FEATURES = 1, ST_INCUT = 2, ST_LAUNCHES = 3, ST_NEAR = 4, ST_REFINED = 5, ST_EENEAR = 6, ST_COUNT = 7
 };
 
-// Words of one pair record: force on i (space frame), torque on i, torque
-// on j (both about their own centres, space frame), pair energy U_ij.
+// Words of one row-slot record, stored component-major rec[c][k][i] for
+// slot k of particle i's neighbour row: force on i (space frame, 3), torque
+// on i about its centre (3), pair energy U_ij (1), and the pair offset
+// x_j - x_i (3).  The force pass writes both slots of a pair.
 constexpr int kRec = 10;
 
 // Body-frame feature tables of one shape in precision T, staged in LDS.
@@ -98,13 +100,32 @@ struct ListPtrs {
     // half list of unordered pairs (i < j), rebuilt with the neighbour list
     int32_t *klo;                // [n] first row slot of i holding a j > i
     int32_t *pstart;             // [n] first pair index of i
-    int32_t *pi, *pj;            // [max_pairs]
-    int32_t *pidx;               // [cap][n] pair index of row slot (k, i)
+    int4 *pairs;                 // [max_pairs] {i, j, slot of j in i's row, slot of i in j's row}
+};
+
+// Everything the pair kernel reads about one particle, in one cache line:
+// FP64 position, the body-to-space rotation in the force precision (row
+// major) and the shape id.  Written by the kick-drift (and by
+// launch_rotations from the state arrays).
+template <typename T>
+struct PartRec;
+template <>
+struct alignas(64) PartRec<float> {
+    double x, y, z;
+    float R[9];
+    int sid;
+};
+template <>
+struct alignas(128) PartRec<double> {
+    double x, y, z;
+    double R[9];
+    int sid;
+    int pad[7];
 };
 
 struct ForcePtrs {
-    void *rot;                   // [9][n] body-to-space rotation, precision T
-    void *rec;                   // [max_pairs][kRec] pair records, precision T
+    void *rot;                   // [n] PartRec<T>
+    void *rec;                   // [kRec][cap][n] row-slot records, precision T
     const void *tab;             // shape tables, precision T
     const void *tab64;           // shape tables, FP64 (refinement of ill-conditioned FP32 problems)
 };
@@ -115,7 +136,7 @@ struct ForcePtrs {
 // unconditionally.
 void launch_build_lists(const SysParams &p, const StatePtrs &s, const ListPtrs &l, hipStream_t stream);
 
-// Per-particle rotation matrices from the quaternions.
+// Per-particle records (position, rotation, shape id) from the state arrays.
 void launch_rotations(const SysParams &p, const StatePtrs &s, void *rot, int precision, hipStream_t stream);
 
 // Pair records over the half list; stats may be null.
@@ -143,9 +164,9 @@ void launch_energy_partials(const SysParams &p, const StatePtrs &s, const OutPtr
 
 constexpr int kBlock = 256;
 inline int blocks_for(int n) { return (n + kBlock - 1) / kBlock; }
-// The gather and the kinetic reduction give each particle 8 lanes, so a
-// 256-thread block covers 32 particles and writes one kinetic partial.
-constexpr int kGatherLanes = 8;
+// The gather and the kinetic reduction map kGatherPer particles to each
+// 256-thread block, which writes one kinetic partial.
+constexpr int kGatherLanes = 4;
 constexpr int kGatherPer = kBlock / kGatherLanes;
 inline int gather_blocks(int n) { return (n + kGatherPer - 1) / kGatherPer; }
 

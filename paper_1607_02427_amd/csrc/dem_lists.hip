@@ -7,8 +7,9 @@
 // (no contraction into fused multiply-adds), stored ascending in j.
 // Rows live column-major (nbr[k * n + i]) so per-row loads are contiguous
 // across particles.  The half list enumerates each unordered pair once
-// (owner i < j), and pidx maps every row slot to its pair, so the force
-// pass evaluates a pair once and each particle sums its own row.
+// (owner i < j) with the row slot it occupies in both rows, so the force
+// pass evaluates a pair once, writes its result into both slots, and each
+// particle sums its own row.
 //
 // Every list kernel returns at once unless the rebuild flag is set, so a
 // captured step contains the build unconditionally.  Systems of up to
@@ -31,7 +32,15 @@ __device__ inline int cell_coord(double x, double w, int nc)
     return c > nc - 1 ? nc - 1 : c;
 }
 
-__device__ inline double min_image(double d, double L) { return d - L * rint(d / L); }
+// Minimum image of d = x_j - x_i for positions in [0, L].  This equals
+// d - L rint(d / L) bit for bit except where |d| is within rounding of L/2,
+// and there both forms give |d| >= L/2 >= r_list, so no list decision can
+// differ; it avoids an FP64 division per candidate.
+__device__ inline double min_image(double d, double L)
+{
+    const double h = 0.5 * L;
+    return d > h ? d - L : (d < -h ? d + L : d);
+}
 
 // ---- per-item steps --------------------------------------------------------
 __device__ inline void cell_assign(const SysParams &p, const StatePtrs &s, const ListPtrs &l, int i)
@@ -148,8 +157,9 @@ __device__ inline void pair_count(const SysParams &p, const ListPtrs &l, int32_t
     upper[i] = m - lo;
 }
 
-// Pair arrays and the slot -> pair map; a slot (k, i) with j < i maps to
-// the pair owned by j, found by bisection in j's row.
+// Pair arrays and, for every pair, the row slot it occupies in each of the
+// two rows; a slot (k, i) with j < i belongs to the pair owned by j, found
+// by bisection in j's row.
 __device__ inline void pair_fill(const SysParams &p, const ListPtrs &l, int i)
 {
     const int n = p.n, m = l.n_nbr[i], k0 = l.klo[i];
@@ -158,11 +168,10 @@ __device__ inline void pair_fill(const SysParams &p, const ListPtrs &l, int i)
         int q = -1;
         if (k >= k0) {
             q = l.pstart[i] + (k - k0);
-            if (q < p.max_pairs) {
-                l.pi[q] = i;
-                l.pj[q] = j;
-            } else {
-                q = -1;  // only after a row overflow, which is reported
+            if (q < p.max_pairs) {  // (q beyond the capacity only after a row overflow, which is reported)
+                l.pairs[q].x = i;
+                l.pairs[q].y = j;
+                l.pairs[q].z = k;
             }
         } else {
             int lo = l.klo[j], hi = l.n_nbr[j];
@@ -172,9 +181,8 @@ __device__ inline void pair_fill(const SysParams &p, const ListPtrs &l, int i)
                 else hi = mid;
             }
             if (lo < l.n_nbr[j] && l.nbr[(size_t)lo * n + j] == i) q = l.pstart[j] + (lo - l.klo[j]);
-            if (q >= p.max_pairs) q = -1;
+            if (q >= 0 && q < p.max_pairs) l.pairs[q].w = k;
         }
-        l.pidx[(size_t)k * n + i] = q;
     }
 }
 

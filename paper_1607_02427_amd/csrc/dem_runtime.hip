@@ -286,12 +286,12 @@ void free_lists(dem_system *h)
     (void)hipFree(h->lst.xlast);
     (void)hipFree(h->lst.klo);
     (void)hipFree(h->lst.pstart);
-    (void)hipFree(h->lst.pi);
-    (void)hipFree(h->lst.pj);
-    (void)hipFree(h->lst.pidx);
+    (void)hipFree(h->lst.pairs);
     (void)hipFree(h->rec);
     (void)hipFree(h->rot);
+    int32_t *flags = h->lst.flags;  // freed with the handle
     h->lst = ListPtrs{};
+    h->lst.flags = flags;
     h->rec = h->rot = nullptr;
 }
 
@@ -310,26 +310,23 @@ size_t force_word(const dem_system *h) { return h->prm.precision == DEM_FP32 ? s
 dem_status alloc_nbr(dem_system *h, int cap)
 {
     (void)hipFree(h->lst.nbr);
-    (void)hipFree(h->lst.pidx);
-    (void)hipFree(h->lst.pi);
-    (void)hipFree(h->lst.pj);
+    (void)hipFree(h->lst.pairs);
     (void)hipFree(h->rec);
-    h->lst.nbr = h->lst.pidx = h->lst.pi = h->lst.pj = nullptr;
+    h->lst.nbr = nullptr;
+    h->lst.pairs = nullptr;
     h->rec = nullptr;
     const size_t n = (size_t)std::max(h->sp.n, 1);
     const size_t maxp = n * (size_t)cap / 2 + 64;
     if (maxp > (size_t)INT32_MAX) return fail(h, DEM_E_ARG, "pair capacity overflows int32");
     if (hipMalloc(&h->lst.nbr, sizeof(int32_t) * (size_t)cap * n) != hipSuccess ||
-        hipMalloc(&h->lst.pidx, sizeof(int32_t) * (size_t)cap * n) != hipSuccess ||
-        hipMalloc(&h->lst.pi, sizeof(int32_t) * maxp) != hipSuccess ||
-        hipMalloc(&h->lst.pj, sizeof(int32_t) * maxp) != hipSuccess ||
-        hipMalloc(&h->rec, force_word(h) * kRec * maxp) != hipSuccess)
+        hipMalloc(&h->lst.pairs, sizeof(int4) * maxp) != hipSuccess ||
+        hipMalloc(&h->rec, force_word(h) * kRec * (size_t)cap * n) != hipSuccess)
         return fail(h, DEM_E_OOM, "neighbour list of %d x %zu entries", cap, n);
     h->sp.cap = cap;
     h->sp.max_pairs = (int)maxp;
     // grid-stride pair kernel: enough waves to fill the chip, no more than the pairs need
     const size_t want = (maxp + 15) / 16;  // four waves per block, four pairs per wave
-    h->sp.pair_blocks = (int)std::max<size_t>(1, std::min<size_t>(want, 2048));
+    h->sp.pair_blocks = (int)std::max<size_t>(8, std::min<size_t>(want, 2048));
     drop_graph(h);
     return DEM_OK;
 }
@@ -437,8 +434,8 @@ size_t dem_footprint_bytes(const dem_params *p)
     size_t nblk = (n + kBlock - 1) / kBlock;
     const size_t w = p->precision == DEM_FP32 ? sizeof(float) : sizeof(double);
     const size_t maxp = n * (size_t)cap / 2 + 64;
-    return sizeof(int32_t) * (2 * n * (size_t)cap + 6 * n + 2 * ncell + 2 + 2 * maxp) +
-           sizeof(double) * (3 * n + 14 * nblk + TH_COUNT) + w * (9 * n + kRec * maxp) +
+    return sizeof(int32_t) * (n * (size_t)cap + 6 * n + 2 * ncell + 2 + 4 * maxp) +
+           sizeof(double) * (3 * n + 14 * nblk + TH_COUNT) + w * (16 * n + kRec * (size_t)cap * n) +
            2 * DEM_MAX_SHAPES * sizeof(ShapeTab<double>) + 256;
 }
 
@@ -557,7 +554,8 @@ dem_status dem_create_system(const dem_params *params, const dem_state_ptrs *sta
               hipMalloc(&h->lst.xlast, sizeof(double) * 3 * n) == hipSuccess &&
               hipMalloc(&h->lst.klo, sizeof(int32_t) * n) == hipSuccess &&
               hipMalloc(&h->lst.pstart, sizeof(int32_t) * (n + 1)) == hipSuccess &&
-              hipMalloc(&h->rot, (p.precision == DEM_FP32 ? sizeof(float) : sizeof(double)) * 9 * n) == hipSuccess;
+              hipMalloc(&h->rot, (p.precision == DEM_FP32 ? sizeof(PartRec<float>) : sizeof(PartRec<double>)) * n) ==
+                  hipSuccess;
     if (!ok) return bail(fail(h, DEM_E_OOM, "device allocation failed"));
     if (sp.n > 0) {  // shape ids index the LDS tables: validate before any kernel reads them
         std::vector<int32_t> sid((size_t)sp.n);
