@@ -200,8 +200,74 @@ dem_status dem_set_counting(dem_handle h, int32_t on);
 dem_status dem_time_forces(dem_handle h, int32_t reps, double *mean_ms);
 
 /* Bytes of device memory the library would allocate for these parameters
- * (lists, cells, scratch), excluding caller-owned state and outputs. */
+ * (lists, cells, scratch), excluding caller-owned state and outputs.  For a
+ * replica of a batch this is its share of the batch's arrays, less its state
+ * and outputs (16 doubles and 4 ints per particle). */
 size_t dem_footprint_bytes(const dem_params *params);
+
+/* ---- Batches of independent replicas ------------------------------------
+ * A batch handle holds many independent periodic systems ("replicas") of
+ * one dimension and one force precision, of any sizes and shapes, and
+ * advances all of them with one launch per kernel per step: the pair
+ * kernel walks one list of tiles (16 particle pairs of one replica each)
+ * over every replica, the list build runs one workgroup per replica, and
+ * the integrator and force gather cover every replica's particles.  A
+ * replica's arithmetic does not depend on which other replicas share the
+ * batch: its results are the same bit for bit alone, in any mix, and as a
+ * single system (dem_create_system).  Replicas may be added and removed
+ * between calls; each keeps its state in the batch's own device arrays.
+ * The batch calls below are asynchronous on the batch's stream unless
+ * noted; dem_step, dem_compute_forces, dem_sync, dem_force_stats,
+ * dem_set_counting and dem_time_forces accept a batch handle and act on all
+ * live replicas. */
+typedef struct {
+    int32_t dim;                  /* 2 or 3: every replica's */
+    int32_t precision;            /* DEM_FP64 or DEM_FP32: every replica's */
+    int32_t max_replicas;         /* replica slots */
+    int64_t max_particles;        /* particle slots (replicas take multiples of 64) */
+    int64_t max_cells;            /* cell slots (a replica takes its cell count + 1); 0 = particles + 2 per replica */
+    int32_t max_shapes;           /* shape-table slots; 0 = DEM_MAX_SHAPES per replica */
+    int32_t nbr_capacity;         /* neighbour-row capacity of every replica; 0 = grows as replicas need */
+} dem_batch_params;
+
+/* Creates an empty batch; allocates all its device memory.  Synchronises. */
+dem_status dem_batch_create(const dem_batch_params *params, void *hip_stream, dem_handle *out);
+
+/* Adds a replica: validates params (dim and precision must match the
+ * batch; n <= 65536), copies the state from the caller's device arrays
+ * (dem_state_ptrs, borrowed for the call only), builds its lists and
+ * computes its forces.  The replica then advances with every dem_step for
+ * `steps` steps (0 = without limit) and is held still after that.  Returns
+ * DEM_E_OOM when no run of free particle, cell or shape slots fits it, and
+ * DEM_E_CAPACITY when rows overflow a fixed capacity.  Synchronises. */
+dem_status dem_batch_add(dem_handle h, const dem_params *params, const dem_state_ptrs *state, int64_t steps,
+                         int32_t *replica_id);
+
+/* Removes a replica and frees its slots.  Synchronises. */
+dem_status dem_batch_remove(dem_handle h, int32_t replica_id);
+
+/* Copies a replica's state and outputs (either may be NULL, as may any of
+ * their arrays) to caller-owned device arrays of its length; W as [9][n]. */
+dem_status dem_batch_read(dem_handle h, int32_t replica_id, const dem_state_ptrs *state,
+                          const dem_output_ptrs *outputs);
+
+/* Sets the steps a replica has left (0 holds it still). */
+dem_status dem_batch_set_steps(dem_handle h, int32_t replica_id, int64_t steps);
+
+/* Steps left and steps done of replica slots 0..count-1 (-1 for free slots;
+ * either array may be NULL), and latched device errors.  Synchronises. */
+dem_status dem_batch_progress(dem_handle h, int64_t *steps_left, int64_t *steps_done, int32_t count);
+
+/* out[8]: live replicas, replica slots, free particle slots, largest run of
+ * free particle slots, free cell slots, free shape slots, row capacity,
+ * particle slots. */
+dem_status dem_batch_info(dem_handle h, int64_t *out);
+
+/* dem_energy and dem_copy_lists for one replica of a batch (replica 0 is
+ * what those calls report).  Synchronise. */
+dem_status dem_replica_energy(dem_handle h, int32_t replica_id, dem_energy_out *out);
+dem_status dem_replica_lists(dem_handle h, int32_t replica_id, int32_t *cell_start, int32_t *cell_particles,
+                             int32_t *nbr, int32_t *n_nbr, int32_t *dims);
 
 const char *dem_status_string(dem_status s);
 const char *dem_last_error(dem_handle h);

@@ -33,6 +33,8 @@
 // segment pairs that are nearly parallel (sin^2 < 1e-2) and near the cutoff
 // are redone in FP64, because their closest points are ill-conditioned in
 // FP32 (error ~ eps / sin).
+#include <algorithm>
+
 #include "dem_internal.h"
 
 namespace dem {
@@ -351,48 +353,120 @@ __device__ inline int group_append(bool keep, unsigned char *list, int len, int 
     return len + __popcll(m & gmask);
 }
 
-// FP64 redo of an FP32 edge-edge problem whose closest points are
-// ill-conditioned (nearly parallel edges near the cutoff).
-template <typename T>
-__device__ void refine_edges(const SysParams &p, const StatePtrs &s, int i, int j, const ShapeTab<double> &Di,
-                             const ShapeTab<double> &Dj, int e, int g, V3<T> &Pt, V3<T> &rho)
+// FP64 redo of one FP32 feature-pair problem and of its WCA terms, added to
+// A: family 0 is vertex x of i against face (2D: edge) y of j, family 1
+// vertex x of j against face (edge) y of i, family 2 edge x of i against
+// edge y of j.  It is used where FP32 cannot resolve the answer: within 1%
+// of the cutoff, where the force is a steep function of the distance
+// (dF/dr = 72 eps / r_cut^2 there), and for nearly parallel edges, whose
+// closest points are ill-conditioned (error ~ eps / sin).  Returns 1 if the
+// pair is inside the cutoff.
+template <typename T, int DIM>
+__device__ int refine_pair(const double *box, double eps, double par_s2, const PartRec64 &ri, const PartRec64 &rj,
+                           const ShapeTab<double> &Di, const ShapeTab<double> &Dj, int fam, int x, int y, double sig,
+                           Acc<T> &A)
 {
     double Rd[9], Rjd[9];
-    quat_to_rot(s.qw[i], s.qx[i], s.qy[i], s.qz[i], Rd);
-    quat_to_rot(s.qw[j], s.qx[j], s.qy[j], s.qz[j], Rjd);
-    M3<double> Rrd, Rid;
+    quat_to_rot(ri.qw, ri.qx, ri.qy, ri.qz, Rd);
+    quat_to_rot(rj.qw, rj.qx, rj.qy, rj.qz, Rjd);
+    M3<double> Rr, Ri;
     for (int a = 0; a < 3; ++a)
-        for (int b = 0; b < 3; ++b)
-            Rrd.m[3 * a + b] = Rd[a] * Rjd[b] + Rd[3 + a] * Rjd[3 + b] + Rd[6 + a] * Rjd[6 + b];
-    for (int k = 0; k < 9; ++k) Rid.m[k] = Rd[k];
-    const V3<double> dd = v3<double>(min_image(s.x[j] - s.x[i], p.box[0]), min_image(s.y[j] - s.y[i], p.box[1]),
-                                     min_image(s.z[j] - s.z[i], p.box[2]));
-    const V3<double> td = mulT(Rid, dd);
-    const V3<double> b0 = td + mul(Rrd, ld3(Dj.v[Dj.e[g][0]]));
-    const V3<double> d2 = mul(Rrd, ld3(Dj.ed[g]));
-    V3<double> Pd, Qd;
-    seg_seg(ld3(Di.v[Di.e[e][0]]), ld3(Di.ed[e]), Di.el2[e], Di.einv[e], b0, d2, Dj.el2[g], Dj.einv[g], p.par_s2,
-            Pd, Qd);
-    Pt = cvt<T>(Pd);
-    rho = cvt<T>(Pd - Qd);
+        for (int c = 0; c < 3; ++c)
+            Rr.m[3 * a + c] = Rd[a] * Rjd[c] + Rd[3 + a] * Rjd[3 + c] + Rd[6 + a] * Rjd[6 + c];
+    for (int k = 0; k < 9; ++k) Ri.m[k] = Rd[k];
+    const V3<double> dd = v3<double>(min_image(rj.x - ri.x, box[0]), min_image(rj.y - ri.y, box[1]),
+                                     DIM == 3 ? min_image(rj.z - ri.z, box[2]) : 0.0);
+    const V3<double> td = mulT(Ri, dd);  // j's centre in i's frame
+    V3<double> P, rho;
+    if (fam == 0) {
+        const V3<double> pt = mulT(Rr, ld3(Di.v[x]) - td);  // i's vertex in j's frame
+        const V3<double> q = (DIM == 3) ? face_point(Dj, y, pt)
+                                        : seg_point(pt, ld3(Dj.v[Dj.e[y][0]]), ld3(Dj.ed[y]), Dj.einv[y]);
+        P = ld3(Di.v[x]);
+        rho = mul(Rr, pt - q);
+    } else if (fam == 1) {
+        const V3<double> pt = td + mul(Rr, ld3(Dj.v[x]));  // j's vertex in i's frame
+        P = (DIM == 3) ? face_point(Di, y, pt) : seg_point(pt, ld3(Di.v[Di.e[y][0]]), ld3(Di.ed[y]), Di.einv[y]);
+        rho = P - pt;
+    } else {
+        const V3<double> b0 = td + mul(Rr, ld3(Dj.v[Dj.e[y][0]]));
+        const V3<double> d2 = mul(Rr, ld3(Dj.ed[y]));
+        V3<double> Q;
+        seg_seg(ld3(Di.v[Di.e[x][0]]), ld3(Di.ed[x]), Di.el2[x], Di.einv[x], b0, d2, Dj.el2[y], Dj.einv[y], par_s2,
+                P, Q);
+        rho = P - Q;
+    }
+    const double rc = kWcaCut * sig;
+    Acc<double> B;
+    B.F = B.Ti = B.Tj = v3<double>(0, 0, 0);
+    B.U = 0.0;
+    const int hit = add_wca(B, P, rho, td, sig * sig, rc * rc, eps);
+    if (hit) {
+        A.F = A.F + cvt<T>(B.F);
+        A.Ti = A.Ti + cvt<T>(B.Ti);
+        A.Tj = A.Tj + cvt<T>(B.Tj);
+        A.U += (T)B.U;
+    }
+    return hit;
 }
 
+// The current replica of a pair-kernel block, staged in LDS beside its
+// shape tables.
+struct alignas(16) RepLds {
+    double box[3];
+    double R[DEM_MAX_SHAPES], rad[DEM_MAX_SHAPES];
+    double eps, par_s2;
+    int r, sbase, np, poff, first_tile, pad[3];
+};
+
+// Stages replica r: its shape tables and parameters.  Every thread of the
+// block calls it together.
+template <typename T>
+__device__ void stage_replica(const SysParams *reps, const ListPtrs &l, const ShapeTab<T> *gtab, ShapeTab<T> *tab,
+                              RepLds &rl, int r)
+{
+    __syncthreads();
+    const SysParams &p = reps[r];
+    const int words = p.n_shapes * (int)(sizeof(ShapeTab<T>) / 4);
+    const uint32_t *src = reinterpret_cast<const uint32_t *>(gtab + p.sbase);
+    uint32_t *dst = reinterpret_cast<uint32_t *>(tab);
+    for (int w = threadIdx.x; w < words; w += blockDim.x) dst[w] = src[w];
+    if (threadIdx.x < DEM_MAX_SHAPES) {
+        rl.R[threadIdx.x] = p.R[threadIdx.x];
+        rl.rad[threadIdx.x] = p.rad[threadIdx.x];
+    }
+    if (threadIdx.x == 0) {
+        for (int a = 0; a < 3; ++a) rl.box[a] = p.box[a];
+        rl.eps = p.eps;
+        rl.par_s2 = p.par_s2;
+        rl.r = r;
+        rl.sbase = p.sbase;
+        rl.np = l.flags[r * FLAG_COUNT + FLAG_NPAIRS];
+        rl.poff = p.poff;
+        rl.first_tile = l.tile_start[r];
+    }
+    __syncthreads();
+}
+
+// One block of 4 waves takes a contiguous range of tiles (16 pairs of one
+// replica each; wave w takes pairs 4w..4w+3 of a tile, 16 lanes per pair).
+// Blocks are dealt round-robin to the 8 XCDs, so block b runs on XCD b % 8:
+// XCD x gets the x-th eighth of the tiles, and pairs of neighbouring
+// particles share its L2.  The tables of the block's current replica live
+// in LDS and are restaged when its range crosses into the next replica.
 template <typename T, int DIM>
-__global__ void __launch_bounds__(64 * kWaves) k_pairs(SysParams p, StatePtrs s, ListPtrs l, const PartRec<T> *__restrict__ prec,
+__global__ void __launch_bounds__(64 * kWaves) k_pairs(BatchParams b, const SysParams *__restrict__ reps, StatePtrs s,
+                                                          ListPtrs l, const PartRec<T> *__restrict__ prec,
+                                                          const PartRec64 *__restrict__ rec64,
                                                           T *__restrict__ rec, const ShapeTab<T> *__restrict__ gtab,
                                                           const ShapeTab<double> *__restrict__ gtab64,
                                                           unsigned long long *stats)
 {
     extern __shared__ __align__(16) unsigned char smem[];
+    const size_t orl = b.tab_slots * sizeof(ShapeTab<T>);
     ShapeTab<T> *tab = reinterpret_cast<ShapeTab<T> *>(smem);
-    PairLds<T> *pls = reinterpret_cast<PairLds<T> *>(smem + p.n_shapes * sizeof(ShapeTab<T>));
-    {
-        const int words = p.n_shapes * (int)(sizeof(ShapeTab<T>) / 4);
-        const uint32_t *src = reinterpret_cast<const uint32_t *>(gtab);
-        uint32_t *dst = reinterpret_cast<uint32_t *>(smem);
-        for (int w = threadIdx.x; w < words; w += blockDim.x) dst[w] = src[w];
-    }
-    __syncthreads();
+    RepLds &rl = *reinterpret_cast<RepLds *>(smem + orl);
+    PairLds<T> *pls = reinterpret_cast<PairLds<T> *>(smem + orl + sizeof(RepLds));
 
     const int lane = __lane_id();
     const int wid = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -400,28 +474,42 @@ __global__ void __launch_bounds__(64 * kWaves) k_pairs(SysParams p, StatePtrs s,
     PairLds<T> &W = pls[wid * kGroups + grp];
     const unsigned long long gmask = 0xffffull << (kGL * grp);
     const unsigned long long below = lanes_below();
-    const int n = p.n;
-    const int npairs = l.flags[FLAG_NPAIRS];
-    // XCD-aware order: blocks are dealt round-robin to the 8 XCDs, so each
-    // XCD takes a contiguous eighth of the pair list (pairs of neighbouring
-    // particles share its L2) and its blocks stride through that range.
-    const int G = gridDim.x;
-    const int xcd = blockIdx.x & 7, slot = blockIdx.x >> 3;
-    const int xblocks = (G + 7 - xcd) >> 3;
-    const int per_xcd = (npairs + 7) >> 3;
-    const int x_lo = min(xcd * per_xcd, npairs), x_hi = min(x_lo + per_xcd, npairs);
-    const T par_s2 = (T)p.par_s2;
-    const T eps = (T)p.eps;
+    const size_t N = (size_t)b.N;
+    const int ntiles = l.tile_start[b.nrep];
+    const int G = gridDim.x, per = G >> 3;
+    const int lb = (blockIdx.x & 7) * per + (blockIdx.x >> 3);
+    const int t0 = (int)((long long)ntiles * lb / G), t1 = (int)((long long)ntiles * (lb + 1) / G);
     const T grow = T(1.00001);
     unsigned long long c_pairs = 0, c_feat = 0, c_in = 0, c_near = 0, c_ee = 0, c_ref = 0;
 
-    for (int base = x_lo + (slot * kWaves + wid) * kGroups; base < x_hi; base += xblocks * kWaves * kGroups) {
-        const int pr = base + grp;
-        const bool active = pr < x_hi;
+    int r = 0, r_end = 0;
+    if (t0 < t1) {  // replica of the first tile: the last r with tile_start[r] <= t0
+        int lo = 0, hi = b.nrep;
+        while (hi - lo > 1) {
+            const int mid = (lo + hi) >> 1;
+            if (l.tile_start[mid] <= t0) lo = mid;
+            else hi = mid;
+        }
+        r = lo;
+        r_end = l.tile_start[r + 1];
+        stage_replica(reps, l, gtab, tab, rl, r);
+    }
+    for (int tt = t0; tt < t1; ++tt) {
+        if (tt >= r_end) {
+            do {
+                ++r;
+                r_end = l.tile_start[r + 1];
+            } while (tt >= r_end);
+            stage_replica(reps, l, gtab, tab, rl, r);
+        }
+        const int q = (tt - rl.first_tile) * kTile + wid * kGroups + grp;
+        const bool active = q < rl.np;
+        const T par_s2 = (T)rl.par_s2;
+        const T eps = (T)rl.eps;
         // two dependent round trips: the pair entry, then both particle
         // records (position, rotation and shape in one line each)
         int4 ent = make_int4(0, 0, 0, 0);
-        if (active) ent = l.pairs[pr];
+        if (active) ent = l.pairs[rl.poff + q];
         const int i = ent.x, j = ent.y;
         int si = 0, sj = 0;
         double dx = 0.0, dy = 0.0, dz = 0.0;
@@ -435,17 +523,17 @@ __global__ void __launch_bounds__(64 * kWaves) k_pairs(SysParams p, StatePtrs s,
                 Ri.m[k] = ri.R[k];
                 Rj.m[k] = rj.R[k];
             }
-            dx = min_image(rj.x - ri.x, p.box[0]);
-            dy = min_image(rj.y - ri.y, p.box[1]);
-            dz = (DIM == 3) ? min_image(rj.z - ri.z, p.box[2]) : 0.0;
+            dx = min_image(rj.x - ri.x, rl.box[0]);
+            dy = min_image(rj.y - ri.y, rl.box[1]);
+            dz = (DIM == 3) ? min_image(rj.z - ri.z, rl.box[2]) : 0.0;
             si = ri.sid;
             sj = rj.sid;
-            const double bound = p.R[si] + p.R[sj] + kWcaCut * (p.rad[si] + p.rad[sj]);
+            const double bound = rl.R[si] + rl.R[sj] + kWcaCut * (rl.rad[si] + rl.rad[sj]);
             live = dx * dx + dy * dy + dz * dz < bound * bound;
             if (!live && sub < kRec) {  // zero both row slots of a pair out of reach
-                const size_t cs = (size_t)sub * p.cap * n;
-                rec[cs + (size_t)ent.z * n + i] = T(0);
-                rec[cs + (size_t)ent.w * n + j] = T(0);
+                const size_t cs = (size_t)sub * b.cap * N;
+                rec[cs + (size_t)ent.z * N + i] = T(0);
+                if (ent.w >= 0) rec[cs + (size_t)ent.w * N + j] = T(0);
             }
         }
         if (__ballot(live) == 0) continue;
@@ -457,16 +545,17 @@ __global__ void __launch_bounds__(64 * kWaves) k_pairs(SysParams p, StatePtrs s,
         for (int k = 0; k < 9; ++k) Rr.m[k] = T(0);
         if (live) {
             for (int a = 0; a < 3; ++a)
-                for (int b = 0; b < 3; ++b)
-                    Rr.m[3 * a + b] = Ri.m[a] * Rj.m[b] + Ri.m[3 + a] * Rj.m[3 + b] + Ri.m[6 + a] * Rj.m[6 + b];
+                for (int c = 0; c < 3; ++c)
+                    Rr.m[3 * a + c] = Ri.m[a] * Rj.m[c] + Ri.m[3 + a] * Rj.m[3 + c] + Ri.m[6 + a] * Rj.m[6 + c];
             t = mulT(Ri, v3<T>((T)dx, (T)dy, (T)dz));
-            const double sigd = p.rad[si] + p.rad[sj];
+            const double sigd = rl.rad[si] + rl.rad[sj];
             sig2 = (T)(sigd * sigd);
             rc = (T)(kWcaCut * sigd);
-            Bi = (T)p.R[si] + rc;
-            Bj = (T)p.R[sj] + rc;
+            Bi = (T)rl.R[si] + rc;
+            Bj = (T)rl.R[sj] + rc;
         }
         const T rc2 = rc * rc;
+        const T rcm = rc * T(1.0001);  // the cull keeps pairs FP32 may place just outside the cutoff
 
         // Feature prefilter (conservative): a vertex, edge or face can touch
         // the other body only if it lies within R_other + r_cut of that body's
@@ -565,7 +654,7 @@ __global__ void __launch_bounds__(64 * kWaves) k_pairs(SysParams p, StatePtrs s,
             const bool has = q < total;
             const bool last = __ballot(has) == 0;
             if (!last) {
-                const bool keep = has && P.candidate(q, rc);
+                const bool keep = has && P.candidate(q, rcm);
                 const unsigned long long m = __ballot(keep);
                 if (keep) W.queue[count + __popcll(m & below & gmask)] = (unsigned short)q;
                 count += __popcll(m & gmask);
@@ -582,12 +671,17 @@ __global__ void __launch_bounds__(64 * kWaves) k_pairs(SysParams p, StatePtrs s,
                         const int fam = P.solve(W.queue[k], par_s2, Pt, rho, sin2, e, g);
                         c_near += fam < 2 ? 1 : 0;
                         c_ee += fam == 2 ? 1 : 0;
-                        if (sizeof(T) == 4 && DIM == 3 && fam == 2 && sin2 < T(1e-2) &&
-                            dot(rho, rho) < T(1.0001) * rc2 + T(1e-3) * rc) {
-                            refine_edges(p, s, i, j, gtab64[si], gtab64[sj], e, g, Pt, rho);
+                        const T r2 = dot(rho, rho);
+                        const bool redo = sizeof(T) == 4 &&
+                                          ((r2 > T(0.99) * rc2 && r2 < T(1.0001) * rc2) ||
+                                           (DIM == 3 && fam == 2 && sin2 < T(1e-2) && r2 < T(1.0001) * rc2 + T(1e-3) * rc));
+                        if (redo) {
                             c_ref += 1;
+                            c_in += refine_pair<T, DIM>(rl.box, rl.eps, rl.par_s2, rec64[i], rec64[j],
+                                                        gtab64[rl.sbase + si], gtab64[rl.sbase + sj], fam, e, g, rl.rad[si] + rl.rad[sj], A);
+                        } else {
+                            c_in += add_wca(A, Pt, rho, t, sig2, rc2, eps);
                         }
-                        c_in += add_wca(A, Pt, rho, t, sig2, rc2, eps);
                     }
                 }
                 count = 0;
@@ -619,9 +713,9 @@ __global__ void __launch_bounds__(64 * kWaves) k_pairs(SysParams p, StatePtrs s,
                 vi = (T)(sub == 7 ? dx : (sub == 8 ? dy : dz));
                 vj = -vi;
             }
-            const size_t cs = (size_t)sub * p.cap * n;
-            rec[cs + (size_t)ent.z * n + i] = vi;
-            rec[cs + (size_t)ent.w * n + j] = vj;
+            const size_t cs = (size_t)sub * b.cap * N;
+            rec[cs + (size_t)ent.z * N + i] = vi;
+            if (ent.w >= 0) rec[cs + (size_t)ent.w * N + j] = vj;
         }
     }
     if (stats) {
@@ -684,49 +778,60 @@ __device__ inline double nh_half(const SysParams &p, double &xi, double &eta, do
 }
 
 // Per-particle sums of the row-slot records, optionally fused with the
-// closing kick.  Each particle's row is split over kGatherLanes lanes (lane
-// l takes slots l, l + kGatherLanes, ... in order) and combined by a fixed
-// butterfly, so the result does not depend on scheduling.  With NVT the block's
-// kinetic partial is published and the last block to finish (ticket
-// counter, no waiting) applies the step's closing Nose-Hoover half step and
-// the next step's opening one.
-template <typename T, int DIM, bool KICK, bool NVT>
-__global__ void __launch_bounds__(kBlock) k_gather(SysParams p, StatePtrs s, OutPtrs o, ListPtrs l,
-                                                      const T *__restrict__ rec, double *ke_part, double *th)
+// closing kick.  One block per chunk, so a block belongs to one replica.
+// Each particle's row is split over kGatherLanes lanes (lane l takes slots
+// l, l + kGatherLanes, ... in order) and combined by a fixed butterfly, so
+// the result does not depend on scheduling.  With the kick, the last block
+// of a replica to finish (ticket counter, no waiting) spends one step of the
+// replica's budget and, with NVT, applies the step's closing Nose-Hoover
+// half step and the next step's opening one from the replica's per-chunk
+// kinetic partials, summed in chunk order.  A replica with no budget left is
+// skipped.
+template <typename T, int DIM, bool KICK>
+__global__ void __launch_bounds__(kBlock) k_gather(BatchParams b, const SysParams *reps, StatePtrs s, OutPtrs o,
+                                                      ListPtrs l, const T *__restrict__ rec, double *ke_part,
+                                                      double *thermo, int64_t *budget, int64_t *steps)
 {
     __shared__ double sh[kBlock];
     __shared__ int last;
+    const int r = l.chunk_rep[blockIdx.x];
+    if (r < 0) return;
+    const SysParams &p = reps[r];
+    int32_t *fl = l.flags + r * FLAG_COUNT;
+    if (KICK && budget[r] <= 0) return;
     const int sub = threadIdx.x % kGatherLanes;
     const int i = blockIdx.x * kGatherPer + threadIdx.x / kGatherLanes;
-    if (blockIdx.x == 0 && threadIdx.x == 0 && l.flags[FLAG_REBUILD] != 0) {
+    const bool nvt = KICK && p.ensemble == DEM_NVT;
+    if (blockIdx.x * kChunk == p.off && threadIdx.x == 0 && fl[FLAG_REBUILD] != 0) {
         // the lists consumed by this step are fresh: count the build and clear the trigger
-        l.flags[FLAG_REBUILD] = 0;
-        l.flags[FLAG_NBUILDS] += 1;
+        fl[FLAG_REBUILD] = 0;
+        fl[FLAG_NBUILDS] += 1;
     }
-    const int n = p.n;
+    const size_t N = (size_t)b.N;
+    const bool mine = i < p.off + p.n;
     double acc[16];
     for (int c = 0; c < 16; ++c) acc[c] = 0.0;  // F[3], T[3], U, W[9]
-    if (i < n) {
+    if (mine) {
         const int m = l.n_nbr[i];
-        const size_t cs = (size_t)p.cap * n;
+        const size_t cs = (size_t)b.cap * N;
 #pragma unroll 2
         for (int k = sub; k < m; k += kGatherLanes) {
-            const T *r = rec + (size_t)k * n + i;  // component c at r[c * cs]
-            const double f[3] = {(double)r[0], (double)r[cs], (double)r[2 * cs]};
+            const T *rp = rec + (size_t)k * N + i;  // component c at rp[c * cs]
+            const double f[3] = {(double)rp[0], (double)rp[cs], (double)rp[2 * cs]};
             for (int a = 0; a < 3; ++a) {
                 acc[a] += f[a];
-                acc[3 + a] += (double)r[(3 + a) * cs];
+                acc[3 + a] += (double)rp[(3 + a) * cs];
             }
-            acc[6] += 0.5 * (double)r[6 * cs];
-            const double d[3] = {(double)r[7 * cs], (double)r[8 * cs], (double)r[9 * cs]};
+            acc[6] += 0.5 * (double)rp[6 * cs];
+            const double d[3] = {(double)rp[7 * cs], (double)rp[8 * cs], (double)rp[9 * cs]};
             for (int a = 0; a < 3; ++a)
-                for (int b = 0; b < 3; ++b) acc[7 + 3 * a + b] -= 0.5 * d[a] * f[b];
+                for (int c = 0; c < 3; ++c) acc[7 + 3 * a + c] -= 0.5 * d[a] * f[c];
         }
     }
     for (int off = 1; off < kGatherLanes; off <<= 1)
         for (int c = 0; c < 16; ++c) acc[c] += __shfl_xor(acc[c], off, kGatherLanes);
     double kt = 0.0, kr = 0.0;
-    if (i < n && sub == 0) {
+    if (mine && sub == 0) {
         double *F = acc, *Tq = acc + 3;
         if (DIM == 2) {
             F[2] = 0.0;
@@ -739,7 +844,7 @@ __global__ void __launch_bounds__(kBlock) k_gather(SysParams p, StatePtrs s, Out
         o.Ty[i] = Tq[1];
         o.Tz[i] = Tq[2];
         o.U[i] = acc[6];
-        for (int c = 0; c < 9; ++c) o.W[(size_t)c * n + i] = acc[7 + c];
+        for (int c = 0; c < 9; ++c) o.W[(size_t)c * b.wstride + i] = acc[7 + c];
         if (KICK) {
             const int sid = s.sid[i];
             const double hm = 0.5 * p.dt / p.mass[sid];
@@ -763,124 +868,159 @@ __global__ void __launch_bounds__(kBlock) k_gather(SysParams p, StatePtrs s, Out
                 L[2] = s.Lz[i] + 0.5 * p.dt * Tq[2];
                 s.Lz[i] = L[2];
             }
-            if (NVT) {
+            if (nvt) {
                 kt = 0.5 * p.mass[sid] * (v[0] * v[0] + v[1] * v[1] + v[2] * v[2]);
                 for (int a = 0; a < 3; ++a)
                     if (p.inertia[sid][a] > 0.0) kr += 0.5 * L[a] * L[a] / p.inertia[sid][a];
             }
         }
     }
-    if (KICK && NVT) {
+    if (!KICK) return;
+    if (nvt) {
         kt = block_sum<kBlock>(kt, sh);
         kr = block_sum<kBlock>(kr, sh);
-        if (threadIdx.x == 0) {
+    }
+    const int nblk = (p.n + kChunk - 1) / kChunk;
+    if (threadIdx.x == 0) {
+        if (nvt) {
             ke_part[2 * blockIdx.x] = kt;
             ke_part[2 * blockIdx.x + 1] = kr;
-            __threadfence();
-            const int ticket = atomicAdd(&l.flags[FLAG_TICKET], 1);
-            last = (ticket == (int)gridDim.x - 1);
         }
-        __syncthreads();
-        if (last) {
-            __threadfence();
-            double acc2 = 0.0;
-            for (int b = threadIdx.x; b < (int)gridDim.x; b += blockDim.x) {
-                const volatile double *vp = ke_part;
-                acc2 += vp[2 * b] + vp[2 * b + 1];
-            }
-            double K = block_sum<kBlock>(acc2, sh);
-            if (threadIdx.x == 0) {
-                double xi = th[TH_XI], eta = th[TH_ETA];
-                const double sb = nh_half(p, xi, eta, K);  // closes this step
-                th[TH_XI_B] = xi;
-                th[TH_ETA_B] = eta;
-                th[TH_SCALE_B] = sb;
-                const double sa = nh_half(p, xi, eta, K);  // opens the next step
-                th[TH_XI] = xi;
-                th[TH_ETA] = eta;
-                th[TH_SCALE] = sb * sa;
-                l.flags[FLAG_TICKET] = 0;
-            }
+        __threadfence();
+        const int ticket = atomicAdd(&fl[FLAG_TICKET], 1);
+        last = (ticket == nblk - 1);
+    }
+    __syncthreads();
+    if (!last) return;
+    __threadfence();
+    if (nvt) {
+        const int c0 = p.off / kChunk;
+        const volatile double *vp = ke_part;
+        double acc2 = 0.0;
+        for (int c = threadIdx.x; c < nblk; c += blockDim.x) acc2 += vp[2 * (c0 + c)] + vp[2 * (c0 + c) + 1];
+        double K = block_sum<kBlock>(acc2, sh);
+        if (threadIdx.x == 0) {
+            double *th = thermo + r * TH_COUNT;
+            double xi = th[TH_XI], eta = th[TH_ETA];
+            const double sb = nh_half(p, xi, eta, K);  // closes this step
+            th[TH_XI_B] = xi;
+            th[TH_ETA_B] = eta;
+            th[TH_SCALE_B] = sb;
+            const double sa = nh_half(p, xi, eta, K);  // opens the next step
+            th[TH_XI] = xi;
+            th[TH_ETA] = eta;
+            th[TH_SCALE] = sb * sa;
         }
+    }
+    if (threadIdx.x == 0) {
+        budget[r] -= 1;
+        steps[r] += 1;
+        fl[FLAG_TICKET] = 0;
     }
 }
 
 template <typename T>
-__global__ void k_rotations(SysParams p, StatePtrs s, PartRec<T> *rot)
+__global__ void k_rotations(BatchParams b, const SysParams *reps, StatePtrs s, ListPtrs l, PartRec<T> *rot,
+                            PartRec64 *rec64)
 {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= p.n) return;
+    const int c = i / kChunk;
+    if (c >= b.nchunk) return;
+    const int r = l.chunk_rep[c];
+    if (r < 0 || i >= reps[r].off + reps[r].n) return;
     double R[9];
     quat_to_rot(s.qw[i], s.qx[i], s.qy[i], s.qz[i], R);
-    PartRec<T> r;
-    r.x = s.x[i];
-    r.y = s.y[i];
-    r.z = p.dim == 3 ? s.z[i] : 0.0;
-    for (int k = 0; k < 9; ++k) r.R[k] = (T)R[k];
-    r.sid = s.sid[i];
-    rot[i] = r;
+    PartRec<T> rc;
+    rc.x = s.x[i];
+    rc.y = s.y[i];
+    rc.z = b.dim == 3 ? s.z[i] : 0.0;
+    for (int k = 0; k < 9; ++k) rc.R[k] = (T)R[k];
+    rc.sid = s.sid[i];
+    rot[i] = rc;
+    if (sizeof(T) == 4) rec64[i] = PartRec64{rc.x, rc.y, rc.z, s.qw[i], s.qx[i], s.qy[i], s.qz[i], 0.0};
 }
 
 template <typename T, int DIM>
-void pairs_t(const SysParams &p, const StatePtrs &s, const ListPtrs &l, const ForcePtrs &f,
-             unsigned long long *stats, hipStream_t stream)
+void pairs_t(const Launch &L, unsigned long long *stats, hipStream_t stream)
 {
-    const size_t sh = (size_t)p.n_shapes * sizeof(ShapeTab<T>) + kWaves * kGroups * sizeof(PairLds<T>);
-    k_pairs<T, DIM><<<p.pair_blocks, 64 * kWaves, sh, stream>>>(
-        p, s, l, reinterpret_cast<const PartRec<T> *>(f.rot), reinterpret_cast<T *>(f.rec),
-        reinterpret_cast<const ShapeTab<T> *>(f.tab), reinterpret_cast<const ShapeTab<double> *>(f.tab64), stats);
+    const size_t sh = pair_kernel_lds(sizeof(T) == 4 ? DEM_FP32 : DEM_FP64, L.b.tab_slots);
+    k_pairs<T, DIM><<<L.b.pair_blocks, 64 * kWaves, sh, stream>>>(
+        L.b, L.reps, L.s, L.l, reinterpret_cast<const PartRec<T> *>(L.f.rot), L.f.rec64, reinterpret_cast<T *>(L.f.rec),
+        reinterpret_cast<const ShapeTab<T> *>(L.f.tab), reinterpret_cast<const ShapeTab<double> *>(L.f.tab64), stats);
 }
 
 template <typename T, int DIM>
-void gather_t(const SysParams &p, const StatePtrs &s, const OutPtrs &o, const ListPtrs &l, const ForcePtrs &f, bool kick,
-              double *ke_part, double *th, hipStream_t stream)
+void gather_t(const Launch &L, bool kick, hipStream_t stream)
 {
-    const T *rec = reinterpret_cast<const T *>(f.rec);
-    const int nb = gather_blocks(p.n);
-    const bool nvt = p.ensemble == DEM_NVT;
-    if (!kick)
-        k_gather<T, DIM, false, false><<<nb, kBlock, 0, stream>>>(p, s, o, l, rec, ke_part, th);
-    else if (nvt)
-        k_gather<T, DIM, true, true><<<nb, kBlock, 0, stream>>>(p, s, o, l, rec, ke_part, th);
+    const T *rec = reinterpret_cast<const T *>(L.f.rec);
+    if (kick)
+        k_gather<T, DIM, true><<<L.b.nchunk, kBlock, 0, stream>>>(L.b, L.reps, L.s, L.o, L.l, rec, L.ke_part,
+                                                                    L.thermo, L.budget, L.steps);
     else
-        k_gather<T, DIM, true, false><<<nb, kBlock, 0, stream>>>(p, s, o, l, rec, ke_part, th);
+        k_gather<T, DIM, false><<<L.b.nchunk, kBlock, 0, stream>>>(L.b, L.reps, L.s, L.o, L.l, rec, L.ke_part,
+                                                                     L.thermo, L.budget, L.steps);
 }
 
 }  // namespace
 
-void launch_rotations(const SysParams &p, const StatePtrs &s, void *rot, int precision, hipStream_t stream)
+void launch_rotations(const Launch &L, hipStream_t stream)
 {
-    if (p.n == 0) return;
-    if (precision == DEM_FP32)
-        k_rotations<float><<<blocks_for(p.n), kBlock, 0, stream>>>(p, s, reinterpret_cast<PartRec<float> *>(rot));
+    if (L.b.nchunk == 0) return;
+    const int nb = blocks_for(L.b.nchunk * kChunk);
+    if (L.precision == DEM_FP32)
+        k_rotations<float><<<nb, kBlock, 0, stream>>>(L.b, L.reps, L.s, L.l, reinterpret_cast<PartRec<float> *>(L.f.rot),
+                                                      L.f.rec64);
     else
-        k_rotations<double><<<blocks_for(p.n), kBlock, 0, stream>>>(p, s, reinterpret_cast<PartRec<double> *>(rot));
+        k_rotations<double><<<nb, kBlock, 0, stream>>>(L.b, L.reps, L.s, L.l, reinterpret_cast<PartRec<double> *>(L.f.rot),
+                                                       L.f.rec64);
 }
 
-void launch_pairs(const SysParams &p, const StatePtrs &s, const ListPtrs &l, const ForcePtrs &f, int precision,
-                  unsigned long long *stats, hipStream_t stream)
+void launch_pairs(const Launch &L, unsigned long long *stats, hipStream_t stream)
 {
-    if (p.n == 0) return;
-    if (precision == DEM_FP32) {
-        if (p.dim == 3) pairs_t<float, 3>(p, s, l, f, stats, stream);
-        else pairs_t<float, 2>(p, s, l, f, stats, stream);
+    if (L.b.nchunk == 0) return;
+    if (L.precision == DEM_FP32) {
+        if (L.b.dim == 3) pairs_t<float, 3>(L, stats, stream);
+        else pairs_t<float, 2>(L, stats, stream);
     } else {
-        if (p.dim == 3) pairs_t<double, 3>(p, s, l, f, stats, stream);
-        else pairs_t<double, 2>(p, s, l, f, stats, stream);
+        if (L.b.dim == 3) pairs_t<double, 3>(L, stats, stream);
+        else pairs_t<double, 2>(L, stats, stream);
     }
 }
 
-void launch_gather(const SysParams &p, const StatePtrs &s, const OutPtrs &o, const ListPtrs &l, const ForcePtrs &f,
-                   int precision, bool kick, double *ke_part, double *thermo, hipStream_t stream)
+void launch_gather(const Launch &L, bool kick, hipStream_t stream)
 {
-    if (p.n == 0) return;
-    if (precision == DEM_FP32) {
-        if (p.dim == 3) gather_t<float, 3>(p, s, o, l, f, kick, ke_part, thermo, stream);
-        else gather_t<float, 2>(p, s, o, l, f, kick, ke_part, thermo, stream);
+    if (L.b.nchunk == 0) return;
+    if (L.precision == DEM_FP32) {
+        if (L.b.dim == 3) gather_t<float, 3>(L, kick, stream);
+        else gather_t<float, 2>(L, kick, stream);
     } else {
-        if (p.dim == 3) gather_t<double, 3>(p, s, o, l, f, kick, ke_part, thermo, stream);
-        else gather_t<double, 2>(p, s, o, l, f, kick, ke_part, thermo, stream);
+        if (L.b.dim == 3) gather_t<double, 3>(L, kick, stream);
+        else gather_t<double, 2>(L, kick, stream);
     }
+}
+
+size_t pair_kernel_lds(int precision, int tab_slots)
+{
+    const size_t w = precision == DEM_FP32 ? sizeof(ShapeTab<float>) : sizeof(ShapeTab<double>);
+    const size_t pl = precision == DEM_FP32 ? sizeof(PairLds<float>) : sizeof(PairLds<double>);
+    return (size_t)tab_slots * w + sizeof(RepLds) + kWaves * kGroups * pl;
+}
+
+int pair_blocks_resident(int precision, int dim, int tab_slots)
+{
+    const size_t lds = pair_kernel_lds(precision, tab_slots);
+    int per_cu = 0, cus = 0, dev = 0;
+    hipError_t e;
+    if (precision == DEM_FP32)
+        e = dim == 3 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_pairs<float, 3>, 64 * kWaves, lds)
+                     : hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_pairs<float, 2>, 64 * kWaves, lds);
+    else
+        e = dim == 3 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_pairs<double, 3>, 64 * kWaves, lds)
+                     : hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_pairs<double, 2>, 64 * kWaves, lds);
+    if (e != hipSuccess || hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+        return 512;
+    return std::max(8, per_cu * cus);
 }
 
 }  // namespace dem

@@ -92,38 +92,59 @@ __device__ inline double nh_half(const SysParams &p, double &xi, double &eta, do
     return sc;
 }
 
-__device__ inline double sum_partials(const double *part, int nblk, double *sh)
+// Replica of the wave's particles (chunks never straddle replicas), or -1.
+__device__ inline int wave_replica(const BatchParams &b, const ListPtrs &l, int i)
 {
-    double acc = 0.0;
-    for (int b = threadIdx.x; b < nblk; b += blockDim.x) acc += part[2 * b] + part[2 * b + 1];
-    return block_sum<kBlock>(acc, sh);
+    const int c = i / kChunk;
+    return __builtin_amdgcn_readfirstlane(c < b.nchunk ? l.chunk_rep[c] : -1);
 }
 
-// Opening half step of the first step of a call, from the kinetic partials.
-__global__ void __launch_bounds__(kBlock) k_nh_begin(SysParams p, const double *ke_part, int nblk, double *th)
+// Opening half step of the first step of a call, one workgroup per replica,
+// from the replica's kinetic partials (one per chunk, summed in order).
+__global__ void __launch_bounds__(kBlock) k_nh_begin(BatchParams b, const SysParams *reps, const double *ke_part,
+                                                        double *thermo, const int64_t *budget)
 {
     __shared__ double sh[kBlock];
-    double K = sum_partials(ke_part, nblk, sh);
+    const SysParams &p = reps[blockIdx.x];
+    double *th = thermo + blockIdx.x * TH_COUNT;
+    if (!p.live || p.n == 0 || p.ensemble != DEM_NVT || budget[blockIdx.x] <= 0) {
+        if (threadIdx.x == 0) th[TH_OPEN] = 0.0;
+        return;
+    }
+    const int c0 = p.off / kChunk, nc = (p.n + kChunk - 1) / kChunk;
+    double acc = 0.0;
+    for (int c = threadIdx.x; c < nc; c += blockDim.x) acc += ke_part[2 * (c0 + c)] + ke_part[2 * (c0 + c) + 1];
+    double K = block_sum<kBlock>(acc, sh);
     if (threadIdx.x != 0) return;
     double xi = th[TH_XI], eta = th[TH_ETA];
     const double sc = nh_half(p, xi, eta, K);
     th[TH_XI] = xi;
     th[TH_ETA] = eta;
     th[TH_SCALE] = sc;
+    th[TH_OPEN] = 1.0;
 }
 
-// After the last step of a call: back to the state after its closing half step.
-__global__ void k_nh_end(double *th)
+// After the last step of a call: back to the state after its closing half
+// step, for every replica whose first step of the call opened one.
+__global__ void k_nh_end(int nrep, double *thermo)
 {
+    const int r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= nrep) return;
+    double *th = thermo + r * TH_COUNT;
+    if (th[TH_OPEN] == 0.0) return;
     th[TH_XI] = th[TH_XI_B];
     th[TH_ETA] = th[TH_ETA_B];
     th[TH_SCALE] = th[TH_SCALE_B];
 }
 
-__global__ void k_scale(SysParams p, StatePtrs s, const double *th)
+// Applies the pending velocity scale of every replica closed by k_nh_end.
+__global__ void k_scale(BatchParams b, const SysParams *reps, StatePtrs s, ListPtrs l, double *thermo)
 {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= p.n) return;
+    const int r = wave_replica(b, l, i);
+    if (r < 0 || i >= reps[r].off + reps[r].n) return;
+    const double *th = thermo + r * TH_COUNT;
+    if (th[TH_OPEN] == 0.0) return;
     const double sc = th[TH_SCALE];
     s.vx[i] *= sc;
     s.vy[i] *= sc;
@@ -133,13 +154,28 @@ __global__ void k_scale(SysParams p, StatePtrs s, const double *th)
     s.Lz[i] *= sc;
 }
 
-template <typename T, int DIM, bool NVT>
-__global__ void __launch_bounds__(kBlock) k_kick_drift(SysParams p, StatePtrs s, OutPtrs o, ListPtrs l,
-                                                          const double *th, void *rot)
+__global__ void k_nh_close(int nrep, double *thermo)
+{
+    const int r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= nrep) return;
+    double *th = thermo + r * TH_COUNT;
+    if (th[TH_OPEN] == 0.0) return;
+    th[TH_SCALE] = 1.0;
+    th[TH_SCALE_B] = 1.0;
+    th[TH_OPEN] = 0.0;
+}
+
+template <typename T, int DIM>
+__global__ void __launch_bounds__(kBlock) k_kick_drift(BatchParams b, const SysParams *reps, StatePtrs s, OutPtrs o,
+                                                          ListPtrs l, const double *thermo, const int64_t *budget,
+                                                          void *rot, PartRec64 *rec64)
 {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= p.n) return;
-    const double sc = NVT ? th[TH_SCALE] : 1.0;
+    const int r = wave_replica(b, l, i);
+    if (r < 0) return;
+    const SysParams &p = reps[r];
+    if (i >= p.off + p.n || budget[r] <= 0) return;
+    const double sc = p.ensemble == DEM_NVT ? thermo[r * TH_COUNT + TH_SCALE] : 1.0;
     const int sid = s.sid[i];
     const double hm = 0.5 * p.dt / p.mass[sid];
     const double I[3] = {p.inertia[sid][0], p.inertia[sid][1], p.inertia[sid][2]};
@@ -189,13 +225,14 @@ __global__ void __launch_bounds__(kBlock) k_kick_drift(SysParams p, StatePtrs s,
     {  // the force pass's record: new position, rotation of the new orientation, shape
         double R[9];
         quat_to_rot(q[0], q[1], q[2], q[3], R);
-        PartRec<T> r;
-        r.x = x[0];
-        r.y = x[1];
-        r.z = x[2];
-        for (int k = 0; k < 9; ++k) r.R[k] = (T)R[k];
-        r.sid = sid;
-        reinterpret_cast<PartRec<T> *>(rot)[i] = r;
+        PartRec<T> rc;
+        rc.x = x[0];
+        rc.y = x[1];
+        rc.z = x[2];
+        for (int k = 0; k < 9; ++k) rc.R[k] = (T)R[k];
+        rc.sid = sid;
+        reinterpret_cast<PartRec<T> *>(rot)[i] = rc;
+        if (sizeof(T) == 4) rec64[i] = PartRec64{x[0], x[1], x[2], q[0], q[1], q[2], q[3], 0.0};
     }
     s.x[i] = x[0];
     s.y[i] = x[1];
@@ -214,22 +251,29 @@ __global__ void __launch_bounds__(kBlock) k_kick_drift(SysParams p, StatePtrs s,
     // displacement since the last list build triggers a rebuild
     double d2 = 0.0;
     for (int a = 0; a < DIM; ++a) {
-        const double d = min_image(x[a] - l.xlast[(size_t)a * p.n + i], p.box[a]);
+        const double d = min_image(x[a] - l.xlast[(size_t)a * b.N + i], p.box[a]);
         d2 += d * d;
     }
-    if (d2 > p.disp2) atomicOr(&l.flags[FLAG_REBUILD], 1);
+    if (d2 > p.disp2) {
+        atomicOr(&l.flags[r * FLAG_COUNT + FLAG_REBUILD], 1);
+        atomicOr(&l.gflags[G_ANY], 1);
+    }
     if (!(isfinite(x[0]) && isfinite(x[1]) && isfinite(x[2]) && isfinite(v[0]) && isfinite(v[1]) && isfinite(v[2])))
-        atomicOr(&l.flags[FLAG_NONFINITE], 1);
+        atomicOr(&l.flags[r * FLAG_COUNT + FLAG_NONFINITE], 1);
 }
 
-// Per-block kinetic partials of the current state, with the particle-to-
-// block mapping of the gather (kGatherPer particles per block).
-__global__ void __launch_bounds__(kBlock) k_kinetic(SysParams p, StatePtrs s, double *ke_part)
+// Per-chunk kinetic partials of the current state, with the particle-to-
+// block mapping of the gather (one chunk per block).
+__global__ void __launch_bounds__(kBlock) k_kinetic(BatchParams b, const SysParams *reps, StatePtrs s, ListPtrs l,
+                                                       double *ke_part)
 {
     __shared__ double sh[kBlock];
+    const int r = l.chunk_rep[blockIdx.x];
+    if (r < 0) return;
+    const SysParams &p = reps[r];
     const int i = blockIdx.x * kGatherPer + threadIdx.x / kGatherLanes;
     double kt = 0.0, kr = 0.0;
-    if (i < p.n && (threadIdx.x % kGatherLanes) == 0) {
+    if (i < p.off + p.n && (threadIdx.x % kGatherLanes) == 0) {
         const int sid = s.sid[i];
         const double m = p.mass[sid];
         kt = 0.5 * m * (s.vx[i] * s.vx[i] + s.vy[i] * s.vy[i] + s.vz[i] * s.vz[i]);
@@ -245,78 +289,78 @@ __global__ void __launch_bounds__(kBlock) k_kinetic(SysParams p, StatePtrs s, do
     }
 }
 
-// Per-block partials of U, K_trans, K_rot and W (9): part[blk * 12 + c].
-__global__ void __launch_bounds__(kBlock) k_energy_partials(SysParams p, StatePtrs s, OutPtrs o, double *part)
+// Per-chunk partials of U, K_trans, K_rot and W (9): part[chunk * 12 + c].
+__global__ void __launch_bounds__(kChunk) k_energy_partials(BatchParams b, const SysParams *reps, StatePtrs s,
+                                                               OutPtrs o, ListPtrs l, double *part)
 {
-    __shared__ double sh[kBlock];
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    __shared__ double sh[kChunk];
+    const int r = l.chunk_rep[blockIdx.x];
+    if (r < 0) return;
+    const SysParams &p = reps[r];
+    const int i = blockIdx.x * kChunk + threadIdx.x;
     double val[12];
     for (int c = 0; c < 12; ++c) val[c] = 0.0;
-    if (i < p.n) {
+    if (i < p.off + p.n) {
         const int sid = s.sid[i];
         val[0] = o.U[i];
         val[1] = 0.5 * p.mass[sid] * (s.vx[i] * s.vx[i] + s.vy[i] * s.vy[i] + s.vz[i] * s.vz[i]);
         const double L[3] = {s.Lx[i], s.Ly[i], s.Lz[i]};
         for (int a = 0; a < 3; ++a)
             if (p.inertia[sid][a] > 0.0) val[2] += 0.5 * L[a] * L[a] / p.inertia[sid][a];
-        for (int c = 0; c < 9; ++c) val[3 + c] = o.W[(size_t)c * p.n + i];
+        for (int c = 0; c < 9; ++c) val[3 + c] = o.W[(size_t)c * b.wstride + i];
     }
     for (int c = 0; c < 12; ++c) {
-        const double r = block_sum<kBlock>(val[c], sh);
-        if (threadIdx.x == 0) part[12 * blockIdx.x + c] = r;
+        const double v = block_sum<kChunk>(val[c], sh);
+        if (threadIdx.x == 0) part[12 * blockIdx.x + c] = v;
     }
 }
 
 }  // namespace
 
-void launch_nh_begin(const SysParams &p, const double *ke_part, int nblk, double *thermo, hipStream_t stream)
+void launch_nh_begin(const Launch &L, hipStream_t stream)
 {
-    k_nh_begin<<<1, kBlock, 0, stream>>>(p, ke_part, nblk, thermo);
+    if (L.b.nrep == 0) return;
+    k_nh_begin<<<L.b.nrep, kBlock, 0, stream>>>(L.b, L.reps, L.ke_part, L.thermo, L.budget);
 }
 
-void launch_nh_end(const SysParams &p, const StatePtrs &s, const double *ke_part, int nblk, double *thermo,
-                   hipStream_t stream)
+void launch_nh_end(const Launch &L, hipStream_t stream)
 {
-    (void)ke_part;
-    (void)nblk;
-    k_nh_end<<<1, 1, 0, stream>>>(thermo);
-    if (p.n > 0) k_scale<<<blocks_for(p.n), kBlock, 0, stream>>>(p, s, thermo);
+    if (L.b.nrep == 0) return;
+    const int nr = (L.b.nrep + kBlock - 1) / kBlock;
+    k_nh_end<<<nr, kBlock, 0, stream>>>(L.b.nrep, L.thermo);
+    if (L.b.nchunk > 0) k_scale<<<blocks_for(L.b.nchunk * kChunk), kBlock, 0, stream>>>(L.b, L.reps, L.s, L.l, L.thermo);
+    k_nh_close<<<nr, kBlock, 0, stream>>>(L.b.nrep, L.thermo);
 }
 
 template <typename T>
-void kick_drift_t(const SysParams &p, const StatePtrs &s, const OutPtrs &o, const ListPtrs &l, const double *thermo,
-                  void *rot, hipStream_t stream)
+void kick_drift_t(const Launch &L, hipStream_t stream)
 {
-    const int nb = blocks_for(p.n);
-    const bool nvt = p.ensemble == DEM_NVT;
-    if (p.dim == 3) {
-        if (nvt) k_kick_drift<T, 3, true><<<nb, kBlock, 0, stream>>>(p, s, o, l, thermo, rot);
-        else k_kick_drift<T, 3, false><<<nb, kBlock, 0, stream>>>(p, s, o, l, thermo, rot);
-    } else {
-        if (nvt) k_kick_drift<T, 2, true><<<nb, kBlock, 0, stream>>>(p, s, o, l, thermo, rot);
-        else k_kick_drift<T, 2, false><<<nb, kBlock, 0, stream>>>(p, s, o, l, thermo, rot);
-    }
+    const int nb = blocks_for(L.b.nchunk * kChunk);
+    if (L.b.dim == 3)
+        k_kick_drift<T, 3><<<nb, kBlock, 0, stream>>>(L.b, L.reps, L.s, L.o, L.l, L.thermo, L.budget, L.f.rot,
+                                                       L.f.rec64);
+    else
+        k_kick_drift<T, 2><<<nb, kBlock, 0, stream>>>(L.b, L.reps, L.s, L.o, L.l, L.thermo, L.budget, L.f.rot,
+                                                       L.f.rec64);
 }
 
-void launch_kick_drift(const SysParams &p, const StatePtrs &s, const OutPtrs &o, const ListPtrs &l,
-                       const double *thermo, void *rot, int precision, hipStream_t stream)
+void launch_kick_drift(const Launch &L, hipStream_t stream)
 {
-    if (p.n == 0) return;
-    if (precision == DEM_FP32) kick_drift_t<float>(p, s, o, l, thermo, rot, stream);
-    else kick_drift_t<double>(p, s, o, l, thermo, rot, stream);
+    if (L.b.nchunk == 0) return;
+    if (L.precision == DEM_FP32) kick_drift_t<float>(L, stream);
+    else kick_drift_t<double>(L, stream);
 }
 
-void launch_kinetic(const SysParams &p, const StatePtrs &s, double *ke_part, hipStream_t stream)
+void launch_kinetic(const Launch &L, hipStream_t stream)
 {
-    if (p.n == 0) return;
-    k_kinetic<<<gather_blocks(p.n), kBlock, 0, stream>>>(p, s, ke_part);
+    if (L.b.nchunk == 0) return;
+    k_kinetic<<<L.b.nchunk, kBlock, 0, stream>>>(L.b, L.reps, L.s, L.l, L.ke_part);
 }
 
-void launch_energy_partials(const SysParams &p, const StatePtrs &s, const OutPtrs &o, double *part,
-                            hipStream_t stream)
+void launch_energy_partials(const Launch &L, double *part, hipStream_t stream)
 {
-    if (p.n == 0) return;
-    k_energy_partials<<<blocks_for(p.n), kBlock, 0, stream>>>(p, s, o, part);
+    if (L.b.nchunk == 0) return;
+    k_energy_partials<<<L.b.nchunk, kChunk, 0, stream>>>(L.b, L.reps, L.s, L.o, L.l, part);
 }
 
 }  // namespace dem

@@ -13,14 +13,26 @@ namespace dem {
 // 2^(1/6): the WCA cutoff in units of sigma (Sec. II, Eq. 4).
 constexpr double kWcaCut = 1.122462048309373;
 
-// Device flag words.
+// Particles per chunk.  Every replica of a batch starts on a chunk
+// boundary, so a wavefront's particles (and a gather block's) belong to one
+// replica, and per-chunk partial sums do not depend on the other replicas.
+constexpr int kChunk = 64;
+// Particle pairs per tile of the pair kernel; tiles never straddle replicas.
+constexpr int kTile = 16;
+
+// Per-replica device flag words (flags[r * FLAG_COUNT + w]).
 enum Flag {
-    FLAG_REBUILD = 0, FLAG_NBUILDS = 1, FLAG_MAXROW = 2, FLAG_NONFINITE = 3, FLAG_NPAIRS = 4, FLAG_TICKET = 5, FLAG_COUNT = 8
+    FLAG_REBUILD = 0, FLAG_NBUILDS = 1, FLAG_MAXROW = 2, FLAG_NONFINITE = 3, FLAG_NPAIRS = 4, FLAG_TICKET = 5,
+    FLAG_COUNT = 8
 };
-// Thermostat words (double): running xi and eta, the velocity scale the next
-// kick-drift applies, and the state right after the closing half step of the
-// last completed step (xi, eta and its velocity scale).
-enum Thermo { TH_XI = 0, TH_ETA = 1, TH_SCALE = 2, TH_XI_B = 3, TH_ETA_B = 4, TH_SCALE_B = 5, TH_COUNT = 8 };
+// Batch-wide words: a list rebuild is pending somewhere; the list kernel's
+// completion ticket.
+enum GWord { G_ANY = 0, G_TICKET = 1, G_COUNT = 4 };
+// Per-replica thermostat words (double, thermo[r * TH_COUNT + w]): running
+// xi and eta, the velocity scale the next kick-drift applies, the state
+// right after the closing half step of the last completed step (xi, eta and
+// its velocity scale), and whether the current call opened a half step.
+enum Thermo { TH_XI = 0, TH_ETA = 1, TH_SCALE = 2, TH_XI_B = 3, TH_ETA_B = 4, TH_SCALE_B = 5, TH_OPEN = 6, TH_COUNT = 8 };
 // Force work counters (unsigned long long).
 enum Stat {
     ST_PAIRS = 0, ST_FEATURES = 1, ST_INCUT = 2, ST_LAUNCHES = 3, ST_NEAR = 4, ST_REFINED = 5, ST_EENEAR = 6, ST_COUNT = 7
@@ -39,7 +51,7 @@ constexpr int kRec = 10;
 // of each loop edge (convex inside test), face coordinates of each loop
 // vertex (crossing-number test for concave faces) and 1/|loop edge|^2.
 template <typename T>
-struct ShapeTab {
+struct alignas(16) ShapeTab {
     int nv, ne, nf, pad0;
     T r, R, pad1, pad2;
     T v[DEM_MAX_VERTS][3];
@@ -63,15 +75,21 @@ struct ShapeTab {
     T lxy[DEM_MAX_LOOP][2];      // face coordinates of loop vertex k
 };
 
-// Parameters of one system, passed by value to every kernel.
+// One replica: a periodic system of its own.  A single system is a batch
+// of one replica.  Indices into batch arrays are global particle slots;
+// replica r owns slots [off, off + n), cells [coff, coff + ncell] and pair
+// slots [poff, poff + pcap).
 struct SysParams {
-    int n, dim, n_shapes, cap;
+    int n, dim, n_shapes, live;
+    int off;                     // first particle slot (a multiple of kChunk)
+    int coff;                    // first cell slot (ncell + 1 entries of cell_start)
+    int poff;                    // first pair slot
+    int pcap;                    // pair slots
+    int sbase;                   // first shape-table slot
     int nc[3], ncell;
     int use_cells;               // 1 if every periodic axis has >= 3 cells
     int ensemble;
-    int max_pairs;               // capacity of the pair arrays
-    int force_multi_kernel_lists;  // build lists with one kernel per phase even when small
-    int pair_blocks;             // grid of the pair kernel (grid-stride over pairs)
+    int rid;                     // replica slot
     double box[3];
     double cellw[3];             // box / nc
     double rl2;                  // r_list^2
@@ -82,6 +100,18 @@ struct SysParams {
     double inertia[DEM_MAX_SHAPES][3];
     double R[DEM_MAX_SHAPES];    // circumradius about the body origin
     double rad[DEM_MAX_SHAPES];  // rounding radius
+};
+
+// Batch-wide parameters, passed by value to every kernel.
+struct BatchParams {
+    int nrep;                    // replica slots in use (slots with live == 0 are skipped)
+    int N;                       // particle slots: stride of the library's column-major arrays
+    int wstride;                 // stride of the virial output W[9][.]
+    int nchunk;                  // chunks in use (kernels over particles cover nchunk * kChunk slots)
+    int cap;                     // neighbour-row capacity
+    int tab_slots;               // shape tables of one replica staged in LDS
+    int pair_blocks;             // grid of the pair kernel (a multiple of 8)
+    int dim;
 };
 
 struct StatePtrs {
@@ -95,12 +125,15 @@ struct OutPtrs {
 
 struct ListPtrs {
     int32_t *cell_count, *cell_start, *cell_particles, *pcell, *nbr, *n_nbr;
-    double *xlast;               // [3][n]
-    int32_t *flags;
+    double *xlast;               // [3][N]
+    int32_t *flags;              // [replica][FLAG_COUNT]
+    int32_t *gflags;             // [G_COUNT]
+    int32_t *tile_start;         // [nrep + 1] first pair tile of each replica
+    const int32_t *chunk_rep;    // [nchunk] replica of each chunk, -1 if free
     // half list of unordered pairs (i < j), rebuilt with the neighbour list
-    int32_t *klo;                // [n] first row slot of i holding a j > i
-    int32_t *pstart;             // [n] first pair index of i
-    int4 *pairs;                 // [max_pairs] {i, j, slot of j in i's row, slot of i in j's row}
+    int32_t *klo;                // [N] first row slot of i holding a j > i
+    int32_t *pstart;             // [N + 1] first pair index of i, local to its replica
+    int4 *pairs;                 // [pair slots] {i, j, slot of j in i's row, slot of i in j's row (-1: missing)}
 };
 
 // Everything the pair kernel reads about one particle, in one cache line:
@@ -123,52 +156,79 @@ struct alignas(128) PartRec<double> {
     int pad[7];
 };
 
+// FP64 position and orientation of one particle, for the FP32 pair path's
+// FP64 redo of problems FP32 cannot resolve.
+struct alignas(64) PartRec64 {
+    double x, y, z, qw, qx, qy, qz, pad;
+};
+
 struct ForcePtrs {
-    void *rot;                   // [n] PartRec<T>
-    void *rec;                   // [kRec][cap][n] row-slot records, precision T
+    void *rot;                   // [N] PartRec<T>
+    PartRec64 *rec64;            // [N], FP32 path only (else null)
+    void *rec;                   // [kRec][cap][N] row-slot records, precision T
     const void *tab;             // shape tables, precision T
     const void *tab64;           // shape tables, FP64 (refinement of ill-conditioned FP32 problems)
 };
 
 // ---- launchers (all asynchronous on `stream`) ----
-// Cell list, neighbour list and half pair list.  The kernels exit at once
-// unless the rebuild flag is set, so a captured step contains them
-// unconditionally.
-void launch_build_lists(const SysParams &p, const StatePtrs &s, const ListPtrs &l, hipStream_t stream);
+// `reps` is the device array of replica parameters; `host` the host copy of
+// replica 0, used only by the one-kernel-per-phase list build of a single
+// large system.
+struct Launch {
+    BatchParams b;
+    const SysParams *reps;
+    StatePtrs s;
+    OutPtrs o;
+    ListPtrs l;
+    ForcePtrs f;
+    int precision;
+    double *ke_part;             // [2 * nchunk]
+    double *thermo;              // [replica][TH_COUNT]
+    int64_t *budget;             // [replica] steps left; a replica with none left is held still
+    int64_t *steps;              // [replica] steps done
+};
+
+// Cell list, neighbour list, half pair list and the tile plan of the pair
+// kernel, for every replica whose rebuild flag is set.  The kernels exit at
+// once unless a rebuild is pending, so a captured step contains them
+// unconditionally.  multi != 0 (one replica only) runs one kernel per phase.
+void launch_build_lists(const Launch &L, int multi, const SysParams &host, hipStream_t stream);
+// Largest replica the one-workgroup list build accepts.
+int fused_list_max_n();
+// Dynamic LDS of the pair kernel, and how many of its blocks the device
+// holds at once.
+size_t pair_kernel_lds(int precision, int tab_slots);
+int pair_blocks_resident(int precision, int dim, int tab_slots);
 
 // Per-particle records (position, rotation, shape id) from the state arrays.
-void launch_rotations(const SysParams &p, const StatePtrs &s, void *rot, int precision, hipStream_t stream);
+void launch_rotations(const Launch &L, hipStream_t stream);
 
-// Pair records over the half list; stats may be null.
-void launch_pairs(const SysParams &p, const StatePtrs &s, const ListPtrs &l, const ForcePtrs &f, int precision,
-                  unsigned long long *stats, hipStream_t stream);
+// Pair records over the half lists; stats may be null.
+void launch_pairs(const Launch &L, unsigned long long *stats, hipStream_t stream);
 
 // Per-particle sums of pair records in row order (fixed, atomic-free):
 // F, tau, U_i, W_i; with kick != 0 also the closing velocity/angular
-// momentum kick and (NVT) per-block kinetic partials.
-void launch_gather(const SysParams &p, const StatePtrs &s, const OutPtrs &o, const ListPtrs &l, const ForcePtrs &f,
-                   int precision, bool kick, double *ke_part, double *thermo, hipStream_t stream);
+// momentum kick, the Nose-Hoover half steps and the step budget.
+void launch_gather(const Launch &L, bool kick, hipStream_t stream);
 
-// Integrator pieces.  With NVT the gather's last workgroup applies the
-// closing half step of the step and the opening half step of the next one;
-// launch_nh_begin opens the first step of a call, launch_nh_end restores
+// Integrator pieces.  With NVT the gather's last block of a replica applies
+// the closing half step of the step and the opening half step of the next
+// one; launch_nh_begin opens the first step of a call, launch_nh_end restores
 // the state after the last closing half step and rescales the velocities.
-void launch_nh_begin(const SysParams &p, const double *ke_part, int nblk, double *thermo, hipStream_t stream);
-void launch_kick_drift(const SysParams &p, const StatePtrs &s, const OutPtrs &o, const ListPtrs &l,
-                       const double *thermo, void *rot, int precision, hipStream_t stream);
-void launch_kinetic(const SysParams &p, const StatePtrs &s, double *ke_part, hipStream_t stream);
-void launch_nh_end(const SysParams &p, const StatePtrs &s, const double *ke_part, int nblk, double *thermo,
-                   hipStream_t stream);
-void launch_energy_partials(const SysParams &p, const StatePtrs &s, const OutPtrs &o, double *part,
-                            hipStream_t stream);
+void launch_nh_begin(const Launch &L, hipStream_t stream);
+void launch_kick_drift(const Launch &L, hipStream_t stream);
+void launch_kinetic(const Launch &L, hipStream_t stream);
+void launch_nh_end(const Launch &L, hipStream_t stream);
+// Per-chunk partials of U, K_trans, K_rot and W (9): part[12 * chunk + c].
+void launch_energy_partials(const Launch &L, double *part, hipStream_t stream);
 
 constexpr int kBlock = 256;
 inline int blocks_for(int n) { return (n + kBlock - 1) / kBlock; }
-// The gather and the kinetic reduction map kGatherPer particles to each
-// 256-thread block, which writes one kinetic partial.
+// The gather and the kinetic reduction map one chunk (kGatherPer = kChunk
+// particles) to each 256-thread block, which writes one kinetic partial.
 constexpr int kGatherLanes = 4;
 constexpr int kGatherPer = kBlock / kGatherLanes;
-inline int gather_blocks(int n) { return (n + kGatherPer - 1) / kGatherPer; }
+static_assert(kGatherPer == kChunk, "one gather block per chunk");
 
 // Rotation matrix (row-major, body to space) of a unit quaternion (w, x, y, z).
 __host__ __device__ inline void quat_to_rot(double w, double x, double y, double z, double *R)

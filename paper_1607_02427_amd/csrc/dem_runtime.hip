@@ -1,10 +1,15 @@
 // libdem host runtime: the C ABI of dem.h.
 //
-// A handle owns the device copies of the shape tables (FP64 and FP32), the
-// cell and neighbour lists, flags, reduction scratch and one captured graph
-// of a whole time step, which dem_step replays.  State and outputs are the
-// caller's device arrays.  Every launch goes to the caller's stream; graphs
-// are recorded on a private stream and launched on the caller's.
+// A handle is a batch of replicas (a single system is a batch of one).  It
+// owns the device copies of the shape tables (FP64 and FP32), the replica
+// parameter table, the cell and neighbour lists of every replica, flags,
+// reduction scratch and one captured graph of a whole time step, which
+// dem_step replays for every live replica at once.  A single system uses
+// the caller's state and output arrays in place; a batch keeps its
+// replicas' state in arrays of its own (particle slots, 64 to a chunk,
+// handed out first-fit) and copies it in and out on request.  Every launch
+// goes to the handle's stream; graphs are recorded on a private stream and
+// launched on the handle's.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -20,34 +25,92 @@
 
 using namespace dem;
 
-struct dem_system {
-    dem_params prm{};
+namespace {
+
+// First-fit allocator over slots [0, size).
+struct SlotArena {
+    std::vector<uint8_t> used;
+    void reset(int size) { used.assign((size_t)std::max(size, 0), 0); }
+    int size() const { return (int)used.size(); }
+    // first offset of `count` free slots, or -1
+    int find(int count) const
+    {
+        if (count == 0) return 0;
+        int run = 0;
+        for (int k = 0; k < size(); ++k) {
+            run = used[k] ? 0 : run + 1;
+            if (run == count) return k - count + 1;
+        }
+        return -1;
+    }
+    void mark(int off, int count, uint8_t v)
+    {
+        for (int k = off; k < off + count; ++k) used[k] = v;
+    }
+    // one past the last used slot
+    int high() const
+    {
+        for (int k = size(); k > 0; --k)
+            if (used[k - 1]) return k;
+        return 0;
+    }
+    int free_slots() const
+    {
+        int f = 0;
+        for (uint8_t u : used) f += u ? 0 : 1;
+        return f;
+    }
+};
+
+struct Replica {
+    bool live = false;
     SysParams sp{};
+    dem_params prm{};            // copy; shapes not kept
+    double r_list = 0.0;
+    int chunk0 = 0, nchunks = 0;
+    int cell0 = 0, ncells = 0;
+    int shape0 = 0, nshapes = 0;
+};
+
+}  // namespace
+
+struct dem_system {
+    bool batch = false;
+    int dim = 0, precision = 0;
+    int list_multi = 0;          // single system: one kernel per list phase
+    bool auto_cap = true;
+    bool counting = false;
+    BatchParams bp{};
+    std::vector<Replica> reps;
+    SlotArena chunks, cells, shapes;
+    int Ncap = 0;                // particle slots
+    SysParams *d_reps = nullptr;
+    int32_t *d_chunk_rep = nullptr;
+    std::vector<int32_t> h_chunk_rep;
     StatePtrs st{};
     OutPtrs out{};
     ListPtrs lst{};
     hipStream_t stream = nullptr;
     hipStream_t cap_stream = nullptr;
     void *tab64 = nullptr, *tab32 = nullptr;
-    void *rot = nullptr;          // [9][n] in the force precision
-    void *rec = nullptr;          // [max_pairs][kRec] in the force precision
-    double *ke_part = nullptr;    // [2 * nblk]
-    double *e_part = nullptr;     // [12 * nblk]
-    double *thermo = nullptr;     // [TH_COUNT]
+    void *rot = nullptr;         // [N] PartRec in the force precision
+    PartRec64 *rec64 = nullptr;  // [N] FP64 position and orientation (FP32 path)
+    void *rec = nullptr;         // [kRec][cap][N] in the force precision
+    double *ke_part = nullptr;   // [2 * chunks]
+    double *e_part = nullptr;    // [12 * chunks]
+    double *thermo = nullptr;    // [replica][TH_COUNT]
+    int64_t *budget = nullptr;   // [replica] steps left
+    int64_t *steps = nullptr;    // [replica] steps done
     unsigned long long *stats = nullptr;
-    int nblk = 0;
-    bool auto_cap = true;
-    bool counting = false;
     hipGraph_t graph = nullptr;
     hipGraphExec_t gexec = nullptr;
-    int64_t step = 0;
-    double r_list = 0.0;
     std::string err;
 };
 
 namespace {
 
 std::string g_err;
+constexpr int64_t kUnbounded = (int64_t)1 << 62;
 
 dem_status fail(dem_system *h, dem_status s, const char *fmt, ...)
 {
@@ -67,7 +130,17 @@ dem_status fail(dem_system *h, dem_status s, const char *fmt, ...)
         if (e_ != hipSuccess) return fail(h, DEM_E_HIP, "%s: %s", #call, hipGetErrorString(e_));  \
     } while (0)
 
-__global__ void k_set_int(int32_t *p, int32_t v) { *p = v; }
+__global__ void k_set_i32(int32_t *p, int32_t v) { *p = v; }
+__global__ void k_set_i64(int64_t *p, int64_t v) { *p = v; }
+// A replica without particles advances by bookkeeping only.
+__global__ void k_advance_empty(int64_t *budget, int64_t *steps, int64_t n)
+{
+    const int64_t d = *budget < n ? *budget : n;
+    if (d > 0) {
+        *budget -= d;
+        *steps += d;
+    }
+}
 __global__ void k_end_build(int32_t *flags)
 {
     if (flags[FLAG_REBUILD] != 0) flags[FLAG_NBUILDS] += 1;
@@ -78,6 +151,7 @@ __global__ void k_set_thermo(double *th, double xi, double eta)
     th[TH_XI] = th[TH_XI_B] = xi;
     th[TH_ETA] = th[TH_ETA_B] = eta;
     th[TH_SCALE] = th[TH_SCALE_B] = 1.0;
+    th[TH_OPEN] = 0.0;
 }
 
 struct HostVec {
@@ -271,29 +345,13 @@ int auto_capacity(const dem_params &p, double rl)
     double dens = vol > 0.0 ? (double)p.n / vol : 0.0;
     double expect = p.dim == 3 ? dens * 4.0 / 3.0 * M_PI * rl * rl * rl : dens * M_PI * rl * rl;
     int cap = (int)std::ceil(1.8 * expect) + 16;
-    cap = (cap + 3) & ~3;
-    return std::max(16, std::min(cap, (int)std::max<int64_t>(p.n, 16)));
+    cap = std::max(16, std::min(cap, (int)std::max<int64_t>(p.n, 16)));
+    return (cap + 3) & ~3;
 }
 
-void free_lists(dem_system *h)
-{
-    (void)hipFree(h->lst.cell_count);
-    (void)hipFree(h->lst.cell_start);
-    (void)hipFree(h->lst.cell_particles);
-    (void)hipFree(h->lst.pcell);
-    (void)hipFree(h->lst.nbr);
-    (void)hipFree(h->lst.n_nbr);
-    (void)hipFree(h->lst.xlast);
-    (void)hipFree(h->lst.klo);
-    (void)hipFree(h->lst.pstart);
-    (void)hipFree(h->lst.pairs);
-    (void)hipFree(h->rec);
-    (void)hipFree(h->rot);
-    int32_t *flags = h->lst.flags;  // freed with the handle
-    h->lst = ListPtrs{};
-    h->lst.flags = flags;
-    h->rec = h->rot = nullptr;
-}
+
+size_t force_word(int precision) { return precision == DEM_FP32 ? sizeof(float) : sizeof(double); }
+size_t partrec_bytes(int precision) { return precision == DEM_FP32 ? sizeof(PartRec<float>) : sizeof(PartRec<double>); }
 
 void drop_graph(dem_system *h)
 {
@@ -303,62 +361,211 @@ void drop_graph(dem_system *h)
     h->graph = nullptr;
 }
 
-size_t force_word(const dem_system *h) { return h->prm.precision == DEM_FP32 ? sizeof(float) : sizeof(double); }
+Launch make_launch(const dem_system *h)
+{
+    Launch L;
+    L.b = h->bp;
+    L.reps = h->d_reps;
+    L.s = h->st;
+    L.o = h->out;
+    L.l = h->lst;
+    L.l.chunk_rep = h->d_chunk_rep;
+    L.f.rot = h->rot;
+    L.f.rec64 = h->rec64;
+    L.f.rec = h->rec;
+    L.f.tab = h->precision == DEM_FP32 ? h->tab32 : h->tab64;
+    L.f.tab64 = h->tab64;
+    L.precision = h->precision;
+    L.ke_part = h->ke_part;
+    L.thermo = h->thermo;
+    L.budget = h->budget;
+    L.steps = h->steps;
+    return L;
+}
 
-// Row storage and everything sized by the row capacity: slot -> pair map,
-// pair arrays and pair records.
+int tiles_of(int pcap) { return (pcap + kTile - 1) / kTile; }
+
+// Batch-wide launch parameters from the replica table.
+void refresh_batch(dem_system *h)
+{
+    BatchParams &b = h->bp;
+    b.nrep = 0;
+    b.tab_slots = 1;
+    long long tiles = 0;
+    for (size_t r = 0; r < h->reps.size(); ++r) {
+        const Replica &R = h->reps[r];
+        if (!R.live) continue;
+        b.nrep = (int)r + 1;
+        b.tab_slots = std::max(b.tab_slots, R.sp.n_shapes);
+        tiles += tiles_of(R.sp.pcap);
+    }
+    b.nchunk = h->chunks.high();
+    b.dim = h->dim;
+    // one round of blocks, as many as the device holds at once (a second
+    // round would add a whole block's latency), no more than the tiles use
+    const int resident = pair_blocks_resident(h->precision, h->dim, b.tab_slots);
+    const long long want = std::max<long long>(8, std::min<long long>(tiles, resident));
+    b.pair_blocks = (int)((want + 7) / 8 * 8);
+}
+
+// Pair slots of every replica follow its particle slots: cap / 2 per slot.
+void place_pairs(dem_system *h)
+{
+    for (Replica &R : h->reps) {
+        R.sp.poff = (int)((int64_t)R.chunk0 * kChunk * h->bp.cap / 2);
+        R.sp.pcap = (int)((int64_t)R.nchunks * kChunk * h->bp.cap / 2);
+    }
+}
+
+dem_status upload_tables(dem_system *h)
+{
+    std::vector<SysParams> sp(h->reps.size());
+    for (size_t r = 0; r < h->reps.size(); ++r) {
+        sp[r] = h->reps[r].sp;
+        sp[r].live = h->reps[r].live ? 1 : 0;
+        sp[r].rid = (int)r;
+    }
+    h->h_chunk_rep.assign((size_t)h->chunks.size(), -1);
+    for (size_t r = 0; r < h->reps.size(); ++r) {
+        const Replica &R = h->reps[r];
+        if (!R.live) continue;
+        for (int c = R.chunk0; c < R.chunk0 + R.nchunks; ++c) h->h_chunk_rep[c] = (int32_t)r;
+    }
+    // in stream order, so kernels already queued see the old tables; the
+    // host sources must live until the copies are done
+    HIPCHK(h, hipMemcpyAsync(h->d_reps, sp.data(), sizeof(SysParams) * sp.size(), hipMemcpyHostToDevice, h->stream));
+    if (!h->h_chunk_rep.empty())
+        HIPCHK(h, hipMemcpyAsync(h->d_chunk_rep, h->h_chunk_rep.data(), sizeof(int32_t) * h->h_chunk_rep.size(),
+                                 hipMemcpyHostToDevice, h->stream));
+    HIPCHK(h, hipStreamSynchronize(h->stream));
+    refresh_batch(h);
+    drop_graph(h);
+    return DEM_OK;
+}
+
+// Row storage and everything sized by the row capacity: rows, pair entries
+// and pair records.  Every replica rebuilds its lists afterwards.
 dem_status alloc_nbr(dem_system *h, int cap)
 {
+    (void)hipStreamSynchronize(h->stream);
     (void)hipFree(h->lst.nbr);
     (void)hipFree(h->lst.pairs);
     (void)hipFree(h->rec);
     h->lst.nbr = nullptr;
     h->lst.pairs = nullptr;
     h->rec = nullptr;
-    const size_t n = (size_t)std::max(h->sp.n, 1);
-    const size_t maxp = n * (size_t)cap / 2 + 64;
+    const size_t N = (size_t)std::max(h->Ncap, kChunk);
+    const size_t maxp = N * (size_t)cap / 2;
     if (maxp > (size_t)INT32_MAX) return fail(h, DEM_E_ARG, "pair capacity overflows int32");
-    if (hipMalloc(&h->lst.nbr, sizeof(int32_t) * (size_t)cap * n) != hipSuccess ||
+    if (hipMalloc(&h->lst.nbr, sizeof(int32_t) * (size_t)cap * N) != hipSuccess ||
         hipMalloc(&h->lst.pairs, sizeof(int4) * maxp) != hipSuccess ||
-        hipMalloc(&h->rec, force_word(h) * kRec * (size_t)cap * n) != hipSuccess)
-        return fail(h, DEM_E_OOM, "neighbour list of %d x %zu entries", cap, n);
-    h->sp.cap = cap;
-    h->sp.max_pairs = (int)maxp;
-    // grid-stride pair kernel: enough waves to fill the chip, no more than the pairs need
-    const size_t want = (maxp + 15) / 16;  // four waves per block, four pairs per wave
-    h->sp.pair_blocks = (int)std::max<size_t>(8, std::min<size_t>(want, 2048));
-    drop_graph(h);
+        hipMalloc(&h->rec, force_word(h->precision) * kRec * (size_t)cap * N) != hipSuccess)
+        return fail(h, DEM_E_OOM, "neighbour list of %d x %zu entries", cap, N);
+    h->bp.cap = cap;
+    place_pairs(h);
+    return upload_tables(h);
+}
+
+dem_status alloc_core(dem_system *h, int Ncap, int Ccap, int Scap, int Rcap)
+{
+    h->Ncap = Ncap;
+    const size_t N = (size_t)std::max(Ncap, kChunk);
+    const size_t nch = N / kChunk;
+    h->chunks.reset(Ncap / kChunk);
+    h->cells.reset(Ccap);
+    h->shapes.reset(Scap);
+    h->reps.assign((size_t)Rcap, Replica{});
+    h->bp.N = (int)N;
+    bool ok = hipMalloc(&h->d_reps, sizeof(SysParams) * Rcap) == hipSuccess &&
+              hipMalloc(&h->d_chunk_rep, sizeof(int32_t) * nch) == hipSuccess &&
+              hipMalloc(&h->tab64, sizeof(ShapeTab<double>) * Scap) == hipSuccess &&
+              hipMalloc(&h->tab32, sizeof(ShapeTab<float>) * Scap) == hipSuccess &&
+              hipMalloc(&h->ke_part, sizeof(double) * 2 * nch) == hipSuccess &&
+              hipMalloc(&h->e_part, sizeof(double) * 12 * nch) == hipSuccess &&
+              hipMalloc(&h->thermo, sizeof(double) * TH_COUNT * Rcap) == hipSuccess &&
+              hipMalloc(&h->budget, sizeof(int64_t) * Rcap) == hipSuccess &&
+              hipMalloc(&h->steps, sizeof(int64_t) * Rcap) == hipSuccess &&
+              hipMalloc(&h->stats, sizeof(unsigned long long) * ST_COUNT) == hipSuccess &&
+              hipMalloc(&h->lst.flags, sizeof(int32_t) * FLAG_COUNT * Rcap) == hipSuccess &&
+              hipMalloc(&h->lst.gflags, sizeof(int32_t) * G_COUNT) == hipSuccess &&
+              hipMalloc(&h->lst.tile_start, sizeof(int32_t) * (Rcap + 1)) == hipSuccess &&
+              hipMalloc(&h->lst.cell_count, sizeof(int32_t) * std::max(Ccap, 1)) == hipSuccess &&
+              hipMalloc(&h->lst.cell_start, sizeof(int32_t) * std::max(Ccap, 1)) == hipSuccess &&
+              hipMalloc(&h->lst.cell_particles, sizeof(int32_t) * N) == hipSuccess &&
+              hipMalloc(&h->lst.pcell, sizeof(int32_t) * N) == hipSuccess &&
+              hipMalloc(&h->lst.n_nbr, sizeof(int32_t) * N) == hipSuccess &&
+              hipMalloc(&h->lst.xlast, sizeof(double) * 3 * N) == hipSuccess &&
+              hipMalloc(&h->lst.klo, sizeof(int32_t) * N) == hipSuccess &&
+              hipMalloc(&h->lst.pstart, sizeof(int32_t) * (N + 1)) == hipSuccess &&
+              hipMalloc(&h->rot, partrec_bytes(h->precision) * N) == hipSuccess &&
+              (h->precision != DEM_FP32 || hipMalloc(&h->rec64, sizeof(PartRec64) * N) == hipSuccess);
+    if (!ok) return fail(h, DEM_E_OOM, "device allocation failed");
+    if (h->batch) {  // the batch's own state and output arrays
+        double **d[] = {&h->st.x,  &h->st.y,  &h->st.z,  &h->st.qw, &h->st.qx, &h->st.qy, &h->st.qz,
+                        &h->st.vx, &h->st.vy, &h->st.vz, &h->st.Lx, &h->st.Ly, &h->st.Lz, &h->out.Fx,
+                        &h->out.Fy, &h->out.Fz, &h->out.Tx, &h->out.Ty, &h->out.Tz, &h->out.U};
+        for (double **p : d)
+            if (hipMalloc(p, sizeof(double) * N) != hipSuccess) return fail(h, DEM_E_OOM, "device allocation failed");
+        if (hipMalloc(&h->out.W, sizeof(double) * 9 * N) != hipSuccess ||
+            hipMalloc(&h->st.sid, sizeof(int32_t) * N) != hipSuccess ||
+            hipMalloc(&h->st.image, sizeof(int32_t) * 3 * N) != hipSuccess)
+            return fail(h, DEM_E_OOM, "device allocation failed");
+        HIPCHK(h, hipMemsetAsync(h->st.sid, 0, sizeof(int32_t) * N, h->stream));
+        h->bp.wstride = (int)N;
+    }
+    // initial contents (not captured: plain memsets are fine here)
+    HIPCHK(h, hipMemsetAsync(h->lst.flags, 0, sizeof(int32_t) * FLAG_COUNT * Rcap, h->stream));
+    HIPCHK(h, hipMemsetAsync(h->lst.gflags, 0, sizeof(int32_t) * G_COUNT, h->stream));
+    HIPCHK(h, hipMemsetAsync(h->lst.tile_start, 0, sizeof(int32_t) * (Rcap + 1), h->stream));
+    HIPCHK(h, hipMemsetAsync(h->lst.cell_count, 0, sizeof(int32_t) * std::max(Ccap, 1), h->stream));
+    HIPCHK(h, hipMemsetAsync(h->lst.n_nbr, 0, sizeof(int32_t) * N, h->stream));
+    HIPCHK(h, hipMemsetAsync(h->stats, 0, sizeof(unsigned long long) * ST_COUNT, h->stream));
+    HIPCHK(h, hipMemsetAsync(h->ke_part, 0, sizeof(double) * 2 * nch, h->stream));
+    HIPCHK(h, hipMemsetAsync(h->budget, 0, sizeof(int64_t) * Rcap, h->stream));
+    HIPCHK(h, hipMemsetAsync(h->steps, 0, sizeof(int64_t) * Rcap, h->stream));
     return DEM_OK;
 }
 
-ForcePtrs force_ptrs(const dem_system *h)
+void free_all(dem_system *h)
 {
-    ForcePtrs f;
-    f.rot = h->rot;
-    f.rec = h->rec;
-    f.tab = h->prm.precision == DEM_FP32 ? h->tab32 : h->tab64;
-    f.tab64 = h->tab64;
-    return f;
+    drop_graph(h);
+    void *ptrs[] = {h->d_reps, h->d_chunk_rep, h->tab64, h->tab32, h->ke_part, h->e_part, h->thermo, h->budget,
+                    h->steps, h->stats, h->lst.flags, h->lst.gflags, h->lst.tile_start, h->lst.cell_count,
+                    h->lst.cell_start, h->lst.cell_particles, h->lst.pcell, h->lst.n_nbr, h->lst.xlast, h->lst.klo,
+                    h->lst.pstart, h->lst.nbr, h->lst.pairs, h->rot, h->rec, h->rec64};
+    for (void *p : ptrs) (void)hipFree(p);
+    if (h->batch) {
+        void *own[] = {h->st.x,  h->st.y,  h->st.z,  h->st.qw, h->st.qx,  h->st.qy,  h->st.qz,  h->st.vx,
+                       h->st.vy, h->st.vz, h->st.Lx, h->st.Ly, h->st.Lz,  h->st.sid, h->st.image, h->out.Fx,
+                       h->out.Fy, h->out.Fz, h->out.Tx, h->out.Ty, h->out.Tz, h->out.U, h->out.W};
+        for (void *p : own) (void)hipFree(p);
+    }
 }
 
 dem_status latched(dem_system *h)
 {
-    int32_t flags[FLAG_COUNT];
-    HIPCHK(h, hipMemcpyAsync(flags, h->lst.flags, sizeof flags, hipMemcpyDeviceToHost, h->stream));
+    std::vector<int32_t> flags((size_t)FLAG_COUNT * h->reps.size());
+    HIPCHK(h, hipMemcpyAsync(flags.data(), h->lst.flags, sizeof(int32_t) * flags.size(), hipMemcpyDeviceToHost,
+                             h->stream));
     HIPCHK(h, hipStreamSynchronize(h->stream));
-    if (flags[FLAG_NONFINITE]) return fail(h, DEM_E_NONFINITE, "non-finite position or velocity");
-    if (flags[FLAG_MAXROW] > h->sp.cap)
-        return fail(h, DEM_E_CAPACITY, "neighbour row of %d exceeds capacity %d", flags[FLAG_MAXROW], h->sp.cap);
+    for (size_t r = 0; r < h->reps.size(); ++r) {
+        if (!h->reps[r].live) continue;
+        const int32_t *f = flags.data() + FLAG_COUNT * r;
+        if (f[FLAG_NONFINITE]) return fail(h, DEM_E_NONFINITE, "replica %zu: non-finite position or velocity", r);
+        if (f[FLAG_MAXROW] > h->bp.cap)
+            return fail(h, DEM_E_CAPACITY, "replica %zu: neighbour row of %d exceeds capacity %d", r, f[FLAG_MAXROW],
+                        h->bp.cap);
+    }
     return DEM_OK;
 }
 
 void enqueue_step(dem_system *h, hipStream_t s)
 {
-    const ForcePtrs f = force_ptrs(h);
-    launch_kick_drift(h->sp, h->st, h->out, h->lst, h->thermo, h->rot, h->prm.precision, s);
-    launch_build_lists(h->sp, h->st, h->lst, s);
-    launch_pairs(h->sp, h->st, h->lst, f, h->prm.precision, h->counting ? h->stats : nullptr, s);
-    launch_gather(h->sp, h->st, h->out, h->lst, f, h->prm.precision, true, h->ke_part, h->thermo, s);
+    const Launch L = make_launch(h);
+    launch_kick_drift(L, s);
+    launch_build_lists(L, h->list_multi, h->reps[0].sp, s);
+    launch_pairs(L, h->counting ? h->stats : nullptr, s);
+    launch_gather(L, true, s);
 }
 
 dem_status ensure_graph(dem_system *h)
@@ -374,23 +581,304 @@ dem_status ensure_graph(dem_system *h)
     return DEM_OK;
 }
 
-dem_status build_lists_sync(dem_system *h)
+// Rebuilds the lists of the replicas in `which` (all live ones if empty)
+// now, growing the row capacity while it overflows and is automatic.
+dem_status build_lists_sync(dem_system *h, int only)
 {
     for (int attempt = 0; attempt < 4; ++attempt) {
-        k_set_int<<<1, 1, 0, h->stream>>>(h->lst.flags + FLAG_REBUILD, 1);
-        k_set_int<<<1, 1, 0, h->stream>>>(h->lst.flags + FLAG_MAXROW, 0);
-        launch_build_lists(h->sp, h->st, h->lst, h->stream);
+        int marked = 0;
+        for (size_t r = 0; r < h->reps.size(); ++r) {
+            if (!h->reps[r].live || (only >= 0 && (int)r != only)) continue;
+            k_set_i32<<<1, 1, 0, h->stream>>>(h->lst.flags + FLAG_COUNT * r + FLAG_REBUILD, 1);
+            k_set_i32<<<1, 1, 0, h->stream>>>(h->lst.flags + FLAG_COUNT * r + FLAG_MAXROW, 0);
+            ++marked;
+        }
+        if (marked == 0) return DEM_OK;
+        k_set_i32<<<1, 1, 0, h->stream>>>(h->lst.gflags + G_ANY, 1);
+        launch_build_lists(make_launch(h), h->list_multi, h->reps[0].sp, h->stream);
         HIPCHK(h, hipGetLastError());
-        int32_t maxrow = 0;
-        HIPCHK(h, hipMemcpyAsync(&maxrow, h->lst.flags + FLAG_MAXROW, sizeof maxrow, hipMemcpyDeviceToHost, h->stream));
+        std::vector<int32_t> flags((size_t)FLAG_COUNT * h->reps.size());
+        HIPCHK(h, hipMemcpyAsync(flags.data(), h->lst.flags, sizeof(int32_t) * flags.size(), hipMemcpyDeviceToHost,
+                                 h->stream));
         HIPCHK(h, hipStreamSynchronize(h->stream));
-        if (maxrow <= h->sp.cap) return DEM_OK;
+        int maxrow = 0;
+        for (size_t r = 0; r < h->reps.size(); ++r)
+            if (h->reps[r].live) maxrow = std::max(maxrow, flags[FLAG_COUNT * r + FLAG_MAXROW]);
+        if (maxrow <= h->bp.cap) return DEM_OK;
         if (!h->auto_cap)
-            return fail(h, DEM_E_CAPACITY, "neighbour row of %d exceeds capacity %d", maxrow, h->sp.cap);
+            return fail(h, DEM_E_CAPACITY, "neighbour row of %d exceeds capacity %d", maxrow, h->bp.cap);
         dem_status st = alloc_nbr(h, ((maxrow * 5) / 4 + 8 + 3) & ~3);
         if (st != DEM_OK) return st;
+        only = -1;  // a new capacity moves every replica's rows: rebuild them all
     }
     return fail(h, DEM_E_CAPACITY, "neighbour capacity did not converge");
+}
+
+// Validates params against the handle and builds the replica's tables and
+// parameters (everything but its slots).
+dem_status describe_replica(dem_system *h, const dem_params &p, Replica &R, std::vector<ShapeTab<double>> &t64,
+                            std::vector<ShapeTab<float>> &t32)
+{
+    if (p.dim != 2 && p.dim != 3) return fail(h, DEM_E_ARG, "dim must be 2 or 3");
+    if (p.dim != h->dim) return fail(h, DEM_E_ARG, "replica dim %d differs from the batch's %d", p.dim, h->dim);
+    if (p.precision != h->precision) return fail(h, DEM_E_ARG, "replica precision differs from the batch's");
+    if (p.n < 0 || p.n > (int64_t)INT32_MAX / 64) return fail(h, DEM_E_ARG, "n out of range");
+    if (p.n_shapes < 1 || p.n_shapes > DEM_MAX_SHAPES || !p.shapes)
+        return fail(h, DEM_E_ARG, "n_shapes must be 1..%d", DEM_MAX_SHAPES);
+    if (p.ensemble != DEM_NVE && p.ensemble != DEM_NVT) return fail(h, DEM_E_ARG, "bad ensemble");
+    if (p.list_mode != DEM_LISTS_AUTO && p.list_mode != DEM_LISTS_MULTI) return fail(h, DEM_E_ARG, "bad list_mode");
+    if (!(p.dt > 0.0) || !(p.skin >= 0.0) || !(p.rebuild_frac > 0.0) || !(p.epsilon > 0.0) || !(p.parallel_sin2 >= 0.0))
+        return fail(h, DEM_E_ARG, "dt, epsilon, rebuild_frac must be > 0; skin, parallel_sin2 >= 0");
+    if (p.ensemble == DEM_NVT && (!(p.kT > 0.0) || !(p.tau_T > 0.0)))
+        return fail(h, DEM_E_ARG, "NVT needs kT > 0 and tau_T > 0");
+    for (int a = 0; a < p.dim; ++a)
+        if (!(p.box[a] > 0.0)) return fail(h, DEM_E_ARG, "box must be positive");
+    R = Replica{};
+    R.prm = p;
+    R.prm.shapes = nullptr;
+    t64.assign((size_t)p.n_shapes, ShapeTab<double>{});
+    t32.assign((size_t)p.n_shapes, ShapeTab<float>{});
+    double Rmax = 0.0, rmax = 0.0;
+    SysParams &sp = R.sp;
+    std::memset(&sp, 0, sizeof sp);
+    for (int s = 0; s < p.n_shapes; ++s) {
+        dem_status st = build_table(h, s, p.shapes[s], p.dim, t64[s]);
+        if (st != DEM_OK) return st;
+        to_float(t64[s], t32[s]);
+        sp.mass[s] = p.shapes[s].mass;
+        for (int a = 0; a < 3; ++a) sp.inertia[s][a] = (p.dim == 2 && a < 2) ? 0.0 : p.shapes[s].inertia[a];
+        sp.R[s] = t64[s].R;
+        sp.rad[s] = p.shapes[s].rounding_radius;
+        Rmax = std::max(Rmax, t64[s].R);
+        rmax = std::max(rmax, p.shapes[s].rounding_radius);
+    }
+    // r_list = 2 R_max + 2^(1/6) sigma_max + skin
+    const double rl = 2.0 * Rmax + kWcaCut * (2.0 * rmax) + p.skin;
+    R.r_list = rl;
+    sp.n = (int)p.n;
+    sp.dim = p.dim;
+    sp.n_shapes = p.n_shapes;
+    sp.ensemble = p.ensemble;
+    sp.use_cells = 1;
+    for (int a = 0; a < 3; ++a) {
+        sp.box[a] = (a < p.dim) ? p.box[a] : 1.0;
+        if (a < p.dim) {
+            if (p.box[a] < 2.0 * rl)
+                return fail(h, DEM_E_ARG, "box %g on axis %d is below 2 r_list = %g", p.box[a], a, 2.0 * rl);
+            sp.nc[a] = (int)std::floor(p.box[a] / rl);
+            if (sp.nc[a] < 3) sp.use_cells = 0;
+        } else {
+            sp.nc[a] = 1;
+        }
+        sp.cellw[a] = sp.box[a] / (double)sp.nc[a];
+    }
+    sp.ncell = sp.nc[0] * sp.nc[1] * sp.nc[2];
+    sp.rl2 = rl * rl;
+    sp.disp2 = (p.rebuild_frac * p.skin) * (p.rebuild_frac * p.skin);
+    sp.eps = p.epsilon;
+    sp.par_s2 = p.parallel_sin2;
+    sp.dt = p.dt;
+    sp.kT = p.kT;
+    const int drot = p.dim == 2 ? 1 : 3;
+    sp.g = (double)(p.dim * p.n + drot * p.n - p.dim);
+    sp.Qm = sp.g * p.kT * p.tau_T * p.tau_T;
+    return DEM_OK;
+}
+
+// Takes slots for a described replica, uploads its tables, copies its state
+// in (a batch) and checks its shape ids.  Returns the slot in *rid.
+dem_status place_replica(dem_system *h, Replica &R, const std::vector<ShapeTab<double>> &t64,
+                         const std::vector<ShapeTab<float>> &t32, const dem_state_ptrs *src, int *rid)
+{
+    int slot = -1;
+    for (size_t r = 0; r < h->reps.size(); ++r)
+        if (!h->reps[r].live) {
+            slot = (int)r;
+            break;
+        }
+    if (slot < 0) return fail(h, DEM_E_OOM, "no free replica slot (%zu in use)", h->reps.size());
+    const int n = R.sp.n;
+    R.nchunks = (n + kChunk - 1) / kChunk;
+    R.ncells = R.sp.ncell + 1;
+    R.nshapes = R.sp.n_shapes;
+    R.chunk0 = h->chunks.find(R.nchunks);
+    R.cell0 = h->cells.find(R.ncells);
+    R.shape0 = h->shapes.find(R.nshapes);
+    if (R.chunk0 < 0) return fail(h, DEM_E_OOM, "no run of %d free particle slots", R.nchunks * kChunk);
+    if (R.cell0 < 0) return fail(h, DEM_E_OOM, "no run of %d free cell slots", R.ncells);
+    if (R.shape0 < 0) return fail(h, DEM_E_OOM, "no run of %d free shape slots", R.nshapes);
+    R.sp.off = R.chunk0 * kChunk;
+    R.sp.coff = R.cell0;
+    R.sp.sbase = R.shape0;
+    R.sp.rid = slot;
+    const size_t off = (size_t)R.sp.off;
+    if (n > 0 && h->batch) {  // copy the replica's state into the batch's arrays
+        const double *from[] = {src->x,  src->y,  src->qw, src->qx, src->qy, src->qz,
+                                src->vx, src->vy, src->vz, src->Lx, src->Ly, src->Lz};
+        double *to[] = {h->st.x, h->st.y, h->st.qw, h->st.qx, h->st.qy, h->st.qz,
+                        h->st.vx, h->st.vy, h->st.vz, h->st.Lx, h->st.Ly, h->st.Lz};
+        for (int k = 0; k < 12; ++k) {
+            if (!from[k]) return fail(h, DEM_E_ARG, "null state array");
+            HIPCHK(h, hipMemcpyAsync(to[k] + off, from[k], sizeof(double) * n, hipMemcpyDeviceToDevice, h->stream));
+        }
+        if (h->dim == 3) {
+            if (!src->z) return fail(h, DEM_E_ARG, "null state array");
+            HIPCHK(h, hipMemcpyAsync(h->st.z + off, src->z, sizeof(double) * n, hipMemcpyDeviceToDevice, h->stream));
+        } else {
+            HIPCHK(h, hipMemsetAsync(h->st.z + off, 0, sizeof(double) * n, h->stream));
+        }
+        if (!src->shape_id || !src->image) return fail(h, DEM_E_ARG, "null state array");
+        HIPCHK(h, hipMemcpyAsync(h->st.sid + off, src->shape_id, sizeof(int32_t) * n, hipMemcpyDeviceToDevice,
+                                 h->stream));
+        HIPCHK(h, hipMemcpyAsync(h->st.image + 3 * off, src->image, sizeof(int32_t) * 3 * n,
+                                 hipMemcpyDeviceToDevice, h->stream));
+    }
+    if (n > 0) {  // shape ids index the LDS tables: validate before any kernel reads them
+        std::vector<int32_t> sid((size_t)n);
+        HIPCHK(h, hipMemcpyAsync(sid.data(), h->st.sid + off, sizeof(int32_t) * n, hipMemcpyDeviceToHost, h->stream));
+        HIPCHK(h, hipStreamSynchronize(h->stream));
+        for (int i = 0; i < n; ++i)
+            if (sid[i] < 0 || sid[i] >= R.sp.n_shapes)
+                return fail(h, DEM_E_ARG, "shape_id[%d] = %d outside [0, %d)", i, sid[i], R.sp.n_shapes);
+    }
+    HIPCHK(h, hipMemcpyAsync(static_cast<ShapeTab<double> *>(h->tab64) + R.shape0, t64.data(),
+                             sizeof(ShapeTab<double>) * R.nshapes, hipMemcpyHostToDevice, h->stream));
+    HIPCHK(h, hipMemcpyAsync(static_cast<ShapeTab<float> *>(h->tab32) + R.shape0, t32.data(),
+                             sizeof(ShapeTab<float>) * R.nshapes, hipMemcpyHostToDevice, h->stream));
+    HIPCHK(h, hipMemsetAsync(h->lst.cell_count + R.cell0, 0, sizeof(int32_t) * R.ncells, h->stream));
+    HIPCHK(h, hipMemsetAsync(h->lst.flags + FLAG_COUNT * slot, 0, sizeof(int32_t) * FLAG_COUNT, h->stream));
+    if (n > 0) HIPCHK(h, hipMemsetAsync(h->lst.n_nbr + off, 0, sizeof(int32_t) * n, h->stream));
+    k_set_thermo<<<1, 1, 0, h->stream>>>(h->thermo + TH_COUNT * slot, 0.0, 0.0);
+    k_set_i64<<<1, 1, 0, h->stream>>>(h->budget + slot, kUnbounded);
+    k_set_i64<<<1, 1, 0, h->stream>>>(h->steps + slot, 0);
+    h->chunks.mark(R.chunk0, R.nchunks, 1);
+    h->cells.mark(R.cell0, R.ncells, 1);
+    h->shapes.mark(R.shape0, R.nshapes, 1);
+    R.live = true;
+    h->reps[slot] = R;
+    place_pairs(h);
+    *rid = slot;
+    return upload_tables(h);
+}
+
+void release_replica(dem_system *h, int r)
+{
+    Replica &R = h->reps[r];
+    if (!R.live) return;
+    h->chunks.mark(R.chunk0, R.nchunks, 0);
+    h->cells.mark(R.cell0, R.ncells, 0);
+    h->shapes.mark(R.shape0, R.nshapes, 0);
+    R = Replica{};
+}
+
+dem_status compute_forces(dem_system *h)
+{
+    const Launch L = make_launch(h);
+    launch_rotations(L, h->stream);
+    launch_build_lists(L, h->list_multi, h->reps[0].sp, h->stream);  // gated: only if a rebuild is due
+    launch_pairs(L, h->stats, h->stream);
+    launch_gather(L, false, h->stream);
+    HIPCHK(h, hipGetLastError());
+    return DEM_OK;
+}
+
+bool valid_replica(const dem_system *h, int r) { return h && r >= 0 && r < (int)h->reps.size() && h->reps[r].live; }
+
+dem_status replica_energy(dem_system *h, int r, dem_energy_out *o)
+{
+    std::memset(o, 0, sizeof *o);
+    const Replica &R = h->reps[r];
+    const SysParams &sp = R.sp;
+    std::vector<double> part((size_t)12 * std::max(R.nchunks, 1), 0.0);
+    double th[TH_COUNT];
+    int32_t flags[FLAG_COUNT];
+    int64_t steps = 0;
+    launch_energy_partials(make_launch(h), h->e_part, h->stream);
+    HIPCHK(h, hipGetLastError());
+    if (R.nchunks > 0)
+        HIPCHK(h, hipMemcpyAsync(part.data(), h->e_part + (size_t)12 * R.chunk0, sizeof(double) * 12 * R.nchunks,
+                                 hipMemcpyDeviceToHost, h->stream));
+    HIPCHK(h, hipMemcpyAsync(th, h->thermo + TH_COUNT * r, sizeof th, hipMemcpyDeviceToHost, h->stream));
+    HIPCHK(h, hipMemcpyAsync(flags, h->lst.flags + FLAG_COUNT * r, sizeof flags, hipMemcpyDeviceToHost, h->stream));
+    HIPCHK(h, hipMemcpyAsync(&steps, h->steps + r, sizeof steps, hipMemcpyDeviceToHost, h->stream));
+    HIPCHK(h, hipStreamSynchronize(h->stream));
+    double acc[12] = {0};
+    for (int b = 0; b < R.nchunks; ++b)
+        for (int c = 0; c < 12; ++c) acc[c] += part[(size_t)12 * b + c];
+    o->U = acc[0];
+    o->K_trans = acc[1];
+    o->K_rot = acc[2];
+    for (int c = 0; c < 9; ++c) o->W[c] = acc[3 + c];
+    const double K = o->K_trans + o->K_rot;
+    o->T = sp.g > 0 ? 2.0 * K / sp.g : 0.0;
+    const int d = sp.dim;
+    const double vol = d == 3 ? sp.box[0] * sp.box[1] * sp.box[2] : sp.box[0] * sp.box[1];
+    const double trW = d == 3 ? o->W[0] + o->W[4] + o->W[8] : o->W[0] + o->W[4];
+    o->P = (2.0 * o->K_trans + trW) / (d * vol);
+    o->xi = th[TH_XI];
+    o->eta = th[TH_ETA];
+    o->H = K + o->U;
+    if (sp.ensemble == DEM_NVT) o->H += 0.5 * sp.Qm * o->xi * o->xi + sp.g * sp.kT * o->eta;
+    o->step = steps;
+    o->n_rebuilds = flags[FLAG_NBUILDS];
+    if (flags[FLAG_NONFINITE]) return fail(h, DEM_E_NONFINITE, "non-finite position or velocity");
+    if (flags[FLAG_MAXROW] > h->bp.cap)
+        return fail(h, DEM_E_CAPACITY, "neighbour row of %d exceeds capacity %d", flags[FLAG_MAXROW], h->bp.cap);
+    return DEM_OK;
+}
+
+dem_status copy_lists(dem_system *h, int r, int32_t *cell_start, int32_t *cell_particles, int32_t *nbr,
+                      int32_t *n_nbr, int32_t *dims)
+{
+    const Replica &R = h->reps[r];
+    const size_t n = (size_t)R.sp.n, off = (size_t)R.sp.off, N = (size_t)h->bp.N;
+    if (cell_start)
+        HIPCHK(h, hipMemcpyAsync(cell_start, h->lst.cell_start + R.cell0, sizeof(int32_t) * (R.sp.ncell + 1),
+                                 hipMemcpyDeviceToHost, h->stream));
+    if (cell_particles && n)
+        HIPCHK(h, hipMemcpyAsync(cell_particles, h->lst.cell_particles + off, sizeof(int32_t) * n,
+                                 hipMemcpyDeviceToHost, h->stream));
+    if (nbr && n)
+        HIPCHK(h, hipMemcpy2DAsync(nbr, sizeof(int32_t) * n, h->lst.nbr + off, sizeof(int32_t) * N,
+                                   sizeof(int32_t) * n, (size_t)h->bp.cap, hipMemcpyDeviceToHost, h->stream));
+    if (n_nbr && n)
+        HIPCHK(h, hipMemcpyAsync(n_nbr, h->lst.n_nbr + off, sizeof(int32_t) * n, hipMemcpyDeviceToHost, h->stream));
+    HIPCHK(h, hipStreamSynchronize(h->stream));
+    // particle indices of the replica, from its slots
+    if (cell_particles)
+        for (size_t k = 0; k < n; ++k) cell_particles[k] -= (int32_t)off;
+    if (nbr && n_nbr)
+        for (size_t i = 0; i < n; ++i)
+            for (int k = 0; k < n_nbr[i]; ++k) nbr[(size_t)k * n + i] -= (int32_t)off;
+    if (dims) {
+        dims[0] = R.sp.nc[0];
+        dims[1] = R.sp.nc[1];
+        dims[2] = R.sp.nc[2];
+        dims[3] = h->bp.cap;
+    }
+    return DEM_OK;
+}
+
+dem_status run_steps(dem_system *h, int64_t n_steps)
+{
+    if (n_steps < 0) return fail(h, DEM_E_ARG, "n_steps < 0");
+    if (n_steps == 0) return DEM_OK;
+    for (size_t r = 0; r < h->reps.size(); ++r)
+        if (h->reps[r].live && h->reps[r].sp.n == 0) k_advance_empty<<<1, 1, 0, h->stream>>>(h->budget + r, h->steps + r, n_steps);
+    if (h->bp.nchunk == 0) {
+        HIPCHK(h, hipGetLastError());
+        return DEM_OK;
+    }
+    dem_status st = ensure_graph(h);
+    if (st != DEM_OK) return st;
+    const Launch L = make_launch(h);
+    // opening half step of the first step, from the current kinetic energy
+    launch_kinetic(L, h->stream);
+    launch_nh_begin(L, h->stream);
+    for (int64_t k = 0; k < n_steps; ++k) HIPCHK(h, hipGraphLaunch(h->gexec, h->stream));
+    launch_nh_end(L, h->stream);
+    HIPCHK(h, hipGetLastError());
+    return DEM_OK;
 }
 
 }  // namespace
@@ -417,7 +905,7 @@ const char *dem_last_error(dem_handle h) { return h ? h->err.c_str() : g_err.c_s
 size_t dem_footprint_bytes(const dem_params *p)
 {
     if (!p || p->n < 0) return 0;
-    const size_t n = (size_t)std::max<int64_t>(p->n, 1);
+    const size_t n = (size_t)((std::max<int64_t>(p->n, 1) + kChunk - 1) / kChunk * kChunk);
     double Rm = 0.0, rm = 0.0;
     for (int s = 0; s < p->n_shapes && p->shapes; ++s) {
         const dem_shape_desc &d = p->shapes[s];
@@ -431,12 +919,12 @@ size_t dem_footprint_bytes(const dem_params *p)
     int cap = p->nbr_capacity > 0 ? p->nbr_capacity : auto_capacity(*p, rl);
     size_t ncell = 1;
     for (int a = 0; a < p->dim && a < 3; ++a) ncell *= (size_t)std::max(1.0, std::floor(p->box[a] / rl));
-    size_t nblk = (n + kBlock - 1) / kBlock;
-    const size_t w = p->precision == DEM_FP32 ? sizeof(float) : sizeof(double);
-    const size_t maxp = n * (size_t)cap / 2 + 64;
-    return sizeof(int32_t) * (n * (size_t)cap + 6 * n + 2 * ncell + 2 + 4 * maxp) +
-           sizeof(double) * (3 * n + 14 * nblk + TH_COUNT) + w * (16 * n + kRec * (size_t)cap * n) +
-           2 * DEM_MAX_SHAPES * sizeof(ShapeTab<double>) + 256;
+    const size_t nch = n / kChunk;
+    const size_t w = force_word(p->precision);
+    const size_t maxp = n * (size_t)cap / 2;
+    return sizeof(int32_t) * (n * (size_t)cap + 7 * n + 2 * ncell + 2 + 4 * maxp + nch) +
+           sizeof(double) * (3 * n + 14 * nch + TH_COUNT + 2) + partrec_bytes(p->precision) * n +
+           w * kRec * (size_t)cap * n + sizeof(SysParams) + 2 * DEM_MAX_SHAPES * sizeof(ShapeTab<double>) + 256;
 }
 
 dem_status dem_create_system(const dem_params *params, const dem_state_ptrs *state, const dem_output_ptrs *outputs,
@@ -446,18 +934,8 @@ dem_status dem_create_system(const dem_params *params, const dem_state_ptrs *sta
     if (!params || !state || !outputs || !out) return fail(nullptr, DEM_E_ARG, "null argument");
     const dem_params &p = *params;
     if (p.dim != 2 && p.dim != 3) return fail(nullptr, DEM_E_ARG, "dim must be 2 or 3");
-    if (p.n < 0 || p.n > (int64_t)INT32_MAX / 64) return fail(nullptr, DEM_E_ARG, "n out of range");
-    if (p.n_shapes < 1 || p.n_shapes > DEM_MAX_SHAPES || !p.shapes)
-        return fail(nullptr, DEM_E_ARG, "n_shapes must be 1..%d", DEM_MAX_SHAPES);
-    if (p.ensemble != DEM_NVE && p.ensemble != DEM_NVT) return fail(nullptr, DEM_E_ARG, "bad ensemble");
     if (p.precision != DEM_FP64 && p.precision != DEM_FP32) return fail(nullptr, DEM_E_ARG, "bad precision");
-    if (p.list_mode != DEM_LISTS_AUTO && p.list_mode != DEM_LISTS_MULTI) return fail(nullptr, DEM_E_ARG, "bad list_mode");
-    if (!(p.dt > 0.0) || !(p.skin >= 0.0) || !(p.rebuild_frac > 0.0) || !(p.epsilon > 0.0) || !(p.parallel_sin2 >= 0.0))
-        return fail(nullptr, DEM_E_ARG, "dt, epsilon, rebuild_frac must be > 0; skin, parallel_sin2 >= 0");
-    if (p.ensemble == DEM_NVT && (!(p.kT > 0.0) || !(p.tau_T > 0.0)))
-        return fail(nullptr, DEM_E_ARG, "NVT needs kT > 0 and tau_T > 0");
-    for (int a = 0; a < p.dim; ++a)
-        if (!(p.box[a] > 0.0)) return fail(nullptr, DEM_E_ARG, "box must be positive");
+    if (p.n < 0 || p.n > (int64_t)INT32_MAX / 64) return fail(nullptr, DEM_E_ARG, "n out of range");
     if (p.n > 0) {
         const double *req[] = {state->x, state->y, state->qw, state->qx, state->qy, state->qz, state->vx, state->vy,
                                state->vz, state->Lx, state->Ly, state->Lz, outputs->Fx, outputs->Fy, outputs->Fz,
@@ -467,125 +945,205 @@ dem_status dem_create_system(const dem_params *params, const dem_state_ptrs *sta
         if (!state->shape_id || !state->image || (p.dim == 3 && !state->z))
             return fail(nullptr, DEM_E_ARG, "null state array");
     }
-
     dem_system *h = new (std::nothrow) dem_system();
     if (!h) return fail(nullptr, DEM_E_OOM, "host allocation");
-    h->prm = p;
-    h->prm.shapes = nullptr;
+    h->batch = false;
+    h->dim = p.dim;
+    h->precision = p.precision;
     h->stream = (hipStream_t)hip_stream;
     auto bail = [&](dem_status s) {
+        g_err = h->err;
         dem_destroy_system(h);
         return s;
     };
-
-    std::vector<ShapeTab<double>> t64(p.n_shapes);
-    std::vector<ShapeTab<float>> t32(p.n_shapes);
-    double Rmax = 0.0, rmax = 0.0;
-    SysParams &sp = h->sp;
-    std::memset(&sp, 0, sizeof sp);
-    for (int s = 0; s < p.n_shapes; ++s) {
-        dem_status st = build_table(h, s, p.shapes[s], p.dim, t64[s]);
-        if (st != DEM_OK) {
-            g_err = h->err;
-            return bail(st);
-        }
-        to_float(t64[s], t32[s]);
-        sp.mass[s] = p.shapes[s].mass;
-        for (int a = 0; a < 3; ++a) sp.inertia[s][a] = (p.dim == 2 && a < 2) ? 0.0 : p.shapes[s].inertia[a];
-        sp.R[s] = t64[s].R;
-        sp.rad[s] = p.shapes[s].rounding_radius;
-        Rmax = std::max(Rmax, t64[s].R);
-        rmax = std::max(rmax, p.shapes[s].rounding_radius);
-    }
-    // r_list = 2 R_max + 2^(1/6) sigma_max + skin
-    const double rl = 2.0 * Rmax + kWcaCut * (2.0 * rmax) + p.skin;
-    h->r_list = rl;
-    sp.n = (int)p.n;
-    sp.dim = p.dim;
-    sp.n_shapes = p.n_shapes;
-    sp.ensemble = p.ensemble;
-    sp.use_cells = 1;
-    sp.force_multi_kernel_lists = p.list_mode == DEM_LISTS_MULTI ? 1 : 0;
-    for (int a = 0; a < 3; ++a) {
-        sp.box[a] = (a < p.dim) ? p.box[a] : 1.0;
-        if (a < p.dim) {
-            if (p.box[a] < 2.0 * rl)
-                return bail(fail(h, DEM_E_ARG, "box %g on axis %d is below 2 r_list = %g", p.box[a], a, 2.0 * rl));
-            sp.nc[a] = (int)std::floor(p.box[a] / rl);
-            if (sp.nc[a] < 3) sp.use_cells = 0;
-        } else {
-            sp.nc[a] = 1;
-        }
-        sp.cellw[a] = sp.box[a] / (double)sp.nc[a];
-    }
-    sp.ncell = sp.nc[0] * sp.nc[1] * sp.nc[2];
-    sp.rl2 = rl * rl;
-    sp.disp2 = (p.rebuild_frac * p.skin) * (p.rebuild_frac * p.skin);
-    sp.eps = p.epsilon;
-    sp.par_s2 = p.parallel_sin2;
-    sp.dt = p.dt;
-    sp.kT = p.kT;
-    const int drot = p.dim == 2 ? 1 : 3;
-    sp.g = (double)(p.dim * p.n + drot * p.n - p.dim);
-    sp.Qm = sp.g * p.kT * p.tau_T * p.tau_T;
-
-    h->st = {state->x, state->y, p.dim == 3 ? state->z : nullptr, state->qw, state->qx, state->qy, state->qz,
-             state->vx, state->vy, state->vz, state->Lx, state->Ly, state->Lz, state->shape_id, state->image};
-    if (p.dim == 2) h->st.z = state->z;  // may be null; never read in 2D
+    Replica R;
+    std::vector<ShapeTab<double>> t64;
+    std::vector<ShapeTab<float>> t32;
+    dem_status st = describe_replica(h, p, R, t64, t32);
+    if (st != DEM_OK) return bail(st);
+    h->st = {state->x, state->y, state->z, state->qw, state->qx, state->qy, state->qz, state->vx, state->vy,
+             state->vz, state->Lx, state->Ly, state->Lz, state->shape_id, state->image};
     h->out = {outputs->Fx, outputs->Fy, outputs->Fz, outputs->Tx, outputs->Ty, outputs->Tz, outputs->U, outputs->W};
-
-    const size_t n = (size_t)std::max(sp.n, 1);
-    h->nblk = (int)((n + kBlock - 1) / kBlock);
-    const int kblk = gather_blocks((int)n);
+    h->bp.wstride = (int)p.n;
+    h->list_multi = (p.list_mode == DEM_LISTS_MULTI || p.n > fused_list_max_n()) ? 1 : 0;
     if (hipStreamCreateWithFlags(&h->cap_stream, hipStreamNonBlocking) != hipSuccess)
         return bail(fail(h, DEM_E_HIP, "stream creation failed"));
-    bool ok = hipMalloc(&h->tab64, sizeof(ShapeTab<double>) * p.n_shapes) == hipSuccess &&
-              hipMalloc(&h->tab32, sizeof(ShapeTab<float>) * p.n_shapes) == hipSuccess &&
-              hipMalloc(&h->ke_part, sizeof(double) * 2 * kblk) == hipSuccess &&
-              hipMalloc(&h->e_part, sizeof(double) * 12 * h->nblk) == hipSuccess &&
-              hipMalloc(&h->thermo, sizeof(double) * TH_COUNT) == hipSuccess &&
-              hipMalloc(&h->stats, sizeof(unsigned long long) * ST_COUNT) == hipSuccess &&
-              hipMalloc(&h->lst.flags, sizeof(int32_t) * FLAG_COUNT) == hipSuccess &&
-              hipMalloc(&h->lst.cell_count, sizeof(int32_t) * sp.ncell) == hipSuccess &&
-              hipMalloc(&h->lst.cell_start, sizeof(int32_t) * (sp.ncell + 1)) == hipSuccess &&
-              hipMalloc(&h->lst.cell_particles, sizeof(int32_t) * n) == hipSuccess &&
-              hipMalloc(&h->lst.pcell, sizeof(int32_t) * n) == hipSuccess &&
-              hipMalloc(&h->lst.n_nbr, sizeof(int32_t) * n) == hipSuccess &&
-              hipMalloc(&h->lst.xlast, sizeof(double) * 3 * n) == hipSuccess &&
-              hipMalloc(&h->lst.klo, sizeof(int32_t) * n) == hipSuccess &&
-              hipMalloc(&h->lst.pstart, sizeof(int32_t) * (n + 1)) == hipSuccess &&
-              hipMalloc(&h->rot, (p.precision == DEM_FP32 ? sizeof(PartRec<float>) : sizeof(PartRec<double>)) * n) ==
-                  hipSuccess;
-    if (!ok) return bail(fail(h, DEM_E_OOM, "device allocation failed"));
-    if (sp.n > 0) {  // shape ids index the LDS tables: validate before any kernel reads them
-        std::vector<int32_t> sid((size_t)sp.n);
-        if (hipMemcpyAsync(sid.data(), state->shape_id, sizeof(int32_t) * sid.size(), hipMemcpyDeviceToHost,
-                           h->stream) != hipSuccess ||
-            hipStreamSynchronize(h->stream) != hipSuccess)
-            return bail(fail(h, DEM_E_HIP, "reading shape_id failed"));
-        for (size_t i = 0; i < sid.size(); ++i)
-            if (sid[i] < 0 || sid[i] >= p.n_shapes)
-                return bail(fail(h, DEM_E_ARG, "shape_id[%zu] = %d outside [0, %d)", i, sid[i], p.n_shapes));
-    }
+    const int nch = (int)((p.n + kChunk - 1) / kChunk);
+    if ((st = alloc_core(h, nch * kChunk, R.sp.ncell + 1, p.n_shapes, 1)) != DEM_OK) return bail(st);
     h->auto_cap = p.nbr_capacity <= 0;
-    dem_status st = alloc_nbr(h, h->auto_cap ? auto_capacity(p, rl) : p.nbr_capacity);
-    if (st != DEM_OK) return bail(st);
-    // initial contents (not captured: plain memsets are fine here)
-    if (hipMemcpyAsync(h->tab64, t64.data(), sizeof(ShapeTab<double>) * p.n_shapes, hipMemcpyHostToDevice, h->stream) !=
-            hipSuccess ||
-        hipMemcpyAsync(h->tab32, t32.data(), sizeof(ShapeTab<float>) * p.n_shapes, hipMemcpyHostToDevice, h->stream) !=
-            hipSuccess ||
-        hipMemsetAsync(h->lst.flags, 0, sizeof(int32_t) * FLAG_COUNT, h->stream) != hipSuccess ||
-        hipMemsetAsync(h->lst.cell_count, 0, sizeof(int32_t) * sp.ncell, h->stream) != hipSuccess ||
-        hipMemsetAsync(h->lst.n_nbr, 0, sizeof(int32_t) * n, h->stream) != hipSuccess ||
-        hipMemsetAsync(h->stats, 0, sizeof(unsigned long long) * ST_COUNT, h->stream) != hipSuccess ||
-        hipMemsetAsync(h->ke_part, 0, sizeof(double) * 2 * kblk, h->stream) != hipSuccess)
-        return bail(fail(h, DEM_E_HIP, "initial upload failed"));
-    k_set_thermo<<<1, 1, 0, h->stream>>>(h->thermo, 0.0, 0.0);
-    if ((st = build_lists_sync(h)) != DEM_OK) return bail(st);
-    if ((st = dem_compute_forces(h)) != DEM_OK) return bail(st);
-    if ((st = dem_sync(h)) != DEM_OK) return bail(st);
+    if ((st = alloc_nbr(h, h->auto_cap ? auto_capacity(p, R.r_list) : p.nbr_capacity)) != DEM_OK) return bail(st);
+    int rid = -1;
+    if ((st = place_replica(h, R, t64, t32, nullptr, &rid)) != DEM_OK) return bail(st);
+    if ((st = build_lists_sync(h, -1)) != DEM_OK) return bail(st);
+    if ((st = compute_forces(h)) != DEM_OK) return bail(st);
+    if ((st = latched(h)) != DEM_OK) return bail(st);
     *out = h;
+    return DEM_OK;
+}
+
+dem_status dem_batch_create(const dem_batch_params *bpar, void *hip_stream, dem_handle *out)
+{
+    if (out) *out = nullptr;
+    if (!bpar || !out) return fail(nullptr, DEM_E_ARG, "null argument");
+    const dem_batch_params &b = *bpar;
+    if (b.dim != 2 && b.dim != 3) return fail(nullptr, DEM_E_ARG, "dim must be 2 or 3");
+    if (b.precision != DEM_FP64 && b.precision != DEM_FP32) return fail(nullptr, DEM_E_ARG, "bad precision");
+    if (b.max_replicas < 1 || b.max_replicas > 65536) return fail(nullptr, DEM_E_ARG, "max_replicas out of range");
+    if (b.max_particles < 1 || b.max_particles > (int64_t)INT32_MAX / 128)
+        return fail(nullptr, DEM_E_ARG, "max_particles out of range");
+    if (b.max_cells < 0 || b.max_cells > (int64_t)INT32_MAX / 2 || b.max_shapes < 0 || b.nbr_capacity < 0)
+        return fail(nullptr, DEM_E_ARG, "negative or oversized limit");
+    dem_system *h = new (std::nothrow) dem_system();
+    if (!h) return fail(nullptr, DEM_E_OOM, "host allocation");
+    h->batch = true;
+    h->dim = b.dim;
+    h->precision = b.precision;
+    h->stream = (hipStream_t)hip_stream;
+    auto bail = [&](dem_status s) {
+        g_err = h->err;
+        dem_destroy_system(h);
+        return s;
+    };
+    const int Ncap = (int)((b.max_particles + kChunk - 1) / kChunk * kChunk);
+    const int Ccap = b.max_cells > 0 ? (int)b.max_cells : Ncap + 2 * b.max_replicas;
+    const int Scap = b.max_shapes > 0 ? b.max_shapes : DEM_MAX_SHAPES * b.max_replicas;
+    dem_status st;
+    if (hipStreamCreateWithFlags(&h->cap_stream, hipStreamNonBlocking) != hipSuccess)
+        return bail(fail(h, DEM_E_HIP, "stream creation failed"));
+    if ((st = alloc_core(h, Ncap, Ccap, Scap, b.max_replicas)) != DEM_OK) return bail(st);
+    h->auto_cap = b.nbr_capacity <= 0;
+    if ((st = alloc_nbr(h, h->auto_cap ? 16 : ((b.nbr_capacity + 3) & ~3))) != DEM_OK) return bail(st);
+    if ((st = upload_tables(h)) != DEM_OK) return bail(st);
+    HIPCHK(h, hipStreamSynchronize(h->stream));
+    *out = h;
+    return DEM_OK;
+}
+
+dem_status dem_batch_add(dem_handle h, const dem_params *params, const dem_state_ptrs *state, int64_t steps,
+                         int32_t *replica_id)
+{
+    if (replica_id) *replica_id = -1;
+    if (!h || !params || !state || !replica_id) return fail(h, DEM_E_ARG, "null argument");
+    if (!h->batch) return fail(h, DEM_E_STATE, "not a batch handle");
+    if (params->n > fused_list_max_n())
+        return fail(h, DEM_E_ARG, "replica of %lld particles exceeds the batch limit %d", (long long)params->n,
+                    fused_list_max_n());
+    if (steps < 0) return fail(h, DEM_E_ARG, "steps < 0");
+    Replica R;
+    std::vector<ShapeTab<double>> t64;
+    std::vector<ShapeTab<float>> t32;
+    dem_status st = describe_replica(h, *params, R, t64, t32);
+    if (st != DEM_OK) return st;
+    if (R.nchunks * kChunk > h->Ncap) return fail(h, DEM_E_OOM, "replica larger than the batch");
+    const int want = h->auto_cap ? auto_capacity(*params, R.r_list) : h->bp.cap;
+    int rid = -1;
+    if ((st = place_replica(h, R, t64, t32, state, &rid)) != DEM_OK) return st;
+    if (want > h->bp.cap) {
+        if ((st = alloc_nbr(h, want)) != DEM_OK) return st;
+        if ((st = build_lists_sync(h, -1)) != DEM_OK) return st;
+    } else if ((st = build_lists_sync(h, rid)) != DEM_OK) {
+        return st;
+    }
+    if ((st = compute_forces(h)) != DEM_OK) return st;
+    if (steps > 0) k_set_i64<<<1, 1, 0, h->stream>>>(h->budget + rid, steps);
+    HIPCHK(h, hipGetLastError());
+    *replica_id = rid;
+    return DEM_OK;
+}
+
+dem_status dem_batch_remove(dem_handle h, int32_t rid)
+{
+    if (!h || !h->batch) return fail(h, DEM_E_ARG, "not a batch handle");
+    if (!valid_replica(h, rid)) return fail(h, DEM_E_ARG, "no replica %d", rid);
+    release_replica(h, rid);
+    place_pairs(h);
+    dem_status st = upload_tables(h);
+    if (st != DEM_OK) return st;
+    // the tile plan must drop the replica before the next pair launch
+    k_set_i32<<<1, 1, 0, h->stream>>>(h->lst.gflags + G_ANY, 1);
+    HIPCHK(h, hipGetLastError());
+    return DEM_OK;
+}
+
+dem_status dem_batch_read(dem_handle h, int32_t rid, const dem_state_ptrs *state, const dem_output_ptrs *outputs)
+{
+    if (!h || !h->batch) return fail(h, DEM_E_ARG, "not a batch handle");
+    if (!valid_replica(h, rid)) return fail(h, DEM_E_ARG, "no replica %d", rid);
+    const Replica &R = h->reps[rid];
+    const size_t n = (size_t)R.sp.n, off = (size_t)R.sp.off;
+    if (n == 0) return DEM_OK;
+    if (state) {
+        double *to[] = {state->x, state->y, state->z, state->qw, state->qx, state->qy, state->qz,
+                        state->vx, state->vy, state->vz, state->Lx, state->Ly, state->Lz};
+        const double *from[] = {h->st.x, h->st.y, h->st.z, h->st.qw, h->st.qx, h->st.qy, h->st.qz,
+                                h->st.vx, h->st.vy, h->st.vz, h->st.Lx, h->st.Ly, h->st.Lz};
+        for (int k = 0; k < 13; ++k)
+            if (to[k])
+                HIPCHK(h, hipMemcpyAsync(to[k], from[k] + off, sizeof(double) * n, hipMemcpyDeviceToDevice, h->stream));
+        if (state->shape_id)
+            HIPCHK(h, hipMemcpyAsync(state->shape_id, h->st.sid + off, sizeof(int32_t) * n, hipMemcpyDeviceToDevice,
+                                     h->stream));
+        if (state->image)
+            HIPCHK(h, hipMemcpyAsync(state->image, h->st.image + 3 * off, sizeof(int32_t) * 3 * n,
+                                     hipMemcpyDeviceToDevice, h->stream));
+    }
+    if (outputs) {
+        double *to[] = {outputs->Fx, outputs->Fy, outputs->Fz, outputs->Tx, outputs->Ty, outputs->Tz, outputs->U};
+        const double *from[] = {h->out.Fx, h->out.Fy, h->out.Fz, h->out.Tx, h->out.Ty, h->out.Tz, h->out.U};
+        for (int k = 0; k < 7; ++k)
+            if (to[k])
+                HIPCHK(h, hipMemcpyAsync(to[k], from[k] + off, sizeof(double) * n, hipMemcpyDeviceToDevice, h->stream));
+        if (outputs->W)
+            HIPCHK(h, hipMemcpy2DAsync(outputs->W, sizeof(double) * n, h->out.W + off, sizeof(double) * h->bp.wstride,
+                                       sizeof(double) * n, 9, hipMemcpyDeviceToDevice, h->stream));
+    }
+    return DEM_OK;
+}
+
+dem_status dem_batch_set_steps(dem_handle h, int32_t rid, int64_t steps)
+{
+    if (!h || !h->batch) return fail(h, DEM_E_ARG, "not a batch handle");
+    if (!valid_replica(h, rid)) return fail(h, DEM_E_ARG, "no replica %d", rid);
+    k_set_i64<<<1, 1, 0, h->stream>>>(h->budget + rid, steps > 0 ? steps : 0);
+    HIPCHK(h, hipGetLastError());
+    return DEM_OK;
+}
+
+dem_status dem_batch_progress(dem_handle h, int64_t *steps_left, int64_t *steps_done, int32_t count)
+{
+    if (!h || count < 0) return fail(h, DEM_E_ARG, "bad argument");
+    const int n = std::min<int>(count, (int)h->reps.size());
+    if (n > 0 && steps_left)
+        HIPCHK(h, hipMemcpyAsync(steps_left, h->budget, sizeof(int64_t) * n, hipMemcpyDeviceToHost, h->stream));
+    if (n > 0 && steps_done)
+        HIPCHK(h, hipMemcpyAsync(steps_done, h->steps, sizeof(int64_t) * n, hipMemcpyDeviceToHost, h->stream));
+    HIPCHK(h, hipStreamSynchronize(h->stream));
+    for (int r = 0; r < n; ++r)
+        if (!h->reps[r].live) {
+            if (steps_left) steps_left[r] = -1;
+            if (steps_done) steps_done[r] = -1;
+        }
+    return latched(h);
+}
+
+dem_status dem_batch_info(dem_handle h, int64_t *out)
+{
+    if (!h || !out) return fail(h, DEM_E_ARG, "null argument");
+    int live = 0;
+    for (const Replica &R : h->reps) live += R.live ? 1 : 0;
+    int run = 0, best = 0;
+    for (int k = 0; k < h->chunks.size(); ++k) {
+        run = h->chunks.used[k] ? 0 : run + 1;
+        best = std::max(best, run);
+    }
+    out[0] = live;
+    out[1] = (int64_t)h->reps.size();
+    out[2] = (int64_t)h->chunks.free_slots() * kChunk;
+    out[3] = (int64_t)best * kChunk;
+    out[4] = h->cells.free_slots();
+    out[5] = h->shapes.free_slots();
+    out[6] = h->bp.cap;
+    out[7] = h->Ncap;
     return DEM_OK;
 }
 
@@ -593,15 +1151,7 @@ dem_status dem_destroy_system(dem_handle h)
 {
     if (!h) return DEM_E_ARG;
     if (h->stream) (void)hipStreamSynchronize(h->stream);
-    drop_graph(h);
-    free_lists(h);
-    (void)hipFree(h->lst.flags);
-    (void)hipFree(h->tab64);
-    (void)hipFree(h->tab32);
-    (void)hipFree(h->ke_part);
-    (void)hipFree(h->e_part);
-    (void)hipFree(h->thermo);
-    (void)hipFree(h->stats);
+    free_all(h);
     if (h->cap_stream) (void)hipStreamDestroy(h->cap_stream);
     delete h;
     return DEM_OK;
@@ -610,9 +1160,10 @@ dem_status dem_destroy_system(dem_handle h)
 dem_status dem_build_celllist(dem_handle h)
 {
     if (!h) return fail(nullptr, DEM_E_ARG, "null handle");
-    dem_status st = build_lists_sync(h);
+    dem_status st = build_lists_sync(h, -1);
     if (st != DEM_OK) return st;
-    k_end_build<<<1, 1, 0, h->stream>>>(h->lst.flags);
+    for (size_t r = 0; r < h->reps.size(); ++r)
+        if (h->reps[r].live) k_end_build<<<1, 1, 0, h->stream>>>(h->lst.flags + FLAG_COUNT * r);
     HIPCHK(h, hipGetLastError());
     return DEM_OK;
 }
@@ -620,35 +1171,13 @@ dem_status dem_build_celllist(dem_handle h)
 dem_status dem_compute_forces(dem_handle h)
 {
     if (!h) return fail(nullptr, DEM_E_ARG, "null handle");
-    const ForcePtrs f = force_ptrs(h);
-    launch_rotations(h->sp, h->st, h->rot, h->prm.precision, h->stream);
-    launch_build_lists(h->sp, h->st, h->lst, h->stream);  // gated: only if a rebuild is due
-    launch_pairs(h->sp, h->st, h->lst, f, h->prm.precision, h->stats, h->stream);
-    launch_gather(h->sp, h->st, h->out, h->lst, f, h->prm.precision, false, h->ke_part, h->thermo, h->stream);
-    HIPCHK(h, hipGetLastError());
-    return DEM_OK;
+    return compute_forces(h);
 }
 
 dem_status dem_step(dem_handle h, int64_t n_steps)
 {
     if (!h) return fail(nullptr, DEM_E_ARG, "null handle");
-    if (n_steps < 0) return fail(h, DEM_E_ARG, "n_steps < 0");
-    if (n_steps == 0 || h->sp.n == 0) {
-        h->step += n_steps;
-        return DEM_OK;
-    }
-    dem_status st = ensure_graph(h);
-    if (st != DEM_OK) return st;
-    const bool nvt = h->sp.ensemble == DEM_NVT;
-    if (nvt) {  // opening half step of the first step, from the current kinetic energy
-        launch_kinetic(h->sp, h->st, h->ke_part, h->stream);
-        launch_nh_begin(h->sp, h->ke_part, gather_blocks(h->sp.n), h->thermo, h->stream);
-    }
-    for (int64_t k = 0; k < n_steps; ++k) HIPCHK(h, hipGraphLaunch(h->gexec, h->stream));
-    if (nvt) launch_nh_end(h->sp, h->st, h->ke_part, h->nblk, h->thermo, h->stream);
-    HIPCHK(h, hipGetLastError());
-    h->step += n_steps;
-    return DEM_OK;
+    return run_steps(h, n_steps);
 }
 
 dem_status dem_sync(dem_handle h)
@@ -661,45 +1190,21 @@ dem_status dem_sync(dem_handle h)
 dem_status dem_energy(dem_handle h, dem_energy_out *o)
 {
     if (!h || !o) return fail(h, DEM_E_ARG, "null argument");
-    std::memset(o, 0, sizeof *o);
-    std::vector<double> part((size_t)12 * h->nblk, 0.0);
-    double th[TH_COUNT];
-    int32_t flags[FLAG_COUNT];
-    launch_energy_partials(h->sp, h->st, h->out, h->e_part, h->stream);
-    HIPCHK(h, hipGetLastError());
-    HIPCHK(h, hipMemcpyAsync(part.data(), h->e_part, sizeof(double) * part.size(), hipMemcpyDeviceToHost, h->stream));
-    HIPCHK(h, hipMemcpyAsync(th, h->thermo, sizeof th, hipMemcpyDeviceToHost, h->stream));
-    HIPCHK(h, hipMemcpyAsync(flags, h->lst.flags, sizeof flags, hipMemcpyDeviceToHost, h->stream));
-    HIPCHK(h, hipStreamSynchronize(h->stream));
-    double acc[12] = {0};
-    if (h->sp.n > 0)
-        for (int b = 0; b < h->nblk; ++b)
-            for (int c = 0; c < 12; ++c) acc[c] += part[(size_t)12 * b + c];
-    o->U = acc[0];
-    o->K_trans = acc[1];
-    o->K_rot = acc[2];
-    for (int c = 0; c < 9; ++c) o->W[c] = acc[3 + c];
-    const double K = o->K_trans + o->K_rot;
-    o->T = h->sp.g > 0 ? 2.0 * K / h->sp.g : 0.0;
-    const int d = h->sp.dim;
-    const double vol = d == 3 ? h->sp.box[0] * h->sp.box[1] * h->sp.box[2] : h->sp.box[0] * h->sp.box[1];
-    const double trW = d == 3 ? o->W[0] + o->W[4] + o->W[8] : o->W[0] + o->W[4];
-    o->P = (2.0 * o->K_trans + trW) / (d * vol);
-    o->xi = th[TH_XI];
-    o->eta = th[TH_ETA];
-    o->H = K + o->U;
-    if (h->sp.ensemble == DEM_NVT) o->H += 0.5 * h->sp.Qm * o->xi * o->xi + h->sp.g * h->sp.kT * o->eta;
-    o->step = h->step;
-    o->n_rebuilds = flags[FLAG_NBUILDS];
-    if (flags[FLAG_NONFINITE]) return fail(h, DEM_E_NONFINITE, "non-finite position or velocity");
-    if (flags[FLAG_MAXROW] > h->sp.cap)
-        return fail(h, DEM_E_CAPACITY, "neighbour row of %d exceeds capacity %d", flags[FLAG_MAXROW], h->sp.cap);
-    return DEM_OK;
+    if (!valid_replica(h, 0)) return fail(h, DEM_E_ARG, "no replica 0");
+    return replica_energy(h, 0, o);
+}
+
+dem_status dem_replica_energy(dem_handle h, int32_t rid, dem_energy_out *o)
+{
+    if (!h || !o) return fail(h, DEM_E_ARG, "null argument");
+    if (!valid_replica(h, rid)) return fail(h, DEM_E_ARG, "no replica %d", rid);
+    return replica_energy(h, rid, o);
 }
 
 dem_status dem_set_thermostat(dem_handle h, double xi, double eta)
 {
     if (!h) return fail(nullptr, DEM_E_ARG, "null handle");
+    if (!valid_replica(h, 0)) return fail(h, DEM_E_ARG, "no replica 0");
     k_set_thermo<<<1, 1, 0, h->stream>>>(h->thermo, xi, eta);
     HIPCHK(h, hipGetLastError());
     return DEM_OK;
@@ -709,33 +1214,25 @@ dem_status dem_copy_lists(dem_handle h, int32_t *cell_start, int32_t *cell_parti
                           int32_t *dims)
 {
     if (!h) return fail(nullptr, DEM_E_ARG, "null handle");
-    const size_t n = (size_t)h->sp.n;
-    if (cell_start)
-        HIPCHK(h, hipMemcpyAsync(cell_start, h->lst.cell_start, sizeof(int32_t) * (h->sp.ncell + 1),
-                                 hipMemcpyDeviceToHost, h->stream));
-    if (cell_particles && n)
-        HIPCHK(h, hipMemcpyAsync(cell_particles, h->lst.cell_particles, sizeof(int32_t) * n, hipMemcpyDeviceToHost,
-                                 h->stream));
-    if (nbr && n)
-        HIPCHK(h, hipMemcpyAsync(nbr, h->lst.nbr, sizeof(int32_t) * n * h->sp.cap, hipMemcpyDeviceToHost, h->stream));
-    if (n_nbr && n)
-        HIPCHK(h, hipMemcpyAsync(n_nbr, h->lst.n_nbr, sizeof(int32_t) * n, hipMemcpyDeviceToHost, h->stream));
-    HIPCHK(h, hipStreamSynchronize(h->stream));
-    if (dims) {
-        dims[0] = h->sp.nc[0];
-        dims[1] = h->sp.nc[1];
-        dims[2] = h->sp.nc[2];
-        dims[3] = h->sp.cap;
-    }
-    return DEM_OK;
+    if (!valid_replica(h, 0)) return fail(h, DEM_E_ARG, "no replica 0");
+    return copy_lists(h, 0, cell_start, cell_particles, nbr, n_nbr, dims);
+}
+
+dem_status dem_replica_lists(dem_handle h, int32_t rid, int32_t *cell_start, int32_t *cell_particles, int32_t *nbr,
+                             int32_t *n_nbr, int32_t *dims)
+{
+    if (!h) return fail(nullptr, DEM_E_ARG, "null handle");
+    if (!valid_replica(h, rid)) return fail(h, DEM_E_ARG, "no replica %d", rid);
+    return copy_lists(h, rid, cell_start, cell_particles, nbr, n_nbr, dims);
 }
 
 dem_status dem_list_info(dem_handle h, double *r_list, int32_t *n_cells, int32_t *capacity)
 {
     if (!h) return fail(nullptr, DEM_E_ARG, "null handle");
-    if (r_list) *r_list = h->r_list;
-    if (n_cells) *n_cells = h->sp.ncell;
-    if (capacity) *capacity = h->sp.cap;
+    if (!valid_replica(h, 0)) return fail(h, DEM_E_ARG, "no replica 0");
+    if (r_list) *r_list = h->reps[0].r_list;
+    if (n_cells) *n_cells = h->reps[0].sp.ncell;
+    if (capacity) *capacity = h->bp.cap;
     return DEM_OK;
 }
 
@@ -766,10 +1263,10 @@ dem_status dem_time_forces(dem_handle h, int32_t reps, double *mean_ms)
     hipEvent_t e0, e1;
     HIPCHK(h, hipEventCreate(&e0));
     HIPCHK(h, hipEventCreate(&e1));
-    const ForcePtrs f = force_ptrs(h);
-    launch_pairs(h->sp, h->st, h->lst, f, h->prm.precision, nullptr, h->stream);  // warm
+    const Launch L = make_launch(h);
+    launch_pairs(L, nullptr, h->stream);  // warm
     HIPCHK(h, hipEventRecord(e0, h->stream));
-    for (int r = 0; r < reps; ++r) launch_pairs(h->sp, h->st, h->lst, f, h->prm.precision, nullptr, h->stream);
+    for (int r = 0; r < reps; ++r) launch_pairs(L, nullptr, h->stream);
     HIPCHK(h, hipEventRecord(e1, h->stream));
     HIPCHK(h, hipEventSynchronize(e1));
     float ms = 0.0f;

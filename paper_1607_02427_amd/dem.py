@@ -49,6 +49,12 @@ class OutPtrs(C.Structure):
     _fields_ = [(k, C.c_void_p) for k in ("Fx", "Fy", "Fz", "Tx", "Ty", "Tz", "U", "W")]
 
 
+class BatchParams(C.Structure):
+    _fields_ = [("dim", C.c_int32), ("precision", C.c_int32), ("max_replicas", C.c_int32),
+                ("max_particles", C.c_int64), ("max_cells", C.c_int64), ("max_shapes", C.c_int32),
+                ("nbr_capacity", C.c_int32)]
+
+
 class EnergyOut(C.Structure):
     _fields_ = [("U", C.c_double), ("K_trans", C.c_double), ("K_rot", C.c_double), ("H", C.c_double),
                 ("T", C.c_double), ("P", C.c_double), ("W", C.c_double * 9), ("xi", C.c_double),
@@ -102,6 +108,25 @@ def lib():
         L.dem_time_forces.restype = st
         L.dem_footprint_bytes.argtypes = [C.POINTER(Params)]
         L.dem_footprint_bytes.restype = C.c_size_t
+        L.dem_batch_create.argtypes = [C.POINTER(BatchParams), C.c_void_p, C.POINTER(C.c_void_p)]
+        L.dem_batch_create.restype = st
+        L.dem_batch_add.argtypes = [C.c_void_p, C.POINTER(Params), C.POINTER(StatePtrs), C.c_int64,
+                                    C.POINTER(C.c_int32)]
+        L.dem_batch_add.restype = st
+        L.dem_batch_remove.argtypes = [C.c_void_p, C.c_int32]
+        L.dem_batch_remove.restype = st
+        L.dem_batch_read.argtypes = [C.c_void_p, C.c_int32, C.POINTER(StatePtrs), C.POINTER(OutPtrs)]
+        L.dem_batch_read.restype = st
+        L.dem_batch_set_steps.argtypes = [C.c_void_p, C.c_int32, C.c_int64]
+        L.dem_batch_set_steps.restype = st
+        L.dem_batch_progress.argtypes = [C.c_void_p, C.POINTER(C.c_int64), C.POINTER(C.c_int64), C.c_int32]
+        L.dem_batch_progress.restype = st
+        L.dem_batch_info.argtypes = [C.c_void_p, C.POINTER(C.c_int64)]
+        L.dem_batch_info.restype = st
+        L.dem_replica_energy.argtypes = [C.c_void_p, C.c_int32, C.POINTER(EnergyOut)]
+        L.dem_replica_energy.restype = st
+        L.dem_replica_lists.argtypes = [C.c_void_p, C.c_int32, _ip, _ip, _ip, _ip, _ip]
+        L.dem_replica_lists.restype = st
         L.dem_status_string.argtypes = [C.c_int]
         L.dem_status_string.restype = C.c_char_p
         L.dem_last_error.argtypes = [C.c_void_p]
@@ -162,11 +187,76 @@ def footprint_bytes(system, precision="fp64", nbr_capacity=0) -> int:
     return int(lib().dem_footprint_bytes(C.byref(p)))
 
 
+STATE = ("x", "y", "z", "qw", "qx", "qy", "qz", "vx", "vy", "vz", "Lx", "Ly", "Lz")
+OUT = ("Fx", "Fy", "Fz", "Tx", "Ty", "Tz", "U")
+
+
+def _state_tensors(system, device):
+    import torch
+    cols = {"x": system.x[:, 0], "y": system.x[:, 1], "z": system.x[:, 2], "qw": system.q[:, 0],
+            "qx": system.q[:, 1], "qy": system.q[:, 2], "qz": system.q[:, 3], "vx": system.v[:, 0],
+            "vy": system.v[:, 1], "vz": system.v[:, 2], "Lx": system.L[:, 0], "Ly": system.L[:, 1],
+            "Lz": system.L[:, 2]}
+    t = {k: torch.tensor(np.ascontiguousarray(cols[k]), dtype=torch.float64, device=device) for k in STATE}
+    t["shape_id"] = torch.tensor(np.ascontiguousarray(system.shape_id, dtype=np.int32), device=device)
+    t["image"] = torch.tensor(np.ascontiguousarray(system.image, dtype=np.int32).reshape(-1), device=device)
+    return t
+
+
+def _output_tensors(n, device):
+    import torch
+    o = {k: torch.zeros(n, dtype=torch.float64, device=device) for k in OUT}
+    o["W"] = torch.zeros(9 * n, dtype=torch.float64, device=device)
+    return o
+
+
+def _state_ptrs(t):
+    return StatePtrs(**{k: t[k].data_ptr() for k in STATE + ("shape_id", "image")})
+
+
+def _out_ptrs(o):
+    return OutPtrs(**{k: o[k].data_ptr() for k in OUT + ("W",)})
+
+
+def _outputs_np(o, n):
+    o = {k: v.cpu().numpy() for k, v in o.items()}
+    return dict(F=np.stack([o["Fx"], o["Fy"], o["Fz"]], axis=1), T=np.stack([o["Tx"], o["Ty"], o["Tz"]], axis=1),
+                U=o["U"], W=o["W"].reshape(9, n).T.copy())
+
+
+def _state_np(t, template):
+    t = {k: v.cpu().numpy() for k, v in t.items()}
+    s = template.copy()
+    s.x = np.stack([t["x"], t["y"], t["z"]], axis=1)
+    s.q = np.stack([t["qw"], t["qx"], t["qy"], t["qz"]], axis=1)
+    s.v = np.stack([t["vx"], t["vy"], t["vz"]], axis=1)
+    s.L = np.stack([t["Lx"], t["Ly"], t["Lz"]], axis=1)
+    s.image = t["image"].reshape(-1, 3).copy()
+    return s
+
+
+def _energy_dict(e):
+    return dict(U=e.U, K_trans=e.K_trans, K_rot=e.K_rot, H=e.H, T=e.T, P=e.P, W=np.array(e.W[:]), xi=e.xi,
+                eta=e.eta, step=e.step, n_rebuilds=e.n_rebuilds)
+
+
+def _lists_np(call, n, ncell, cap):
+    cs = np.zeros(ncell + 1, np.int32)
+    cp = np.zeros(max(n, 1), np.int32)
+    nb = np.zeros(max(cap * n, 1), np.int32)
+    nn = np.zeros(max(n, 1), np.int32)
+    dims = np.zeros(4, np.int32)
+    call(cs.ctypes.data_as(_ip), cp.ctypes.data_as(_ip), nb.ctypes.data_as(_ip), nn.ctypes.data_as(_ip),
+         dims.ctypes.data_as(_ip))
+    return dict(dims=dims[:3].copy(), capacity=int(dims[3]), cell_start=cs, cell_particles=cp[:n],
+                nbr=nb[: cap * n].reshape(cap, n) if n else nb[:0].reshape(cap, 0), n_nbr=nn[:n])
+
+
 class DemSystem:
     """One libdem system whose state and outputs are torch tensors on `device`."""
 
-    STATE = ("x", "y", "z", "qw", "qx", "qy", "qz", "vx", "vy", "vz", "Lx", "Ly", "Lz")
-    OUT = ("Fx", "Fy", "Fz", "Tx", "Ty", "Tz", "U")
+    STATE = STATE
+    OUT = OUT
 
     def __init__(self, system, precision: str = "fp64", nbr_capacity: int = 0, device: str = "cuda:0",
                  stream=None, list_mode: str = "auto"):
@@ -177,20 +267,11 @@ class DemSystem:
         self.device = torch.device(device)
         self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
         n = system.n
-        cols = {"x": system.x[:, 0], "y": system.x[:, 1], "z": system.x[:, 2], "qw": system.q[:, 0],
-                "qx": system.q[:, 1], "qy": system.q[:, 2], "qz": system.q[:, 3], "vx": system.v[:, 0],
-                "vy": system.v[:, 1], "vz": system.v[:, 2], "Lx": system.L[:, 0], "Ly": system.L[:, 1],
-                "Lz": system.L[:, 2]}
         with torch.cuda.device(self.device):
-            self.t = {k: torch.tensor(np.ascontiguousarray(cols[k]), dtype=torch.float64, device=self.device)
-                      for k in self.STATE}
-            self.t["shape_id"] = torch.tensor(np.ascontiguousarray(system.shape_id, dtype=np.int32), device=self.device)
-            self.t["image"] = torch.tensor(np.ascontiguousarray(system.image, dtype=np.int32).reshape(-1),
-                                           device=self.device)
-            self.o = {k: torch.zeros(n, dtype=torch.float64, device=self.device) for k in self.OUT}
-            self.o["W"] = torch.zeros(9 * n, dtype=torch.float64, device=self.device)
-        sp = StatePtrs(**{k: self.t[k].data_ptr() for k in self.STATE + ("shape_id", "image")})
-        op = OutPtrs(**{k: self.o[k].data_ptr() for k in self.OUT + ("W",)})
+            self.t = _state_tensors(system, self.device)
+            self.o = _output_tensors(n, self.device)
+        sp = _state_ptrs(self.t)
+        op = _out_ptrs(self.o)
         self._params, self._keep = make_params(system, precision, nbr_capacity, list_mode)
         h = C.c_void_p()
         torch.cuda.synchronize(self.device)
@@ -227,8 +308,7 @@ class DemSystem:
     def energy(self) -> Dict[str, float]:
         e = EnergyOut()
         self._check(lib().dem_energy(self.h, C.byref(e)), "dem_energy")
-        return dict(U=e.U, K_trans=e.K_trans, K_rot=e.K_rot, H=e.H, T=e.T, P=e.P, W=np.array(e.W[:]), xi=e.xi,
-                    eta=e.eta, step=e.step, n_rebuilds=e.n_rebuilds)
+        return _energy_dict(e)
 
     def list_info(self):
         rl = C.c_double()
@@ -239,18 +319,10 @@ class DemSystem:
 
     def lists(self):
         rl, ncell, cap = self.list_info()
-        n = self.system.n
-        cs = np.zeros(ncell + 1, np.int32)
-        cp = np.zeros(max(n, 1), np.int32)
-        nb = np.zeros(max(cap * n, 1), np.int32)
-        nn = np.zeros(max(n, 1), np.int32)
-        dims = np.zeros(4, np.int32)
-        self._check(lib().dem_copy_lists(self.h, cs.ctypes.data_as(_ip), cp.ctypes.data_as(_ip),
-                                         nb.ctypes.data_as(_ip), nn.ctypes.data_as(_ip), dims.ctypes.data_as(_ip)),
-                    "dem_copy_lists")
-        return dict(r_list=rl, dims=dims[:3].copy(), capacity=int(dims[3]), cell_start=cs,
-                    cell_particles=cp[:n], nbr=nb[: cap * n].reshape(cap, n) if n else nb[:0].reshape(cap, 0),
-                    n_nbr=nn[:n])
+        out = _lists_np(lambda *a: self._check(lib().dem_copy_lists(self.h, *a), "dem_copy_lists"),
+                        self.system.n, ncell, cap)
+        out["r_list"] = rl
+        return out
 
     def force_stats(self, reset: bool = False):
         out = (C.c_int64 * 7)()
@@ -267,22 +339,146 @@ class DemSystem:
     def outputs(self) -> Dict[str, np.ndarray]:
         """Synchronises and returns F (n,3), T (n,3), U (n,), W (n,9)."""
         self.sync()
-        o = {k: v.cpu().numpy() for k, v in self.o.items()}
-        n = self.system.n
-        return dict(F=np.stack([o["Fx"], o["Fy"], o["Fz"]], axis=1), T=np.stack([o["Tx"], o["Ty"], o["Tz"]], axis=1),
-                    U=o["U"], W=o["W"].reshape(9, n).T.copy())
+        return _outputs_np(self.o, self.system.n)
 
     def state(self):
         """Synchronises and returns a numpy copy of the system at its current state."""
         self.sync()
-        t = {k: v.cpu().numpy() for k, v in self.t.items()}
-        s = self.system.copy()
-        s.x = np.stack([t["x"], t["y"], t["z"]], axis=1)
-        s.q = np.stack([t["qw"], t["qx"], t["qy"], t["qz"]], axis=1)
-        s.v = np.stack([t["vx"], t["vy"], t["vz"]], axis=1)
-        s.L = np.stack([t["Lx"], t["Ly"], t["Lz"]], axis=1)
-        s.image = t["image"].reshape(-1, 3).copy()
-        return s
+        return _state_np(self.t, self.system)
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().dem_destroy_system(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+
+class DemBatch:
+    """A libdem batch: many independent replicas advanced together.  The
+    batch keeps every replica's state in its own device arrays; add() copies
+    a system in, read() copies a replica out."""
+
+    def __init__(self, dim: int, precision: str = "fp32", max_replicas: int = 128, max_particles: int = 1 << 20,
+                 max_cells: int = 0, max_shapes: int = 0, nbr_capacity: int = 0, device: str = "cuda:0",
+                 stream=None):
+        import torch
+        self.torch = torch
+        self.dim = dim
+        self.precision = precision
+        self.device = torch.device(device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        self.systems = {}
+        bp = BatchParams(dim=dim, precision=DEM_FP32 if precision == "fp32" else DEM_FP64, max_replicas=max_replicas,
+                         max_particles=max_particles, max_cells=max_cells, max_shapes=max_shapes,
+                         nbr_capacity=nbr_capacity)
+        h = C.c_void_p()
+        torch.cuda.synchronize(self.device)
+        with torch.cuda.device(self.device):
+            st = lib().dem_batch_create(C.byref(bp), C.c_void_p(self.stream.cuda_stream), C.byref(h))
+        if st != 0:
+            raise DemError(st, "dem_batch_create", lib().dem_last_error(None).decode())
+        self.h = h
+
+    def _check(self, st, where):
+        if st != 0:
+            raise DemError(st, where, lib().dem_last_error(self.h).decode())
+
+    def add(self, system, steps: int = 0) -> int:
+        """Adds a replica (copied in) that advances `steps` steps (0: without limit); returns its id."""
+        torch = self.torch
+        with torch.cuda.device(self.device):
+            t = _state_tensors(system, self.device)
+        params, keep = make_params(system, self.precision)
+        rid = C.c_int32(-1)
+        torch.cuda.current_stream(self.device).synchronize()
+        with torch.cuda.device(self.device):
+            st = lib().dem_batch_add(self.h, C.byref(params), C.byref(_state_ptrs(t)), int(steps), C.byref(rid))
+        self._check(st, "dem_batch_add")
+        self.systems[rid.value] = system
+        del t, keep
+        return rid.value
+
+    def remove(self, rid: int):
+        self._check(lib().dem_batch_remove(self.h, int(rid)), "dem_batch_remove")
+        self.systems.pop(rid, None)
+
+    def step(self, n: int):
+        self._check(lib().dem_step(self.h, int(n)), "dem_step")
+
+    def compute_forces(self):
+        self._check(lib().dem_compute_forces(self.h), "dem_compute_forces")
+
+    def sync(self):
+        self._check(lib().dem_sync(self.h), "dem_sync")
+
+    def set_steps(self, rid: int, n: int):
+        self._check(lib().dem_batch_set_steps(self.h, int(rid), int(n)), "dem_batch_set_steps")
+
+    def progress(self, count: int):
+        left = (C.c_int64 * max(count, 1))()
+        done = (C.c_int64 * max(count, 1))()
+        self._check(lib().dem_batch_progress(self.h, left, done, int(count)), "dem_batch_progress")
+        return np.array(left[:count]), np.array(done[:count])
+
+    def info(self):
+        out = (C.c_int64 * 8)()
+        self._check(lib().dem_batch_info(self.h, out), "dem_batch_info")
+        keys = ("live", "slots", "free_particles", "largest_free_run", "free_cells", "free_shapes", "capacity",
+                "particle_slots")
+        return dict(zip(keys, out[:8]))
+
+    def energy(self, rid: int):
+        e = EnergyOut()
+        self._check(lib().dem_replica_energy(self.h, int(rid), C.byref(e)), "dem_replica_energy")
+        return _energy_dict(e)
+
+    def lists(self, rid: int):
+        n = self.systems[rid].n
+        info = self.info()
+        dims_probe = np.zeros(4, np.int32)
+        self._check(lib().dem_replica_lists(self.h, int(rid), None, None, None, None, dims_probe.ctypes.data_as(_ip)),
+                    "dem_replica_lists")
+        ncell = int(dims_probe[0] * dims_probe[1] * dims_probe[2])
+        return _lists_np(lambda *a: self._check(lib().dem_replica_lists(self.h, int(rid), *a), "dem_replica_lists"),
+                         n, ncell, int(info["capacity"]))
+
+    def read(self, rid: int):
+        """Synchronises and returns (state as a System, outputs dict) of one replica."""
+        torch = self.torch
+        system = self.systems[rid]
+        n = system.n
+        with torch.cuda.device(self.device):
+            t = _state_tensors(system, self.device)
+            o = _output_tensors(n, self.device)
+        self._check(lib().dem_batch_read(self.h, int(rid), C.byref(_state_ptrs(t)), C.byref(_out_ptrs(o))),
+                    "dem_batch_read")
+        self.sync()
+        return _state_np(t, system), _outputs_np(o, n)
+
+    def force_stats(self, reset: bool = False):
+        out = (C.c_int64 * 7)()
+        self._check(lib().dem_force_stats(self.h, out, 1 if reset else 0), "dem_force_stats")
+        return dict(pairs=out[0], features=out[1], in_cutoff=out[2], launches=out[3], vf_near=out[4],
+                    refined=out[5], ee_near=out[6])
+
+    def set_counting(self, on: bool):
+        self._check(lib().dem_set_counting(self.h, 1 if on else 0), "dem_set_counting")
+
+    def time_forces(self, reps: int = 100) -> float:
+        ms = C.c_double()
+        self._check(lib().dem_time_forces(self.h, int(reps), C.byref(ms)), "dem_time_forces")
+        return ms.value
 
     def close(self):
         if getattr(self, "h", None):

@@ -1,0 +1,155 @@
+"""GPU batches of independent replicas (many systems, one launch per kernel
+per step), through the C ABI.
+
+* Every replica of a mixed batch matches the FP64 oracle (forces to the
+  tolerances of parity_metrics.py, lists bit for bit).
+* A replica's results are the same bit for bit alone (a single system), in
+  a mix, and in a mix assembled in another order, after steps that cross
+  list rebuilds, NVE and NVT replicas together.
+* Step budgets: a replica with a budget stops exactly there; removing and
+  adding replicas mid-run leaves the others bit-identical to their solo runs.
+"""
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_1607_02427_amd import inputs as I
+from parity_metrics import TOL, compare
+
+pytestmark = pytest.mark.gpu
+
+
+def _dem():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    from paper_1607_02427_amd import dem
+    return dem
+
+
+def _drop_last(s):
+    s = s.copy()
+    s.x, s.q, s.v, s.L = s.x[:-1], s.q[:-1], s.v[:-1], s.L[:-1]
+    s.shape_id, s.image = s.shape_id[:-1], s.image[:-1]
+    return s
+
+
+def _mix3d():
+    a = I.cubes_3d_contact(n_side=8)                       # 512 cubes, every neighbour in contact
+    b = I.dimer_gas("tetrahedron", 100, seed=11)           # 200 tetrahedra in contact pairs
+    c = I.dimer_gas("lprism", 40, seed=12, quad_h=0.05)    # 80 concave L-prisms
+    d = _drop_last(I.dimer_gas("cube", 19, seed=13))       # 37: a ragged chunk
+    e = I.cubes_3d(n_side=6)                               # 216 cubes at volume fraction 0.4, NVT
+    f = I.dimer_gas("octahedron", 70, seed=14)             # 140 octahedra
+    b.ensemble = c.ensemble = "nve"
+    return [a, b, c, d, e, f]
+
+
+def _mix2d():
+    a = I.squares_2d_contact()
+    b = I.dimer_gas("pentagon", 90, seed=21, dim=2)
+    c = _drop_last(I.dimer_gas("square", 33, seed=22, dim=2))
+    return [a, b, c]
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("dim", [3, 2])
+def test_batch_matches_oracle(dim, prec):
+    dem = _dem()
+    systems = _mix3d() if dim == 3 else _mix2d()
+    print(f"[batch-oracle] dim={dim} {prec} sizes={[s.n for s in systems]}", flush=True)
+    with dem.DemBatch(dim, prec, max_replicas=16, max_particles=4096) as B:
+        rids = [B.add(s) for s in systems]
+        for s, r in zip(systems, rids):
+            _, out = B.read(r)
+            ref = O.forces(s)
+            err = compare(out, ref, prec)
+            print(r, s.n, err, flush=True)
+            for k, e in err.items():
+                assert e <= TOL[prec], (r, k, e)
+            L = B.lists(r)
+            rl = O.OracleSystem.of(s).r_list(s.skin)
+            nc, cs, cp = O.cell_list(s, rl)
+            assert np.array_equal(L["dims"], nc)
+            assert np.array_equal(L["cell_start"], cs)
+            assert np.array_equal(L["cell_particles"], cp)
+            nb, nn, _ = O.nbr_list(s, rl, cap=L["capacity"], mode=1)
+            assert np.array_equal(L["n_nbr"], nn)
+            for i in range(s.n):
+                assert np.array_equal(L["nbr"][: nn[i], i], nb[: nn[i], i])
+
+
+def _solo(dem, s, prec, steps):
+    with dem.DemSystem(s, prec) as g:
+        b0 = g.energy()["n_rebuilds"]
+        g.step(steps)
+        st = g.state()
+        out = g.outputs()
+        e = g.energy()
+        e["rebuilds_in_run"] = e["n_rebuilds"] - b0
+    return st, out, e
+
+
+def _same(a, b):
+    sa, oa = a
+    sb, ob = b
+    for k in ("x", "q", "v", "L", "image"):
+        assert np.array_equal(getattr(sa, k), getattr(sb, k)), k
+    for k in ("F", "T", "U", "W"):
+        assert np.array_equal(oa[k], ob[k]), k
+
+
+@pytest.mark.parametrize("prec", ["fp32", "fp64"])
+def test_alone_equals_in_mix(prec):
+    dem = _dem()
+    systems = _mix3d()
+    steps = 300
+    solo = [_solo(dem, s, prec, steps) for s in systems]
+    for order in (list(range(len(systems))), list(reversed(range(len(systems))))):
+        print(f"[mix] {prec} order={order}", flush=True)
+        with dem.DemBatch(3, prec, max_replicas=16, max_particles=8192) as B:
+            rids = {k: B.add(systems[k]) for k in order}
+            b0 = {k: B.energy(r)["n_rebuilds"] for k, r in rids.items()}
+            B.step(steps)
+            for k, r in rids.items():
+                st, out = B.read(r)
+                _same((st, out), solo[k][:2])
+                e = B.energy(r)
+                assert e["step"] == steps
+                assert e["H"] == solo[k][2]["H"]
+                assert e["n_rebuilds"] - b0[k] == solo[k][2]["rebuilds_in_run"]
+    assert max(x[2]["rebuilds_in_run"] for x in solo) > 0  # the run crossed list rebuilds
+
+
+def test_budgets_add_remove():
+    dem = _dem()
+    a, b, c = I.cubes_3d(n_side=5), I.dimer_gas("tetrahedron", 60, seed=31), I.cubes_3d_contact(n_side=5)
+    b.ensemble = "nve"
+    print("[budget] sizes", a.n, b.n, c.n, flush=True)
+    with dem.DemBatch(3, "fp32", max_replicas=4, max_particles=1024) as B:
+        ra = B.add(a, steps=100)
+        rb = B.add(b)
+        B.step(150)
+        left, done = B.progress(4)
+        assert done[ra] == 100 and left[ra] == 0
+        assert done[rb] == 150
+        _same(B.read(ra), _solo(dem, a, "fp32", 100)[:2])
+        B.remove(ra)
+        rc = B.add(c, steps=40)
+        B.step(50)
+        left, done = B.progress(4)
+        assert done[rb] == 200 and done[rc] == 40
+        _same(B.read(rb), _solo(dem, b, "fp32", 200)[:2])
+        _same(B.read(rc), _solo(dem, c, "fp32", 40)[:2])
+        info = B.info()
+        assert info["live"] == 2
+
+
+def test_batch_full_is_reported():
+    dem = _dem()
+    with dem.DemBatch(3, "fp32", max_replicas=2, max_particles=576) as B:
+        B.add(I.cubes_3d_contact(n_side=8))                 # 512 of 576 slots
+        with pytest.raises(dem.DemError) as ei:
+            B.add(I.cubes_3d(n_side=5))                      # 125 more (two chunks of 64) do not fit
+        assert ei.value.status == 3
+        with pytest.raises(dem.DemError):
+            B.add(I.squares_2d())                            # wrong dimension
