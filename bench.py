@@ -87,6 +87,50 @@ def force_roofline(g, system, reps=200):
                 mean_launch_ms=mean_ms, flops_per_launch=flops, counters=st)
 
 
+def run_batched(replicas, steps, warmup, precision="fp32"):
+    """All replicas in one batch: every step is one launch per kernel."""
+    import torch
+    from paper_1607_02427_amd import dem
+    total = sum(s.n for s in replicas)
+    b = dem.DemBatch(3, precision, max_replicas=len(replicas) + 8, max_particles=total + 64 * len(replicas))
+    for s in replicas:
+        b.add(s)
+    b.step(warmup)
+    b.sync()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(b.stream)
+    b.step(steps)
+    e1.record(b.stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1)
+    b.sync()
+    b.close()
+    return dict(value=total * steps / (ms * 1e-3), ms_per_step=ms / steps, particles=total)
+
+
+def run_plain_sequential(replicas, steps, warmup):
+    """The same replicas one after another, each a single FP64 system."""
+    import torch
+    from paper_1607_02427_amd import dem
+    total_ms = 0.0
+    for s in replicas:
+        with dem.DemSystem(s, "fp64") as g:
+            g.step(warmup)
+            g.sync()
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            torch.cuda.synchronize()
+            e0.record(g.stream)
+            g.step(steps)
+            e1.record(g.stream)
+            torch.cuda.synchronize()
+            total_ms += e0.elapsed_time(e1)
+    work = sum(s.n for s in replicas) * steps
+    return dict(value=work / (total_ms * 1e-3), seconds=total_ms * 1e-3)
+
+
 def cpu_baseline(system, target_s):
     import oracle as O
     threads = len(os.sched_getaffinity(0))
@@ -112,6 +156,11 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-plain", action="store_true", help="skip the plain FP64 path")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--replicas", type=int, default=96, help="replicas of the batched workload")
+    ap.add_argument("--batched-steps", type=int, default=500)
+    ap.add_argument("--requests", type=int, default=32, help="requests of the served trace")
+    ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--no-served", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU layout is design-only.",
@@ -148,6 +197,46 @@ def main():
         line["plain_fp64"] = {"value": n * args.steps / (r64["gpu_ms"] * 1e-3), "ms_per_step": r64["gpu_ms"] / args.steps}
         line["fp32_over_plain"] = ptps / line["plain_fp64"]["value"]
         g64.close()
+    if not args.no_batched:
+        reps = I.batched_replicas(args.replicas, steps=args.batched_steps)
+        log(f"[bench] batched: {len(reps)} replicas, {sum(s.n for s in reps)} particles, "
+            f"{args.batched_steps} steps")
+        rb = run_batched(reps, args.batched_steps, 20)
+        log(f"[bench] batched fp32 {rb['value']:.3e} PTPS; plain fp64 one replica at a time")
+        rp = run_plain_sequential(reps, args.batched_steps, 20)
+        line["batched"] = {
+            "workload": f"{len(reps)} NVT replicas (kT 1), sizes log-uniform 512-32768, shapes uniform over rounded "
+                        f"cube / tetrahedron / concave L-prism, rounding U[0.1, 0.2], packing fraction U[0.3, 0.5] "
+                        f"capped by an overlap-free lattice, {args.batched_steps} steps after 20 warm-up",
+            "replicas": len(reps), "particles": rb["particles"], "steps": args.batched_steps,
+            "value": rb["value"], "unit": "particle-timesteps/s", "ms_per_step": rb["ms_per_step"], "dtype": "f32",
+            "plain_fp64_sequential": rp["value"], "speedup_vs_plain": rb["value"] / rp["value"]}
+    if not args.no_served:
+        from paper_1607_02427_amd import serve
+        trace = I.served_trace(args.requests)
+        work = sum(s.n * s.steps for s in trace)
+        log(f"[bench] served: {len(trace)} requests, {work:.3e} particle-steps, arrivals over "
+            f"{trace[-1].arrival:.2f} s")
+        srv = serve.Server(budget_bytes=64 << 30, precision="fp32", max_replicas=len(trace) + 8,
+                           max_particles={2: sum(s.n for s in trace if s.dim == 2) + 64 * len(trace),
+                                          3: sum(s.n for s in trace if s.dim == 3) + 64 * len(trace)},
+                           chunk=100)
+        try:
+            srs = serve.summarize(srv.run(trace))
+        finally:
+            srv.close()
+        log(f"[bench] served p50 {srs['p50_latency_s']:.2f} s p99 {srs['p99_latency_s']:.2f} s, "
+            f"{srs['value']:.3e} PTPS; sequential plain fp64")
+        sqs = serve.summarize(serve.run_sequential(trace, "fp64"))
+        line["served"] = {
+            "workload": f"{len(trace)} requests, Poisson arrivals at 40/s, sizes log-uniform 256-65536, 2D rounded "
+                        f"pentagons or 3D rounded cubes / octahedra, 1000-5000 NVT steps, kT U[0.5, 2]; "
+                        f"64 GiB admission budget, continuous batching in chunks of 100 steps",
+            "requests": len(trace), "p50_latency_s": srs["p50_latency_s"], "p99_latency_s": srs["p99_latency_s"],
+            "value": srs["value"], "unit": "particle-timesteps/s", "makespan_s": srs["makespan_s"],
+            "offered_load": work / trace[-1].arrival, "dtype": "f32",
+            "sequential_plain_fp64": {"p50_latency_s": sqs["p50_latency_s"], "p99_latency_s": sqs["p99_latency_s"],
+                                      "value": sqs["value"], "makespan_s": sqs["makespan_s"]}}
     if not args.no_cpu:
         log("[bench] cpu oracle baseline")
         line["cpu_baseline"] = cpu_baseline(system, args.cpu_seconds)

@@ -155,7 +155,11 @@ dem_status dem_build_celllist(dem_handle h);
  * over the current neighbour list (Eq. 1 / Eq. 2 with Eq. 4). */
 dem_status dem_compute_forces(dem_handle h);
 
-/* Advances n_steps time steps (lists rebuilt on the displacement trigger). */
+/* Advances n_steps time steps (lists rebuilt on the displacement trigger).
+ * With NVT the thermostat half steps that fall between two steps are
+ * carried across calls: dem_step(a) then dem_step(b) gives the same numbers,
+ * bit for bit, as dem_step(a + b).  On return the velocities, L and the
+ * reported xi, eta are those at the end of the last step. */
 dem_status dem_step(dem_handle h, int64_t n_steps);
 
 /* Reduces energies, kinetic terms, virial and thermostat state in FP64 and
@@ -165,7 +169,8 @@ dem_status dem_energy(dem_handle h, dem_energy_out *out);
 /* Synchronises and reports latched device errors. */
 dem_status dem_sync(dem_handle h);
 
-/* Sets the Nose-Hoover variables (for checkpoint/restore). */
+/* Sets the Nose-Hoover variables (for checkpoint/restore); the next step
+ * opens its half step from the current kinetic energy. */
 dem_status dem_set_thermostat(dem_handle h, double xi, double eta);
 
 /* Copies the lists to host buffers (synchronises): cell_start[n_cells+1],

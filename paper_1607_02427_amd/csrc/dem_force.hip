@@ -785,8 +785,9 @@ __device__ inline double nh_half(const SysParams &p, double &xi, double &eta, do
 // of a replica to finish (ticket counter, no waiting) spends one step of the
 // replica's budget and, with NVT, applies the step's closing Nose-Hoover
 // half step and the next step's opening one from the replica's per-chunk
-// kinetic partials, summed in chunk order.  A replica with no budget left is
-// skipped.
+// kinetic partials, summed in chunk order; it also counts a list build done
+// in this step and schedules one for the next step if a particle moved far
+// enough.  A replica with no budget left is skipped.
 template <typename T, int DIM, bool KICK>
 __global__ void __launch_bounds__(kBlock) k_gather(BatchParams b, const SysParams *reps, StatePtrs s, OutPtrs o,
                                                       ListPtrs l, const T *__restrict__ rec, double *ke_part,
@@ -802,11 +803,6 @@ __global__ void __launch_bounds__(kBlock) k_gather(BatchParams b, const SysParam
     const int sub = threadIdx.x % kGatherLanes;
     const int i = blockIdx.x * kGatherPer + threadIdx.x / kGatherLanes;
     const bool nvt = KICK && p.ensemble == DEM_NVT;
-    if (blockIdx.x * kChunk == p.off && threadIdx.x == 0 && fl[FLAG_REBUILD] != 0) {
-        // the lists consumed by this step are fresh: count the build and clear the trigger
-        fl[FLAG_REBUILD] = 0;
-        fl[FLAG_NBUILDS] += 1;
-    }
     const size_t N = (size_t)b.N;
     const bool mine = i < p.off + p.n;
     double acc[16];
@@ -905,17 +901,28 @@ __global__ void __launch_bounds__(kBlock) k_gather(BatchParams b, const SysParam
             const double sb = nh_half(p, xi, eta, K);  // closes this step
             th[TH_XI_B] = xi;
             th[TH_ETA_B] = eta;
-            th[TH_SCALE_B] = sb;
+            th[TH_SB] = sb;
             const double sa = nh_half(p, xi, eta, K);  // opens the next step
             th[TH_XI] = xi;
             th[TH_ETA] = eta;
-            th[TH_SCALE] = sb * sa;
+            th[TH_SA] = sa;
+            th[TH_OPEN] = 1.0;
         }
     }
     if (threadIdx.x == 0) {
         budget[r] -= 1;
         steps[r] += 1;
         fl[FLAG_TICKET] = 0;
+        if (fl[FLAG_REBUILD] != 0) {  // this step's lists are built: count them
+            fl[FLAG_REBUILD] = 0;
+            fl[FLAG_NBUILDS] += 1;
+            atomicSub(&l.gflags[G_ANY], 1);
+        }
+        if (fl[FLAG_TRIGGER] != 0) {  // the next step rebuilds
+            fl[FLAG_TRIGGER] = 0;
+            fl[FLAG_REBUILD] = 1;
+            atomicAdd(&l.gflags[G_ANY], 1);
+        }
     }
 }
 

@@ -14,9 +14,9 @@
 //   xi += h/2 (2K - g kT)/Q,
 // with g = d N + d_rot N - d and Q = g kT tau_T^2.  The closing half step
 // of a step and the opening half step of the next are computed together by
-// the last workgroup of the force gather (dem_force.hip); their velocity
-// scale is applied by the next kick-drift, and after the last step of a call
-// k_nh_end and k_scale apply the closing half step alone, so a captured step
+// the last workgroup of each replica in the force gather (dem_force.hip);
+// their velocity factors are applied by the next kick-drift, and at the end
+// of a call k_scale applies the closing factor alone, so a captured step
 // needs no extra pass over the particles.
 #include "dem_internal.h"
 
@@ -99,53 +99,37 @@ __device__ inline int wave_replica(const BatchParams &b, const ListPtrs &l, int 
     return __builtin_amdgcn_readfirstlane(c < b.nchunk ? l.chunk_rep[c] : -1);
 }
 
-// Opening half step of the first step of a call, one workgroup per replica,
-// from the replica's kinetic partials (one per chunk, summed in order).
+// Opening half step of a closed replica's next step, one workgroup per
+// replica, from its kinetic partials (one per chunk, summed in order).
 __global__ void __launch_bounds__(kBlock) k_nh_begin(BatchParams b, const SysParams *reps, const double *ke_part,
                                                         double *thermo, const int64_t *budget)
 {
     __shared__ double sh[kBlock];
     const SysParams &p = reps[blockIdx.x];
     double *th = thermo + blockIdx.x * TH_COUNT;
-    if (!p.live || p.n == 0 || p.ensemble != DEM_NVT || budget[blockIdx.x] <= 0) {
-        if (threadIdx.x == 0) th[TH_OPEN] = 0.0;
-        return;
-    }
+    if (!p.live || p.n == 0 || p.ensemble != DEM_NVT || budget[blockIdx.x] <= 0 || th[TH_OPEN] != 0.0) return;
     const int c0 = p.off / kChunk, nc = (p.n + kChunk - 1) / kChunk;
     double acc = 0.0;
     for (int c = threadIdx.x; c < nc; c += blockDim.x) acc += ke_part[2 * (c0 + c)] + ke_part[2 * (c0 + c) + 1];
     double K = block_sum<kBlock>(acc, sh);
     if (threadIdx.x != 0) return;
     double xi = th[TH_XI], eta = th[TH_ETA];
-    const double sc = nh_half(p, xi, eta, K);
+    const double sa = nh_half(p, xi, eta, K);
     th[TH_XI] = xi;
     th[TH_ETA] = eta;
-    th[TH_SCALE] = sc;
+    th[TH_SB] = 1.0;
+    th[TH_SA] = sa;
     th[TH_OPEN] = 1.0;
 }
 
-// After the last step of a call: back to the state after its closing half
-// step, for every replica whose first step of the call opened one.
-__global__ void k_nh_end(int nrep, double *thermo)
-{
-    const int r = blockIdx.x * blockDim.x + threadIdx.x;
-    if (r >= nrep) return;
-    double *th = thermo + r * TH_COUNT;
-    if (th[TH_OPEN] == 0.0) return;
-    th[TH_XI] = th[TH_XI_B];
-    th[TH_ETA] = th[TH_ETA_B];
-    th[TH_SCALE] = th[TH_SCALE_B];
-}
-
-// Applies the pending velocity scale of every replica closed by k_nh_end.
-__global__ void k_scale(BatchParams b, const SysParams *reps, StatePtrs s, ListPtrs l, double *thermo)
+// End of a call: the velocities take the pending closing factor.
+__global__ void k_scale(BatchParams b, const SysParams *reps, StatePtrs s, ListPtrs l, const double *thermo)
 {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     const int r = wave_replica(b, l, i);
     if (r < 0 || i >= reps[r].off + reps[r].n) return;
-    const double *th = thermo + r * TH_COUNT;
-    if (th[TH_OPEN] == 0.0) return;
-    const double sc = th[TH_SCALE];
+    const double sc = thermo[r * TH_COUNT + TH_SB];
+    if (reps[r].ensemble != DEM_NVT || sc == 1.0) return;
     s.vx[i] *= sc;
     s.vy[i] *= sc;
     s.vz[i] *= sc;
@@ -157,12 +141,7 @@ __global__ void k_scale(BatchParams b, const SysParams *reps, StatePtrs s, ListP
 __global__ void k_nh_close(int nrep, double *thermo)
 {
     const int r = blockIdx.x * blockDim.x + threadIdx.x;
-    if (r >= nrep) return;
-    double *th = thermo + r * TH_COUNT;
-    if (th[TH_OPEN] == 0.0) return;
-    th[TH_SCALE] = 1.0;
-    th[TH_SCALE_B] = 1.0;
-    th[TH_OPEN] = 0.0;
+    if (r < nrep) thermo[r * TH_COUNT + TH_SB] = 1.0;
 }
 
 template <typename T, int DIM>
@@ -175,24 +154,28 @@ __global__ void __launch_bounds__(kBlock) k_kick_drift(BatchParams b, const SysP
     if (r < 0) return;
     const SysParams &p = reps[r];
     if (i >= p.off + p.n || budget[r] <= 0) return;
-    const double sc = p.ensemble == DEM_NVT ? thermo[r * TH_COUNT + TH_SCALE] : 1.0;
+    // pending thermostat factors: the closing half step of the last step,
+    // then the opening half step of this one (1 and 1 without a thermostat)
+    const bool nvt = p.ensemble == DEM_NVT;
+    const double sb = nvt ? thermo[r * TH_COUNT + TH_SB] : 1.0;
+    const double sa = nvt ? thermo[r * TH_COUNT + TH_SA] : 1.0;
     const int sid = s.sid[i];
     const double hm = 0.5 * p.dt / p.mass[sid];
     const double I[3] = {p.inertia[sid][0], p.inertia[sid][1], p.inertia[sid][2]};
     double q[4] = {s.qw[i], s.qx[i], s.qy[i], s.qz[i]};
-    double v[3] = {sc * s.vx[i] + hm * o.Fx[i], sc * s.vy[i] + hm * o.Fy[i], 0.0};
+    double v[3] = {(s.vx[i] * sb) * sa + hm * o.Fx[i], (s.vy[i] * sb) * sa + hm * o.Fy[i], 0.0};
     double L[3];
     if (DIM == 3) {
-        v[2] = sc * s.vz[i] + hm * o.Fz[i];
+        v[2] = (s.vz[i] * sb) * sa + hm * o.Fz[i];
         double tb[3];
         body_torque(q, o.Tx[i], o.Ty[i], o.Tz[i], tb);
-        L[0] = sc * s.Lx[i] + 0.5 * p.dt * tb[0];
-        L[1] = sc * s.Ly[i] + 0.5 * p.dt * tb[1];
-        L[2] = sc * s.Lz[i] + 0.5 * p.dt * tb[2];
+        L[0] = (s.Lx[i] * sb) * sa + 0.5 * p.dt * tb[0];
+        L[1] = (s.Ly[i] * sb) * sa + 0.5 * p.dt * tb[1];
+        L[2] = (s.Lz[i] * sb) * sa + 0.5 * p.dt * tb[2];
     } else {
         L[0] = 0.0;
         L[1] = 0.0;
-        L[2] = sc * s.Lz[i] + 0.5 * p.dt * o.Tz[i];
+        L[2] = (s.Lz[i] * sb) * sa + 0.5 * p.dt * o.Tz[i];
     }
     double x[3] = {s.x[i], s.y[i], (DIM == 3) ? s.z[i] : 0.0};
     int img[3] = {s.image[3 * i], s.image[3 * i + 1], s.image[3 * i + 2]};
@@ -248,15 +231,21 @@ __global__ void __launch_bounds__(kBlock) k_kick_drift(BatchParams b, const SysP
     s.image[3 * i] = img[0];
     s.image[3 * i + 1] = img[1];
     s.image[3 * i + 2] = img[2];
-    // displacement since the last list build triggers a rebuild
-    double d2 = 0.0;
-    for (int a = 0; a < DIM; ++a) {
-        const double d = min_image(x[a] - l.xlast[(size_t)a * b.N + i], p.box[a]);
-        d2 += d * d;
-    }
-    if (d2 > p.disp2) {
-        atomicOr(&l.flags[r * FLAG_COUNT + FLAG_REBUILD], 1);
-        atomicOr(&l.gflags[G_ANY], 1);
+    if (l.flags[r * FLAG_COUNT + FLAG_REBUILD] != 0) {
+        // this step rebuilds the lists: the particle goes into its cell now
+        cell_insert(p, l, i, x[0], x[1], x[2]);
+    } else {
+        // The next step rebuilds them if the displacement since the last
+        // build, plus one more step like this one, exceeds rebuild_frac * skin
+        // (so no force is evaluated on a list older than that).
+        double d2 = 0.0, v2 = 0.0;
+        for (int a = 0; a < DIM; ++a) {
+            const double d = min_image(x[a] - l.xlast[(size_t)a * b.N + i], p.box[a]);
+            d2 += d * d;
+            v2 += v[a] * v[a];
+        }
+        const double reach = sqrt(d2) + p.dt * sqrt(v2);
+        if (reach * reach > p.disp2) atomicOr(&l.flags[r * FLAG_COUNT + FLAG_TRIGGER], 1);
     }
     if (!(isfinite(x[0]) && isfinite(x[1]) && isfinite(x[2]) && isfinite(v[0]) && isfinite(v[1]) && isfinite(v[2])))
         atomicOr(&l.flags[r * FLAG_COUNT + FLAG_NONFINITE], 1);
@@ -327,7 +316,6 @@ void launch_nh_end(const Launch &L, hipStream_t stream)
 {
     if (L.b.nrep == 0) return;
     const int nr = (L.b.nrep + kBlock - 1) / kBlock;
-    k_nh_end<<<nr, kBlock, 0, stream>>>(L.b.nrep, L.thermo);
     if (L.b.nchunk > 0) k_scale<<<blocks_for(L.b.nchunk * kChunk), kBlock, 0, stream>>>(L.b, L.reps, L.s, L.l, L.thermo);
     k_nh_close<<<nr, kBlock, 0, stream>>>(L.b.nrep, L.thermo);
 }

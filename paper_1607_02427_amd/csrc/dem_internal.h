@@ -20,19 +20,30 @@ constexpr int kChunk = 64;
 // Particle pairs per tile of the pair kernel; tiles never straddle replicas.
 constexpr int kTile = 16;
 
-// Per-replica device flag words (flags[r * FLAG_COUNT + w]).
+// Per-replica device flag words (flags[r * FLAG_COUNT + w], one 64-byte
+// line per replica).  FLAG_TRIGGER: some particle has moved far enough
+// since the last build that the next step must rebuild the lists;
+// FLAG_REBUILD: the current step rebuilds them.
 enum Flag {
     FLAG_REBUILD = 0, FLAG_NBUILDS = 1, FLAG_MAXROW = 2, FLAG_NONFINITE = 3, FLAG_NPAIRS = 4, FLAG_TICKET = 5,
-    FLAG_COUNT = 8
+    FLAG_TRIGGER = 6, FLAG_CELLOVF = 7, FLAG_NBRTICKET = 8, FLAG_COUNT = 16
 };
-// Batch-wide words: a list rebuild is pending somewhere; the list kernel's
-// completion ticket.
-enum GWord { G_ANY = 0, G_TICKET = 1, G_COUNT = 4 };
-// Per-replica thermostat words (double, thermo[r * TH_COUNT + w]): running
-// xi and eta, the velocity scale the next kick-drift applies, the state
-// right after the closing half step of the last completed step (xi, eta and
-// its velocity scale), and whether the current call opened a half step.
-enum Thermo { TH_XI = 0, TH_ETA = 1, TH_SCALE = 2, TH_XI_B = 3, TH_ETA_B = 4, TH_SCALE_B = 5, TH_OPEN = 6, TH_COUNT = 8 };
+// Batch-wide words: how many replicas rebuild their lists in the current
+// step (the list kernels return at once when none does).
+enum GWord { G_ANY = 0, G_COUNT = 4 };
+// Particles one cell can hold, and the longest neighbour row.
+constexpr int kCellCap = 64;
+constexpr int kRowMax = 128;
+// Per-replica thermostat words (double, thermo[r * TH_COUNT + w]).  Between
+// steps a replica is either closed (its velocities carry every half step
+// so far) or open: the closing half step of its last step has scaled the
+// thermostat but not yet the velocities (pending factor TH_SB), and the
+// opening half step of its next step is computed (pending factor TH_SA;
+// TH_XI, TH_ETA after it).  TH_XI_B, TH_ETA_B hold xi and eta at the end of
+// the last completed step.  The next kick applies (v * SB) * SA, and the
+// end of a call applies SB alone, so a run split into calls and the same
+// run in one call give the same numbers.
+enum Thermo { TH_XI = 0, TH_ETA = 1, TH_SB = 2, TH_SA = 3, TH_XI_B = 4, TH_ETA_B = 5, TH_OPEN = 6, TH_COUNT = 8 };
 // Force work counters (unsigned long long).
 enum Stat {
     ST_PAIRS = 0, ST_FEATURES = 1, ST_INCUT = 2, ST_LAUNCHES = 3, ST_NEAR = 4, ST_REFINED = 5, ST_EENEAR = 6, ST_COUNT = 7
@@ -124,15 +135,18 @@ struct OutPtrs {
 };
 
 struct ListPtrs {
-    int32_t *cell_count, *cell_start, *cell_particles, *pcell, *nbr, *n_nbr;
-    double *xlast;               // [3][N]
+    int32_t *cell_count;         // [cells] particles in each cell (zero between builds)
+    int32_t *cell_slot;          // [cells][kCellCap] particles of each cell, unordered
+    int32_t *pcell;              // [N] cell of each particle, local to its replica
+    int32_t *nbr, *n_nbr;        // [cap][N] rows (ascending), [N] row lengths
+    double *xlast;               // [3][N] positions at the last build
     int32_t *flags;              // [replica][FLAG_COUNT]
     int32_t *gflags;             // [G_COUNT]
     int32_t *tile_start;         // [nrep + 1] first pair tile of each replica
     const int32_t *chunk_rep;    // [nchunk] replica of each chunk, -1 if free
     // half list of unordered pairs (i < j), rebuilt with the neighbour list
     int32_t *klo;                // [N] first row slot of i holding a j > i
-    int32_t *pstart;             // [N + 1] first pair index of i, local to its replica
+    int32_t *pstart;             // [N] first pair index of i, local to its replica
     int4 *pairs;                 // [pair slots] {i, j, slot of j in i's row, slot of i in j's row (-1: missing)}
 };
 
@@ -189,12 +203,37 @@ struct Launch {
 };
 
 // Cell list, neighbour list, half pair list and the tile plan of the pair
-// kernel, for every replica whose rebuild flag is set.  The kernels exit at
-// once unless a rebuild is pending, so a captured step contains them
-// unconditionally.  multi != 0 (one replica only) runs one kernel per phase.
-void launch_build_lists(const Launch &L, int multi, const SysParams &host, hipStream_t stream);
-// Largest replica the one-workgroup list build accepts.
-int fused_list_max_n();
+// kernel.  mode LISTS_STEP: inside a step, for every replica whose rebuild
+// flag is set and that has steps left (the kick-drift has put its particles
+// into cells); the kernels return at once when no replica rebuilds, so a
+// captured step contains them unconditionally.  mode LISTS_ALL or a replica
+// index: from the current positions, now, for every live replica or for
+// that one (cells included).  LISTS_PLAN recomputes the tile plan alone;
+// LISTS_REFILL writes every live replica's pair entries again from its
+// rows (after the pair slots moved) and the plan.
+enum { LISTS_STEP = -1, LISTS_ALL = -2, LISTS_PLAN = -3, LISTS_REFILL = -4 };
+void launch_lists(const Launch &L, int mode, hipStream_t stream);
+
+// Cell of particle i at (x, y, z), and its insertion into the cell's slots
+// (for replicas that use cells).  Bit-exact FP64 binning: the cell is
+// min(n_c - 1, floor(x / (L / n_c))) per axis.
+__device__ inline void cell_insert(const SysParams &p, const ListPtrs &l, int i, double x, double y, double z)
+{
+    const double xs[3] = {x, y, z};
+    int c3[3] = {0, 0, 0};
+    for (int a = 0; a < p.dim; ++a) {
+        int c = (int)floor(xs[a] / p.cellw[a]);
+        c = c < 0 ? 0 : c;
+        c3[a] = c > p.nc[a] - 1 ? p.nc[a] - 1 : c;
+    }
+    const int c = c3[0] + p.nc[0] * (c3[1] + p.nc[1] * c3[2]);
+    l.pcell[i] = c;
+    if (!p.use_cells) return;
+    const int slot = atomicAdd(&l.cell_count[p.coff + c], 1);
+    if (slot < kCellCap) l.cell_slot[(size_t)(p.coff + c) * kCellCap + slot] = i;
+    else atomicOr(&l.flags[p.rid * FLAG_COUNT + FLAG_CELLOVF], 1);
+}
+
 // Dynamic LDS of the pair kernel, and how many of its blocks the device
 // holds at once.
 size_t pair_kernel_lds(int precision, int tab_slots);
@@ -213,8 +252,8 @@ void launch_gather(const Launch &L, bool kick, hipStream_t stream);
 
 // Integrator pieces.  With NVT the gather's last block of a replica applies
 // the closing half step of the step and the opening half step of the next
-// one; launch_nh_begin opens the first step of a call, launch_nh_end restores
-// the state after the last closing half step and rescales the velocities.
+// one; launch_nh_begin opens the first step of a closed replica,
+// launch_nh_end applies the pending closing factor to the velocities.
 void launch_nh_begin(const Launch &L, hipStream_t stream);
 void launch_kick_drift(const Launch &L, hipStream_t stream);
 void launch_kinetic(const Launch &L, hipStream_t stream);

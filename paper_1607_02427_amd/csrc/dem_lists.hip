@@ -1,23 +1,26 @@
-// Cell list, full neighbour list and half pair list of every replica.
+// Cell list, full neighbour list and half pair list of every replica, built
+// across the whole device.
 //
 // The lists are an integer contract: the cell of a particle is
-// min(n_c - 1, floor(x / (L / n_c))) per axis, cells are CSR with particles
-// ascending inside a cell, and the neighbours of i are every j != i of the
-// same replica with |minimum image (x_j - x_i)|^2 < r_list^2, evaluated in
-// FP64 as written (no contraction into fused multiply-adds), stored
-// ascending in j.  Rows live column-major (nbr[k * N + i]) so per-row loads
-// are contiguous across particles.  The half list enumerates each unordered
-// pair once (owner i < j) with the row slot it occupies in both rows, so
-// the force pass evaluates a pair once, writes its result into both slots,
-// and each particle sums its own row.
+// min(n_c - 1, floor(x / (L / n_c))) per axis, and the neighbours of i are
+// every j != i of the same replica with |minimum image (x_j - x_i)|^2 <
+// r_list^2, evaluated in FP64 as written (no contraction into fused
+// multiply-adds), stored ascending in j.  Rows live column-major
+// (nbr[k * N + i]) so per-row loads are contiguous across particles.  The
+// half list enumerates each unordered pair once (owner i < j) with the row
+// slot it occupies in both rows, so the force pass evaluates a pair once,
+// writes its result into both slots, and each particle sums its own row.
 //
-// Every list kernel returns at once unless a rebuild is pending, so a
-// captured step contains the build unconditionally.  Replicas of up to
-// kFusedMaxN particles build everything in one workgroup each (one launch
-// per step for the whole batch, the phases separated by workgroup
-// barriers); a single larger system uses one grid-wide kernel per phase.
-// Both run the same per-item code.  After a build the pair kernel's tile
-// plan (the first tile of each replica) is recomputed.
+// A build has three parts, each a grid over particles:
+//   1. cells: every particle goes into the fixed-capacity slots of its cell
+//      (inside a step the kick-drift does this as it moves the particle);
+//   2. k_nbr: 16 lanes per particle scan the 3^d neighbour cells, collect
+//      the hits in LDS by wave ballots, and rank-sort them into the row; the
+//      last block of each replica scans the replica's pair counts;
+//   3. k_fill: each particle writes the pair entries it owns and empties its
+//      cell; block 0 recomputes the tile plan (the first tile of every
+//      replica) for the pair kernel.
+// Inside a step the kernels return at once unless some replica rebuilds.
 #include "dem_internal.h"
 
 #pragma clang fp contract(off)
@@ -25,14 +28,8 @@
 namespace dem {
 namespace {
 
-constexpr int kFusedMaxN = 65536;
-
-__device__ inline int cell_coord(double x, double w, int nc)
-{
-    int c = (int)floor(x / w);
-    c = c < 0 ? 0 : c;
-    return c > nc - 1 ? nc - 1 : c;
-}
+constexpr int kNbrLanes = 16;                   // lanes per particle in k_nbr
+constexpr int kNbrPer = kBlock / kNbrLanes;     // particles per k_nbr block (a quarter chunk)
 
 // Minimum image of d = x_j - x_i for positions in [0, L].  This equals
 // d - L rint(d / L) bit for bit except where |d| is within rounding of L/2,
@@ -42,40 +39,6 @@ __device__ inline double min_image(double d, double L)
 {
     const double h = 0.5 * L;
     return d > h ? d - L : (d < -h ? d + L : d);
-}
-
-// ---- per-item steps (i, j: global particle slots; cells: replica-local) ----
-__device__ inline void cell_assign(const SysParams &p, const StatePtrs &s, const ListPtrs &l, int i)
-{
-    const int cx = cell_coord(s.x[i], p.cellw[0], p.nc[0]);
-    const int cy = cell_coord(s.y[i], p.cellw[1], p.nc[1]);
-    const int cz = (p.dim == 3) ? cell_coord(s.z[i], p.cellw[2], p.nc[2]) : 0;
-    const int c = cx + p.nc[0] * (cy + p.nc[1] * cz);
-    l.pcell[i] = c;
-    atomicAdd(&l.cell_count[p.coff + c], 1);
-}
-
-// Scatter; counting each cell back down leaves cell_count zeroed for the next build.
-__device__ inline void cell_fill(const SysParams &p, const ListPtrs &l, int i)
-{
-    const int c = l.pcell[i];
-    const int slot = atomicSub(&l.cell_count[p.coff + c], 1) - 1;
-    l.cell_particles[p.off + l.cell_start[p.coff + c] + slot] = i;
-}
-
-// The scatter order is arbitrary: sort every cell ascending (cells hold a few particles).
-__device__ inline void cell_sort(const SysParams &p, const ListPtrs &l, int c)
-{
-    const int lo = p.off + l.cell_start[p.coff + c], hi = p.off + l.cell_start[p.coff + c + 1];
-    for (int a = lo + 1; a < hi; ++a) {
-        const int key = l.cell_particles[a];
-        int b = a - 1;
-        while (b >= lo && l.cell_particles[b] > key) {
-            l.cell_particles[b + 1] = l.cell_particles[b];
-            --b;
-        }
-        l.cell_particles[b + 1] = key;
-    }
 }
 
 __device__ inline bool within(const SysParams &p, const StatePtrs &s, double xi, double yi, double zi, int j)
@@ -90,85 +53,188 @@ __device__ inline bool within(const SysParams &p, const StatePtrs &s, double xi,
     return r2 < p.rl2;
 }
 
-__device__ inline void nbr_build(const SysParams &p, const BatchParams &b, const StatePtrs &s, const ListPtrs &l, int i)
+__device__ inline unsigned long long lanes_below()
 {
-    const size_t N = (size_t)b.N;
-    const int cap = b.cap;
-    const double xi = s.x[i], yi = s.y[i], zi = (p.dim == 3) ? s.z[i] : 0.0;
-    int count = 0;
-    if (p.use_cells) {
-        const int c = l.pcell[i];
-        const int cx = c % p.nc[0];
-        const int cy = (c / p.nc[0]) % p.nc[1];
-        const int cz = c / (p.nc[0] * p.nc[1]);
-        const int zlo = (p.dim == 3) ? -1 : 0, zhi = (p.dim == 3) ? 1 : 0;
-        for (int dz = zlo; dz <= zhi; ++dz)
-            for (int dy = -1; dy <= 1; ++dy)
-                for (int dx = -1; dx <= 1; ++dx) {
-                    int ax = cx + dx, ay = cy + dy, az = cz + dz;
-                    ax += (ax < 0) ? p.nc[0] : 0;
-                    ax -= (ax >= p.nc[0]) ? p.nc[0] : 0;
-                    ay += (ay < 0) ? p.nc[1] : 0;
-                    ay -= (ay >= p.nc[1]) ? p.nc[1] : 0;
-                    az += (az < 0) ? p.nc[2] : 0;
-                    az -= (az >= p.nc[2]) ? p.nc[2] : 0;
-                    const int cc = p.coff + ax + p.nc[0] * (ay + p.nc[1] * az);
-                    for (int t = p.off + l.cell_start[cc]; t < p.off + l.cell_start[cc + 1]; ++t) {
-                        const int j = l.cell_particles[t];
-                        if (j != i && within(p, s, xi, yi, zi, j)) {
-                            if (count < cap) l.nbr[(size_t)count * N + i] = j;
-                            ++count;
-                        }
-                    }
-                }
-    } else {
-        for (int j = p.off; j < p.off + p.n; ++j)
-            if (j != i && within(p, s, xi, yi, zi, j)) {
-                if (count < cap) l.nbr[(size_t)count * N + i] = j;
-                ++count;
-            }
-    }
-    const int m = count < cap ? count : cap;
-    for (int a = 1; a < m; ++a) {  // ascending row
-        const int key = l.nbr[(size_t)a * N + i];
-        int c = a - 1;
-        while (c >= 0 && l.nbr[(size_t)c * N + i] > key) {
-            l.nbr[(size_t)(c + 1) * N + i] = l.nbr[(size_t)c * N + i];
-            --c;
-        }
-        l.nbr[(size_t)(c + 1) * N + i] = key;
-    }
-    l.n_nbr[i] = m;
-    if (count > cap) atomicMax(&l.flags[p.rid * FLAG_COUNT + FLAG_MAXROW], count);
-    l.xlast[i] = xi;
-    l.xlast[N + i] = yi;
-    l.xlast[2 * N + i] = zi;
+    const unsigned lane = __lane_id();
+    return lane == 0 ? 0ull : (~0ull >> (64 - lane));
 }
 
-// First slot of row i holding a neighbour j > i (rows ascend), and the
-// number of such slots: i owns the pairs (i, j > i) of the half list.
-__device__ inline void pair_count(const BatchParams &b, const ListPtrs &l, int32_t *upper, int i)
+// Does this launch build replica r?  (LISTS_REFILL: every live replica
+// that has lists.)
+__device__ inline bool building(int mode, int r, const SysParams &p, const int32_t *fl, const int64_t *budget)
 {
-    const size_t N = (size_t)b.N;
-    const int m = l.n_nbr[i];
-    int lo = 0, hi = m;
-    while (lo < hi) {
-        const int mid = (lo + hi) >> 1;
-        if (l.nbr[(size_t)mid * N + i] > i) hi = mid;
-        else lo = mid + 1;
+    if (!p.live) return false;
+    if (mode == LISTS_STEP) return fl[FLAG_REBUILD] != 0 && budget[r] > 0;
+    if (mode == LISTS_REFILL) return fl[FLAG_NBUILDS] > 0;
+    return mode == LISTS_ALL || mode == r;
+}
+
+// Exclusive scan of count[0..m) into start[0..m) by one workgroup of kBlock
+// threads (count may be start; it is read through volatile loads, as other
+// workgroups wrote it); returns the total to every thread.
+__device__ int block_scan(const int32_t *count, int32_t *start, int m, int *part)
+{
+    const volatile int32_t *vc = count;
+    const int t = threadIdx.x;
+    const int per = (m + kBlock - 1) / kBlock;
+    const int lo = min(t * per, m), hi = min(lo + per, m);
+    int sum = 0;
+    for (int c = lo; c < hi; ++c) sum += vc[c];
+    part[t] = sum;
+    __syncthreads();
+    for (int off = 1; off < kBlock; off <<= 1) {
+        const int v = (t >= off) ? part[t - off] : 0;
+        __syncthreads();
+        part[t] += v;
+        __syncthreads();
     }
-    l.klo[i] = lo;
-    upper[i] = m - lo;
+    int run = part[t] - sum;
+    for (int c = lo; c < hi; ++c) {
+        const int cnt = vc[c];
+        start[c] = run;
+        run += cnt;
+    }
+    const int total = part[kBlock - 1];
+    __syncthreads();
+    return total;
+}
+
+// Cells from the current positions (builds outside a step).
+__global__ void __launch_bounds__(kBlock) k_assign(BatchParams b, const SysParams *reps, StatePtrs s, ListPtrs l,
+                                                      const int64_t *budget, int mode)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int c = i / kChunk;
+    const int r = __builtin_amdgcn_readfirstlane(c < b.nchunk ? l.chunk_rep[c] : -1);
+    if (r < 0) return;
+    const SysParams &p = reps[r];
+    if (!building(mode, r, p, l.flags + r * FLAG_COUNT, budget) || i >= p.off + p.n) return;
+    cell_insert(p, l, i, s.x[i], s.y[i], p.dim == 3 ? s.z[i] : 0.0);
+}
+
+// Neighbour rows: 16 lanes per particle, 16 particles per block (all of one
+// chunk, so of one replica).  Each lane scans some of the neighbour cells
+// (or, without cells, a sixteenth of the replica); hits are appended to the
+// particle's LDS buffer in ballot order, then every kept hit finds its rank
+// (the number of smaller hits) and is stored in that row slot, so the row
+// ascends and keeps the cap smallest j.  The row's count of j > i is the
+// particle's pair count; the replica's last block scans those counts into
+// pair offsets.
+template <int DIM>
+__global__ void __launch_bounds__(kBlock) k_nbr(BatchParams b, const SysParams *reps, StatePtrs s, ListPtrs l,
+                                                   const int64_t *budget, int mode)
+{
+    __shared__ int buf[kNbrPer][kRowMax];
+    __shared__ int part[kBlock];
+    __shared__ int last;
+    if (mode == LISTS_STEP && l.gflags[G_ANY] == 0) return;
+    const int base = blockIdx.x * kNbrPer;
+    const int r = l.chunk_rep[base / kChunk];
+    if (r < 0) return;
+    const SysParams &p = reps[r];
+    int32_t *fl = l.flags + r * FLAG_COUNT;
+    if (!building(mode, r, p, fl, budget)) return;
+    const int g = threadIdx.x / kNbrLanes, sub = threadIdx.x % kNbrLanes;
+    const int i = base + g;
+    const bool mine = i < p.off + p.n;
+    const unsigned long long gmask = 0xffffull << (kNbrLanes * ((threadIdx.x & 63) / kNbrLanes));
+    const unsigned long long below = lanes_below();
+    const double xi = mine ? s.x[i] : 0.0, yi = mine ? s.y[i] : 0.0, zi = (mine && DIM == 3) ? s.z[i] : 0.0;
+    int m = 0;  // hits so far (the same in all lanes of the particle)
+    if (p.use_cells) {
+        const int c = mine ? l.pcell[i] : 0;
+        const int cx = c % p.nc[0], cy = (c / p.nc[0]) % p.nc[1], cz = c / (p.nc[0] * p.nc[1]);
+        constexpr int kNb = DIM == 3 ? 27 : 9;
+        for (int t0 = 0; t0 < kNb; t0 += kNbrLanes) {
+            const int t = t0 + sub;
+            int cc = 0, cnt = 0;
+            if (mine && t < kNb) {
+                int ax = cx + t % 3 - 1, ay = cy + (t / 3) % 3 - 1, az = cz + (DIM == 3 ? t / 9 - 1 : 0);
+                ax += (ax < 0) ? p.nc[0] : 0;
+                ax -= (ax >= p.nc[0]) ? p.nc[0] : 0;
+                ay += (ay < 0) ? p.nc[1] : 0;
+                ay -= (ay >= p.nc[1]) ? p.nc[1] : 0;
+                az += (az < 0) ? p.nc[2] : 0;
+                az -= (az >= p.nc[2]) ? p.nc[2] : 0;
+                cc = p.coff + ax + p.nc[0] * (ay + p.nc[1] * az);
+                cnt = min(l.cell_count[cc], kCellCap);
+            }
+            for (int k = 0;; ++k) {
+                const bool has = k < cnt;
+                if (__ballot(has) == 0) break;
+                int j = 0;
+                bool hit = false;
+                if (has) {
+                    j = l.cell_slot[(size_t)cc * kCellCap + k];
+                    hit = j != i && within(p, s, xi, yi, zi, j);
+                }
+                const unsigned long long hm = __ballot(hit);
+                const int pos = m + __popcll(hm & below & gmask);
+                if (hit && pos < kRowMax) buf[g][pos] = j;
+                m += __popcll(hm & gmask);
+            }
+        }
+    } else {
+        for (int k0 = 0; k0 < p.n; k0 += kNbrLanes) {
+            const int j = p.off + k0 + sub;
+            const bool hit = mine && k0 + sub < p.n && j != i && within(p, s, xi, yi, zi, j);
+            const unsigned long long hm = __ballot(hit);
+            const int pos = m + __popcll(hm & below & gmask);
+            if (hit && pos < kRowMax) buf[g][pos] = j;
+            m += __popcll(hm & gmask);
+        }
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    const size_t N = (size_t)b.N;
+    const int cap = b.cap;
+    const int mm = min(m, kRowMax);
+    int lower = 0;  // kept hits below i
+    if (mine)
+        for (int e = sub; e < mm; e += kNbrLanes) {
+            const int v = buf[g][e];
+            int rank = 0;
+            for (int f = 0; f < mm; ++f) rank += buf[g][f] < v ? 1 : 0;
+            if (rank < cap) {
+                l.nbr[(size_t)rank * N + i] = v;
+                lower += v < i ? 1 : 0;
+            }
+        }
+    for (int off = kNbrLanes / 2; off > 0; off >>= 1) lower += __shfl_xor(lower, off, kNbrLanes);
+    if (mine && sub == 0) {
+        const int kept = min(m, cap);
+        l.n_nbr[i] = kept;
+        l.klo[i] = lower;
+        l.pstart[i] = kept - lower;  // pair count; the scan below turns it into an offset
+        if (m > cap) atomicMax(&fl[FLAG_MAXROW], m);
+        l.xlast[i] = xi;
+        l.xlast[N + i] = yi;
+        l.xlast[2 * N + i] = zi;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        __threadfence();
+        const int nblk = (p.n + kChunk - 1) / kChunk * (kChunk / kNbrPer);
+        last = atomicAdd(&fl[FLAG_NBRTICKET], 1) == nblk - 1;
+    }
+    __syncthreads();
+    if (!last) return;
+    __threadfence();
+    const int np = block_scan(l.pstart + p.off, l.pstart + p.off, p.n, part);
+    if (threadIdx.x == 0) {
+        fl[FLAG_NPAIRS] = min(np, p.pcap);
+        fl[FLAG_NBRTICKET] = 0;
+    }
 }
 
 // Pair entries: the owner i of pair q writes {i, j, slot of j in i's row,
 // slot of i in j's row} with one store, the last found by bisection in j's
-// row (-1 if a row overflow left i out of it, which is reported).  Pair
-// indices are local to the replica.
+// row (-1 if a row overflow left i out of it, which is reported).
 __device__ inline void pair_fill(const SysParams &p, const BatchParams &b, const ListPtrs &l, int i)
 {
     const size_t N = (size_t)b.N;
-    const int m = l.n_nbr[i], k0 = l.klo[i];
+    const int m = min(l.n_nbr[i], b.cap), k0 = max(l.klo[i], 0);
     int4 *pairs = l.pairs + p.poff;
     for (int k = k0; k < m; ++k) {
         const int q = l.pstart[i] + (k - k0);
@@ -185,165 +251,56 @@ __device__ inline void pair_fill(const SysParams &p, const BatchParams &b, const
     }
 }
 
-// Exclusive scan of count[0..m) into start[0..m) by one workgroup of 1024
-// threads; returns the total to every thread.  count and start may alias.
-__device__ inline int block_scan(const int32_t *count, int32_t *start, int m, int *part)
+// Tile plan: the first tile of each replica (kTile pairs per tile), by one
+// workgroup.
+__device__ void plan(const BatchParams &b, const SysParams *reps, const ListPtrs &l, int *part)
 {
-    const int t = threadIdx.x;
-    const int per = (m + 1023) / 1024;
-    const int lo = t * per, hi = min(lo + per, m);
-    int sum = 0;
-    for (int c = lo; c < hi; ++c) sum += count[c];
-    part[t] = sum;
-    __syncthreads();
-    for (int off = 1; off < 1024; off <<= 1) {
-        const int v = (t >= off) ? part[t - off] : 0;
-        __syncthreads();
-        part[t] += v;
-        __syncthreads();
-    }
-    int run = part[t] - sum;
-    for (int c = lo; c < hi; ++c) {
-        const int cnt = count[c];
-        start[c] = run;
-        run += cnt;
-    }
-    const int total = part[1023];
-    __syncthreads();
-    return total;
-}
-
-// ---- one kernel per phase (a single replica, slot 0) -----------------------
-__global__ void k_cell_assign(SysParams p, StatePtrs s, ListPtrs l)
-{
-    if (l.flags[FLAG_REBUILD] == 0) return;
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < p.n) cell_assign(p, s, l, i);
-}
-
-__global__ void __launch_bounds__(1024) k_scan(const int32_t *count, int32_t *start, int m, const int32_t *flags)
-{
-    if (flags[FLAG_REBUILD] == 0) return;
-    __shared__ int part[1024];
-    const int total = block_scan(count, start, m, part);
-    if (threadIdx.x == 0) start[m] = total;
-}
-
-__global__ void k_cell_fill(SysParams p, ListPtrs l)
-{
-    if (l.flags[FLAG_REBUILD] == 0) return;
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < p.n) cell_fill(p, l, i);
-}
-
-__global__ void k_cell_sort(SysParams p, ListPtrs l)
-{
-    if (l.flags[FLAG_REBUILD] == 0) return;
-    const int c = blockIdx.x * blockDim.x + threadIdx.x;
-    if (c < p.ncell) cell_sort(p, l, c);
-}
-
-__global__ void k_nbr_build(SysParams p, BatchParams b, StatePtrs s, ListPtrs l)
-{
-    if (l.flags[FLAG_REBUILD] == 0) return;
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < p.n) nbr_build(p, b, s, l, i);
-}
-
-__global__ void k_pair_count(SysParams p, BatchParams b, ListPtrs l)
-{
-    if (l.flags[FLAG_REBUILD] == 0) return;
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < p.n) pair_count(b, l, l.pcell, i);  // pcell is free after the neighbour build
-}
-
-__global__ void k_pair_fill(SysParams p, BatchParams b, ListPtrs l)
-{
-    if (l.flags[FLAG_REBUILD] == 0) return;
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i == 0) {
-        const int np = min(l.pstart[p.n], p.pcap);
-        l.flags[FLAG_NPAIRS] = np;
-        l.tile_start[0] = 0;
-        l.tile_start[1] = (np + kTile - 1) / kTile;
-        l.gflags[G_ANY] = 0;
-    }
-    if (i < p.n) pair_fill(p, b, l, i);
-}
-
-// ---- the whole build of one replica per workgroup ---------------------------
-// Workgroup r rebuilds replica r if its flag is set; the last workgroup to
-// finish recomputes the tile plan over all replicas.
-__global__ void __launch_bounds__(1024) k_lists_fused(BatchParams b, const SysParams *reps, StatePtrs s, ListPtrs l)
-{
-    if (l.gflags[G_ANY] == 0) return;
-    __shared__ int part[1024];
-    __shared__ int last;
-    const int t = threadIdx.x;
-    const SysParams &p = reps[blockIdx.x];
-    int32_t *fl = l.flags + blockIdx.x * FLAG_COUNT;
-    if (p.live && p.n > 0 && fl[FLAG_REBUILD] != 0) {
-        const int lo = p.off, hi = p.off + p.n;
-        for (int i = lo + t; i < hi; i += 1024) cell_assign(p, s, l, i);
-        __syncthreads();
-        const int ncp = block_scan(l.cell_count + p.coff, l.cell_start + p.coff, p.ncell, part);
-        if (t == 0) l.cell_start[p.coff + p.ncell] = ncp;
-        for (int i = lo + t; i < hi; i += 1024) cell_fill(p, l, i);
-        __syncthreads();
-        for (int c = t; c < p.ncell; c += 1024) cell_sort(p, l, c);
-        __syncthreads();
-        for (int i = lo + t; i < hi; i += 1024) nbr_build(p, b, s, l, i);
-        __syncthreads();
-        for (int i = lo + t; i < hi; i += 1024) pair_count(b, l, l.pcell, i);
-        __syncthreads();
-        const int np = block_scan(l.pcell + p.off, l.pstart + p.off, p.n, part);
-        for (int i = lo + t; i < hi; i += 1024) pair_fill(p, b, l, i);
-        if (t == 0) fl[FLAG_NPAIRS] = min(np, p.pcap);
-    }
-    __syncthreads();
-    if (t == 0) {
-        __threadfence();
-        last = atomicAdd(&l.gflags[G_TICKET], 1) == (int)gridDim.x - 1;
-    }
-    __syncthreads();
-    if (!last) return;
-    __threadfence();
-    // tiles per replica, then their exclusive scan in place
     const volatile int32_t *vfl = l.flags;
-    for (int r = t; r < b.nrep; r += 1024) {
+    for (int r = threadIdx.x; r < b.nrep; r += blockDim.x) {
         const int np = vfl[r * FLAG_COUNT + FLAG_NPAIRS];
         l.tile_start[r] = reps[r].live ? (np + kTile - 1) / kTile : 0;
     }
     __syncthreads();
     const int total = block_scan(l.tile_start, l.tile_start, b.nrep, part);
-    if (t == 0) {
-        l.tile_start[b.nrep] = total;
-        l.gflags[G_ANY] = 0;
-        l.gflags[G_TICKET] = 0;
-    }
+    if (threadIdx.x == 0) l.tile_start[b.nrep] = total;
+}
+
+__global__ void __launch_bounds__(kBlock) k_fill(BatchParams b, const SysParams *reps, ListPtrs l,
+                                                    const int64_t *budget, int mode, int clear_cells)
+{
+    __shared__ int part[kBlock];
+    if (mode == LISTS_STEP && l.gflags[G_ANY] == 0) return;
+    if (blockIdx.x == 0) plan(b, reps, l, part);
+    if (mode == LISTS_PLAN) return;
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int c = i / kChunk;
+    const int r = __builtin_amdgcn_readfirstlane(c < b.nchunk ? l.chunk_rep[c] : -1);
+    if (r < 0) return;
+    const SysParams &p = reps[r];
+    if (!building(mode, r, p, l.flags + r * FLAG_COUNT, budget) || i >= p.off + p.n) return;
+    pair_fill(p, b, l, i);
+    if (clear_cells && p.use_cells) l.cell_count[p.coff + l.pcell[i]] = 0;  // every particle of the cell writes the same zero
 }
 
 }  // namespace
 
-void launch_build_lists(const Launch &L, int multi, const SysParams &p, hipStream_t stream)
+void launch_lists(const Launch &L, int mode, hipStream_t stream)
 {
     if (L.b.nrep == 0) return;
-    if (!multi) {
-        k_lists_fused<<<L.b.nrep, 1024, 0, stream>>>(L.b, L.reps, L.s, L.l);
+    const int nb = blocks_for(L.b.nchunk * kChunk);
+    if (mode == LISTS_PLAN || L.b.nchunk == 0) {
+        k_fill<<<1, kBlock, 0, stream>>>(L.b, L.reps, L.l, L.budget, LISTS_PLAN, 0);
         return;
     }
-    if (p.n == 0) return;
-    const int nb = blocks_for(p.n);
-    k_cell_assign<<<nb, kBlock, 0, stream>>>(p, L.s, L.l);
-    k_scan<<<1, 1024, 0, stream>>>(L.l.cell_count, L.l.cell_start, p.ncell, L.l.flags);
-    k_cell_fill<<<nb, kBlock, 0, stream>>>(p, L.l);
-    k_cell_sort<<<blocks_for(p.ncell), kBlock, 0, stream>>>(p, L.l);
-    k_nbr_build<<<nb, kBlock, 0, stream>>>(p, L.b, L.s, L.l);
-    k_pair_count<<<nb, kBlock, 0, stream>>>(p, L.b, L.l);
-    k_scan<<<1, 1024, 0, stream>>>(L.l.pcell, L.l.pstart, p.n, L.l.flags);
-    k_pair_fill<<<nb, kBlock, 0, stream>>>(p, L.b, L.l);
+    if (mode == LISTS_REFILL) {
+        k_fill<<<nb, kBlock, 0, stream>>>(L.b, L.reps, L.l, L.budget, LISTS_REFILL, 0);
+        return;
+    }
+    if (mode != LISTS_STEP) k_assign<<<nb, kBlock, 0, stream>>>(L.b, L.reps, L.s, L.l, L.budget, mode);
+    const int nbn = L.b.nchunk * (kChunk / kNbrPer);
+    if (L.b.dim == 3) k_nbr<3><<<nbn, kBlock, 0, stream>>>(L.b, L.reps, L.s, L.l, L.budget, mode);
+    else k_nbr<2><<<nbn, kBlock, 0, stream>>>(L.b, L.reps, L.s, L.l, L.budget, mode);
+    k_fill<<<nb, kBlock, 0, stream>>>(L.b, L.reps, L.l, L.budget, mode, 1);
 }
-
-int fused_list_max_n() { return kFusedMaxN; }
 
 }  // namespace dem

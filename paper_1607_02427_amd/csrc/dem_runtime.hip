@@ -77,7 +77,6 @@ struct Replica {
 struct dem_system {
     bool batch = false;
     int dim = 0, precision = 0;
-    int list_multi = 0;          // single system: one kernel per list phase
     bool auto_cap = true;
     bool counting = false;
     BatchParams bp{};
@@ -141,16 +140,18 @@ __global__ void k_advance_empty(int64_t *budget, int64_t *steps, int64_t n)
         *steps += d;
     }
 }
-__global__ void k_end_build(int32_t *flags)
+__global__ void k_count_build(int32_t *flags) { flags[FLAG_NBUILDS] += 1; }
+// A replica leaves the batch: drop its pending list build from the count.
+__global__ void k_retire_flags(int32_t *flags, int32_t *gflags)
 {
-    if (flags[FLAG_REBUILD] != 0) flags[FLAG_NBUILDS] += 1;
-    flags[FLAG_REBUILD] = 0;
+    if (flags[FLAG_REBUILD] != 0) atomicSub(&gflags[G_ANY], 1);
+    for (int w = 0; w < FLAG_COUNT; ++w) flags[w] = 0;
 }
 __global__ void k_set_thermo(double *th, double xi, double eta)
 {
     th[TH_XI] = th[TH_XI_B] = xi;
     th[TH_ETA] = th[TH_ETA_B] = eta;
-    th[TH_SCALE] = th[TH_SCALE_B] = 1.0;
+    th[TH_SB] = th[TH_SA] = 1.0;
     th[TH_OPEN] = 0.0;
 }
 
@@ -346,7 +347,7 @@ int auto_capacity(const dem_params &p, double rl)
     double expect = p.dim == 3 ? dens * 4.0 / 3.0 * M_PI * rl * rl * rl : dens * M_PI * rl * rl;
     int cap = (int)std::ceil(1.8 * expect) + 16;
     cap = std::max(16, std::min(cap, (int)std::max<int64_t>(p.n, 16)));
-    return (cap + 3) & ~3;
+    return std::min(kRowMax, (cap + 3) & ~3);
 }
 
 
@@ -444,26 +445,40 @@ dem_status upload_tables(dem_system *h)
 }
 
 // Row storage and everything sized by the row capacity: rows, pair entries
-// and pair records.  Every replica rebuilds its lists afterwards.
+// and pair records.  Rows keep their contents (row k of particle i sits at
+// k * N + i whatever the capacity); the pair entries, whose slots move with
+// the capacity, are written again from the rows, so the lists do not change.
 dem_status alloc_nbr(dem_system *h, int cap)
 {
+    if (cap > kRowMax) return fail(h, DEM_E_CAPACITY, "neighbour rows of %d exceed the limit %d", cap, kRowMax);
     (void)hipStreamSynchronize(h->stream);
-    (void)hipFree(h->lst.nbr);
-    (void)hipFree(h->lst.pairs);
-    (void)hipFree(h->rec);
-    h->lst.nbr = nullptr;
-    h->lst.pairs = nullptr;
-    h->rec = nullptr;
     const size_t N = (size_t)std::max(h->Ncap, kChunk);
     const size_t maxp = N * (size_t)cap / 2;
     if (maxp > (size_t)INT32_MAX) return fail(h, DEM_E_ARG, "pair capacity overflows int32");
-    if (hipMalloc(&h->lst.nbr, sizeof(int32_t) * (size_t)cap * N) != hipSuccess ||
-        hipMalloc(&h->lst.pairs, sizeof(int4) * maxp) != hipSuccess ||
+    int32_t *nbr = nullptr;
+    if (hipMalloc(&nbr, sizeof(int32_t) * (size_t)cap * N) != hipSuccess)
+        return fail(h, DEM_E_OOM, "neighbour list of %d x %zu entries", cap, N);
+    if (h->lst.nbr && h->bp.cap > 0)
+        HIPCHK(h, hipMemcpyAsync(nbr, h->lst.nbr, sizeof(int32_t) * (size_t)std::min(cap, h->bp.cap) * N,
+                                 hipMemcpyDeviceToDevice, h->stream));
+    HIPCHK(h, hipStreamSynchronize(h->stream));
+    (void)hipFree(h->lst.nbr);
+    (void)hipFree(h->lst.pairs);
+    (void)hipFree(h->rec);
+    h->lst.nbr = nbr;
+    h->lst.pairs = nullptr;
+    h->rec = nullptr;
+    if (hipMalloc(&h->lst.pairs, sizeof(int4) * maxp) != hipSuccess ||
         hipMalloc(&h->rec, force_word(h->precision) * kRec * (size_t)cap * N) != hipSuccess)
         return fail(h, DEM_E_OOM, "neighbour list of %d x %zu entries", cap, N);
     h->bp.cap = cap;
     place_pairs(h);
-    return upload_tables(h);
+    dem_status st = upload_tables(h);
+    if (st != DEM_OK) return st;
+    launch_lists(make_launch(h), LISTS_REFILL, h->stream);
+    HIPCHK(h, hipGetLastError());
+    HIPCHK(h, hipStreamSynchronize(h->stream));
+    return DEM_OK;
 }
 
 dem_status alloc_core(dem_system *h, int Ncap, int Ccap, int Scap, int Rcap)
@@ -490,13 +505,12 @@ dem_status alloc_core(dem_system *h, int Ncap, int Ccap, int Scap, int Rcap)
               hipMalloc(&h->lst.gflags, sizeof(int32_t) * G_COUNT) == hipSuccess &&
               hipMalloc(&h->lst.tile_start, sizeof(int32_t) * (Rcap + 1)) == hipSuccess &&
               hipMalloc(&h->lst.cell_count, sizeof(int32_t) * std::max(Ccap, 1)) == hipSuccess &&
-              hipMalloc(&h->lst.cell_start, sizeof(int32_t) * std::max(Ccap, 1)) == hipSuccess &&
-              hipMalloc(&h->lst.cell_particles, sizeof(int32_t) * N) == hipSuccess &&
+              hipMalloc(&h->lst.cell_slot, sizeof(int32_t) * kCellCap * (size_t)std::max(Ccap, 1)) == hipSuccess &&
               hipMalloc(&h->lst.pcell, sizeof(int32_t) * N) == hipSuccess &&
               hipMalloc(&h->lst.n_nbr, sizeof(int32_t) * N) == hipSuccess &&
               hipMalloc(&h->lst.xlast, sizeof(double) * 3 * N) == hipSuccess &&
               hipMalloc(&h->lst.klo, sizeof(int32_t) * N) == hipSuccess &&
-              hipMalloc(&h->lst.pstart, sizeof(int32_t) * (N + 1)) == hipSuccess &&
+              hipMalloc(&h->lst.pstart, sizeof(int32_t) * N) == hipSuccess &&
               hipMalloc(&h->rot, partrec_bytes(h->precision) * N) == hipSuccess &&
               (h->precision != DEM_FP32 || hipMalloc(&h->rec64, sizeof(PartRec64) * N) == hipSuccess);
     if (!ok) return fail(h, DEM_E_OOM, "device allocation failed");
@@ -518,7 +532,12 @@ dem_status alloc_core(dem_system *h, int Ncap, int Ccap, int Scap, int Rcap)
     HIPCHK(h, hipMemsetAsync(h->lst.gflags, 0, sizeof(int32_t) * G_COUNT, h->stream));
     HIPCHK(h, hipMemsetAsync(h->lst.tile_start, 0, sizeof(int32_t) * (Rcap + 1), h->stream));
     HIPCHK(h, hipMemsetAsync(h->lst.cell_count, 0, sizeof(int32_t) * std::max(Ccap, 1), h->stream));
+    // rows, pair offsets and cells start empty, so a pass over a replica that
+    // has no lists yet reads zeros
     HIPCHK(h, hipMemsetAsync(h->lst.n_nbr, 0, sizeof(int32_t) * N, h->stream));
+    HIPCHK(h, hipMemsetAsync(h->lst.klo, 0, sizeof(int32_t) * N, h->stream));
+    HIPCHK(h, hipMemsetAsync(h->lst.pstart, 0, sizeof(int32_t) * N, h->stream));
+    HIPCHK(h, hipMemsetAsync(h->lst.pcell, 0, sizeof(int32_t) * N, h->stream));
     HIPCHK(h, hipMemsetAsync(h->stats, 0, sizeof(unsigned long long) * ST_COUNT, h->stream));
     HIPCHK(h, hipMemsetAsync(h->ke_part, 0, sizeof(double) * 2 * nch, h->stream));
     HIPCHK(h, hipMemsetAsync(h->budget, 0, sizeof(int64_t) * Rcap, h->stream));
@@ -531,7 +550,7 @@ void free_all(dem_system *h)
     drop_graph(h);
     void *ptrs[] = {h->d_reps, h->d_chunk_rep, h->tab64, h->tab32, h->ke_part, h->e_part, h->thermo, h->budget,
                     h->steps, h->stats, h->lst.flags, h->lst.gflags, h->lst.tile_start, h->lst.cell_count,
-                    h->lst.cell_start, h->lst.cell_particles, h->lst.pcell, h->lst.n_nbr, h->lst.xlast, h->lst.klo,
+                    h->lst.cell_slot, h->lst.pcell, h->lst.n_nbr, h->lst.xlast, h->lst.klo,
                     h->lst.pstart, h->lst.nbr, h->lst.pairs, h->rot, h->rec, h->rec64};
     for (void *p : ptrs) (void)hipFree(p);
     if (h->batch) {
@@ -563,7 +582,7 @@ void enqueue_step(dem_system *h, hipStream_t s)
 {
     const Launch L = make_launch(h);
     launch_kick_drift(L, s);
-    launch_build_lists(L, h->list_multi, h->reps[0].sp, s);
+    launch_lists(L, LISTS_STEP, s);
     launch_pairs(L, h->counting ? h->stats : nullptr, s);
     launch_gather(L, true, s);
 }
@@ -581,35 +600,41 @@ dem_status ensure_graph(dem_system *h)
     return DEM_OK;
 }
 
-// Rebuilds the lists of the replicas in `which` (all live ones if empty)
-// now, growing the row capacity while it overflows and is automatic.
+// Builds the lists of replica `only` (all live replicas if LISTS_ALL) from
+// the current positions, now, growing the row capacity while rows overflow
+// and the capacity is automatic.  Other replicas' lists, and any rebuild
+// their next step has pending, are left as they are.
 dem_status build_lists_sync(dem_system *h, int only)
 {
     for (int attempt = 0; attempt < 4; ++attempt) {
-        int marked = 0;
         for (size_t r = 0; r < h->reps.size(); ++r) {
             if (!h->reps[r].live || (only >= 0 && (int)r != only)) continue;
-            k_set_i32<<<1, 1, 0, h->stream>>>(h->lst.flags + FLAG_COUNT * r + FLAG_REBUILD, 1);
             k_set_i32<<<1, 1, 0, h->stream>>>(h->lst.flags + FLAG_COUNT * r + FLAG_MAXROW, 0);
-            ++marked;
         }
-        if (marked == 0) return DEM_OK;
-        k_set_i32<<<1, 1, 0, h->stream>>>(h->lst.gflags + G_ANY, 1);
-        launch_build_lists(make_launch(h), h->list_multi, h->reps[0].sp, h->stream);
+        launch_lists(make_launch(h), only, h->stream);
         HIPCHK(h, hipGetLastError());
         std::vector<int32_t> flags((size_t)FLAG_COUNT * h->reps.size());
         HIPCHK(h, hipMemcpyAsync(flags.data(), h->lst.flags, sizeof(int32_t) * flags.size(), hipMemcpyDeviceToHost,
                                  h->stream));
         HIPCHK(h, hipStreamSynchronize(h->stream));
         int maxrow = 0;
-        for (size_t r = 0; r < h->reps.size(); ++r)
-            if (h->reps[r].live) maxrow = std::max(maxrow, flags[FLAG_COUNT * r + FLAG_MAXROW]);
-        if (maxrow <= h->bp.cap) return DEM_OK;
+        for (size_t r = 0; r < h->reps.size(); ++r) {
+            if (!h->reps[r].live || (only >= 0 && (int)r != only)) continue;
+            if (flags[FLAG_COUNT * r + FLAG_CELLOVF])
+                return fail(h, DEM_E_CAPACITY, "replica %zu: a cell holds more than %d particles", r, kCellCap);
+            maxrow = std::max(maxrow, flags[FLAG_COUNT * r + FLAG_MAXROW]);
+        }
+        if (maxrow <= h->bp.cap) {
+            for (size_t r = 0; r < h->reps.size(); ++r)
+                if (h->reps[r].live && (only < 0 || (int)r == only))
+                    k_count_build<<<1, 1, 0, h->stream>>>(h->lst.flags + FLAG_COUNT * r);
+            HIPCHK(h, hipGetLastError());
+            return DEM_OK;
+        }
         if (!h->auto_cap)
             return fail(h, DEM_E_CAPACITY, "neighbour row of %d exceeds capacity %d", maxrow, h->bp.cap);
-        dem_status st = alloc_nbr(h, ((maxrow * 5) / 4 + 8 + 3) & ~3);
+        dem_status st = alloc_nbr(h, std::min(kRowMax, ((maxrow * 5) / 4 + 8 + 3) & ~3));
         if (st != DEM_OK) return st;
-        only = -1;  // a new capacity moves every replica's rows: rebuild them all
     }
     return fail(h, DEM_E_CAPACITY, "neighbour capacity did not converge");
 }
@@ -699,7 +724,7 @@ dem_status place_replica(dem_system *h, Replica &R, const std::vector<ShapeTab<d
     if (slot < 0) return fail(h, DEM_E_OOM, "no free replica slot (%zu in use)", h->reps.size());
     const int n = R.sp.n;
     R.nchunks = (n + kChunk - 1) / kChunk;
-    R.ncells = R.sp.ncell + 1;
+    R.ncells = R.sp.ncell;
     R.nshapes = R.sp.n_shapes;
     R.chunk0 = h->chunks.find(R.nchunks);
     R.cell0 = h->cells.find(R.ncells);
@@ -747,7 +772,12 @@ dem_status place_replica(dem_system *h, Replica &R, const std::vector<ShapeTab<d
                              sizeof(ShapeTab<float>) * R.nshapes, hipMemcpyHostToDevice, h->stream));
     HIPCHK(h, hipMemsetAsync(h->lst.cell_count + R.cell0, 0, sizeof(int32_t) * R.ncells, h->stream));
     HIPCHK(h, hipMemsetAsync(h->lst.flags + FLAG_COUNT * slot, 0, sizeof(int32_t) * FLAG_COUNT, h->stream));
-    if (n > 0) HIPCHK(h, hipMemsetAsync(h->lst.n_nbr + off, 0, sizeof(int32_t) * n, h->stream));
+    if (n > 0) {  // the slots' previous owner left its lists there
+        HIPCHK(h, hipMemsetAsync(h->lst.n_nbr + off, 0, sizeof(int32_t) * n, h->stream));
+        HIPCHK(h, hipMemsetAsync(h->lst.klo + off, 0, sizeof(int32_t) * n, h->stream));
+        HIPCHK(h, hipMemsetAsync(h->lst.pstart + off, 0, sizeof(int32_t) * n, h->stream));
+        HIPCHK(h, hipMemsetAsync(h->lst.pcell + off, 0, sizeof(int32_t) * n, h->stream));
+    }
     k_set_thermo<<<1, 1, 0, h->stream>>>(h->thermo + TH_COUNT * slot, 0.0, 0.0);
     k_set_i64<<<1, 1, 0, h->stream>>>(h->budget + slot, kUnbounded);
     k_set_i64<<<1, 1, 0, h->stream>>>(h->steps + slot, 0);
@@ -775,7 +805,6 @@ dem_status compute_forces(dem_system *h)
 {
     const Launch L = make_launch(h);
     launch_rotations(L, h->stream);
-    launch_build_lists(L, h->list_multi, h->reps[0].sp, h->stream);  // gated: only if a rebuild is due
     launch_pairs(L, h->stats, h->stream);
     launch_gather(L, false, h->stream);
     HIPCHK(h, hipGetLastError());
@@ -815,8 +844,8 @@ dem_status replica_energy(dem_system *h, int r, dem_energy_out *o)
     const double vol = d == 3 ? sp.box[0] * sp.box[1] * sp.box[2] : sp.box[0] * sp.box[1];
     const double trW = d == 3 ? o->W[0] + o->W[4] + o->W[8] : o->W[0] + o->W[4];
     o->P = (2.0 * o->K_trans + trW) / (d * vol);
-    o->xi = th[TH_XI];
-    o->eta = th[TH_ETA];
+    o->xi = th[TH_XI_B];
+    o->eta = th[TH_ETA_B];
     o->H = K + o->U;
     if (sp.ensemble == DEM_NVT) o->H += 0.5 * sp.Qm * o->xi * o->xi + sp.g * sp.kT * o->eta;
     o->step = steps;
@@ -827,26 +856,32 @@ dem_status replica_energy(dem_system *h, int r, dem_energy_out *o)
     return DEM_OK;
 }
 
+// The lists of replica r in their canonical form: the cell list as CSR with
+// particles ascending inside each cell (from each particle's cell), rows as
+// stored.  Indices are the replica's own.
 dem_status copy_lists(dem_system *h, int r, int32_t *cell_start, int32_t *cell_particles, int32_t *nbr,
                       int32_t *n_nbr, int32_t *dims)
 {
     const Replica &R = h->reps[r];
     const size_t n = (size_t)R.sp.n, off = (size_t)R.sp.off, N = (size_t)h->bp.N;
-    if (cell_start)
-        HIPCHK(h, hipMemcpyAsync(cell_start, h->lst.cell_start + R.cell0, sizeof(int32_t) * (R.sp.ncell + 1),
-                                 hipMemcpyDeviceToHost, h->stream));
-    if (cell_particles && n)
-        HIPCHK(h, hipMemcpyAsync(cell_particles, h->lst.cell_particles + off, sizeof(int32_t) * n,
-                                 hipMemcpyDeviceToHost, h->stream));
+    std::vector<int32_t> pcell(n);
+    if (n) HIPCHK(h, hipMemcpyAsync(pcell.data(), h->lst.pcell + off, sizeof(int32_t) * n, hipMemcpyDeviceToHost,
+                                    h->stream));
     if (nbr && n)
         HIPCHK(h, hipMemcpy2DAsync(nbr, sizeof(int32_t) * n, h->lst.nbr + off, sizeof(int32_t) * N,
                                    sizeof(int32_t) * n, (size_t)h->bp.cap, hipMemcpyDeviceToHost, h->stream));
     if (n_nbr && n)
         HIPCHK(h, hipMemcpyAsync(n_nbr, h->lst.n_nbr + off, sizeof(int32_t) * n, hipMemcpyDeviceToHost, h->stream));
     HIPCHK(h, hipStreamSynchronize(h->stream));
-    // particle indices of the replica, from its slots
-    if (cell_particles)
-        for (size_t k = 0; k < n; ++k) cell_particles[k] -= (int32_t)off;
+    const int ncell = R.sp.ncell;
+    std::vector<int32_t> start((size_t)ncell + 1, 0);
+    for (size_t i = 0; i < n; ++i) start[(size_t)pcell[i] + 1] += 1;
+    for (int c = 0; c < ncell; ++c) start[(size_t)c + 1] += start[c];
+    if (cell_start) std::copy(start.begin(), start.end(), cell_start);
+    if (cell_particles) {
+        std::vector<int32_t> at(start.begin(), start.end() - 1);
+        for (size_t i = 0; i < n; ++i) cell_particles[at[pcell[i]]++] = (int32_t)i;
+    }
     if (nbr && n_nbr)
         for (size_t i = 0; i < n; ++i)
             for (int k = 0; k < n_nbr[i]; ++k) nbr[(size_t)k * n + i] -= (int32_t)off;
@@ -965,16 +1000,17 @@ dem_status dem_create_system(const dem_params *params, const dem_state_ptrs *sta
              state->vz, state->Lx, state->Ly, state->Lz, state->shape_id, state->image};
     h->out = {outputs->Fx, outputs->Fy, outputs->Fz, outputs->Tx, outputs->Ty, outputs->Tz, outputs->U, outputs->W};
     h->bp.wstride = (int)p.n;
-    h->list_multi = (p.list_mode == DEM_LISTS_MULTI || p.n > fused_list_max_n()) ? 1 : 0;
     if (hipStreamCreateWithFlags(&h->cap_stream, hipStreamNonBlocking) != hipSuccess)
         return bail(fail(h, DEM_E_HIP, "stream creation failed"));
     const int nch = (int)((p.n + kChunk - 1) / kChunk);
     if ((st = alloc_core(h, nch * kChunk, R.sp.ncell + 1, p.n_shapes, 1)) != DEM_OK) return bail(st);
     h->auto_cap = p.nbr_capacity <= 0;
+    if (!h->auto_cap && p.nbr_capacity > kRowMax)
+        return bail(fail(h, DEM_E_ARG, "nbr_capacity %d above the limit %d", p.nbr_capacity, kRowMax));
     if ((st = alloc_nbr(h, h->auto_cap ? auto_capacity(p, R.r_list) : p.nbr_capacity)) != DEM_OK) return bail(st);
     int rid = -1;
     if ((st = place_replica(h, R, t64, t32, nullptr, &rid)) != DEM_OK) return bail(st);
-    if ((st = build_lists_sync(h, -1)) != DEM_OK) return bail(st);
+    if ((st = build_lists_sync(h, LISTS_ALL)) != DEM_OK) return bail(st);
     if ((st = compute_forces(h)) != DEM_OK) return bail(st);
     if ((st = latched(h)) != DEM_OK) return bail(st);
     *out = h;
@@ -1025,9 +1061,6 @@ dem_status dem_batch_add(dem_handle h, const dem_params *params, const dem_state
     if (replica_id) *replica_id = -1;
     if (!h || !params || !state || !replica_id) return fail(h, DEM_E_ARG, "null argument");
     if (!h->batch) return fail(h, DEM_E_STATE, "not a batch handle");
-    if (params->n > fused_list_max_n())
-        return fail(h, DEM_E_ARG, "replica of %lld particles exceeds the batch limit %d", (long long)params->n,
-                    fused_list_max_n());
     if (steps < 0) return fail(h, DEM_E_ARG, "steps < 0");
     Replica R;
     std::vector<ShapeTab<double>> t64;
@@ -1040,10 +1073,8 @@ dem_status dem_batch_add(dem_handle h, const dem_params *params, const dem_state
     if ((st = place_replica(h, R, t64, t32, state, &rid)) != DEM_OK) return st;
     if (want > h->bp.cap) {
         if ((st = alloc_nbr(h, want)) != DEM_OK) return st;
-        if ((st = build_lists_sync(h, -1)) != DEM_OK) return st;
-    } else if ((st = build_lists_sync(h, rid)) != DEM_OK) {
-        return st;
     }
+    if ((st = build_lists_sync(h, rid)) != DEM_OK) return st;
     if ((st = compute_forces(h)) != DEM_OK) return st;
     if (steps > 0) k_set_i64<<<1, 1, 0, h->stream>>>(h->budget + rid, steps);
     HIPCHK(h, hipGetLastError());
@@ -1055,12 +1086,12 @@ dem_status dem_batch_remove(dem_handle h, int32_t rid)
 {
     if (!h || !h->batch) return fail(h, DEM_E_ARG, "not a batch handle");
     if (!valid_replica(h, rid)) return fail(h, DEM_E_ARG, "no replica %d", rid);
+    k_retire_flags<<<1, 1, 0, h->stream>>>(h->lst.flags + FLAG_COUNT * rid, h->lst.gflags);
     release_replica(h, rid);
     place_pairs(h);
     dem_status st = upload_tables(h);
     if (st != DEM_OK) return st;
-    // the tile plan must drop the replica before the next pair launch
-    k_set_i32<<<1, 1, 0, h->stream>>>(h->lst.gflags + G_ANY, 1);
+    launch_lists(make_launch(h), LISTS_PLAN, h->stream);  // the tile plan drops the replica
     HIPCHK(h, hipGetLastError());
     return DEM_OK;
 }
@@ -1160,12 +1191,7 @@ dem_status dem_destroy_system(dem_handle h)
 dem_status dem_build_celllist(dem_handle h)
 {
     if (!h) return fail(nullptr, DEM_E_ARG, "null handle");
-    dem_status st = build_lists_sync(h, -1);
-    if (st != DEM_OK) return st;
-    for (size_t r = 0; r < h->reps.size(); ++r)
-        if (h->reps[r].live) k_end_build<<<1, 1, 0, h->stream>>>(h->lst.flags + FLAG_COUNT * r);
-    HIPCHK(h, hipGetLastError());
-    return DEM_OK;
+    return build_lists_sync(h, LISTS_ALL);
 }
 
 dem_status dem_compute_forces(dem_handle h)

@@ -758,3 +758,107 @@ def _qmat(q):
     return np.array([[1 - 2 * (y * y + z * z), 2 * (x * y - w * z), 2 * (x * z + w * y)],
                      [2 * (x * y + w * z), 1 - 2 * (x * x + z * z), 2 * (y * z - w * x)],
                      [2 * (x * z - w * y), 2 * (y * z + w * x), 1 - 2 * (x * x + y * y)]])
+
+
+# --------------------------------------------------------------------------
+# Replicas for batched and served runs
+# --------------------------------------------------------------------------
+# Time steps per shape (2D 1e-4, cube and tetrahedron and L-prism 5e-4,
+# octahedron 2e-4).
+DT = {"square": 1e-4, "pentagon": 1e-4, "cube": 5e-4, "tetrahedron": 5e-4, "lprism": 5e-4, "octahedron": 2e-4}
+
+
+def replica_system(shape: Shape, n: int, fraction: float, seed: int, *, kT: float = 1.0, max_deg: float = 10.0,
+                   dt: float = 5e-4, ensemble: str = "nvt", name: str = "") -> System:
+    """n particles on an orthorhombic (2D: rectangular) lattice, n of its
+    sites drawn at random, rotations up to max_deg (3D: about random axes;
+    2D: in [-max_deg, max_deg]).  The lattice cell is the shape's rounded
+    bounding box widened by 4 sin(max_deg / 2) R on every axis (a rotation
+    by at most max_deg moves no point of the body farther than
+    2 sin(max_deg / 2) R), stretched by a common factor >= 1 to reach the
+    requested area or volume fraction; where even the unstretched cell is
+    too large, the lattice is that cell and `fraction_realized` says what it
+    gives.  Neighbouring bodies can therefore not overlap."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    dim = shape.dim
+    ext = shape.vertices[:, :dim].max(axis=0) - shape.vertices[:, :dim].min(axis=0) + 2.0 * shape.r
+    ext = ext + 4.0 * math.sin(math.radians(max_deg) / 2.0) * shape.circumradius
+    c = (n * float(np.prod(ext))) ** (1.0 / dim)
+    k = np.maximum(1, np.rint(c / ext)).astype(int)
+    while int(np.prod(k)) < n:
+        a = int(np.argmin(k * ext))
+        k[a] += 1
+    lam = (n * shape.volume / (fraction * float(np.prod(k * ext)))) ** (1.0 / dim)
+    lam = max(lam, 1.0)
+    spacing = lam * ext
+    box = np.ones(3)
+    box[:dim] = k * spacing
+    sites = np.sort(rng.choice(int(np.prod(k)), size=n, replace=False))
+    idx = np.stack(np.unravel_index(sites, tuple(k)), axis=1)
+    x = np.zeros((n, 3))
+    x[:, :dim] = (idx + 0.5) * spacing
+    if dim == 2:
+        q = planar_quaternions(np.deg2rad(rng.uniform(-max_deg, max_deg, n)))
+    else:
+        q = small_rotations(rng, n, max_deg)
+    shape_id = np.zeros(n, dtype=np.int32)
+    v, Lm = thermal_momenta(rng, [shape], shape_id, dim, kT)
+    s = System(dim=dim, box=box, shapes=[shape], shape_id=shape_id, x=x, q=q, v=v, L=Lm,
+               image=np.zeros((n, 3), dtype=np.int32), kT=kT, name=name)
+    s.dt = dt
+    s.ensemble = ensemble
+    s.fraction_realized = n * shape.volume / float(np.prod(box[:dim]))
+    return s
+
+
+def batched_replicas(count: int = 96, seed: int = 4, n_range=(512, 32768), steps: int = 500) -> List[System]:
+    """The batched workload: `count` independent NVT replicas (kT = 1), sizes
+    log-uniform in n_range, shapes uniform over {rounded cube, rounded
+    tetrahedron, concave L-prism}, rounding radius U[0.1, 0.2], packing
+    fraction U[0.3, 0.5] (capped by the lattice, see replica_system),
+    replica r drawn from seed 1000 * seed + r.  `steps` is recorded on each
+    as `steps`."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    names = ("cube", "tetrahedron", "lprism")
+    out = []
+    for r in range(count):
+        n = int(round(math.exp(rng.uniform(math.log(n_range[0]), math.log(n_range[1])))))
+        name = names[int(rng.integers(0, 3))]
+        rr = float(rng.uniform(0.1, 0.2))
+        phi = float(rng.uniform(0.3, 0.5))
+        shp = SHAPES[name](r=rr) if name != "lprism" else lprism(r=rr, quad_h=0.02)
+        s = replica_system(shp, n, phi, 1000 * seed + r, dt=DT[name], name=f"replica{r}_{name}_{n}")
+        s.steps = steps
+        s.fraction_requested = phi
+        out.append(s)
+    return out
+
+
+def served_trace(count: int = 256, seed: int = 5, rate: float = 40.0, n_range=(256, 65536),
+                 steps_range=(1000, 5000)) -> List[System]:
+    """The served workload: `count` requests arriving as a Poisson process of
+    `rate` per second (attribute `arrival`, seconds), each an NVT replica of
+    size log-uniform in n_range, shape uniform over {2D rounded pentagon, 3D
+    rounded cube, 3D rounded octahedron}, rounding U[0.1, 0.2], packing
+    fraction U[0.3, 0.5] (capped by the lattice), kT U[0.5, 2.0] and
+    U{steps_range} steps (attribute `steps`); request k drawn from seed
+    1000 * seed + k."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    names = ("pentagon", "cube", "octahedron")
+    t = 0.0
+    out = []
+    for k in range(count):
+        t += float(rng.exponential(1.0 / rate))
+        n = int(round(math.exp(rng.uniform(math.log(n_range[0]), math.log(n_range[1])))))
+        name = names[int(rng.integers(0, 3))]
+        rr = float(rng.uniform(0.1, 0.2))
+        phi = float(rng.uniform(0.3, 0.5))
+        kT = float(rng.uniform(0.5, 2.0))
+        steps = int(rng.integers(steps_range[0], steps_range[1] + 1))
+        shp = SHAPES[name](r=rr)
+        s = replica_system(shp, n, phi, 1000 * seed + k, kT=kT, dt=DT[name], name=f"request{k}_{name}_{n}")
+        s.arrival = t
+        s.steps = steps
+        s.fraction_requested = phi
+        out.append(s)
+    return out

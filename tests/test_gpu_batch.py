@@ -153,3 +153,45 @@ def test_batch_full_is_reported():
         assert ei.value.status == 3
         with pytest.raises(dem.DemError):
             B.add(I.squares_2d())                            # wrong dimension
+
+
+@pytest.mark.parametrize("prec", ["fp32", "fp64"])
+def test_split_calls_equal_one_call(prec):
+    """NVT steps split over several dem_step calls give the same numbers as
+    one call (the thermostat's pending half steps carry across calls)."""
+    dem = _dem()
+    s = I.cubes_3d(n_side=6)
+    one = _solo(dem, s, prec, 122)
+    with dem.DemSystem(s, prec) as g:
+        for n in (37, 37, 37, 11):
+            g.step(n)
+        _same((g.state(), g.outputs()), one[:2])
+        e = g.energy()
+    assert e["H"] == one[2]["H"] and e["xi"] == one[2]["xi"]
+
+
+def test_served_requests_equal_solo():
+    """Requests served with continuous batching (arrivals while others run,
+    two dimensions, chunked steps, admission and retirement mid-run) return
+    the same state and forces, bit for bit, as each request run alone."""
+    dem = _dem()
+    from paper_1607_02427_amd import serve
+    reqs = [I.replica_system(I.cube(r=0.15), 300, 0.4, 41, dt=5e-4),
+            I.replica_system(I.pentagon(r=0.12), 256, 0.45, 42, dt=1e-4, kT=1.5),
+            I.replica_system(I.octahedron(r=0.2), 200, 0.3, 43, dt=2e-4, kT=0.7),
+            I.replica_system(I.tetrahedron(r=0.1), 150, 0.3, 44, dt=5e-4),
+            I.replica_system(I.pentagon(r=0.18), 333, 0.4, 45, dt=1e-4, ensemble="nve")]
+    for k, (t, n) in enumerate([(0.0, 130), (0.0, 95), (0.05, 70), (0.1, 111), (0.12, 64)]):
+        reqs[k].arrival = t
+        reqs[k].steps = n
+    srv = serve.Server(budget_bytes=1 << 30, precision="fp32", max_replicas=8,
+                       max_particles={2: 4096, 3: 4096}, chunk=20, keep_results=True)
+    try:
+        recs = srv.run(reqs)
+    finally:
+        srv.close()
+    for r, s in zip(recs, reqs):
+        print(f"[serve] request {r.index} n={s.n} steps={s.steps} latency {r.latency:.3f} s", flush=True)
+        st, out = r.result
+        solo = _solo(dem, s, "fp32", s.steps)
+        _same((st, out), solo[:2])
