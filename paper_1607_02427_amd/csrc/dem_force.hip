@@ -149,9 +149,9 @@ __device__ inline unsigned long long lanes_below()
     return lane == 0 ? 0ull : (~0ull >> (64 - lane));
 }
 
-constexpr int kWaves = 4;          // waves per block
-constexpr int kGL = 16;            // lanes per particle pair
-constexpr int kGroups = 64 / kGL;  // pairs per wave
+constexpr int kWaves = kPairWaves;  // waves per block
+constexpr int kGL = kPairLanes;      // lanes per particle pair
+constexpr int kGroups = 64 / kGL;   // pairs per wave
 constexpr int kQueue = 128;        // survivor queue entries per pair
 
 // Reciprocal: the hardware FP32 estimate (1 ulp), exact division in FP64.
@@ -472,7 +472,7 @@ __global__ void __launch_bounds__(64 * kWaves) k_pairs(BatchParams b, const SysP
     const int wid = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int grp = lane / kGL, sub = lane % kGL;
     PairLds<T> &W = pls[wid * kGroups + grp];
-    const unsigned long long gmask = 0xffffull << (kGL * grp);
+    const unsigned long long gmask = ((kGL == 64) ? ~0ull : ((1ull << kGL) - 1)) << (kGL * grp);
     const unsigned long long below = lanes_below();
     const size_t N = (size_t)b.N;
     const int ntiles = l.tile_start[b.nrep];
@@ -530,11 +530,12 @@ __global__ void __launch_bounds__(64 * kWaves) k_pairs(BatchParams b, const SysP
             sj = rj.sid;
             const double bound = rl.R[si] + rl.R[sj] + kWcaCut * (rl.rad[si] + rl.rad[sj]);
             live = dx * dx + dy * dy + dz * dz < bound * bound;
-            if (!live && sub < kRec) {  // zero both row slots of a pair out of reach
-                const size_t cs = (size_t)sub * b.cap * N;
-                rec[cs + (size_t)ent.z * N + i] = T(0);
-                if (ent.w >= 0) rec[cs + (size_t)ent.w * N + j] = T(0);
-            }
+            if (!live)  // zero both row slots of a pair out of reach
+                for (int c = sub; c < kRec; c += kGL) {
+                    const size_t cs = (size_t)c * b.cap * N;
+                    rec[cs + (size_t)ent.z * N + i] = T(0);
+                    if (ent.w >= 0) rec[cs + (size_t)ent.w * N + j] = T(0);
+                }
         }
         if (__ballot(live) == 0) continue;
         const ShapeTab<T> &Si = tab[si];
@@ -561,23 +562,28 @@ __global__ void __launch_bounds__(64 * kWaves) k_pairs(BatchParams b, const SysP
         // the other body only if it lies within R_other + r_cut of that body's
         // centre, widened by the edge half length or the face's bounding
         // radius.  One lane per feature; survivors are listed by index.
-        bool nj = false, ni = false;
-        if (live && sub < Sj.nv) {
-            const V3<T> v = t + mul(Rr, ld3(Sj.v[sub]));
-            W.vj[sub][0] = v.x;
-            W.vj[sub][1] = v.y;
-            W.vj[sub][2] = v.z;
-            nj = dot(v, v) < grow * Bi * Bi;
+        int cvj = 0, cvi = 0;
+        for (int v0 = 0; v0 < DEM_MAX_VERTS; v0 += kGL) {
+            const int vk = v0 + sub;
+            bool nj = false, ni = false;
+            if (live && vk < Sj.nv) {
+                const V3<T> v = t + mul(Rr, ld3(Sj.v[vk]));
+                W.vj[vk][0] = v.x;
+                W.vj[vk][1] = v.y;
+                W.vj[vk][2] = v.z;
+                nj = dot(v, v) < grow * Bi * Bi;
+            }
+            if (live && vk < Si.nv) {
+                const V3<T> v = mulT(Rr, ld3(Si.v[vk]) - t);
+                W.vi[vk][0] = v.x;
+                W.vi[vk][1] = v.y;
+                W.vi[vk][2] = v.z;
+                ni = dot(v, v) < grow * Bj * Bj;
+            }
+            cvj = group_append(nj, W.vj_near, cvj, vk, gmask, below);
+            cvi = group_append(ni, W.vi_near, cvi, vk, gmask, below);
+            if (__ballot(live && (v0 + kGL < Si.nv || v0 + kGL < Sj.nv)) == 0) break;
         }
-        if (live && sub < Si.nv) {
-            const V3<T> v = mulT(Rr, ld3(Si.v[sub]) - t);
-            W.vi[sub][0] = v.x;
-            W.vi[sub][1] = v.y;
-            W.vi[sub][2] = v.z;
-            ni = dot(v, v) < grow * Bj * Bj;
-        }
-        const int cvj = group_append(nj, W.vj_near, 0, sub, gmask, below);
-        const int cvi = group_append(ni, W.vi_near, 0, sub, gmask, below);
         wave_sync_lds();
         int cei = 0, cej = 0;
         for (int e0 = 0; e0 < DEM_MAX_EDGES; e0 += kGL) {
@@ -695,27 +701,29 @@ __global__ void __launch_bounds__(64 * kWaves) k_pairs(BatchParams b, const SysP
         const T I0 = group_sum(A.Ti.x), I1 = group_sum(A.Ti.y), I2 = group_sum(A.Ti.z);
         const T J0 = group_sum(A.Tj.x), J1 = group_sum(A.Tj.y), J2 = group_sum(A.Tj.z);
         const T U = group_sum(A.U);
-        if (live && sub < kRec) {
+        if (live) {
             const V3<T> Fs = mul(Ri, v3<T>(F0, F1, F2));
             const V3<T> Is = mul(Ri, v3<T>(I0, I1, I2));
             const V3<T> Js = mul(Ri, v3<T>(J0, J1, J2));
-            T vi, vj;  // component sub of the records in i's slot and in j's slot
-            if (sub < 3) {
-                vi = sub == 0 ? Fs.x : (sub == 1 ? Fs.y : Fs.z);
-                vj = -vi;
-            } else if (sub < 6) {
-                vi = sub == 3 ? Is.x : (sub == 4 ? Is.y : Is.z);
-                vj = sub == 3 ? Js.x : (sub == 4 ? Js.y : Js.z);
-            } else if (sub == 6) {
-                vi = U;
-                vj = U;
-            } else {
-                vi = (T)(sub == 7 ? dx : (sub == 8 ? dy : dz));
-                vj = -vi;
+            for (int c = sub; c < kRec; c += kGL) {
+                T vi, vj;  // component c of the records in i's slot and in j's slot
+                if (c < 3) {
+                    vi = c == 0 ? Fs.x : (c == 1 ? Fs.y : Fs.z);
+                    vj = -vi;
+                } else if (c < 6) {
+                    vi = c == 3 ? Is.x : (c == 4 ? Is.y : Is.z);
+                    vj = c == 3 ? Js.x : (c == 4 ? Js.y : Js.z);
+                } else if (c == 6) {
+                    vi = U;
+                    vj = U;
+                } else {
+                    vi = (T)(c == 7 ? dx : (c == 8 ? dy : dz));
+                    vj = -vi;
+                }
+                const size_t cs = (size_t)c * b.cap * N;
+                rec[cs + (size_t)ent.z * N + i] = vi;
+                if (ent.w >= 0) rec[cs + (size_t)ent.w * N + j] = vj;
             }
-            const size_t cs = (size_t)sub * b.cap * N;
-            rec[cs + (size_t)ent.z * N + i] = vi;
-            if (ent.w >= 0) rec[cs + (size_t)ent.w * N + j] = vj;
         }
     }
     if (stats) {
@@ -789,11 +797,11 @@ __device__ inline double nh_half(const SysParams &p, double &xi, double &eta, do
 // in this step and schedules one for the next step if a particle moved far
 // enough.  A replica with no budget left is skipped.
 template <typename T, int DIM, bool KICK>
-__global__ void __launch_bounds__(kBlock) k_gather(BatchParams b, const SysParams *reps, StatePtrs s, OutPtrs o,
+__global__ void __launch_bounds__(kGatherBlock) k_gather(BatchParams b, const SysParams *reps, StatePtrs s, OutPtrs o,
                                                       ListPtrs l, const T *__restrict__ rec, double *ke_part,
                                                       double *thermo, int64_t *budget, int64_t *steps)
 {
-    __shared__ double sh[kBlock];
+    __shared__ double sh[kGatherBlock];
     __shared__ int last;
     const int r = l.chunk_rep[blockIdx.x];
     if (r < 0) return;
@@ -873,8 +881,8 @@ __global__ void __launch_bounds__(kBlock) k_gather(BatchParams b, const SysParam
     }
     if (!KICK) return;
     if (nvt) {
-        kt = block_sum<kBlock>(kt, sh);
-        kr = block_sum<kBlock>(kr, sh);
+        kt = block_sum<kGatherBlock>(kt, sh);
+        kr = block_sum<kGatherBlock>(kr, sh);
     }
     const int nblk = (p.n + kChunk - 1) / kChunk;
     if (threadIdx.x == 0) {
@@ -894,7 +902,7 @@ __global__ void __launch_bounds__(kBlock) k_gather(BatchParams b, const SysParam
         const volatile double *vp = ke_part;
         double acc2 = 0.0;
         for (int c = threadIdx.x; c < nblk; c += blockDim.x) acc2 += vp[2 * (c0 + c)] + vp[2 * (c0 + c) + 1];
-        double K = block_sum<kBlock>(acc2, sh);
+        double K = block_sum<kGatherBlock>(acc2, sh);
         if (threadIdx.x == 0) {
             double *th = thermo + r * TH_COUNT;
             double xi = th[TH_XI], eta = th[TH_ETA];
@@ -961,10 +969,10 @@ void gather_t(const Launch &L, bool kick, hipStream_t stream)
 {
     const T *rec = reinterpret_cast<const T *>(L.f.rec);
     if (kick)
-        k_gather<T, DIM, true><<<L.b.nchunk, kBlock, 0, stream>>>(L.b, L.reps, L.s, L.o, L.l, rec, L.ke_part,
+        k_gather<T, DIM, true><<<L.b.nchunk, kGatherBlock, 0, stream>>>(L.b, L.reps, L.s, L.o, L.l, rec, L.ke_part,
                                                                     L.thermo, L.budget, L.steps);
     else
-        k_gather<T, DIM, false><<<L.b.nchunk, kBlock, 0, stream>>>(L.b, L.reps, L.s, L.o, L.l, rec, L.ke_part,
+        k_gather<T, DIM, false><<<L.b.nchunk, kGatherBlock, 0, stream>>>(L.b, L.reps, L.s, L.o, L.l, rec, L.ke_part,
                                                                      L.thermo, L.budget, L.steps);
 }
 

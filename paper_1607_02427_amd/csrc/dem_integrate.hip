@@ -253,10 +253,10 @@ __global__ void __launch_bounds__(kBlock) k_kick_drift(BatchParams b, const SysP
 
 // Per-chunk kinetic partials of the current state, with the particle-to-
 // block mapping of the gather (one chunk per block).
-__global__ void __launch_bounds__(kBlock) k_kinetic(BatchParams b, const SysParams *reps, StatePtrs s, ListPtrs l,
+__global__ void __launch_bounds__(kGatherBlock) k_kinetic(BatchParams b, const SysParams *reps, StatePtrs s, ListPtrs l,
                                                        double *ke_part)
 {
-    __shared__ double sh[kBlock];
+    __shared__ double sh[kGatherBlock];
     const int r = l.chunk_rep[blockIdx.x];
     if (r < 0) return;
     const SysParams &p = reps[r];
@@ -270,8 +270,8 @@ __global__ void __launch_bounds__(kBlock) k_kinetic(BatchParams b, const SysPara
         for (int a = 0; a < 3; ++a)
             if (p.inertia[sid][a] > 0.0) kr += 0.5 * L[a] * L[a] / p.inertia[sid][a];
     }
-    kt = block_sum<kBlock>(kt, sh);
-    kr = block_sum<kBlock>(kr, sh);
+    kt = block_sum<kGatherBlock>(kt, sh);
+    kr = block_sum<kGatherBlock>(kr, sh);
     if (threadIdx.x == 0) {
         ke_part[2 * blockIdx.x] = kt;
         ke_part[2 * blockIdx.x + 1] = kr;
@@ -342,7 +342,7 @@ void launch_kick_drift(const Launch &L, hipStream_t stream)
 void launch_kinetic(const Launch &L, hipStream_t stream)
 {
     if (L.b.nchunk == 0) return;
-    k_kinetic<<<L.b.nchunk, kBlock, 0, stream>>>(L.b, L.reps, L.s, L.l, L.ke_part);
+    k_kinetic<<<L.b.nchunk, kGatherBlock, 0, stream>>>(L.b, L.reps, L.s, L.l, L.ke_part);
 }
 
 void launch_energy_partials(const Launch &L, double *part, hipStream_t stream)

@@ -17,8 +17,12 @@ constexpr double kWcaCut = 1.122462048309373;
 // boundary, so a wavefront's particles (and a gather block's) belong to one
 // replica, and per-chunk partial sums do not depend on the other replicas.
 constexpr int kChunk = 64;
-// Particle pairs per tile of the pair kernel; tiles never straddle replicas.
-constexpr int kTile = 16;
+// The pair kernel: kPairLanes lanes per particle pair, kPairWaves waves
+// per workgroup; a tile is what one workgroup takes at a time (one pair per
+// lane group), and tiles never straddle replicas.
+constexpr int kPairLanes = 16;
+constexpr int kPairWaves = 4;
+constexpr int kTile = kPairWaves * (64 / kPairLanes);
 
 // Per-replica device flag words (flags[r * FLAG_COUNT + w], one 64-byte
 // line per replica).  FLAG_TRIGGER: some particle has moved far enough
@@ -264,10 +268,11 @@ void launch_energy_partials(const Launch &L, double *part, hipStream_t stream);
 constexpr int kBlock = 256;
 inline int blocks_for(int n) { return (n + kBlock - 1) / kBlock; }
 // The gather and the kinetic reduction map one chunk (kGatherPer = kChunk
-// particles) to each 256-thread block, which writes one kinetic partial.
-constexpr int kGatherLanes = 4;
-constexpr int kGatherPer = kBlock / kGatherLanes;
-static_assert(kGatherPer == kChunk, "one gather block per chunk");
+// particles) to each block of kGatherLanes lanes per particle, which writes
+// one kinetic partial.
+constexpr int kGatherLanes = 1;
+constexpr int kGatherPer = kChunk;
+constexpr int kGatherBlock = kChunk * kGatherLanes;
 
 // Rotation matrix (row-major, body to space) of a unit quaternion (w, x, y, z).
 __host__ __device__ inline void quat_to_rot(double w, double x, double y, double z, double *R)
