@@ -161,6 +161,8 @@ def main():
     ap.add_argument("--requests", type=int, default=32, help="requests of the served trace")
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-served", action="store_true")
+    ap.add_argument("--no-sequential", action="store_true",
+                    help="skip the one-at-a-time plain FP64 runs of the batched and served workloads")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU layout is design-only.",
@@ -202,15 +204,16 @@ def main():
         log(f"[bench] batched: {len(reps)} replicas, {sum(s.n for s in reps)} particles, "
             f"{args.batched_steps} steps")
         rb = run_batched(reps, args.batched_steps, 20)
-        log(f"[bench] batched fp32 {rb['value']:.3e} PTPS; plain fp64 one replica at a time")
-        rp = run_plain_sequential(reps, args.batched_steps, 20)
+        log(f"[bench] batched fp32 {rb['value']:.3e} PTPS")
+        rp = None if args.no_sequential else run_plain_sequential(reps, args.batched_steps, 20)
         line["batched"] = {
             "workload": f"{len(reps)} NVT replicas (kT 1), sizes log-uniform 512-32768, shapes uniform over rounded "
                         f"cube / tetrahedron / concave L-prism, rounding U[0.1, 0.2], packing fraction U[0.3, 0.5] "
                         f"capped by an overlap-free lattice, {args.batched_steps} steps after 20 warm-up",
             "replicas": len(reps), "particles": rb["particles"], "steps": args.batched_steps,
             "value": rb["value"], "unit": "particle-timesteps/s", "ms_per_step": rb["ms_per_step"], "dtype": "f32",
-            "plain_fp64_sequential": rp["value"], "speedup_vs_plain": rb["value"] / rp["value"]}
+            "plain_fp64_sequential": rp["value"] if rp else None,
+            "speedup_vs_plain": rb["value"] / rp["value"] if rp else None}
     if not args.no_served:
         from paper_1607_02427_amd import serve
         trace = I.served_trace(args.requests)
@@ -227,7 +230,7 @@ def main():
             srv.close()
         log(f"[bench] served p50 {srs['p50_latency_s']:.2f} s p99 {srs['p99_latency_s']:.2f} s, "
             f"{srs['value']:.3e} PTPS; sequential plain fp64")
-        sqs = serve.summarize(serve.run_sequential(trace, "fp64"))
+        sqs = None if args.no_sequential else serve.summarize(serve.run_sequential(trace, "fp64"))
         line["served"] = {
             "workload": f"{len(trace)} requests, Poisson arrivals at 40/s, sizes log-uniform 256-65536, 2D rounded "
                         f"pentagons or 3D rounded cubes / octahedra, 1000-5000 NVT steps, kT U[0.5, 2]; "
@@ -235,8 +238,9 @@ def main():
             "requests": len(trace), "p50_latency_s": srs["p50_latency_s"], "p99_latency_s": srs["p99_latency_s"],
             "value": srs["value"], "unit": "particle-timesteps/s", "makespan_s": srs["makespan_s"],
             "offered_load": work / trace[-1].arrival, "dtype": "f32",
-            "sequential_plain_fp64": {"p50_latency_s": sqs["p50_latency_s"], "p99_latency_s": sqs["p99_latency_s"],
-                                      "value": sqs["value"], "makespan_s": sqs["makespan_s"]}}
+            "sequential_plain_fp64": None if sqs is None else {
+                "p50_latency_s": sqs["p50_latency_s"], "p99_latency_s": sqs["p99_latency_s"], "value": sqs["value"],
+                "makespan_s": sqs["makespan_s"]}}
     if not args.no_cpu:
         log("[bench] cpu oracle baseline")
         line["cpu_baseline"] = cpu_baseline(system, args.cpu_seconds)
