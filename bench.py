@@ -29,7 +29,9 @@ METRIC = "particle-timesteps/s (3D cubes) FP32-batched vs plain; p50/p99 replica
 # divide or reciprocal 1), per unit of work its counters report.
 FLOPS = {
     "pair": 60,        # relative rotation R_i^T R_j and offset R_i^T d (once per particle pair)
-    "vertex": 23,      # vertex carried into the other body's frame + reach test (nv_i + nv_j per pair)
+    "sep_vertex": 18,  # vertex carried into the other body's frame for the separation test (nv_i + nv_j per pair)
+    "plane_test": 6,   # one vertex against one supporting plane
+    "vertex": 23,      # vertex carried across again + reach test (nv_i + nv_j per pair not separated)
     "edge": 12,        # edge reach test (ne_i + ne_j per pair)
     "face": 12,        # face reach test (nf_i + nf_j per pair)
     "cull": 17,        # per-problem test: plane + bounding circle, or segment bounding spheres
@@ -78,9 +80,11 @@ def force_roofline(g, system, reps=200):
     st = g.force_stats(reset=True)
     mean_ms = g.time_forces(reps)
     shp = system.shapes[0]
-    per_pair = FLOPS["pair"] + 2 * (shp.nv * FLOPS["vertex"] + shp.ne * FLOPS["edge"] + shp.nf * FLOPS["face"])
-    flops = (st["pairs"] * per_pair + st["features"] * FLOPS["cull"] + st["vf_near"] * FLOPS["vf_solve"]
-             + st["ee_near"] * FLOPS["ee_solve"] + st["in_cutoff"] * FLOPS["wca"])
+    per_pair = FLOPS["pair"] + 2 * shp.nv * FLOPS["sep_vertex"]
+    per_feature_pair = 2 * (shp.nv * FLOPS["vertex"] + shp.ne * FLOPS["edge"] + shp.nf * FLOPS["face"])
+    flops = (st["pairs"] * per_pair + st["plane_tests"] * FLOPS["plane_test"]
+             + (st["pairs"] - st["separated"]) * per_feature_pair + st["features"] * FLOPS["cull"]
+             + st["vf_near"] * FLOPS["vf_solve"] + st["ee_near"] * FLOPS["ee_solve"] + st["in_cutoff"] * FLOPS["wca"])
     achieved = flops / (mean_ms * 1e-3)
     return dict(bound="alu", achieved=achieved / 1e12, peak=PEAK_FP32 / 1e12, unit="TFLOP/s",
                 frac=achieved / PEAK_FP32, traffic=None, kernel="k_pairs<float,3>",

@@ -184,12 +184,15 @@ dem_status dem_copy_lists(dem_handle h, int32_t *cell_start, int32_t *cell_parti
 dem_status dem_list_info(dem_handle h, double *r_list, int32_t *n_cells, int32_t *capacity);
 
 /* Work counters accumulated by counted force evaluations since the last
- * reset (out must hold 7 entries): out[0] unordered particle pairs within
+ * reset (out must hold 9 entries): out[0] unordered particle pairs within
  * R_i + R_j + r_cut, out[1] feature-pair problems of Eq. 1/2 left after the
  * per-pair feature prefilter, out[2] feature pairs inside the cutoff,
  * out[3] counted launches, out[4] vertex-face (2D: vertex-edge) problems
- * that pass the per-problem cull and are solved exactly, out[5] FP32 edge
- * pairs redone in FP64, out[6] edge-edge problems solved exactly.
+ * that pass the per-problem cull and are solved exactly, out[5] FP32
+ * feature pairs redone in FP64, out[6] edge-edge problems solved exactly,
+ * out[7] pairs of out[0] that a supporting plane of one body separates from
+ * the other by more than r_cut (no feature work), out[8] vertex-plane
+ * tests made for that separation test.
  * reset != 0 clears them after reading.  Synchronises. */
 dem_status dem_force_stats(dem_handle h, int64_t *out, int32_t reset);
 

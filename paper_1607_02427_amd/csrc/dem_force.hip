@@ -448,12 +448,37 @@ __device__ void stage_replica(const SysParams *reps, const ListPtrs &l, const Sh
     __syncthreads();
 }
 
+// A live pair that no supporting plane separates, parked in its wave's LDS
+// queue until the wave holds one for each of its groups.
+template <typename T>
+struct alignas(16) QEnt {
+    int4 ent;    // i, j, slot of j in row i, slot of i in row j (-1: none)
+    int si, sj, pad0, pad1;
+    T Rr[9];     // R_i^T R_j: j's body frame in i's
+    T t[3];      // R_i^T d: j's centre in i's frame
+    T Ri[9];     // R_i, body to space
+    T d[3];      // minimum-image x_j - x_i
+};
+constexpr int kQCap = 2 * kGroups;                              // queue slots per wave
+constexpr int kVP = (DEM_MAX_VERTS + kGL - 1) / kGL;            // vertices per lane
+
 // One block of 4 waves takes a contiguous range of tiles (16 pairs of one
 // replica each; wave w takes pairs 4w..4w+3 of a tile, 16 lanes per pair).
 // Blocks are dealt round-robin to the 8 XCDs, so block b runs on XCD b % 8:
 // XCD x gets the x-th eighth of the tiles, and pairs of neighbouring
 // particles share its L2.  The tables of the block's current replica live
 // in LDS and are restaged when its range crosses into the next replica.
+//
+// A pair passes two stages.  The first loads it and tests it against the
+// bound R_i + R_j + r_cut and against the supporting planes of both bodies:
+// when every vertex of one body lies more than r_cut beyond a supporting
+// plane of the other, the two inner bodies are farther apart than r_cut, no
+// feature pair of Eq. 1/2 is inside the cutoff, and the pair's record is
+// zero.  The other live pairs wait in the wave's LDS queue; whenever it
+// holds one for each group (or the range or the replica ends) the second
+// stage runs the feature prefilter, the per-problem cull and the exact
+// solves on them, so the costly stage runs on full waves.  A pair's result
+// does not depend on which group or round takes it.
 template <typename T, int DIM>
 __global__ void __launch_bounds__(64 * kWaves) k_pairs(BatchParams b, const SysParams *__restrict__ reps, StatePtrs s,
                                                           ListPtrs l, const PartRec<T> *__restrict__ prec,
@@ -467,11 +492,13 @@ __global__ void __launch_bounds__(64 * kWaves) k_pairs(BatchParams b, const SysP
     ShapeTab<T> *tab = reinterpret_cast<ShapeTab<T> *>(smem);
     RepLds &rl = *reinterpret_cast<RepLds *>(smem + orl);
     PairLds<T> *pls = reinterpret_cast<PairLds<T> *>(smem + orl + sizeof(RepLds));
+    QEnt<T> *qall = reinterpret_cast<QEnt<T> *>(smem + orl + sizeof(RepLds) + kWaves * kGroups * sizeof(PairLds<T>));
 
     const int lane = __lane_id();
     const int wid = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int grp = lane / kGL, sub = lane % kGL;
     PairLds<T> &W = pls[wid * kGroups + grp];
+    QEnt<T> *qb = qall + wid * kQCap;
     const unsigned long long gmask = ((kGL == 64) ? ~0ull : ((1ull << kGL) - 1)) << (kGL * grp);
     const unsigned long long below = lanes_below();
     const size_t N = (size_t)b.N;
@@ -480,7 +507,7 @@ __global__ void __launch_bounds__(64 * kWaves) k_pairs(BatchParams b, const SysP
     const int lb = (blockIdx.x & 7) * per + (blockIdx.x >> 3);
     const int t0 = (int)((long long)ntiles * lb / G), t1 = (int)((long long)ntiles * (lb + 1) / G);
     const T grow = T(1.00001);
-    unsigned long long c_pairs = 0, c_feat = 0, c_in = 0, c_near = 0, c_ee = 0, c_ref = 0;
+    unsigned c_pairs = 0, c_feat = 0, c_in = 0, c_near = 0, c_ee = 0, c_ref = 0, c_sep = 0, c_pv = 0;
 
     int r = 0, r_end = 0;
     if (t0 < t1) {  // replica of the first tile: the last r with tile_start[r] <= t0
@@ -494,18 +521,227 @@ __global__ void __launch_bounds__(64 * kWaves) k_pairs(BatchParams b, const SysP
         r_end = l.tile_start[r + 1];
         stage_replica(reps, l, gtab, tab, rl, r);
     }
-    for (int tt = t0; tt < t1; ++tt) {
-        if (tt >= r_end) {
+    int head = 0, tail = 0;  // queue positions, the same in every lane of the wave
+    int tt = t0;
+    for (;;) {
+        const bool done = tt >= t1;
+        const bool restage = !done && tt >= r_end;
+        const int pending = tail - head;
+        if (pending >= kGroups || (pending > 0 && (done || restage))) {
+            // ---- second stage: group g takes queue entry head + g ----
+            const int take = pending < kGroups ? pending : kGroups;
+            const bool live = grp < take;
+            int4 ent = make_int4(0, 0, 0, 0);
+            int si = 0, sj = 0;
+            M3<T> Rr, Ri;
+            V3<T> t = v3<T>(0, 0, 0), dv = v3<T>(0, 0, 0);
+            for (int k = 0; k < 9; ++k) Rr.m[k] = Ri.m[k] = T(0);
+            if (live) {
+                const QEnt<T> &e = qb[(head + grp) % kQCap];
+                ent = e.ent;
+                si = e.si;
+                sj = e.sj;
+                for (int k = 0; k < 9; ++k) {
+                    Rr.m[k] = e.Rr[k];
+                    Ri.m[k] = e.Ri[k];
+                }
+                t = v3<T>(e.t[0], e.t[1], e.t[2]);
+                dv = v3<T>(e.d[0], e.d[1], e.d[2]);
+            }
+            head += take;
+            const int i = ent.x, j = ent.y;
+            const ShapeTab<T> &Si = tab[si];
+            const ShapeTab<T> &Sj = tab[sj];
+            const T par_s2 = (T)rl.par_s2;
+            const T eps = (T)rl.eps;
+            T sig2 = T(0), rc = T(0), Bi = T(0), Bj = T(0);
+            if (live) {
+                const double sigd = rl.rad[si] + rl.rad[sj];
+                sig2 = (T)(sigd * sigd);
+                rc = (T)(kWcaCut * sigd);
+                Bi = (T)rl.R[si] + rc;
+                Bj = (T)rl.R[sj] + rc;
+            }
+            const T rc2 = rc * rc;
+            const T rcm = rc * T(1.0001);  // the cull keeps pairs FP32 may place just outside the cutoff
+
+            // Feature prefilter (conservative): a vertex, edge or face can touch
+            // the other body only if it lies within R_other + r_cut of that body's
+            // centre, widened by the edge half length or the face's bounding
+            // radius.  One lane per feature; survivors are listed by index.
+            int cvj = 0, cvi = 0;
+            for (int v0 = 0; v0 < DEM_MAX_VERTS; v0 += kGL) {
+                const int vk = v0 + sub;
+                bool nj = false, ni = false;
+                if (live && vk < Sj.nv) {
+                    const V3<T> v = t + mul(Rr, ld3(Sj.v[vk]));
+                    W.vj[vk][0] = v.x;
+                    W.vj[vk][1] = v.y;
+                    W.vj[vk][2] = v.z;
+                    nj = dot(v, v) < grow * Bi * Bi;
+                }
+                if (live && vk < Si.nv) {
+                    const V3<T> v = mulT(Rr, ld3(Si.v[vk]) - t);
+                    W.vi[vk][0] = v.x;
+                    W.vi[vk][1] = v.y;
+                    W.vi[vk][2] = v.z;
+                    ni = dot(v, v) < grow * Bj * Bj;
+                }
+                cvj = group_append(nj, W.vj_near, cvj, vk, gmask, below);
+                cvi = group_append(ni, W.vi_near, cvi, vk, gmask, below);
+                if (__ballot(live && (v0 + kGL < Si.nv || v0 + kGL < Sj.nv)) == 0) break;
+            }
+            wave_sync_lds();
+            int cei = 0, cej = 0;
+            for (int e0 = 0; e0 < DEM_MAX_EDGES; e0 += kGL) {
+                const int e = e0 + sub;
+                bool ne = false, me = false;
+                if (live && e < Si.ne) {
+                    const V3<T> d = ld3(Si.em[e]) - t;
+                    const T lim = Bj + Si.eh[e];
+                    ne = dot(d, d) < grow * lim * lim;
+                }
+                if (live && e < Sj.ne) {
+                    const V3<T> m = T(0.5) * (ld3(W.vj[Sj.e[e][0]]) + ld3(W.vj[Sj.e[e][1]]));
+                    const T lim = Bi + Sj.eh[e];
+                    me = dot(m, m) < grow * lim * lim;
+                }
+                cei = group_append(ne, W.ei_near, cei, e, gmask, below);
+                cej = group_append(me, W.ej_near, cej, e, gmask, below);
+                if (__ballot(live && (e0 + kGL < Si.ne || e0 + kGL < Sj.ne)) == 0) break;
+            }
+            int cfi = 0, cfj = 0;
+            if (DIM == 3) {
+                const V3<T> ti = -(T)1 * mulT(Rr, t);  // i's centre in j's frame
+                for (int f0 = 0; f0 < DEM_MAX_FACES; f0 += kGL) {
+                    const int f = f0 + sub;
+                    bool nf = false, mf = false;
+                    if (live && f < Si.nf) {
+                        const V3<T> d = ld3(Si.fc[f]) - t;
+                        const T lim = Bj + Si.frad[f];
+                        nf = dot(d, d) < grow * lim * lim;
+                    }
+                    if (live && f < Sj.nf) {
+                        const V3<T> d = ld3(Sj.fc[f]) - ti;
+                        const T lim = Bi + Sj.frad[f];
+                        mf = dot(d, d) < grow * lim * lim;
+                    }
+                    cfi = group_append(nf, W.fi_near, cfi, f, gmask, below);
+                    cfj = group_append(mf, W.fj_near, cfj, f, gmask, below);
+                    if (__ballot(live && (f0 + kGL < Si.nf || f0 + kGL < Sj.nf)) == 0) break;
+                }
+            }
+            wave_sync_lds();
+
+            Problem<T, DIM> P{Si, Sj, W, Rr, t, 0, 0, 1, 1, 1, 1.f, 1.f, 1.f};
+            int total;
+            if (DIM == 3) {
+                P.nA = cvi * cfj;
+                P.nB = cvj * cfi;
+                total = P.nA + P.nB + cei * cej;
+                P.nfj = cfj;
+                P.nfi = cfi;
+            } else {
+                P.nA = cvi * cej;
+                P.nB = cvj * cei;
+                total = P.nA + P.nB;
+                P.nfj = cej;
+                P.nfi = cei;
+            }
+            P.nej = cej;
+            P.inv_fj = 1.0f / (float)(P.nfj > 0 ? P.nfj : 1);
+            P.inv_fi = 1.0f / (float)(P.nfi > 0 ? P.nfi : 1);
+            P.inv_ej = 1.0f / (float)(P.nej > 0 ? P.nej : 1);
+            if (!live) total = 0;
+            if (sub == 0 && live) c_feat += total;
+
+            Acc<T> A;
+            A.F = A.Ti = A.Tj = v3<T>(0, 0, 0);
+            A.U = T(0);
+            int count = 0;
+            for (int qb = 0;; qb += kGL) {
+                const int q = qb + sub;
+                const bool has = q < total;
+                const bool last = __ballot(has) == 0;
+                if (!last) {
+                    const bool keep = has && P.candidate(q, rcm);
+                    const unsigned long long m = __ballot(keep);
+                    if (keep) W.queue[count + __popcll(m & below & gmask)] = (unsigned short)q;
+                    count += __popcll(m & gmask);
+                }
+                if (last || __ballot(count > kQueue - kGL) != 0) {
+                    wave_sync_lds();
+                    for (int k = sub;; k += kGL) {
+                        const bool w = k < count;
+                        if (__ballot(w) == 0) break;
+                        if (w) {
+                            V3<T> Pt, rho;
+                            T sin2;
+                            int e, g;
+                            const int fam = P.solve(W.queue[k], par_s2, Pt, rho, sin2, e, g);
+                            c_near += fam < 2 ? 1 : 0;
+                            c_ee += fam == 2 ? 1 : 0;
+                            const T r2 = dot(rho, rho);
+                            const bool redo = sizeof(T) == 4 &&
+                                              ((r2 > T(0.99) * rc2 && r2 < T(1.0001) * rc2) ||
+                                               (DIM == 3 && fam == 2 && sin2 < T(1e-2) && r2 < T(1.0001) * rc2 + T(1e-3) * rc));
+                            if (redo) {
+                                c_ref += 1;
+                                c_in += refine_pair<T, DIM>(rl.box, rl.eps, rl.par_s2, rec64[i], rec64[j],
+                                                            gtab64[rl.sbase + si], gtab64[rl.sbase + sj], fam, e, g, rl.rad[si] + rl.rad[sj], A);
+                            } else {
+                                c_in += add_wca(A, Pt, rho, t, sig2, rc2, eps);
+                            }
+                        }
+                    }
+                    count = 0;
+                    wave_sync_lds();
+                }
+                if (last) break;
+            }
+            // group reduction (every lane of the group gets the sums); rotate to
+            // the space frame and write both row slots, one component per lane
+            const T F0 = group_sum(A.F.x), F1 = group_sum(A.F.y), F2 = group_sum(A.F.z);
+            const T I0 = group_sum(A.Ti.x), I1 = group_sum(A.Ti.y), I2 = group_sum(A.Ti.z);
+            const T J0 = group_sum(A.Tj.x), J1 = group_sum(A.Tj.y), J2 = group_sum(A.Tj.z);
+            const T U = group_sum(A.U);
+            if (live) {
+                const V3<T> Fs = mul(Ri, v3<T>(F0, F1, F2));
+                const V3<T> Is = mul(Ri, v3<T>(I0, I1, I2));
+                const V3<T> Js = mul(Ri, v3<T>(J0, J1, J2));
+                for (int c = sub; c < kRec; c += kGL) {
+                    T vi, vj;  // component c of the records in i's slot and in j's slot
+                    if (c < 3) {
+                        vi = c == 0 ? Fs.x : (c == 1 ? Fs.y : Fs.z);
+                        vj = -vi;
+                    } else if (c < 6) {
+                        vi = c == 3 ? Is.x : (c == 4 ? Is.y : Is.z);
+                        vj = c == 3 ? Js.x : (c == 4 ? Js.y : Js.z);
+                    } else if (c == 6) {
+                        vi = U;
+                        vj = U;
+                    } else {
+                        vi = c == 7 ? dv.x : (c == 8 ? dv.y : dv.z);
+                        vj = -vi;
+                    }
+                    const size_t cs = (size_t)c * b.cap * N;
+                    rec[cs + (size_t)ent.z * N + i] = vi;
+                    if (ent.w >= 0) rec[cs + (size_t)ent.w * N + j] = vj;
+                }
+            }
+            continue;
+        }
+        if (done) break;
+        if (restage) {
             do {
                 ++r;
                 r_end = l.tile_start[r + 1];
             } while (tt >= r_end);
             stage_replica(reps, l, gtab, tab, rl, r);
         }
+        // ---- first stage on tile tt ----
         const int q = (tt - rl.first_tile) * kTile + wid * kGroups + grp;
         const bool active = q < rl.np;
-        const T par_s2 = (T)rl.par_s2;
-        const T eps = (T)rl.eps;
         // two dependent round trips: the pair entry, then both particle
         // records (position, rotation and shape in one line each)
         int4 ent = make_int4(0, 0, 0, 0);
@@ -530,221 +766,110 @@ __global__ void __launch_bounds__(64 * kWaves) k_pairs(BatchParams b, const SysP
             sj = rj.sid;
             const double bound = rl.R[si] + rl.R[sj] + kWcaCut * (rl.rad[si] + rl.rad[sj]);
             live = dx * dx + dy * dy + dz * dz < bound * bound;
-            if (!live)  // zero both row slots of a pair out of reach
-                for (int c = sub; c < kRec; c += kGL) {
-                    const size_t cs = (size_t)c * b.cap * N;
-                    rec[cs + (size_t)ent.z * N + i] = T(0);
-                    if (ent.w >= 0) rec[cs + (size_t)ent.w * N + j] = T(0);
-                }
         }
-        if (__ballot(live) == 0) continue;
-        const ShapeTab<T> &Si = tab[si];
-        const ShapeTab<T> &Sj = tab[sj];
-        M3<T> Rr;
-        V3<T> t = v3<T>(0, 0, 0);
-        T sig2 = T(0), rc = T(0), Bi = T(0), Bj = T(0);
-        for (int k = 0; k < 9; ++k) Rr.m[k] = T(0);
-        if (live) {
-            for (int a = 0; a < 3; ++a)
-                for (int c = 0; c < 3; ++c)
-                    Rr.m[3 * a + c] = Ri.m[a] * Rj.m[c] + Ri.m[3 + a] * Rj.m[3 + c] + Ri.m[6 + a] * Rj.m[6 + c];
-            t = mulT(Ri, v3<T>((T)dx, (T)dy, (T)dz));
-            const double sigd = rl.rad[si] + rl.rad[sj];
-            sig2 = (T)(sigd * sigd);
-            rc = (T)(kWcaCut * sigd);
-            Bi = (T)rl.R[si] + rc;
-            Bj = (T)rl.R[sj] + rc;
-        }
-        const T rc2 = rc * rc;
-        const T rcm = rc * T(1.0001);  // the cull keeps pairs FP32 may place just outside the cutoff
-
-        // Feature prefilter (conservative): a vertex, edge or face can touch
-        // the other body only if it lies within R_other + r_cut of that body's
-        // centre, widened by the edge half length or the face's bounding
-        // radius.  One lane per feature; survivors are listed by index.
-        int cvj = 0, cvi = 0;
-        for (int v0 = 0; v0 < DEM_MAX_VERTS; v0 += kGL) {
-            const int vk = v0 + sub;
-            bool nj = false, ni = false;
-            if (live && vk < Sj.nv) {
-                const V3<T> v = t + mul(Rr, ld3(Sj.v[vk]));
-                W.vj[vk][0] = v.x;
-                W.vj[vk][1] = v.y;
-                W.vj[vk][2] = v.z;
-                nj = dot(v, v) < grow * Bi * Bi;
+        bool need = false;
+        if (__ballot(live) != 0) {
+            const ShapeTab<T> &Si = tab[si];
+            const ShapeTab<T> &Sj = tab[sj];
+            M3<T> Rr;
+            V3<T> t = v3<T>(0, 0, 0);
+            T rc = T(0), Bi = T(0), Bj = T(0);
+            for (int k = 0; k < 9; ++k) Rr.m[k] = T(0);
+            if (live) {
+                for (int a = 0; a < 3; ++a)
+                    for (int c = 0; c < 3; ++c)
+                        Rr.m[3 * a + c] = Ri.m[a] * Rj.m[c] + Ri.m[3 + a] * Rj.m[3 + c] + Ri.m[6 + a] * Rj.m[6 + c];
+                t = mulT(Ri, v3<T>((T)dx, (T)dy, (T)dz));
+                rc = (T)(kWcaCut * (rl.rad[si] + rl.rad[sj]));
+                Bi = (T)rl.R[si] + rc;
+                Bj = (T)rl.R[sj] + rc;
             }
-            if (live && vk < Si.nv) {
-                const V3<T> v = mulT(Rr, ld3(Si.v[vk]) - t);
-                W.vi[vk][0] = v.x;
-                W.vi[vk][1] = v.y;
-                W.vi[vk][2] = v.z;
-                ni = dot(v, v) < grow * Bj * Bj;
+            // separation beyond which no feature pair can be inside the
+            // cutoff, with room for the rounding of the transformed vertices
+            const T thr = rc * T(1.0001) + T(1e-5) * (Bi + Bj);
+            V3<T> wj[kVP], wi[kVP];  // this lane's vertices: j's in i's frame, i's in j's frame
+            bool hj[kVP], hi[kVP];
+#pragma unroll
+            for (int p = 0; p < kVP; ++p) {
+                const int k = p * kGL + sub;
+                hj[p] = live && k < Sj.nv;
+                hi[p] = live && k < Si.nv;
+                wj[p] = wi[p] = v3<T>(0, 0, 0);
+                if (hj[p]) wj[p] = t + mul(Rr, ld3(Sj.v[k]));
+                if (hi[p]) wi[p] = mulT(Rr, ld3(Si.v[k]) - t);
             }
-            cvj = group_append(nj, W.vj_near, cvj, vk, gmask, below);
-            cvi = group_append(ni, W.vi_near, cvi, vk, gmask, below);
-            if (__ballot(live && (v0 + kGL < Si.nv || v0 + kGL < Sj.nv)) == 0) break;
-        }
-        wave_sync_lds();
-        int cei = 0, cej = 0;
-        for (int e0 = 0; e0 < DEM_MAX_EDGES; e0 += kGL) {
-            const int e = e0 + sub;
-            bool ne = false, me = false;
-            if (live && e < Si.ne) {
-                const V3<T> d = ld3(Si.em[e]) - t;
-                const T lim = Bj + Si.eh[e];
-                ne = dot(d, d) < grow * lim * lim;
-            }
-            if (live && e < Sj.ne) {
-                const V3<T> m = T(0.5) * (ld3(W.vj[Sj.e[e][0]]) + ld3(W.vj[Sj.e[e][1]]));
-                const T lim = Bi + Sj.eh[e];
-                me = dot(m, m) < grow * lim * lim;
-            }
-            cei = group_append(ne, W.ei_near, cei, e, gmask, below);
-            cej = group_append(me, W.ej_near, cej, e, gmask, below);
-            if (__ballot(live && (e0 + kGL < Si.ne || e0 + kGL < Sj.ne)) == 0) break;
-        }
-        int cfi = 0, cfj = 0;
-        if (DIM == 3) {
-            const V3<T> ti = -(T)1 * mulT(Rr, t);  // i's centre in j's frame
-            for (int f0 = 0; f0 < DEM_MAX_FACES; f0 += kGL) {
-                const int f = f0 + sub;
-                bool nf = false, mf = false;
-                if (live && f < Si.nf) {
-                    const V3<T> d = ld3(Si.fc[f]) - t;
-                    const T lim = Bj + Si.frad[f];
-                    nf = dot(d, d) < grow * lim * lim;
-                }
-                if (live && f < Sj.nf) {
-                    const V3<T> d = ld3(Sj.fc[f]) - ti;
-                    const T lim = Bi + Sj.frad[f];
-                    mf = dot(d, d) < grow * lim * lim;
-                }
-                cfi = group_append(nf, W.fi_near, cfi, f, gmask, below);
-                cfj = group_append(mf, W.fj_near, cfj, f, gmask, below);
-                if (__ballot(live && (f0 + kGL < Si.nf || f0 + kGL < Sj.nf)) == 0) break;
-            }
-        }
-        wave_sync_lds();
-
-        Problem<T, DIM> P{Si, Sj, W, Rr, t, 0, 0, 1, 1, 1, 1.f, 1.f, 1.f};
-        int total;
-        if (DIM == 3) {
-            P.nA = cvi * cfj;
-            P.nB = cvj * cfi;
-            total = P.nA + P.nB + cei * cej;
-            P.nfj = cfj;
-            P.nfi = cfi;
-        } else {
-            P.nA = cvi * cej;
-            P.nB = cvj * cei;
-            total = P.nA + P.nB;
-            P.nfj = cej;
-            P.nfi = cei;
-        }
-        P.nej = cej;
-        P.inv_fj = 1.0f / (float)(P.nfj > 0 ? P.nfj : 1);
-        P.inv_fi = 1.0f / (float)(P.nfi > 0 ? P.nfi : 1);
-        P.inv_ej = 1.0f / (float)(P.nej > 0 ? P.nej : 1);
-        if (!live) total = 0;
-        if (sub == 0 && live) {
-            c_pairs += 1;
-            c_feat += total;
-        }
-
-        Acc<T> A;
-        A.F = A.Ti = A.Tj = v3<T>(0, 0, 0);
-        A.U = T(0);
-        int count = 0;
-        for (int qb = 0;; qb += kGL) {
-            const int q = qb + sub;
-            const bool has = q < total;
-            const bool last = __ballot(has) == 0;
-            if (!last) {
-                const bool keep = has && P.candidate(q, rcm);
-                const unsigned long long m = __ballot(keep);
-                if (keep) W.queue[count + __popcll(m & below & gmask)] = (unsigned short)q;
-                count += __popcll(m & gmask);
-            }
-            if (last || __ballot(count > kQueue - kGL) != 0) {
-                wave_sync_lds();
-                for (int k = sub;; k += kGL) {
-                    const bool w = k < count;
-                    if (__ballot(w) == 0) break;
-                    if (w) {
-                        V3<T> Pt, rho;
-                        T sin2;
-                        int e, g;
-                        const int fam = P.solve(W.queue[k], par_s2, Pt, rho, sin2, e, g);
-                        c_near += fam < 2 ? 1 : 0;
-                        c_ee += fam == 2 ? 1 : 0;
-                        const T r2 = dot(rho, rho);
-                        const bool redo = sizeof(T) == 4 &&
-                                          ((r2 > T(0.99) * rc2 && r2 < T(1.0001) * rc2) ||
-                                           (DIM == 3 && fam == 2 && sin2 < T(1e-2) && r2 < T(1.0001) * rc2 + T(1e-3) * rc));
-                        if (redo) {
-                            c_ref += 1;
-                            c_in += refine_pair<T, DIM>(rl.box, rl.eps, rl.par_s2, rec64[i], rec64[j],
-                                                        gtab64[rl.sbase + si], gtab64[rl.sbase + sj], fam, e, g, rl.rad[si] + rl.rad[sj], A);
-                        } else {
-                            c_in += add_wca(A, Pt, rho, t, sig2, rc2, eps);
+            bool sep = false;
+            const int npl = live ? (Si.nsep > Sj.nsep ? Si.nsep : Sj.nsep) : 0;
+            for (int p = 0; __ballot(!sep && p < npl) != 0; ++p) {
+                const bool ti = !sep && p < Si.nsep, tj = !sep && p < Sj.nsep;
+                bool bi = true, bj = true;  // every vertex of this lane beyond plane p
+                if (ti) {
+                    const V3<T> n = ld3(Si.sn[p]);
+                    const T o = Si.so[p];
+#pragma unroll
+                    for (int v = 0; v < kVP; ++v)
+                        if (hj[v]) {
+                            bi = bi && dot(n, wj[v]) - o > thr;
+                            ++c_pv;
                         }
-                    }
                 }
-                count = 0;
-                wave_sync_lds();
+                if (tj) {
+                    const V3<T> n = ld3(Sj.sn[p]);
+                    const T o = Sj.so[p];
+#pragma unroll
+                    for (int v = 0; v < kVP; ++v)
+                        if (hi[v]) {
+                            bj = bj && dot(n, wi[v]) - o > thr;
+                            ++c_pv;
+                        }
+                }
+                const unsigned long long mi = __ballot(bi), mj = __ballot(bj);
+                sep = sep || (ti && (mi & gmask) == gmask) || (tj && (mj & gmask) == gmask);
             }
-            if (last) break;
+            need = live && !sep;
+            if (sub == 0 && live) {
+                c_pairs += 1;
+                c_sep += sep ? 1 : 0;
+            }
+            // queue the pairs that need the feature stage, one entry per group
+            const unsigned long long m = __ballot(need && sub == 0);
+            if (need && sub == 0) {
+                QEnt<T> &e = qb[(tail + __popcll(m & below)) % kQCap];
+                e.ent = ent;
+                e.si = si;
+                e.sj = sj;
+                for (int k = 0; k < 9; ++k) {
+                    e.Rr[k] = Rr.m[k];
+                    e.Ri[k] = Ri.m[k];
+                }
+                e.t[0] = t.x;
+                e.t[1] = t.y;
+                e.t[2] = t.z;
+                e.d[0] = (T)dx;
+                e.d[1] = (T)dy;
+                e.d[2] = (T)dz;
+            }
+            tail += __popcll(m);
         }
-        // group reduction (every lane of the group gets the sums); rotate to
-        // the space frame and write both row slots, one component per lane
-        const T F0 = group_sum(A.F.x), F1 = group_sum(A.F.y), F2 = group_sum(A.F.z);
-        const T I0 = group_sum(A.Ti.x), I1 = group_sum(A.Ti.y), I2 = group_sum(A.Ti.z);
-        const T J0 = group_sum(A.Tj.x), J1 = group_sum(A.Tj.y), J2 = group_sum(A.Tj.z);
-        const T U = group_sum(A.U);
-        if (live) {
-            const V3<T> Fs = mul(Ri, v3<T>(F0, F1, F2));
-            const V3<T> Is = mul(Ri, v3<T>(I0, I1, I2));
-            const V3<T> Js = mul(Ri, v3<T>(J0, J1, J2));
+        if (active && !need)  // out of reach or separated: zero both row slots
             for (int c = sub; c < kRec; c += kGL) {
-                T vi, vj;  // component c of the records in i's slot and in j's slot
-                if (c < 3) {
-                    vi = c == 0 ? Fs.x : (c == 1 ? Fs.y : Fs.z);
-                    vj = -vi;
-                } else if (c < 6) {
-                    vi = c == 3 ? Is.x : (c == 4 ? Is.y : Is.z);
-                    vj = c == 3 ? Js.x : (c == 4 ? Js.y : Js.z);
-                } else if (c == 6) {
-                    vi = U;
-                    vj = U;
-                } else {
-                    vi = (T)(c == 7 ? dx : (c == 8 ? dy : dz));
-                    vj = -vi;
-                }
                 const size_t cs = (size_t)c * b.cap * N;
-                rec[cs + (size_t)ent.z * N + i] = vi;
-                if (ent.w >= 0) rec[cs + (size_t)ent.w * N + j] = vj;
+                rec[cs + (size_t)ent.z * N + i] = T(0);
+                if (ent.w >= 0) rec[cs + (size_t)ent.w * N + j] = T(0);
             }
-        }
+        wave_sync_lds();  // the queue entries are visible to every lane
+        ++tt;
     }
     if (stats) {
-        unsigned long long in_w = c_in, near_w = c_near, ee_w = c_ee, ref_w = c_ref, pr_w = c_pairs, ft_w = c_feat;
-        for (int off = 32; off > 0; off >>= 1) {
-            in_w += __shfl_xor(in_w, off, 64);
-            near_w += __shfl_xor(near_w, off, 64);
-            ee_w += __shfl_xor(ee_w, off, 64);
-            ref_w += __shfl_xor(ref_w, off, 64);
-            pr_w += __shfl_xor(pr_w, off, 64);
-            ft_w += __shfl_xor(ft_w, off, 64);
+        const unsigned cnt[8] = {c_pairs, c_feat, c_in, c_near, c_ref, c_ee, c_sep, c_pv};
+        const int slot[8] = {ST_PAIRS, ST_FEATURES, ST_INCUT, ST_NEAR, ST_REFINED, ST_EENEAR, ST_SEPARATED, ST_PLANETESTS};
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            unsigned long long w = cnt[k];
+            for (int off = 32; off > 0; off >>= 1) w += __shfl_xor(w, off, 64);
+            if (lane == 0) atomicAdd(&stats[slot[k]], w);
         }
-        if (lane == 0) {
-            atomicAdd(&stats[ST_PAIRS], pr_w);
-            atomicAdd(&stats[ST_FEATURES], ft_w);
-            atomicAdd(&stats[ST_INCUT], in_w);
-            atomicAdd(&stats[ST_NEAR], near_w);
-            atomicAdd(&stats[ST_REFINED], ref_w);
-            atomicAdd(&stats[ST_EENEAR], ee_w);
-            if (blockIdx.x == 0 && wid == 0) atomicAdd(&stats[ST_LAUNCHES], 1ull);
-        }
+        if (lane == 0 && blockIdx.x == 0 && wid == 0) atomicAdd(&stats[ST_LAUNCHES], 1ull);
     }
 }
 
@@ -1018,7 +1143,8 @@ size_t pair_kernel_lds(int precision, int tab_slots)
 {
     const size_t w = precision == DEM_FP32 ? sizeof(ShapeTab<float>) : sizeof(ShapeTab<double>);
     const size_t pl = precision == DEM_FP32 ? sizeof(PairLds<float>) : sizeof(PairLds<double>);
-    return (size_t)tab_slots * w + sizeof(RepLds) + kWaves * kGroups * pl;
+    const size_t qe = precision == DEM_FP32 ? sizeof(QEnt<float>) : sizeof(QEnt<double>);
+    return (size_t)tab_slots * w + sizeof(RepLds) + kWaves * kGroups * pl + kWaves * kQCap * qe;
 }
 
 int pair_blocks_resident(int precision, int dim, int tab_slots)

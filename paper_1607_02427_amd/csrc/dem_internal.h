@@ -50,7 +50,8 @@ constexpr int kRowMax = 128;
 enum Thermo { TH_XI = 0, TH_ETA = 1, TH_SB = 2, TH_SA = 3, TH_XI_B = 4, TH_ETA_B = 5, TH_OPEN = 6, TH_COUNT = 8 };
 // Force work counters (unsigned long long).
 enum Stat {
-    ST_PAIRS = 0, ST_FEATURES = 1, ST_INCUT = 2, ST_LAUNCHES = 3, ST_NEAR = 4, ST_REFINED = 5, ST_EENEAR = 6, ST_COUNT = 7
+    ST_PAIRS = 0, ST_FEATURES = 1, ST_INCUT = 2, ST_LAUNCHES = 3, ST_NEAR = 4, ST_REFINED = 5, ST_EENEAR = 6,
+    ST_SEPARATED = 7, ST_PLANETESTS = 8, ST_COUNT = 9
 };
 
 // Words of one row-slot record, stored component-major rec[c][k][i] for
@@ -65,6 +66,11 @@ constexpr int kRec = 10;
 // bounding circle (centroid, radius), the in-plane inward normal and offset
 // of each loop edge (convex inside test), face coordinates of each loop
 // vertex (crossing-number test for concave faces) and 1/|loop edge|^2.
+// The supporting planes (3D: the face planes with the whole body on their
+// inner side; 2D: such edge lines) carry unit normal sn and offset so =
+// max over vertices of sn.v, so every point of the inner body satisfies
+// sn.x <= so.
+constexpr int kMaxSep = DEM_MAX_EDGES > DEM_MAX_FACES ? DEM_MAX_EDGES : DEM_MAX_FACES;
 template <typename T>
 struct alignas(16) ShapeTab {
     int nv, ne, nf, pad0;
@@ -88,6 +94,9 @@ struct alignas(16) ShapeTab {
     T loff[DEM_MAX_LOOP];        // lnrm . b_k
     T linv[DEM_MAX_LOOP];        // 1 / |b_{k+1} - b_k|^2
     T lxy[DEM_MAX_LOOP][2];      // face coordinates of loop vertex k
+    int nsep, pad3[3];
+    T sn[kMaxSep][3];            // supporting-plane normals
+    T so[kMaxSep];               // and offsets
 };
 
 // One replica: a periodic system of its own.  A single system is a batch

@@ -162,6 +162,48 @@ inline HostVec hsub(HostVec a, HostVec b) { return {a.x - b.x, a.y - b.y, a.z - 
 inline HostVec hcross(HostVec a, HostVec b) { return {a.y * b.z - a.z * b.y, a.z * b.x - a.x * b.z, a.x * b.y - a.y * b.x}; }
 inline double hdot(HostVec a, HostVec b) { return a.x * b.x + a.y * b.y + a.z * b.z; }
 
+// Supporting planes of the inner body (the vertices' convex hull lies on
+// their inner side): in 3D every face plane that has no vertex beyond it
+// (all of them for a convex body), in 2D every edge line with all vertices
+// on one side, its normal pointing away from them.  The offset is the exact
+// support value max_k n.v_k, so a point farther than r_cut beyond such a
+// plane is farther than r_cut from every feature of the body.
+void support_planes(ShapeTab<double> &T, int dim)
+{
+    T.nsep = 0;
+    const double tol = 1e-9 * (1.0 + T.R);
+    auto support = [&](HostVec n) {
+        double hi = -1e300;
+        for (int k = 0; k < T.nv; ++k) hi = std::max(hi, hdot(n, HostVec{T.v[k][0], T.v[k][1], T.v[k][2]}));
+        return hi;
+    };
+    auto add = [&](HostVec n, double o) {
+        if (T.nsep >= kMaxSep) return;
+        T.sn[T.nsep][0] = n.x;
+        T.sn[T.nsep][1] = n.y;
+        T.sn[T.nsep][2] = n.z;
+        T.so[T.nsep] = o;
+        ++T.nsep;
+    };
+    if (dim == 3) {
+        for (int f = 0; f < T.nf; ++f) {
+            const HostVec n{T.fn[f][0], T.fn[f][1], T.fn[f][2]};
+            const double hi = support(n);
+            if (hi <= T.fo[f] + tol) add(n, hi);
+        }
+    } else {
+        for (int k = 0; k < T.ne; ++k) {
+            const double l = std::sqrt(T.el2[k]);
+            const HostVec n{T.ed[k][1] / l, -T.ed[k][0] / l, 0.0};
+            const HostVec a{T.v[T.e[k][0]][0], T.v[T.e[k][0]][1], 0.0};
+            const double o = hdot(n, a);
+            const double hi = support(n), lo = -support(HostVec{-n.x, -n.y, 0.0});
+            if (hi <= o + tol) add(n, hi);
+            else if (lo >= o - tol) add(HostVec{-n.x, -n.y, 0.0}, -lo);
+        }
+    }
+}
+
 // Validates one shape and fills the FP64 table.
 dem_status build_table(dem_system *h, int idx, const dem_shape_desc &d, int dim, ShapeTab<double> &T)
 {
@@ -295,6 +337,7 @@ dem_status build_table(dem_system *h, int idx, const dem_shape_desc &d, int dim,
         if (!(vol6 > 0.0))
             return fail(h, DEM_E_SHAPE, "shape %d: face loops are not counter-clockwise seen from outside", idx);
     }
+    support_planes(T, dim);
     return DEM_OK;
 }
 
@@ -337,6 +380,13 @@ void to_float(const ShapeTab<double> &D, ShapeTab<float> &F)
         F.linv[k] = (float)D.linv[k];
         F.lxy[k][0] = (float)D.lxy[k][0];
         F.lxy[k][1] = (float)D.lxy[k][1];
+    }
+    F.nsep = D.nsep;
+    for (int k = 0; k < kMaxSep; ++k) {
+        for (int a = 0; a < 3; ++a) F.sn[k][a] = (float)D.sn[k][a];
+        float o = (float)D.so[k];  // rounded up, so the FP32 plane still bounds the body
+        if ((double)o < D.so[k]) o = std::nextafter(o, 3.0e38f);
+        F.so[k] = o;
     }
 }
 

@@ -325,10 +325,10 @@ class DemSystem:
         return out
 
     def force_stats(self, reset: bool = False):
-        out = (C.c_int64 * 7)()
+        out = (C.c_int64 * 9)()
         self._check(lib().dem_force_stats(self.h, out, 1 if reset else 0), "dem_force_stats")
         return dict(pairs=out[0], features=out[1], in_cutoff=out[2], launches=out[3], vf_near=out[4],
-                    refined=out[5], ee_near=out[6])
+                    refined=out[5], ee_near=out[6], separated=out[7], plane_tests=out[8])
 
     def time_forces(self, reps: int = 100) -> float:
         """Mean duration (ms) of one force-kernel launch, HIP events on the system's stream."""
@@ -467,10 +467,10 @@ class DemBatch:
         return _state_np(t, system), _outputs_np(o, n)
 
     def force_stats(self, reset: bool = False):
-        out = (C.c_int64 * 7)()
+        out = (C.c_int64 * 9)()
         self._check(lib().dem_force_stats(self.h, out, 1 if reset else 0), "dem_force_stats")
         return dict(pairs=out[0], features=out[1], in_cutoff=out[2], launches=out[3], vf_near=out[4],
-                    refined=out[5], ee_near=out[6])
+                    refined=out[5], ee_near=out[6], separated=out[7], plane_tests=out[8])
 
     def set_counting(self, on: bool):
         self._check(lib().dem_set_counting(self.h, 1 if on else 0), "dem_set_counting")
