@@ -483,7 +483,7 @@ template <typename T, int DIM>
 __global__ void __launch_bounds__(64 * kWaves) k_pairs(BatchParams b, const SysParams *__restrict__ reps, StatePtrs s,
                                                           ListPtrs l, const PartRec<T> *__restrict__ prec,
                                                           const PartRec64 *__restrict__ rec64,
-                                                          T *__restrict__ rec, const ShapeTab<T> *__restrict__ gtab,
+                                                          SlotRec<T> *__restrict__ rec, const ShapeTab<T> *__restrict__ gtab,
                                                           const ShapeTab<double> *__restrict__ gtab64,
                                                           unsigned long long *stats)
 {
@@ -700,33 +700,31 @@ __global__ void __launch_bounds__(64 * kWaves) k_pairs(BatchParams b, const SysP
                 if (last) break;
             }
             // group reduction (every lane of the group gets the sums); rotate to
-            // the space frame and write both row slots, one component per lane
+            // the space frame and write both row slots, one record per lane
             const T F0 = group_sum(A.F.x), F1 = group_sum(A.F.y), F2 = group_sum(A.F.z);
             const T I0 = group_sum(A.Ti.x), I1 = group_sum(A.Ti.y), I2 = group_sum(A.Ti.z);
             const T J0 = group_sum(A.Tj.x), J1 = group_sum(A.Tj.y), J2 = group_sum(A.Tj.z);
             const T U = group_sum(A.U);
-            if (live) {
+            if (live && sub < 2) {  // lane 0 writes i's slot, lane 1 j's
                 const V3<T> Fs = mul(Ri, v3<T>(F0, F1, F2));
-                const V3<T> Is = mul(Ri, v3<T>(I0, I1, I2));
-                const V3<T> Js = mul(Ri, v3<T>(J0, J1, J2));
-                for (int c = sub; c < kRec; c += kGL) {
-                    T vi, vj;  // component c of the records in i's slot and in j's slot
-                    if (c < 3) {
-                        vi = c == 0 ? Fs.x : (c == 1 ? Fs.y : Fs.z);
-                        vj = -vi;
-                    } else if (c < 6) {
-                        vi = c == 3 ? Is.x : (c == 4 ? Is.y : Is.z);
-                        vj = c == 3 ? Js.x : (c == 4 ? Js.y : Js.z);
-                    } else if (c == 6) {
-                        vi = U;
-                        vj = U;
-                    } else {
-                        vi = c == 7 ? dv.x : (c == 8 ? dv.y : dv.z);
-                        vj = -vi;
-                    }
-                    const size_t cs = (size_t)c * b.cap * N;
-                    rec[cs + (size_t)ent.z * N + i] = vi;
-                    if (ent.w >= 0) rec[cs + (size_t)ent.w * N + j] = vj;
+                const bool js = sub == 1;
+                const V3<T> Ts = mul(Ri, js ? v3<T>(J0, J1, J2) : v3<T>(I0, I1, I2));
+                const T sg = js ? T(-1) : T(1);
+                const int slot = js ? ent.w : ent.z;
+                if (slot >= 0) {
+                    SlotRec<T> w;
+                    w.F[0] = sg * Fs.x;
+                    w.F[1] = sg * Fs.y;
+                    w.F[2] = sg * Fs.z;
+                    w.U = U;
+                    w.tq[0] = Ts.x;
+                    w.tq[1] = Ts.y;
+                    w.tq[2] = Ts.z;
+                    w.d[0] = sg * dv.x;
+                    w.d[1] = sg * dv.y;
+                    w.d[2] = sg * dv.z;
+                    w.pad0 = w.pad1 = T(0);
+                    rec[(size_t)slot * N + (js ? j : i)] = w;
                 }
             }
             continue;
@@ -851,12 +849,16 @@ __global__ void __launch_bounds__(64 * kWaves) k_pairs(BatchParams b, const SysP
             }
             tail += __popcll(m);
         }
-        if (active && !need)  // out of reach or separated: zero both row slots
-            for (int c = sub; c < kRec; c += kGL) {
-                const size_t cs = (size_t)c * b.cap * N;
-                rec[cs + (size_t)ent.z * N + i] = T(0);
-                if (ent.w >= 0) rec[cs + (size_t)ent.w * N + j] = T(0);
+        if (active && !need && sub < 2) {  // out of reach or separated: zero both row slots
+            const int slot = sub == 1 ? ent.w : ent.z;
+            if (slot >= 0) {
+                SlotRec<T> w;
+                w.F[0] = w.F[1] = w.F[2] = w.U = T(0);
+                w.tq[0] = w.tq[1] = w.tq[2] = w.pad0 = T(0);
+                w.d[0] = w.d[1] = w.d[2] = w.pad1 = T(0);
+                rec[(size_t)slot * N + (sub == 1 ? j : i)] = w;
             }
+        }
         wave_sync_lds();  // the queue entries are visible to every lane
         ++tt;
     }
@@ -923,7 +925,7 @@ __device__ inline double nh_half(const SysParams &p, double &xi, double &eta, do
 // enough.  A replica with no budget left is skipped.
 template <typename T, int DIM, bool KICK>
 __global__ void __launch_bounds__(kGatherBlock) k_gather(BatchParams b, const SysParams *reps, StatePtrs s, OutPtrs o,
-                                                      ListPtrs l, const T *__restrict__ rec, double *ke_part,
+                                                      ListPtrs l, const SlotRec<T> *__restrict__ rec, double *ke_part,
                                                       double *thermo, int64_t *budget, int64_t *steps)
 {
     __shared__ double sh[kGatherBlock];
@@ -942,17 +944,16 @@ __global__ void __launch_bounds__(kGatherBlock) k_gather(BatchParams b, const Sy
     for (int c = 0; c < 16; ++c) acc[c] = 0.0;  // F[3], T[3], U, W[9]
     if (mine) {
         const int m = l.n_nbr[i];
-        const size_t cs = (size_t)b.cap * N;
 #pragma unroll 2
         for (int k = sub; k < m; k += kGatherLanes) {
-            const T *rp = rec + (size_t)k * N + i;  // component c at rp[c * cs]
-            const double f[3] = {(double)rp[0], (double)rp[cs], (double)rp[2 * cs]};
+            const SlotRec<T> w = rec[(size_t)k * N + i];
+            const double f[3] = {(double)w.F[0], (double)w.F[1], (double)w.F[2]};
             for (int a = 0; a < 3; ++a) {
                 acc[a] += f[a];
-                acc[3 + a] += (double)rp[(3 + a) * cs];
+                acc[3 + a] += (double)w.tq[a];
             }
-            acc[6] += 0.5 * (double)rp[6 * cs];
-            const double d[3] = {(double)rp[7 * cs], (double)rp[8 * cs], (double)rp[9 * cs]};
+            acc[6] += 0.5 * (double)w.U;
+            const double d[3] = {(double)w.d[0], (double)w.d[1], (double)w.d[2]};
             for (int a = 0; a < 3; ++a)
                 for (int c = 0; c < 3; ++c) acc[7 + 3 * a + c] -= 0.5 * d[a] * f[c];
         }
@@ -1085,14 +1086,14 @@ void pairs_t(const Launch &L, unsigned long long *stats, hipStream_t stream)
 {
     const size_t sh = pair_kernel_lds(sizeof(T) == 4 ? DEM_FP32 : DEM_FP64, L.b.tab_slots);
     k_pairs<T, DIM><<<L.b.pair_blocks, 64 * kWaves, sh, stream>>>(
-        L.b, L.reps, L.s, L.l, reinterpret_cast<const PartRec<T> *>(L.f.rot), L.f.rec64, reinterpret_cast<T *>(L.f.rec),
+        L.b, L.reps, L.s, L.l, reinterpret_cast<const PartRec<T> *>(L.f.rot), L.f.rec64, reinterpret_cast<SlotRec<T> *>(L.f.rec),
         reinterpret_cast<const ShapeTab<T> *>(L.f.tab), reinterpret_cast<const ShapeTab<double> *>(L.f.tab64), stats);
 }
 
 template <typename T, int DIM>
 void gather_t(const Launch &L, bool kick, hipStream_t stream)
 {
-    const T *rec = reinterpret_cast<const T *>(L.f.rec);
+    const SlotRec<T> *rec = reinterpret_cast<const SlotRec<T> *>(L.f.rec);
     if (kick)
         k_gather<T, DIM, true><<<L.b.nchunk, kGatherBlock, 0, stream>>>(L.b, L.reps, L.s, L.o, L.l, rec, L.ke_part,
                                                                     L.thermo, L.budget, L.steps);

@@ -54,11 +54,17 @@ enum Stat {
     ST_SEPARATED = 7, ST_PLANETESTS = 8, ST_COUNT = 9
 };
 
-// Words of one row-slot record, stored component-major rec[c][k][i] for
-// slot k of particle i's neighbour row: force on i (space frame, 3), torque
-// on i about its centre (3), pair energy U_ij (1), and the pair offset
-// x_j - x_i (3).  The force pass writes both slots of a pair.
-constexpr int kRec = 10;
+// One row-slot record, for slot k of particle i's neighbour row at
+// rec[k * N + i]: the force on i (space frame) and the pair energy U_ij,
+// the torque on i about its centre, and the pair offset x_j - x_i, each
+// padded to a 16-byte word so one record is three (FP64: six) whole
+// vector loads.  The force pass writes both slots of a pair.
+template <typename T>
+struct alignas(16) SlotRec {
+    T F[3], U;
+    T tq[3], pad0;
+    T d[3], pad1;
+};
 
 // Body-frame feature tables of one shape in precision T, staged in LDS.
 // Edges carry their vector, midpoint, half length and 1/|edge|^2; faces
@@ -192,7 +198,7 @@ struct alignas(64) PartRec64 {
 struct ForcePtrs {
     void *rot;                   // [N] PartRec<T>
     PartRec64 *rec64;            // [N], FP32 path only (else null)
-    void *rec;                   // [kRec][cap][N] row-slot records, precision T
+    void *rec;                   // [cap][N] SlotRec<T> row-slot records
     const void *tab;             // shape tables, precision T
     const void *tab64;           // shape tables, FP64 (refinement of ill-conditioned FP32 problems)
 };

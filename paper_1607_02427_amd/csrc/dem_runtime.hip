@@ -94,7 +94,7 @@ struct dem_system {
     void *tab64 = nullptr, *tab32 = nullptr;
     void *rot = nullptr;         // [N] PartRec in the force precision
     PartRec64 *rec64 = nullptr;  // [N] FP64 position and orientation (FP32 path)
-    void *rec = nullptr;         // [kRec][cap][N] in the force precision
+    void *rec = nullptr;         // [cap][N] SlotRec in the force precision
     double *ke_part = nullptr;   // [2 * chunks]
     double *e_part = nullptr;    // [12 * chunks]
     double *thermo = nullptr;    // [replica][TH_COUNT]
@@ -401,7 +401,7 @@ int auto_capacity(const dem_params &p, double rl)
 }
 
 
-size_t force_word(int precision) { return precision == DEM_FP32 ? sizeof(float) : sizeof(double); }
+size_t rec_bytes(int precision) { return precision == DEM_FP32 ? sizeof(SlotRec<float>) : sizeof(SlotRec<double>); }
 size_t partrec_bytes(int precision) { return precision == DEM_FP32 ? sizeof(PartRec<float>) : sizeof(PartRec<double>); }
 
 void drop_graph(dem_system *h)
@@ -519,7 +519,7 @@ dem_status alloc_nbr(dem_system *h, int cap)
     h->lst.pairs = nullptr;
     h->rec = nullptr;
     if (hipMalloc(&h->lst.pairs, sizeof(int4) * maxp) != hipSuccess ||
-        hipMalloc(&h->rec, force_word(h->precision) * kRec * (size_t)cap * N) != hipSuccess)
+        hipMalloc(&h->rec, rec_bytes(h->precision) * (size_t)cap * N) != hipSuccess)
         return fail(h, DEM_E_OOM, "neighbour list of %d x %zu entries", cap, N);
     h->bp.cap = cap;
     place_pairs(h);
@@ -1004,12 +1004,12 @@ size_t dem_footprint_bytes(const dem_params *p)
     int cap = p->nbr_capacity > 0 ? p->nbr_capacity : auto_capacity(*p, rl);
     size_t ncell = 1;
     for (int a = 0; a < p->dim && a < 3; ++a) ncell *= (size_t)std::max(1.0, std::floor(p->box[a] / rl));
-    const size_t nch = n / kChunk;
-    const size_t w = force_word(p->precision);
+    const size_t nch = (n + kChunk - 1) / kChunk;
     const size_t maxp = n * (size_t)cap / 2;
-    return sizeof(int32_t) * (n * (size_t)cap + 7 * n + 2 * ncell + 2 + 4 * maxp + nch) +
-           sizeof(double) * (3 * n + 14 * nch + TH_COUNT + 2) + partrec_bytes(p->precision) * n +
-           w * kRec * (size_t)cap * n + sizeof(SysParams) + 2 * DEM_MAX_SHAPES * sizeof(ShapeTab<double>) + 256;
+    return sizeof(int32_t) * (n * (size_t)cap + 4 * n + ncell * (1 + kCellCap) + 4 * maxp + nch + 2 * FLAG_COUNT + G_COUNT + 2) +
+           sizeof(double) * (3 * n + 14 * nch + TH_COUNT + 2) + sizeof(unsigned long long) * ST_COUNT +
+           (partrec_bytes(p->precision) + (p->precision == DEM_FP32 ? sizeof(PartRec64) : 0)) * n +
+           rec_bytes(p->precision) * (size_t)cap * n + sizeof(SysParams) + 2 * DEM_MAX_SHAPES * sizeof(ShapeTab<double>) + 256;
 }
 
 dem_status dem_create_system(const dem_params *params, const dem_state_ptrs *state, const dem_output_ptrs *outputs,
