@@ -47,7 +47,7 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
-def run_path(system, precision, steps, warmup, counting=False):
+def run_path(system, precision, steps, warmup, counting=False, tune=True):
     import torch
     from paper_1607_02427_amd import dem
     g = dem.DemSystem(system, precision)
@@ -56,6 +56,7 @@ def run_path(system, precision, steps, warmup, counting=False):
         g.set_counting(True)
     g.step(warmup)
     g.sync()
+    shape = g.tune_pairs(20) if tune else None
     if counting:
         g.force_stats(reset=True)
     e0 = torch.cuda.Event(enable_timing=True)
@@ -69,7 +70,7 @@ def run_path(system, precision, steps, warmup, counting=False):
     wall = time.perf_counter() - t0
     gpu_ms = e0.elapsed_time(e1)
     en = g.energy()
-    return g, dict(wall_s=wall, gpu_ms=gpu_ms, energy=en)
+    return g, dict(wall_s=wall, gpu_ms=gpu_ms, energy=en, pair_shape=shape)
 
 
 def force_roofline(g, system, reps=200):
@@ -101,6 +102,7 @@ def run_batched(replicas, steps, warmup, precision="fp32"):
         b.add(s)
     b.step(warmup)
     b.sync()
+    shape = b.tune_pairs(3)
     e0 = torch.cuda.Event(enable_timing=True)
     e1 = torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
@@ -111,7 +113,7 @@ def run_batched(replicas, steps, warmup, precision="fp32"):
     ms = e0.elapsed_time(e1)
     b.sync()
     b.close()
-    return dict(value=total * steps / (ms * 1e-3), ms_per_step=ms / steps, particles=total)
+    return dict(value=total * steps / (ms * 1e-3), ms_per_step=ms / steps, particles=total, pair_shape=shape)
 
 
 def run_plain_sequential(replicas, steps, warmup):
@@ -194,6 +196,7 @@ def main():
                    "precision": "fp32 geometry, fp64 state"},
         "wall_s": r32["wall_s"],
         "rebuilds": r32["energy"]["n_rebuilds"],
+        "pair_shape": r32["pair_shape"],
         "roofline": roof,
     }
     g.close()
@@ -216,6 +219,7 @@ def main():
                         f"capped by an overlap-free lattice, {args.batched_steps} steps after 20 warm-up",
             "replicas": len(reps), "particles": rb["particles"], "steps": args.batched_steps,
             "value": rb["value"], "unit": "particle-timesteps/s", "ms_per_step": rb["ms_per_step"], "dtype": "f32",
+            "pair_shape": rb["pair_shape"],
             "plain_fp64_sequential": rp["value"] if rp else None,
             "speedup_vs_plain": rb["value"] / rp["value"] if rp else None}
     if not args.no_served:

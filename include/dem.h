@@ -207,6 +207,25 @@ dem_status dem_set_counting(dem_handle h, int32_t on);
  * Outputs are overwritten with the same values.  Synchronises. */
 dem_status dem_time_forces(dem_handle h, int32_t reps, double *mean_ms);
 
+/* Pair-kernel launch shape (a tuning knob; results do not depend on it,
+ * bit for bit): lanes_per_pair (8 or 16) lanes evaluate one particle pair,
+ * so a 64-lane wavefront takes 8 or 4 pairs at a time, and the grid holds
+ * grid_factor (1 to 4) times as many workgroups as the device keeps
+ * resident at once.  The default is 16 lanes, factor 1.  The next dem_step
+ * captures its graph again.  DEM_E_ARG for other values. */
+enum { DEM_PAIR_SHAPES = 4 };
+dem_status dem_set_pair_shape(dem_handle h, int32_t lanes_per_pair, int32_t grid_factor);
+
+/* Pair-shape autotuner: times `reps` launches of the pair kernel on the
+ * current state for each of the DEM_PAIR_SHAPES shapes {16 lanes, factor 1},
+ * {8, 1}, {16, 2}, {8, 2} (HIP events on the handle's stream) and keeps the
+ * fastest.  Outputs (each may be null): the chosen shape and the mean
+ * launch time in ms of every shape, in that order (mean_ms holds
+ * DEM_PAIR_SHAPES entries).  The state and lists are not changed; the
+ * records of the pair kernel are overwritten by the next step as always.
+ * Synchronises. */
+dem_status dem_tune_pairs(dem_handle h, int32_t reps, int32_t *lanes_per_pair, int32_t *grid_factor, double *mean_ms);
+
 /* Bytes of device memory the library would allocate for these parameters
  * (lists, cells, scratch), excluding caller-owned state and outputs.  For a
  * replica of a batch this is its share of the batch's arrays, less its state

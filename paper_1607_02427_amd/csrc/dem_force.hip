@@ -150,9 +150,11 @@ __device__ inline unsigned long long lanes_below()
 }
 
 constexpr int kWaves = kPairWaves;  // waves per block
-constexpr int kGL = kPairLanes;      // lanes per particle pair
-constexpr int kGroups = 64 / kGL;   // pairs per wave
 constexpr int kQueue = 128;        // survivor queue entries per pair
+// Problem k of a solve round adds into partial sum k % kVirt, whatever the
+// number of lanes per pair, and the partial sums are combined by one fixed
+// tree: the result of a pair is the same bit for bit with 8 or 16 lanes.
+constexpr int kVirt = 16;
 
 // Reciprocal: the hardware FP32 estimate (1 ulp), exact division in FP64.
 __device__ inline float rcp(float x) { return __builtin_amdgcn_rcpf(x); }
@@ -329,10 +331,14 @@ __device__ inline int add_wca(Acc<T> &A, V3<T> P, V3<T> rho, V3<T> t, T sig2, T 
     return 1;
 }
 
-template <typename T>
-__device__ inline T group_sum(T v)
+// Sum over the GL lanes of a group of the lanes' two partial sums (a, b):
+// partial sum s of the kVirt canonical ones is a of lane s (s < GL) or b of
+// lane s - GL; the tree pairs s with s + 8 first, then halves.
+template <int GL, typename T>
+__device__ inline T group_sum(T a, T b)
 {
-    for (int off = kGL / 2; off > 0; off >>= 1) v += __shfl_xor(v, off, kGL);
+    T v = GL == kVirt ? a : a + b;
+    for (int off = (GL == kVirt ? kVirt / 2 : GL / 2); off > 0; off >>= 1) v += __shfl_xor(v, off, GL);
     return v;
 }
 
@@ -459,8 +465,9 @@ struct alignas(16) QEnt {
     T Ri[9];     // R_i, body to space
     T d[3];      // minimum-image x_j - x_i
 };
-constexpr int kQCap = 2 * kGroups;                              // queue slots per wave
-constexpr int kVP = (DEM_MAX_VERTS + kGL - 1) / kGL;            // vertices per lane
+// queue slots per wave: one stage-1 tile adds at most one entry per group
+// to fewer than one per group already waiting
+constexpr int queue_slots(int lanes) { return 2 * (64 / lanes); }
 
 // One block of 4 waves takes a contiguous range of tiles (16 pairs of one
 // replica each; wave w takes pairs 4w..4w+3 of a tile, 16 lanes per pair).
@@ -479,7 +486,7 @@ constexpr int kVP = (DEM_MAX_VERTS + kGL - 1) / kGL;            // vertices per 
 // stage runs the feature prefilter, the per-problem cull and the exact
 // solves on them, so the costly stage runs on full waves.  A pair's result
 // does not depend on which group or round takes it.
-template <typename T, int DIM>
+template <typename T, int DIM, int GL>
 __global__ void __launch_bounds__(64 * kWaves) k_pairs(BatchParams b, const SysParams *__restrict__ reps, StatePtrs s,
                                                           ListPtrs l, const PartRec<T> *__restrict__ prec,
                                                           const PartRec64 *__restrict__ rec64,
@@ -487,6 +494,13 @@ __global__ void __launch_bounds__(64 * kWaves) k_pairs(BatchParams b, const SysP
                                                           const ShapeTab<double> *__restrict__ gtab64,
                                                           unsigned long long *stats)
 {
+    static_assert(GL == 8 || GL == 16, "8 or 16 lanes per pair");
+    constexpr int kGL = GL;                                    // lanes per particle pair
+    constexpr int kGroups = 64 / kGL;                         // pairs per wave
+    constexpr int kTile = kWaves * kGroups;                   // pairs per block tile
+    constexpr int kQCap = queue_slots(kGL);
+    constexpr int kVP = (DEM_MAX_VERTS + kGL - 1) / kGL;       // vertices per lane in the separation test
+    constexpr int kSets = kVirt / kGL;                        // partial sums per lane
     extern __shared__ __align__(16) unsigned char smem[];
     const size_t orl = b.tab_slots * sizeof(ShapeTab<T>);
     ShapeTab<T> *tab = reinterpret_cast<ShapeTab<T> *>(smem);
@@ -655,9 +669,9 @@ __global__ void __launch_bounds__(64 * kWaves) k_pairs(BatchParams b, const SysP
             if (!live) total = 0;
             if (sub == 0 && live) c_feat += total;
 
-            Acc<T> A;
-            A.F = A.Ti = A.Tj = v3<T>(0, 0, 0);
-            A.U = T(0);
+            Acc<T> A0, A1;  // partial sums kVirt-canonical: sub and sub + GL
+            A0.F = A0.Ti = A0.Tj = A1.F = A1.Ti = A1.Tj = v3<T>(0, 0, 0);
+            A0.U = A1.U = T(0);
             int count = 0;
             for (int qb = 0;; qb += kGL) {
                 const int q = qb + sub;
@@ -669,12 +683,18 @@ __global__ void __launch_bounds__(64 * kWaves) k_pairs(BatchParams b, const SysP
                     if (keep) W.queue[count + __popcll(m & below & gmask)] = (unsigned short)q;
                     count += __popcll(m & gmask);
                 }
-                if (last || __ballot(count > kQueue - kGL) != 0) {
+                // rounds end at the same problems for any lane count: the
+                // queue is checked after each kVirt candidates
+                if (last || ((qb + kGL) % kVirt == 0 && __ballot(count > kQueue - kVirt) != 0)) {
                     wave_sync_lds();
-                    for (int k = sub;; k += kGL) {
+                    for (int m = 0;; ++m) {
+                        const int k = m * kGL + sub;
                         const bool w = k < count;
                         if (__ballot(w) == 0) break;
                         if (w) {
+                            Acc<T> A;
+                            A.F = A.Ti = A.Tj = v3<T>(0, 0, 0);
+                            A.U = T(0);
                             V3<T> Pt, rho;
                             T sin2;
                             int e, g;
@@ -692,6 +712,11 @@ __global__ void __launch_bounds__(64 * kWaves) k_pairs(BatchParams b, const SysP
                             } else {
                                 c_in += add_wca(A, Pt, rho, t, sig2, rc2, eps);
                             }
+                            Acc<T> &S = (kSets == 1 || (m & 1) == 0) ? A0 : A1;
+                            S.F = S.F + A.F;
+                            S.Ti = S.Ti + A.Ti;
+                            S.Tj = S.Tj + A.Tj;
+                            S.U += A.U;
                         }
                     }
                     count = 0;
@@ -701,10 +726,13 @@ __global__ void __launch_bounds__(64 * kWaves) k_pairs(BatchParams b, const SysP
             }
             // group reduction (every lane of the group gets the sums); rotate to
             // the space frame and write both row slots, one record per lane
-            const T F0 = group_sum(A.F.x), F1 = group_sum(A.F.y), F2 = group_sum(A.F.z);
-            const T I0 = group_sum(A.Ti.x), I1 = group_sum(A.Ti.y), I2 = group_sum(A.Ti.z);
-            const T J0 = group_sum(A.Tj.x), J1 = group_sum(A.Tj.y), J2 = group_sum(A.Tj.z);
-            const T U = group_sum(A.U);
+            const T F0 = group_sum<kGL>(A0.F.x, A1.F.x), F1 = group_sum<kGL>(A0.F.y, A1.F.y),
+                    F2 = group_sum<kGL>(A0.F.z, A1.F.z);
+            const T I0 = group_sum<kGL>(A0.Ti.x, A1.Ti.x), I1 = group_sum<kGL>(A0.Ti.y, A1.Ti.y),
+                    I2 = group_sum<kGL>(A0.Ti.z, A1.Ti.z);
+            const T J0 = group_sum<kGL>(A0.Tj.x, A1.Tj.x), J1 = group_sum<kGL>(A0.Tj.y, A1.Tj.y),
+                    J2 = group_sum<kGL>(A0.Tj.z, A1.Tj.z);
+            const T U = group_sum<kGL>(A0.U, A1.U);
             if (live && sub < 2) {  // lane 0 writes i's slot, lane 1 j's
                 const V3<T> Fs = mul(Ri, v3<T>(F0, F1, F2));
                 const bool js = sub == 1;
@@ -1081,11 +1109,11 @@ __global__ void k_rotations(BatchParams b, const SysParams *reps, StatePtrs s, L
     if (sizeof(T) == 4) rec64[i] = PartRec64{rc.x, rc.y, rc.z, s.qw[i], s.qx[i], s.qy[i], s.qz[i], 0.0};
 }
 
-template <typename T, int DIM>
+template <typename T, int DIM, int GL>
 void pairs_t(const Launch &L, unsigned long long *stats, hipStream_t stream)
 {
-    const size_t sh = pair_kernel_lds(sizeof(T) == 4 ? DEM_FP32 : DEM_FP64, L.b.tab_slots);
-    k_pairs<T, DIM><<<L.b.pair_blocks, 64 * kWaves, sh, stream>>>(
+    const size_t sh = pair_kernel_lds(sizeof(T) == 4 ? DEM_FP32 : DEM_FP64, L.b.tab_slots, GL);
+    k_pairs<T, DIM, GL><<<L.b.pair_blocks, 64 * kWaves, sh, stream>>>(
         L.b, L.reps, L.s, L.l, reinterpret_cast<const PartRec<T> *>(L.f.rot), L.f.rec64, reinterpret_cast<SlotRec<T> *>(L.f.rec),
         reinterpret_cast<const ShapeTab<T> *>(L.f.tab), reinterpret_cast<const ShapeTab<double> *>(L.f.tab64), stats);
 }
@@ -1119,12 +1147,13 @@ void launch_rotations(const Launch &L, hipStream_t stream)
 void launch_pairs(const Launch &L, unsigned long long *stats, hipStream_t stream)
 {
     if (L.b.nchunk == 0) return;
+    const bool g8 = L.b.pair_lanes == 8;
     if (L.precision == DEM_FP32) {
-        if (L.b.dim == 3) pairs_t<float, 3>(L, stats, stream);
-        else pairs_t<float, 2>(L, stats, stream);
+        if (L.b.dim == 3) g8 ? pairs_t<float, 3, 8>(L, stats, stream) : pairs_t<float, 3, 16>(L, stats, stream);
+        else g8 ? pairs_t<float, 2, 8>(L, stats, stream) : pairs_t<float, 2, 16>(L, stats, stream);
     } else {
-        if (L.b.dim == 3) pairs_t<double, 3>(L, stats, stream);
-        else pairs_t<double, 2>(L, stats, stream);
+        if (L.b.dim == 3) g8 ? pairs_t<double, 3, 8>(L, stats, stream) : pairs_t<double, 3, 16>(L, stats, stream);
+        else g8 ? pairs_t<double, 2, 8>(L, stats, stream) : pairs_t<double, 2, 16>(L, stats, stream);
     }
 }
 
@@ -1140,25 +1169,34 @@ void launch_gather(const Launch &L, bool kick, hipStream_t stream)
     }
 }
 
-size_t pair_kernel_lds(int precision, int tab_slots)
+size_t pair_kernel_lds(int precision, int tab_slots, int lanes)
 {
     const size_t w = precision == DEM_FP32 ? sizeof(ShapeTab<float>) : sizeof(ShapeTab<double>);
     const size_t pl = precision == DEM_FP32 ? sizeof(PairLds<float>) : sizeof(PairLds<double>);
     const size_t qe = precision == DEM_FP32 ? sizeof(QEnt<float>) : sizeof(QEnt<double>);
-    return (size_t)tab_slots * w + sizeof(RepLds) + kWaves * kGroups * pl + kWaves * kQCap * qe;
+    return (size_t)tab_slots * w + sizeof(RepLds) + kWaves * (64 / lanes) * pl + kWaves * queue_slots(lanes) * qe;
 }
 
-int pair_blocks_resident(int precision, int dim, int tab_slots)
+namespace {
+template <typename T, int DIM, int GL>
+hipError_t pair_occupancy(int *per_cu, size_t lds)
 {
-    const size_t lds = pair_kernel_lds(precision, tab_slots);
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, k_pairs<T, DIM, GL>, 64 * kWaves, lds);
+}
+}  // namespace
+
+int pair_blocks_resident(int precision, int dim, int tab_slots, int lanes)
+{
+    const size_t lds = pair_kernel_lds(precision, tab_slots, lanes);
     int per_cu = 0, cus = 0, dev = 0;
     hipError_t e;
+    const bool g8 = lanes == 8;
     if (precision == DEM_FP32)
-        e = dim == 3 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_pairs<float, 3>, 64 * kWaves, lds)
-                     : hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_pairs<float, 2>, 64 * kWaves, lds);
+        e = dim == 3 ? (g8 ? pair_occupancy<float, 3, 8>(&per_cu, lds) : pair_occupancy<float, 3, 16>(&per_cu, lds))
+                     : (g8 ? pair_occupancy<float, 2, 8>(&per_cu, lds) : pair_occupancy<float, 2, 16>(&per_cu, lds));
     else
-        e = dim == 3 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_pairs<double, 3>, 64 * kWaves, lds)
-                     : hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_pairs<double, 2>, 64 * kWaves, lds);
+        e = dim == 3 ? (g8 ? pair_occupancy<double, 3, 8>(&per_cu, lds) : pair_occupancy<double, 3, 16>(&per_cu, lds))
+                     : (g8 ? pair_occupancy<double, 2, 8>(&per_cu, lds) : pair_occupancy<double, 2, 16>(&per_cu, lds));
     if (e != hipSuccess || hipGetDevice(&dev) != hipSuccess ||
         hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
         return 512;

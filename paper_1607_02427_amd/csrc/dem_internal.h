@@ -17,12 +17,13 @@ constexpr double kWcaCut = 1.122462048309373;
 // boundary, so a wavefront's particles (and a gather block's) belong to one
 // replica, and per-chunk partial sums do not depend on the other replicas.
 constexpr int kChunk = 64;
-// The pair kernel: kPairLanes lanes per particle pair, kPairWaves waves
-// per workgroup; a tile is what one workgroup takes at a time (one pair per
-// lane group), and tiles never straddle replicas.
-constexpr int kPairLanes = 16;
+// The pair kernel: 8 or 16 lanes per particle pair (BatchParams::pair_lanes,
+// chosen by the pair-shape tuner), kPairWaves waves per workgroup; a tile
+// is what one workgroup takes at a time (one pair per lane group), and
+// tiles never straddle replicas.
 constexpr int kPairWaves = 4;
-constexpr int kTile = kPairWaves * (64 / kPairLanes);
+constexpr int kDefaultPairLanes = 16;
+constexpr int pair_tile(int lanes) { return kPairWaves * (64 / lanes); }
 
 // Per-replica device flag words (flags[r * FLAG_COUNT + w], one 64-byte
 // line per replica).  FLAG_TRIGGER: some particle has moved far enough
@@ -141,6 +142,8 @@ struct BatchParams {
     int cap;                     // neighbour-row capacity
     int tab_slots;               // shape tables of one replica staged in LDS
     int pair_blocks;             // grid of the pair kernel (a multiple of 8)
+    int pair_lanes;              // lanes per particle pair in the pair kernel (8 or 16)
+    int tile;                    // pairs per tile: pair_tile(pair_lanes)
     int dim;
 };
 
@@ -255,8 +258,8 @@ __device__ inline void cell_insert(const SysParams &p, const ListPtrs &l, int i,
 
 // Dynamic LDS of the pair kernel, and how many of its blocks the device
 // holds at once.
-size_t pair_kernel_lds(int precision, int tab_slots);
-int pair_blocks_resident(int precision, int dim, int tab_slots);
+size_t pair_kernel_lds(int precision, int tab_slots, int lanes);
+int pair_blocks_resident(int precision, int dim, int tab_slots, int lanes);
 
 // Per-particle records (position, rotation, shape id) from the state arrays.
 void launch_rotations(const Launch &L, hipStream_t stream);

@@ -251,14 +251,14 @@ __device__ inline void pair_fill(const SysParams &p, const BatchParams &b, const
     }
 }
 
-// Tile plan: the first tile of each replica (kTile pairs per tile), by one
+// Tile plan: the first tile of each replica (b.tile pairs per tile), by one
 // workgroup.
 __device__ void plan(const BatchParams &b, const SysParams *reps, const ListPtrs &l, int *part)
 {
     const volatile int32_t *vfl = l.flags;
     for (int r = threadIdx.x; r < b.nrep; r += blockDim.x) {
         const int np = vfl[r * FLAG_COUNT + FLAG_NPAIRS];
-        l.tile_start[r] = reps[r].live ? (np + kTile - 1) / kTile : 0;
+        l.tile_start[r] = reps[r].live ? (np + b.tile - 1) / b.tile : 0;
     }
     __syncthreads();
     const int total = block_scan(l.tile_start, l.tile_start, b.nrep, part);

@@ -79,6 +79,8 @@ struct dem_system {
     int dim = 0, precision = 0;
     bool auto_cap = true;
     bool counting = false;
+    int pair_lanes = kDefaultPairLanes;  // pair-kernel shape: lanes per pair
+    int pair_grid = 1;                   // and blocks per resident block slot
     BatchParams bp{};
     std::vector<Replica> reps;
     SlotArena chunks, cells, shapes;
@@ -434,7 +436,7 @@ Launch make_launch(const dem_system *h)
     return L;
 }
 
-int tiles_of(int pcap) { return (pcap + kTile - 1) / kTile; }
+int tiles_of(int pcap, int tile) { return (pcap + tile - 1) / tile; }
 
 // Batch-wide launch parameters from the replica table.
 void refresh_batch(dem_system *h)
@@ -442,19 +444,23 @@ void refresh_batch(dem_system *h)
     BatchParams &b = h->bp;
     b.nrep = 0;
     b.tab_slots = 1;
+    b.pair_lanes = h->pair_lanes;
+    b.tile = pair_tile(h->pair_lanes);
     long long tiles = 0;
     for (size_t r = 0; r < h->reps.size(); ++r) {
         const Replica &R = h->reps[r];
         if (!R.live) continue;
         b.nrep = (int)r + 1;
         b.tab_slots = std::max(b.tab_slots, R.sp.n_shapes);
-        tiles += tiles_of(R.sp.pcap);
+        tiles += tiles_of(R.sp.pcap, b.tile);
     }
     b.nchunk = h->chunks.high();
     b.dim = h->dim;
-    // one round of blocks, as many as the device holds at once (a second
-    // round would add a whole block's latency), no more than the tiles use
-    const int resident = pair_blocks_resident(h->precision, h->dim, b.tab_slots);
+    // by default one round of blocks, as many as the device holds at once
+    // (a second round adds a whole block's latency but evens out the
+    // tail), no more than the tiles use
+    const long long resident =
+        (long long)pair_blocks_resident(h->precision, h->dim, b.tab_slots, b.pair_lanes) * h->pair_grid;
     const long long want = std::max<long long>(8, std::min<long long>(tiles, resident));
     b.pair_blocks = (int)((want + 7) / 8 * 8);
 }
@@ -1350,6 +1356,46 @@ dem_status dem_time_forces(dem_handle h, int32_t reps, double *mean_ms)
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     *mean_ms = (double)ms / reps;
+    return DEM_OK;
+}
+
+dem_status dem_set_pair_shape(dem_handle h, int32_t lanes_per_pair, int32_t grid_factor)
+{
+    if (!h) return fail(nullptr, DEM_E_ARG, "null handle");
+    if ((lanes_per_pair != 8 && lanes_per_pair != 16) || grid_factor < 1 || grid_factor > 4)
+        return fail(h, DEM_E_ARG, "pair shape: %d lanes per pair (8 or 16), grid factor %d (1 to 4)", lanes_per_pair,
+                    grid_factor);
+    if (lanes_per_pair == h->pair_lanes && grid_factor == h->pair_grid) return DEM_OK;
+    h->pair_lanes = lanes_per_pair;
+    h->pair_grid = grid_factor;
+    refresh_batch(h);
+    launch_lists(make_launch(h), LISTS_PLAN, h->stream);  // tiles of the new size
+    HIPCHK(h, hipGetLastError());
+    drop_graph(h);
+    return DEM_OK;
+}
+
+dem_status dem_tune_pairs(dem_handle h, int32_t reps, int32_t *lanes_per_pair, int32_t *grid_factor, double *mean_ms)
+{
+    if (!h || reps < 1) return fail(h, DEM_E_ARG, "bad argument");
+    static const int kShapes[DEM_PAIR_SHAPES][2] = {{16, 1}, {8, 1}, {16, 2}, {8, 2}};
+    double best = 0.0;
+    int pick = 0;
+    for (int k = 0; k < DEM_PAIR_SHAPES; ++k) {
+        dem_status st = dem_set_pair_shape(h, kShapes[k][0], kShapes[k][1]);
+        double ms = 0.0;
+        if (st == DEM_OK) st = dem_time_forces(h, reps, &ms);
+        if (st != DEM_OK) return st;
+        if (mean_ms) mean_ms[k] = ms;
+        if (k == 0 || ms < best) {
+            best = ms;
+            pick = k;
+        }
+    }
+    dem_status st = dem_set_pair_shape(h, kShapes[pick][0], kShapes[pick][1]);
+    if (st != DEM_OK) return st;
+    if (lanes_per_pair) *lanes_per_pair = kShapes[pick][0];
+    if (grid_factor) *grid_factor = kShapes[pick][1];
     return DEM_OK;
 }
 

@@ -12,7 +12,9 @@ exactly at its requested step count, and it is retired (its state copied
 out if asked, its slots freed) at the next poll.  The loop steps the
 batches in chunks of `chunk` steps and polls between chunks, which is when
 arrivals are admitted and finished requests retired: requests that arrive
-while others are on the device join them without waiting for them.
+while others are on the device join them without waiting for them.  Each
+batch retunes its pair-kernel shape whenever its live particle count has
+doubled since the last tuning (the shape never changes results).
 
 All arithmetic runs in libdem's kernels; this module only schedules calls.
 """
@@ -64,6 +66,7 @@ class Server:
         self.keep_results = keep_results
         self.clock = clock
         self.batches: Dict[int, dem.DemBatch] = {}
+        self.tuned_at: Dict[int, int] = {}  # live particles of each batch when its pair shape was last tuned
         self.used = 0
 
     def _batch(self, dim: int) -> dem.DemBatch:
@@ -114,7 +117,12 @@ class Server:
                     raise RuntimeError("a queued request can never be admitted (budget or slots too small)")
                 break
             for dim, b in self.batches.items():
-                if any(d == dim for d, _ in live):
+                n_live = sum(systems[k].n for (d, _), k in live.items() if d == dim)
+                if n_live >= 2 * self.tuned_at.get(dim, 0) and n_live > 0:
+                    # the pair-kernel shape follows the batch as it grows
+                    b.tune_pairs(2)
+                    self.tuned_at[dim] = n_live
+                if n_live > 0:
                     b.step(self.chunk)
             for dim, b in self.batches.items():
                 mine = [rid for d, rid in live if d == dim]
