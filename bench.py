@@ -37,9 +37,11 @@ FLOPS = {
     "cull": 17,        # per-problem test: plane + bounding circle, or segment bounding spheres
     "vf_solve": 100,   # inside test, projection or boundary edges, offset back to i's frame
     "ee_solve": 65,    # segment-segment closest points and offset
+    "ve_solve": 20,    # 2D point-segment nearest point and offset
     "wca": 56,         # WCA energy/force, accumulation of F, both torques and U
 }
-PEAK_FP32 = 157.3e12   # MI355X FP32 vector, published
+PEAK_FP32 = 157.3e12   # MI355X FP32 vector, published (needs packed FP32)
+PEAK_FP32_NONPACKED = 78.6e12  # one FP32 lane operation per cycle, the rate this build's code can reach
 PEAK_HBM = 8.0e12
 
 
@@ -75,21 +77,36 @@ def run_path(system, precision, steps, warmup, counting=False, tune=True):
 
 def force_roofline(g, system, reps=200):
     """Work counters of one force launch on the current state, and the mean
-    launch duration of the force kernel alone (HIP events on its stream)."""
+    launch duration of the force kernel alone (HIP events on its stream).
+
+    achieved: the method's algorithmic work per launch (every feature-pair
+    problem of Eq. 1 for every unordered pair within R_i + R_j + r_cut,
+    solved exactly, plus the WCA terms inside the cutoff) over the mean
+    launch time.  executed: the work the kernel actually does after it
+    proves problems empty (separation test, prefilter, cull)."""
     g.force_stats(reset=True)
     g.compute_forces()
     st = g.force_stats(reset=True)
     mean_ms = g.time_forces(reps)
+    assert len(system.shapes) == 1
     shp = system.shapes[0]
+    if system.dim == 3:
+        problems = 2 * shp.nv * shp.nf * FLOPS["vf_solve"] + shp.ne * shp.ne * FLOPS["ee_solve"]
+    else:
+        problems = 2 * shp.nv * shp.ne * FLOPS["ve_solve"]
+    algorithmic = st["pairs"] * (FLOPS["pair"] + problems) + st["in_cutoff"] * FLOPS["wca"]
     per_pair = FLOPS["pair"] + 2 * shp.nv * FLOPS["sep_vertex"]
     per_feature_pair = 2 * (shp.nv * FLOPS["vertex"] + shp.ne * FLOPS["edge"] + shp.nf * FLOPS["face"])
-    flops = (st["pairs"] * per_pair + st["plane_tests"] * FLOPS["plane_test"]
-             + (st["pairs"] - st["separated"]) * per_feature_pair + st["features"] * FLOPS["cull"]
-             + st["vf_near"] * FLOPS["vf_solve"] + st["ee_near"] * FLOPS["ee_solve"] + st["in_cutoff"] * FLOPS["wca"])
-    achieved = flops / (mean_ms * 1e-3)
-    return dict(bound="alu", achieved=achieved / 1e12, peak=PEAK_FP32 / 1e12, unit="TFLOP/s",
-                frac=achieved / PEAK_FP32, traffic=None, kernel="k_pairs<float,3>",
-                mean_launch_ms=mean_ms, flops_per_launch=flops, counters=st)
+    executed = (st["pairs"] * per_pair + st["plane_tests"] * FLOPS["plane_test"]
+                + (st["pairs"] - st["separated"]) * per_feature_pair + st["features"] * FLOPS["cull"]
+                + st["vf_near"] * FLOPS["vf_solve"] + st["ee_near"] * FLOPS["ee_solve"] + st["in_cutoff"] * FLOPS["wca"])
+    t = mean_ms * 1e-3
+    return dict(bound="alu", achieved=algorithmic / t / 1e12, peak=PEAK_FP32 / 1e12, unit="TFLOP/s",
+                frac=algorithmic / t / PEAK_FP32, traffic=None, kernel="k_pairs<float,3>",
+                mean_launch_ms=mean_ms, flops_per_launch=algorithmic,
+                executed_tflops=executed / t / 1e12, executed_frac=executed / t / PEAK_FP32,
+                executed_flops_per_launch=executed, peak_fp32_nonpacked=PEAK_FP32_NONPACKED / 1e12,
+                frac_nonpacked=algorithmic / t / PEAK_FP32_NONPACKED, counters=st)
 
 
 def run_batched(replicas, steps, warmup, precision="fp32"):
@@ -167,6 +184,8 @@ def main():
     ap.add_argument("--requests", type=int, default=32, help="requests of the served trace")
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-served", action="store_true")
+    ap.add_argument("--no-scale", action="store_true", help="skip the 262,144-octahedra run")
+    ap.add_argument("--scale-steps", type=int, default=300)
     ap.add_argument("--no-sequential", action="store_true",
                     help="skip the one-at-a-time plain FP64 runs of the batched and served workloads")
     args = ap.parse_args()
@@ -185,7 +204,8 @@ def main():
     log(f"[bench] fp32 {r32['gpu_ms'] / args.steps * 1e3:.2f} us/step, {ptps:.3e} PTPS, rebuilds "
         f"{r32['energy']['n_rebuilds']}")
     roof = force_roofline(g, system)
-    log(f"[bench] force kernel {roof['mean_launch_ms'] * 1e3:.2f} us, {roof['achieved']:.2f} TFLOP/s")
+    log(f"[bench] force kernel {roof['mean_launch_ms'] * 1e3:.2f} us, {roof['achieved']:.2f} TFLOP/s algorithmic, "
+        f"{roof['executed_tflops']:.2f} TFLOP/s executed")
     line = {
         "metric": METRIC, "value": ptps, "unit": "particle-timesteps/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": r32["gpu_ms"] / args.steps, "higher_is_better": True,
@@ -206,6 +226,18 @@ def main():
         line["plain_fp64"] = {"value": n * args.steps / (r64["gpu_ms"] * 1e-3), "ms_per_step": r64["gpu_ms"] / args.steps}
         line["fp32_over_plain"] = ptps / line["plain_fp64"]["value"]
         g64.close()
+    if not args.no_scale:
+        big = I.octahedra_3d()
+        log(f"[bench] at scale: {big.n} octahedra, {args.scale_steps} steps")
+        gs, rs = run_path(big, "fp32", args.scale_steps, 50)
+        gs.close()
+        line["at_scale"] = {
+            "workload": f"{big.n} rounded octahedra (edge 1, r 0.1), BCC at volume fraction 0.55, common orientation "
+                        f"plus rotations up to 5 degrees, NVT kT 1, dt 2e-4, {args.scale_steps} steps after 50 warm-up",
+            "n": big.n, "value": big.n * args.scale_steps / (rs["gpu_ms"] * 1e-3), "unit": "particle-timesteps/s",
+            "ms_per_step": rs["gpu_ms"] / args.scale_steps, "rebuilds": rs["energy"]["n_rebuilds"],
+            "pair_shape": rs["pair_shape"], "dtype": "f32"}
+        log(f"[bench] at scale {line['at_scale']['value']:.3e} PTPS")
     if not args.no_batched:
         reps = I.batched_replicas(args.replicas, steps=args.batched_steps)
         log(f"[bench] batched: {len(reps)} replicas, {sum(s.n for s in reps)} particles, "

@@ -53,8 +53,10 @@ typedef enum {
 
 enum { DEM_FP64 = 0, DEM_FP32 = 1 };  /* pair-geometry precision */
 enum { DEM_NVE = 0, DEM_NVT = 1 };
-/* List build: automatic (one workgroup for small systems, one kernel per
- * phase for large ones) or always one kernel per phase.  Same lists. */
+/* List build selector.  Both values take the same device-wide build (cells,
+ * then a neighbour scan of 16 lanes per particle, then the pair list), so
+ * the lists are the same; the field is kept so parameter blocks stay
+ * valid. */
 enum { DEM_LISTS_AUTO = 0, DEM_LISTS_MULTI = 1 };
 
 /* Limits of one shape (vertices, edges, faces, face-loop entries) and of the

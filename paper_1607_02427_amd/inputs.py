@@ -761,6 +761,83 @@ def _qmat(q):
 
 
 # --------------------------------------------------------------------------
+# Octahedra at scale
+# --------------------------------------------------------------------------
+def _quat_mul(a: np.ndarray, b: np.ndarray) -> np.ndarray:
+    """Hamilton product a b (rotation b first, then a); rows (w, x, y, z)."""
+    aw, ax, ay, az = np.moveaxis(a, -1, 0)
+    bw, bx, by, bz = np.moveaxis(b, -1, 0)
+    return np.stack([aw * bw - ax * bx - ay * by - az * bz, aw * bx + ax * bw + ay * bz - az * by,
+                     aw * by - ax * bz + ay * bw + az * bx, aw * bz + ax * by - ay * bx + az * bw], axis=-1)
+
+
+def _cross_polytope_distance(p: np.ndarray, c: float) -> np.ndarray:
+    """Euclidean distance from points p (..., 3) to {x : |x|_1 <= c}, by the
+    sorted-threshold projection onto the l1 ball."""
+    ap = np.abs(p)
+    u = -np.sort(-ap, axis=-1)
+    cs = np.cumsum(u, axis=-1)
+    k = np.arange(1, p.shape[-1] + 1)
+    ok = u - (cs - c) / k > 0
+    rho = p.shape[-1] - 1 - np.argmax(ok[..., ::-1], axis=-1)
+    theta = (np.take_along_axis(cs, rho[..., None], -1)[..., 0] - c) / (rho + 1)
+    w = np.sign(p) * np.maximum(ap - theta[..., None], 0.0)
+    inside = ap.sum(-1) <= c
+    return np.where(inside, 0.0, np.linalg.norm(p - w, axis=-1))
+
+
+def octahedra_3d(seed: int = 3, n: int = 262144, fraction: float = 0.55, n_cells: int = 51,
+                 max_deg: float = 5.0, jitter: float = 0.0, kT: float = 1.0, trials: int = 4000) -> System:
+    """n rounded octahedra (edge 1, r = 0.1) at volume fraction `fraction` on
+    a BCC lattice of n_cells^3 cubic cells (2 n_cells^3 sites, n of them
+    drawn at random, the rest left empty), box L = (n V / fraction)^(1/3).
+
+    All bodies share one orientation: of `trials` seeded uniform rotations,
+    the one that maximises the smallest distance between the inner
+    octahedra of two lattice sites (K - K = 2K for the centrally symmetric
+    octahedron K, so that distance is the distance from the site offset,
+    in the body frame, to 2K), recorded as `min_gap`.  Each body is then
+    rotated by <= max_deg about a random axis, which brings no two inner
+    bodies closer than min_gap - 4 sin(max_deg / 2) R, and moved by
+    U[-jitter, jitter] per axis.  NVT, kT = 1, dt = 2e-4."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    shp = octahedron(1.0, 0.1)
+    a = float(np.abs(shp.vertices).max())  # the inner octahedron is |x|_1 <= a
+    L = (n * shp.volume / fraction) ** (1.0 / 3.0)
+    cell = L / n_cells
+    offs = []
+    for i in range(-2, 3):
+        for j in range(-2, 3):
+            for k in range(-2, 3):
+                for h in (0.0, 0.5):
+                    d = np.array([i + h, j + h, k + h]) * cell
+                    if 1e-9 < np.linalg.norm(d) < 2.0 * shp.circumradius + 2.5 * shp.r:
+                        offs.append(d)
+    offs = np.array(offs)
+    qs = uniform_quaternions(rng, trials)
+    gaps = np.array([_cross_polytope_distance(offs @ _qmat(q), 2.0 * a).min() for q in qs])
+    best = int(np.argmax(gaps))
+    q0 = qs[best]
+    g = np.arange(n_cells)
+    corner = np.stack(np.meshgrid(g, g, g, indexing="ij"), axis=-1).reshape(-1, 3).astype(np.float64)
+    sites = np.concatenate([corner, corner + 0.5]) * cell
+    pick = np.sort(rng.choice(sites.shape[0], size=n, replace=False))
+    x = sites[pick]
+    if jitter > 0:
+        x = x + rng.uniform(-jitter, jitter, x.shape)
+    x %= L
+    q = _quat_mul(small_rotations(rng, n, max_deg), np.tile(q0, (n, 1)))
+    q /= np.linalg.norm(q, axis=1, keepdims=True)
+    shape_id = np.zeros(n, dtype=np.int32)
+    v, Lm = thermal_momenta(rng, [shp], shape_id, 3, kT)
+    s = System(dim=3, box=np.array([L, L, L]), shapes=[shp], shape_id=shape_id, x=x, q=q, v=v, L=Lm,
+               image=np.zeros((n, 3), dtype=np.int32), kT=kT, dt=2e-4, ensemble="nvt",
+               name=f"octahedra_bcc_{n}")
+    s.min_gap = float(gaps[best])
+    return s
+
+
+# --------------------------------------------------------------------------
 # Replicas for batched and served runs
 # --------------------------------------------------------------------------
 # Time steps per shape (2D 1e-4, cube and tetrahedron and L-prism 5e-4,

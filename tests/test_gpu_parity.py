@@ -115,6 +115,28 @@ def test_cubes_4096_full_size_fp32():
         assert e <= TOL["fp32"], (k, e)
 
 
+def test_octahedra_262144_full_size():
+    """The at-scale configuration: 262,144 rounded octahedra on a BCC lattice
+    at volume fraction 0.55, perturbed (positions by up to 0.05 per axis,
+    rotations up to 8 degrees) so that about 8,000 particles are in contact,
+    with the tuned pair shape: every particle against the oracle, FP32 and
+    FP64."""
+    dem = _dem()
+    s = I.octahedra_3d(jitter=0.05, max_deg=8.0)
+    print(f"[full] octahedra_bcc n={s.n}", flush=True)
+    ref = O.forces(s)
+    assert int((ref["scale"][:, 0] > 0).sum()) > 1000
+    for prec in ("fp32", "fp64"):
+        with dem.DemSystem(s, prec) as g:
+            shape = g.tune_pairs(2)
+            g.compute_forces()
+            out = g.outputs()
+        err = compare(out, ref, prec)
+        print("octahedra", prec, shape["lanes"], shape["grid"], err, ref["stats"], flush=True)
+        for k, e in err.items():
+            assert e <= TOL[prec], (prec, k, e)
+
+
 @pytest.mark.parametrize("which", ["2d", "3d_nvt"])
 def test_short_trajectory_fp64(which):
     dem = _dem()

@@ -73,3 +73,36 @@ def test_workloads_shapes_and_sizes():
     # determinism of the seeded generators
     s1b = I.cubes_3d()
     assert np.array_equal(s1.q, s1b.q) and np.array_equal(s1.v, s1b.v)
+
+
+def test_cross_polytope_distance_matches_face_projection():
+    """The distance used to place the at-scale octahedra, against the
+    nearest point of each of the octahedron's eight triangular faces (the
+    oracle's point-polygon primitive) for points outside, and zero inside."""
+    import oracle as O
+    rng = np.random.default_rng(7)
+    c = 1.3
+    e = np.eye(3)
+    faces = [[sx * c * e[0], sy * c * e[1], sz * c * e[2]] for sx in (1, -1) for sy in (1, -1) for sz in (1, -1)]
+    pts = rng.normal(size=(300, 3)) * 1.2
+    got = I._cross_polytope_distance(pts, c)
+    for p, g in zip(pts, got):
+        if np.abs(p).sum() <= c:
+            assert g == 0.0
+            continue
+        want = min(np.linalg.norm(p - O.point_polygon(p, np.array(f))) for f in faces)
+        assert abs(g - want) < 1e-12
+
+
+def test_octahedra_start_is_overlap_free():
+    """A small lattice of the at-scale recipe (same spacing): the common
+    orientation keeps every pair of inner bodies min_gap apart, the start
+    rotations cost at most 4 sin(5 deg / 2) R of it, and the oracle finds no
+    feature pair inside the cutoff."""
+    import oracle as O
+    s = I.octahedra_3d(n=1000, n_cells=8)
+    shp = s.shapes[0]
+    rc = 2 ** (1 / 6) * 2 * shp.r
+    assert s.min_gap - 4 * math.sin(math.radians(5.0) / 2) * shp.circumradius > rc
+    ref = O.forces(s)
+    assert ref["stats"]["pairs"] > 0 and ref["stats"]["feature_in"] == 0
