@@ -972,7 +972,7 @@ __global__ void __launch_bounds__(kGatherBlock) k_gather(BatchParams b, const Sy
     for (int c = 0; c < 16; ++c) acc[c] = 0.0;  // F[3], T[3], U, W[9]
     if (mine) {
         const int m = l.n_nbr[i];
-#pragma unroll 2
+#pragma unroll 8  // many slot loads in flight: the loop is latency-bound
         for (int k = sub; k < m; k += kGatherLanes) {
             const SlotRec<T> w = rec[(size_t)k * N + i];
             const double f[3] = {(double)w.F[0], (double)w.F[1], (double)w.F[2]};

@@ -103,8 +103,8 @@ struct dem_system {
     int64_t *budget = nullptr;   // [replica] steps left
     int64_t *steps = nullptr;    // [replica] steps done
     unsigned long long *stats = nullptr;
-    hipGraph_t graph = nullptr;
-    hipGraphExec_t gexec = nullptr;
+    hipGraph_t graph = nullptr, graph_multi = nullptr;  // one step; kGraphSteps steps
+    hipGraphExec_t gexec = nullptr, gexec_multi = nullptr;
     std::string err;
 };
 
@@ -410,8 +410,10 @@ void drop_graph(dem_system *h)
 {
     if (h->gexec) (void)hipGraphExecDestroy(h->gexec);
     if (h->graph) (void)hipGraphDestroy(h->graph);
-    h->gexec = nullptr;
-    h->graph = nullptr;
+    if (h->gexec_multi) (void)hipGraphExecDestroy(h->gexec_multi);
+    if (h->graph_multi) (void)hipGraphDestroy(h->graph_multi);
+    h->gexec = h->gexec_multi = nullptr;
+    h->graph = h->graph_multi = nullptr;
 }
 
 Launch make_launch(const dem_system *h)
@@ -643,17 +645,30 @@ void enqueue_step(dem_system *h, hipStream_t s)
     launch_gather(L, true, s);
 }
 
-dem_status ensure_graph(dem_system *h)
+// Steps per launch of the long graph: consecutive graph launches leave a
+// gap of several microseconds on the device, which a chain of steps in one
+// graph does not.
+constexpr int kGraphSteps = 8;
+
+dem_status capture_steps(dem_system *h, int steps, hipGraph_t *graph, hipGraphExec_t *exec)
 {
-    if (h->gexec) return DEM_OK;
     HIPCHK(h, hipStreamBeginCapture(h->cap_stream, hipStreamCaptureModeThreadLocal));
-    enqueue_step(h, h->cap_stream);
+    for (int k = 0; k < steps; ++k) enqueue_step(h, h->cap_stream);
     hipGraph_t g = nullptr;
     hipError_t e = hipStreamEndCapture(h->cap_stream, &g);
     if (e != hipSuccess || !g) return fail(h, DEM_E_HIP, "graph capture failed: %s", hipGetErrorString(e));
-    h->graph = g;
-    HIPCHK(h, hipGraphInstantiate(&h->gexec, h->graph, nullptr, nullptr, 0));
+    *graph = g;
+    HIPCHK(h, hipGraphInstantiate(exec, g, nullptr, nullptr, 0));
     return DEM_OK;
+}
+
+dem_status ensure_graph(dem_system *h)
+{
+    if (h->gexec && h->gexec_multi) return DEM_OK;
+    drop_graph(h);
+    dem_status st = capture_steps(h, 1, &h->graph, &h->gexec);
+    if (st == DEM_OK) st = capture_steps(h, kGraphSteps, &h->graph_multi, &h->gexec_multi);
+    return st;
 }
 
 // Builds the lists of replica `only` (all live replicas if LISTS_ALL) from
@@ -966,7 +981,9 @@ dem_status run_steps(dem_system *h, int64_t n_steps)
     // opening half step of the first step, from the current kinetic energy
     launch_kinetic(L, h->stream);
     launch_nh_begin(L, h->stream);
-    for (int64_t k = 0; k < n_steps; ++k) HIPCHK(h, hipGraphLaunch(h->gexec, h->stream));
+    int64_t k = 0;
+    for (; k + kGraphSteps <= n_steps; k += kGraphSteps) HIPCHK(h, hipGraphLaunch(h->gexec_multi, h->stream));
+    for (; k < n_steps; ++k) HIPCHK(h, hipGraphLaunch(h->gexec, h->stream));
     launch_nh_end(L, h->stream);
     HIPCHK(h, hipGetLastError());
     return DEM_OK;
