@@ -465,12 +465,19 @@ struct alignas(16) QEnt {
     T Ri[9];     // R_i, body to space
     T d[3];      // minimum-image x_j - x_i
 };
-// queue slots per wave: one stage-1 tile adds at most one entry per group
-// to fewer than one per group already waiting
-constexpr int queue_slots(int lanes) { return 2 * (64 / lanes); }
+// The separation stage takes kSepLanes lanes per pair, so a wavefront
+// settles kPairsPerWave pairs at a time whatever the feature stage's lane
+// count; a tile is kPairWaves * kPairsPerWave pairs.
+constexpr int kSepLanes = 4;
+constexpr int kPairsPerWave = 64 / kSepLanes;
+static_assert(kPairWaves * kPairsPerWave == pair_tile(), "tile size");
+// queue slots per wave: one separation tile adds at most kPairsPerWave
+// entries to fewer than one per feature-stage group already waiting
+constexpr int queue_slots(int lanes) { return kPairsPerWave + 64 / lanes; }
 
-// One block of 4 waves takes a contiguous range of tiles (16 pairs of one
-// replica each; wave w takes pairs 4w..4w+3 of a tile, 16 lanes per pair).
+// One block of 4 waves takes a contiguous range of tiles (64 pairs of one
+// replica each; wave w takes pairs 16w..16w+15 of a tile in the first
+// stage).
 // Blocks are dealt round-robin to the 8 XCDs, so block b runs on XCD b % 8:
 // XCD x gets the x-th eighth of the tiles, and pairs of neighbouring
 // particles share its L2.  The tables of the block's current replica live
@@ -481,8 +488,9 @@ constexpr int queue_slots(int lanes) { return 2 * (64 / lanes); }
 // when every vertex of one body lies more than r_cut beyond a supporting
 // plane of the other, the two inner bodies are farther apart than r_cut, no
 // feature pair of Eq. 1/2 is inside the cutoff, and the pair's record is
-// zero.  The other live pairs wait in the wave's LDS queue; whenever it
-// holds one for each group (or the range or the replica ends) the second
+// zero (4 lanes per pair, 16 pairs per wavefront).  The other live pairs
+// wait in the wave's LDS queue; whenever it holds one for each group of the
+// second stage (GL lanes per pair; or the range or the replica ends) that
 // stage runs the feature prefilter, the per-problem cull and the exact
 // solves on them, so the costly stage runs on full waves.  A pair's result
 // does not depend on which group or round takes it.
@@ -496,10 +504,10 @@ __global__ void __launch_bounds__(64 * kWaves) k_pairs(BatchParams b, const SysP
 {
     static_assert(GL == 8 || GL == 16, "8 or 16 lanes per pair");
     constexpr int kGL = GL;                                    // lanes per particle pair
-    constexpr int kGroups = 64 / kGL;                         // pairs per wave
-    constexpr int kTile = kWaves * kGroups;                   // pairs per block tile
+    constexpr int kGroups = 64 / kGL;                         // pairs per wave in the feature stage
+    constexpr int kTile = kWaves * kPairsPerWave;             // pairs per block tile
     constexpr int kQCap = queue_slots(kGL);
-    constexpr int kVP = (DEM_MAX_VERTS + kGL - 1) / kGL;       // vertices per lane in the separation test
+    constexpr int kVP = (DEM_MAX_VERTS + kSepLanes - 1) / kSepLanes;  // vertices per lane in the separation test
     constexpr int kSets = kVirt / kGL;                        // partial sums per lane
     extern __shared__ __align__(16) unsigned char smem[];
     const size_t orl = b.tab_slots * sizeof(ShapeTab<T>);
@@ -765,8 +773,10 @@ __global__ void __launch_bounds__(64 * kWaves) k_pairs(BatchParams b, const SysP
             } while (tt >= r_end);
             stage_replica(reps, l, gtab, tab, rl, r);
         }
-        // ---- first stage on tile tt ----
-        const int q = (tt - rl.first_tile) * kTile + wid * kGroups + grp;
+        // ---- first stage on tile tt: 4 lanes per pair ----
+        const int grp1 = lane / kSepLanes, sub1 = lane % kSepLanes;
+        const unsigned long long gmask1 = ((1ull << kSepLanes) - 1) << (kSepLanes * grp1);
+        const int q = (tt - rl.first_tile) * kTile + wid * kPairsPerWave + grp1;
         const bool active = q < rl.np;
         // two dependent round trips: the pair entry, then both particle
         // records (position, rotation and shape in one line each)
@@ -817,7 +827,7 @@ __global__ void __launch_bounds__(64 * kWaves) k_pairs(BatchParams b, const SysP
             bool hj[kVP], hi[kVP];
 #pragma unroll
             for (int p = 0; p < kVP; ++p) {
-                const int k = p * kGL + sub;
+                const int k = p * kSepLanes + sub1;
                 hj[p] = live && k < Sj.nv;
                 hi[p] = live && k < Si.nv;
                 wj[p] = wi[p] = v3<T>(0, 0, 0);
@@ -850,16 +860,16 @@ __global__ void __launch_bounds__(64 * kWaves) k_pairs(BatchParams b, const SysP
                         }
                 }
                 const unsigned long long mi = __ballot(bi), mj = __ballot(bj);
-                sep = sep || (ti && (mi & gmask) == gmask) || (tj && (mj & gmask) == gmask);
+                sep = sep || (ti && (mi & gmask1) == gmask1) || (tj && (mj & gmask1) == gmask1);
             }
             need = live && !sep;
-            if (sub == 0 && live) {
+            if (sub1 == 0 && live) {
                 c_pairs += 1;
                 c_sep += sep ? 1 : 0;
             }
             // queue the pairs that need the feature stage, one entry per group
-            const unsigned long long m = __ballot(need && sub == 0);
-            if (need && sub == 0) {
+            const unsigned long long m = __ballot(need && sub1 == 0);
+            if (need && sub1 == 0) {
                 QEnt<T> &e = qb[(tail + __popcll(m & below)) % kQCap];
                 e.ent = ent;
                 e.si = si;
@@ -877,14 +887,14 @@ __global__ void __launch_bounds__(64 * kWaves) k_pairs(BatchParams b, const SysP
             }
             tail += __popcll(m);
         }
-        if (active && !need && sub < 2) {  // out of reach or separated: zero both row slots
-            const int slot = sub == 1 ? ent.w : ent.z;
+        if (active && !need && sub1 < 2) {  // out of reach or separated: zero both row slots
+            const int slot = sub1 == 1 ? ent.w : ent.z;
             if (slot >= 0) {
                 SlotRec<T> w;
                 w.F[0] = w.F[1] = w.F[2] = w.U = T(0);
                 w.tq[0] = w.tq[1] = w.tq[2] = w.pad0 = T(0);
                 w.d[0] = w.d[1] = w.d[2] = w.pad1 = T(0);
-                rec[(size_t)slot * N + (sub == 1 ? j : i)] = w;
+                rec[(size_t)slot * N + (sub1 == 1 ? j : i)] = w;
             }
         }
         wave_sync_lds();  // the queue entries are visible to every lane

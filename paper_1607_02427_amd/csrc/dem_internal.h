@@ -17,13 +17,14 @@ constexpr double kWcaCut = 1.122462048309373;
 // boundary, so a wavefront's particles (and a gather block's) belong to one
 // replica, and per-chunk partial sums do not depend on the other replicas.
 constexpr int kChunk = 64;
-// The pair kernel: 8 or 16 lanes per particle pair (BatchParams::pair_lanes,
-// chosen by the pair-shape tuner), kPairWaves waves per workgroup; a tile
-// is what one workgroup takes at a time (one pair per lane group), and
-// tiles never straddle replicas.
+// The pair kernel: kPairWaves waves per workgroup; its separation stage
+// takes 4 lanes per particle pair and its feature stage 8 or 16
+// (BatchParams::pair_lanes, chosen by the pair-shape tuner).  A tile is what
+// one workgroup takes at a time (16 pairs per wavefront), and tiles never
+// straddle replicas.
 constexpr int kPairWaves = 4;
 constexpr int kDefaultPairLanes = 16;
-constexpr int pair_tile(int lanes) { return kPairWaves * (64 / lanes); }
+constexpr int pair_tile() { return kPairWaves * 16; }
 
 // Per-replica device flag words (flags[r * FLAG_COUNT + w], one 64-byte
 // line per replica).  FLAG_TRIGGER: some particle has moved far enough
@@ -143,7 +144,7 @@ struct BatchParams {
     int tab_slots;               // shape tables of one replica staged in LDS
     int pair_blocks;             // grid of the pair kernel (a multiple of 8)
     int pair_lanes;              // lanes per particle pair in the pair kernel (8 or 16)
-    int tile;                    // pairs per tile: pair_tile(pair_lanes)
+    int tile;                    // pairs per tile: pair_tile()
     int dim;
 };
 

@@ -447,7 +447,7 @@ void refresh_batch(dem_system *h)
     b.nrep = 0;
     b.tab_slots = 1;
     b.pair_lanes = h->pair_lanes;
-    b.tile = pair_tile(h->pair_lanes);
+    b.tile = pair_tile();
     long long tiles = 0;
     for (size_t r = 0; r < h->reps.size(); ++r) {
         const Replica &R = h->reps[r];
