@@ -961,6 +961,24 @@ __device__ inline double nh_half(const SysParams &p, double &xi, double &eta, do
 // kinetic partials, summed in chunk order; it also counts a list build done
 // in this step and schedules one for the next step if a particle moved far
 // enough.  A replica with no budget left is skipped.
+constexpr int kGatherBatch = 4;  // row slots loaded together in the gather
+
+// Adds one row-slot record to a particle's sums: F, tau, U_i = 1/2 sum U_ij
+// and W_i = 1/2 sum r_ij (x) F_ij with r_ij = -d.
+template <typename T>
+__device__ inline void add_slot(double acc[16], const SlotRec<T> &w)
+{
+    const double f[3] = {(double)w.F[0], (double)w.F[1], (double)w.F[2]};
+    for (int a = 0; a < 3; ++a) {
+        acc[a] += f[a];
+        acc[3 + a] += (double)w.tq[a];
+    }
+    acc[6] += 0.5 * (double)w.U;
+    const double d[3] = {(double)w.d[0], (double)w.d[1], (double)w.d[2]};
+    for (int a = 0; a < 3; ++a)
+        for (int c = 0; c < 3; ++c) acc[7 + 3 * a + c] -= 0.5 * d[a] * f[c];
+}
+
 template <typename T, int DIM, bool KICK>
 __global__ void __launch_bounds__(kGatherBlock) k_gather(BatchParams b, const SysParams *reps, StatePtrs s, OutPtrs o,
                                                       ListPtrs l, const SlotRec<T> *__restrict__ rec, double *ke_part,
@@ -982,19 +1000,18 @@ __global__ void __launch_bounds__(kGatherBlock) k_gather(BatchParams b, const Sy
     for (int c = 0; c < 16; ++c) acc[c] = 0.0;  // F[3], T[3], U, W[9]
     if (mine) {
         const int m = l.n_nbr[i];
-#pragma unroll 8  // many slot loads in flight: the loop is latency-bound
-        for (int k = sub; k < m; k += kGatherLanes) {
-            const SlotRec<T> w = rec[(size_t)k * N + i];
-            const double f[3] = {(double)w.F[0], (double)w.F[1], (double)w.F[2]};
-            for (int a = 0; a < 3; ++a) {
-                acc[a] += f[a];
-                acc[3 + a] += (double)w.tq[a];
-            }
-            acc[6] += 0.5 * (double)w.U;
-            const double d[3] = {(double)w.d[0], (double)w.d[1], (double)w.d[2]};
-            for (int a = 0; a < 3; ++a)
-                for (int c = 0; c < 3; ++c) acc[7 + 3 * a + c] -= 0.5 * d[a] * f[c];
+        // slots in batches: every load of a batch is issued before any of
+        // its sums, so the batch's memory round trips overlap
+        int k = sub;
+        for (; k + (kGatherBatch - 1) * kGatherLanes < m; k += kGatherBatch * kGatherLanes) {
+            SlotRec<T> w[kGatherBatch];
+#pragma unroll
+            for (int u = 0; u < kGatherBatch; ++u) w[u] = rec[(size_t)(k + u * kGatherLanes) * N + i];
+            __builtin_amdgcn_sched_barrier(0);  // keep the loads ahead of the sums
+#pragma unroll
+            for (int u = 0; u < kGatherBatch; ++u) add_slot(acc, w[u]);
         }
+        for (; k < m; k += kGatherLanes) add_slot(acc, rec[(size_t)k * N + i]);
     }
     for (int off = 1; off < kGatherLanes; off <<= 1)
         for (int c = 0; c < 16; ++c) acc[c] += __shfl_xor(acc[c], off, kGatherLanes);
