@@ -9,30 +9,31 @@
 // interaction point.  Nearly parallel edges interact at the midpoints of
 // their overlap (Sec. II, paragraph on parallel edges).
 //
-// Mapping to gfx950 (two kernels):
-//  1. k_pairs: 16 lanes per unordered pair of the half list, so one wave64
-//     works on four pairs at once and shares every latency stage among them
-//     (grid-stride over the list).  A group builds j's frame relative to
-//     i's once, transforms both
-//     vertex sets across (one lane per vertex, kept in LDS), then runs the
-//     contact search in three levels, all conservative: a feature prefilter
-//     keeps only vertices, edges and faces within reach of the other body
-//     (one lane per feature, ballot-compacted index lists); every remaining
-//     feature pair of Eq. 1/2 gets a cheap test (plane distance and
-//     bounding circle for vertex-face, bounding spheres for edge-edge and
-//     vertex-edge); and the survivors are compacted into a per-wave LDS
-//     queue so the exact nearest-point and WCA work runs on dense lanes.  The
-//     group reduces force, both torques and energy across its 16 lanes and
-//     writes one record per pair (FP32 pair records in FP32 mode; every sum
+// Mapping to gfx950:
+//  1. k_pairs: each unordered pair of the half list once, in two stages.
+//     The separation stage (4 lanes per pair, 16 pairs per wavefront) loads
+//     the pair, drops it beyond R_i + R_j + r_cut, and tests each body's
+//     vertices against the other's supporting planes; a pair separated by
+//     more than r_cut has no feature pair inside the cutoff.  The rest queue
+//     in LDS for the feature stage (8 or 16 lanes per pair, a tuning knob):
+//     a per-feature prefilter keeps only vertices, edges and faces within
+//     reach of the other body, every remaining feature pair of Eq. 1/2 gets a
+//     cheap conservative test (plane distance and bounding circle for
+//     vertex-face, bounding spheres for edge-edge and vertex-edge), and the
+//     survivors are compacted into a per-pair LDS queue so the exact
+//     nearest-point and WCA work runs on dense lanes.  The group reduces
+//     force, both torques and energy in a fixed order and writes one record
+//     into each particle's row slot (FP32 records in FP32 mode; every sum
 //     over pairs is FP64).
 //  2. k_gather: each particle sums the records of its row in slot order (no
-//     atomics, deterministic) into F, tau, U_i and W_i, optionally
-//     fused with the closing kick of the integrator and, with NVT, the
-//     thermostat half steps between two steps.
+//     atomics, deterministic) into F, tau, U_i and W_i, optionally fused
+//     with the closing kick of the integrator; k_replica_tail then closes
+//     the step of each replica (thermostat half steps, budget, rebuilds).
 // FP32 mode does the geometry in FP32 from FP64 pair offsets rounded once;
-// segment pairs that are nearly parallel (sin^2 < 1e-2) and near the cutoff
-// are redone in FP64, because their closest points are ill-conditioned in
-// FP32 (error ~ eps / sin).
+// problems within 1% of the cutoff and segment pairs that are nearly
+// parallel (sin^2 < 1e-2) are redone in FP64, because FP32 cannot resolve
+// them (steep force near the cutoff; closest points ill-conditioned, error
+// ~ eps / sin^2).
 #include <algorithm>
 
 #include "dem_internal.h"
@@ -954,13 +955,9 @@ __device__ inline double nh_half(const SysParams &p, double &xi, double &eta, do
 // closing kick.  One block per chunk, so a block belongs to one replica.
 // Each particle's row is split over kGatherLanes lanes (lane l takes slots
 // l, l + kGatherLanes, ... in order) and combined by a fixed butterfly, so
-// the result does not depend on scheduling.  With the kick, the last block
-// of a replica to finish (ticket counter, no waiting) spends one step of the
-// replica's budget and, with NVT, applies the step's closing Nose-Hoover
-// half step and the next step's opening one from the replica's per-chunk
-// kinetic partials, summed in chunk order; it also counts a list build done
-// in this step and schedules one for the next step if a particle moved far
-// enough.  A replica with no budget left is skipped.
+// the result does not depend on scheduling.  With the kick and NVT each
+// block writes its chunk's kinetic partials for k_replica_tail.  A replica
+// with no budget left is skipped.
 constexpr int kGatherBatch = 4;  // row slots loaded together in the gather
 
 // Adds one row-slot record to a particle's sums: F, tau, U_i = 1/2 sum U_ij
@@ -985,11 +982,9 @@ __global__ void __launch_bounds__(kGatherBlock) k_gather(BatchParams b, const Sy
                                                       double *thermo, int64_t *budget, int64_t *steps)
 {
     __shared__ double sh[kGatherBlock];
-    __shared__ int last;
     const int r = l.chunk_rep[blockIdx.x];
     if (r < 0) return;
     const SysParams &p = reps[r];
-    int32_t *fl = l.flags + r * FLAG_COUNT;
     if (KICK && budget[r] <= 0) return;
     const int sub = threadIdx.x % kGatherLanes;
     const int i = blockIdx.x * kGatherPer + threadIdx.x / kGatherLanes;
@@ -1060,29 +1055,37 @@ __global__ void __launch_bounds__(kGatherBlock) k_gather(BatchParams b, const Sy
             }
         }
     }
-    if (!KICK) return;
-    if (nvt) {
-        kt = block_sum<kGatherBlock>(kt, sh);
-        kr = block_sum<kGatherBlock>(kr, sh);
-    }
-    const int nblk = (p.n + kChunk - 1) / kChunk;
+    if (!nvt) return;
+    kt = block_sum<kGatherBlock>(kt, sh);
+    kr = block_sum<kGatherBlock>(kr, sh);
     if (threadIdx.x == 0) {
-        if (nvt) {
-            ke_part[2 * blockIdx.x] = kt;
-            ke_part[2 * blockIdx.x + 1] = kr;
-        }
-        __threadfence();
-        const int ticket = atomicAdd(&fl[FLAG_TICKET], 1);
-        last = (ticket == nblk - 1);
+        ke_part[2 * blockIdx.x] = kt;
+        ke_part[2 * blockIdx.x + 1] = kr;
     }
-    __syncthreads();
-    if (!last) return;
-    __threadfence();
-    if (nvt) {
+}
+
+// The end of a step for each replica (one block per replica slot, after
+// k_gather): the thermostat's closing half step and the next step's
+// opening half step from the kinetic energy after the closing kick (the
+// gather's partial sums per chunk, added in chunk order), the step budget
+// and count, and the list-rebuild transitions: this step's build is
+// counted, and a trigger raised during the step schedules a build for the
+// next step.  A kernel of its own, so the partial sums are visible without
+// a device-wide fence in every gather block.
+__global__ void __launch_bounds__(kGatherBlock) k_replica_tail(const SysParams *reps, ListPtrs l,
+                                                               const double *ke_part, double *thermo, int64_t *budget,
+                                                               int64_t *steps)
+{
+    __shared__ double sh[kGatherBlock];
+    const int r = blockIdx.x;
+    const SysParams &p = reps[r];
+    if (!p.live || p.n == 0 || budget[r] <= 0) return;
+    int32_t *fl = l.flags + r * FLAG_COUNT;
+    if (p.ensemble == DEM_NVT) {
+        const int nblk = (p.n + kChunk - 1) / kChunk;
         const int c0 = p.off / kChunk;
-        const volatile double *vp = ke_part;
         double acc2 = 0.0;
-        for (int c = threadIdx.x; c < nblk; c += blockDim.x) acc2 += vp[2 * (c0 + c)] + vp[2 * (c0 + c) + 1];
+        for (int c = threadIdx.x; c < nblk; c += blockDim.x) acc2 += ke_part[2 * (c0 + c)] + ke_part[2 * (c0 + c) + 1];
         double K = block_sum<kGatherBlock>(acc2, sh);
         if (threadIdx.x == 0) {
             double *th = thermo + r * TH_COUNT;
@@ -1101,7 +1104,6 @@ __global__ void __launch_bounds__(kGatherBlock) k_gather(BatchParams b, const Sy
     if (threadIdx.x == 0) {
         budget[r] -= 1;
         steps[r] += 1;
-        fl[FLAG_TICKET] = 0;
         if (fl[FLAG_REBUILD] != 0) {  // this step's lists are built: count them
             fl[FLAG_REBUILD] = 0;
             fl[FLAG_NBUILDS] += 1;
@@ -1149,9 +1151,11 @@ template <typename T, int DIM>
 void gather_t(const Launch &L, bool kick, hipStream_t stream)
 {
     const SlotRec<T> *rec = reinterpret_cast<const SlotRec<T> *>(L.f.rec);
-    if (kick)
+    if (kick) {
         k_gather<T, DIM, true><<<L.b.nchunk, kGatherBlock, 0, stream>>>(L.b, L.reps, L.s, L.o, L.l, rec, L.ke_part,
                                                                     L.thermo, L.budget, L.steps);
+        k_replica_tail<<<L.b.nrep, kGatherBlock, 0, stream>>>(L.reps, L.l, L.ke_part, L.thermo, L.budget, L.steps);
+    }
     else
         k_gather<T, DIM, false><<<L.b.nchunk, kGatherBlock, 0, stream>>>(L.b, L.reps, L.s, L.o, L.l, rec, L.ke_part,
                                                                      L.thermo, L.budget, L.steps);

@@ -270,12 +270,13 @@ void launch_pairs(const Launch &L, unsigned long long *stats, hipStream_t stream
 
 // Per-particle sums of pair records in row order (fixed, atomic-free):
 // F, tau, U_i, W_i; with kick != 0 also the closing velocity/angular
-// momentum kick, the Nose-Hoover half steps and the step budget.
+// momentum kick and then the step tail of every replica (Nose-Hoover half
+// steps, step budget and count, rebuild scheduling).
 void launch_gather(const Launch &L, bool kick, hipStream_t stream);
 
-// Integrator pieces.  With NVT the gather's last block of a replica applies
-// the closing half step of the step and the opening half step of the next
-// one; launch_nh_begin opens the first step of a closed replica,
+// Integrator pieces.  With NVT the step tail after the gather applies the
+// closing half step of the step and the opening half step of the next one;
+// launch_nh_begin opens the first step of a closed replica,
 // launch_nh_end applies the pending closing factor to the velocities.
 void launch_nh_begin(const Launch &L, hipStream_t stream);
 void launch_kick_drift(const Launch &L, hipStream_t stream);
