@@ -233,6 +233,8 @@ __global__ void __launch_bounds__(kBlock) k_kick_drift(BatchParams b, const SysP
     s.image[3 * i + 2] = img[2];
     if (l.flags[r * FLAG_COUNT + FLAG_REBUILD] != 0) {
         // this step rebuilds the lists: the particle goes into its cell now
+        // (and the replica's pair total restarts for k_nbr to add to)
+        if (i == p.off) l.flags[r * FLAG_COUNT + FLAG_NPAIRS] = 0;
         cell_insert(p, l, i, x[0], x[1], x[2]);
     } else {
         // The next step rebuilds them if the displacement since the last

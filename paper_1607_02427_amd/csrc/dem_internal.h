@@ -170,6 +170,7 @@ struct ListPtrs {
     // half list of unordered pairs (i < j), rebuilt with the neighbour list
     int32_t *klo;                // [N] first row slot of i holding a j > i
     int32_t *pstart;             // [N] first pair index of i, local to its replica
+    int32_t *ptot;               // [N / 16] pairs owned by the particles of each k_nbr block
     int4 *pairs;                 // [pair slots] {i, j, slot of j in i's row, slot of i in j's row (-1: missing)}
 };
 

@@ -109,6 +109,7 @@ __global__ void __launch_bounds__(kBlock) k_assign(BatchParams b, const SysParam
     if (r < 0) return;
     const SysParams &p = reps[r];
     if (!building(mode, r, p, l.flags + r * FLAG_COUNT, budget) || i >= p.off + p.n) return;
+    if (i == p.off) l.flags[r * FLAG_COUNT + FLAG_NPAIRS] = 0;  // k_nbr adds the replica's pairs
     cell_insert(p, l, i, s.x[i], s.y[i], p.dim == 3 ? s.z[i] : 0.0);
 }
 
@@ -118,15 +119,14 @@ __global__ void __launch_bounds__(kBlock) k_assign(BatchParams b, const SysParam
 // particle's LDS buffer in ballot order, then every kept hit finds its rank
 // (the number of smaller hits) and is stored in that row slot, so the row
 // ascends and keeps the cap smallest j.  The row's count of j > i is the
-// particle's pair count; the replica's last block scans those counts into
-// pair offsets.
+// particle's pair count; the block stores its total and adds it to the
+// replica's (FLAG_NPAIRS, cleared when the build starts).
 template <int DIM>
 __global__ void __launch_bounds__(kBlock) k_nbr(BatchParams b, const SysParams *reps, StatePtrs s, ListPtrs l,
                                                    const int64_t *budget, int mode)
 {
     __shared__ int buf[kNbrPer][kRowMax];
     __shared__ int part[kBlock];
-    __shared__ int last;
     if (mode == LISTS_STEP && l.gflags[G_ANY] == 0) return;
     const int base = blockIdx.x * kNbrPer;
     const int r = l.chunk_rep[base / kChunk];
@@ -202,29 +202,27 @@ __global__ void __launch_bounds__(kBlock) k_nbr(BatchParams b, const SysParams *
             }
         }
     for (int off = kNbrLanes / 2; off > 0; off >>= 1) lower += __shfl_xor(lower, off, kNbrLanes);
+    const int kept = min(m, cap);
     if (mine && sub == 0) {
-        const int kept = min(m, cap);
         l.n_nbr[i] = kept;
         l.klo[i] = lower;
-        l.pstart[i] = kept - lower;  // pair count; the scan below turns it into an offset
+        l.pstart[i] = kept - lower;  // pair count; k_fill turns it into an offset
         if (m > cap) atomicMax(&fl[FLAG_MAXROW], m);
         l.xlast[i] = xi;
         l.xlast[N + i] = yi;
         l.xlast[2 * N + i] = zi;
     }
+    // the block's pair count, for k_fill's offsets and (an integer sum, in
+    // any order) the replica's total
+    part[threadIdx.x] = (mine && sub == 0) ? kept - lower : 0;
     __syncthreads();
-    if (threadIdx.x == 0) {
-        __threadfence();
-        const int nblk = (p.n + kChunk - 1) / kChunk * (kChunk / kNbrPer);
-        last = atomicAdd(&fl[FLAG_NBRTICKET], 1) == nblk - 1;
+    for (int off = kBlock / 2; off > 0; off >>= 1) {
+        if (threadIdx.x < off) part[threadIdx.x] += part[threadIdx.x + off];
+        __syncthreads();
     }
-    __syncthreads();
-    if (!last) return;
-    __threadfence();
-    const int np = block_scan(l.pstart + p.off, l.pstart + p.off, p.n, part);
     if (threadIdx.x == 0) {
-        fl[FLAG_NPAIRS] = min(np, p.pcap);
-        fl[FLAG_NBRTICKET] = 0;
+        l.ptot[blockIdx.x] = part[0];
+        atomicAdd(&fl[FLAG_NPAIRS], part[0]);
     }
 }
 
@@ -257,7 +255,8 @@ __device__ void plan(const BatchParams &b, const SysParams *reps, const ListPtrs
 {
     const volatile int32_t *vfl = l.flags;
     for (int r = threadIdx.x; r < b.nrep; r += blockDim.x) {
-        const int np = vfl[r * FLAG_COUNT + FLAG_NPAIRS];
+        const int np = min(vfl[r * FLAG_COUNT + FLAG_NPAIRS], reps[r].pcap);  // (above pcap only after an overflow)
+        l.flags[r * FLAG_COUNT + FLAG_NPAIRS] = np;
         l.tile_start[r] = reps[r].live ? (np + b.tile - 1) / b.tile : 0;
     }
     __syncthreads();
@@ -277,7 +276,25 @@ __global__ void __launch_bounds__(kBlock) k_fill(BatchParams b, const SysParams 
     const int r = __builtin_amdgcn_readfirstlane(c < b.nchunk ? l.chunk_rep[c] : -1);
     if (r < 0) return;
     const SysParams &p = reps[r];
-    if (!building(mode, r, p, l.flags + r * FLAG_COUNT, budget) || i >= p.off + p.n) return;
+    if (!building(mode, r, p, l.flags + r * FLAG_COUNT, budget)) return;
+    const bool mine = i < p.off + p.n;
+    if (mode != LISTS_REFILL) {
+        // pair offset of i: the counts of the replica's k_nbr blocks before
+        // this chunk, plus the counts of the chunk's particles before i (one
+        // wavefront is one chunk)
+        const int lane = __lane_id();
+        const int cnt = mine ? l.pstart[i] : 0;
+        int incl = cnt;
+        for (int off = 1; off < 64; off <<= 1) {
+            const int v = __shfl_up(incl, off, 64);
+            if (lane >= off) incl += v;
+        }
+        int prior = 0;
+        for (int q = p.off / kNbrPer + lane; q < c * (kChunk / kNbrPer); q += 64) prior += l.ptot[q];
+        for (int off = 32; off > 0; off >>= 1) prior += __shfl_xor(prior, off, 64);
+        if (mine) l.pstart[i] = prior + incl - cnt;
+    }
+    if (!mine) return;
     pair_fill(p, b, l, i);
     if (clear_cells && p.use_cells) l.cell_count[p.coff + l.pcell[i]] = 0;  // every particle of the cell writes the same zero
 }

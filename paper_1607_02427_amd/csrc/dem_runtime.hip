@@ -569,6 +569,7 @@ dem_status alloc_core(dem_system *h, int Ncap, int Ccap, int Scap, int Rcap)
               hipMalloc(&h->lst.xlast, sizeof(double) * 3 * N) == hipSuccess &&
               hipMalloc(&h->lst.klo, sizeof(int32_t) * N) == hipSuccess &&
               hipMalloc(&h->lst.pstart, sizeof(int32_t) * N) == hipSuccess &&
+              hipMalloc(&h->lst.ptot, sizeof(int32_t) * (N / 16 + 1)) == hipSuccess &&
               hipMalloc(&h->rot, partrec_bytes(h->precision) * N) == hipSuccess &&
               (h->precision != DEM_FP32 || hipMalloc(&h->rec64, sizeof(PartRec64) * N) == hipSuccess);
     if (!ok) return fail(h, DEM_E_OOM, "device allocation failed");
@@ -595,6 +596,7 @@ dem_status alloc_core(dem_system *h, int Ncap, int Ccap, int Scap, int Rcap)
     HIPCHK(h, hipMemsetAsync(h->lst.n_nbr, 0, sizeof(int32_t) * N, h->stream));
     HIPCHK(h, hipMemsetAsync(h->lst.klo, 0, sizeof(int32_t) * N, h->stream));
     HIPCHK(h, hipMemsetAsync(h->lst.pstart, 0, sizeof(int32_t) * N, h->stream));
+    HIPCHK(h, hipMemsetAsync(h->lst.ptot, 0, sizeof(int32_t) * (N / 16 + 1), h->stream));
     HIPCHK(h, hipMemsetAsync(h->lst.pcell, 0, sizeof(int32_t) * N, h->stream));
     HIPCHK(h, hipMemsetAsync(h->stats, 0, sizeof(unsigned long long) * ST_COUNT, h->stream));
     HIPCHK(h, hipMemsetAsync(h->ke_part, 0, sizeof(double) * 2 * nch, h->stream));
@@ -609,7 +611,7 @@ void free_all(dem_system *h)
     void *ptrs[] = {h->d_reps, h->d_chunk_rep, h->tab64, h->tab32, h->ke_part, h->e_part, h->thermo, h->budget,
                     h->steps, h->stats, h->lst.flags, h->lst.gflags, h->lst.tile_start, h->lst.cell_count,
                     h->lst.cell_slot, h->lst.pcell, h->lst.n_nbr, h->lst.xlast, h->lst.klo,
-                    h->lst.pstart, h->lst.nbr, h->lst.pairs, h->rot, h->rec, h->rec64};
+                    h->lst.pstart, h->lst.ptot, h->lst.nbr, h->lst.pairs, h->rot, h->rec, h->rec64};
     for (void *p : ptrs) (void)hipFree(p);
     if (h->batch) {
         void *own[] = {h->st.x,  h->st.y,  h->st.z,  h->st.qw, h->st.qx,  h->st.qy,  h->st.qz,  h->st.vx,
