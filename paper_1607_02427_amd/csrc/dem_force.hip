@@ -143,6 +143,30 @@ __device__ inline V3<T> face_point(const ShapeTab<T> &S, int f, V3<T> p)
 }
 
 __device__ inline double min_image(double d, double L) { return d - L * rint(d / L); }
+// The same for |d| < L (positions in [0, L)) without a division; it differs
+// from min_image only where |d| is within rounding of L/2, far beyond any
+// interaction.
+__device__ inline double min_image_near(double d, double L)
+{
+    const double h = 0.5 * L;
+    return d > h ? d - L : (d < -h ? d + L : d);
+}
+
+// Hamilton product a b of quaternions (w, x, y, z), and the rotation of v by
+// a unit quaternion q = (w, u): v + 2 w (u x v) + 2 u x (u x v).
+__device__ inline void qmul(const double a[4], const double b[4], double o[4])
+{
+    o[0] = a[0] * b[0] - a[1] * b[1] - a[2] * b[2] - a[3] * b[3];
+    o[1] = a[0] * b[1] + a[1] * b[0] + a[2] * b[3] - a[3] * b[2];
+    o[2] = a[0] * b[2] - a[1] * b[3] + a[2] * b[0] + a[3] * b[1];
+    o[3] = a[0] * b[3] + a[1] * b[2] - a[2] * b[1] + a[3] * b[0];
+}
+__device__ inline V3<double> qrot(const double q[4], V3<double> v)
+{
+    const V3<double> u = v3<double>(q[1], q[2], q[3]);
+    const V3<double> c = cross(u, v);
+    return v + (2.0 * q[0]) * c + 2.0 * cross(u, c);
+}
 
 __device__ inline unsigned long long lanes_below()
 {
@@ -373,31 +397,31 @@ __device__ int refine_pair(const double *box, double eps, double par_s2, const P
                            const ShapeTab<double> &Di, const ShapeTab<double> &Dj, int fam, int x, int y, double sig,
                            Acc<T> &A)
 {
-    double Rd[9], Rjd[9];
-    quat_to_rot(ri.qw, ri.qx, ri.qy, ri.qz, Rd);
-    quat_to_rot(rj.qw, rj.qx, rj.qy, rj.qz, Rjd);
-    M3<double> Rr, Ri;
-    for (int a = 0; a < 3; ++a)
-        for (int c = 0; c < 3; ++c)
-            Rr.m[3 * a + c] = Rd[a] * Rjd[c] + Rd[3 + a] * Rjd[3 + c] + Rd[6 + a] * Rjd[6 + c];
-    for (int k = 0; k < 9; ++k) Ri.m[k] = Rd[k];
-    const V3<double> dd = v3<double>(min_image(rj.x - ri.x, box[0]), min_image(rj.y - ri.y, box[1]),
-                                     DIM == 3 ? min_image(rj.z - ri.z, box[2]) : 0.0);
-    const V3<double> td = mulT(Ri, dd);  // j's centre in i's frame
+    // the pair's transform as quaternions, which keeps few values live:
+    // qr = conj(q_i) q_j takes j's body frame to i's, td = conj(q_i) d is
+    // j's centre in i's frame
+    const double qi[4] = {ri.qw, -ri.qx, -ri.qy, -ri.qz};
+    const double qj[4] = {rj.qw, rj.qx, rj.qy, rj.qz};
+    double qr[4];
+    qmul(qi, qj, qr);
+    const double qrc[4] = {qr[0], -qr[1], -qr[2], -qr[3]};
+    const V3<double> dd = v3<double>(min_image_near(rj.x - ri.x, box[0]), min_image_near(rj.y - ri.y, box[1]),
+                                     DIM == 3 ? min_image_near(rj.z - ri.z, box[2]) : 0.0);
+    const V3<double> td = qrot(qi, dd);
     V3<double> P, rho;
     if (fam == 0) {
-        const V3<double> pt = mulT(Rr, ld3(Di.v[x]) - td);  // i's vertex in j's frame
+        const V3<double> pt = qrot(qrc, ld3(Di.v[x]) - td);  // i's vertex in j's frame
         const V3<double> q = (DIM == 3) ? face_point(Dj, y, pt)
                                         : seg_point(pt, ld3(Dj.v[Dj.e[y][0]]), ld3(Dj.ed[y]), Dj.einv[y]);
         P = ld3(Di.v[x]);
-        rho = mul(Rr, pt - q);
+        rho = qrot(qr, pt - q);
     } else if (fam == 1) {
-        const V3<double> pt = td + mul(Rr, ld3(Dj.v[x]));  // j's vertex in i's frame
+        const V3<double> pt = td + qrot(qr, ld3(Dj.v[x]));  // j's vertex in i's frame
         P = (DIM == 3) ? face_point(Di, y, pt) : seg_point(pt, ld3(Di.v[Di.e[y][0]]), ld3(Di.ed[y]), Di.einv[y]);
         rho = P - pt;
     } else {
-        const V3<double> b0 = td + mul(Rr, ld3(Dj.v[Dj.e[y][0]]));
-        const V3<double> d2 = mul(Rr, ld3(Dj.ed[y]));
+        const V3<double> b0 = td + qrot(qr, ld3(Dj.v[Dj.e[y][0]]));
+        const V3<double> d2 = qrot(qr, ld3(Dj.ed[y]));
         V3<double> Q;
         seg_seg(ld3(Di.v[Di.e[x][0]]), ld3(Di.ed[x]), Di.el2[x], Di.einv[x], b0, d2, Dj.el2[y], Dj.einv[y], par_s2,
                 P, Q);
