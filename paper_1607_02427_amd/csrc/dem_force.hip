@@ -519,8 +519,26 @@ constexpr int queue_slots(int lanes) { return kPairsPerWave + 64 / lanes; }
 // stage runs the feature prefilter, the per-problem cull and the exact
 // solves on them, so the costly stage runs on full waves.  A pair's result
 // does not depend on which group or round takes it.
-template <typename T, int DIM, int GL>
-__global__ void __launch_bounds__(64 * kWaves) k_pairs(BatchParams b, const SysParams *__restrict__ reps, StatePtrs s,
+// Work counter of one lane; the uncounted kernel keeps none (registers).
+template <bool ON>
+struct Tally {
+    unsigned v = 0;
+    __device__ void add(unsigned x) { v += x; }
+    __device__ unsigned get() const { return v; }
+};
+template <>
+struct Tally<false> {
+    __device__ void add(unsigned) {}
+    __device__ unsigned get() const { return 0; }
+};
+
+// OCC wavefronts per SIMD (2 or 3, a tuning knob): the kernel is
+// latency-bound, so more resident waves overlap more round trips, but at 3
+// the compiler must fit 168 registers and schedules with less freedom.  The
+// uncounted variants fit without spilling because the feature stage reads
+// the pair's transform from the LDS queue instead of holding it.
+template <typename T, int DIM, int GL, bool COUNT, int OCC>
+__global__ void __launch_bounds__(64 * kWaves, OCC) k_pairs(BatchParams b, const SysParams *__restrict__ reps, StatePtrs s,
                                                           ListPtrs l, const PartRec<T> *__restrict__ prec,
                                                           const PartRec64 *__restrict__ rec64,
                                                           SlotRec<T> *__restrict__ rec, const ShapeTab<T> *__restrict__ gtab,
@@ -528,6 +546,7 @@ __global__ void __launch_bounds__(64 * kWaves) k_pairs(BatchParams b, const SysP
                                                           unsigned long long *stats)
 {
     static_assert(GL == 8 || GL == 16, "8 or 16 lanes per pair");
+    static_assert(OCC == 2 || OCC == 3, "2 or 3 wavefronts per SIMD");
     constexpr int kGL = GL;                                    // lanes per particle pair
     constexpr int kGroups = 64 / kGL;                         // pairs per wave in the feature stage
     constexpr int kTile = kWaves * kPairsPerWave;             // pairs per block tile
@@ -554,7 +573,7 @@ __global__ void __launch_bounds__(64 * kWaves) k_pairs(BatchParams b, const SysP
     const int lb = (blockIdx.x & 7) * per + (blockIdx.x >> 3);
     const int t0 = (int)((long long)ntiles * lb / G), t1 = (int)((long long)ntiles * (lb + 1) / G);
     const T grow = T(1.00001);
-    unsigned c_pairs = 0, c_feat = 0, c_in = 0, c_near = 0, c_ee = 0, c_ref = 0, c_sep = 0, c_pv = 0;
+    Tally<COUNT> c_pairs, c_feat, c_in, c_near, c_ee, c_ref, c_sep, c_pv;
 
     int r = 0, r_end = 0;
     if (t0 < t1) {  // replica of the first tile: the last r with tile_start[r] <= t0
@@ -578,25 +597,20 @@ __global__ void __launch_bounds__(64 * kWaves) k_pairs(BatchParams b, const SysP
             // ---- second stage: group g takes queue entry head + g ----
             const int take = pending < kGroups ? pending : kGroups;
             const bool live = grp < take;
-            int4 ent = make_int4(0, 0, 0, 0);
+            // the entry stays in LDS for the whole round (nothing is queued
+            // before the next separation tile): the transform is read from
+            // there where it is used, which keeps registers free for the
+            // solves and the FP64 redo
+            const QEnt<T> &qe = qb[(head + grp) % kQCap];
+            const M3<T> &Rr = *reinterpret_cast<const M3<T> *>(qe.Rr);
             int si = 0, sj = 0;
-            M3<T> Rr, Ri;
-            V3<T> t = v3<T>(0, 0, 0), dv = v3<T>(0, 0, 0);
-            for (int k = 0; k < 9; ++k) Rr.m[k] = Ri.m[k] = T(0);
+            V3<T> t = v3<T>(0, 0, 0);
             if (live) {
-                const QEnt<T> &e = qb[(head + grp) % kQCap];
-                ent = e.ent;
-                si = e.si;
-                sj = e.sj;
-                for (int k = 0; k < 9; ++k) {
-                    Rr.m[k] = e.Rr[k];
-                    Ri.m[k] = e.Ri[k];
-                }
-                t = v3<T>(e.t[0], e.t[1], e.t[2]);
-                dv = v3<T>(e.d[0], e.d[1], e.d[2]);
+                si = qe.si;
+                sj = qe.sj;
+                t = v3<T>(qe.t[0], qe.t[1], qe.t[2]);
             }
             head += take;
-            const int i = ent.x, j = ent.y;
             const ShapeTab<T> &Si = tab[si];
             const ShapeTab<T> &Sj = tab[sj];
             const T par_s2 = (T)rl.par_s2;
@@ -700,7 +714,7 @@ __global__ void __launch_bounds__(64 * kWaves) k_pairs(BatchParams b, const SysP
             P.inv_fi = 1.0f / (float)(P.nfi > 0 ? P.nfi : 1);
             P.inv_ej = 1.0f / (float)(P.nej > 0 ? P.nej : 1);
             if (!live) total = 0;
-            if (sub == 0 && live) c_feat += total;
+            if (sub == 0 && live) c_feat.add(total);
 
             Acc<T> A0, A1;  // partial sums kVirt-canonical: sub and sub + GL
             A0.F = A0.Ti = A0.Tj = A1.F = A1.Ti = A1.Tj = v3<T>(0, 0, 0);
@@ -732,18 +746,18 @@ __global__ void __launch_bounds__(64 * kWaves) k_pairs(BatchParams b, const SysP
                             T sin2;
                             int e, g;
                             const int fam = P.solve(W.queue[k], par_s2, Pt, rho, sin2, e, g);
-                            c_near += fam < 2 ? 1 : 0;
-                            c_ee += fam == 2 ? 1 : 0;
+                            c_near.add(fam < 2 ? 1 : 0);
+                            c_ee.add(fam == 2 ? 1 : 0);
                             const T r2 = dot(rho, rho);
                             const bool redo = sizeof(T) == 4 &&
                                               ((r2 > T(0.99) * rc2 && r2 < T(1.0001) * rc2) ||
                                                (DIM == 3 && fam == 2 && sin2 < T(1e-2) && r2 < T(1.0001) * rc2 + T(1e-3) * rc));
                             if (redo) {
-                                c_ref += 1;
-                                c_in += refine_pair<T, DIM>(rl.box, rl.eps, rl.par_s2, rec64[i], rec64[j],
-                                                            gtab64[rl.sbase + si], gtab64[rl.sbase + sj], fam, e, g, rl.rad[si] + rl.rad[sj], A);
+                                c_ref.add(1);
+                                c_in.add(refine_pair<T, DIM>(rl.box, rl.eps, rl.par_s2, rec64[qe.ent.x], rec64[qe.ent.y],
+                                                            gtab64[rl.sbase + si], gtab64[rl.sbase + sj], fam, e, g, rl.rad[si] + rl.rad[sj], A));
                             } else {
-                                c_in += add_wca(A, Pt, rho, t, sig2, rc2, eps);
+                                c_in.add(add_wca(A, Pt, rho, t, sig2, rc2, eps));
                             }
                             Acc<T> &S = (kSets == 1 || (m & 1) == 0) ? A0 : A1;
                             S.F = S.F + A.F;
@@ -767,6 +781,11 @@ __global__ void __launch_bounds__(64 * kWaves) k_pairs(BatchParams b, const SysP
                     J2 = group_sum<kGL>(A0.Tj.z, A1.Tj.z);
             const T U = group_sum<kGL>(A0.U, A1.U);
             if (live && sub < 2) {  // lane 0 writes i's slot, lane 1 j's
+                const int4 ent = qe.ent;
+                const int i = ent.x, j = ent.y;
+                M3<T> Ri;
+                for (int k = 0; k < 9; ++k) Ri.m[k] = qe.Ri[k];
+                const V3<T> dv = v3<T>(qe.d[0], qe.d[1], qe.d[2]);
                 const V3<T> Fs = mul(Ri, v3<T>(F0, F1, F2));
                 const bool js = sub == 1;
                 const V3<T> Ts = mul(Ri, js ? v3<T>(J0, J1, J2) : v3<T>(I0, I1, I2));
@@ -871,7 +890,7 @@ __global__ void __launch_bounds__(64 * kWaves) k_pairs(BatchParams b, const SysP
                     for (int v = 0; v < kVP; ++v)
                         if (hj[v]) {
                             bi = bi && dot(n, wj[v]) - o > thr;
-                            ++c_pv;
+                            c_pv.add(1);
                         }
                 }
                 if (tj) {
@@ -881,7 +900,7 @@ __global__ void __launch_bounds__(64 * kWaves) k_pairs(BatchParams b, const SysP
                     for (int v = 0; v < kVP; ++v)
                         if (hi[v]) {
                             bj = bj && dot(n, wi[v]) - o > thr;
-                            ++c_pv;
+                            c_pv.add(1);
                         }
                 }
                 const unsigned long long mi = __ballot(bi), mj = __ballot(bj);
@@ -889,8 +908,8 @@ __global__ void __launch_bounds__(64 * kWaves) k_pairs(BatchParams b, const SysP
             }
             need = live && !sep;
             if (sub1 == 0 && live) {
-                c_pairs += 1;
-                c_sep += sep ? 1 : 0;
+                c_pairs.add(1);
+                c_sep.add(sep ? 1 : 0);
             }
             // queue the pairs that need the feature stage, one entry per group
             const unsigned long long m = __ballot(need && sub1 == 0);
@@ -925,8 +944,9 @@ __global__ void __launch_bounds__(64 * kWaves) k_pairs(BatchParams b, const SysP
         wave_sync_lds();  // the queue entries are visible to every lane
         ++tt;
     }
-    if (stats) {
-        const unsigned cnt[8] = {c_pairs, c_feat, c_in, c_near, c_ref, c_ee, c_sep, c_pv};
+    if (COUNT && stats) {
+        const unsigned cnt[8] = {c_pairs.get(), c_feat.get(), c_in.get(), c_near.get(), c_ref.get(), c_ee.get(),
+                                 c_sep.get(), c_pv.get()};
         const int slot[8] = {ST_PAIRS, ST_FEATURES, ST_INCUT, ST_NEAR, ST_REFINED, ST_EENEAR, ST_SEPARATED, ST_PLANETESTS};
 #pragma unroll
         for (int k = 0; k < 8; ++k) {
@@ -1162,13 +1182,31 @@ __global__ void k_rotations(BatchParams b, const SysParams *reps, StatePtrs s, L
     if (sizeof(T) == 4) rec64[i] = PartRec64{rc.x, rc.y, rc.z, s.qw[i], s.qx[i], s.qy[i], s.qz[i], 0.0};
 }
 
-template <typename T, int DIM, int GL>
+template <typename T, int DIM, int GL, int OCC>
+void pairs_t(const Launch &L, unsigned long long *stats, hipStream_t stream);
+
+template <typename T, int DIM>
+void pairs_shape(const Launch &L, unsigned long long *stats, hipStream_t stream)
+{
+    const bool g8 = L.b.pair_lanes == 8, o3 = L.b.pair_waves == 3;
+    if (g8) o3 ? pairs_t<T, DIM, 8, 3>(L, stats, stream) : pairs_t<T, DIM, 8, 2>(L, stats, stream);
+    else o3 ? pairs_t<T, DIM, 16, 3>(L, stats, stream) : pairs_t<T, DIM, 16, 2>(L, stats, stream);
+}
+
+template <typename T, int DIM, int GL, int OCC>
 void pairs_t(const Launch &L, unsigned long long *stats, hipStream_t stream)
 {
     const size_t sh = pair_kernel_lds(sizeof(T) == 4 ? DEM_FP32 : DEM_FP64, L.b.tab_slots, GL);
-    k_pairs<T, DIM, GL><<<L.b.pair_blocks, 64 * kWaves, sh, stream>>>(
-        L.b, L.reps, L.s, L.l, reinterpret_cast<const PartRec<T> *>(L.f.rot), L.f.rec64, reinterpret_cast<SlotRec<T> *>(L.f.rec),
-        reinterpret_cast<const ShapeTab<T> *>(L.f.tab), reinterpret_cast<const ShapeTab<double> *>(L.f.tab64), stats);
+    const auto rot = reinterpret_cast<const PartRec<T> *>(L.f.rot);
+    const auto rec = reinterpret_cast<SlotRec<T> *>(L.f.rec);
+    const auto tab = reinterpret_cast<const ShapeTab<T> *>(L.f.tab);
+    const auto tab64 = reinterpret_cast<const ShapeTab<double> *>(L.f.tab64);
+    if (stats)
+        k_pairs<T, DIM, GL, true, OCC><<<L.b.pair_blocks, 64 * kWaves, sh, stream>>>(
+            L.b, L.reps, L.s, L.l, rot, L.f.rec64, rec, tab, tab64, stats);
+    else
+        k_pairs<T, DIM, GL, false, OCC><<<L.b.pair_blocks, 64 * kWaves, sh, stream>>>(
+            L.b, L.reps, L.s, L.l, rot, L.f.rec64, rec, tab, tab64, nullptr);
 }
 
 template <typename T, int DIM>
@@ -1202,13 +1240,12 @@ void launch_rotations(const Launch &L, hipStream_t stream)
 void launch_pairs(const Launch &L, unsigned long long *stats, hipStream_t stream)
 {
     if (L.b.nchunk == 0) return;
-    const bool g8 = L.b.pair_lanes == 8;
     if (L.precision == DEM_FP32) {
-        if (L.b.dim == 3) g8 ? pairs_t<float, 3, 8>(L, stats, stream) : pairs_t<float, 3, 16>(L, stats, stream);
-        else g8 ? pairs_t<float, 2, 8>(L, stats, stream) : pairs_t<float, 2, 16>(L, stats, stream);
+        if (L.b.dim == 3) pairs_shape<float, 3>(L, stats, stream);
+        else pairs_shape<float, 2>(L, stats, stream);
     } else {
-        if (L.b.dim == 3) g8 ? pairs_t<double, 3, 8>(L, stats, stream) : pairs_t<double, 3, 16>(L, stats, stream);
-        else g8 ? pairs_t<double, 2, 8>(L, stats, stream) : pairs_t<double, 2, 16>(L, stats, stream);
+        if (L.b.dim == 3) pairs_shape<double, 3>(L, stats, stream);
+        else pairs_shape<double, 2>(L, stats, stream);
     }
 }
 
@@ -1233,25 +1270,28 @@ size_t pair_kernel_lds(int precision, int tab_slots, int lanes)
 }
 
 namespace {
-template <typename T, int DIM, int GL>
-hipError_t pair_occupancy(int *per_cu, size_t lds)
+template <typename T, int DIM>
+hipError_t pair_occupancy(int *per_cu, size_t lds, int lanes, int waves)
 {
-    return hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, k_pairs<T, DIM, GL>, 64 * kWaves, lds);
+    const int t = 64 * kWaves;
+    if (lanes == 8)
+        return waves == 3 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, k_pairs<T, DIM, 8, false, 3>, t, lds)
+                          : hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, k_pairs<T, DIM, 8, false, 2>, t, lds);
+    return waves == 3 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, k_pairs<T, DIM, 16, false, 3>, t, lds)
+                      : hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, k_pairs<T, DIM, 16, false, 2>, t, lds);
 }
 }  // namespace
 
-int pair_blocks_resident(int precision, int dim, int tab_slots, int lanes)
+int pair_blocks_resident(int precision, int dim, int tab_slots, int lanes, int waves)
 {
     const size_t lds = pair_kernel_lds(precision, tab_slots, lanes);
     int per_cu = 0, cus = 0, dev = 0;
     hipError_t e;
-    const bool g8 = lanes == 8;
     if (precision == DEM_FP32)
-        e = dim == 3 ? (g8 ? pair_occupancy<float, 3, 8>(&per_cu, lds) : pair_occupancy<float, 3, 16>(&per_cu, lds))
-                     : (g8 ? pair_occupancy<float, 2, 8>(&per_cu, lds) : pair_occupancy<float, 2, 16>(&per_cu, lds));
+        e = dim == 3 ? pair_occupancy<float, 3>(&per_cu, lds, lanes, waves) : pair_occupancy<float, 2>(&per_cu, lds, lanes, waves);
     else
-        e = dim == 3 ? (g8 ? pair_occupancy<double, 3, 8>(&per_cu, lds) : pair_occupancy<double, 3, 16>(&per_cu, lds))
-                     : (g8 ? pair_occupancy<double, 2, 8>(&per_cu, lds) : pair_occupancy<double, 2, 16>(&per_cu, lds));
+        e = dim == 3 ? pair_occupancy<double, 3>(&per_cu, lds, lanes, waves)
+                     : pair_occupancy<double, 2>(&per_cu, lds, lanes, waves);
     if (e != hipSuccess || hipGetDevice(&dev) != hipSuccess ||
         hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
         return 512;

@@ -24,6 +24,7 @@ constexpr int kChunk = 64;
 // straddle replicas.
 constexpr int kPairWaves = 4;
 constexpr int kDefaultPairLanes = 16;
+constexpr int kDefaultPairWaves = 2;
 constexpr int pair_tile() { return kPairWaves * 16; }
 
 // Per-replica device flag words (flags[r * FLAG_COUNT + w], one 64-byte
@@ -144,6 +145,7 @@ struct BatchParams {
     int tab_slots;               // shape tables of one replica staged in LDS
     int pair_blocks;             // grid of the pair kernel (a multiple of 8)
     int pair_lanes;              // lanes per particle pair in the pair kernel (8 or 16)
+    int pair_waves;              // its wavefronts per SIMD (2 or 3)
     int tile;                    // pairs per tile: pair_tile()
     int dim;
 };
@@ -261,7 +263,7 @@ __device__ inline void cell_insert(const SysParams &p, const ListPtrs &l, int i,
 // Dynamic LDS of the pair kernel, and how many of its blocks the device
 // holds at once.
 size_t pair_kernel_lds(int precision, int tab_slots, int lanes);
-int pair_blocks_resident(int precision, int dim, int tab_slots, int lanes);
+int pair_blocks_resident(int precision, int dim, int tab_slots, int lanes, int waves);
 
 // Per-particle records (position, rotation, shape id) from the state arrays.
 void launch_rotations(const Launch &L, hipStream_t stream);

@@ -79,8 +79,9 @@ struct dem_system {
     int dim = 0, precision = 0;
     bool auto_cap = true;
     bool counting = false;
-    int pair_lanes = kDefaultPairLanes;  // pair-kernel shape: lanes per pair
-    int pair_grid = 1;                   // and blocks per resident block slot
+    int pair_lanes = kDefaultPairLanes;  // pair-kernel shape: lanes per pair,
+    int pair_grid = 1;                   // blocks per resident block slot
+    int pair_waves = kDefaultPairWaves;  // and wavefronts per SIMD
     BatchParams bp{};
     std::vector<Replica> reps;
     SlotArena chunks, cells, shapes;
@@ -447,6 +448,7 @@ void refresh_batch(dem_system *h)
     b.nrep = 0;
     b.tab_slots = 1;
     b.pair_lanes = h->pair_lanes;
+    b.pair_waves = h->pair_waves;
     b.tile = pair_tile();
     long long tiles = 0;
     for (size_t r = 0; r < h->reps.size(); ++r) {
@@ -462,7 +464,7 @@ void refresh_batch(dem_system *h)
     // (a second round adds a whole block's latency but evens out the
     // tail), no more than the tiles use
     const long long resident =
-        (long long)pair_blocks_resident(h->precision, h->dim, b.tab_slots, b.pair_lanes) * h->pair_grid;
+        (long long)pair_blocks_resident(h->precision, h->dim, b.tab_slots, b.pair_lanes, b.pair_waves) * h->pair_grid;
     const long long want = std::max<long long>(8, std::min<long long>(tiles, resident));
     b.pair_blocks = (int)((want + 7) / 8 * 8);
 }
@@ -1378,15 +1380,17 @@ dem_status dem_time_forces(dem_handle h, int32_t reps, double *mean_ms)
     return DEM_OK;
 }
 
-dem_status dem_set_pair_shape(dem_handle h, int32_t lanes_per_pair, int32_t grid_factor)
+dem_status dem_set_pair_shape(dem_handle h, int32_t lanes_per_pair, int32_t grid_factor, int32_t waves_per_simd)
 {
     if (!h) return fail(nullptr, DEM_E_ARG, "null handle");
-    if ((lanes_per_pair != 8 && lanes_per_pair != 16) || grid_factor < 1 || grid_factor > 4)
-        return fail(h, DEM_E_ARG, "pair shape: %d lanes per pair (8 or 16), grid factor %d (1 to 4)", lanes_per_pair,
-                    grid_factor);
-    if (lanes_per_pair == h->pair_lanes && grid_factor == h->pair_grid) return DEM_OK;
+    if ((lanes_per_pair != 8 && lanes_per_pair != 16) || grid_factor < 1 || grid_factor > 4 ||
+        (waves_per_simd != 2 && waves_per_simd != 3))
+        return fail(h, DEM_E_ARG, "pair shape: %d lanes per pair (8 or 16), grid factor %d (1 to 4), %d waves per SIMD "
+                    "(2 or 3)", lanes_per_pair, grid_factor, waves_per_simd);
+    if (lanes_per_pair == h->pair_lanes && grid_factor == h->pair_grid && waves_per_simd == h->pair_waves) return DEM_OK;
     h->pair_lanes = lanes_per_pair;
     h->pair_grid = grid_factor;
+    h->pair_waves = waves_per_simd;
     refresh_batch(h);
     launch_lists(make_launch(h), LISTS_PLAN, h->stream);  // tiles of the new size
     HIPCHK(h, hipGetLastError());
@@ -1394,14 +1398,15 @@ dem_status dem_set_pair_shape(dem_handle h, int32_t lanes_per_pair, int32_t grid
     return DEM_OK;
 }
 
-dem_status dem_tune_pairs(dem_handle h, int32_t reps, int32_t *lanes_per_pair, int32_t *grid_factor, double *mean_ms)
+dem_status dem_tune_pairs(dem_handle h, int32_t reps, int32_t *shape, double *mean_ms)
 {
     if (!h || reps < 1) return fail(h, DEM_E_ARG, "bad argument");
-    static const int kShapes[DEM_PAIR_SHAPES][2] = {{16, 1}, {8, 1}, {16, 2}, {8, 2}};
+    static const int kShapes[DEM_PAIR_SHAPES][3] = {{16, 1, 2}, {8, 1, 2}, {16, 2, 2}, {8, 2, 2},
+                                                    {16, 1, 3}, {8, 1, 3}, {16, 2, 3}, {8, 2, 3}};
     double best = 0.0;
     int pick = 0;
     for (int k = 0; k < DEM_PAIR_SHAPES; ++k) {
-        dem_status st = dem_set_pair_shape(h, kShapes[k][0], kShapes[k][1]);
+        dem_status st = dem_set_pair_shape(h, kShapes[k][0], kShapes[k][1], kShapes[k][2]);
         double ms = 0.0;
         if (st == DEM_OK) st = dem_time_forces(h, reps, &ms);
         if (st != DEM_OK) return st;
@@ -1411,10 +1416,10 @@ dem_status dem_tune_pairs(dem_handle h, int32_t reps, int32_t *lanes_per_pair, i
             pick = k;
         }
     }
-    dem_status st = dem_set_pair_shape(h, kShapes[pick][0], kShapes[pick][1]);
+    dem_status st = dem_set_pair_shape(h, kShapes[pick][0], kShapes[pick][1], kShapes[pick][2]);
     if (st != DEM_OK) return st;
-    if (lanes_per_pair) *lanes_per_pair = kShapes[pick][0];
-    if (grid_factor) *grid_factor = kShapes[pick][1];
+    if (shape)
+        for (int a = 0; a < 3; ++a) shape[a] = kShapes[pick][a];
     return DEM_OK;
 }
 

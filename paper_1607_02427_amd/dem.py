@@ -106,9 +106,9 @@ def lib():
         L.dem_set_counting.restype = st
         L.dem_time_forces.argtypes = [C.c_void_p, C.c_int32, _dp]
         L.dem_time_forces.restype = st
-        L.dem_set_pair_shape.argtypes = [C.c_void_p, C.c_int32, C.c_int32]
+        L.dem_set_pair_shape.argtypes = [C.c_void_p, C.c_int32, C.c_int32, C.c_int32]
         L.dem_set_pair_shape.restype = st
-        L.dem_tune_pairs.argtypes = [C.c_void_p, C.c_int32, _ip, _ip, _dp]
+        L.dem_tune_pairs.argtypes = [C.c_void_p, C.c_int32, _ip, _dp]
         L.dem_tune_pairs.restype = st
         L.dem_footprint_bytes.argtypes = [C.POINTER(Params)]
         L.dem_footprint_bytes.restype = C.c_size_t
@@ -256,15 +256,16 @@ def _lists_np(call, n, ncell, cap):
                 nbr=nb[: cap * n].reshape(cap, n) if n else nb[:0].reshape(cap, 0), n_nbr=nn[:n])
 
 
-PAIR_SHAPES = ((16, 1), (8, 1), (16, 2), (8, 2))  # the tuner's candidates, in dem_tune_pairs order
+# the tuner's candidates (lanes per pair, grid factor, waves per SIMD), in dem_tune_pairs order
+PAIR_SHAPES = ((16, 1, 2), (8, 1, 2), (16, 2, 2), (8, 2, 2), (16, 1, 3), (8, 1, 3), (16, 2, 3), (8, 2, 3))
 
 
 def _tune_pairs(check, h, reps):
-    lanes, grid = C.c_int32(), C.c_int32()
+    shape = (C.c_int32 * 3)()
     ms = (C.c_double * len(PAIR_SHAPES))()
-    check(lib().dem_tune_pairs(h, int(reps), C.byref(lanes), C.byref(grid), ms), "dem_tune_pairs")
-    return dict(lanes=lanes.value, grid=grid.value,
-                mean_ms={f"{a}x{b}": ms[k] for k, (a, b) in enumerate(PAIR_SHAPES)})
+    check(lib().dem_tune_pairs(h, int(reps), shape, ms), "dem_tune_pairs")
+    return dict(lanes=shape[0], grid=shape[1], waves=shape[2],
+                mean_ms={f"{a}x{b}x{c}": ms[k] for k, (a, b, c) in enumerate(PAIR_SHAPES)})
 
 
 class DemSystem:
@@ -345,9 +346,10 @@ class DemSystem:
         return dict(pairs=out[0], features=out[1], in_cutoff=out[2], launches=out[3], vf_near=out[4],
                     refined=out[5], ee_near=out[6], separated=out[7], plane_tests=out[8])
 
-    def set_pair_shape(self, lanes: int, grid: int = 1):
-        """Pair-kernel launch shape (8 or 16 lanes per pair, grid factor 1..4); results do not change."""
-        self._check(lib().dem_set_pair_shape(self.h, int(lanes), int(grid)), "dem_set_pair_shape")
+    def set_pair_shape(self, lanes: int, grid: int = 1, waves: int = 2):
+        """Pair-kernel launch shape (8 or 16 lanes per pair, grid factor 1..4, 2 or 3 waves per SIMD);
+        results do not change."""
+        self._check(lib().dem_set_pair_shape(self.h, int(lanes), int(grid), int(waves)), "dem_set_pair_shape")
 
     def tune_pairs(self, reps: int = 20) -> dict:
         """Times every pair-kernel shape on the current state and keeps the fastest."""
@@ -498,8 +500,8 @@ class DemBatch:
     def set_counting(self, on: bool):
         self._check(lib().dem_set_counting(self.h, 1 if on else 0), "dem_set_counting")
 
-    def set_pair_shape(self, lanes: int, grid: int = 1):
-        self._check(lib().dem_set_pair_shape(self.h, int(lanes), int(grid)), "dem_set_pair_shape")
+    def set_pair_shape(self, lanes: int, grid: int = 1, waves: int = 2):
+        self._check(lib().dem_set_pair_shape(self.h, int(lanes), int(grid), int(waves)), "dem_set_pair_shape")
 
     def tune_pairs(self, reps: int = 5) -> dict:
         return _tune_pairs(self._check, self.h, reps)
