@@ -31,7 +31,8 @@ FLOPS = {
     "pair": 60,        # relative rotation R_i^T R_j and offset R_i^T d (once per particle pair)
     "sep_vertex": 18,  # vertex carried into the other body's frame for the separation test (nv_i + nv_j per pair)
     "plane_test": 6,   # one vertex against one supporting plane
-    "vertex": 23,      # vertex carried across again + reach test (nv_i + nv_j per pair not separated)
+    "vertex": 23,      # vertex carried across again + reach test (nv_i + nv_j per pair not separated),
+                       # plus one plane_test per supporting plane of the other body
     "edge": 12,        # edge reach test (ne_i + ne_j per pair)
     "face": 12,        # face reach test (nf_i + nf_j per pair)
     "cull": 17,        # per-problem test: plane + bounding circle, or segment bounding spheres
@@ -96,7 +97,9 @@ def force_roofline(g, system, reps=200):
         problems = 2 * shp.nv * shp.ne * FLOPS["ve_solve"]
     algorithmic = st["pairs"] * (FLOPS["pair"] + problems) + st["in_cutoff"] * FLOPS["wca"]
     per_pair = FLOPS["pair"] + 2 * shp.nv * FLOPS["sep_vertex"]
-    per_feature_pair = 2 * (shp.nv * FLOPS["vertex"] + shp.ne * FLOPS["edge"] + shp.nf * FLOPS["face"])
+    planes = shp.nf if system.dim == 3 else shp.ne  # supporting planes of a convex body
+    per_feature_pair = 2 * (shp.nv * (FLOPS["vertex"] + planes * FLOPS["plane_test"]) + shp.ne * FLOPS["edge"]
+                            + shp.nf * FLOPS["face"])
     executed = (st["pairs"] * per_pair + st["plane_tests"] * FLOPS["plane_test"]
                 + (st["pairs"] - st["separated"]) * per_feature_pair + st["features"] * FLOPS["cull"]
                 + st["vf_near"] * FLOPS["vf_solve"] + st["ee_near"] * FLOPS["ee_solve"] + st["in_cutoff"] * FLOPS["wca"])

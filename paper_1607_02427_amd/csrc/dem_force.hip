@@ -193,6 +193,9 @@ struct PairLds {
     unsigned char vi_near[DEM_MAX_VERTS], vj_near[DEM_MAX_VERTS];
     unsigned char ei_near[DEM_MAX_EDGES], ej_near[DEM_MAX_EDGES];
     unsigned char fi_near[DEM_MAX_FACES], fj_near[DEM_MAX_FACES];
+    // supporting planes of the other body that each vertex lies more than
+    // r_cut beyond (bit p: plane p)
+    unsigned vib[DEM_MAX_VERTS], vjb[DEM_MAX_VERTS];
     unsigned short queue[kQueue];
 };
 
@@ -629,7 +632,11 @@ __global__ void __launch_bounds__(64 * kWaves, OCC) k_pairs(BatchParams b, const
             // Feature prefilter (conservative): a vertex, edge or face can touch
             // the other body only if it lies within R_other + r_cut of that body's
             // centre, widened by the edge half length or the face's bounding
-            // radius.  One lane per feature; survivors are listed by index.
+            // radius, and if it is not wholly more than r_cut beyond one of
+            // the other body's supporting planes (for an edge or a face: all
+            // its vertices beyond the same plane).  One lane per feature;
+            // survivors are listed by index.
+            const T thr = rcm + T(1e-5) * (Bi + Bj);
             int cvj = 0, cvi = 0;
             for (int v0 = 0; v0 < DEM_MAX_VERTS; v0 += kGL) {
                 const int vk = v0 + sub;
@@ -639,14 +646,20 @@ __global__ void __launch_bounds__(64 * kWaves, OCC) k_pairs(BatchParams b, const
                     W.vj[vk][0] = v.x;
                     W.vj[vk][1] = v.y;
                     W.vj[vk][2] = v.z;
-                    nj = dot(v, v) < grow * Bi * Bi;
+                    unsigned mb = 0;
+                    for (int p = 0; p < Si.nsep; ++p) mb |= (dot(ld3(Si.sn[p]), v) - Si.so[p] > thr ? 1u : 0u) << p;
+                    W.vjb[vk] = mb;
+                    nj = mb == 0 && dot(v, v) < grow * Bi * Bi;
                 }
                 if (live && vk < Si.nv) {
                     const V3<T> v = mulT(Rr, ld3(Si.v[vk]) - t);
                     W.vi[vk][0] = v.x;
                     W.vi[vk][1] = v.y;
                     W.vi[vk][2] = v.z;
-                    ni = dot(v, v) < grow * Bj * Bj;
+                    unsigned mb = 0;
+                    for (int p = 0; p < Sj.nsep; ++p) mb |= (dot(ld3(Sj.sn[p]), v) - Sj.so[p] > thr ? 1u : 0u) << p;
+                    W.vib[vk] = mb;
+                    ni = mb == 0 && dot(v, v) < grow * Bj * Bj;
                 }
                 cvj = group_append(nj, W.vj_near, cvj, vk, gmask, below);
                 cvi = group_append(ni, W.vi_near, cvi, vk, gmask, below);
@@ -660,12 +673,12 @@ __global__ void __launch_bounds__(64 * kWaves, OCC) k_pairs(BatchParams b, const
                 if (live && e < Si.ne) {
                     const V3<T> d = ld3(Si.em[e]) - t;
                     const T lim = Bj + Si.eh[e];
-                    ne = dot(d, d) < grow * lim * lim;
+                    ne = (W.vib[Si.e[e][0]] & W.vib[Si.e[e][1]]) == 0 && dot(d, d) < grow * lim * lim;
                 }
                 if (live && e < Sj.ne) {
                     const V3<T> m = T(0.5) * (ld3(W.vj[Sj.e[e][0]]) + ld3(W.vj[Sj.e[e][1]]));
                     const T lim = Bi + Sj.eh[e];
-                    me = dot(m, m) < grow * lim * lim;
+                    me = (W.vjb[Sj.e[e][0]] & W.vjb[Sj.e[e][1]]) == 0 && dot(m, m) < grow * lim * lim;
                 }
                 cei = group_append(ne, W.ei_near, cei, e, gmask, below);
                 cej = group_append(me, W.ej_near, cej, e, gmask, below);
@@ -680,12 +693,16 @@ __global__ void __launch_bounds__(64 * kWaves, OCC) k_pairs(BatchParams b, const
                     if (live && f < Si.nf) {
                         const V3<T> d = ld3(Si.fc[f]) - t;
                         const T lim = Bj + Si.frad[f];
-                        nf = dot(d, d) < grow * lim * lim;
+                        unsigned all = ~0u;
+                        for (int k = Si.foff[f]; k < Si.foff[f + 1]; ++k) all &= W.vib[Si.floop[k]];
+                        nf = all == 0 && dot(d, d) < grow * lim * lim;
                     }
                     if (live && f < Sj.nf) {
                         const V3<T> d = ld3(Sj.fc[f]) - ti;
                         const T lim = Bi + Sj.frad[f];
-                        mf = dot(d, d) < grow * lim * lim;
+                        unsigned all = ~0u;
+                        for (int k = Sj.foff[f]; k < Sj.foff[f + 1]; ++k) all &= W.vjb[Sj.floop[k]];
+                        mf = all == 0 && dot(d, d) < grow * lim * lim;
                     }
                     cfi = group_append(nf, W.fi_near, cfi, f, gmask, below);
                     cfj = group_append(mf, W.fj_near, cfj, f, gmask, below);
