@@ -41,6 +41,8 @@ FLOPS = {
     "ve_solve": 20,    # 2D point-segment nearest point and offset
     "wca": 56,         # WCA energy/force, accumulation of F, both torques and U
 }
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_k_pairs_cubes4096.txt")
+PAIR_SOURCES = [os.path.join(ROOT, "paper_1607_02427_amd", "csrc", f) for f in ("dem_force.hip", "dem_internal.h")]
 PEAK_FP32 = 157.3e12   # MI355X FP32 vector, published (needs packed FP32)
 PEAK_FP32_NONPACKED = 78.6e12  # one FP32 lane operation per cycle, the rate this build's code can reach
 PEAK_HBM = 8.0e12
@@ -76,6 +78,45 @@ def run_path(system, precision, steps, warmup, counting=False, tune=True):
     return g, dict(wall_s=wall, gpu_ms=gpu_ms, energy=en, pair_shape=shape)
 
 
+def pair_sources_digest():
+    import hashlib
+    h = hashlib.sha256()
+    for p in PAIR_SOURCES:
+        with open(p, "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
+def measured_traffic():
+    """HBM bytes per k_pairs launch from the committed counter summary, if it
+    was taken on the kernel as it is now (same source digest), else None."""
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    vals = {}
+    for line in open(TRAFFIC_FILE):
+        if ":" in line:
+            k, v = line.split(":", 1)
+            vals[k.strip()] = v.strip()
+    if vals.get("source_sha256") != pair_sources_digest():
+        return None
+    try:
+        return float(vals["fetch_bytes_per_launch"]) + float(vals["write_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def copy_calibration(mb):
+    """A plain device copy of known size, for scaling the HBM byte counters."""
+    import torch
+    n = int(mb) * (1 << 20) // 4
+    src = torch.ones(n, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(5):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    log(f"[bench] copy calibration: 5 copies of {mb} MiB")
+
+
 def force_roofline(g, system, reps=200):
     """Work counters of one force launch on the current state, and the mean
     launch duration of the force kernel alone (HIP events on its stream).
@@ -105,7 +146,7 @@ def force_roofline(g, system, reps=200):
                 + st["vf_near"] * FLOPS["vf_solve"] + st["ee_near"] * FLOPS["ee_solve"] + st["in_cutoff"] * FLOPS["wca"])
     t = mean_ms * 1e-3
     return dict(bound="alu", achieved=algorithmic / t / 1e12, peak=PEAK_FP32 / 1e12, unit="TFLOP/s",
-                frac=algorithmic / t / PEAK_FP32, traffic=None, kernel="k_pairs<float,3>",
+                frac=algorithmic / t / PEAK_FP32, traffic=measured_traffic(), kernel="k_pairs<float,3>",
                 mean_launch_ms=mean_ms, flops_per_launch=algorithmic,
                 executed_tflops=executed / t / 1e12, executed_frac=executed / t / PEAK_FP32,
                 executed_flops_per_launch=executed, peak_fp32_nonpacked=PEAK_FP32_NONPACKED / 1e12,
@@ -189,6 +230,8 @@ def main():
     ap.add_argument("--no-served", action="store_true")
     ap.add_argument("--no-scale", action="store_true", help="skip the 262,144-octahedra run")
     ap.add_argument("--scale-steps", type=int, default=300)
+    ap.add_argument("--copy-mb", type=int, default=0,
+                    help="finish with device copies of this many MiB (scale for the HBM byte counters)")
     ap.add_argument("--no-sequential", action="store_true",
                     help="skip the one-at-a-time plain FP64 runs of the batched and served workloads")
     args = ap.parse_args()
@@ -284,6 +327,8 @@ def main():
             "sequential_plain_fp64": None if sqs is None else {
                 "p50_latency_s": sqs["p50_latency_s"], "p99_latency_s": sqs["p99_latency_s"], "value": sqs["value"],
                 "makespan_s": sqs["makespan_s"]}}
+    if args.copy_mb > 0:
+        copy_calibration(args.copy_mb)
     if not args.no_cpu:
         log("[bench] cpu oracle baseline")
         line["cpu_baseline"] = cpu_baseline(system, args.cpu_seconds)
