@@ -572,6 +572,7 @@ __global__ void __launch_bounds__(64 * kWaves, OCC) k_pairs(BatchParams b, const
     const unsigned long long below = lanes_below();
     const size_t N = (size_t)b.N;
     const int ntiles = l.tile_start[b.nrep];
+    const unsigned stamp = (unsigned)l.gflags[G_STAMP];
     const int G = gridDim.x, per = G >> 3;
     const int lb = (blockIdx.x & 7) * per + (blockIdx.x >> 3);
     const int t0 = (int)((long long)ntiles * lb / G), t1 = (int)((long long)ntiles * (lb + 1) / G);
@@ -820,7 +821,8 @@ __global__ void __launch_bounds__(64 * kWaves, OCC) k_pairs(BatchParams b, const
                     w.d[0] = sg * dv.x;
                     w.d[1] = sg * dv.y;
                     w.d[2] = sg * dv.z;
-                    w.pad0 = w.pad1 = T(0);
+                    w.pad1 = T(0);
+                    set_stamp(w, stamp);
                     rec[(size_t)slot * N + (js ? j : i)] = w;
                 }
             }
@@ -948,16 +950,6 @@ __global__ void __launch_bounds__(64 * kWaves, OCC) k_pairs(BatchParams b, const
             }
             tail += __popcll(m);
         }
-        if (active && !need && sub1 < 2) {  // out of reach or separated: zero both row slots
-            const int slot = sub1 == 1 ? ent.w : ent.z;
-            if (slot >= 0) {
-                SlotRec<T> w;
-                w.F[0] = w.F[1] = w.F[2] = w.U = T(0);
-                w.tq[0] = w.tq[1] = w.tq[2] = w.pad0 = T(0);
-                w.d[0] = w.d[1] = w.d[2] = w.pad1 = T(0);
-                rec[(size_t)slot * N + (sub1 == 1 ? j : i)] = w;
-            }
-        }
         wave_sync_lds();  // the queue entries are visible to every lane
         ++tt;
     }
@@ -1056,6 +1048,7 @@ __global__ void __launch_bounds__(kGatherBlock) k_gather(BatchParams b, const Sy
     for (int c = 0; c < 16; ++c) acc[c] = 0.0;  // F[3], T[3], U, W[9]
     if (mine) {
         const int m = l.n_nbr[i];
+        const unsigned stamp = (unsigned)l.gflags[G_STAMP];  // records of this evaluation only
         // slots in batches: every load of a batch is issued before any of
         // its sums, so the batch's memory round trips overlap
         int k = sub;
@@ -1065,9 +1058,13 @@ __global__ void __launch_bounds__(kGatherBlock) k_gather(BatchParams b, const Sy
             for (int u = 0; u < kGatherBatch; ++u) w[u] = rec[(size_t)(k + u * kGatherLanes) * N + i];
             __builtin_amdgcn_sched_barrier(0);  // keep the loads ahead of the sums
 #pragma unroll
-            for (int u = 0; u < kGatherBatch; ++u) add_slot(acc, w[u]);
+            for (int u = 0; u < kGatherBatch; ++u)
+                if (slot_stamp(w[u]) == stamp) add_slot(acc, w[u]);
         }
-        for (; k < m; k += kGatherLanes) add_slot(acc, rec[(size_t)k * N + i]);
+        for (; k < m; k += kGatherLanes) {
+            const SlotRec<T> w = rec[(size_t)k * N + i];
+            if (slot_stamp(w) == stamp) add_slot(acc, w);
+        }
     }
     for (int off = 1; off < kGatherLanes; off <<= 1)
         for (int c = 0; c < 16; ++c) acc[c] += __shfl_xor(acc[c], off, kGatherLanes);

@@ -150,6 +150,7 @@ __global__ void __launch_bounds__(kBlock) k_kick_drift(BatchParams b, const SysP
                                                           void *rot, PartRec64 *rec64)
 {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i == 0) l.gflags[G_STAMP] += 1;  // this step's force evaluation
     const int r = wave_replica(b, l, i);
     if (r < 0) return;
     const SysParams &p = reps[r];

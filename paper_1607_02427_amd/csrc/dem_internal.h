@@ -37,7 +37,9 @@ enum Flag {
 };
 // Batch-wide words: how many replicas rebuild their lists in the current
 // step (the list kernels return at once when none does).
-enum GWord { G_ANY = 0, G_COUNT = 4 };
+// G_STAMP: number of the current force evaluation (bumped before every
+// launch of the pair kernel in a step or a force computation).
+enum GWord { G_ANY = 0, G_STAMP = 1, G_COUNT = 4 };
 // Particles one cell can hold, and the longest neighbour row.
 constexpr int kCellCap = 64;
 constexpr int kRowMax = 128;
@@ -68,6 +70,14 @@ struct alignas(16) SlotRec {
     T tq[3], pad0;
     T d[3], pad1;
 };
+// The first pad word carries the G_STAMP of the force evaluation that wrote
+// the record.  The gather adds only records of the current evaluation, so a
+// pair with no feature pair inside the cutoff writes nothing at all.
+// (Storage starts zeroed: a record never written adds zeros.)
+__device__ inline unsigned slot_stamp(const SlotRec<float> &w) { return __float_as_uint(w.pad0); }
+__device__ inline unsigned slot_stamp(const SlotRec<double> &w) { return (unsigned)__double_as_longlong(w.pad0); }
+__device__ inline void set_stamp(SlotRec<float> &w, unsigned s) { w.pad0 = __uint_as_float(s); }
+__device__ inline void set_stamp(SlotRec<double> &w, unsigned s) { w.pad0 = __longlong_as_double((long long)s); }
 
 // Body-frame feature tables of one shape in precision T, staged in LDS.
 // Edges carry their vector, midpoint, half length and 1/|edge|^2; faces

@@ -133,6 +133,7 @@ dem_status fail(dem_system *h, dem_status s, const char *fmt, ...)
     } while (0)
 
 __global__ void k_set_i32(int32_t *p, int32_t v) { *p = v; }
+__global__ void k_bump(int32_t *p) { *p += 1; }
 __global__ void k_set_i64(int64_t *p, int64_t v) { *p = v; }
 // A replica without particles advances by bookkeeping only.
 __global__ void k_advance_empty(int64_t *budget, int64_t *steps, int64_t n)
@@ -531,6 +532,8 @@ dem_status alloc_nbr(dem_system *h, int cap)
     if (hipMalloc(&h->lst.pairs, sizeof(int4) * maxp) != hipSuccess ||
         hipMalloc(&h->rec, rec_bytes(h->precision) * (size_t)cap * N) != hipSuccess)
         return fail(h, DEM_E_OOM, "neighbour list of %d x %zu entries", cap, N);
+    // records never written read as zeros (stamp 0, no force)
+    HIPCHK(h, hipMemsetAsync(h->rec, 0, rec_bytes(h->precision) * (size_t)cap * N, h->stream));
     h->bp.cap = cap;
     place_pairs(h);
     dem_status st = upload_tables(h);
@@ -879,6 +882,7 @@ void release_replica(dem_system *h, int r)
 dem_status compute_forces(dem_system *h)
 {
     const Launch L = make_launch(h);
+    k_bump<<<1, 1, 0, h->stream>>>(h->lst.gflags + G_STAMP);  // a new force evaluation
     launch_rotations(L, h->stream);
     launch_pairs(L, h->stats, h->stream);
     launch_gather(L, false, h->stream);
