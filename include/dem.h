@@ -164,6 +164,39 @@ dem_status dem_compute_forces(dem_handle h);
  * reported xi, eta are those at the end of the last step. */
 dem_status dem_step(dem_handle h, int64_t n_steps);
 
+/* dem_step under the batch name: on a batch handle every live replica
+ * advances up to n_steps steps, each stopping at its own step budget. */
+dem_status dem_batch_step(dem_handle h, int64_t n_steps);
+
+/* Where the handle's results live on the device: the force outputs (for a
+ * single system the caller's own arrays; for a batch its internal ones,
+ * replica r at particle slots [offset, offset + n) of dem_batch_info) with
+ * the virial's stride (W[c * w_stride + i]), and the neighbour rows,
+ * library-owned: nbr[k * nbr_stride + i] for k < n_nbr[i], ascending, at
+ * most capacity per row.  The addresses stay valid until a call changes the
+ * row capacity or destroys the handle. */
+typedef struct {
+    const double *Fx, *Fy, *Fz, *Tx, *Ty, *Tz, *U, *W;
+    int64_t w_stride;
+    const int32_t *nbr, *n_nbr;
+    int64_t nbr_stride;
+    int32_t capacity;
+} dem_output_view;
+dem_status dem_get_outputs(dem_handle h, dem_output_view *out);
+
+/* Checkpoint of a single system (the whole state and the thermostat, so a
+ * run resumed from it continues bit for bit as the original would have).
+ * dem_state_bytes gives the buffer size (0 for a batch handle or a null
+ * handle).  dem_get_state synchronises and writes the checkpoint to a host
+ * buffer of at least that size; dem_set_state reads one back (same
+ * dimension and particle count), rebuilds the lists, recomputes the forces
+ * and clears latched device errors.  DEM_E_ARG for a short buffer, a
+ * foreign or mismatched checkpoint or a batch handle (whose replicas are
+ * saved with dem_batch_read and restored with dem_batch_add). */
+size_t dem_state_bytes(dem_handle h);
+dem_status dem_get_state(dem_handle h, void *host_buf, size_t bytes);
+dem_status dem_set_state(dem_handle h, const void *host_buf, size_t bytes);
+
 /* Reduces energies, kinetic terms, virial and thermostat state in FP64 and
  * reports latched device errors.  Synchronises. */
 dem_status dem_energy(dem_handle h, dem_energy_out *out);

@@ -1384,6 +1384,116 @@ dem_status dem_time_forces(dem_handle h, int32_t reps, double *mean_ms)
     return DEM_OK;
 }
 
+dem_status dem_batch_step(dem_handle h, int64_t n_steps) { return dem_step(h, n_steps); }
+
+dem_status dem_get_outputs(dem_handle h, dem_output_view *o)
+{
+    if (!h || !o) return fail(h, DEM_E_ARG, "null argument");
+    o->Fx = h->out.Fx;
+    o->Fy = h->out.Fy;
+    o->Fz = h->out.Fz;
+    o->Tx = h->out.Tx;
+    o->Ty = h->out.Ty;
+    o->Tz = h->out.Tz;
+    o->U = h->out.U;
+    o->W = h->out.W;
+    o->w_stride = h->bp.wstride;
+    o->nbr = h->lst.nbr;
+    o->n_nbr = h->lst.n_nbr;
+    o->nbr_stride = h->bp.N;
+    o->capacity = h->bp.cap;
+    return DEM_OK;
+}
+
+// Checkpoint layout: this header, then x, y, z, qw, qx, qy, qz, vx, vy, vz,
+// Lx, Ly, Lz (n doubles each; z is zero in 2D), shape id (n int32) and
+// image (3n int32).
+struct CheckpointHeader {
+    char magic[8];
+    int32_t version, dim;
+    int64_t n, step, n_rebuilds;
+    double thermo[TH_COUNT];
+};
+constexpr char kCheckpointMagic[8] = {'D', 'E', 'M', 'C', 'K', 'P', 'T', '1'};
+
+size_t dem_state_bytes(dem_handle h)
+{
+    if (!h || h->batch || !valid_replica(h, 0)) return 0;
+    const size_t n = (size_t)h->reps[0].sp.n;
+    return sizeof(CheckpointHeader) + n * (13 * sizeof(double) + 4 * sizeof(int32_t));
+}
+
+dem_status dem_get_state(dem_handle h, void *host_buf, size_t bytes)
+{
+    if (!h || !host_buf) return fail(h, DEM_E_ARG, "null argument");
+    if (h->batch || !valid_replica(h, 0)) return fail(h, DEM_E_ARG, "checkpoints are for single systems");
+    const size_t need = dem_state_bytes(h);
+    if (bytes < need) return fail(h, DEM_E_ARG, "checkpoint buffer of %zu bytes, %zu needed", bytes, need);
+    const size_t n = (size_t)h->reps[0].sp.n;
+    unsigned char *b = static_cast<unsigned char *>(host_buf);
+    CheckpointHeader hd{};
+    std::memcpy(hd.magic, kCheckpointMagic, 8);
+    hd.version = 1;
+    hd.dim = h->dim;
+    hd.n = (int64_t)n;
+    int32_t nb = 0;
+    HIPCHK(h, hipMemcpyAsync(hd.thermo, h->thermo, sizeof hd.thermo, hipMemcpyDeviceToHost, h->stream));
+    HIPCHK(h, hipMemcpyAsync(&hd.step, h->steps, sizeof hd.step, hipMemcpyDeviceToHost, h->stream));
+    HIPCHK(h, hipMemcpyAsync(&nb, h->lst.flags + FLAG_NBUILDS, sizeof nb, hipMemcpyDeviceToHost, h->stream));
+    double *dst = reinterpret_cast<double *>(b + sizeof hd);
+    double *const cols[13] = {h->st.x, h->st.y, h->st.z, h->st.qw, h->st.qx, h->st.qy, h->st.qz,
+                              h->st.vx, h->st.vy, h->st.vz, h->st.Lx, h->st.Ly, h->st.Lz};
+    for (int c = 0; c < 13; ++c) {
+        if (cols[c] && n) HIPCHK(h, hipMemcpyAsync(dst + c * n, cols[c], sizeof(double) * n, hipMemcpyDeviceToHost, h->stream));
+        else std::memset(dst + c * n, 0, sizeof(double) * n);
+    }
+    int32_t *idst = reinterpret_cast<int32_t *>(dst + 13 * n);
+    if (n) {
+        HIPCHK(h, hipMemcpyAsync(idst, h->st.sid, sizeof(int32_t) * n, hipMemcpyDeviceToHost, h->stream));
+        HIPCHK(h, hipMemcpyAsync(idst + n, h->st.image, sizeof(int32_t) * 3 * n, hipMemcpyDeviceToHost, h->stream));
+    }
+    HIPCHK(h, hipStreamSynchronize(h->stream));
+    hd.n_rebuilds = nb;
+    std::memcpy(b, &hd, sizeof hd);
+    return DEM_OK;
+}
+
+dem_status dem_set_state(dem_handle h, const void *host_buf, size_t bytes)
+{
+    if (!h || !host_buf) return fail(h, DEM_E_ARG, "null argument");
+    if (h->batch || !valid_replica(h, 0)) return fail(h, DEM_E_ARG, "checkpoints are for single systems");
+    const size_t n = (size_t)h->reps[0].sp.n;
+    if (bytes < sizeof(CheckpointHeader)) return fail(h, DEM_E_ARG, "checkpoint too short");
+    CheckpointHeader hd;
+    std::memcpy(&hd, host_buf, sizeof hd);
+    if (std::memcmp(hd.magic, kCheckpointMagic, 8) != 0 || hd.version != 1)
+        return fail(h, DEM_E_ARG, "not a checkpoint of this library");
+    if (hd.dim != h->dim || hd.n != (int64_t)n) return fail(h, DEM_E_ARG, "checkpoint of another system");
+    if (bytes < dem_state_bytes(h)) return fail(h, DEM_E_ARG, "checkpoint too short");
+    const unsigned char *b = static_cast<const unsigned char *>(host_buf);
+    const double *src = reinterpret_cast<const double *>(b + sizeof hd);
+    double *const cols[13] = {h->st.x, h->st.y, h->st.z, h->st.qw, h->st.qx, h->st.qy, h->st.qz,
+                              h->st.vx, h->st.vy, h->st.vz, h->st.Lx, h->st.Ly, h->st.Lz};
+    for (int c = 0; c < 13; ++c)
+        if (cols[c] && n) HIPCHK(h, hipMemcpyAsync(cols[c], src + c * n, sizeof(double) * n, hipMemcpyHostToDevice, h->stream));
+    const int32_t *isrc = reinterpret_cast<const int32_t *>(src + 13 * n);
+    if (n) {
+        HIPCHK(h, hipMemcpyAsync(h->st.sid, isrc, sizeof(int32_t) * n, hipMemcpyHostToDevice, h->stream));
+        HIPCHK(h, hipMemcpyAsync(h->st.image, isrc + n, sizeof(int32_t) * 3 * n, hipMemcpyHostToDevice, h->stream));
+    }
+    HIPCHK(h, hipMemcpyAsync(h->thermo, hd.thermo, sizeof hd.thermo, hipMemcpyHostToDevice, h->stream));
+    k_set_i64<<<1, 1, 0, h->stream>>>(h->steps, hd.step);
+    // latched device errors belong to the state being replaced
+    for (int w : {FLAG_NONFINITE, FLAG_MAXROW, FLAG_CELLOVF}) k_set_i32<<<1, 1, 0, h->stream>>>(h->lst.flags + w, 0);
+    HIPCHK(h, hipStreamSynchronize(h->stream));  // the host buffer may be freed on return
+    dem_status st = build_lists_sync(h, LISTS_ALL);
+    if (st == DEM_OK) st = compute_forces(h);
+    if (st != DEM_OK) return st;
+    k_set_i32<<<1, 1, 0, h->stream>>>(h->lst.flags + FLAG_NBUILDS, (int32_t)hd.n_rebuilds);
+    HIPCHK(h, hipGetLastError());
+    return latched(h);
+}
+
 dem_status dem_set_pair_shape(dem_handle h, int32_t lanes_per_pair, int32_t grid_factor, int32_t waves_per_simd)
 {
     if (!h) return fail(nullptr, DEM_E_ARG, "null handle");

@@ -55,6 +55,13 @@ class BatchParams(C.Structure):
                 ("nbr_capacity", C.c_int32)]
 
 
+class OutputView(C.Structure):
+    _fields_ = [("Fx", C.c_void_p), ("Fy", C.c_void_p), ("Fz", C.c_void_p), ("Tx", C.c_void_p),
+                ("Ty", C.c_void_p), ("Tz", C.c_void_p), ("U", C.c_void_p), ("W", C.c_void_p),
+                ("w_stride", C.c_int64), ("nbr", C.c_void_p), ("n_nbr", C.c_void_p), ("nbr_stride", C.c_int64),
+                ("capacity", C.c_int32)]
+
+
 class EnergyOut(C.Structure):
     _fields_ = [("U", C.c_double), ("K_trans", C.c_double), ("K_rot", C.c_double), ("H", C.c_double),
                 ("T", C.c_double), ("P", C.c_double), ("W", C.c_double * 9), ("xi", C.c_double),
@@ -92,6 +99,16 @@ def lib():
             getattr(L, name).restype = st
         L.dem_step.argtypes = [C.c_void_p, C.c_int64]
         L.dem_step.restype = st
+        L.dem_batch_step.argtypes = [C.c_void_p, C.c_int64]
+        L.dem_batch_step.restype = st
+        L.dem_get_outputs.argtypes = [C.c_void_p, C.POINTER(OutputView)]
+        L.dem_get_outputs.restype = st
+        L.dem_state_bytes.argtypes = [C.c_void_p]
+        L.dem_state_bytes.restype = C.c_size_t
+        L.dem_get_state.argtypes = [C.c_void_p, C.c_void_p, C.c_size_t]
+        L.dem_get_state.restype = st
+        L.dem_set_state.argtypes = [C.c_void_p, C.c_void_p, C.c_size_t]
+        L.dem_set_state.restype = st
         L.dem_energy.argtypes = [C.c_void_p, C.POINTER(EnergyOut)]
         L.dem_energy.restype = st
         L.dem_set_thermostat.argtypes = [C.c_void_p, C.c_double, C.c_double]
@@ -346,6 +363,24 @@ class DemSystem:
         return dict(pairs=out[0], features=out[1], in_cutoff=out[2], launches=out[3], vf_near=out[4],
                     refined=out[5], ee_near=out[6], separated=out[7], plane_tests=out[8])
 
+    def get_state(self) -> bytes:
+        """Checkpoint of the whole state and thermostat (host bytes, dem_get_state)."""
+        n = lib().dem_state_bytes(self.h)
+        buf = C.create_string_buffer(n)
+        self._check(lib().dem_get_state(self.h, buf, n), "dem_get_state")
+        return buf.raw
+
+    def set_state(self, blob: bytes):
+        """Restores a checkpoint from get_state (lists rebuilt, forces recomputed)."""
+        buf = C.create_string_buffer(blob, len(blob))
+        self._check(lib().dem_set_state(self.h, buf, len(blob)), "dem_set_state")
+
+    def output_view(self) -> dict:
+        """Device addresses of the outputs and neighbour rows (dem_get_outputs)."""
+        v = OutputView()
+        self._check(lib().dem_get_outputs(self.h, C.byref(v)), "dem_get_outputs")
+        return {name: getattr(v, name) for name, _ in OutputView._fields_}
+
     def set_pair_shape(self, lanes: int, grid: int = 1, waves: int = 2):
         """Pair-kernel launch shape (8 or 16 lanes per pair, grid factor 1..4, 2 or 3 waves per SIMD);
         results do not change."""
@@ -439,7 +474,7 @@ class DemBatch:
         self.systems.pop(rid, None)
 
     def step(self, n: int):
-        self._check(lib().dem_step(self.h, int(n)), "dem_step")
+        self._check(lib().dem_batch_step(self.h, int(n)), "dem_batch_step")
 
     def compute_forces(self):
         self._check(lib().dem_compute_forces(self.h), "dem_compute_forces")
