@@ -36,6 +36,7 @@ FLOPS = {
     "edge": 12,        # edge reach test (ne_i + ne_j per pair)
     "face": 12,        # face reach test (nf_i + nf_j per pair)
     "cull": 17,        # per-problem test: plane + bounding circle, or segment bounding spheres
+                       # (the line-distance test of edge pairs whose spheres meet is not counted)
     "vf_solve": 100,   # inside test, projection or boundary edges, offset back to i's frame
     "ee_solve": 65,    # segment-segment closest points and offset
     "ve_solve": 20,    # 2D point-segment nearest point and offset

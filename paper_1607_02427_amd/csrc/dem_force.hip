@@ -288,11 +288,18 @@ struct Problem {
                 const T lim = S.frad[y] + rc;
                 return fabs(sd) < rc && dot(dc, dc) < lim * lim;
             }
-            // edge against edge: bounding spheres of the two segments
-            const V3<T> mj = T(0.5) * (ld3(W.vj[Sj.e[y][0]]) + ld3(W.vj[Sj.e[y][1]]));
-            const V3<T> dm = ld3(Si.em[x]) - mj;
+            // edge against edge: bounding spheres of the two segments, then,
+            // unless they are close to parallel, the distance between their
+            // lines (a lower bound of the segments' distance)
+            const V3<T> a = ld3(W.vj[Sj.e[y][0]]), d2 = ld3(W.vj[Sj.e[y][1]]) - a;
+            const V3<T> dm = ld3(Si.em[x]) - (a + T(0.5) * d2);
             const T lim = Si.eh[x] + Sj.eh[y] + rc;
-            return dot(dm, dm) < lim * lim;
+            if (!(dot(dm, dm) < lim * lim)) return false;
+            const V3<T> d1 = ld3(Si.ed[x]);
+            const V3<T> n = cross(d1, d2);
+            const T nn = dot(n, n);
+            const T rn = dot(ld3(Si.em[x]) - a, n);
+            return !(nn > T(1e-4) * Si.el2[x] * dot(d2, d2) && rn * rn > T(1.001) * rc * rc * nn);
         } else {  // vertex against edge, in the edge owner's frame
             const ShapeTab<T> &S = fam == 0 ? Sj : Si;
             const V3<T> dm = (fam == 0 ? ld3(W.vi[x]) : ld3(W.vj[x])) - ld3(S.em[y]);
