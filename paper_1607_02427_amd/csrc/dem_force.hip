@@ -99,21 +99,28 @@ __device__ inline V3<T> seg_point(V3<T> p, V3<T> a, V3<T> u, T inv_uu)
 // Nearest point of face f of shape S to p, both in S's body frame: the
 // projection if it is inside the closed polygon (in-plane half-spaces for
 // convex faces, crossing number for concave ones), else the nearest point of
-// the face's own boundary edges.
-template <typename T>
-__device__ inline V3<T> face_point(const ShapeTab<T> &S, int f, V3<T> p)
+// the face's own boundary edges.  The face's loop (foff, floop, fconvex) is
+// read from `top`, a table of the same shape that may sit in faster memory
+// than S (the FP32 table in LDS beside the FP64 one in global memory); the
+// loops are unrolled and free of early exits, so the loads of a face's
+// loop entries are issued together instead of one round trip each.
+template <typename T, typename TT>
+__device__ inline V3<T> face_point(const TT &top, const ShapeTab<T> &S, int f, V3<T> p)
 {
+    // unrolled where S is in global memory or FP32 (registers allow it)
+    constexpr int kU = (sizeof(T) == 8 && sizeof(TT) == sizeof(ShapeTab<T>)) ? 1 : 4;
     const V3<T> n = ld3(S.fn[f]);
     const T sd = dot(n, p) - S.fo[f];
-    const int k0 = S.foff[f], k1 = S.foff[f + 1];
+    const int k0 = top.foff[f], k1 = top.foff[f + 1];
     bool inside;
-    if (S.fconvex[f]) {
+    if (top.fconvex[f]) {
         inside = true;
-        for (int k = k0; k < k1; ++k) inside = inside && (dot(ld3(S.lnrm[k]), p) >= S.loff[k]);
+#pragma unroll kU
+        for (int k = k0; k < k1; ++k) inside &= dot(ld3(S.lnrm[k]), p) >= S.loff[k];
     } else {
         const V3<T> e1 = ld3(S.fe1[f]);
         const V3<T> e2 = cross(n, e1);
-        const V3<T> o = ld3(S.v[S.floop[k0]]);
+        const V3<T> o = ld3(S.v[top.floop[k0]]);
         const T px = dot(p - o, e1), py = dot(p - o, e2);
         inside = false;
         for (int k = k0; k < k1; ++k) {
@@ -128,10 +135,11 @@ __device__ inline V3<T> face_point(const ShapeTab<T> &S, int f, V3<T> p)
     if (inside) return p - sd * n;
     T best = T(3.0e38);
     V3<T> q = p;
+#pragma unroll kU
     for (int k = k0; k < k1; ++k) {
         const int kn = (k + 1 < k1) ? k + 1 : k0;
-        const V3<T> a = ld3(S.v[S.floop[k]]);
-        const V3<T> c = seg_point(p, a, ld3(S.v[S.floop[kn]]) - a, S.linv[k]);
+        const V3<T> a = ld3(S.v[top.floop[k]]);
+        const V3<T> c = seg_point(p, a, ld3(S.v[top.floop[kn]]) - a, S.linv[k]);
         const V3<T> d = p - c;
         const T d2 = dot(d, d);
         if (d2 < best) {
@@ -320,12 +328,12 @@ struct Problem {
         if (fam == 0) {
             const V3<T> pt = ld3(W.vi[x]);
             P = ld3(Si.v[x]);
-            const V3<T> qj = (DIM == 3) ? face_point(Sj, y, pt)
+            const V3<T> qj = (DIM == 3) ? face_point(Sj, Sj, y, pt)
                                         : seg_point(pt, ld3(Sj.v[Sj.e[y][0]]), ld3(Sj.ed[y]), Sj.einv[y]);
             rho = mul(Rr, pt - qj);  // offset formed in j's frame, then rotated
         } else if (fam == 1) {
             const V3<T> pt = ld3(W.vj[x]);
-            P = (DIM == 3) ? face_point(Si, y, pt) : seg_point(pt, ld3(Si.v[Si.e[y][0]]), ld3(Si.ed[y]), Si.einv[y]);
+            P = (DIM == 3) ? face_point(Si, Si, y, pt) : seg_point(pt, ld3(Si.v[Si.e[y][0]]), ld3(Si.ed[y]), Si.einv[y]);
             rho = P - pt;
         } else {
             const V3<T> b0 = ld3(W.vj[Sj.e[y][0]]);
@@ -401,11 +409,12 @@ __device__ inline int group_append(bool keep, unsigned char *list, int len, int 
 // of the cutoff, where the force is a steep function of the distance
 // (dF/dr = 72 eps / r_cut^2 there), and for nearly parallel edges, whose
 // closest points are ill-conditioned (error ~ eps / sin).  Returns 1 if the
-// pair is inside the cutoff.
+// pair is inside the cutoff.  Indices (edge ends, face loops) are read from
+// the FP32 tables Ti, Tj in LDS, coordinates from the FP64 tables Di, Dj.
 template <typename T, int DIM>
 __device__ int refine_pair(const double *box, double eps, double par_s2, const PartRec64 &ri, const PartRec64 &rj,
-                           const ShapeTab<double> &Di, const ShapeTab<double> &Dj, int fam, int x, int y, double sig,
-                           Acc<T> &A)
+                           const ShapeTab<T> &Ti, const ShapeTab<T> &Tj, const ShapeTab<double> &Di,
+                           const ShapeTab<double> &Dj, int fam, int x, int y, double sig, Acc<T> &A)
 {
     // the pair's transform as quaternions, which keeps few values live:
     // qr = conj(q_i) q_j takes j's body frame to i's, td = conj(q_i) d is
@@ -421,19 +430,19 @@ __device__ int refine_pair(const double *box, double eps, double par_s2, const P
     V3<double> P, rho;
     if (fam == 0) {
         const V3<double> pt = qrot(qrc, ld3(Di.v[x]) - td);  // i's vertex in j's frame
-        const V3<double> q = (DIM == 3) ? face_point(Dj, y, pt)
-                                        : seg_point(pt, ld3(Dj.v[Dj.e[y][0]]), ld3(Dj.ed[y]), Dj.einv[y]);
+        const V3<double> q = (DIM == 3) ? face_point(Tj, Dj, y, pt)
+                                        : seg_point(pt, ld3(Dj.v[Tj.e[y][0]]), ld3(Dj.ed[y]), Dj.einv[y]);
         P = ld3(Di.v[x]);
         rho = qrot(qr, pt - q);
     } else if (fam == 1) {
         const V3<double> pt = td + qrot(qr, ld3(Dj.v[x]));  // j's vertex in i's frame
-        P = (DIM == 3) ? face_point(Di, y, pt) : seg_point(pt, ld3(Di.v[Di.e[y][0]]), ld3(Di.ed[y]), Di.einv[y]);
+        P = (DIM == 3) ? face_point(Ti, Di, y, pt) : seg_point(pt, ld3(Di.v[Ti.e[y][0]]), ld3(Di.ed[y]), Di.einv[y]);
         rho = P - pt;
     } else {
-        const V3<double> b0 = td + qrot(qr, ld3(Dj.v[Dj.e[y][0]]));
+        const V3<double> b0 = td + qrot(qr, ld3(Dj.v[Tj.e[y][0]]));
         const V3<double> d2 = qrot(qr, ld3(Dj.ed[y]));
         V3<double> Q;
-        seg_seg(ld3(Di.v[Di.e[x][0]]), ld3(Di.ed[x]), Di.el2[x], Di.einv[x], b0, d2, Dj.el2[y], Dj.einv[y], par_s2,
+        seg_seg(ld3(Di.v[Ti.e[x][0]]), ld3(Di.ed[x]), Di.el2[x], Di.einv[x], b0, d2, Dj.el2[y], Dj.einv[y], par_s2,
                 P, Q);
         rho = P - Q;
     }
@@ -655,6 +664,7 @@ __global__ void __launch_bounds__(64 * kWaves, OCC) k_pairs(BatchParams b, const
                     W.vj[vk][1] = v.y;
                     W.vj[vk][2] = v.z;
                     unsigned mb = 0;
+#pragma unroll 4
                     for (int p = 0; p < Si.nsep; ++p) mb |= (dot(ld3(Si.sn[p]), v) - Si.so[p] > thr ? 1u : 0u) << p;
                     W.vjb[vk] = mb;
                     nj = mb == 0 && dot(v, v) < grow * Bi * Bi;
@@ -665,6 +675,7 @@ __global__ void __launch_bounds__(64 * kWaves, OCC) k_pairs(BatchParams b, const
                     W.vi[vk][1] = v.y;
                     W.vi[vk][2] = v.z;
                     unsigned mb = 0;
+#pragma unroll 4
                     for (int p = 0; p < Sj.nsep; ++p) mb |= (dot(ld3(Sj.sn[p]), v) - Sj.so[p] > thr ? 1u : 0u) << p;
                     W.vib[vk] = mb;
                     ni = mb == 0 && dot(v, v) < grow * Bj * Bj;
@@ -779,7 +790,7 @@ __global__ void __launch_bounds__(64 * kWaves, OCC) k_pairs(BatchParams b, const
                                                (DIM == 3 && fam == 2 && sin2 < T(1e-2) && r2 < T(1.0001) * rc2 + T(1e-3) * rc));
                             if (redo) {
                                 c_ref.add(1);
-                                c_in.add(refine_pair<T, DIM>(rl.box, rl.eps, rl.par_s2, rec64[qe.ent.x], rec64[qe.ent.y],
+                                c_in.add(refine_pair<T, DIM>(rl.box, rl.eps, rl.par_s2, rec64[qe.ent.x], rec64[qe.ent.y], Si, Sj,
                                                             gtab64[rl.sbase + si], gtab64[rl.sbase + sj], fam, e, g, rl.rad[si] + rl.rad[sj], A));
                             } else {
                                 c_in.add(add_wca(A, Pt, rho, t, sig2, rc2, eps));
@@ -904,34 +915,41 @@ __global__ void __launch_bounds__(64 * kWaves, OCC) k_pairs(BatchParams b, const
                 if (hj[p]) wj[p] = t + mul(Rr, ld3(Sj.v[k]));
                 if (hi[p]) wi[p] = mulT(Rr, ld3(Si.v[k]) - t);
             }
-            bool sep = false;
-            const int npl = live ? (Si.nsep > Sj.nsep ? Si.nsep : Sj.nsep) : 0;
-            for (int p = 0; __ballot(!sep && p < npl) != 0; ++p) {
-                const bool ti = !sep && p < Si.nsep, tj = !sep && p < Sj.nsep;
-                bool bi = true, bj = true;  // every vertex of this lane beyond plane p
-                if (ti) {
-                    const V3<T> n = ld3(Si.sn[p]);
-                    const T o = Si.so[p];
+            // bit p of bi (bj): every vertex of j (i) this lane holds lies
+            // more than thr beyond supporting plane p of i (j); no early exit
+            // and one group reduction at the end, so the plane loads of
+            // successive planes overlap
+            unsigned bi = 0, bj = 0;
+            const int nsi = live ? Si.nsep : 0, nsj = live ? Sj.nsep : 0;
+#pragma unroll 2
+            for (int p = 0; p < nsi; ++p) {
+                const V3<T> n = ld3(Si.sn[p]);
+                const T o = Si.so[p];
+                bool all = true;
 #pragma unroll
-                    for (int v = 0; v < kVP; ++v)
-                        if (hj[v]) {
-                            bi = bi && dot(n, wj[v]) - o > thr;
-                            c_pv.add(1);
-                        }
+                for (int v = 0; v < kVP; ++v) {
+                    all &= !hj[v] || dot(n, wj[v]) - o > thr;
+                    c_pv.add(hj[v] ? 1 : 0);
                 }
-                if (tj) {
-                    const V3<T> n = ld3(Sj.sn[p]);
-                    const T o = Sj.so[p];
-#pragma unroll
-                    for (int v = 0; v < kVP; ++v)
-                        if (hi[v]) {
-                            bj = bj && dot(n, wi[v]) - o > thr;
-                            c_pv.add(1);
-                        }
-                }
-                const unsigned long long mi = __ballot(bi), mj = __ballot(bj);
-                sep = sep || (ti && (mi & gmask1) == gmask1) || (tj && (mj & gmask1) == gmask1);
+                bi |= (all ? 1u : 0u) << p;
             }
+#pragma unroll 2
+            for (int p = 0; p < nsj; ++p) {
+                const V3<T> n = ld3(Sj.sn[p]);
+                const T o = Sj.so[p];
+                bool all = true;
+#pragma unroll
+                for (int v = 0; v < kVP; ++v) {
+                    all &= !hi[v] || dot(n, wi[v]) - o > thr;
+                    c_pv.add(hi[v] ? 1 : 0);
+                }
+                bj |= (all ? 1u : 0u) << p;
+            }
+            for (int off = 1; off < kSepLanes; off <<= 1) {
+                bi &= __shfl_xor(bi, off, kSepLanes);
+                bj &= __shfl_xor(bj, off, kSepLanes);
+            }
+            const bool sep = (bi | bj) != 0;
             need = live && !sep;
             if (sub1 == 0 && live) {
                 c_pairs.add(1);
