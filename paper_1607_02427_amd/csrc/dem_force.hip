@@ -477,10 +477,25 @@ __device__ void stage_replica(const SysParams *reps, const ListPtrs &l, const Sh
 {
     __syncthreads();
     const SysParams &p = reps[r];
-    const int words = p.n_shapes * (int)(sizeof(ShapeTab<T>) / 4);
-    const uint32_t *src = reinterpret_cast<const uint32_t *>(gtab + p.sbase);
-    uint32_t *dst = reinterpret_cast<uint32_t *>(tab);
-    for (int w = threadIdx.x; w < words; w += blockDim.x) dst[w] = src[w];
+    // 16-byte words (the tables are 16-byte aligned and sized), up to four
+    // loads per thread in flight before their stores
+    constexpr int kU = 4;
+    const int n16 = p.n_shapes * (int)(sizeof(ShapeTab<T>) / 16);
+    const uint4 *src = reinterpret_cast<const uint4 *>(gtab + p.sbase);
+    uint4 *dst = reinterpret_cast<uint4 *>(tab);
+    for (int w0 = threadIdx.x; w0 < n16; w0 += kU * blockDim.x) {
+        uint4 v[kU];
+#pragma unroll
+        for (int u = 0; u < kU; ++u) {
+            const int w = w0 + u * (int)blockDim.x;
+            v[u] = w < n16 ? src[w] : make_uint4(0, 0, 0, 0);
+        }
+#pragma unroll
+        for (int u = 0; u < kU; ++u) {
+            const int w = w0 + u * (int)blockDim.x;
+            if (w < n16) dst[w] = v[u];
+        }
+    }
     if (threadIdx.x < DEM_MAX_SHAPES) {
         rl.R[threadIdx.x] = p.R[threadIdx.x];
         rl.rad[threadIdx.x] = p.rad[threadIdx.x];
@@ -713,6 +728,7 @@ __global__ void __launch_bounds__(64 * kWaves, OCC) k_pairs(BatchParams b, const
                         const V3<T> d = ld3(Si.fc[f]) - t;
                         const T lim = Bj + Si.frad[f];
                         unsigned all = ~0u;
+#pragma unroll 4
                         for (int k = Si.foff[f]; k < Si.foff[f + 1]; ++k) all &= W.vib[Si.floop[k]];
                         nf = all == 0 && dot(d, d) < grow * lim * lim;
                     }
@@ -720,6 +736,7 @@ __global__ void __launch_bounds__(64 * kWaves, OCC) k_pairs(BatchParams b, const
                         const V3<T> d = ld3(Sj.fc[f]) - ti;
                         const T lim = Bi + Sj.frad[f];
                         unsigned all = ~0u;
+#pragma unroll 4
                         for (int k = Sj.foff[f]; k < Sj.foff[f + 1]; ++k) all &= W.vjb[Sj.floop[k]];
                         mf = all == 0 && dot(d, d) < grow * lim * lim;
                     }

@@ -118,6 +118,8 @@ struct alignas(16) ShapeTab {
     T so[kMaxSep];               // and offsets
 };
 
+static_assert(sizeof(ShapeTab<float>) % 16 == 0 && sizeof(ShapeTab<double>) % 16 == 0, "tables are copied in 16-byte words");
+
 // One replica: a periodic system of its own.  A single system is a batch
 // of one replica.  Indices into batch arrays are global particle slots;
 // replica r owns slots [off, off + n), cells [coff, coff + ncell] and pair
