@@ -1053,7 +1053,10 @@ __device__ inline double nh_half(const SysParams &p, double &xi, double &eta, do
 // the result does not depend on scheduling.  With the kick and NVT each
 // block writes its chunk's kinetic partials for k_replica_tail.  A replica
 // with no budget left is skipped.
-constexpr int kGatherBatch = 4;  // row slots loaded together in the gather
+// row slots a lane loads together in the gather (a record is 48 bytes in
+// FP32, 96 in FP64)
+template <typename T>
+constexpr int gather_batch() { return sizeof(T) == 4 ? 8 : 4; }
 
 // Adds one row-slot record to a particle's sums: F, tau, U_i = 1/2 sum U_ij
 // and W_i = 1/2 sum r_ij (x) F_ij with r_ij = -d.
@@ -1077,35 +1080,56 @@ __global__ void __launch_bounds__(kGatherBlock) k_gather(BatchParams b, const Sy
                                                       double *thermo, int64_t *budget, int64_t *steps)
 {
     __shared__ double sh[kGatherBlock];
+    constexpr int kB = gather_batch<T>();
+    const int sub = threadIdx.x % kGatherLanes;
+    const int i = blockIdx.x * kGatherPer + threadIdx.x / kGatherLanes;
+    // what depends on the slot alone is requested with the replica's
+    // parameters instead of after them (the row length from the library's
+    // N slots; the state only within the length of its arrays)
+    const int m_row = i < b.N ? l.n_nbr[i] : 0;
+    double sv[3] = {0.0, 0.0, 0.0}, sL[3] = {0.0, 0.0, 0.0}, sq[4] = {1.0, 0.0, 0.0, 0.0};
+    int ssid = 0;
+    if (KICK && i < b.nstate) {
+        ssid = s.sid[i];
+        sv[0] = s.vx[i];
+        sv[1] = s.vy[i];
+        sL[2] = s.Lz[i];
+        if (DIM == 3) {
+            sv[2] = s.vz[i];
+            sL[0] = s.Lx[i];
+            sL[1] = s.Ly[i];
+            sq[0] = s.qw[i];
+            sq[1] = s.qx[i];
+            sq[2] = s.qy[i];
+            sq[3] = s.qz[i];
+        }
+    }
+    const unsigned stamp = (unsigned)l.gflags[G_STAMP];  // records of this evaluation only
     const int r = l.chunk_rep[blockIdx.x];
     if (r < 0) return;
     const SysParams &p = reps[r];
     if (KICK && budget[r] <= 0) return;
-    const int sub = threadIdx.x % kGatherLanes;
-    const int i = blockIdx.x * kGatherPer + threadIdx.x / kGatherLanes;
     const bool nvt = KICK && p.ensemble == DEM_NVT;
     const size_t N = (size_t)b.N;
     const bool mine = i < p.off + p.n;
     double acc[16];
     for (int c = 0; c < 16; ++c) acc[c] = 0.0;  // F[3], T[3], U, W[9]
     if (mine) {
-        const int m = l.n_nbr[i];
-        const unsigned stamp = (unsigned)l.gflags[G_STAMP];  // records of this evaluation only
+        const int m = m_row;
         // slots in batches: every load of a batch is issued before any of
-        // its sums, so the batch's memory round trips overlap
-        int k = sub;
-        for (; k + (kGatherBatch - 1) * kGatherLanes < m; k += kGatherBatch * kGatherLanes) {
-            SlotRec<T> w[kGatherBatch];
+        // its sums, so the batch's memory round trips overlap; slots are
+        // added in row order
+        for (int k = sub; k < m; k += kB * kGatherLanes) {
+            SlotRec<T> w[kB];
 #pragma unroll
-            for (int u = 0; u < kGatherBatch; ++u) w[u] = rec[(size_t)(k + u * kGatherLanes) * N + i];
+            for (int u = 0; u < kB; ++u) {
+                const int ku = k + u * kGatherLanes;
+                w[u] = ku < m ? rec[(size_t)ku * N + i] : SlotRec<T>{};
+            }
             __builtin_amdgcn_sched_barrier(0);  // keep the loads ahead of the sums
 #pragma unroll
-            for (int u = 0; u < kGatherBatch; ++u)
-                if (slot_stamp(w[u]) == stamp) add_slot(acc, w[u]);
-        }
-        for (; k < m; k += kGatherLanes) {
-            const SlotRec<T> w = rec[(size_t)k * N + i];
-            if (slot_stamp(w) == stamp) add_slot(acc, w);
+            for (int u = 0; u < kB; ++u)
+                if (k + u * kGatherLanes < m && slot_stamp(w[u]) == stamp) add_slot(acc, w[u]);
         }
     }
     for (int off = 1; off < kGatherLanes; off <<= 1)
@@ -1126,26 +1150,25 @@ __global__ void __launch_bounds__(kGatherBlock) k_gather(BatchParams b, const Sy
         o.U[i] = acc[6];
         for (int c = 0; c < 9; ++c) o.W[(size_t)c * b.wstride + i] = acc[7 + c];
         if (KICK) {
-            const int sid = s.sid[i];
+            const int sid = ssid;
             const double hm = 0.5 * p.dt / p.mass[sid];
-            double v[3] = {s.vx[i] + hm * F[0], s.vy[i] + hm * F[1], 0.0};
+            double v[3] = {sv[0] + hm * F[0], sv[1] + hm * F[1], 0.0};
             s.vx[i] = v[0];
             s.vy[i] = v[1];
             double L[3] = {0.0, 0.0, 0.0};
             if (DIM == 3) {
-                v[2] = s.vz[i] + hm * F[2];
+                v[2] = sv[2] + hm * F[2];
                 s.vz[i] = v[2];
-                const double q[4] = {s.qw[i], s.qx[i], s.qy[i], s.qz[i]};
                 double tb[3];
-                body_torque(q, Tq[0], Tq[1], Tq[2], tb);
-                L[0] = s.Lx[i] + 0.5 * p.dt * tb[0];
-                L[1] = s.Ly[i] + 0.5 * p.dt * tb[1];
-                L[2] = s.Lz[i] + 0.5 * p.dt * tb[2];
+                body_torque(sq, Tq[0], Tq[1], Tq[2], tb);
+                L[0] = sL[0] + 0.5 * p.dt * tb[0];
+                L[1] = sL[1] + 0.5 * p.dt * tb[1];
+                L[2] = sL[2] + 0.5 * p.dt * tb[2];
                 s.Lx[i] = L[0];
                 s.Ly[i] = L[1];
                 s.Lz[i] = L[2];
             } else {
-                L[2] = s.Lz[i] + 0.5 * p.dt * Tq[2];
+                L[2] = sL[2] + 0.5 * p.dt * Tq[2];
                 s.Lz[i] = L[2];
             }
             if (nvt) {

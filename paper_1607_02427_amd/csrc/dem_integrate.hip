@@ -36,13 +36,27 @@ __device__ inline void quat_mul(double &w, double &x, double &y, double &z, doub
     z = nz;
 }
 
+// sin and cos of an angle: for |a| <= 1/16 (every turn of a stable step)
+// their Taylor series through the a^9 and a^10 terms in nested form, whose
+// truncation is below 1e-19 relative there; sincos otherwise.
+__device__ inline void sincos_turn(double a, double *sn, double *cs)
+{
+    if (fabs(a) <= 0.0625) {
+        const double a2 = a * a;
+        *sn = a * (1.0 - a2 * (1.0 / 6.0) * (1.0 - a2 * (1.0 / 20.0) * (1.0 - a2 * (1.0 / 42.0) * (1.0 - a2 * (1.0 / 72.0)))));
+        *cs = 1.0 - a2 * 0.5 * (1.0 - a2 * (1.0 / 12.0) * (1.0 - a2 * (1.0 / 30.0) * (1.0 - a2 * (1.0 / 56.0) * (1.0 - a2 * (1.0 / 90.0)))));
+    } else {
+        sincos(a, sn, cs);
+    }
+}
+
 // Free rotation about body axis k for time h.
 __device__ inline void turn(double q[4], double L[3], const double I[3], int k, double h)
 {
     if (I[k] <= 0.0) return;
     const double phi = h * L[k] / I[k];
     double sn, cs;
-    sincos(0.5 * phi, &sn, &cs);
+    sincos_turn(0.5 * phi, &sn, &cs);
     double b[3] = {0.0, 0.0, 0.0};
     b[k] = sn;
     quat_mul(q[0], q[1], q[2], q[3], cs, b[0], b[1], b[2]);
@@ -151,6 +165,41 @@ __global__ void __launch_bounds__(kBlock) k_kick_drift(BatchParams b, const SysP
 {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i == 0) l.gflags[G_STAMP] += 1;  // this step's force evaluation
+    // the particle's own values are requested with the replica's parameters
+    // instead of after them (within the length of the state arrays)
+    double q[4] = {1.0, 0.0, 0.0, 0.0}, v0[3] = {0.0, 0.0, 0.0}, L0[3] = {0.0, 0.0, 0.0};
+    double F0[3] = {0.0, 0.0, 0.0}, T0[3] = {0.0, 0.0, 0.0}, x[3] = {0.0, 0.0, 0.0};
+    int img[3] = {0, 0, 0}, sid = 0;
+    if (i < b.nstate) {
+        sid = s.sid[i];
+        x[0] = s.x[i];
+        x[1] = s.y[i];
+        v0[0] = s.vx[i];
+        v0[1] = s.vy[i];
+        L0[2] = s.Lz[i];
+        F0[0] = o.Fx[i];
+        F0[1] = o.Fy[i];
+        T0[2] = o.Tz[i];
+        if (DIM == 3) {
+            x[2] = s.z[i];
+            v0[2] = s.vz[i];
+            L0[0] = s.Lx[i];
+            L0[1] = s.Ly[i];
+            F0[2] = o.Fz[i];
+            T0[0] = o.Tx[i];
+            T0[1] = o.Ty[i];
+        }
+        q[0] = s.qw[i];
+        q[1] = s.qx[i];
+        q[2] = s.qy[i];
+        q[3] = s.qz[i];
+        img[0] = s.image[3 * i];
+        img[1] = s.image[3 * i + 1];
+        img[2] = s.image[3 * i + 2];
+    }
+    double xl[3] = {0.0, 0.0, 0.0};  // position at the last list build (the library's N slots)
+    if (i < b.N)
+        for (int a = 0; a < DIM; ++a) xl[a] = l.xlast[(size_t)a * b.N + i];
     const int r = wave_replica(b, l, i);
     if (r < 0) return;
     const SysParams &p = reps[r];
@@ -160,26 +209,22 @@ __global__ void __launch_bounds__(kBlock) k_kick_drift(BatchParams b, const SysP
     const bool nvt = p.ensemble == DEM_NVT;
     const double sb = nvt ? thermo[r * TH_COUNT + TH_SB] : 1.0;
     const double sa = nvt ? thermo[r * TH_COUNT + TH_SA] : 1.0;
-    const int sid = s.sid[i];
     const double hm = 0.5 * p.dt / p.mass[sid];
     const double I[3] = {p.inertia[sid][0], p.inertia[sid][1], p.inertia[sid][2]};
-    double q[4] = {s.qw[i], s.qx[i], s.qy[i], s.qz[i]};
-    double v[3] = {(s.vx[i] * sb) * sa + hm * o.Fx[i], (s.vy[i] * sb) * sa + hm * o.Fy[i], 0.0};
+    double v[3] = {(v0[0] * sb) * sa + hm * F0[0], (v0[1] * sb) * sa + hm * F0[1], 0.0};
     double L[3];
     if (DIM == 3) {
-        v[2] = (s.vz[i] * sb) * sa + hm * o.Fz[i];
+        v[2] = (v0[2] * sb) * sa + hm * F0[2];
         double tb[3];
-        body_torque(q, o.Tx[i], o.Ty[i], o.Tz[i], tb);
-        L[0] = (s.Lx[i] * sb) * sa + 0.5 * p.dt * tb[0];
-        L[1] = (s.Ly[i] * sb) * sa + 0.5 * p.dt * tb[1];
-        L[2] = (s.Lz[i] * sb) * sa + 0.5 * p.dt * tb[2];
+        body_torque(q, T0[0], T0[1], T0[2], tb);
+        L[0] = (L0[0] * sb) * sa + 0.5 * p.dt * tb[0];
+        L[1] = (L0[1] * sb) * sa + 0.5 * p.dt * tb[1];
+        L[2] = (L0[2] * sb) * sa + 0.5 * p.dt * tb[2];
     } else {
         L[0] = 0.0;
         L[1] = 0.0;
-        L[2] = (s.Lz[i] * sb) * sa + 0.5 * p.dt * o.Tz[i];
+        L[2] = (L0[2] * sb) * sa + 0.5 * p.dt * T0[2];
     }
-    double x[3] = {s.x[i], s.y[i], (DIM == 3) ? s.z[i] : 0.0};
-    int img[3] = {s.image[3 * i], s.image[3 * i + 1], s.image[3 * i + 2]};
     for (int a = 0; a < DIM; ++a) {
         double xa = x[a] + p.dt * v[a];
         if (xa >= p.box[a]) {
@@ -243,7 +288,7 @@ __global__ void __launch_bounds__(kBlock) k_kick_drift(BatchParams b, const SysP
         // (so no force is evaluated on a list older than that).
         double d2 = 0.0, v2 = 0.0;
         for (int a = 0; a < DIM; ++a) {
-            const double d = min_image(x[a] - l.xlast[(size_t)a * b.N + i], p.box[a]);
+            const double d = min_image(x[a] - xl[a], p.box[a]);
             d2 += d * d;
             v2 += v[a] * v[a];
         }

@@ -152,6 +152,8 @@ struct BatchParams {
     int nrep;                    // replica slots in use (slots with live == 0 are skipped)
     int N;                       // particle slots: stride of the library's column-major arrays
     int wstride;                 // stride of the virial output W[9][.]
+    int nstate;                  // length of the state and output arrays: N for a batch's own
+                                 // arrays, n for the arrays a single system borrows
     int nchunk;                  // chunks in use (kernels over particles cover nchunk * kChunk slots)
     int cap;                     // neighbour-row capacity
     int tab_slots;               // shape tables of one replica staged in LDS

@@ -590,6 +590,7 @@ dem_status alloc_core(dem_system *h, int Ncap, int Ccap, int Scap, int Rcap)
             return fail(h, DEM_E_OOM, "device allocation failed");
         HIPCHK(h, hipMemsetAsync(h->st.sid, 0, sizeof(int32_t) * N, h->stream));
         h->bp.wstride = (int)N;
+        h->bp.nstate = (int)N;
     }
     // initial contents (not captured: plain memsets are fine here)
     HIPCHK(h, hipMemsetAsync(h->lst.flags, 0, sizeof(int32_t) * FLAG_COUNT * Rcap, h->stream));
@@ -1081,6 +1082,7 @@ dem_status dem_create_system(const dem_params *params, const dem_state_ptrs *sta
              state->vz, state->Lx, state->Ly, state->Lz, state->shape_id, state->image};
     h->out = {outputs->Fx, outputs->Fy, outputs->Fz, outputs->Tx, outputs->Ty, outputs->Tz, outputs->U, outputs->W};
     h->bp.wstride = (int)p.n;
+    h->bp.nstate = (int)p.n;
     if (hipStreamCreateWithFlags(&h->cap_stream, hipStreamNonBlocking) != hipSuccess)
         return bail(fail(h, DEM_E_HIP, "stream creation failed"));
     const int nch = (int)((p.n + kChunk - 1) / kChunk);
