@@ -170,6 +170,36 @@ def test_short_trajectory_fp64(which):
     assert compare(out, rf)["F"] < 1e-6
 
 
+def test_fast_rotors_fp64():
+    """Free rotors whose half-angle per turn lies on both sides of 1/16, so
+    both ways the kernel takes the sine and cosine of a turn (series and
+    library call) meet the oracle's integrator (Sec. IV.A)."""
+    dem = _dem()
+    cube, lp = I.cube(), I.lprism(0.1, quad_h=0.05)
+    box = 40.0
+    s = I.System(dim=3, box=np.array([box, box, box]), shapes=[cube, lp],
+                 shape_id=np.array([0, 0, 1, 1], np.int32),
+                 x=np.array([[5.0, 5.0, 5.0], [15.0, 15.0, 15.0], [25.0, 25.0, 25.0], [35.0, 5.0, 25.0]]),
+                 q=I.uniform_quaternions(np.random.default_rng(11), 4),
+                 v=np.array([[0.1, -0.2, 0.05], [0.0, 0.3, -0.1], [-0.2, 0.0, 0.1], [0.05, 0.05, 0.05]]),
+                 L=np.array([[0.8, -0.5, 0.3], [9.0, 4.0, -6.0], [12.0, -3.0, 8.0], [0.2, 7.0, -25.0]]),
+                 image=np.zeros((4, 3), np.int32), dt=0.01)
+    inertia = np.array([cube.inertia, cube.inertia, lp.inertia, lp.inertia])
+    half = np.abs(s.L) * s.dt / (2 * inertia)  # the x turn spans dt; y and z turns span dt/2
+    half[:, 1:] *= 0.5
+    assert (half > 1 / 16).any() and (half < 1 / 16).any()
+    n = 50
+    print(f"[rotors] n={s.n} steps={n} max half-angle {half.max():.3f}", flush=True)
+    ref, _, _, _ = O.run(s, n)
+    with dem.DemSystem(s, "fp64") as g:
+        g.step(n)
+        st = g.state()
+    sgn = np.sign(np.sum(st.q * ref.q, axis=1))[:, None]
+    assert np.abs(st.q * sgn - ref.q).max() < 1e-11
+    assert np.abs(st.L - ref.L).max() < 1e-10
+    assert np.abs((st.x + st.image * s.box) - (ref.x + ref.image * s.box)).max() < 1e-12
+
+
 def test_energy_and_virial_totals():
     dem = _dem()
     s = I.cubes_3d_contact(n_side=8)
