@@ -216,6 +216,49 @@ def cpu_baseline(system, target_s):
                        f"(FP64 brute force over every feature pair, own cell list), {dt:.1f} s")
 
 
+def energy_fluctuations(dts_tau=(0.000625, 0.00125, 0.0025, 0.005, 0.01), duration_tau=10.0, samples=1000,
+                        thermal_tau=10.0, n_side=None):
+    """The short-term energy conservation study of Sec. IV.A on this engine:
+    each fluid (2D squares of edge 4.24 sigma, 3D tetrahedra of edge 8.49
+    sigma) is thermalized at kT = 1 (Nose-Hoover, FP64, dt = 0.005 tau) and
+    then run NVE for duration_tau at each timestep, in FP64 and FP32 pair
+    geometry, recording E = U + K_trans + K_rot `samples` times; reported are
+    sigma(E/N) and the drift (E(end) - E(0)) / (N duration), both in eps and
+    tau units (tau = sigma sqrt(m / eps), sigma = 2 r)."""
+    import numpy as np
+    from paper_1607_02427_amd import dem, inputs as I
+    out = {}
+    for dim in (2, 3):
+        s = I.energy_fluid(dim, n_side=n_side)
+        tau = 2 * s.shapes[0].r
+        with dem.DemSystem(s, "fp64") as g:
+            g.step(int(round(thermal_tau / 0.005)))
+            th = g.state()
+        rows = []
+        for prec in ("fp64", "fp32"):
+            for dtt in dts_tau:
+                t = th.copy()
+                t.ensemble = "nve"
+                t.dt = dtt * tau
+                n = int(round(duration_tau / dtt))
+                k = max(1, n // samples)
+                E = []
+                with dem.DemSystem(t, prec) as g:
+                    for _ in range(n // k):
+                        e = g.energy()
+                        E.append(e["U"] + e["K_trans"] + e["K_rot"])
+                        g.step(k)
+                    e = g.energy()
+                    E.append(e["U"] + e["K_trans"] + e["K_rot"])
+                E = np.asarray(E) / t.n
+                rows.append(dict(precision=prec, dt_tau=dtt, steps=n, sigma_E_per_N=float(E.std()),
+                                 drift_per_N_per_tau=float((E[-1] - E[0]) / duration_tau)))
+                log(f"[energy] {s.name} {prec} dt {dtt:g} tau: sigma(E/N) {E.std():.3e}, "
+                    f"drift {(E[-1] - E[0]) / duration_tau:.2e} per tau")
+        out[s.name] = dict(n=s.n, tau=tau, runs=rows)
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -233,6 +276,8 @@ def main():
     ap.add_argument("--scale-steps", type=int, default=300)
     ap.add_argument("--copy-mb", type=int, default=0,
                     help="finish with device copies of this many MiB (scale for the HBM byte counters)")
+    ap.add_argument("--energy-study", action="store_true",
+                    help="run only the NVE energy-fluctuation study (Sec. IV.A) and print its JSON line")
     ap.add_argument("--no-sequential", action="store_true",
                     help="skip the one-at-a-time plain FP64 runs of the batched and served workloads")
     args = ap.parse_args()
@@ -243,6 +288,10 @@ def main():
     import torch
     from paper_1607_02427_amd import inputs as I
     assert torch.cuda.is_available(), "bench.py needs a GPU"
+    if args.energy_study:
+        print(json.dumps({"metric": "sigma(E/N) of NVE runs against the timestep (Sec. IV.A)", "unit": "eps",
+                          "data": "synthetic", "study": energy_fluctuations()}), flush=True)
+        return
     system = I.cubes_3d()
     n = system.n
     log(f"[bench] fp32 path: {n} cubes, warmup {args.warmup}, steps {args.steps}")

@@ -657,6 +657,30 @@ def cubes_3d_contact(seed: int = 12, n_side: int = 8) -> System:
     return s
 
 
+def energy_fluid(dim: int, n_side: int = None, seed: int = 21) -> System:
+    """The fluids of the energy-conservation study (Sec. IV.A): 2D rounded
+    squares of edge 4.24 sigma (edge 1, r = 1 / 8.48) on a 32 x 32 lattice at
+    area fraction 0.4 with uniform orientations, or 3D rounded tetrahedra of
+    edge 8.49 sigma (edge 1, r = 1 / 16.98) on a 10^3 simple-cubic lattice at
+    volume fraction 0.15, all aligned (the spacing, 1.17, exceeds the
+    tetrahedron's extent plus 2r, 1.12, so no two touch).  kT = 1, unit mass;
+    the study thermalizes them before its NVE runs.  The time unit is
+    tau = sigma sqrt(m / eps) = 2 r."""
+    if dim == 2:
+        shp = square(1.0, 1.0 / (2 * 4.24))
+        k = n_side or 32
+        s = lattice_system(shp, k, 0.4, seed, orient="uniform", name=f"squares_4.24sigma_{k * k}")
+        assert not _bounding_overlap(s.x, s.box, shp.circumradius + shp.r, 2)
+    else:
+        shp = tetrahedron(1.0, 1.0 / (2 * 8.49))
+        k = n_side or 10
+        s = lattice_system(shp, k, 0.15, seed, orient="aligned", name=f"tetrahedra_8.49sigma_{k ** 3}")
+        assert s.box[0] / k > 1.0 + 2 * shp.r
+    s.ensemble = "nvt"
+    s.dt = 0.005 * 2 * shp.r
+    return s
+
+
 def _gas_box(shp: Shape, n: int, excl_fraction: float) -> float:
     sep = 2.0 * shp.circumradius + 0.8 * 2.0 * shp.r
     if shp.dim == 3:
