@@ -858,7 +858,9 @@ __global__ void __launch_bounds__(64 * kWaves, OCC) k_pairs(BatchParams b, const
                     w.d[2] = sg * dv.z;
                     w.pad1 = T(0);
                     set_stamp(w, stamp);
-                    rec[(size_t)slot * N + (js ? j : i)] = w;
+                    const int pi = js ? j : i;
+                    rec[(size_t)slot * N + pi] = w;
+                    atomicOr(&l.smask[(size_t)(slot >> 5) * N + pi], 1u << (slot & 31));
                 }
             }
             continue;
@@ -1053,10 +1055,11 @@ __device__ inline double nh_half(const SysParams &p, double &xi, double &eta, do
 // the result does not depend on scheduling.  With the kick and NVT each
 // block writes its chunk's kinetic partials for k_replica_tail.  A replica
 // with no budget left is skipped.
-// row slots a lane loads together in the gather (a record is 48 bytes in
-// FP32, 96 in FP64)
+// written row slots a lane loads together in the gather (a record is 48
+// bytes in FP32, 96 in FP64; about a quarter of a row's slots are written)
 template <typename T>
-constexpr int gather_batch() { return sizeof(T) == 4 ? 8 : 4; }
+constexpr int gather_batch() { return 4; }
+static_assert(kGatherLanes == 1, "the gather walks a particle's written-slot bits in one lane");
 
 // Adds one row-slot record to a particle's sums: F, tau, U_i = 1/2 sum U_ij
 // and W_i = 1/2 sum r_ij (x) F_ij with r_ij = -d.
@@ -1087,6 +1090,7 @@ __global__ void __launch_bounds__(kGatherBlock) k_gather(BatchParams b, const Sy
     // parameters instead of after them (the row length from the library's
     // N slots; the state only within the length of its arrays)
     const int m_row = i < b.N ? l.n_nbr[i] : 0;
+    const uint32_t mask0 = i < b.N ? l.smask[i] : 0u;  // slots 0..31 written since the last gather
     double sv[3] = {0.0, 0.0, 0.0}, sL[3] = {0.0, 0.0, 0.0}, sq[4] = {1.0, 0.0, 0.0, 0.0};
     int ssid = 0;
     if (KICK && i < b.nstate) {
@@ -1116,20 +1120,30 @@ __global__ void __launch_bounds__(kGatherBlock) k_gather(BatchParams b, const Sy
     for (int c = 0; c < 16; ++c) acc[c] = 0.0;  // F[3], T[3], U, W[9]
     if (mine) {
         const int m = m_row;
-        // slots in batches: every load of a batch is issued before any of
-        // its sums, so the batch's memory round trips overlap; slots are
-        // added in row order
-        for (int k = sub; k < m; k += kB * kGatherLanes) {
-            SlotRec<T> w[kB];
+        // only the slots written since the last gather, whose words are
+        // cleared for the next evaluation; ascending, so they are added in
+        // row order.  Loads go in batches: every load of a batch is issued
+        // before any of its sums, so the batch's round trips overlap.
+        for (int wd = 0; wd < slot_words(m); ++wd) {
+            uint32_t bits = wd == 0 ? mask0 : l.smask[(size_t)wd * N + i];
+            if (bits == 0u) continue;
+            l.smask[(size_t)wd * N + i] = 0u;
+            if (32 * (wd + 1) > m) bits &= (1u << (m - 32 * wd)) - 1u;  // slots below the row length
+            while (bits != 0u) {
+                SlotRec<T> w[kB];
+                bool h[kB];
 #pragma unroll
-            for (int u = 0; u < kB; ++u) {
-                const int ku = k + u * kGatherLanes;
-                w[u] = ku < m ? rec[(size_t)ku * N + i] : SlotRec<T>{};
+                for (int u = 0; u < kB; ++u) {
+                    h[u] = bits != 0u;
+                    const int k = 32 * wd + (h[u] ? __builtin_ctz(bits) : 0);
+                    w[u] = h[u] ? rec[(size_t)k * N + i] : SlotRec<T>{};
+                    bits &= bits - 1u;
+                }
+                __builtin_amdgcn_sched_barrier(0);  // keep the loads ahead of the sums
+#pragma unroll
+                for (int u = 0; u < kB; ++u)
+                    if (h[u] && slot_stamp(w[u]) == stamp) add_slot(acc, w[u]);
             }
-            __builtin_amdgcn_sched_barrier(0);  // keep the loads ahead of the sums
-#pragma unroll
-            for (int u = 0; u < kB; ++u)
-                if (k + u * kGatherLanes < m && slot_stamp(w[u]) == stamp) add_slot(acc, w[u]);
         }
     }
     for (int off = 1; off < kGatherLanes; off <<= 1)

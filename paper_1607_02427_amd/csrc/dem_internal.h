@@ -188,7 +188,12 @@ struct ListPtrs {
     int32_t *pstart;             // [N] first pair index of i, local to its replica
     int32_t *ptot;               // [N / 16] pairs owned by the particles of each k_nbr block
     int4 *pairs;                 // [pair slots] {i, j, slot of j in i's row, slot of i in j's row (-1: missing)}
+    // row slots whose record was written since the particle's last gather:
+    // bit k % 32 of word k / 32, [slot_words(cap)][N]; the gather reads
+    // only those records and clears the words
+    uint32_t *smask;
 };
+__host__ __device__ inline int slot_words(int cap) { return (cap + 31) / 32; }
 
 // Everything the pair kernel reads about one particle, in one cache line:
 // FP64 position, the body-to-space rotation in the force precision (row

@@ -526,14 +526,18 @@ dem_status alloc_nbr(dem_system *h, int cap)
     (void)hipFree(h->lst.nbr);
     (void)hipFree(h->lst.pairs);
     (void)hipFree(h->rec);
+    (void)hipFree(h->lst.smask);
     h->lst.nbr = nbr;
     h->lst.pairs = nullptr;
     h->rec = nullptr;
+    h->lst.smask = nullptr;
     if (hipMalloc(&h->lst.pairs, sizeof(int4) * maxp) != hipSuccess ||
-        hipMalloc(&h->rec, rec_bytes(h->precision) * (size_t)cap * N) != hipSuccess)
+        hipMalloc(&h->rec, rec_bytes(h->precision) * (size_t)cap * N) != hipSuccess ||
+        hipMalloc(&h->lst.smask, sizeof(uint32_t) * (size_t)slot_words(cap) * N) != hipSuccess)
         return fail(h, DEM_E_OOM, "neighbour list of %d x %zu entries", cap, N);
-    // records never written read as zeros (stamp 0, no force)
+    // records never written read as zeros (stamp 0, no force); no slot written yet
     HIPCHK(h, hipMemsetAsync(h->rec, 0, rec_bytes(h->precision) * (size_t)cap * N, h->stream));
+    HIPCHK(h, hipMemsetAsync(h->lst.smask, 0, sizeof(uint32_t) * (size_t)slot_words(cap) * N, h->stream));
     h->bp.cap = cap;
     place_pairs(h);
     dem_status st = upload_tables(h);
@@ -617,7 +621,7 @@ void free_all(dem_system *h)
     void *ptrs[] = {h->d_reps, h->d_chunk_rep, h->tab64, h->tab32, h->ke_part, h->e_part, h->thermo, h->budget,
                     h->steps, h->stats, h->lst.flags, h->lst.gflags, h->lst.tile_start, h->lst.cell_count,
                     h->lst.cell_slot, h->lst.pcell, h->lst.n_nbr, h->lst.xlast, h->lst.klo,
-                    h->lst.pstart, h->lst.ptot, h->lst.nbr, h->lst.pairs, h->rot, h->rec, h->rec64};
+                    h->lst.pstart, h->lst.ptot, h->lst.nbr, h->lst.pairs, h->lst.smask, h->rot, h->rec, h->rec64};
     for (void *p : ptrs) (void)hipFree(p);
     if (h->batch) {
         void *own[] = {h->st.x,  h->st.y,  h->st.z,  h->st.qw, h->st.qx,  h->st.qy,  h->st.qz,  h->st.vx,
@@ -1041,7 +1045,7 @@ size_t dem_footprint_bytes(const dem_params *p)
     return sizeof(int32_t) * (n * (size_t)cap + 4 * n + ncell * (1 + kCellCap) + 4 * maxp + nch + 2 * FLAG_COUNT + G_COUNT + 2) +
            sizeof(double) * (3 * n + 14 * nch + TH_COUNT + 2) + sizeof(unsigned long long) * ST_COUNT +
            (partrec_bytes(p->precision) + (p->precision == DEM_FP32 ? sizeof(PartRec64) : 0)) * n +
-           rec_bytes(p->precision) * (size_t)cap * n + sizeof(SysParams) + 2 * DEM_MAX_SHAPES * sizeof(ShapeTab<double>) + 256;
+           rec_bytes(p->precision) * (size_t)cap * n + sizeof(uint32_t) * (size_t)slot_words(cap) * n + sizeof(SysParams) + 2 * DEM_MAX_SHAPES * sizeof(ShapeTab<double>) + 256;
 }
 
 dem_status dem_create_system(const dem_params *params, const dem_state_ptrs *state, const dem_output_ptrs *outputs,
