@@ -17,18 +17,22 @@
 //     more than r_cut has no feature pair inside the cutoff.  The rest queue
 //     in LDS for the feature stage (8 or 16 lanes per pair, a tuning knob):
 //     a per-feature prefilter keeps only vertices, edges and faces within
-//     reach of the other body, every remaining feature pair of Eq. 1/2 gets a
-//     cheap conservative test (plane distance and bounding circle for
-//     vertex-face, bounding spheres for edge-edge and vertex-edge), and the
-//     survivors are compacted into a per-pair LDS queue so the exact
-//     nearest-point and WCA work runs on dense lanes.  The group reduces
-//     force, both torques and energy in a fixed order and writes one record
-//     into each particle's row slot (FP32 records in FP32 mode; every sum
-//     over pairs is FP64).
-//  2. k_gather: each particle sums the records of its row in slot order (no
-//     atomics, deterministic) into F, tau, U_i and W_i, optionally fused
-//     with the closing kick of the integrator; k_replica_tail then closes
-//     the step of each replica (thermostat half steps, budget, rebuilds).
+//     reach of the other body and not wholly beyond one of its supporting
+//     planes, every remaining feature pair of Eq. 1/2 gets a cheap
+//     conservative test (plane distance and bounding circle for
+//     vertex-face; bounding spheres, then the distance of the two lines, for
+//     edge-edge; bounding spheres for vertex-edge), and the survivors are
+//     compacted into a per-pair LDS queue so the exact nearest-point and WCA
+//     work runs on dense lanes.  The group reduces force, both torques and
+//     energy in a fixed order; a pair with a feature pair inside the cutoff
+//     writes one record into each particle's row slot (FP32 records in FP32
+//     mode; every sum over pairs is FP64) and sets the slot's bit in the
+//     particle's written-slot mask.
+//  2. k_gather: each particle sums the records of its written slots in slot
+//     order (deterministic) into F, tau, U_i and W_i and clears its mask,
+//     optionally fused with the closing kick of the integrator;
+//     k_replica_tail then closes the step of each replica (thermostat half
+//     steps, budget, rebuilds).
 // FP32 mode does the geometry in FP32 from FP64 pair offsets rounded once;
 // problems within 1% of the cutoff and segment pairs that are nearly
 // parallel (sin^2 < 1e-2) are redone in FP64, because FP32 cannot resolve
