@@ -235,6 +235,30 @@ def test_nve_energy_fp32_tracks_fp64():
     assert bands["fp32"] < 1.2 * bands["fp64"] + 1e-5
 
 
+def test_long_rows_forces_match_oracle():
+    """Rows longer than 32 slots (56 with a skin of 1.0): records in the
+    second word of a particle's written-slot mask are gathered too."""
+    dem = _dem()
+    s = I.cubes_3d_contact(n_side=8)
+    s.skin = 1.0
+    ref = O.forces(s)
+    for prec in ("fp32", "fp64"):
+        with dem.DemSystem(s, prec) as g:
+            L = g.lists()
+            out = g.outputs()
+        n_nbr, nbr = L["n_nbr"], L["nbr"]
+        assert n_nbr.max() > 40
+        bound = 2 * s.shapes[0].circumradius + 2 ** (1 / 6) * 2 * s.shapes[0].r
+        far = [(i, nbr[k, i]) for i in range(s.n) for k in range(32, n_nbr[i])]
+        d = np.array([s.x[j] - s.x[i] for i, j in far])
+        d -= s.box * np.round(d / s.box)
+        assert (np.sum(d * d, axis=1) < bound ** 2).any(), "no interacting pair beyond slot 31"
+        err = compare(out, ref, prec)
+        print("long rows", prec, int(n_nbr.max()), err, flush=True)
+        for k, e in err.items():
+            assert e <= TOL[prec], (prec, k, e)
+
+
 def test_capacity_overflow_is_reported():
     dem = _dem()
     s = I.cubes_3d_contact(n_side=6)
