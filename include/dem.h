@@ -237,9 +237,11 @@ dem_status dem_force_stats(dem_handle h, int64_t *out, int32_t reset);
 dem_status dem_set_counting(dem_handle h, int32_t on);
 
 /* Launches the force kernel alone `reps` times on the current state (no
- * list work, no counters), bracketed by HIP events recorded on the system's
- * stream, and returns the mean duration of one launch in milliseconds.
- * Outputs are overwritten with the same values.  Synchronises. */
+ * list work, no counters): the launches are captured in one HIP graph, which
+ * runs once to warm up and once bracketed by HIP events recorded on the
+ * system's stream, and the mean duration of one launch in milliseconds is
+ * returned (back-to-back launches, as inside a step graph).  Outputs are
+ * overwritten with the same values.  Synchronises. */
 dem_status dem_time_forces(dem_handle h, int32_t reps, double *mean_ms);
 
 /* Pair-kernel launch shape (a tuning knob; results do not depend on it,

@@ -1373,19 +1373,32 @@ dem_status dem_set_counting(dem_handle h, int32_t on)
 dem_status dem_time_forces(dem_handle h, int32_t reps, double *mean_ms)
 {
     if (!h || !mean_ms || reps < 1) return fail(h, DEM_E_ARG, "bad argument");
-    hipEvent_t e0, e1;
-    HIPCHK(h, hipEventCreate(&e0));
-    HIPCHK(h, hipEventCreate(&e1));
+    // The launches are captured in one graph, so they run back to back as
+    // in a step graph and the mean is the kernel's own duration (separate
+    // launches would add the host-side gap between them).
     const Launch L = make_launch(h);
-    launch_pairs(L, nullptr, h->stream);  // warm
-    HIPCHK(h, hipEventRecord(e0, h->stream));
-    for (int r = 0; r < reps; ++r) launch_pairs(L, nullptr, h->stream);
-    HIPCHK(h, hipEventRecord(e1, h->stream));
-    HIPCHK(h, hipEventSynchronize(e1));
+    HIPCHK(h, hipStreamBeginCapture(h->cap_stream, hipStreamCaptureModeThreadLocal));
+    for (int r = 0; r < reps; ++r) launch_pairs(L, nullptr, h->cap_stream);
+    hipGraph_t g = nullptr;
+    hipError_t e = hipStreamEndCapture(h->cap_stream, &g);
+    if (e != hipSuccess || !g) return fail(h, DEM_E_HIP, "graph capture failed: %s", hipGetErrorString(e));
+    hipGraphExec_t x = nullptr;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
     float ms = 0.0f;
-    HIPCHK(h, hipEventElapsedTime(&ms, e0, e1));
-    (void)hipEventDestroy(e0);
-    (void)hipEventDestroy(e1);
+    e = hipGraphInstantiate(&x, g, nullptr, nullptr, 0);
+    if (e == hipSuccess) e = hipEventCreate(&e0);
+    if (e == hipSuccess) e = hipEventCreate(&e1);
+    if (e == hipSuccess) e = hipGraphLaunch(x, h->stream);  // warm
+    if (e == hipSuccess) e = hipEventRecord(e0, h->stream);
+    if (e == hipSuccess) e = hipGraphLaunch(x, h->stream);
+    if (e == hipSuccess) e = hipEventRecord(e1, h->stream);
+    if (e == hipSuccess) e = hipEventSynchronize(e1);
+    if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+    if (e1) (void)hipEventDestroy(e1);
+    if (e0) (void)hipEventDestroy(e0);
+    if (x) (void)hipGraphExecDestroy(x);
+    (void)hipGraphDestroy(g);
+    if (e != hipSuccess) return fail(h, DEM_E_HIP, "force timing failed: %s", hipGetErrorString(e));
     *mean_ms = (double)ms / reps;
     return DEM_OK;
 }
