@@ -409,9 +409,27 @@ def lprism(r: float = 0.1, quad_h: float = 0.01) -> Shape:
     return _finish_3d("lprism", verts, faces, r, V, M1, S)
 
 
+def icosahedron(edge: float = 1.0, r: float = 0.1) -> Shape:
+    """Regular icosahedron (12 vertices, 30 edges, 20 triangular faces: the
+    face limit of the shape tables), vertices at the cyclic permutations of
+    (0, +-1, +-phi) scaled to the edge."""
+    phi = 0.5 * (1.0 + math.sqrt(5.0))
+    base = []
+    for a in (-1.0, 1.0):
+        for b in (-phi, phi):
+            base += [[0.0, a, b], [a, b, 0.0], [b, 0.0, a]]
+    return convex_polyhedron(0.5 * edge * np.array(base), r, "icosahedron")
+
+
+def hexadecagon(edge: float = 0.5, r: float = 0.1) -> Shape:
+    """Regular 16-gon: the vertex limit of the shape tables, in 2D."""
+    return regular_polygon(16, edge, r, "hexadecagon")
+
+
 SHAPES = {
     "square": square, "pentagon": pentagon, "cube": cube,
     "octahedron": octahedron, "tetrahedron": tetrahedron, "lprism": lprism,
+    "icosahedron": icosahedron, "hexadecagon": hexadecagon,
 }
 
 

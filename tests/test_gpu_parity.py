@@ -33,6 +33,9 @@ def _cases():
         "dimers_tetra_256": lambda: I.dimer_gas("tetrahedron", 128),
         "dimers_lprism_128": lambda: I.dimer_gas("lprism", 64, quad_h=0.05),
         "dimers_pentagon_256": lambda: I.dimer_gas("pentagon", 128, dim=2),
+        # the table limits: 20 faces and 30 edges (3D), 16 vertices (2D)
+        "dimers_icosa_128": lambda: I.dimer_gas("icosahedron", 64),
+        "dimers_16gon_128": lambda: I.dimer_gas("hexadecagon", 64, dim=2),
         "ragged_cubes_37": lambda: _drop_last(I.dimer_gas("cube", 19, seed=5)),
     }
 

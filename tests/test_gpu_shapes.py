@@ -18,6 +18,7 @@ CASES = {
     "dimers_lprism_128": lambda: I.dimer_gas("lprism", 64, quad_h=0.05),
     "squares_2d_contact_256": lambda: I.squares_2d_contact(),
     "dimers_pentagon_256": lambda: I.dimer_gas("pentagon", 128, dim=2),
+    "dimers_icosa_128": lambda: I.dimer_gas("icosahedron", 64),
 }
 
 

@@ -19,7 +19,7 @@ def test_rounded_square_closed_form():
     assert s.inertia[2] == pytest.approx(0.3605121, abs=1e-7)
 
 
-@pytest.mark.parametrize("name,r", [("cube", 0.15), ("octahedron", 0.1), ("tetrahedron", 0.2)])
+@pytest.mark.parametrize("name,r", [("cube", 0.15), ("octahedron", 0.1), ("tetrahedron", 0.2), ("icosahedron", 0.1)])
 def test_steiner_volume(name, r):
     s = I.SHAPES[name](r=r)
     v = s.vertices
@@ -29,12 +29,27 @@ def test_steiner_volume(name, r):
         a = 1.0
         V, S = math.sqrt(2) / 3 * a ** 3, 2 * math.sqrt(3) * a ** 2
         M = 12 * a * (math.pi - math.acos(-1 / 3)) / 2
+    elif name == "icosahedron":
+        a = 1.0
+        V, S = 5 * (3 + math.sqrt(5)) / 12 * a ** 3, 5 * math.sqrt(3) * a ** 2
+        M = 30 * a * (math.pi - math.acos(-math.sqrt(5) / 3)) / 2
+        assert (len(s.vertices), len(s.edges), len(s.faces)) == (12, 30, 20)
     else:
         a = 1.0
         V, S = a ** 3 / (6 * math.sqrt(2)), math.sqrt(3) * a ** 2
         M = 6 * a * (math.pi - math.acos(1 / 3)) / 2
     assert s.volume == pytest.approx(V + S * r + M * r * r + 4 / 3 * math.pi * r ** 3, rel=1e-12)
     assert np.allclose(s.inertia, s.inertia[0], rtol=1e-10)   # symmetric bodies
+
+
+def test_hexadecagon_at_the_vertex_limit():
+    """Regular 16-gon of edge a, rounded by r: area n a^2 / (4 tan(pi/n)) +
+    perimeter r + pi r^2 (Steiner in 2D)."""
+    a, r, n = 0.5, 0.1, 16
+    s = I.hexadecagon(a, r)
+    assert len(s.vertices) == 16 and len(s.edges) == 16
+    A0 = n * a * a / (4 * math.tan(math.pi / n))
+    assert s.volume == pytest.approx(A0 + n * a * r + math.pi * r * r, rel=1e-12)
 
 
 def test_cube_inertia_matches_quadrature():
