@@ -259,6 +259,29 @@ def energy_fluctuations(dts_tau=(0.000625, 0.00125, 0.0025, 0.005, 0.01), durati
     return out
 
 
+def table1_workloads(steps=(2000, 1000, 300), warmup=200):
+    """The paper's Table I shapes and sizes on this engine: rounded cubes and
+    rounded icosahedra (edge 1, r = 0.15 and 0.1) at N = 6^3, 16^3 and 40^3
+    (its 256, 4096 and 65536 on cubic lattices), volume fraction 0.4, NVT
+    kT = 1 after `warmup` steps, FP32 pair geometry, tuned pair shape.  The
+    paper gives no densities; these are ours."""
+    from paper_1607_02427_amd import inputs as I
+    out = []
+    for name, shp, orient in (("cube", I.cube(1.0, 0.15), "small"), ("icosahedron", I.icosahedron(1.0, 0.1), "aligned")):
+        for n_side, k in zip((6, 16, 40), steps):
+            s = I.lattice_system(shp, n_side, 0.4, 31 + n_side, orient=orient, max_deg=10.0,
+                                 name=f"{name}_{n_side ** 3}")
+            s.ensemble = "nvt"
+            s.dt = 5e-4
+            g, r = run_path(s, "fp32", k, warmup)
+            g.close()
+            ptps = s.n * k / (r["gpu_ms"] * 1e-3)
+            out.append(dict(shape=name, n=s.n, steps=k, value=ptps, ms_per_step=r["gpu_ms"] / k,
+                            pair_shape=[r["pair_shape"][a] for a in ("lanes", "grid", "waves")]))
+            log(f"[table1] {name} N={s.n}: {ptps:.3e} PTPS ({r['gpu_ms'] / k * 1e3:.1f} us/step)")
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -276,6 +299,8 @@ def main():
     ap.add_argument("--scale-steps", type=int, default=300)
     ap.add_argument("--copy-mb", type=int, default=0,
                     help="finish with device copies of this many MiB (scale for the HBM byte counters)")
+    ap.add_argument("--table1", action="store_true",
+                    help="run only the cube and icosahedron workloads of the paper's Table I and print their JSON line")
     ap.add_argument("--energy-study", action="store_true",
                     help="run only the NVE energy-fluctuation study (Sec. IV.A) and print its JSON line")
     ap.add_argument("--no-sequential", action="store_true",
@@ -288,6 +313,10 @@ def main():
     import torch
     from paper_1607_02427_amd import inputs as I
     assert torch.cuda.is_available(), "bench.py needs a GPU"
+    if args.table1:
+        print(json.dumps({"metric": "particle-timesteps/s, Table I shapes and sizes", "unit": "particle-timesteps/s",
+                          "data": "synthetic", "dtype": "f32", "runs": table1_workloads()}), flush=True)
+        return
     if args.energy_study:
         print(json.dumps({"metric": "sigma(E/N) of NVE runs against the timestep (Sec. IV.A)", "unit": "eps",
                           "data": "synthetic", "study": energy_fluctuations()}), flush=True)
