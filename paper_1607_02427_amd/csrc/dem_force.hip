@@ -209,6 +209,9 @@ struct PairLds {
     // r_cut beyond (bit p: plane p)
     unsigned vib[DEM_MAX_VERTS], vjb[DEM_MAX_VERTS];
     unsigned short queue[kQueue];
+    // the pair's problem counts and queue length, for the lanes of other
+    // groups that solve its problems in the pooled solve (16 lanes per pair)
+    int nA, nB, nfj, nfi, nej, cnt;
 };
 
 // Closest points of segments p1 + s d1 and p2 + t d2 (s, t in [0,1]) with
@@ -597,6 +600,9 @@ __global__ void __launch_bounds__(64 * kWaves, OCC) k_pairs(BatchParams b, const
     RepLds &rl = *reinterpret_cast<RepLds *>(smem + orl);
     PairLds<T> *pls = reinterpret_cast<PairLds<T> *>(smem + orl + sizeof(RepLds));
     QEnt<T> *qall = reinterpret_cast<QEnt<T> *>(smem + orl + sizeof(RepLds) + kWaves * kGroups * sizeof(PairLds<T>));
+    // results of one pooled solve step, one per lane (16 lanes per pair only)
+    constexpr bool kPool = kGL == 16;
+    Acc<T> *pres = reinterpret_cast<Acc<T> *>(reinterpret_cast<unsigned char *>(qall) + kWaves * kQCap * sizeof(QEnt<T>));
 
     const int lane = __lane_id();
     const int wid = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -649,6 +655,7 @@ __global__ void __launch_bounds__(64 * kWaves, OCC) k_pairs(BatchParams b, const
                 sj = qe.sj;
                 t = v3<T>(qe.t[0], qe.t[1], qe.t[2]);
             }
+            const int h0 = head;  // the round's first entry
             head += take;
             const ShapeTab<T> &Si = tab[si];
             const ShapeTab<T> &Sj = tab[sj];
@@ -791,6 +798,91 @@ __global__ void __launch_bounds__(64 * kWaves, OCC) k_pairs(BatchParams b, const
                 // queue is checked after each kVirt candidates
                 if (last || ((qb + kGL) % kVirt == 0 && __ballot(count > kQueue - kVirt) != 0)) {
                     wave_sync_lds();
+                    if constexpr (kPool) {
+                        // The round's problems of all the wavefront's pairs
+                        // are shared out over its 64 lanes, so a pair with
+                        // many problems no longer holds up the others; each
+                        // result goes through LDS to the lane that owns its
+                        // partial sum (problem k: lane k mod 16 of the pair's
+                        // group) and is added there in problem order, the
+                        // order of the unpooled steps, so every pair shape
+                        // gives the same bits.
+                        if (sub == 0) {
+                            W.nA = P.nA;
+                            W.nB = P.nB;
+                            W.nfj = P.nfj;
+                            W.nfi = P.nfi;
+                            W.nej = P.nej;
+                            W.cnt = count;
+                        }
+                        wave_sync_lds();
+                        int offs[kGroups + 1];
+                        offs[0] = 0;
+#pragma unroll
+                        for (int h = 0; h < kGroups; ++h) offs[h + 1] = offs[h] + pls[wid * kGroups + h].cnt;
+                        Acc<T> *res = pres + wid * 64;
+                        for (int c0 = 0; c0 < offs[kGroups]; c0 += 64) {
+                            const int c = c0 + lane;
+                            Acc<T> A;
+                            A.F = A.Ti = A.Tj = v3<T>(0, 0, 0);
+                            A.U = T(0);
+                            if (c < offs[kGroups]) {
+                                int g = 0;
+#pragma unroll
+                                for (int h = 1; h < kGroups; ++h) g += c >= offs[h] ? 1 : 0;
+                                const PairLds<T> &Wg = pls[wid * kGroups + g];
+                                const QEnt<T> &qg = qall[wid * kQCap + (h0 + g) % kQCap];
+                                const int gi = qg.si, gj = qg.sj;
+                                const ShapeTab<T> &Sgi = tab[gi];
+                                const ShapeTab<T> &Sgj = tab[gj];
+                                const V3<T> tg = v3<T>(qg.t[0], qg.t[1], qg.t[2]);
+                                const Problem<T, DIM> Pg{Sgi, Sgj, Wg, *reinterpret_cast<const M3<T> *>(qg.Rr), tg,
+                                                         Wg.nA, Wg.nB, Wg.nfj, Wg.nfi, Wg.nej,
+                                                         1.0f / (float)(Wg.nfj > 0 ? Wg.nfj : 1),
+                                                         1.0f / (float)(Wg.nfi > 0 ? Wg.nfi : 1),
+                                                         1.0f / (float)(Wg.nej > 0 ? Wg.nej : 1)};
+                                const double sigd = rl.rad[gi] + rl.rad[gj];
+                                const T gsig2 = (T)(sigd * sigd);
+                                const T grc = (T)(kWcaCut * sigd);
+                                const T grc2 = grc * grc;
+                                V3<T> Pt, rho;
+                                T sin2;
+                                int e, gf;
+                                const int fam = Pg.solve(Wg.queue[c - offs[g]], par_s2, Pt, rho, sin2, e, gf);
+                                c_near.add(fam < 2 ? 1 : 0);
+                                c_ee.add(fam == 2 ? 1 : 0);
+                                const T r2 = dot(rho, rho);
+                                const bool redo = sizeof(T) == 4 &&
+                                                  ((r2 > T(0.99) * grc2 && r2 < T(1.0001) * grc2) ||
+                                                   (DIM == 3 && fam == 2 && sin2 < T(1e-2) &&
+                                                    r2 < T(1.0001) * grc2 + T(1e-3) * grc));
+                                if (redo) {
+                                    c_ref.add(1);
+                                    c_in.add(refine_pair<T, DIM>(rl.box, rl.eps, rl.par_s2, rec64[qg.ent.x], rec64[qg.ent.y],
+                                                                Sgi, Sgj, gtab64[rl.sbase + gi], gtab64[rl.sbase + gj], fam,
+                                                                e, gf, sigd, A));
+                                } else {
+                                    c_in.add(add_wca(A, Pt, rho, tg, gsig2, grc2, eps));
+                                }
+                            }
+                            res[lane] = A;
+                            wave_sync_lds();
+                            // this lane's partial sum: problems sub, sub + 16, ...
+                            // of its pair that fall in this step
+                            const int lo = offs[grp] > c0 ? offs[grp] : c0;
+                            const int hi = offs[grp + 1] < c0 + 64 ? offs[grp + 1] : c0 + 64;
+                            int k = lo - offs[grp];
+                            k += (sub - k % kVirt + kVirt) % kVirt;
+                            for (; offs[grp] + k < hi; k += kVirt) {
+                                const Acc<T> &B = res[offs[grp] + k - c0];
+                                A0.F = A0.F + B.F;
+                                A0.Ti = A0.Ti + B.Ti;
+                                A0.Tj = A0.Tj + B.Tj;
+                                A0.U += B.U;
+                            }
+                            wave_sync_lds();
+                        }
+                    } else
                     for (int m = 0;; ++m) {
                         const int k = m * kGL + sub;
                         const bool w = k < count;
@@ -1363,7 +1455,9 @@ size_t pair_kernel_lds(int precision, int tab_slots, int lanes)
     const size_t w = precision == DEM_FP32 ? sizeof(ShapeTab<float>) : sizeof(ShapeTab<double>);
     const size_t pl = precision == DEM_FP32 ? sizeof(PairLds<float>) : sizeof(PairLds<double>);
     const size_t qe = precision == DEM_FP32 ? sizeof(QEnt<float>) : sizeof(QEnt<double>);
-    return (size_t)tab_slots * w + sizeof(RepLds) + kWaves * (64 / lanes) * pl + kWaves * queue_slots(lanes) * qe;
+    const size_t acc = precision == DEM_FP32 ? sizeof(Acc<float>) : sizeof(Acc<double>);
+    return (size_t)tab_slots * w + sizeof(RepLds) + kWaves * (64 / lanes) * pl + kWaves * queue_slots(lanes) * qe +
+           (lanes == 16 ? kWaves * 64 * acc : 0);
 }
 
 namespace {
