@@ -794,9 +794,14 @@ __global__ void __launch_bounds__(64 * kWaves, OCC) k_pairs(BatchParams b, const
                     if (keep) W.queue[count + __popcll(m & below & gmask)] = (unsigned short)q;
                     count += __popcll(m & gmask);
                 }
-                // rounds end at the same problems for any lane count: the
-                // queue is checked after each kVirt candidates
-                if (last || ((qb + kGL) % kVirt == 0 && __ballot(count > kQueue - kVirt) != 0)) {
+                // rounds end at the same problems for any lane count and any
+                // other pairs in the wavefront: a pair's queue is checked
+                // after each kVirt of its candidates, and only a pair whose
+                // queue is nearly full (or every pair, after its last
+                // candidate) solves it at that point
+                const bool full = (qb + kGL) % kVirt == 0 && count > kQueue - kVirt;
+                if (last || __ballot(full) != 0) {
+                    const int scount = (last || full) ? count : 0;  // this pair's problems solved now
                     wave_sync_lds();
                     if constexpr (kPool) {
                         // The round's problems of all the wavefront's pairs
@@ -813,7 +818,7 @@ __global__ void __launch_bounds__(64 * kWaves, OCC) k_pairs(BatchParams b, const
                             W.nfj = P.nfj;
                             W.nfi = P.nfi;
                             W.nej = P.nej;
-                            W.cnt = count;
+                            W.cnt = scount;
                         }
                         wave_sync_lds();
                         int offs[kGroups + 1];
@@ -885,7 +890,7 @@ __global__ void __launch_bounds__(64 * kWaves, OCC) k_pairs(BatchParams b, const
                     } else
                     for (int m = 0;; ++m) {
                         const int k = m * kGL + sub;
-                        const bool w = k < count;
+                        const bool w = k < scount;
                         if (__ballot(w) == 0) break;
                         if (w) {
                             Acc<T> A;
@@ -915,7 +920,7 @@ __global__ void __launch_bounds__(64 * kWaves, OCC) k_pairs(BatchParams b, const
                             S.U += A.U;
                         }
                     }
-                    count = 0;
+                    count -= scount;
                     wave_sync_lds();
                 }
                 if (last) break;
