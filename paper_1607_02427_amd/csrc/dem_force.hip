@@ -801,7 +801,7 @@ __global__ void __launch_bounds__(64 * kWaves, OCC) k_pairs(BatchParams b, const
                 // candidate) solves it at that point
                 const bool full = (qb + kGL) % kVirt == 0 && count > kQueue - kVirt;
                 if (last || __ballot(full) != 0) {
-                    const int scount = (last || full) ? count : 0;  // this pair's problems solved now
+                    const bool mine = last || full;  // this pair solves its queue now
                     wave_sync_lds();
                     if constexpr (kPool) {
                         // The round's problems of all the wavefront's pairs
@@ -818,7 +818,7 @@ __global__ void __launch_bounds__(64 * kWaves, OCC) k_pairs(BatchParams b, const
                             W.nfj = P.nfj;
                             W.nfi = P.nfi;
                             W.nej = P.nej;
-                            W.cnt = scount;
+                            W.cnt = mine ? count : 0;
                         }
                         wave_sync_lds();
                         int offs[kGroups + 1];
@@ -890,7 +890,7 @@ __global__ void __launch_bounds__(64 * kWaves, OCC) k_pairs(BatchParams b, const
                     } else
                     for (int m = 0;; ++m) {
                         const int k = m * kGL + sub;
-                        const bool w = k < scount;
+                        const bool w = mine && k < count;
                         if (__ballot(w) == 0) break;
                         if (w) {
                             Acc<T> A;
@@ -920,7 +920,7 @@ __global__ void __launch_bounds__(64 * kWaves, OCC) k_pairs(BatchParams b, const
                             S.U += A.U;
                         }
                     }
-                    count -= scount;
+                    if (mine) count = 0;
                     wave_sync_lds();
                 }
                 if (last) break;

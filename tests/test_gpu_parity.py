@@ -36,6 +36,12 @@ def _cases():
         # the table limits: 20 faces and 30 edges (3D), 16 vertices (2D)
         "dimers_icosa_128": lambda: I.dimer_gas("icosahedron", 64),
         "dimers_16gon_128": lambda: I.dimer_gas("hexadecagon", 64, dim=2),
+        # small cores with a large rounding radius: a hundred to several
+        # hundred feature problems per pair in range, so solve rounds end
+        # part-way through a pair and pairs of one wavefront end them at
+        # different points
+        "fat_dimers_16gon_128": lambda: I.dimer_gas("hexadecagon", 64, dim=2, edge=0.1, r=0.5),
+        "fat_dimers_icosa_128": lambda: I.dimer_gas("icosahedron", 64, edge=0.3, r=0.5),
         "ragged_cubes_37": lambda: _drop_last(I.dimer_gas("cube", 19, seed=5)),
     }
 

@@ -19,6 +19,10 @@ CASES = {
     "squares_2d_contact_256": lambda: I.squares_2d_contact(),
     "dimers_pentagon_256": lambda: I.dimer_gas("pentagon", 128, dim=2),
     "dimers_icosa_128": lambda: I.dimer_gas("icosahedron", 64),
+    # hundreds of in-range problems per pair: solve rounds end part-way
+    # through pairs, at different points for the pairs of one wavefront
+    "fat_dimers_16gon_128": lambda: I.dimer_gas("hexadecagon", 64, dim=2, edge=0.1, r=0.5),
+    "fat_dimers_icosa_128": lambda: I.dimer_gas("icosahedron", 64, edge=0.3, r=0.5),
 }
 
 
