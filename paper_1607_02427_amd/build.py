@@ -3,6 +3,7 @@
 Every HIP source is compiled with packed-FP32 instructions disabled (the
 compiler would otherwise form v_pk_* FP32 operations on its own)."""
 import os
+import re
 import subprocess
 import sys
 from concurrent.futures import ThreadPoolExecutor
@@ -19,12 +20,26 @@ FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-Wall",
          "-I" + os.path.join(ROOT, "include"), "-I" + CSRC]
 
 
+def resources_path(src: str) -> str:
+    """The compiler's per-kernel resource report (registers, scratch, LDS,
+    occupancy) for one source, written by the last build."""
+    return os.path.join(BUILD, src.replace(".hip", ".resources.txt"))
+
+
 def _compile(src: str, verbose: bool) -> str:
     obj = os.path.join(BUILD, src.replace(".hip", ".o"))
-    cmd = [HIPCC] + FLAGS + ["-c", os.path.join(CSRC, src), "-o", obj]
+    cmd = [HIPCC] + FLAGS + ["-Rpass-analysis=kernel-resource-usage", "-c", os.path.join(CSRC, src), "-o", obj]
     if verbose:
         print(" ".join(cmd), flush=True)
-    subprocess.run(cmd, check=True)
+    r = subprocess.run(cmd, stderr=subprocess.PIPE, text=True)
+    with open(resources_path(src), "w") as f:
+        f.write(r.stderr)
+    # pass warnings and errors through; the resource remarks go to the file
+    rest = [ln for ln in r.stderr.splitlines() if "remark:" not in ln and not re.match(r"\s*\d*\s*\|", ln)]
+    if rest:
+        print("\n".join(rest), file=sys.stderr, flush=True)
+    if r.returncode != 0:
+        raise subprocess.CalledProcessError(r.returncode, cmd)
     return obj
 
 

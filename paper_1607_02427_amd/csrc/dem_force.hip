@@ -976,7 +976,6 @@ __global__ void __launch_bounds__(64 * kWaves, OCC) k_pairs(BatchParams b, const
         }
         // ---- first stage on tile tt: 4 lanes per pair ----
         const int grp1 = lane / kSepLanes, sub1 = lane % kSepLanes;
-        const unsigned long long gmask1 = ((1ull << kSepLanes) - 1) << (kSepLanes * grp1);
         const int q = (tt - rl.first_tile) * kTile + wid * kPairsPerWave + grp1;
         const bool active = q < rl.np;
         // two dependent round trips: the pair entry, then both particle
