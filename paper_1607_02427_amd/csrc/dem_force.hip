@@ -1315,9 +1315,15 @@ __global__ void __launch_bounds__(kGatherBlock) k_replica_tail(const SysParams *
 {
     __shared__ double sh[kGatherBlock];
     const int r = blockIdx.x;
-    const SysParams &p = reps[r];
-    if (!p.live || p.n == 0 || budget[r] <= 0) return;
     int32_t *fl = l.flags + r * FLAG_COUNT;
+    double *th = thermo + r * TH_COUNT;
+    // the slot's step values are requested together with its parameters
+    // (the thermostat slots exist for every replica slot)
+    const int64_t left = budget[r];
+    const int32_t rebuilt = fl[FLAG_REBUILD], trigger = fl[FLAG_TRIGGER];
+    const double xi0 = th[TH_XI], eta0 = th[TH_ETA];
+    const SysParams &p = reps[r];
+    if (!p.live || p.n == 0 || left <= 0) return;
     if (p.ensemble == DEM_NVT) {
         const int nblk = (p.n + kChunk - 1) / kChunk;
         const int c0 = p.off / kChunk;
@@ -1325,8 +1331,7 @@ __global__ void __launch_bounds__(kGatherBlock) k_replica_tail(const SysParams *
         for (int c = threadIdx.x; c < nblk; c += blockDim.x) acc2 += ke_part[2 * (c0 + c)] + ke_part[2 * (c0 + c) + 1];
         double K = block_sum<kGatherBlock>(acc2, sh);
         if (threadIdx.x == 0) {
-            double *th = thermo + r * TH_COUNT;
-            double xi = th[TH_XI], eta = th[TH_ETA];
+            double xi = xi0, eta = eta0;
             const double sb = nh_half(p, xi, eta, K);  // closes this step
             th[TH_XI_B] = xi;
             th[TH_ETA_B] = eta;
@@ -1339,14 +1344,14 @@ __global__ void __launch_bounds__(kGatherBlock) k_replica_tail(const SysParams *
         }
     }
     if (threadIdx.x == 0) {
-        budget[r] -= 1;
+        budget[r] = left - 1;
         steps[r] += 1;
-        if (fl[FLAG_REBUILD] != 0) {  // this step's lists are built: count them
+        if (rebuilt != 0) {  // this step's lists are built: count them
             fl[FLAG_REBUILD] = 0;
             fl[FLAG_NBUILDS] += 1;
             atomicSub(&l.gflags[G_ANY], 1);
         }
-        if (fl[FLAG_TRIGGER] != 0) {  // the next step rebuilds
+        if (trigger != 0) {  // the next step rebuilds
             fl[FLAG_TRIGGER] = 0;
             fl[FLAG_REBUILD] = 1;
             atomicAdd(&l.gflags[G_ANY], 1);

@@ -202,13 +202,19 @@ __global__ void __launch_bounds__(kBlock) k_kick_drift(BatchParams b, const SysP
         for (int a = 0; a < DIM; ++a) xl[a] = l.xlast[(size_t)a * b.N + i];
     const int r = wave_replica(b, l, i);
     if (r < 0) return;
+    // the replica's per-step values are requested together with its
+    // parameters, not one round trip after another (this kernel writes
+    // none of them; the thermostat slots exist for every replica)
+    const int64_t left = budget[r];
+    const double th_sb = thermo[r * TH_COUNT + TH_SB], th_sa = thermo[r * TH_COUNT + TH_SA];
+    const int32_t rebuild = l.flags[r * FLAG_COUNT + FLAG_REBUILD];
     const SysParams &p = reps[r];
-    if (i >= p.off + p.n || budget[r] <= 0) return;
+    if (i >= p.off + p.n || left <= 0) return;
     // pending thermostat factors: the closing half step of the last step,
     // then the opening half step of this one (1 and 1 without a thermostat)
     const bool nvt = p.ensemble == DEM_NVT;
-    const double sb = nvt ? thermo[r * TH_COUNT + TH_SB] : 1.0;
-    const double sa = nvt ? thermo[r * TH_COUNT + TH_SA] : 1.0;
+    const double sb = nvt ? th_sb : 1.0;
+    const double sa = nvt ? th_sa : 1.0;
     const double hm = 0.5 * p.dt / p.mass[sid];
     const double I[3] = {p.inertia[sid][0], p.inertia[sid][1], p.inertia[sid][2]};
     double v[3] = {(v0[0] * sb) * sa + hm * F0[0], (v0[1] * sb) * sa + hm * F0[1], 0.0};
@@ -277,7 +283,7 @@ __global__ void __launch_bounds__(kBlock) k_kick_drift(BatchParams b, const SysP
     s.image[3 * i] = img[0];
     s.image[3 * i + 1] = img[1];
     s.image[3 * i + 2] = img[2];
-    if (l.flags[r * FLAG_COUNT + FLAG_REBUILD] != 0) {
+    if (rebuild != 0) {
         // this step rebuilds the lists: the particle goes into its cell now
         // (and the replica's pair total restarts for k_nbr to add to)
         if (i == p.off) l.flags[r * FLAG_COUNT + FLAG_NPAIRS] = 0;
