@@ -1185,7 +1185,8 @@ __global__ void __launch_bounds__(kGatherBlock) k_gather(BatchParams b, const Sy
     __shared__ double sh[kGatherBlock];
     constexpr int kB = gather_batch<T>();
     const int sub = threadIdx.x % kGatherLanes;
-    const int i = blockIdx.x * kGatherPer + threadIdx.x / kGatherLanes;
+    const int cb = xcd_block(blockIdx.x, gridDim.x);  // this block's chunk
+    const int i = cb * kGatherPer + threadIdx.x / kGatherLanes;
     // what depends on the slot alone is requested with the replica's
     // parameters instead of after them (the row length from the library's
     // N slots; the state only within the length of its arrays)
@@ -1209,7 +1210,7 @@ __global__ void __launch_bounds__(kGatherBlock) k_gather(BatchParams b, const Sy
         }
     }
     const unsigned stamp = (unsigned)l.gflags[G_STAMP];  // records of this evaluation only
-    const int r = l.chunk_rep[blockIdx.x];
+    const int r = cb < b.nchunk ? l.chunk_rep[cb] : -1;
     if (r < 0) return;
     const SysParams &p = reps[r];
     if (KICK && budget[r] <= 0) return;
@@ -1296,8 +1297,8 @@ __global__ void __launch_bounds__(kGatherBlock) k_gather(BatchParams b, const Sy
     kt = block_sum<kGatherBlock>(kt, sh);
     kr = block_sum<kGatherBlock>(kr, sh);
     if (threadIdx.x == 0) {
-        ke_part[2 * blockIdx.x] = kt;
-        ke_part[2 * blockIdx.x + 1] = kr;
+        ke_part[2 * cb] = kt;
+        ke_part[2 * cb + 1] = kr;
     }
 }
 
@@ -1412,12 +1413,12 @@ void gather_t(const Launch &L, bool kick, hipStream_t stream)
 {
     const SlotRec<T> *rec = reinterpret_cast<const SlotRec<T> *>(L.f.rec);
     if (kick) {
-        k_gather<T, DIM, true><<<L.b.nchunk, kGatherBlock, 0, stream>>>(L.b, L.reps, L.s, L.o, L.l, rec, L.ke_part,
+        k_gather<T, DIM, true><<<pad8(L.b.nchunk), kGatherBlock, 0, stream>>>(L.b, L.reps, L.s, L.o, L.l, rec, L.ke_part,
                                                                     L.thermo, L.budget, L.steps);
         k_replica_tail<<<L.b.nrep, kGatherBlock, 0, stream>>>(L.reps, L.l, L.ke_part, L.thermo, L.budget, L.steps);
     }
     else
-        k_gather<T, DIM, false><<<L.b.nchunk, kGatherBlock, 0, stream>>>(L.b, L.reps, L.s, L.o, L.l, rec, L.ke_part,
+        k_gather<T, DIM, false><<<pad8(L.b.nchunk), kGatherBlock, 0, stream>>>(L.b, L.reps, L.s, L.o, L.l, rec, L.ke_part,
                                                                      L.thermo, L.budget, L.steps);
 }
 

@@ -163,7 +163,7 @@ __global__ void __launch_bounds__(kBlock) k_kick_drift(BatchParams b, const SysP
                                                           ListPtrs l, const double *thermo, const int64_t *budget,
                                                           void *rot, PartRec64 *rec64)
 {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int i = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
     if (i == 0) l.gflags[G_STAMP] += 1;  // this step's force evaluation
     // the particle's own values are requested with the replica's parameters
     // instead of after them (within the length of the state arrays)
@@ -377,7 +377,7 @@ void launch_nh_end(const Launch &L, hipStream_t stream)
 template <typename T>
 void kick_drift_t(const Launch &L, hipStream_t stream)
 {
-    const int nb = blocks_for(L.b.nchunk * kChunk);
+    const int nb = pad8(blocks_for(L.b.nchunk * kChunk));
     if (L.b.dim == 3)
         k_kick_drift<T, 3><<<nb, kBlock, 0, stream>>>(L.b, L.reps, L.s, L.o, L.l, L.thermo, L.budget, L.f.rot,
                                                        L.f.rec64);

@@ -309,6 +309,14 @@ void launch_energy_partials(const Launch &L, double *part, hipStream_t stream);
 
 constexpr int kBlock = 256;
 inline int blocks_for(int n) { return (n + kBlock - 1) / kBlock; }
+// Workgroups go to the eight XCDs in turn (block b to XCD b mod 8), each
+// with its own L2. A grid of a multiple of 8 blocks read through
+// xcd_block() gives XCD x the x-th eighth of the logical blocks, so the
+// step kernels (kick and drift, gather) and the pair kernel, which splits
+// its tiles the same way, touch a particle's data on the same XCD step
+// after step and find it in that L2.
+inline int pad8(int blocks) { return (blocks + 7) / 8 * 8; }
+__device__ inline int xcd_block(int b, int G) { return (b & 7) * (G >> 3) + (b >> 3); }
 // The gather and the kinetic reduction map one chunk (kGatherPer = kChunk
 // particles) to each block of kGatherLanes lanes per particle, which writes
 // one kinetic partial.
