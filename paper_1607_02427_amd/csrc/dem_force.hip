@@ -1329,6 +1329,9 @@ __global__ void __launch_bounds__(kGatherBlock) k_replica_tail(const SysParams *
         const int nblk = (p.n + kChunk - 1) / kChunk;
         const int c0 = p.off / kChunk;
         double acc2 = 0.0;
+        // unrolled so that many loads are in flight at once (large
+        // replicas have thousands of chunks); the sums keep their order
+#pragma unroll 8
         for (int c = threadIdx.x; c < nblk; c += blockDim.x) acc2 += ke_part[2 * (c0 + c)] + ke_part[2 * (c0 + c) + 1];
         double K = block_sum<kGatherBlock>(acc2, sh);
         if (threadIdx.x == 0) {
