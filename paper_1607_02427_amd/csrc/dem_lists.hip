@@ -290,6 +290,7 @@ __global__ void __launch_bounds__(kBlock) k_fill(BatchParams b, const SysParams 
             if (lane >= off) incl += v;
         }
         int prior = 0;
+#pragma unroll 8
         for (int q = p.off / kNbrPer + lane; q < c * (kChunk / kNbrPer); q += 64) prior += l.ptot[q];
         for (int off = 32; off > 0; off >>= 1) prior += __shfl_xor(prior, off, 64);
         if (mine) l.pstart[i] = prior + incl - cnt;
