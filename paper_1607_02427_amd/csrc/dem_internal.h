@@ -314,9 +314,10 @@ inline int blocks_for(int n) { return (n + kBlock - 1) / kBlock; }
 // xcd_block() gives XCD x the x-th eighth of the logical blocks, so the
 // step kernels (kick and drift, gather) and the pair kernel, which splits
 // its tiles the same way, touch a particle's data on the same XCD step
-// after step and find it in that L2.
+// after step and find it in that L2. Any other grid size keeps the plain
+// order (still a permutation, only without the locality).
 inline int pad8(int blocks) { return (blocks + 7) / 8 * 8; }
-__device__ inline int xcd_block(int b, int G) { return (b & 7) * (G >> 3) + (b >> 3); }
+__device__ inline int xcd_block(int b, int G) { return (G & 7) ? b : (b & 7) * (G >> 3) + (b >> 3); }
 // The gather and the kinetic reduction map one chunk (kGatherPer = kChunk
 // particles) to each block of kGatherLanes lanes per particle, which writes
 // one kinetic partial.
