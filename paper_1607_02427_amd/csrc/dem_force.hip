@@ -1123,16 +1123,23 @@ __device__ inline void body_torque(const double q[4], double tx, double ty, doub
 template <int NT>
 __device__ inline double block_sum(double v, double *sh)
 {
-    const int t = threadIdx.x;
-    sh[t] = v;
-    __syncthreads();
-    for (int off = NT / 2; off > 0; off >>= 1) {
-        if (t < off) sh[t] += sh[t + off];
+    if constexpr (NT == 64) {
+        // one wavefront: the same pairs as the tree below (lane t adds
+        // lane t + off), through lane shuffles instead of LDS and barriers
+        for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+        return __shfl(v, 0, 64);
+    } else {
+        const int t = threadIdx.x;
+        sh[t] = v;
         __syncthreads();
+        for (int off = NT / 2; off > 0; off >>= 1) {
+            if (t < off) sh[t] += sh[t + off];
+            __syncthreads();
+        }
+        const double r = sh[0];
+        __syncthreads();
+        return r;
     }
-    const double r = sh[0];
-    __syncthreads();
-    return r;
 }
 
 // Nose-Hoover half step of length dt/2 on xi and eta (one variable for
