@@ -159,7 +159,7 @@ __global__ void k_nh_close(int nrep, double *thermo)
 }
 
 template <typename T, int DIM>
-__global__ void __launch_bounds__(kBlock) k_kick_drift(BatchParams b, const SysParams *reps, StatePtrs s, OutPtrs o,
+__global__ void __launch_bounds__(kChunk) k_kick_drift(BatchParams b, const SysParams *reps, StatePtrs s, OutPtrs o,
                                                           ListPtrs l, const double *thermo, const int64_t *budget,
                                                           void *rot, PartRec64 *rec64)
 {
@@ -377,12 +377,14 @@ void launch_nh_end(const Launch &L, hipStream_t stream)
 template <typename T>
 void kick_drift_t(const Launch &L, hipStream_t stream)
 {
-    const int nb = pad8(blocks_for(L.b.nchunk * kChunk));
+    // one wavefront (one chunk) per block: the chunks spread over as many
+    // CUs as there are chunks
+    const int nb = pad8(L.b.nchunk);
     if (L.b.dim == 3)
-        k_kick_drift<T, 3><<<nb, kBlock, 0, stream>>>(L.b, L.reps, L.s, L.o, L.l, L.thermo, L.budget, L.f.rot,
+        k_kick_drift<T, 3><<<nb, kChunk, 0, stream>>>(L.b, L.reps, L.s, L.o, L.l, L.thermo, L.budget, L.f.rot,
                                                        L.f.rec64);
     else
-        k_kick_drift<T, 2><<<nb, kBlock, 0, stream>>>(L.b, L.reps, L.s, L.o, L.l, L.thermo, L.budget, L.f.rot,
+        k_kick_drift<T, 2><<<nb, kChunk, 0, stream>>>(L.b, L.reps, L.s, L.o, L.l, L.thermo, L.budget, L.f.rot,
                                                        L.f.rec64);
 }
 
