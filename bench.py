@@ -2,16 +2,20 @@
 """Benchmark of the rounded-polytope DEM step on one MI355X.
 
 Workload: 4096 rounded cubes (edge 1, rounding radius 0.15, so sigma 0.3) at
-volume fraction 0.4 in a periodic cube, 16^3 simple-cubic start with
-rotations up to 10 degrees, Nose-Hoover NVT at kT = 1, dt = 5e-4; FP32 pair
-geometry with FP64 positions, integration and reductions.  One step is the
-whole path: thermostat, kick-drift, displacement-triggered cell and
-neighbour lists, pair forces (Eq. 1 with WCA), closing kick.
+volume fraction 0.4 in a periodic cube, Nose-Hoover NVT at kT = 1,
+dt = 5e-4; FP32 pair geometry with FP64 positions, integration and
+reductions.  The timed steps start from the workload's own state at step
+1000 of its NVT run from the seeded 16^3 lattice (a fluid with contacts,
+integrated by the oracle and stored with its SHA-256), after --warmup more
+steps on the GPU.  One step is the whole path: thermostat, kick-drift,
+displacement-triggered cell and neighbour lists, pair forces (Eq. 1 with
+WCA), closing kick.
 
 Prints one JSON line: particle-timesteps/s of the FP32 path (the value), the
 plain FP64 single-system path on the same inputs, the force kernel's ALU
-roofline (work counters x per-problem flop weights / mean launch time from
-HIP events on the launch stream) and the CPU oracle timed on this host.
+roofline (the method's work per launch at fixed per-problem flop weights /
+mean launch time from HIP events on the launch stream), the work counters
+at both ends of the timed window, and the CPU oracle timed on this host.
 """
 import argparse
 import json
@@ -42,6 +46,23 @@ FLOPS = {
     "ve_solve": 20,    # 2D point-segment nearest point and offset
     "wca": 56,         # WCA energy/force, accumulation of F, both torques and U
 }
+# Algorithmic work of Eq. 1 / Eq. 2 per unordered particle pair within
+# R_i + R_j + r_cut: every feature-pair problem at a fixed flop weight
+# (vertex-edge 15, edge-edge 45, vertex-triangle 45, vertex-quadrilateral 60;
+# a face of k > 4 vertices 60 + 15 (k - 4), one more edge test per vertex),
+# plus 40 per feature pair inside the cutoff (WCA and accumulation).
+METHOD_FLOPS = {"ve": 15, "ee": 45, "vtri": 45, "vquad": 60, "wca": 40}
+
+
+def method_flops_per_pair(si, sj, dim):
+    """Flops of every feature-pair problem between shapes si and sj."""
+    if dim == 2:
+        return (si.nv * sj.ne + sj.nv * si.ne) * METHOD_FLOPS["ve"]
+    w = lambda k: METHOD_FLOPS["vtri"] if k == 3 else METHOD_FLOPS["vquad"] + METHOD_FLOPS["ve"] * (k - 4)
+    vf = si.nv * sum(w(len(f)) for f in sj.faces) + sj.nv * sum(w(len(f)) for f in si.faces)
+    return vf + si.ne * sj.ne * METHOD_FLOPS["ee"]
+
+
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_k_pairs_cubes4096.txt")
 PAIR_SOURCES = [os.path.join(ROOT, "paper_1607_02427_amd", "csrc", f) for f in ("dem_force.hip", "dem_internal.h")]
 PEAK_FP32 = 157.3e12   # MI355X FP32 vector, published (needs packed FP32)
@@ -51,6 +72,13 @@ PEAK_HBM = 8.0e12
 
 def log(msg):
     print(msg, file=sys.stderr, flush=True)
+
+
+def counters_now(g):
+    """Work counters of one force evaluation on the current state."""
+    g.force_stats(reset=True)
+    g.compute_forces()
+    return g.force_stats(reset=True)
 
 
 def run_path(system, precision, steps, warmup, counting=False, tune=True):
@@ -63,6 +91,7 @@ def run_path(system, precision, steps, warmup, counting=False, tune=True):
     g.step(warmup)
     g.sync()
     shape = g.tune_pairs(20) if tune else None
+    start = counters_now(g)  # the state the timed window starts from (forces are recomputed, unchanged)
     if counting:
         g.force_stats(reset=True)
     e0 = torch.cuda.Event(enable_timing=True)
@@ -76,7 +105,7 @@ def run_path(system, precision, steps, warmup, counting=False, tune=True):
     wall = time.perf_counter() - t0
     gpu_ms = e0.elapsed_time(e1)
     en = g.energy()
-    return g, dict(wall_s=wall, gpu_ms=gpu_ms, energy=en, pair_shape=shape)
+    return g, dict(wall_s=wall, gpu_ms=gpu_ms, energy=en, pair_shape=shape, counters_start=start)
 
 
 def pair_sources_digest():
@@ -123,35 +152,36 @@ def force_roofline(g, system, reps=200):
     launch duration of the force kernel alone (HIP events on its stream).
 
     achieved: the method's algorithmic work per launch (every feature-pair
-    problem of Eq. 1 for every unordered pair within R_i + R_j + r_cut,
-    solved exactly, plus the WCA terms inside the cutoff) over the mean
-    launch time.  executed: the work the kernel actually does after it
-    proves problems empty (separation test, prefilter, cull)."""
-    g.force_stats(reset=True)
-    g.compute_forces()
-    st = g.force_stats(reset=True)
+    problem of Eq. 1 for every unordered pair within R_i + R_j + r_cut, at
+    the METHOD_FLOPS weights, plus the WCA terms inside the cutoff) over the
+    mean launch time.  executed: the work the kernel actually does after it
+    proves problems empty (separation test, prefilter, cull), at the
+    weights of its own formulas (FLOPS), in separate fields."""
+    st = counters_now(g)
     mean_ms = g.time_forces(reps)
     assert len(system.shapes) == 1
     shp = system.shapes[0]
-    if system.dim == 3:
-        problems = 2 * shp.nv * shp.nf * FLOPS["vf_solve"] + shp.ne * shp.ne * FLOPS["ee_solve"]
-    else:
-        problems = 2 * shp.nv * shp.ne * FLOPS["ve_solve"]
-    algorithmic = st["pairs"] * (FLOPS["pair"] + problems) + st["in_cutoff"] * FLOPS["wca"]
-    per_pair = FLOPS["pair"] + 2 * shp.nv * FLOPS["sep_vertex"]
+    per_pair = method_flops_per_pair(shp, shp, system.dim)
+    algorithmic = st["pairs"] * per_pair + st["in_cutoff"] * METHOD_FLOPS["wca"]
+    exec_per_pair = FLOPS["pair"] + 2 * shp.nv * FLOPS["sep_vertex"]
     planes = shp.nf if system.dim == 3 else shp.ne  # supporting planes of a convex body
     per_feature_pair = 2 * (shp.nv * (FLOPS["vertex"] + planes * FLOPS["plane_test"]) + shp.ne * FLOPS["edge"]
                             + shp.nf * FLOPS["face"])
-    executed = (st["pairs"] * per_pair + st["plane_tests"] * FLOPS["plane_test"]
+    executed = (st["pairs"] * exec_per_pair + st["plane_tests"] * FLOPS["plane_test"]
                 + (st["pairs"] - st["separated"]) * per_feature_pair + st["features"] * FLOPS["cull"]
                 + st["vf_near"] * FLOPS["vf_solve"] + st["ee_near"] * FLOPS["ee_solve"] + st["in_cutoff"] * FLOPS["wca"])
     t = mean_ms * 1e-3
     return dict(bound="alu", achieved=algorithmic / t / 1e12, peak=PEAK_FP32 / 1e12, unit="TFLOP/s",
                 frac=algorithmic / t / PEAK_FP32, traffic=measured_traffic(), kernel="k_pairs<float,3>",
-                mean_launch_ms=mean_ms, flops_per_launch=algorithmic,
-                executed_tflops=executed / t / 1e12, executed_frac=executed / t / PEAK_FP32,
-                executed_flops_per_launch=executed, peak_fp32_nonpacked=PEAK_FP32_NONPACKED / 1e12,
-                frac_nonpacked=algorithmic / t / PEAK_FP32_NONPACKED, counters=st)
+                mean_launch_ms=mean_ms, flops_per_launch=algorithmic, flops_per_pair=per_pair,
+                flops_per_pts=algorithmic / system.n,
+                peak_fp32_nonpacked=PEAK_FP32_NONPACKED / 1e12,
+                frac_nonpacked=algorithmic / t / PEAK_FP32_NONPACKED,
+                executed={"tflops": executed / t / 1e12, "frac": executed / t / PEAK_FP32,
+                          "flops_per_launch": executed,
+                          "note": "work the kernel executes after its separation test, prefilter and cull, "
+                                  "at its own formulas' weights"},
+                counters=st)
 
 
 def run_batched(replicas, steps, warmup, precision="fp32"):
@@ -200,20 +230,31 @@ def run_plain_sequential(replicas, steps, warmup):
 
 
 def cpu_baseline(system, target_s):
+    """The oracle's own NVT run of the workload on this host's cores: all of
+    them (the reported value) and one thread (the paper's comparison), each
+    over a bounded number of steps from the same state."""
     import oracle as O
     threads = len(os.sched_getaffinity(0))
-    O.set_threads(threads)
-    s = system.copy()
-    t0 = time.perf_counter()
-    O.run(s, 1, log=False)
-    one = time.perf_counter() - t0
-    steps = max(1, min(500, int(target_s / max(one, 1e-6))))
-    t0 = time.perf_counter()
-    O.run(s, steps, log=False)
-    dt = time.perf_counter() - t0
-    return dict(value=system.n * steps / dt, unit="particle-timesteps/s", cores=O.get_threads(), kind="oracle",
-                sample=f"{steps} NVT steps of the same 4096-cube workload from its seeded start "
-                       f"(FP64 brute force over every feature pair, own cell list), {dt:.1f} s")
+    out = {}
+    for label, nt in (("all", threads), ("one", 1)):
+        O.set_threads(nt)
+        s = system.copy()
+        th = list(system.thermo) if system.thermo is not None else None
+        t0 = time.perf_counter()
+        O.run(s, 1, log=False, thermo=th)
+        one = time.perf_counter() - t0
+        steps = max(1, min(500, int(0.5 * target_s / max(one, 1e-6))))
+        t0 = time.perf_counter()
+        O.run(s, steps, log=False, thermo=th)
+        dt = time.perf_counter() - t0
+        out[label] = dict(value=system.n * steps / dt, steps=steps, seconds=dt, threads=O.get_threads())
+    a, o = out["all"], out["one"]
+    return dict(value=a["value"], unit="particle-timesteps/s", cores=a["threads"], kind="oracle",
+                single_thread={"value": o["value"], "unit": "particle-timesteps/s", "cores": 1,
+                               "sample": f"{o['steps']} NVT steps, {o['seconds']:.1f} s"},
+                sample=f"{a['steps']} NVT steps of the same 4096-cube workload from its stored step-1000 state "
+                       f"(FP64 brute force over every feature pair, own cell list) on {a['threads']} threads, "
+                       f"{a['seconds']:.1f} s")
 
 
 def energy_fluctuations(dts_tau=(0.000625, 0.00125, 0.0025, 0.005, 0.01), duration_tau=10.0, samples=1000,
@@ -321,27 +362,32 @@ def main():
         print(json.dumps({"metric": "sigma(E/N) of NVE runs against the timestep (Sec. IV.A)", "unit": "eps",
                           "data": "synthetic", "study": energy_fluctuations()}), flush=True)
         return
-    system = I.cubes_3d()
+    system = I.cubes_3d_equilibrated()
     n = system.n
-    log(f"[bench] fp32 path: {n} cubes, warmup {args.warmup}, steps {args.steps}")
+    log(f"[bench] fp32 path: {n} cubes from {system.name}, warmup {args.warmup}, steps {args.steps}")
     g, r32 = run_path(system, "fp32", args.steps, args.warmup)
     ptps = n * args.steps / (r32["gpu_ms"] * 1e-3)
+    end = counters_now(g)
     log(f"[bench] fp32 {r32['gpu_ms'] / args.steps * 1e3:.2f} us/step, {ptps:.3e} PTPS, rebuilds "
-        f"{r32['energy']['n_rebuilds']}")
+        f"{r32['energy']['n_rebuilds']}, in-cutoff feature pairs {r32['counters_start']['in_cutoff']} -> "
+        f"{end['in_cutoff']}")
+    assert r32["counters_start"]["in_cutoff"] > 0 and end["in_cutoff"] > 0, "the timed window must hold contacts"
     roof = force_roofline(g, system)
     log(f"[bench] force kernel {roof['mean_launch_ms'] * 1e3:.2f} us, {roof['achieved']:.2f} TFLOP/s algorithmic, "
-        f"{roof['executed_tflops']:.2f} TFLOP/s executed")
+        f"{roof['executed']['tflops']:.2f} TFLOP/s executed")
     line = {
         "metric": METRIC, "value": ptps, "unit": "particle-timesteps/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": r32["gpu_ms"] / args.steps, "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
-        "config": {"workload": "4096 rounded cubes, edge 1, r 0.15, volume fraction 0.4, NVT kT 1, dt 5e-4, "
-                               "FP32 pair geometry / FP64 integration, single system",
+        "config": {"workload": f"4096 rounded cubes, edge 1, r 0.15, volume fraction 0.4, NVT kT 1, dt 5e-4, "
+                               f"FP32 pair geometry / FP64 integration, single system; timed from its state at "
+                               f"step 1000 of its NVT run (stored, {system.name}) plus {args.warmup} steps",
                    "n": n, "box": float(system.box[0]), "dt": system.dt, "ensemble": "nvt",
                    "precision": "fp32 geometry, fp64 state"},
         "wall_s": r32["wall_s"],
         "rebuilds": r32["energy"]["n_rebuilds"],
         "pair_shape": r32["pair_shape"],
+        "counters_window": {"start": r32["counters_start"], "end": end},
         "roofline": roof,
     }
     g.close()
@@ -352,23 +398,29 @@ def main():
         line["fp32_over_plain"] = ptps / line["plain_fp64"]["value"]
         g64.close()
     if not args.no_scale:
-        big = I.octahedra_3d()
+        big = I.octahedra_compressed()
         log(f"[bench] at scale: {big.n} octahedra, {args.scale_steps} steps")
         gs, rs = run_path(big, "fp32", args.scale_steps, 50)
+        end = counters_now(gs)
         gs.close()
         line["at_scale"] = {
-            "workload": f"{big.n} rounded octahedra (edge 1, r 0.1), BCC at volume fraction 0.55, common orientation "
-                        f"plus rotations up to 5 degrees, NVT kT 1, dt 2e-4, {args.scale_steps} steps after 50 warm-up",
+            "workload": f"{big.n} rounded octahedra (edge 1, r 0.1) at volume fraction 0.55, random orientations "
+                        f"compressed from BCC at 0.25 (a 4096-body cell, tiled 4 x 4 x 4), NVT kT 1, dt 2e-4, "
+                        f"{args.scale_steps} steps after 50 warm-up",
             "n": big.n, "value": big.n * args.scale_steps / (rs["gpu_ms"] * 1e-3), "unit": "particle-timesteps/s",
             "ms_per_step": rs["gpu_ms"] / args.scale_steps, "rebuilds": rs["energy"]["n_rebuilds"],
-            "pair_shape": rs["pair_shape"], "dtype": "f32"}
-        log(f"[bench] at scale {line['at_scale']['value']:.3e} PTPS")
+            "pair_shape": rs["pair_shape"], "dtype": "f32",
+            "counters_window": {"start": rs["counters_start"], "end": end}}
+        log(f"[bench] at scale {line['at_scale']['value']:.3e} PTPS, in-cutoff feature pairs "
+            f"{rs['counters_start']['in_cutoff']} -> {end['in_cutoff']}")
     if not args.no_batched:
         reps = I.batched_replicas(args.replicas, steps=args.batched_steps)
         log(f"[bench] batched: {len(reps)} replicas, {sum(s.n for s in reps)} particles, "
             f"{args.batched_steps} steps")
         rb = run_batched(reps, args.batched_steps, 20)
         log(f"[bench] batched fp32 {rb['value']:.3e} PTPS")
+        rb64 = run_batched(reps, args.batched_steps, 20, precision="fp64")
+        log(f"[bench] batched fp64 {rb64['value']:.3e} PTPS")
         rp = None if args.no_sequential else run_plain_sequential(reps, args.batched_steps, 20)
         line["batched"] = {
             "workload": f"{len(reps)} NVT replicas (kT 1), sizes log-uniform 512-32768, shapes uniform over rounded "
@@ -377,8 +429,10 @@ def main():
             "replicas": len(reps), "particles": rb["particles"], "steps": args.batched_steps,
             "value": rb["value"], "unit": "particle-timesteps/s", "ms_per_step": rb["ms_per_step"], "dtype": "f32",
             "pair_shape": rb["pair_shape"],
+            "batched_fp64": {"value": rb64["value"], "ms_per_step": rb64["ms_per_step"]},
             "plain_fp64_sequential": rp["value"] if rp else None,
-            "speedup_vs_plain": rb["value"] / rp["value"] if rp else None}
+            "speedup_vs_plain": rb["value"] / rp["value"] if rp else None,
+            "batching_speedup_fp64": rb64["value"] / rp["value"] if rp else None}
     if not args.no_served:
         from paper_1607_02427_amd import serve
         trace = I.served_trace(args.requests)

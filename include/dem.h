@@ -21,8 +21,11 @@
  *     dem_energy, dem_sync, dem_copy_lists and dem_force_stats, which
  *     synchronise that stream.
  *   - Errors: every call returns a dem_status.  Device-side conditions
- *     (neighbour-row overflow, non-finite state) are latched on the device
- *     and reported by the next synchronising call; dem_last_error gives text.
+ *     (neighbour-row overflow and cell overflow: DEM_E_CAPACITY; non-finite
+ *     position or velocity: DEM_E_NONFINITE) are latched on the device and
+ *     reported by every later synchronising call (dem_sync, dem_energy,
+ *     dem_batch_progress) until dem_set_state replaces the state;
+ *     dem_last_error gives text.
  *   - Ownership: state and output arrays belong to the caller, which keeps
  *     them alive and unmoved for the handle's lifetime.  Shape and parameter
  *     structs are copied at creation.  Lists, cells and reduction scratch
@@ -46,7 +49,7 @@ typedef enum {
     DEM_E_SHAPE = 2,     /* shape tables fail validation or exceed limits */
     DEM_E_OOM = 3,       /* device allocation failed */
     DEM_E_HIP = 4,       /* a HIP runtime call failed */
-    DEM_E_CAPACITY = 5,  /* a neighbour row overflowed nbr_capacity */
+    DEM_E_CAPACITY = 5,  /* a neighbour row overflowed nbr_capacity, or a cell its 64 slots */
     DEM_E_NONFINITE = 6, /* a position or velocity became non-finite */
     DEM_E_STATE = 7      /* handle in an unusable state */
 } dem_status;
@@ -277,7 +280,7 @@ size_t dem_footprint_bytes(const dem_params *params);
  * A batch handle holds many independent periodic systems ("replicas") of
  * one dimension and one force precision, of any sizes and shapes, and
  * advances all of them with one launch per kernel per step: the pair
- * kernel walks one list of tiles (16 particle pairs of one replica each)
+ * kernel walks one list of tiles (64 particle pairs of one replica each)
  * over every replica, the list build runs one workgroup per replica, and
  * the integrator and force gather cover every replica's particles.  A
  * replica's arithmetic does not depend on which other replicas share the

@@ -39,6 +39,14 @@ class PairOut(C.Structure):
                 ("n_in", C.c_int), ("n_par", C.c_int), ("n_near_par", C.c_int)]
 
 
+class Term(C.Structure):
+    _fields_ = [("family", C.c_int), ("a", C.c_int), ("b", C.c_int), ("inside", C.c_int), ("par", C.c_int),
+                ("r", C.c_double)]
+
+
+TERM_FAMILIES = {0: "EiEj", 1: "ViFj", 2: "VjFi", 3: "ViEj", 4: "VjEi"}
+
+
 class Stats(C.Structure):
     _fields_ = [("n_pairs_bound", C.c_long), ("n_feature_in", C.c_long), ("n_par", C.c_long),
                 ("n_near_par", C.c_long)]
@@ -61,6 +69,8 @@ def lib():
         L.or_segment_segment.restype = C.c_int
         L.or_point_polygon.argtypes = [_dp, _dp, C.c_int, _dp]
         L.or_pair.argtypes = [C.POINTER(_OrSys), C.c_int, C.c_int, _dp, _dp, _dp, _dp, C.POINTER(PairOut)]
+        L.or_pair_terms.argtypes = [C.POINTER(_OrSys), C.c_int, C.c_int, _dp, _dp, _dp, _dp, C.POINTER(Term), C.c_int]
+        L.or_pair_terms.restype = C.c_int
         L.or_r_list.argtypes = [C.POINTER(_OrSys), C.c_double]
         L.or_r_list.restype = C.c_double
         L.or_cell_dims.argtypes = [C.POINTER(_OrSys), C.c_double, _ip]
@@ -70,6 +80,8 @@ def lib():
         L.or_nbr_list.restype = C.c_int
         L.or_forces.argtypes = [C.POINTER(_OrSys), C.c_int, _dp, _dp, _ip, C.c_int, _dp, _dp, _dp, _dp,
                                 C.POINTER(Stats), _dp]
+        L.or_forces_subset.argtypes = [C.POINTER(_OrSys), C.c_int, _dp, _dp, _ip, C.c_int, _ip, C.c_int, _dp, _dp,
+                                       _dp, _dp, C.POINTER(Stats), _dp]
         L.or_run.argtypes = [C.POINTER(_OrSys), C.c_int, _dp, _dp, _dp, _dp, _ip, _ip, C.c_int, C.c_double,
                              C.c_int, C.c_double, C.c_double, _dp, C.c_int, _dp, _dp, _dp, _dp, _dp]
         L.or_set_threads.argtypes = [C.c_int]
@@ -183,6 +195,30 @@ def pair(osys: OracleSystem, si, sj, xi, qi, xj, qj) -> PairOut:
     return o
 
 
+def pair_terms(osys: OracleSystem, si, sj, xi, qi, xj, qj, cap=4096):
+    """The feature pairs of one particle pair inside the cutoff: a list of
+    dicts (family name, feature indices a and b, inside: 1 projection onto
+    the face, 0 nearest point on the face's edges, -1 not a vertex-face pair;
+    par: the parallel-edge rule; r)."""
+    buf = (Term * cap)()
+    n = lib().or_pair_terms(C.byref(osys.c), int(si), int(sj), _d(_vec(xi)), _d(np.asarray(qi, np.float64).copy()),
+                            _d(_vec(xj)), _d(np.asarray(qj, np.float64).copy()), buf, cap)
+    return [dict(family=TERM_FAMILIES[t.family], a=t.a, b=t.b, inside=t.inside, par=t.par, r=t.r)
+            for t in buf[: min(n, cap)]]
+
+
+def dimer_terms(sysobj, k):
+    """pair_terms for particles 2k and 2k + 1 of a system built in pairs,
+    with the second at its image nearest to the first."""
+    osys = OracleSystem.of(sysobj)
+    i, j = 2 * k, 2 * k + 1
+    d = np.asarray(sysobj.x[j], float) - np.asarray(sysobj.x[i], float)
+    for a in range(sysobj.dim):
+        d[a] -= sysobj.box[a] * np.rint(d[a] / sysobj.box[a])
+    return pair_terms(osys, sysobj.shape_id[i], sysobj.shape_id[j], sysobj.x[i], sysobj.q[i], sysobj.x[i] + d,
+                      sysobj.q[j])
+
+
 # ---------------------------------------------------------------- system-level
 def cell_list(sysobj, r_list):
     osys = OracleSystem.of(sysobj)
@@ -225,6 +261,27 @@ def forces(sysobj, mode=1, threads: Optional[int] = None):
     sc = np.zeros((n, 3))
     lib().or_forces(C.byref(osys.c), int(n), _d(x), _d(q), _i(sid), int(mode), _d(F), _d(T), _d(U), _d(W),
                     C.byref(st), _d(sc))
+    return dict(F=F, T=T, U=U, W=W, scale=sc, stats=dict(pairs=st.n_pairs_bound, feature_in=st.n_feature_in,
+                                                           par=st.n_par, near_par=st.n_near_par))
+
+
+def forces_subset(sysobj, pick, mode=1, threads: Optional[int] = None):
+    """forces() for the particles pick (each against all others): row k of
+    every output belongs to particle pick[k]; stats count their pairs only."""
+    if threads:
+        lib().or_set_threads(int(threads))
+    osys = OracleSystem.of(sysobj)
+    n = sysobj.n
+    pick = np.ascontiguousarray(pick, dtype=np.int32)
+    m = pick.size
+    x = np.ascontiguousarray(sysobj.x, dtype=np.float64)
+    q = np.ascontiguousarray(sysobj.q, dtype=np.float64)
+    sid = np.ascontiguousarray(sysobj.shape_id, dtype=np.int32)
+    F, T, U, W = np.zeros((m, 3)), np.zeros((m, 3)), np.zeros(m), np.zeros((m, 9))
+    st = Stats()
+    sc = np.zeros((m, 3))
+    lib().or_forces_subset(C.byref(osys.c), int(n), _d(x), _d(q), _i(sid), int(mode), _i(pick), int(m), _d(F), _d(T),
+                           _d(U), _d(W), C.byref(st), _d(sc))
     return dict(F=F, T=T, U=U, W=W, scale=sc, stats=dict(pairs=st.n_pairs_bound, feature_in=st.n_feature_in,
                                                            par=st.n_par, near_par=st.n_near_par))
 

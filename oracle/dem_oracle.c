@@ -225,7 +225,14 @@ static int near_parallel(const double *a0, const double *a1, const double *b0, c
  * (k points, xyz) may be concave.  Project onto the plane; if the projection
  * is inside (crossing-number test in face coordinates) it is the nearest
  * point, otherwise the nearest point lies on the polygon's own edges. */
-void or_point_polygon(const double *p, const double *loop, int k, double *q)
+static int point_polygon(const double *p, const double *loop, int k, double *q);
+
+void or_point_polygon(const double *p, const double *loop, int k, double *q) { (void)point_polygon(p, loop, k, q); }
+
+/* The nearest point as above; returns 1 when the projection lies inside
+ * the polygon (the nearest point is the projection), 0 when it lies on the
+ * polygon's edges. */
+static int point_polygon(const double *p, const double *loop, int k, double *q)
 {
     double n[3] = {0, 0, 0};
     for (int a = 0; a < k; ++a) { /* Newell normal */
@@ -266,7 +273,7 @@ void or_point_polygon(const double *p, const double *loop, int k, double *q)
             if (px < xc) inside = !inside;
         }
     }
-    if (inside) { memcpy(q, pr, 3 * sizeof(double)); return; }
+    if (inside) { memcpy(q, pr, 3 * sizeof(double)); return 1; }
     double best = INFINITY;
     for (int a = 0; a < k; ++a) {
         double c[3], d[3];
@@ -275,16 +282,45 @@ void or_point_polygon(const double *p, const double *loop, int k, double *q)
         double r2 = v_dot(d, d);
         if (r2 < best) { best = r2; memcpy(q, c, sizeof c); }
     }
+    return 0;
 }
 
 /* ------------------------------------------------------------ pair energy */
-static void accumulate(or_pair_out *o, const double *P, const double *Q, const double *xi, const double *xj,
-                       double sigma, double eps, int par, int near_par)
+/* One feature pair inside the cutoff, for diagnostics (or_pair_terms):
+ * family 0 = E_i-E_j (a, b edges of i and j), 1 = V_i-F_j (a vertex of i, b
+ * face of j), 2 = V_j-F_i (a vertex of j, b face of i), 3 = 2D V_i-E_j,
+ * 4 = 2D V_j-E_i; inside = 1 when a vertex-face nearest point is the
+ * projection onto the face, 0 when it lies on the face's edges, -1 for the
+ * other families; par = the parallel-edge rule applied; r = |P - Q|. */
+typedef struct {
+    int family, a, b, inside, par;
+    double r;
+} or_term;
+
+typedef struct {
+    or_term *buf;
+    int cap, n;
+} or_terms;
+
+static void note(or_terms *t, int family, int a, int b, int inside, int par, double r)
+{
+    if (!t) return;
+    if (t->n < t->cap) {
+        or_term *e = t->buf + t->n;
+        e->family = family; e->a = a; e->b = b; e->inside = inside; e->par = par; e->r = r;
+    }
+    t->n += 1;
+}
+
+/* Adds the term of nearest points P (on i) and Q (on j) when |P - Q| is
+ * inside the cutoff; returns |P - Q| then, else -1. */
+static double accumulate(or_pair_out *o, const double *P, const double *Q, const double *xi, const double *xj,
+                         double sigma, double eps, int par, int near_par)
 {
     double rho[3];
     v_sub(P, Q, rho);
     double U, fr;
-    if (!or_wca(v_dot(rho, rho), sigma, eps, &U, &fr)) return;
+    if (!or_wca(v_dot(rho, rho), sigma, eps, &U, &fr)) return -1.0;
     double f[3] = {fr * rho[0], fr * rho[1], fr * rho[2]};
     double ai[3], aj[3], ti[3], tj[3], rij[3];
     v_sub(P, xi, ai);
@@ -305,14 +341,15 @@ static void accumulate(or_pair_out *o, const double *P, const double *Q, const d
     o->n_in += 1;
     o->n_par += par;
     o->n_near_par += near_par;
+    return sqrt(v_dot(rho, rho));
 }
 
 /* Full evaluation of U_ij and its derivatives for particles of shapes si, sj
  * at positions xi, xj (xj already the image nearest to xi) and quaternions.
  * 3D: Eq. 1 (every E_i-E_j pair, every V_i-F_j pair, every V_j-F_i pair);
  * 2D: Eq. 2 (every V_i-E_j pair and every V_j-E_i pair). */
-void or_pair(const or_sys *S, int si, int sj, const double *xi, const double *qi, const double *xj,
-             const double *qj, or_pair_out *o)
+static void pair_eval(const or_sys *S, int si, int sj, const double *xi, const double *qi, const double *xj,
+                      const double *qj, or_pair_out *o, or_terms *tl)
 {
     memset(o, 0, sizeof *o);
     double Ri[9], Rj[9];
@@ -339,13 +376,15 @@ void or_pair(const or_sys *S, int si, int sj, const double *xi, const double *qi
             for (int e = 0; e < nej; ++e) {
                 double q[3];
                 or_point_segment(Vi[a], Vj[Ej[2 * e]], Vj[Ej[2 * e + 1]], q);
-                accumulate(o, Vi[a], q, xi, xj, sigma, eps, 0, 0);
+                double r = accumulate(o, Vi[a], q, xi, xj, sigma, eps, 0, 0);
+                if (r >= 0.0) note(tl, 3, a, e, -1, 0, r);
             }
         for (int b = 0; b < nvj; ++b)
             for (int e = 0; e < nei; ++e) {
                 double p[3];
                 or_point_segment(Vj[b], Vi[Ei[2 * e]], Vi[Ei[2 * e + 1]], p);
-                accumulate(o, p, Vj[b], xi, xj, sigma, eps, 0, 0);
+                double r = accumulate(o, p, Vj[b], xi, xj, sigma, eps, 0, 0);
+                if (r >= 0.0) note(tl, 4, b, e, -1, 0, r);
             }
         return;
     }
@@ -355,7 +394,8 @@ void or_pair(const or_sys *S, int si, int sj, const double *xi, const double *qi
             const double *a0 = Vi[Ei[2 * e]], *a1 = Vi[Ei[2 * e + 1]];
             const double *b0 = Vj[Ej[2 * g]], *b1 = Vj[Ej[2 * g + 1]];
             int par = or_segment_segment(a0, a1, b0, b1, S->par_s2, P, Q);
-            accumulate(o, P, Q, xi, xj, sigma, eps, par, near_parallel(a0, a1, b0, b1, S->par_s2));
+            double r = accumulate(o, P, Q, xi, xj, sigma, eps, par, near_parallel(a0, a1, b0, b1, S->par_s2));
+            if (r >= 0.0) note(tl, 0, e, g, -1, par, r);
         }
     double loop[OR_MAXV * 3];
     for (int a = 0; a < nvi; ++a)
@@ -363,17 +403,38 @@ void or_pair(const or_sys *S, int si, int sj, const double *xi, const double *qi
             int gf = S->f_off[sj] + f, k = S->fl_off[gf + 1] - S->fl_off[gf];
             for (int c = 0; c < k; ++c) memcpy(loop + 3 * c, Vj[S->floops[S->fl_off[gf] + c]], 3 * sizeof(double));
             double q[3];
-            or_point_polygon(Vi[a], loop, k, q);
-            accumulate(o, Vi[a], q, xi, xj, sigma, eps, 0, 0);
+            int in = point_polygon(Vi[a], loop, k, q);
+            double r = accumulate(o, Vi[a], q, xi, xj, sigma, eps, 0, 0);
+            if (r >= 0.0) note(tl, 1, a, f, in, 0, r);
         }
     for (int b = 0; b < nvj; ++b)
         for (int f = 0; f < S->nf[si]; ++f) {
             int gf = S->f_off[si] + f, k = S->fl_off[gf + 1] - S->fl_off[gf];
             for (int c = 0; c < k; ++c) memcpy(loop + 3 * c, Vi[S->floops[S->fl_off[gf] + c]], 3 * sizeof(double));
             double p[3];
-            or_point_polygon(Vj[b], loop, k, p);
-            accumulate(o, p, Vj[b], xi, xj, sigma, eps, 0, 0);
+            int in = point_polygon(Vj[b], loop, k, p);
+            double r = accumulate(o, p, Vj[b], xi, xj, sigma, eps, 0, 0);
+            if (r >= 0.0) note(tl, 2, b, f, in, 0, r);
         }
+}
+
+void or_pair(const or_sys *S, int si, int sj, const double *xi, const double *qi, const double *xj,
+             const double *qj, or_pair_out *o)
+{
+    pair_eval(S, si, sj, xi, qi, xj, qj, o, NULL);
+}
+
+/* The same evaluation, listing the feature pairs inside the cutoff (at most
+ * cap of them into terms); returns how many there are.  A diagnostic for
+ * the tests: which families and which branch of the point-polygon rule a
+ * case reaches. */
+int or_pair_terms(const or_sys *S, int si, int sj, const double *xi, const double *qi, const double *xj,
+                  const double *qj, or_term *terms, int cap)
+{
+    or_pair_out o;
+    or_terms t = {terms, cap, 0};
+    pair_eval(S, si, sj, xi, qi, xj, qj, &o, &t);
+    return t.n;
 }
 
 /* ------------------------------------------------------------ geometry */
@@ -528,8 +589,28 @@ typedef struct {
  * interactions over every other particle (mode 0) or over its cell-list
  * neighbours (mode 1); particle pairs farther apart than R_i + R_j + r_cut
  * are skipped because no feature pair can then reach the cutoff. */
+static void forces_of(const or_sys *S, int n, const double *x, const double *q, const int *sid, int mode,
+                      const int *pick, int m_pick, double *F, double *T, double *U, double *W, or_stats *st,
+                      double *scale);
+
 void or_forces(const or_sys *S, int n, const double *x, const double *q, const int *sid, int mode,
                double *F, double *T, double *U, double *W, or_stats *st, double *scale)
+{
+    forces_of(S, n, x, q, sid, mode, NULL, n, F, T, U, W, st, scale);
+}
+
+/* The same sums for the m particles pick[0..m) only (each against every
+ * other particle of the system); output row k belongs to particle pick[k]. */
+void or_forces_subset(const or_sys *S, int n, const double *x, const double *q, const int *sid, int mode,
+                      const int *pick, int m, double *F, double *T, double *U, double *W, or_stats *st,
+                      double *scale)
+{
+    forces_of(S, n, x, q, sid, mode, pick, m, F, T, U, W, st, scale);
+}
+
+static void forces_of(const or_sys *S, int n, const double *x, const double *q, const int *sid, int mode,
+                      const int *pick, int m_pick, double *F, double *T, double *U, double *W, or_stats *st,
+                      double *scale)
 {
     double R[64];
     for (int s = 0; s < S->n_shapes && s < 64; ++s) R[s] = shape_R(S, s);
@@ -551,7 +632,8 @@ void or_forces(const or_sys *S, int n, const double *x, const double *q, const i
     }
     long c_pairs = 0, c_in = 0, c_par = 0, c_near = 0;
 #pragma omp parallel for schedule(dynamic, 16) reduction(+ : c_pairs, c_in, c_par, c_near)
-    for (int i = 0; i < n; ++i) {
+    for (int row = 0; row < m_pick; ++row) {
+        const int i = pick ? pick[row] : row;
         double Fi[3] = {0, 0, 0}, Ti[3] = {0, 0, 0}, Ui = 0.0, Wi[9] = {0}, sF = 0.0, sT = 0.0, sW = 0.0;
         int m = (mode == 1) ? n_nbr[i] : n;
         for (int k = 0; k < m; ++k) {
@@ -577,13 +659,13 @@ void or_forces(const or_sys *S, int n, const double *x, const double *q, const i
             sW += 0.5 * o.Wabs;
         }
         if (scale) {
-            scale[3 * i] = sF;
-            scale[3 * i + 1] = sT;
-            scale[3 * i + 2] = sW;
+            scale[3 * row] = sF;
+            scale[3 * row + 1] = sT;
+            scale[3 * row + 2] = sW;
         }
-        for (int a = 0; a < 3; ++a) { F[3 * i + a] = Fi[a]; T[3 * i + a] = Ti[a]; }
-        U[i] = Ui;
-        for (int a = 0; a < 9; ++a) W[9 * i + a] = Wi[a];
+        for (int a = 0; a < 3; ++a) { F[3 * row + a] = Fi[a]; T[3 * row + a] = Ti[a]; }
+        U[row] = Ui;
+        for (int a = 0; a < 9; ++a) W[9 * row + a] = Wi[a];
     }
     if (st) { st->n_pairs_bound = c_pairs; st->n_feature_in = c_in; st->n_par = c_par; st->n_near_par = c_near; }
     free(nbr);

@@ -14,8 +14,9 @@
 //   xi += h/2 (2K - g kT)/Q,
 // with g = d N + d_rot N - d and Q = g kT tau_T^2.  The closing half step
 // of a step and the opening half step of the next are computed together by
-// the last workgroup of each replica in the force gather (dem_force.hip);
-// their velocity factors are applied by the next kick-drift, and at the end
+// k_replica_tail, one workgroup per replica after the force gather
+// (dem_force.hip); their velocity factors are applied by the next
+// kick-drift, and at the end
 // of a call k_scale applies the closing factor alone, so a captured step
 // needs no extra pass over the particles.
 #include "dem_internal.h"

@@ -267,9 +267,11 @@ __device__ inline void cell_insert(const SysParams &p, const ListPtrs &l, int i,
     const double xs[3] = {x, y, z};
     int c3[3] = {0, 0, 0};
     for (int a = 0; a < p.dim; ++a) {
-        int c = (int)floor(xs[a] / p.cellw[a]);
-        c = c < 0 ? 0 : c;
-        c3[a] = c > p.nc[a] - 1 ? p.nc[a] - 1 : c;
+        // clamped before the conversion, so a non-finite position (reported
+        // by the kick-drift) still lands in a valid cell: fmax and fmin
+        // return the other operand for a NaN
+        const double c = fmin(fmax(floor(xs[a] / p.cellw[a]), 0.0), (double)(p.nc[a] - 1));
+        c3[a] = (int)c;
     }
     const int c = c3[0] + p.nc[0] * (c3[1] + p.nc[1] * c3[2]);
     l.pcell[i] = c;

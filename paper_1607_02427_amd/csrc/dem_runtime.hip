@@ -641,6 +641,9 @@ dem_status latched(dem_system *h)
         if (!h->reps[r].live) continue;
         const int32_t *f = flags.data() + FLAG_COUNT * r;
         if (f[FLAG_NONFINITE]) return fail(h, DEM_E_NONFINITE, "replica %zu: non-finite position or velocity", r);
+        if (f[FLAG_CELLOVF])
+            return fail(h, DEM_E_CAPACITY, "replica %zu: a cell held more than %d particles in a list build", r,
+                        kCellCap);
         if (f[FLAG_MAXROW] > h->bp.cap)
             return fail(h, DEM_E_CAPACITY, "replica %zu: neighbour row of %d exceeds capacity %d", r, f[FLAG_MAXROW],
                         h->bp.cap);
@@ -935,6 +938,8 @@ dem_status replica_energy(dem_system *h, int r, dem_energy_out *o)
     o->step = steps;
     o->n_rebuilds = flags[FLAG_NBUILDS];
     if (flags[FLAG_NONFINITE]) return fail(h, DEM_E_NONFINITE, "non-finite position or velocity");
+    if (flags[FLAG_CELLOVF])
+        return fail(h, DEM_E_CAPACITY, "a cell held more than %d particles in a list build", kCellCap);
     if (flags[FLAG_MAXROW] > h->bp.cap)
         return fail(h, DEM_E_CAPACITY, "neighbour row of %d exceeds capacity %d", flags[FLAG_MAXROW], h->bp.cap);
     return DEM_OK;

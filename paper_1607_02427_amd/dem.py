@@ -314,6 +314,9 @@ class DemSystem:
         if st != 0:
             raise DemError(st, "dem_create_system", lib().dem_last_error(None).decode())
         self.h = h
+        thermo = getattr(system, "thermo", None)  # a stored state's Nose-Hoover (xi, eta)
+        if thermo is not None:
+            self.set_thermostat(*thermo)
 
     # ---------------------------------------------------------------- calls
     def _check(self, st, where):

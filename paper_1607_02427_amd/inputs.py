@@ -18,12 +18,18 @@ Every random draw uses numpy's PCG64 with an explicit seed.
 from __future__ import annotations
 
 import dataclasses
+import hashlib
+import json
 import math
+import os
 from typing import List, Optional, Sequence
 
 import numpy as np
 
 TWO_PI = 2.0 * math.pi
+# stored starting states (written by tests/golden/make_states.py), with the
+# SHA-256 of each file in states.json
+GOLDEN = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "tests", "golden")
 
 
 # --------------------------------------------------------------------------
@@ -53,6 +59,9 @@ class Shape:
     inertia: np.ndarray
     name: str = ""
     volume: float = 0.0  # rounded area (2D) or volume (3D)
+    # (com, U) of the construction frame: a point p given in the coordinates
+    # the shape was built in sits at (p - com) @ U in the body frame
+    frame: Optional[tuple] = None
 
     @property
     def nv(self) -> int:
@@ -334,7 +343,8 @@ def _finish_3d(name, verts, faces, r, V, M1, S, mass=1.0):
     verts_b = (verts - com) @ U
     edges = _edges_from_faces(faces)
     return Shape(dim=3, vertices=np.ascontiguousarray(verts_b), edges=edges, faces=faces, r=float(r),
-                 mass=float(mass), inertia=np.asarray(w, dtype=np.float64), name=name, volume=float(V))
+                 mass=float(mass), inertia=np.asarray(w, dtype=np.float64), name=name, volume=float(V),
+                 frame=(com, U))
 
 
 def polygon(verts2: np.ndarray, r: float, name: str = "polygon", mass: float = 1.0) -> Shape:
@@ -497,6 +507,7 @@ class System:
     tau_T: float = 0.5
     parallel_sin2: float = 1e-6
     name: str = ""
+    thermo: Optional[tuple] = None  # Nose-Hoover (xi, eta) of a stored state; None: (0, 0)
 
     @property
     def n(self) -> int:
@@ -675,6 +686,35 @@ def cubes_3d_contact(seed: int = 12, n_side: int = 8) -> System:
     return s
 
 
+def stored_state(name: str, template: System) -> System:
+    """A stored state (positions, orientations, momenta, image counters and
+    the thermostat variables `thermo` = (xi, eta)) on the template's box,
+    shapes and parameters; the file's SHA-256 must match states.json."""
+    entry = json.load(open(os.path.join(GOLDEN, "states.json")))[name]
+    path = os.path.join(GOLDEN, entry["file"])
+    with open(path, "rb") as f:
+        digest = hashlib.sha256(f.read()).hexdigest()
+    if digest != entry["sha256"]:
+        raise RuntimeError(f"{path}: SHA-256 {digest} differs from states.json")
+    z = np.load(path)
+    s = template.copy()
+    s.x, s.q, s.v, s.L = (np.ascontiguousarray(z[k], dtype=np.float64) for k in ("x", "q", "v", "L"))
+    s.image = np.ascontiguousarray(z["image"], dtype=np.int32)
+    if "box" in z.files:
+        s.box = np.ascontiguousarray(z["box"], dtype=np.float64)
+    s.thermo = tuple(float(t) for t in z["thermo"])
+    s.step = int(z["step"])
+    s.name = name
+    return s
+
+
+def cubes_3d_equilibrated() -> System:
+    """The 4096-cube workload (cubes_3d) after 1000 steps of its own NVT run
+    (0.5 tau), integrated by the oracle from the seeded lattice start: a
+    fluid with contacts, for full-size parity and for timing."""
+    return stored_state("cubes4096_nvt_step1000", cubes_3d())
+
+
 def energy_fluid(dim: int, n_side: int = None, seed: int = 21) -> System:
     """The fluids of the energy-conservation study (Sec. IV.A): 2D rounded
     squares of edge 4.24 sigma (edge 1, r = 1 / 8.48) on a 32 x 32 lattice at
@@ -727,14 +767,19 @@ def gas_2d(n: int = 256, excl_fraction: float = 0.45, seed: int = 14, shape_name
 
 def dimer_gas(shape_name: str = "cube", n_pairs: int = 128, seed: int = 15, gap=(0.85, 1.1),
               excl_fraction: float = 0.25, dim: int = 3, **kw) -> System:
-    """Contact-rich gas at arbitrary angles: particles come in touching pairs.
+    """Gas of close pairs at arbitrary angles.
 
     Each pair has uniform random orientations and a random direction u; the
     second centre sits at distance h_i(u) + h_j(-u) + g along u, where h is
     the support function of the inner shape (max over vertices of v.u), so
-    the inner shapes' projections on u are exactly g apart (no overlap) and
-    the facing features are near g.  g ~ U[gap] * sigma.  Pairs are placed
-    at random with exclusion spheres around each pair."""
+    the inner shapes' projections on u are exactly g apart (no overlap).
+    g ~ U[gap] * sigma.  The inner bodies' distance is g or more (more when
+    u is not a direction in which their nearest features face each other),
+    so only part of the pairs are in contact: by the oracle's count 24 of
+    128 cube pairs, 20 of 128 octahedron pairs and 8 of 128 tetrahedron
+    pairs at the default seed.  contact_dimers places pairs that are all in
+    contact.  Pairs are placed at random with exclusion spheres around each
+    pair."""
     shp = SHAPES[shape_name](**kw)
     rng = np.random.Generator(np.random.PCG64(seed))
     sigma = 2.0 * shp.r
@@ -791,6 +836,184 @@ def dimer_gas(shape_name: str = "cube", n_pairs: int = 128, seed: int = 15, gap=
     v, Lm = thermal_momenta(rng, [shp], shape_id, dim, 1.0)
     s = System(dim=dim, box=box, shapes=[shp], shape_id=shape_id, x=x, q=q, v=v, L=Lm,
                image=np.zeros((n, 3), dtype=np.int32), name=f"dimers_{shape_name}_{n}")
+    s.dt = 5e-4 if dim == 3 else 1e-4
+    return s
+
+
+def _unit(v: np.ndarray) -> np.ndarray:
+    return v / np.linalg.norm(v)
+
+
+def _supporting_features(shp: Shape):
+    """The features of an inner shape that can face another body across a
+    separating plane, each with a direction u in which it is the shape's
+    whole support set (every other vertex lies strictly lower along u):
+    faces (2D: edges) whose plane has the whole body on one side, with their
+    outward normal; edges (3D) and vertices where only such faces meet, with
+    the normalised sum of those faces' normals.  Returns a list of
+    (kind, vertex indices, u) with kind 'face', 'edge' or 'vertex'."""
+    V = shp.vertices
+    if shp.dim == 3:
+        loops = [list(f) for f in shp.faces]
+        normals = [_newell(V, f) for f in loops]
+    else:
+        loops = [[k, (k + 1) % shp.nv] for k in range(shp.nv)]
+        normals = [_unit(np.array([V[b, 1] - V[a, 1], V[a, 0] - V[b, 0], 0.0])) for a, b in loops]
+
+    def strict(idx, u):
+        top = min(float(V[k] @ u) for k in idx)
+        rest = [float(V[k] @ u) for k in range(shp.nv) if k not in idx]
+        return all(abs(float(V[k] @ u) - top) < 1e-9 for k in idx) and (not rest or max(rest) < top - 1e-6)
+
+    out = []
+    sup = []
+    for f, nf in zip(loops, normals):
+        if strict(f, nf):
+            out.append(("face", list(f), nf))
+            sup.append((set(f), nf))
+    if shp.dim == 3:
+        for a, b in shp.edges:
+            adj = [nf for f, nf in zip(loops, normals) if a in f and b in f]
+            if len(adj) == 2 and all(any(nf is n2 for _, n2 in sup) for nf in adj):
+                u = _unit(adj[0] + adj[1])
+                if strict([int(a), int(b)], u):
+                    out.append(("edge", [int(a), int(b)], u))
+    for k in range(shp.nv):
+        adj = [nf for f, nf in zip(loops, normals) if k in f]
+        if adj and all(any(nf is n2 for _, n2 in sup) for nf in adj):
+            u = _unit(np.sum(adj, axis=0))
+            if strict([k], u):
+                out.append(("vertex", [k], u))
+    return out
+
+
+def _align(dim: int, n_body: np.ndarray, target: np.ndarray, spin: float) -> np.ndarray:
+    """A quaternion that turns the body-frame unit vector n_body onto the
+    space-frame unit vector target, then spins by `spin` about target (3D);
+    in 2D the rotation about z that does the same."""
+    if dim == 2:
+        th = math.atan2(target[1], target[0]) - math.atan2(n_body[1], n_body[0])
+        return planar_quaternions(np.array([th]))[0]
+    c = float(np.clip(n_body @ target, -1.0, 1.0))
+    ax = np.cross(n_body, target)
+    if np.linalg.norm(ax) < 1e-12:  # parallel or antiparallel
+        ax = np.cross(n_body, [1.0, 0.0, 0.0] if abs(n_body[0]) < 0.9 else [0.0, 1.0, 0.0])
+    q0 = quat_from_axis_angle(_unit(ax), math.acos(c))
+    qs = quat_from_axis_angle(target, spin)
+    q = _quat_mul(qs, q0)
+    return q / np.linalg.norm(q)
+
+
+def contact_dimers(shape_a: Shape, shape_b: Optional[Shape] = None, n_pairs: int = 128, seed: int = 16,
+                   gap=(0.85, 1.1), excl_fraction: float = 0.25, notch: bool = False, name: str = "") -> System:
+    """Pairs that are all in contact, over every kind of facing features.
+
+    For each pair, body A takes a uniform random orientation and one of its
+    supporting features (a face, an edge or a vertex, see
+    _supporting_features) with its direction u; the anchor point P is a
+    random point of that feature (a random convex combination of a face's
+    vertices, a point of an edge, the vertex).  A's inner body lies in the
+    half space (x - P).u <= 0.  Body B then faces A with a vertex (uniform
+    random orientation, its lowest vertex along u), an edge or a face (a
+    supporting edge or face of B turned to face -u, random spin about u),
+    whose point (the vertex, the edge's midpoint, the face's vertex
+    centroid) is put at P + g u, g ~ U[gap] sigma_AB.  B's inner body lies in
+    (x - P).u >= g, so the inner bodies are exactly g apart, inside the WCA
+    cutoff 2^(1/6) sigma for gap[1] < 2^(1/6).
+
+    notch=True: A is the concave L-prism and its anchor is a point of one of
+    its two concave caps (the L-hexagon (0,0),(2,0),(2,1),(1,1),(1,2),(0,2)),
+    drawn uniformly from the square [0.55, 1.45]^2 around the reflex corner
+    (1,1): three quarters of these points lie on the cap, a quarter over
+    the notch, where B's point hangs g above the cap plane but off the
+    face, so its nearest point on A lies on the notch's edges (a contact
+    when that distance is below the cutoff).  Pairs are placed at random
+    with exclusion spheres around each pair; shape ids are 0 for A and 1 for
+    B (when shape_b is given)."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    sb = shape_a if shape_b is None else shape_b
+    dim = shape_a.dim
+    shapes = [shape_a] if shape_b is None else [shape_a, shape_b]
+    sigma = shape_a.r + sb.r
+    feats_a = _supporting_features(shape_a)
+    feats_b = [f for f in _supporting_features(sb) if f[0] != "vertex"]
+    Ra, Rb = shape_a.circumradius, sb.circumradius
+    reach = Ra + Rb + gap[1] * sigma
+    excl_r = 0.5 * (Ra + Rb + reach) + 1.2 * sigma
+    if dim == 3:
+        Lb = (n_pairs * (4.0 / 3.0) * math.pi * excl_r ** 3 / excl_fraction) ** (1.0 / 3.0)
+    else:
+        Lb = (n_pairs * math.pi * excl_r ** 2 / excl_fraction) ** 0.5
+    box = np.array([Lb, Lb, Lb if dim == 3 else 1.0])
+    n = 2 * n_pairs
+    x = np.zeros((n, 3))
+    q = np.zeros((n, 4))
+    centres = []
+    k = 0
+    tries = 0
+    while k < n_pairs:
+        tries += 1
+        if tries > 500 * n_pairs:
+            raise RuntimeError("contact_dimers: cannot place pairs")
+        c = rng.uniform(0.0, Lb, dim)
+        ok = True
+        for cc in centres:
+            d = c - cc
+            d -= Lb * np.rint(d / Lb)
+            if d @ d < (2 * excl_r) ** 2:
+                ok = False
+                break
+        if not ok:
+            continue
+        qa = planar_quaternions(rng.uniform(0.0, TWO_PI, 1))[0] if dim == 2 else uniform_quaternions(rng, 1)[0]
+        Ma = _qmat(qa)
+        if notch:
+            com, U = shape_a.frame
+            top = rng.random() < 0.5
+            xy = rng.uniform(0.55, 1.45, 2)
+            p_body = (np.array([xy[0], xy[1], 1.0 if top else 0.0]) - com) @ U
+            n_body = np.array([0.0, 0.0, 1.0 if top else -1.0]) @ U
+        else:
+            kind, idx, n_body = feats_a[int(rng.integers(len(feats_a)))]
+            if kind == "face":
+                wts = rng.dirichlet(np.ones(len(idx)))
+                p_body = wts @ shape_a.vertices[idx]
+            elif kind == "edge":
+                t = rng.uniform(0.1, 0.9)
+                p_body = (1 - t) * shape_a.vertices[idx[0]] + t * shape_a.vertices[idx[1]]
+            else:
+                p_body = shape_a.vertices[idx[0]].copy()
+        u = Ma @ n_body
+        mode = int(rng.integers(3)) if feats_b else 0
+        if mode == 0:  # B faces A with a vertex
+            qb = planar_quaternions(rng.uniform(0.0, TWO_PI, 1))[0] if dim == 2 else uniform_quaternions(rng, 1)[0]
+            Mb = _qmat(qb)
+            pb = sb.vertices[int(np.argmin((sb.vertices @ Mb.T) @ u))]
+        else:  # with a supporting edge or face of its own
+            kinds = ("edge", "face") if dim == 3 else ("face",)
+            cand = [f for f in feats_b if f[0] == kinds[(mode - 1) % len(kinds)]] or feats_b
+            kb, idb, nb = cand[int(rng.integers(len(cand)))]
+            qb = _align(dim, nb, -u, rng.uniform(0.0, TWO_PI))
+            Mb = _qmat(qb)
+            pb = sb.vertices[idb].mean(axis=0)
+        g = rng.uniform(gap[0], gap[1]) * sigma
+        off = Ma @ p_body + g * u - Mb @ pb  # x_B - x_A
+        p0 = np.zeros(3)
+        p0[:dim] = c
+        p0[:dim] -= 0.5 * off[:dim]
+        x[2 * k] = p0
+        x[2 * k + 1] = p0
+        x[2 * k + 1, :dim] += off[:dim]
+        q[2 * k], q[2 * k + 1] = qa, qb
+        centres.append(c)
+        k += 1
+    x[:, :dim] %= Lb
+    shape_id = np.zeros(n, dtype=np.int32)
+    if shape_b is not None:
+        shape_id[1::2] = 1
+    v, Lm = thermal_momenta(rng, shapes, shape_id, dim, 1.0)
+    s = System(dim=dim, box=box, shapes=shapes, shape_id=shape_id, x=x, q=q, v=v, L=Lm,
+               image=np.zeros((n, 3), dtype=np.int32), name=name or f"contact_{shape_a.name}_{n}")
     s.dt = 5e-4 if dim == 3 else 1e-4
     return s
 
@@ -879,6 +1102,62 @@ def octahedra_3d(seed: int = 3, n: int = 262144, fraction: float = 0.55, n_cells
     return s
 
 
+def octahedra_bcc_dilute(seed: int = 3, n: int = 4096, n_cells: int = 13, fraction: float = 0.25,
+                         kT: float = 1.0) -> System:
+    """n rounded octahedra (edge 1, r 0.1) with uniform random orientations
+    on a BCC lattice of n_cells^3 cubic cells (2 n_cells^3 sites, n of them
+    drawn at random), box L = (n V / fraction)^(1/3).  At fraction 0.25 the
+    BCC nearest-neighbour distance exceeds twice the rounded circumradius,
+    so no two bodies touch whatever their orientations.  NVT, kT = 1,
+    dt = 2e-4: the start the compressed at-scale state is made from."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    shp = octahedron(1.0, 0.1)
+    L = (n * shp.volume / fraction) ** (1.0 / 3.0)
+    cell = L / n_cells
+    assert 0.5 * math.sqrt(3.0) * cell > 2.0 * (shp.circumradius + shp.r)
+    g = np.arange(n_cells)
+    corner = np.stack(np.meshgrid(g, g, g, indexing="ij"), axis=-1).reshape(-1, 3).astype(np.float64)
+    sites = np.concatenate([corner + 0.25, corner + 0.75]) * cell
+    x = sites[np.sort(rng.choice(sites.shape[0], size=n, replace=False))]
+    q = uniform_quaternions(rng, n)
+    shape_id = np.zeros(n, dtype=np.int32)
+    v, Lm = thermal_momenta(rng, [shp], shape_id, 3, kT)
+    return System(dim=3, box=np.array([L, L, L]), shapes=[shp], shape_id=shape_id, x=x, q=q, v=v, L=Lm,
+                  image=np.zeros((n, 3), dtype=np.int32), kT=kT, dt=2e-4, ensemble="nvt",
+                  name=f"octahedra_bcc_dilute_{n}")
+
+
+def tile(s: System, k: int) -> System:
+    """The periodic system s repeated k times along every axis (a valid
+    periodic state of the k^d times larger box); momenta and image counters
+    are copied with each particle."""
+    dim = s.dim
+    shifts = np.stack(np.meshgrid(*([np.arange(k)] * dim), indexing="ij"), axis=-1).reshape(-1, dim)
+    x = np.concatenate([s.x + np.pad(t * s.box[:dim], (0, 3 - dim)) for t in shifts])
+    t = s.copy()
+    t.box = s.box.copy()
+    t.box[:dim] *= k
+    t.x = np.ascontiguousarray(x)
+    t.q = np.ascontiguousarray(np.tile(s.q, (len(shifts), 1)))
+    t.v = np.ascontiguousarray(np.tile(s.v, (len(shifts), 1)))
+    t.L = np.ascontiguousarray(np.tile(s.L, (len(shifts), 1)))
+    t.image = np.zeros((x.shape[0], 3), dtype=np.int32)
+    t.shape_id = np.tile(s.shape_id, len(shifts))
+    return t
+
+
+def octahedra_compressed() -> System:
+    """The at-scale workload: 262,144 rounded octahedra (edge 1, r 0.1) at
+    volume fraction 0.55, NVT kT = 1, dt = 2e-4: a 4096-body cell compressed
+    by the oracle from random orientations on a dilute BCC lattice
+    (octahedra_bcc_dilute, tests/golden/make_states.py), tiled 4 x 4 x 4."""
+    cell = stored_state("octahedra4096_compressed", octahedra_bcc_dilute())
+    s = tile(cell, 4)
+    s.name = "octahedra262144_compressed"
+    s.thermo = None  # the tiled system has 64 times the degrees of freedom: its thermostat starts afresh
+    return s
+
+
 # --------------------------------------------------------------------------
 # Replicas for batched and served runs
 # --------------------------------------------------------------------------
@@ -949,6 +1228,65 @@ def batched_replicas(count: int = 96, seed: int = 4, n_range=(512, 32768), steps
         s = replica_system(shp, n, phi, 1000 * seed + r, dt=DT[name], name=f"replica{r}_{name}_{n}")
         s.steps = steps
         s.fraction_requested = phi
+        out.append(s)
+    return out
+
+
+def contact_lattice(shape: Shape, n: int, seed: int, *, gap: float = 1.05, max_deg: float = 0.25, kT: float = 1.0,
+                    dt: float = 5e-4, ensemble: str = "nvt", name: str = "") -> System:
+    """n bodies on an orthorhombic lattice whose spacing on each axis is the
+    inner body's extent on that axis plus gap * sigma (sigma = 2 r), n of its
+    sites drawn at random, rotated by at most max_deg about random axes.
+    Aligned neighbours face each other across exactly gap * sigma (faces of
+    cubes and L-prisms, crossed edges of tetrahedra); a rotation by at most
+    max_deg moves no point of a body by more than 2 sin(max_deg / 2) R, so
+    every inner gap between lattice neighbours lies within
+    gap * sigma +- 4 sin(max_deg / 2) R: inside the WCA cutoff 2^(1/6) sigma
+    and above zero for the defaults and rounding radii of 0.1 and more."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    dim = shape.dim
+    ext = shape.vertices[:, :dim].max(axis=0) - shape.vertices[:, :dim].min(axis=0)
+    spacing = ext + gap * 2.0 * shape.r
+    c = (n * float(np.prod(spacing))) ** (1.0 / dim)
+    k = np.maximum(1, np.rint(c / spacing)).astype(int)
+    while int(np.prod(k)) < n:
+        a = int(np.argmin(k * spacing))
+        k[a] += 1
+    box = np.ones(3)
+    box[:dim] = k * spacing
+    sites = np.sort(rng.choice(int(np.prod(k)), size=n, replace=False))
+    idx = np.stack(np.unravel_index(sites, tuple(k)), axis=1)
+    x = np.zeros((n, 3))
+    x[:, :dim] = (idx + 0.5) * spacing
+    if dim == 2:
+        q = planar_quaternions(np.deg2rad(rng.uniform(-max_deg, max_deg, n)))
+    else:
+        q = small_rotations(rng, n, max_deg)
+    shape_id = np.zeros(n, dtype=np.int32)
+    v, Lm = thermal_momenta(rng, [shape], shape_id, dim, kT)
+    s = System(dim=dim, box=box, shapes=[shape], shape_id=shape_id, x=x, q=q, v=v, L=Lm,
+               image=np.zeros((n, 3), dtype=np.int32), kT=kT, name=name)
+    s.dt = dt
+    s.ensemble = ensemble
+    return s
+
+
+def batched_replicas_contact(count: int = 96, seed: int = 4, n_range=(512, 32768), steps: int = 500) -> List[System]:
+    """The batched workload's replicas (the same sizes, shapes and rounding
+    radii, drawn from the same seeds as batched_replicas) on contact
+    lattices (contact_lattice): every lattice neighbour in contact, so a
+    full-size batch exercises every replica's feature pairs."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    names = ("cube", "tetrahedron", "lprism")
+    out = []
+    for r in range(count):
+        n = int(round(math.exp(rng.uniform(math.log(n_range[0]), math.log(n_range[1])))))
+        name = names[int(rng.integers(0, 3))]
+        rr = float(rng.uniform(0.1, 0.2))
+        rng.uniform(0.3, 0.5)  # the packing fraction draw of batched_replicas, unused here
+        shp = SHAPES[name](r=rr) if name != "lprism" else lprism(r=rr, quad_h=0.02)
+        s = contact_lattice(shp, n, 1000 * seed + r, dt=DT[name], name=f"replica{r}_{name}_{n}_contact")
+        s.steps = steps
         out.append(s)
     return out
 

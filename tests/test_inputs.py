@@ -121,3 +121,41 @@ def test_octahedra_start_is_overlap_free():
     assert s.min_gap - 4 * math.sin(math.radians(5.0) / 2) * shp.circumradius > rc
     ref = O.forces(s)
     assert ref["stats"]["pairs"] > 0 and ref["stats"]["feature_in"] == 0
+
+
+def _dimer_summary(s, n_pairs, caps=None):
+    """Pairs with a feature pair inside the cutoff, and (caps: faces of
+    shape A, particle 2k) B's vertices against those faces on the face and
+    off it, by the oracle's term listing."""
+    import oracle as O
+    touching, on_face, off_face = 0, 0, 0
+    for k in range(n_pairs):
+        t = O.dimer_terms(s, k)
+        touching += 1 if t else 0
+        if caps is not None:
+            for e in t:
+                if e["family"] == "VjFi" and e["b"] in caps:
+                    on_face += e["inside"] == 1
+                    off_face += e["inside"] == 0
+    return touching, on_face, off_face
+
+
+@pytest.mark.parametrize("name", ["cube", "octahedron", "tetrahedron", "icosahedron", "lprism", "square", "pentagon"])
+def test_contact_dimers_are_all_in_contact(name):
+    shp = I.lprism(0.1, quad_h=0.05) if name == "lprism" else I.SHAPES[name]()
+    s = I.contact_dimers(shp, n_pairs=24, seed=31)
+    touching, _, _ = _dimer_summary(s, 24)
+    assert touching == 24
+
+
+def test_notch_dimers_reach_both_branches_of_the_concave_cap():
+    """The L-prism's caps (faces 0 and 1) are concave hexagons: the notch
+    case puts the partner's vertices over the cap near its reflex corner,
+    where the oracle's point-polygon rule takes the projection (on the
+    face) and the nearest boundary point (over the notch)."""
+    lp = I.lprism(0.1, quad_h=0.05)
+    assert lp.faces[0] == [0, 5, 4, 3, 2, 1] and lp.faces[1] == [6, 7, 8, 9, 10, 11]
+    s = I.contact_dimers(lp, I.cube(1.0, 0.15), n_pairs=128, notch=True)
+    touching, on_face, off_face = _dimer_summary(s, 128, caps={0, 1})
+    print(touching, on_face, off_face)
+    assert touching >= 120 and on_face >= 100 and off_face >= 20

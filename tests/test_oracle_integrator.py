@@ -151,3 +151,81 @@ def test_nose_hoover_conserved_quantity():
     for dt in (5e-4, 2.5e-4):
         assert ptp["nvt", dt] < 1.5 * ptp["nve", dt]
     assert 3.0 < ptp["nvt", 5e-4] / ptp["nvt", 2.5e-4] < 5.0
+
+
+def _dof(dim, n):
+    """Kinetic degrees of freedom of n rigid bodies with the total momentum
+    held at zero: d n - d translational (the centre-of-mass momentum is
+    conserved and zero) and d_rot n rotational (d_rot = 1 in 2D, 3 in 3D)."""
+    drot = 1 if dim == 2 else 3
+    return dim * n - dim, drot * n
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_nose_hoover_equipartition(dim):
+    """Sec. IV.C thermostats translation and rotation with one variable: over
+    a long NVT run of a small dense fluid the time averages of K_trans and
+    K_rot each carry kT/2 per kinetic degree of freedom (equipartition), so
+    <K_trans + K_rot> is (g/2) kT with g the degrees of freedom counted
+    independently here.  A thermostat that targets another g (say one that
+    forgets the conserved centre-of-mass momentum, or counts one rotational
+    degree of freedom in 3D) fails the total; a wrong split between
+    translation and rotation fails the two parts."""
+    if dim == 2:
+        s = I.lattice_system(I.square(1.0, 0.25), 2, 0.3, 3, orient="uniform", spacing=2.0)
+        steps = 200000
+    else:
+        s = I.lattice_system(I.tetrahedron(1.0, 0.2), 2, 0.3, 5, orient="uniform", spacing=1.7)
+        steps = 30000
+    s.ensemble, s.kT, s.dt, s.tau_T = "nvt", 1.3, 2e-3, 0.5
+    O.set_threads(1)
+    try:
+        _, _, lg, _ = O.run(s, steps, mode=0)
+    finally:
+        O.set_threads(os.cpu_count() or 1)
+    tail = lg[steps // 10:]
+    ft, fr = _dof(dim, s.n)
+    busy = float((tail[:, 0] > 0).mean())  # some pair in contact: a fluid, not a free gas
+    ktot = (tail[:, 1] + tail[:, 2]).mean() / (0.5 * (ft + fr) * s.kT)
+    kt = tail[:, 1].mean() / (0.5 * ft * s.kT)
+    kr = tail[:, 2].mean() / (0.5 * fr * s.kT)
+    print(dim, s.n, busy, ktot, kt, kr)
+    assert busy > 0.25, busy
+    assert abs(ktot - 1.0) < 5e-3, ktot
+    assert abs(kt - 1.0) < 0.08 and abs(kr - 1.0) < 0.08, (kt, kr)
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_nose_hoover_ideal_gas_oscillation(dim):
+    """Bodies that never touch (a dilute box) under Nose-Hoover: with
+    u = ln(K / K0), K0 = g kT / 2, the thermostat equations reduce to
+    du/dt = -2 xi, Q dxi/dt = 2K - g kT, i.e. d2u/dt2 = -(2 g kT / Q)(e^u - 1),
+    an oscillation of angular frequency sqrt(2 g kT / Q) = sqrt(2) / tau_T
+    for Q = g kT tau_T^2 at small amplitude.  Its exact period at the
+    run's amplitude (integrated here with scipy) must match the period of
+    the oracle's xi, which pins the thermostat mass Q."""
+    from scipy.integrate import solve_ivp
+    shp = I.square(1.0, 0.25) if dim == 2 else I.cube(1.0, 0.15)
+    s = I.lattice_system(shp, 2, 0.3, 6, orient="uniform", spacing=20.0)
+    s.ensemble, s.kT, s.dt, s.tau_T = "nvt", 0.8, 1e-3, 0.5
+    _, _, lg, _ = O.run(s, 12000, mode=0)
+    assert not lg[:, 0].any()  # no contact, ever
+    ft, fr = _dof(dim, s.n)
+    g = ft + fr
+    K0 = 0.5 * g * s.kT
+    Kt, Kr = O.kinetic(s)
+    u0 = math.log((Kt + Kr) / K0)
+    w2 = 2.0 / s.tau_T ** 2  # 2 g kT / Q with Q = g kT tau_T^2
+    ev = lambda t, y: y[1]
+    ev.direction = -1.0  # du/dt crosses zero downwards: u at its maximum
+    sol = solve_ivp(lambda t, y: [y[1], -w2 * math.expm1(y[0])], (0.0, 20.0), [u0, 0.0], rtol=1e-12, atol=1e-14,
+                    events=ev)
+    period = float(np.diff(sol.t_events[0]).mean())
+    xi = lg[:, 3]
+    t = (np.arange(len(xi)) + 1) * s.dt
+    k = np.where((xi[:-1] < 0) & (xi[1:] >= 0))[0]  # xi crosses zero upwards once per period
+    tz = t[k] - xi[k] * s.dt / (xi[k + 1] - xi[k])
+    measured = float(np.diff(tz).mean())
+    print(dim, u0, period, measured, 2 * math.pi * s.tau_T / math.sqrt(2))
+    assert len(tz) >= 4
+    assert abs(measured / period - 1.0) < 1e-3, (measured, period)
