@@ -34,10 +34,11 @@
 //     k_replica_tail then closes the step of each replica (thermostat half
 //     steps, budget, rebuilds).
 // FP32 mode does the geometry in FP32 from FP64 pair offsets rounded once;
-// problems within 1% of the cutoff and segment pairs that are nearly
-// parallel (sin^2 < 1e-2) are redone in FP64, because FP32 cannot resolve
-// them (steep force near the cutoff; closest points ill-conditioned, error
-// ~ eps / sin^2).
+// problems within 1% of the cutoff, segment pairs that are nearly parallel
+// (sin^2 < 1e-2) and terms whose force line passes close to a centre are
+// redone in FP64, because FP32 cannot resolve them (steep force near the
+// cutoff; closest points ill-conditioned, error ~ eps / sin^2; a torque that
+// is a small fraction of |lever| |f|).
 #include <algorithm>
 
 #include "dem_internal.h"
@@ -407,6 +408,35 @@ __device__ inline int group_append(bool keep, unsigned char *list, int len, int 
     const unsigned long long m = __ballot(keep);
     if (keep) list[len + __popcll(m & below & gmask)] = (unsigned char)item;
     return len + __popcll(m & gmask);
+}
+
+// Whether FP32 cannot resolve a feature-pair problem, which is then redone
+// in FP64 (refine_pair) from the FP64 positions and orientations.  P is the
+// nearest point on i, rho = P - Q, t is j's centre, all in i's frame.
+//  * Within 1% of the cutoff: the force is a steep function of the distance
+//    (dF/dr = 72 eps / r_cut^2) and an isolated contact there has nothing to
+//    hide behind.
+//  * Nearly parallel edges (sin^2 < 1e-2): their closest points are
+//    ill-conditioned (error ~ eps / sin^2), and the error reaches the lever.
+//  * A force line that passes close to either centre (the angle between
+//    rho and the lever P, or Q - t, has sin^2 < 1e-2): the term's torque is
+//    then a small fraction of |lever| |f|, while the rounding of the pair
+//    offset to FP32 turns the force's direction by about 1e-6, an error of
+//    1e-6 |lever| |f| that would dominate it.  Bodies touching along the
+//    line of their centres (a vertex on its symmetry axis, a face contact
+//    centred under the other body) have zero torque this way.
+template <typename T, int DIM>
+__device__ inline bool fp32_unresolved(int fam, T r2, T rc2, T rc, T sin2, V3<T> P, V3<T> rho, V3<T> t)
+{
+    if (sizeof(T) != 4) return false;
+    if (r2 > T(0.99) * rc2 && r2 < T(1.0001) * rc2) return true;
+    if (DIM == 3 && fam == 2 && sin2 < T(1e-2) && r2 < T(1.0001) * rc2 + T(1e-3) * rc) return true;
+    if (!(r2 < rc2)) return false;
+    const V3<T> ci = cross(P, rho);
+    const V3<T> lj = (P - rho) - t;
+    const V3<T> cj = cross(lj, rho);
+    const T k2 = T(1e-2) * r2;
+    return dot(ci, ci) < k2 * dot(P, P) || dot(cj, cj) < k2 * dot(lj, lj);
 }
 
 // FP64 redo of one FP32 feature-pair problem and of its WCA terms, added to
@@ -857,10 +887,7 @@ __global__ void __launch_bounds__(64 * kWaves, OCC) k_pairs(BatchParams b, const
                                 c_near.add(fam < 2 ? 1 : 0);
                                 c_ee.add(fam == 2 ? 1 : 0);
                                 const T r2 = dot(rho, rho);
-                                const bool redo = sizeof(T) == 4 &&
-                                                  ((r2 > T(0.99) * grc2 && r2 < T(1.0001) * grc2) ||
-                                                   (DIM == 3 && fam == 2 && sin2 < T(1e-2) &&
-                                                    r2 < T(1.0001) * grc2 + T(1e-3) * grc));
+                                const bool redo = fp32_unresolved<T, DIM>(fam, r2, grc2, grc, sin2, Pt, rho, tg);
                                 if (redo) {
                                     c_ref.add(1);
                                     c_in.add(refine_pair<T, DIM>(rl.box, rl.eps, rl.par_s2, rec64[qg.ent.x], rec64[qg.ent.y],
@@ -903,9 +930,7 @@ __global__ void __launch_bounds__(64 * kWaves, OCC) k_pairs(BatchParams b, const
                             c_near.add(fam < 2 ? 1 : 0);
                             c_ee.add(fam == 2 ? 1 : 0);
                             const T r2 = dot(rho, rho);
-                            const bool redo = sizeof(T) == 4 &&
-                                              ((r2 > T(0.99) * rc2 && r2 < T(1.0001) * rc2) ||
-                                               (DIM == 3 && fam == 2 && sin2 < T(1e-2) && r2 < T(1.0001) * rc2 + T(1e-3) * rc));
+                            const bool redo = fp32_unresolved<T, DIM>(fam, r2, rc2, rc, sin2, Pt, rho, t);
                             if (redo) {
                                 c_ref.add(1);
                                 c_in.add(refine_pair<T, DIM>(rl.box, rl.eps, rl.par_s2, rec64[qe.ent.x], rec64[qe.ent.y], Si, Sj,
