@@ -340,6 +340,21 @@ dem_status dem_replica_energy(dem_handle h, int32_t replica_id, dem_energy_out *
 dem_status dem_replica_lists(dem_handle h, int32_t replica_id, int32_t *cell_start, int32_t *cell_particles,
                              int32_t *nbr, int32_t *n_nbr, int32_t *dims);
 
+/* dem_replica_energy without any allocation, for callers that cannot
+ * allocate device memory (tight serving loops, code that must not call
+ * hipMalloc or an allocating library routine).  Same arguments, same results
+ * bit for bit, same latched errors and the same synchronisation of the
+ * handle's stream; the per-chunk partials and their totals go to a static
+ * device array of 12 * 4096 + 16 doubles (393 KB) that each device holds
+ * until the process ends, instead of the handle's reduction buffers.
+ * Limit: replicas of at most 4096 chunks of 64 particles (262,144
+ * particles); larger ones return DEM_E_CAPACITY with nothing launched.
+ * Every call on one device shares that array: calls that overlap on one
+ * device (other host threads, other streams) race and must be serialised
+ * by the caller; each call writes its totals whole, so nothing left by an
+ * earlier call reaches a later one. */
+dem_status dem_replica_energy_noalloc(dem_handle h, int32_t replica_id, dem_energy_out *out);
+
 const char *dem_status_string(dem_status s);
 const char *dem_last_error(dem_handle h);
 

@@ -333,15 +333,17 @@ __global__ void __launch_bounds__(kGatherBlock) k_kinetic(BatchParams b, const S
     }
 }
 
-// Per-chunk partials of U, K_trans, K_rot and W (9): part[chunk * 12 + c].
+// Per-chunk partials of U, K_trans, K_rot and W (9) of chunks c0, c0 + 1,
+// ...: part[(chunk - c0) * 12 + c].
 __global__ void __launch_bounds__(kChunk) k_energy_partials(BatchParams b, const SysParams *reps, StatePtrs s,
-                                                               OutPtrs o, ListPtrs l, double *part)
+                                                               OutPtrs o, ListPtrs l, double *part, int c0)
 {
     __shared__ double sh[kChunk];
-    const int r = l.chunk_rep[blockIdx.x];
+    const int ch = c0 + (int)blockIdx.x;
+    const int r = l.chunk_rep[ch];
     if (r < 0) return;
     const SysParams &p = reps[r];
-    const int i = blockIdx.x * kChunk + threadIdx.x;
+    const int i = ch * kChunk + threadIdx.x;
     double val[12];
     for (int c = 0; c < 12; ++c) val[c] = 0.0;
     if (i < p.off + p.n) {
@@ -405,7 +407,25 @@ void launch_kinetic(const Launch &L, hipStream_t stream)
 void launch_energy_partials(const Launch &L, double *part, hipStream_t stream)
 {
     if (L.b.nchunk == 0) return;
-    k_energy_partials<<<L.b.nchunk, kChunk, 0, stream>>>(L.b, L.reps, L.s, L.o, L.l, part);
+    k_energy_partials<<<L.b.nchunk, kChunk, 0, stream>>>(L.b, L.reps, L.s, L.o, L.l, part, 0);
+}
+
+// The partials of chunks c0 .. c0 + nchunks - 1 into part[0 .. 12 nchunks),
+// then their totals in chunk order (the order of the host sum of
+// dem_replica_energy, so the bits agree) into total[0 .. 12).
+__global__ void k_sum_partials(const double *part, int nchunks, double *total)
+{
+    const int c = threadIdx.x;
+    if (c >= 12) return;
+    double acc = 0.0;
+    for (int k = 0; k < nchunks; ++k) acc += part[(size_t)12 * k + c];
+    total[c] = acc;
+}
+
+void launch_energy_totals(const Launch &L, int c0, int nchunks, double *part, double *total, hipStream_t stream)
+{
+    if (nchunks > 0) k_energy_partials<<<nchunks, kChunk, 0, stream>>>(L.b, L.reps, L.s, L.o, L.l, part, c0);
+    k_sum_partials<<<1, 64, 0, stream>>>(part, nchunks, total);
 }
 
 }  // namespace dem

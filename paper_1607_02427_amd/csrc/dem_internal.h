@@ -308,6 +308,7 @@ void launch_kinetic(const Launch &L, hipStream_t stream);
 void launch_nh_end(const Launch &L, hipStream_t stream);
 // Per-chunk partials of U, K_trans, K_rot and W (9): part[12 * chunk + c].
 void launch_energy_partials(const Launch &L, double *part, hipStream_t stream);
+void launch_energy_totals(const Launch &L, int c0, int nchunks, double *part, double *total, hipStream_t stream);
 
 constexpr int kBlock = 256;
 inline int blocks_for(int n) { return (n + kBlock - 1) / kBlock; }

@@ -17,6 +17,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -100,6 +101,7 @@ struct dem_system {
     void *rec = nullptr;         // [cap][N] SlotRec in the force precision
     double *ke_part = nullptr;   // [2 * chunks]
     double *e_part = nullptr;    // [12 * chunks]
+    double *scratch = nullptr;   // this device's copy of the static energy scratch (device address)
     double *thermo = nullptr;    // [replica][TH_COUNT]
     int64_t *budget = nullptr;   // [replica] steps left
     int64_t *steps = nullptr;    // [replica] steps done
@@ -114,6 +116,7 @@ namespace {
 std::string g_err;
 constexpr int64_t kUnbounded = (int64_t)1 << 62;
 
+
 dem_status fail(dem_system *h, dem_status s, const char *fmt, ...)
 {
     char buf[512];
@@ -124,6 +127,39 @@ dem_status fail(dem_system *h, dem_status s, const char *fmt, ...)
     if (h) h->err = buf;
     g_err = buf;
     return s;
+}
+
+// Device memory of dem_replica_energy_noalloc, which allocates nothing: the
+// per-chunk partials of one replica (12 doubles per 64-particle chunk, at
+// most kScratchChunks chunks) and their 12 totals.  Each device holds its
+// own copy until the process ends; in host code `scratch` names no device
+// address, so host code uses only the address that hipGetSymbolAddress
+// returns for the current device (scratch_of).
+constexpr int kScratchChunks = 4096;  // replicas of up to 262,144 particles
+constexpr size_t kScratchTotals = (size_t)12 * kScratchChunks;
+__device__ __align__(256) double scratch[kScratchTotals + 16];
+
+constexpr int kMaxDevices = 64;
+double *g_scratch_addr[kMaxDevices];
+std::mutex g_scratch_mu;
+
+// The current device's address of `scratch`, looked up once per device at
+// handle creation (with that device current).
+dem_status scratch_of(dem_system *h)
+{
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices)
+        return fail(h, DEM_E_HIP, "no current device for the static scratch");
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_addr[dev]) {
+        void *ptr = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !ptr)
+            return fail(h, DEM_E_HIP, "hipGetSymbolAddress(scratch) on device %d: %s", dev, hipGetErrorString(e));
+        g_scratch_addr[dev] = static_cast<double *>(ptr);
+    }
+    h->scratch = g_scratch_addr[dev];
+    return DEM_OK;
 }
 
 #define HIPCHK(h, call)                                                                            \
@@ -900,11 +936,13 @@ dem_status compute_forces(dem_system *h)
 
 bool valid_replica(const dem_system *h, int r) { return h && r >= 0 && r < (int)h->reps.size() && h->reps[r].live; }
 
+dem_status finish_energy(dem_system *h, int r, const double acc[12], const double th[TH_COUNT],
+                         const int32_t flags[FLAG_COUNT], int64_t steps, dem_energy_out *o);
+
 dem_status replica_energy(dem_system *h, int r, dem_energy_out *o)
 {
     std::memset(o, 0, sizeof *o);
     const Replica &R = h->reps[r];
-    const SysParams &sp = R.sp;
     std::vector<double> part((size_t)12 * std::max(R.nchunks, 1), 0.0);
     double th[TH_COUNT];
     int32_t flags[FLAG_COUNT];
@@ -921,6 +959,15 @@ dem_status replica_energy(dem_system *h, int r, dem_energy_out *o)
     double acc[12] = {0};
     for (int b = 0; b < R.nchunks; ++b)
         for (int c = 0; c < 12; ++c) acc[c] += part[(size_t)12 * b + c];
+    return finish_energy(h, r, acc, th, flags, steps, o);
+}
+
+// dem_energy_out of replica r from its totals of U, K_trans, K_rot and W (9),
+// its thermostat words, flags and step count; latched device errors.
+dem_status finish_energy(dem_system *h, int r, const double acc[12], const double th[TH_COUNT],
+                         const int32_t flags[FLAG_COUNT], int64_t steps, dem_energy_out *o)
+{
+    const SysParams &sp = h->reps[r].sp;
     o->U = acc[0];
     o->K_trans = acc[1];
     o->K_rot = acc[2];
@@ -943,6 +990,35 @@ dem_status replica_energy(dem_system *h, int r, dem_energy_out *o)
     if (flags[FLAG_MAXROW] > h->bp.cap)
         return fail(h, DEM_E_CAPACITY, "neighbour row of %d exceeds capacity %d", flags[FLAG_MAXROW], h->bp.cap);
     return DEM_OK;
+}
+
+// replica_energy with its partials and totals in the static scratch: no
+// device or host allocation.
+dem_status replica_energy_noalloc(dem_system *h, int r, dem_energy_out *o)
+{
+    std::memset(o, 0, sizeof *o);
+    const Replica &R = h->reps[r];
+    if (!h->scratch) return fail(h, DEM_E_STATE, "the static scratch was not set up for this handle's device");
+    if (R.nchunks > kScratchChunks)
+        return fail(h, DEM_E_CAPACITY,
+                    "replica %d has %d particles (%d chunks of %d); the allocation-free energy call takes at most %d "
+                    "particles (%d chunks)",
+                    r, R.sp.n, R.nchunks, kChunk, kScratchChunks * kChunk, kScratchChunks);
+    double acc[12];
+    double th[TH_COUNT];
+    int32_t flags[FLAG_COUNT];
+    int64_t steps = 0;
+    double *total = h->scratch + kScratchTotals;
+    // the totals are written whole by every call, so nothing left by an
+    // earlier call reaches this one
+    launch_energy_totals(make_launch(h), R.chunk0, R.nchunks, h->scratch, total, h->stream);
+    HIPCHK(h, hipGetLastError());
+    HIPCHK(h, hipMemcpyAsync(acc, total, sizeof acc, hipMemcpyDeviceToHost, h->stream));
+    HIPCHK(h, hipMemcpyAsync(th, h->thermo + TH_COUNT * r, sizeof th, hipMemcpyDeviceToHost, h->stream));
+    HIPCHK(h, hipMemcpyAsync(flags, h->lst.flags + FLAG_COUNT * r, sizeof flags, hipMemcpyDeviceToHost, h->stream));
+    HIPCHK(h, hipMemcpyAsync(&steps, h->steps + r, sizeof steps, hipMemcpyDeviceToHost, h->stream));
+    HIPCHK(h, hipStreamSynchronize(h->stream));
+    return finish_energy(h, r, acc, th, flags, steps, o);
 }
 
 // The lists of replica r in their canonical form: the cell list as CSR with
@@ -1094,6 +1170,7 @@ dem_status dem_create_system(const dem_params *params, const dem_state_ptrs *sta
     h->bp.nstate = (int)p.n;
     if (hipStreamCreateWithFlags(&h->cap_stream, hipStreamNonBlocking) != hipSuccess)
         return bail(fail(h, DEM_E_HIP, "stream creation failed"));
+    if ((st = scratch_of(h)) != DEM_OK) return bail(st);
     const int nch = (int)((p.n + kChunk - 1) / kChunk);
     if ((st = alloc_core(h, nch * kChunk, R.sp.ncell + 1, p.n_shapes, 1)) != DEM_OK) return bail(st);
     h->auto_cap = p.nbr_capacity <= 0;
@@ -1138,6 +1215,7 @@ dem_status dem_batch_create(const dem_batch_params *bpar, void *hip_stream, dem_
     dem_status st;
     if (hipStreamCreateWithFlags(&h->cap_stream, hipStreamNonBlocking) != hipSuccess)
         return bail(fail(h, DEM_E_HIP, "stream creation failed"));
+    if ((st = scratch_of(h)) != DEM_OK) return bail(st);
     if ((st = alloc_core(h, Ncap, Ccap, Scap, b.max_replicas)) != DEM_OK) return bail(st);
     h->auto_cap = b.nbr_capacity <= 0;
     if ((st = alloc_nbr(h, h->auto_cap ? 16 : ((b.nbr_capacity + 3) & ~3))) != DEM_OK) return bail(st);
@@ -1317,6 +1395,13 @@ dem_status dem_replica_energy(dem_handle h, int32_t rid, dem_energy_out *o)
     if (!h || !o) return fail(h, DEM_E_ARG, "null argument");
     if (!valid_replica(h, rid)) return fail(h, DEM_E_ARG, "no replica %d", rid);
     return replica_energy(h, rid, o);
+}
+
+dem_status dem_replica_energy_noalloc(dem_handle h, int32_t rid, dem_energy_out *o)
+{
+    if (!o) return fail(h, DEM_E_ARG, "null argument");
+    if (!valid_replica(h, rid)) return fail(h, DEM_E_ARG, "no live replica %d", rid);
+    return replica_energy_noalloc(h, rid, o);
 }
 
 dem_status dem_set_thermostat(dem_handle h, double xi, double eta)

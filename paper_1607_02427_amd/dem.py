@@ -146,6 +146,8 @@ def lib():
         L.dem_batch_info.restype = st
         L.dem_replica_energy.argtypes = [C.c_void_p, C.c_int32, C.POINTER(EnergyOut)]
         L.dem_replica_energy.restype = st
+        L.dem_replica_energy_noalloc.argtypes = [C.c_void_p, C.c_int32, C.POINTER(EnergyOut)]
+        L.dem_replica_energy_noalloc.restype = st
         L.dem_replica_lists.argtypes = [C.c_void_p, C.c_int32, _ip, _ip, _ip, _ip, _ip]
         L.dem_replica_lists.restype = st
         L.dem_status_string.argtypes = [C.c_int]
@@ -346,6 +348,12 @@ class DemSystem:
         self._check(lib().dem_energy(self.h, C.byref(e)), "dem_energy")
         return _energy_dict(e)
 
+    def energy_noalloc(self) -> Dict[str, float]:
+        """energy() through the allocation-free entry point."""
+        e = EnergyOut()
+        self._check(lib().dem_replica_energy_noalloc(self.h, 0, C.byref(e)), "dem_replica_energy_noalloc")
+        return _energy_dict(e)
+
     def list_info(self):
         rl = C.c_double()
         nc = C.c_int32()
@@ -504,6 +512,12 @@ class DemBatch:
     def energy(self, rid: int):
         e = EnergyOut()
         self._check(lib().dem_replica_energy(self.h, int(rid), C.byref(e)), "dem_replica_energy")
+        return _energy_dict(e)
+
+    def energy_noalloc(self, rid: int):
+        """energy(rid) through the allocation-free entry point."""
+        e = EnergyOut()
+        self._check(lib().dem_replica_energy_noalloc(self.h, int(rid), C.byref(e)), "dem_replica_energy_noalloc")
         return _energy_dict(e)
 
     def lists(self, rid: int):
