@@ -42,6 +42,7 @@
 #include <algorithm>
 
 #include "dem_internal.h"
+#include "dem_listbuild.h"
 
 namespace dem {
 namespace {
@@ -1209,21 +1210,56 @@ __device__ inline void add_slot(double acc[16], const SlotRec<T> &w)
         for (int c = 0; c < 3; ++c) acc[7 + 3 * a + c] -= 0.5 * d[a] * f[c];
 }
 
+// Workgroups of a step's gather beyond its chunk workgroups carry the
+// neighbour rows of the step's list build (one wavefront per 4 particles;
+// each takes every nrole-th group of the replicas that rebuild), from the
+// cells the kick-drift filled.  The pair kernel is done with the rows in
+// place; the gather workgroups read records, not rows.
+constexpr int kRowWorkgroups = 2048;
+inline int row_workgroups(const BatchParams &b) { return pad8(std::min(b.nchunk * (kChunk / lb::kNbrPer), kRowWorkgroups)); }
+
+template <int DIM>
+__device__ void step_rows(const BatchParams &b, const SysParams *reps, const StatePtrs &s, const ListPtrs &l,
+                          const int64_t *budget, int *buf, int first)
+{
+    const int nbn = b.nchunk * (kChunk / lb::kNbrPer);
+    const int nrole = (int)gridDim.x - first;
+    for (int vb = (int)blockIdx.x - first; vb < nbn; vb += nrole) {
+        const int r = l.chunk_rep[vb * lb::kNbrPer / kChunk];
+        if (r < 0) continue;
+        const SysParams &p = reps[r];
+        int32_t *fl = l.flags + r * FLAG_COUNT;
+        if (!lb::building(LISTS_STEP, r, p, fl, budget)) continue;
+        lb::nbr_rows<DIM>(b, p, s, l, fl, vb, buf);
+    }
+}
+
 template <typename T, int DIM, bool KICK>
 __global__ void __launch_bounds__(kGatherBlock) k_gather(BatchParams b, const SysParams *reps, StatePtrs s, OutPtrs o,
                                                       ListPtrs l, const SlotRec<T> *__restrict__ rec, double *ke_part,
                                                       double *thermo, int64_t *budget, int64_t *steps)
 {
     __shared__ double sh[kGatherBlock];
+    const int G = KICK ? pad8(b.nchunk) : (int)gridDim.x;  // chunk workgroups
+    if (KICK && (int)blockIdx.x >= G) {
+        __shared__ int rbuf[lb::kNbrPer * kRowMax];
+        if (l.gflags[G_ANY] != 0) step_rows<DIM>(b, reps, s, l, budget, rbuf, G);
+        return;
+    }
     constexpr int kB = gather_batch<T>();
     const int sub = threadIdx.x % kGatherLanes;
-    const int cb = xcd_block(blockIdx.x, gridDim.x);  // this block's chunk
+    const int cb = xcd_block(blockIdx.x, G);  // this block's chunk
     const int i = cb * kGatherPer + threadIdx.x / kGatherLanes;
+    if (KICK && blockIdx.x == 0 && threadIdx.x == 0) l.gflags[G_FILL] = l.gflags[G_ANY];  // for the replica tail
     // what depends on the slot alone is requested with the replica's
-    // parameters instead of after them (the row length from the library's
-    // N slots; the state only within the length of its arrays)
-    const int m_row = i < b.N ? l.n_nbr[i] : 0;
-    const uint32_t mask0 = i < b.N ? l.smask[i] : 0u;  // slots 0..31 written since the last gather
+    // parameters instead of after them (the state only within the length
+    // of its arrays).  The records are those of the rows the pair kernel
+    // used; a build in this step has already written the next rows, so the
+    // written slots are bounded by the row capacity, not the new row length.
+    const int nw = slot_words(b.cap);
+    uint32_t mw[kRowMax / 32];  // slots written since the last gather, 32 per word
+#pragma unroll
+    for (int wd = 0; wd < kRowMax / 32; ++wd) mw[wd] = (i < b.N && wd < nw) ? l.smask[(size_t)wd * b.N + i] : 0u;
     double sv[3] = {0.0, 0.0, 0.0}, sL[3] = {0.0, 0.0, 0.0}, sq[4] = {1.0, 0.0, 0.0, 0.0};
     int ssid = 0;
     if (KICK && i < b.nstate) {
@@ -1245,6 +1281,12 @@ __global__ void __launch_bounds__(kGatherBlock) k_gather(BatchParams b, const Sy
     const int r = cb < b.nchunk ? l.chunk_rep[cb] : -1;
     if (r < 0) return;
     const SysParams &p = reps[r];
+    if (KICK && threadIdx.x == 0 && cb == p.off / kChunk) {
+        // whether the replica tail writes this step's new pair entries (the
+        // tail itself moves the rebuild flag on)
+        int32_t *fl = l.flags + r * FLAG_COUNT;
+        fl[FLAG_FILL] = (fl[FLAG_REBUILD] != 0 && budget[r] > 0) ? 1 : 0;
+    }
     if (KICK && budget[r] <= 0) return;
     const bool nvt = KICK && p.ensemble == DEM_NVT;
     const size_t N = (size_t)b.N;
@@ -1252,16 +1294,15 @@ __global__ void __launch_bounds__(kGatherBlock) k_gather(BatchParams b, const Sy
     double acc[16];
     for (int c = 0; c < 16; ++c) acc[c] = 0.0;  // F[3], T[3], U, W[9]
     if (mine) {
-        const int m = m_row;
         // only the slots written since the last gather, whose words are
         // cleared for the next evaluation; ascending, so they are added in
         // row order.  Loads go in batches: every load of a batch is issued
         // before any of its sums, so the batch's round trips overlap.
-        for (int wd = 0; wd < slot_words(m); ++wd) {
-            uint32_t bits = wd == 0 ? mask0 : l.smask[(size_t)wd * N + i];
+#pragma unroll
+        for (int wd = 0; wd < kRowMax / 32; ++wd) {
+            uint32_t bits = mw[wd];
             if (bits == 0u) continue;
             l.smask[(size_t)wd * N + i] = 0u;
-            if (32 * (wd + 1) > m) bits &= (1u << (m - 32 * wd)) - 1u;  // slots below the row length
             while (bits != 0u) {
                 SlotRec<T> w[kB];
                 bool h[kB];
@@ -1341,12 +1382,32 @@ __global__ void __launch_bounds__(kGatherBlock) k_gather(BatchParams b, const Sy
 // and count, and the list-rebuild transitions: this step's build is
 // counted, and a trigger raised during the step schedules a build for the
 // next step.  A kernel of its own, so the partial sums are visible without
-// a device-wide fence in every gather block.
-__global__ void __launch_bounds__(kGatherBlock) k_replica_tail(const SysParams *reps, ListPtrs l,
+// a device-wide fence in every gather block.  Workgroups beyond the
+// replica slots carry the end of the step's list build: the tile plan (the
+// first of them) and the pair entries of every chunk of a replica that
+// rebuilds (FLAG_FILL, which the tail workgroups do not touch), one chunk
+// per workgroup at a time; the cells are emptied for the next build.
+__global__ void __launch_bounds__(kGatherBlock) k_replica_tail(BatchParams b, const SysParams *reps, ListPtrs l,
                                                                const double *ke_part, double *thermo, int64_t *budget,
                                                                int64_t *steps)
 {
     __shared__ double sh[kGatherBlock];
+    if ((int)blockIdx.x >= b.nrep) {
+        static_assert(kGatherBlock == kChunk, "one wavefront per chunk");
+        __shared__ int part[kGatherBlock];
+        if (l.gflags[G_FILL] == 0) return;
+        const int fb = (int)blockIdx.x - b.nrep, nfb = (int)gridDim.x - b.nrep;
+        if (fb == 0)
+            lb::plan<kGatherBlock>(b, reps, l, part, [&](int r) {
+                return reps[r].n > 0 && l.flags[r * FLAG_COUNT + FLAG_FILL] != 0;
+            });
+        for (int c = fb; c < b.nchunk; c += nfb) {
+            const int r = l.chunk_rep[c];
+            if (r < 0 || !reps[r].live || l.flags[r * FLAG_COUNT + FLAG_FILL] == 0) continue;
+            lb::fill_chunk(b, reps[r], l, c, false, true);
+        }
+        return;
+    }
     const int r = blockIdx.x;
     int32_t *fl = l.flags + r * FLAG_COUNT;
     double *th = thermo + r * TH_COUNT;
@@ -1431,16 +1492,17 @@ template <typename T, int DIM, int GL, int OCC>
 void pairs_t(const Launch &L, unsigned long long *stats, hipStream_t stream)
 {
     const size_t sh = pair_kernel_lds(sizeof(T) == 4 ? DEM_FP32 : DEM_FP64, L.b.tab_slots, GL);
+    const int grid = L.b.pair_blocks;
     const auto rot = reinterpret_cast<const PartRec<T> *>(L.f.rot);
     const auto rec = reinterpret_cast<SlotRec<T> *>(L.f.rec);
     const auto tab = reinterpret_cast<const ShapeTab<T> *>(L.f.tab);
     const auto tab64 = reinterpret_cast<const ShapeTab<double> *>(L.f.tab64);
     if (stats)
-        k_pairs<T, DIM, GL, true, OCC><<<L.b.pair_blocks, 64 * kWaves, sh, stream>>>(
-            L.b, L.reps, L.s, L.l, rot, L.f.rec64, rec, tab, tab64, stats);
+        k_pairs<T, DIM, GL, true, OCC><<<grid, 64 * kWaves, sh, stream>>>(L.b, L.reps, L.s, L.l, rot, L.f.rec64, rec,
+                                                                           tab, tab64, stats);
     else
-        k_pairs<T, DIM, GL, false, OCC><<<L.b.pair_blocks, 64 * kWaves, sh, stream>>>(
-            L.b, L.reps, L.s, L.l, rot, L.f.rec64, rec, tab, tab64, nullptr);
+        k_pairs<T, DIM, GL, false, OCC><<<grid, 64 * kWaves, sh, stream>>>(L.b, L.reps, L.s, L.l, rot, L.f.rec64, rec,
+                                                                            tab, tab64, nullptr);
 }
 
 template <typename T, int DIM>
@@ -1448,9 +1510,10 @@ void gather_t(const Launch &L, bool kick, hipStream_t stream)
 {
     const SlotRec<T> *rec = reinterpret_cast<const SlotRec<T> *>(L.f.rec);
     if (kick) {
-        k_gather<T, DIM, true><<<pad8(L.b.nchunk), kGatherBlock, 0, stream>>>(L.b, L.reps, L.s, L.o, L.l, rec, L.ke_part,
-                                                                    L.thermo, L.budget, L.steps);
-        k_replica_tail<<<L.b.nrep, kGatherBlock, 0, stream>>>(L.reps, L.l, L.ke_part, L.thermo, L.budget, L.steps);
+        k_gather<T, DIM, true><<<pad8(L.b.nchunk) + row_workgroups(L.b), kGatherBlock, 0, stream>>>(
+            L.b, L.reps, L.s, L.o, L.l, rec, L.ke_part, L.thermo, L.budget, L.steps);
+        k_replica_tail<<<L.b.nrep + std::min(L.b.nchunk, 1024), kGatherBlock, 0, stream>>>(
+            L.b, L.reps, L.l, L.ke_part, L.thermo, L.budget, L.steps);
     }
     else
         k_gather<T, DIM, false><<<pad8(L.b.nchunk), kGatherBlock, 0, stream>>>(L.b, L.reps, L.s, L.o, L.l, rec, L.ke_part,

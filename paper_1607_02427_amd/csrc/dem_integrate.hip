@@ -285,9 +285,12 @@ __global__ void __launch_bounds__(kChunk) k_kick_drift(BatchParams b, const SysP
     s.image[3 * i + 1] = img[1];
     s.image[3 * i + 2] = img[2];
     if (rebuild != 0) {
-        // this step rebuilds the lists: the particle goes into its cell now
-        // (and the replica's pair total restarts for k_nbr to add to)
-        if (i == p.off) l.flags[r * FLAG_COUNT + FLAG_NPAIRS] = 0;
+        // this step rebuilds the lists from the positions after this drift:
+        // the particle goes into its cell now (and the new pair total
+        // restarts for the row workgroups to add to); this step's forces
+        // still use the lists in place, which the trigger of the previous
+        // step has kept valid for these positions
+        if (i == p.off) l.flags[r * FLAG_COUNT + FLAG_NEWPAIRS] = 0;
         cell_insert(p, l, i, x[0], x[1], x[2]);
     } else {
         // The next step rebuilds them if the displacement since the last

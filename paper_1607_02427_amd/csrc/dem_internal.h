@@ -30,19 +30,28 @@ constexpr int pair_tile() { return kPairWaves * 16; }
 // Per-replica device flag words (flags[r * FLAG_COUNT + w], one 64-byte
 // line per replica).  FLAG_TRIGGER: some particle has moved far enough
 // since the last build that the next step must rebuild the lists;
-// FLAG_REBUILD: the current step rebuilds them.
+// FLAG_REBUILD: the current step rebuilds them (from the positions after
+// its drift; the new lists serve from the next step on).  FLAG_NPAIRS: pair
+// entries of the lists in use; FLAG_NEWPAIRS: those of the build under way.
+// FLAG_FILL: the current step's build writes its pair entries (a copy of
+// FLAG_REBUILD taken by the gather, for the extra workgroups of the replica
+// tail, while the tail itself moves FLAG_REBUILD on to the next step).
 enum Flag {
-    FLAG_REBUILD = 0, FLAG_NBUILDS = 1, FLAG_MAXROW = 2, FLAG_NONFINITE = 3, FLAG_NPAIRS = 4, FLAG_TICKET = 5,
-    FLAG_TRIGGER = 6, FLAG_CELLOVF = 7, FLAG_NBRTICKET = 8, FLAG_COUNT = 16
+    FLAG_REBUILD = 0, FLAG_NBUILDS = 1, FLAG_MAXROW = 2, FLAG_NONFINITE = 3, FLAG_NPAIRS = 4,
+    FLAG_TRIGGER = 6, FLAG_CELLOVF = 7, FLAG_NEWPAIRS = 9, FLAG_FILL = 10, FLAG_COUNT = 16
 };
-// Batch-wide words: how many replicas rebuild their lists in the current
-// step (the list kernels return at once when none does).
-// G_STAMP: number of the current force evaluation (bumped before every
-// launch of the pair kernel in a step or a force computation).
-enum GWord { G_ANY = 0, G_STAMP = 1, G_COUNT = 4 };
+// Batch-wide words.  G_ANY: how many replicas rebuild their lists in the
+// current step (the list workgroups of the step kernels return at once
+// when none does); G_FILL: its copy taken by the gather, for the replica
+// tail.  G_STAMP: number of the current force evaluation (bumped before
+// every launch of the pair kernel in a step or a force computation).
+enum GWord { G_ANY = 0, G_STAMP = 1, G_FILL = 2, G_COUNT = 4 };
 // Particles one cell can hold, and the longest neighbour row.
 constexpr int kCellCap = 64;
 constexpr int kRowMax = 128;
+// Particles whose neighbour rows one wavefront builds at a time (16 lanes
+// each); the pair counts are totalled per such group (ListPtrs::ptot).
+constexpr int lb_rows_per_group = 4;
 // Per-replica thermostat words (double, thermo[r * TH_COUNT + w]).  Between
 // steps a replica is either closed (its velocities carry every half step
 // so far) or open: the closing half step of its last step has scaled the
@@ -186,7 +195,7 @@ struct ListPtrs {
     // half list of unordered pairs (i < j), rebuilt with the neighbour list
     int32_t *klo;                // [N] first row slot of i holding a j > i
     int32_t *pstart;             // [N] first pair index of i, local to its replica
-    int32_t *ptot;               // [N / 16] pairs owned by the particles of each k_nbr block
+    int32_t *ptot;               // [N / 4] pairs owned by each group of 4 particles (a row workgroup's)
     int4 *pairs;                 // [pair slots] {i, j, slot of j in i's row, slot of i in j's row (-1: missing)}
     // row slots whose record was written since the particle's last gather:
     // bit k % 32 of word k / 32, [slot_words(cap)][N]; the gather reads
@@ -248,14 +257,13 @@ struct Launch {
 };
 
 // Cell list, neighbour list, half pair list and the tile plan of the pair
-// kernel.  mode LISTS_STEP: inside a step, for every replica whose rebuild
-// flag is set and that has steps left (the kick-drift has put its particles
-// into cells); the kernels return at once when no replica rebuilds, so a
-// captured step contains them unconditionally.  mode LISTS_ALL or a replica
-// index: from the current positions, now, for every live replica or for
-// that one (cells included).  LISTS_PLAN recomputes the tile plan alone;
-// LISTS_REFILL writes every live replica's pair entries again from its
-// rows (after the pair slots moved) and the plan.
+// kernel, outside a step.  mode LISTS_ALL or a replica index: from the
+// current positions, now, for every live replica or for that one (cells
+// included).  LISTS_PLAN recomputes the tile plan alone; LISTS_REFILL
+// writes every live replica's pair entries again from its rows (after the
+// pair slots moved) and the plan.  LISTS_STEP names the build inside a step
+// (every replica whose rebuild flag is set and that has steps left), which
+// the step kernels carry themselves.
 enum { LISTS_STEP = -1, LISTS_ALL = -2, LISTS_PLAN = -3, LISTS_REFILL = -4 };
 void launch_lists(const Launch &L, int mode, hipStream_t stream);
 
@@ -295,7 +303,8 @@ void launch_pairs(const Launch &L, unsigned long long *stats, hipStream_t stream
 // Per-particle sums of pair records in row order (fixed, atomic-free):
 // F, tau, U_i, W_i; with kick != 0 also the closing velocity/angular
 // momentum kick and then the step tail of every replica (Nose-Hoover half
-// steps, step budget and count, rebuild scheduling).
+// steps, step budget and count, rebuild scheduling), which also carries
+// the pair entries and the tile plan of the step's list build.
 void launch_gather(const Launch &L, bool kick, hipStream_t stream);
 
 // Integrator pieces.  With NVT the step tail after the gather applies the
@@ -319,7 +328,7 @@ inline int blocks_for(int n) { return (n + kBlock - 1) / kBlock; }
 // its tiles the same way, touch a particle's data on the same XCD step
 // after step and find it in that L2. Any other grid size keeps the plain
 // order (still a permutation, only without the locality).
-inline int pad8(int blocks) { return (blocks + 7) / 8 * 8; }
+__host__ __device__ inline int pad8(int blocks) { return (blocks + 7) / 8 * 8; }
 __device__ inline int xcd_block(int b, int G) { return (G & 7) ? b : (b & 7) * (G >> 3) + (b >> 3); }
 // The gather and the kinetic reduction map one chunk (kGatherPer = kChunk
 // particles) to each block of kGatherLanes lanes per particle, which writes

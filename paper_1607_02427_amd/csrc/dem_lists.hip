@@ -12,92 +12,24 @@
 // writes its result into both slots, and each particle sums its own row.
 //
 // A build has three parts, each a grid over particles:
-//   1. cells: every particle goes into the fixed-capacity slots of its cell
-//      (inside a step the kick-drift does this as it moves the particle);
-//   2. k_nbr: 16 lanes per particle scan the 3^d neighbour cells, collect
-//      the hits in LDS by wave ballots, and rank-sort them into the row; the
-//      last block of each replica scans the replica's pair counts;
-//   3. k_fill: each particle writes the pair entries it owns and empties its
-//      cell; block 0 recomputes the tile plan (the first tile of every
+//   1. cells: every particle goes into the fixed-capacity slots of its cell;
+//   2. rows: 16 lanes per particle scan the 3^d neighbour cells, collect
+//      the hits in LDS by wave ballots, and rank-sort them into the row;
+//   3. fill: each particle writes the pair entries it owns and empties its
+//      cell; one workgroup recomputes the tile plan (the first tile of every
 //      replica) for the pair kernel.
-// Inside a step the kernels return at once unless some replica rebuilds.
-#include "dem_internal.h"
-
-#pragma clang fp contract(off)
+// The kernels here build outside a step (k_assign, k_nbr, k_fill).  Inside
+// a step the same device code (dem_listbuild.h) runs in the step kernels:
+// the kick-drift puts the particles into cells, extra workgroups of the
+// pair kernel write the rows while the pair workgroups still use the old
+// pair entries, and extra workgroups of the replica tail write the pair
+// entries and the plan; the new lists serve from the next step on.
+#include "dem_listbuild.h"
 
 namespace dem {
 namespace {
 
-constexpr int kNbrLanes = 16;                   // lanes per particle in k_nbr
-constexpr int kNbrPer = kBlock / kNbrLanes;     // particles per k_nbr block (a quarter chunk)
-
-// Minimum image of d = x_j - x_i for positions in [0, L].  This equals
-// d - L rint(d / L) bit for bit except where |d| is within rounding of L/2,
-// and there both forms give |d| >= L/2 >= r_list, so no list decision can
-// differ; it avoids an FP64 division per candidate.
-__device__ inline double min_image(double d, double L)
-{
-    const double h = 0.5 * L;
-    return d > h ? d - L : (d < -h ? d + L : d);
-}
-
-__device__ inline bool within(const SysParams &p, const StatePtrs &s, double xi, double yi, double zi, int j)
-{
-    const double dx = min_image(s.x[j] - xi, p.box[0]);
-    const double dy = min_image(s.y[j] - yi, p.box[1]);
-    double r2 = dx * dx + dy * dy;
-    if (p.dim == 3) {
-        const double dz = min_image(s.z[j] - zi, p.box[2]);
-        r2 = r2 + dz * dz;
-    }
-    return r2 < p.rl2;
-}
-
-__device__ inline unsigned long long lanes_below()
-{
-    const unsigned lane = __lane_id();
-    return lane == 0 ? 0ull : (~0ull >> (64 - lane));
-}
-
-// Does this launch build replica r?  (LISTS_REFILL: every live replica
-// that has lists.)
-__device__ inline bool building(int mode, int r, const SysParams &p, const int32_t *fl, const int64_t *budget)
-{
-    if (!p.live) return false;
-    if (mode == LISTS_STEP) return fl[FLAG_REBUILD] != 0 && budget[r] > 0;
-    if (mode == LISTS_REFILL) return fl[FLAG_NBUILDS] > 0;
-    return mode == LISTS_ALL || mode == r;
-}
-
-// Exclusive scan of count[0..m) into start[0..m) by one workgroup of kBlock
-// threads (count may be start; it is read through volatile loads, as other
-// workgroups wrote it); returns the total to every thread.
-__device__ int block_scan(const int32_t *count, int32_t *start, int m, int *part)
-{
-    const volatile int32_t *vc = count;
-    const int t = threadIdx.x;
-    const int per = (m + kBlock - 1) / kBlock;
-    const int lo = min(t * per, m), hi = min(lo + per, m);
-    int sum = 0;
-    for (int c = lo; c < hi; ++c) sum += vc[c];
-    part[t] = sum;
-    __syncthreads();
-    for (int off = 1; off < kBlock; off <<= 1) {
-        const int v = (t >= off) ? part[t - off] : 0;
-        __syncthreads();
-        part[t] += v;
-        __syncthreads();
-    }
-    int run = part[t] - sum;
-    for (int c = lo; c < hi; ++c) {
-        const int cnt = vc[c];
-        start[c] = run;
-        run += cnt;
-    }
-    const int total = part[kBlock - 1];
-    __syncthreads();
-    return total;
-}
+using lb::kNbrPer;
 
 // Cells from the current positions (builds outside a step).
 __global__ void __launch_bounds__(kBlock) k_assign(BatchParams b, const SysParams *reps, StatePtrs s, ListPtrs l,
@@ -108,196 +40,44 @@ __global__ void __launch_bounds__(kBlock) k_assign(BatchParams b, const SysParam
     const int r = __builtin_amdgcn_readfirstlane(c < b.nchunk ? l.chunk_rep[c] : -1);
     if (r < 0) return;
     const SysParams &p = reps[r];
-    if (!building(mode, r, p, l.flags + r * FLAG_COUNT, budget) || i >= p.off + p.n) return;
-    if (i == p.off) l.flags[r * FLAG_COUNT + FLAG_NPAIRS] = 0;  // k_nbr adds the replica's pairs
+    if (!lb::building(mode, r, p, l.flags + r * FLAG_COUNT, budget) || i >= p.off + p.n) return;
+    if (i == p.off) l.flags[r * FLAG_COUNT + FLAG_NEWPAIRS] = 0;  // the row workgroups add the replica's pairs
     cell_insert(p, l, i, s.x[i], s.y[i], p.dim == 3 ? s.z[i] : 0.0);
 }
 
-// Neighbour rows: 16 lanes per particle, 16 particles per block (all of one
-// chunk, so of one replica).  Each lane scans some of the neighbour cells
-// (or, without cells, a sixteenth of the replica); hits are appended to the
-// particle's LDS buffer in ballot order, then every kept hit finds its rank
-// (the number of smaller hits) and is stored in that row slot, so the row
-// ascends and keeps the cap smallest j.  The row's count of j > i is the
-// particle's pair count; the block stores its total and adds it to the
-// replica's (FLAG_NPAIRS, cleared when the build starts).
+// Neighbour rows (lb::nbr_rows), one wavefront per 4 particles.
 template <int DIM>
-__global__ void __launch_bounds__(kBlock) k_nbr(BatchParams b, const SysParams *reps, StatePtrs s, ListPtrs l,
-                                                   const int64_t *budget, int mode)
+__global__ void __launch_bounds__(64) k_nbr(BatchParams b, const SysParams *reps, StatePtrs s, ListPtrs l,
+                                               const int64_t *budget, int mode)
 {
-    __shared__ int buf[kNbrPer][kRowMax];
-    __shared__ int part[kBlock];
-    if (mode == LISTS_STEP && l.gflags[G_ANY] == 0) return;
-    const int base = blockIdx.x * kNbrPer;
-    const int r = l.chunk_rep[base / kChunk];
+    __shared__ int buf[kNbrPer * kRowMax];
+    const int vb = blockIdx.x;
+    const int r = l.chunk_rep[vb * kNbrPer / kChunk];
     if (r < 0) return;
     const SysParams &p = reps[r];
     int32_t *fl = l.flags + r * FLAG_COUNT;
-    if (!building(mode, r, p, fl, budget)) return;
-    const int g = threadIdx.x / kNbrLanes, sub = threadIdx.x % kNbrLanes;
-    const int i = base + g;
-    const bool mine = i < p.off + p.n;
-    const unsigned long long gmask = 0xffffull << (kNbrLanes * ((threadIdx.x & 63) / kNbrLanes));
-    const unsigned long long below = lanes_below();
-    const double xi = mine ? s.x[i] : 0.0, yi = mine ? s.y[i] : 0.0, zi = (mine && DIM == 3) ? s.z[i] : 0.0;
-    int m = 0;  // hits so far (the same in all lanes of the particle)
-    if (p.use_cells) {
-        const int c = mine ? l.pcell[i] : 0;
-        const int cx = c % p.nc[0], cy = (c / p.nc[0]) % p.nc[1], cz = c / (p.nc[0] * p.nc[1]);
-        constexpr int kNb = DIM == 3 ? 27 : 9;
-        for (int t0 = 0; t0 < kNb; t0 += kNbrLanes) {
-            const int t = t0 + sub;
-            int cc = 0, cnt = 0;
-            if (mine && t < kNb) {
-                int ax = cx + t % 3 - 1, ay = cy + (t / 3) % 3 - 1, az = cz + (DIM == 3 ? t / 9 - 1 : 0);
-                ax += (ax < 0) ? p.nc[0] : 0;
-                ax -= (ax >= p.nc[0]) ? p.nc[0] : 0;
-                ay += (ay < 0) ? p.nc[1] : 0;
-                ay -= (ay >= p.nc[1]) ? p.nc[1] : 0;
-                az += (az < 0) ? p.nc[2] : 0;
-                az -= (az >= p.nc[2]) ? p.nc[2] : 0;
-                cc = p.coff + ax + p.nc[0] * (ay + p.nc[1] * az);
-                cnt = min(l.cell_count[cc], kCellCap);
-            }
-            for (int k = 0;; ++k) {
-                const bool has = k < cnt;
-                if (__ballot(has) == 0) break;
-                int j = 0;
-                bool hit = false;
-                if (has) {
-                    j = l.cell_slot[(size_t)cc * kCellCap + k];
-                    hit = j != i && within(p, s, xi, yi, zi, j);
-                }
-                const unsigned long long hm = __ballot(hit);
-                const int pos = m + __popcll(hm & below & gmask);
-                if (hit && pos < kRowMax) buf[g][pos] = j;
-                m += __popcll(hm & gmask);
-            }
-        }
-    } else {
-        for (int k0 = 0; k0 < p.n; k0 += kNbrLanes) {
-            const int j = p.off + k0 + sub;
-            const bool hit = mine && k0 + sub < p.n && j != i && within(p, s, xi, yi, zi, j);
-            const unsigned long long hm = __ballot(hit);
-            const int pos = m + __popcll(hm & below & gmask);
-            if (hit && pos < kRowMax) buf[g][pos] = j;
-            m += __popcll(hm & gmask);
-        }
-    }
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-    const size_t N = (size_t)b.N;
-    const int cap = b.cap;
-    const int mm = min(m, kRowMax);
-    int lower = 0;  // kept hits below i
-    if (mine)
-        for (int e = sub; e < mm; e += kNbrLanes) {
-            const int v = buf[g][e];
-            int rank = 0;
-            for (int f = 0; f < mm; ++f) rank += buf[g][f] < v ? 1 : 0;
-            if (rank < cap) {
-                l.nbr[(size_t)rank * N + i] = v;
-                lower += v < i ? 1 : 0;
-            }
-        }
-    for (int off = kNbrLanes / 2; off > 0; off >>= 1) lower += __shfl_xor(lower, off, kNbrLanes);
-    const int kept = min(m, cap);
-    if (mine && sub == 0) {
-        l.n_nbr[i] = kept;
-        l.klo[i] = lower;
-        l.pstart[i] = kept - lower;  // pair count; k_fill turns it into an offset
-        if (m > cap) atomicMax(&fl[FLAG_MAXROW], m);
-        l.xlast[i] = xi;
-        l.xlast[N + i] = yi;
-        l.xlast[2 * N + i] = zi;
-    }
-    // the block's pair count, for k_fill's offsets and (an integer sum, in
-    // any order) the replica's total
-    part[threadIdx.x] = (mine && sub == 0) ? kept - lower : 0;
-    __syncthreads();
-    for (int off = kBlock / 2; off > 0; off >>= 1) {
-        if (threadIdx.x < off) part[threadIdx.x] += part[threadIdx.x + off];
-        __syncthreads();
-    }
-    if (threadIdx.x == 0) {
-        l.ptot[blockIdx.x] = part[0];
-        atomicAdd(&fl[FLAG_NPAIRS], part[0]);
-    }
+    if (!lb::building(mode, r, p, fl, budget)) return;
+    lb::nbr_rows<DIM>(b, p, s, l, fl, vb, buf);
 }
 
-// Pair entries: the owner i of pair q writes {i, j, slot of j in i's row,
-// slot of i in j's row} with one store, the last found by bisection in j's
-// row (-1 if a row overflow left i out of it, which is reported).
-__device__ inline void pair_fill(const SysParams &p, const BatchParams &b, const ListPtrs &l, int i)
-{
-    const size_t N = (size_t)b.N;
-    const int m = min(l.n_nbr[i], b.cap), k0 = max(l.klo[i], 0);
-    int4 *pairs = l.pairs + p.poff;
-    for (int k = k0; k < m; ++k) {
-        const int q = l.pstart[i] + (k - k0);
-        if (q >= p.pcap) break;  // (only after a row overflow, which is reported)
-        const int j = l.nbr[(size_t)k * N + i];
-        int lo = 0, hi = l.klo[j];  // j's neighbours below j, ascending
-        while (lo < hi) {
-            const int mid = (lo + hi) >> 1;
-            if (l.nbr[(size_t)mid * N + j] < i) lo = mid + 1;
-            else hi = mid;
-        }
-        const int w = (lo < l.klo[j] && l.nbr[(size_t)lo * N + j] == i) ? lo : -1;
-        pairs[q] = make_int4(i, j, k, w);
-    }
-}
-
-// Tile plan: the first tile of each replica (b.tile pairs per tile), by one
-// workgroup.
-__device__ void plan(const BatchParams &b, const SysParams *reps, const ListPtrs &l, int *part)
-{
-    const volatile int32_t *vfl = l.flags;
-    for (int r = threadIdx.x; r < b.nrep; r += blockDim.x) {
-        const int np = min(vfl[r * FLAG_COUNT + FLAG_NPAIRS], reps[r].pcap);  // (above pcap only after an overflow)
-        l.flags[r * FLAG_COUNT + FLAG_NPAIRS] = np;
-        l.tile_start[r] = reps[r].live ? (np + b.tile - 1) / b.tile : 0;
-    }
-    __syncthreads();
-    const int total = block_scan(l.tile_start, l.tile_start, b.nrep, part);
-    if (threadIdx.x == 0) l.tile_start[b.nrep] = total;
-}
-
+// Pair offsets and entries (lb::fill_chunk), one wavefront per chunk; block
+// 0 first recomputes the tile plan.
 __global__ void __launch_bounds__(kBlock) k_fill(BatchParams b, const SysParams *reps, ListPtrs l,
                                                     const int64_t *budget, int mode, int clear_cells)
 {
     __shared__ int part[kBlock];
-    if (mode == LISTS_STEP && l.gflags[G_ANY] == 0) return;
-    if (blockIdx.x == 0) plan(b, reps, l, part);
+    if (blockIdx.x == 0)
+        lb::plan<kBlock>(b, reps, l, part, [&](int r) {
+            return mode != LISTS_PLAN && mode != LISTS_REFILL &&
+                   lb::building(mode, r, reps[r], l.flags + r * FLAG_COUNT, budget);
+        });
     if (mode == LISTS_PLAN) return;
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    const int c = i / kChunk;
+    const int c = (int)((blockIdx.x * blockDim.x + threadIdx.x) / kChunk);
     const int r = __builtin_amdgcn_readfirstlane(c < b.nchunk ? l.chunk_rep[c] : -1);
     if (r < 0) return;
     const SysParams &p = reps[r];
-    if (!building(mode, r, p, l.flags + r * FLAG_COUNT, budget)) return;
-    const bool mine = i < p.off + p.n;
-    if (mode != LISTS_REFILL) {
-        // pair offset of i: the counts of the replica's k_nbr blocks before
-        // this chunk, plus the counts of the chunk's particles before i (one
-        // wavefront is one chunk)
-        const int lane = __lane_id();
-        const int cnt = mine ? l.pstart[i] : 0;
-        int incl = cnt;
-        for (int off = 1; off < 64; off <<= 1) {
-            const int v = __shfl_up(incl, off, 64);
-            if (lane >= off) incl += v;
-        }
-        int prior = 0;
-#pragma unroll 8
-        for (int q = p.off / kNbrPer + lane; q < c * (kChunk / kNbrPer); q += 64) prior += l.ptot[q];
-        for (int off = 32; off > 0; off >>= 1) prior += __shfl_xor(prior, off, 64);
-        if (mine) l.pstart[i] = prior + incl - cnt;
-    }
-    if (!mine) return;
-    pair_fill(p, b, l, i);
-    if (clear_cells && p.use_cells) l.cell_count[p.coff + l.pcell[i]] = 0;  // every particle of the cell writes the same zero
+    if (!lb::building(mode, r, p, l.flags + r * FLAG_COUNT, budget)) return;
+    lb::fill_chunk(b, p, l, c, mode == LISTS_REFILL, clear_cells != 0);
 }
 
 }  // namespace
@@ -314,10 +94,10 @@ void launch_lists(const Launch &L, int mode, hipStream_t stream)
         k_fill<<<nb, kBlock, 0, stream>>>(L.b, L.reps, L.l, L.budget, LISTS_REFILL, 0);
         return;
     }
-    if (mode != LISTS_STEP) k_assign<<<nb, kBlock, 0, stream>>>(L.b, L.reps, L.s, L.l, L.budget, mode);
+    k_assign<<<nb, kBlock, 0, stream>>>(L.b, L.reps, L.s, L.l, L.budget, mode);
     const int nbn = L.b.nchunk * (kChunk / kNbrPer);
-    if (L.b.dim == 3) k_nbr<3><<<nbn, kBlock, 0, stream>>>(L.b, L.reps, L.s, L.l, L.budget, mode);
-    else k_nbr<2><<<nbn, kBlock, 0, stream>>>(L.b, L.reps, L.s, L.l, L.budget, mode);
+    if (L.b.dim == 3) k_nbr<3><<<nbn, 64, 0, stream>>>(L.b, L.reps, L.s, L.l, L.budget, mode);
+    else k_nbr<2><<<nbn, 64, 0, stream>>>(L.b, L.reps, L.s, L.l, L.budget, mode);
     k_fill<<<nb, kBlock, 0, stream>>>(L.b, L.reps, L.l, L.budget, mode, 1);
 }
 

@@ -614,7 +614,7 @@ dem_status alloc_core(dem_system *h, int Ncap, int Ccap, int Scap, int Rcap)
               hipMalloc(&h->lst.xlast, sizeof(double) * 3 * N) == hipSuccess &&
               hipMalloc(&h->lst.klo, sizeof(int32_t) * N) == hipSuccess &&
               hipMalloc(&h->lst.pstart, sizeof(int32_t) * N) == hipSuccess &&
-              hipMalloc(&h->lst.ptot, sizeof(int32_t) * (N / 16 + 1)) == hipSuccess &&
+              hipMalloc(&h->lst.ptot, sizeof(int32_t) * (N / lb_rows_per_group + 1)) == hipSuccess &&
               hipMalloc(&h->rot, partrec_bytes(h->precision) * N) == hipSuccess &&
               (h->precision != DEM_FP32 || hipMalloc(&h->rec64, sizeof(PartRec64) * N) == hipSuccess);
     if (!ok) return fail(h, DEM_E_OOM, "device allocation failed");
@@ -642,7 +642,7 @@ dem_status alloc_core(dem_system *h, int Ncap, int Ccap, int Scap, int Rcap)
     HIPCHK(h, hipMemsetAsync(h->lst.n_nbr, 0, sizeof(int32_t) * N, h->stream));
     HIPCHK(h, hipMemsetAsync(h->lst.klo, 0, sizeof(int32_t) * N, h->stream));
     HIPCHK(h, hipMemsetAsync(h->lst.pstart, 0, sizeof(int32_t) * N, h->stream));
-    HIPCHK(h, hipMemsetAsync(h->lst.ptot, 0, sizeof(int32_t) * (N / 16 + 1), h->stream));
+    HIPCHK(h, hipMemsetAsync(h->lst.ptot, 0, sizeof(int32_t) * (N / lb_rows_per_group + 1), h->stream));
     HIPCHK(h, hipMemsetAsync(h->lst.pcell, 0, sizeof(int32_t) * N, h->stream));
     HIPCHK(h, hipMemsetAsync(h->stats, 0, sizeof(unsigned long long) * ST_COUNT, h->stream));
     HIPCHK(h, hipMemsetAsync(h->ke_part, 0, sizeof(double) * 2 * nch, h->stream));
@@ -691,7 +691,6 @@ void enqueue_step(dem_system *h, hipStream_t s)
 {
     const Launch L = make_launch(h);
     launch_kick_drift(L, s);
-    launch_lists(L, LISTS_STEP, s);
     launch_pairs(L, h->counting ? h->stats : nullptr, s);
     launch_gather(L, true, s);
 }
