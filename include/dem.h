@@ -251,23 +251,28 @@ dem_status dem_time_forces(dem_handle h, int32_t reps, double *mean_ms);
  * bit for bit): lanes_per_pair (8 or 16) lanes evaluate one particle pair in
  * the feature stage, so a 64-lane wavefront takes 8 or 4 pairs at a time;
  * the grid holds grid_factor (1 to 4) times as many workgroups as the
- * device keeps resident at once; and the kernel is compiled for
- * waves_per_simd (2 or 3) resident wavefronts per SIMD (3 overlaps more
- * memory round trips, 2 gives the compiler more registers).  The default
- * is {16, 1, 2}.  The next dem_step captures its graph again.  DEM_E_ARG
- * for other values. */
-enum { DEM_PAIR_SHAPES = 8 };
-dem_status dem_set_pair_shape(dem_handle h, int32_t lanes_per_pair, int32_t grid_factor, int32_t waves_per_simd);
+ * device keeps resident at once; the kernel is compiled for waves_per_simd
+ * (2 or 3) resident wavefronts per SIMD (3 overlaps more memory round
+ * trips, 2 gives the compiler more registers); and sep_lanes (4, or 16 with
+ * 16 lanes per pair) lanes take one pair in the separation stage, so a
+ * wavefront settles 16 or 4 pairs at a time and a tile holds 64 or 16
+ * pairs (16 spreads a small system over four times the wavefronts).  The
+ * default is {16, 1, 2, 4}.  The next dem_step captures its graph again.
+ * DEM_E_ARG for other values. */
+enum { DEM_PAIR_SHAPES = 12 };
+dem_status dem_set_pair_shape(dem_handle h, int32_t lanes_per_pair, int32_t grid_factor, int32_t waves_per_simd,
+                              int32_t sep_lanes);
 
 /* Pair-shape autotuner: times `reps` launches of the pair kernel on the
  * current state for each of the DEM_PAIR_SHAPES shapes {lanes, factor,
- * waves} = {16,1,2}, {8,1,2}, {16,2,2}, {8,2,2}, {16,1,3}, {8,1,3},
- * {16,2,3}, {8,2,3} (HIP events on the handle's stream) and keeps the
- * fastest.  Outputs (each may be null): shape[3] receives the chosen
- * {lanes, factor, waves}, mean_ms[DEM_PAIR_SHAPES] the mean launch time in
- * ms of every shape, in that order.  The state and lists are not changed;
- * the records of the pair kernel are overwritten by the next step as
- * always.  Synchronises. */
+ * waves, sep} = {16,1,2,4}, {8,1,2,4}, {16,2,2,4}, {8,2,2,4}, {16,1,3,4},
+ * {8,1,3,4}, {16,2,3,4}, {8,2,3,4}, {16,1,2,16}, {16,2,2,16}, {16,1,3,16},
+ * {16,2,3,16} (HIP events on the handle's stream) and keeps the fastest.
+ * Outputs (each may be null): shape[4] receives the chosen {lanes, factor,
+ * waves, sep}, mean_ms[DEM_PAIR_SHAPES] the mean launch time in ms of every
+ * shape, in that order.  The state and lists are not changed; the records
+ * of the pair kernel are overwritten by the next step as always.
+ * Synchronises. */
 dem_status dem_tune_pairs(dem_handle h, int32_t reps, int32_t *shape, double *mean_ms);
 
 /* Bytes of device memory the library would allocate for these parameters

@@ -562,19 +562,16 @@ struct alignas(16) QEnt {
     T Ri[9];     // R_i, body to space
     T d[3];      // minimum-image x_j - x_i
 };
-// The separation stage takes kSepLanes lanes per pair, so a wavefront
-// settles kPairsPerWave pairs at a time whatever the feature stage's lane
-// count; a tile is kPairWaves * kPairsPerWave pairs.
-constexpr int kSepLanes = 4;
-constexpr int kPairsPerWave = 64 / kSepLanes;
-static_assert(kPairWaves * kPairsPerWave == pair_tile(), "tile size");
-// queue slots per wave: one separation tile adds at most kPairsPerWave
+// The separation stage takes SL lanes per pair, so a wavefront settles
+// 64 / SL pairs at a time whatever the feature stage's lane count; a tile
+// is kPairWaves * 64 / SL pairs.
+// queue slots per wave: one separation tile adds at most 64 / SL
 // entries to fewer than one per feature-stage group already waiting
-constexpr int queue_slots(int lanes) { return kPairsPerWave + 64 / lanes; }
+constexpr int queue_slots(int sep, int lanes) { return 64 / sep + 64 / lanes; }
 
-// One block of 4 waves takes a contiguous range of tiles (64 pairs of one
-// replica each; wave w takes pairs 16w..16w+15 of a tile in the first
-// stage).
+// One block of 4 waves takes a contiguous range of tiles (64 or 16 pairs
+// of one replica each; wave w takes pairs (64 / SL) w .. (64 / SL)(w + 1)
+// - 1 of a tile in the first stage).
 // Blocks are dealt round-robin to the 8 XCDs, so block b runs on XCD b % 8:
 // XCD x gets the x-th eighth of the tiles, and pairs of neighbouring
 // particles share its L2.  The tables of the block's current replica live
@@ -609,7 +606,7 @@ struct Tally<false> {
 // the compiler must fit 168 registers and schedules with less freedom.  The
 // uncounted variants fit without spilling because the feature stage reads
 // the pair's transform from the LDS queue instead of holding it.
-template <typename T, int DIM, int GL, bool COUNT, int OCC>
+template <typename T, int DIM, int GL, bool COUNT, int OCC, int SL>
 __global__ void __launch_bounds__(64 * kWaves, OCC) k_pairs(BatchParams b, const SysParams *__restrict__ reps, StatePtrs s,
                                                           ListPtrs l, const PartRec<T> *__restrict__ prec,
                                                           const PartRec64 *__restrict__ rec64,
@@ -619,10 +616,13 @@ __global__ void __launch_bounds__(64 * kWaves, OCC) k_pairs(BatchParams b, const
 {
     static_assert(GL == 8 || GL == 16, "8 or 16 lanes per pair");
     static_assert(OCC == 2 || OCC == 3, "2 or 3 wavefronts per SIMD");
+    static_assert(SL == 4 || SL == 16, "4 or 16 lanes per pair in the separation stage");
+    constexpr int kSepLanes = SL;
+    constexpr int kPairsPerWave = 64 / SL;
     constexpr int kGL = GL;                                    // lanes per particle pair
     constexpr int kGroups = 64 / kGL;                         // pairs per wave in the feature stage
     constexpr int kTile = kWaves * kPairsPerWave;             // pairs per block tile
-    constexpr int kQCap = queue_slots(kGL);
+    constexpr int kQCap = queue_slots(SL, kGL);
     constexpr int kVP = (DEM_MAX_VERTS + kSepLanes - 1) / kSepLanes;  // vertices per lane in the separation test
     constexpr int kSets = kVirt / kGL;                        // partial sums per lane
     extern __shared__ __align__(16) unsigned char smem[];
@@ -1477,31 +1477,35 @@ __global__ void k_rotations(BatchParams b, const SysParams *reps, StatePtrs s, L
     if (sizeof(T) == 4) rec64[i] = PartRec64{rc.x, rc.y, rc.z, s.qw[i], s.qx[i], s.qy[i], s.qz[i], 0.0};
 }
 
-template <typename T, int DIM, int GL, int OCC>
+template <typename T, int DIM, int GL, int OCC, int SL>
 void pairs_t(const Launch &L, unsigned long long *stats, hipStream_t stream);
 
+// The compiled shapes: {8, 16} lanes per pair x {2, 3} wavefronts per SIMD
+// with the 4-lane separation stage, and 16 lanes x {2, 3} with the 16-lane
+// one.
 template <typename T, int DIM>
 void pairs_shape(const Launch &L, unsigned long long *stats, hipStream_t stream)
 {
     const bool g8 = L.b.pair_lanes == 8, o3 = L.b.pair_waves == 3;
-    if (g8) o3 ? pairs_t<T, DIM, 8, 3>(L, stats, stream) : pairs_t<T, DIM, 8, 2>(L, stats, stream);
-    else o3 ? pairs_t<T, DIM, 16, 3>(L, stats, stream) : pairs_t<T, DIM, 16, 2>(L, stats, stream);
+    if (L.b.pair_sep == 16) o3 ? pairs_t<T, DIM, 16, 3, 16>(L, stats, stream) : pairs_t<T, DIM, 16, 2, 16>(L, stats, stream);
+    else if (g8) o3 ? pairs_t<T, DIM, 8, 3, 4>(L, stats, stream) : pairs_t<T, DIM, 8, 2, 4>(L, stats, stream);
+    else o3 ? pairs_t<T, DIM, 16, 3, 4>(L, stats, stream) : pairs_t<T, DIM, 16, 2, 4>(L, stats, stream);
 }
 
-template <typename T, int DIM, int GL, int OCC>
+template <typename T, int DIM, int GL, int OCC, int SL>
 void pairs_t(const Launch &L, unsigned long long *stats, hipStream_t stream)
 {
-    const size_t sh = pair_kernel_lds(sizeof(T) == 4 ? DEM_FP32 : DEM_FP64, L.b.tab_slots, GL);
+    const size_t sh = pair_kernel_lds(sizeof(T) == 4 ? DEM_FP32 : DEM_FP64, L.b.tab_slots, GL, SL);
     const int grid = L.b.pair_blocks;
     const auto rot = reinterpret_cast<const PartRec<T> *>(L.f.rot);
     const auto rec = reinterpret_cast<SlotRec<T> *>(L.f.rec);
     const auto tab = reinterpret_cast<const ShapeTab<T> *>(L.f.tab);
     const auto tab64 = reinterpret_cast<const ShapeTab<double> *>(L.f.tab64);
     if (stats)
-        k_pairs<T, DIM, GL, true, OCC><<<grid, 64 * kWaves, sh, stream>>>(L.b, L.reps, L.s, L.l, rot, L.f.rec64, rec,
+        k_pairs<T, DIM, GL, true, OCC, SL><<<grid, 64 * kWaves, sh, stream>>>(L.b, L.reps, L.s, L.l, rot, L.f.rec64, rec,
                                                                            tab, tab64, stats);
     else
-        k_pairs<T, DIM, GL, false, OCC><<<grid, 64 * kWaves, sh, stream>>>(L.b, L.reps, L.s, L.l, rot, L.f.rec64, rec,
+        k_pairs<T, DIM, GL, false, OCC, SL><<<grid, 64 * kWaves, sh, stream>>>(L.b, L.reps, L.s, L.l, rot, L.f.rec64, rec,
                                                                             tab, tab64, nullptr);
 }
 
@@ -1558,39 +1562,43 @@ void launch_gather(const Launch &L, bool kick, hipStream_t stream)
     }
 }
 
-size_t pair_kernel_lds(int precision, int tab_slots, int lanes)
+size_t pair_kernel_lds(int precision, int tab_slots, int lanes, int sep)
 {
     const size_t w = precision == DEM_FP32 ? sizeof(ShapeTab<float>) : sizeof(ShapeTab<double>);
     const size_t pl = precision == DEM_FP32 ? sizeof(PairLds<float>) : sizeof(PairLds<double>);
     const size_t qe = precision == DEM_FP32 ? sizeof(QEnt<float>) : sizeof(QEnt<double>);
     const size_t acc = precision == DEM_FP32 ? sizeof(Acc<float>) : sizeof(Acc<double>);
-    return (size_t)tab_slots * w + sizeof(RepLds) + kWaves * (64 / lanes) * pl + kWaves * queue_slots(lanes) * qe +
+    return (size_t)tab_slots * w + sizeof(RepLds) + kWaves * (64 / lanes) * pl + kWaves * queue_slots(sep, lanes) * qe +
            (lanes == 16 ? kWaves * 64 * acc : 0);
 }
 
 namespace {
 template <typename T, int DIM>
-hipError_t pair_occupancy(int *per_cu, size_t lds, int lanes, int waves)
+hipError_t pair_occupancy(int *per_cu, size_t lds, int lanes, int waves, int sep)
 {
     const int t = 64 * kWaves;
+    if (sep == 16)
+        return waves == 3 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, k_pairs<T, DIM, 16, false, 3, 16>, t, lds)
+                          : hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, k_pairs<T, DIM, 16, false, 2, 16>, t, lds);
     if (lanes == 8)
-        return waves == 3 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, k_pairs<T, DIM, 8, false, 3>, t, lds)
-                          : hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, k_pairs<T, DIM, 8, false, 2>, t, lds);
-    return waves == 3 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, k_pairs<T, DIM, 16, false, 3>, t, lds)
-                      : hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, k_pairs<T, DIM, 16, false, 2>, t, lds);
+        return waves == 3 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, k_pairs<T, DIM, 8, false, 3, 4>, t, lds)
+                          : hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, k_pairs<T, DIM, 8, false, 2, 4>, t, lds);
+    return waves == 3 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, k_pairs<T, DIM, 16, false, 3, 4>, t, lds)
+                      : hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, k_pairs<T, DIM, 16, false, 2, 4>, t, lds);
 }
 }  // namespace
 
-int pair_blocks_resident(int precision, int dim, int tab_slots, int lanes, int waves)
+int pair_blocks_resident(int precision, int dim, int tab_slots, int lanes, int waves, int sep)
 {
-    const size_t lds = pair_kernel_lds(precision, tab_slots, lanes);
+    const size_t lds = pair_kernel_lds(precision, tab_slots, lanes, sep);
     int per_cu = 0, cus = 0, dev = 0;
     hipError_t e;
     if (precision == DEM_FP32)
-        e = dim == 3 ? pair_occupancy<float, 3>(&per_cu, lds, lanes, waves) : pair_occupancy<float, 2>(&per_cu, lds, lanes, waves);
+        e = dim == 3 ? pair_occupancy<float, 3>(&per_cu, lds, lanes, waves, sep)
+                     : pair_occupancy<float, 2>(&per_cu, lds, lanes, waves, sep);
     else
-        e = dim == 3 ? pair_occupancy<double, 3>(&per_cu, lds, lanes, waves)
-                     : pair_occupancy<double, 2>(&per_cu, lds, lanes, waves);
+        e = dim == 3 ? pair_occupancy<double, 3>(&per_cu, lds, lanes, waves, sep)
+                     : pair_occupancy<double, 2>(&per_cu, lds, lanes, waves, sep);
     if (e != hipSuccess || hipGetDevice(&dev) != hipSuccess ||
         hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
         return 512;

@@ -22,10 +22,15 @@ constexpr int kChunk = 64;
 // (BatchParams::pair_lanes, chosen by the pair-shape tuner).  A tile is what
 // one workgroup takes at a time (16 pairs per wavefront), and tiles never
 // straddle replicas.
+// The separation stage takes sep_lanes lanes per pair (4: 16 pairs per
+// wavefront; 16: 4 pairs per wavefront, which spreads a small system's
+// pairs over four times the wavefronts), so a tile is kPairWaves * 64 /
+// sep_lanes pairs.
 constexpr int kPairWaves = 4;
 constexpr int kDefaultPairLanes = 16;
 constexpr int kDefaultPairWaves = 2;
-constexpr int pair_tile() { return kPairWaves * 16; }
+constexpr int kDefaultPairSep = 4;
+__host__ __device__ constexpr int pair_tile(int sep_lanes) { return kPairWaves * (64 / sep_lanes); }
 
 // Per-replica device flag words (flags[r * FLAG_COUNT + w], one 64-byte
 // line per replica).  FLAG_TRIGGER: some particle has moved far enough
@@ -169,7 +174,8 @@ struct BatchParams {
     int pair_blocks;             // grid of the pair kernel (a multiple of 8)
     int pair_lanes;              // lanes per particle pair in the pair kernel (8 or 16)
     int pair_waves;              // its wavefronts per SIMD (2 or 3)
-    int tile;                    // pairs per tile: pair_tile()
+    int pair_sep;                // lanes per pair in its separation stage (4 or 16)
+    int tile;                    // pairs per tile: pair_tile(pair_sep)
     int dim;
 };
 
@@ -291,8 +297,8 @@ __device__ inline void cell_insert(const SysParams &p, const ListPtrs &l, int i,
 
 // Dynamic LDS of the pair kernel, and how many of its blocks the device
 // holds at once.
-size_t pair_kernel_lds(int precision, int tab_slots, int lanes);
-int pair_blocks_resident(int precision, int dim, int tab_slots, int lanes, int waves);
+size_t pair_kernel_lds(int precision, int tab_slots, int lanes, int sep);
+int pair_blocks_resident(int precision, int dim, int tab_slots, int lanes, int waves, int sep);
 
 // Per-particle records (position, rotation, shape id) from the state arrays.
 void launch_rotations(const Launch &L, hipStream_t stream);

@@ -82,7 +82,8 @@ struct dem_system {
     bool counting = false;
     int pair_lanes = kDefaultPairLanes;  // pair-kernel shape: lanes per pair,
     int pair_grid = 1;                   // blocks per resident block slot
-    int pair_waves = kDefaultPairWaves;  // and wavefronts per SIMD
+    int pair_waves = kDefaultPairWaves;  // wavefronts per SIMD
+    int pair_sep = kDefaultPairSep;      // and lanes per pair of its separation stage
     BatchParams bp{};
     std::vector<Replica> reps;
     SlotArena chunks, cells, shapes;
@@ -486,7 +487,8 @@ void refresh_batch(dem_system *h)
     b.tab_slots = 1;
     b.pair_lanes = h->pair_lanes;
     b.pair_waves = h->pair_waves;
-    b.tile = pair_tile();
+    b.pair_sep = h->pair_sep;
+    b.tile = pair_tile(h->pair_sep);
     long long tiles = 0;
     for (size_t r = 0; r < h->reps.size(); ++r) {
         const Replica &R = h->reps[r];
@@ -501,7 +503,8 @@ void refresh_batch(dem_system *h)
     // (a second round adds a whole block's latency but evens out the
     // tail), no more than the tiles use
     const long long resident =
-        (long long)pair_blocks_resident(h->precision, h->dim, b.tab_slots, b.pair_lanes, b.pair_waves) * h->pair_grid;
+        (long long)pair_blocks_resident(h->precision, h->dim, b.tab_slots, b.pair_lanes, b.pair_waves, b.pair_sep) *
+        h->pair_grid;
     const long long want = std::max<long long>(8, std::min<long long>(tiles, resident));
     b.pair_blocks = (int)((want + 7) / 8 * 8);
 }
@@ -1602,17 +1605,24 @@ dem_status dem_set_state(dem_handle h, const void *host_buf, size_t bytes)
     return latched(h);
 }
 
-dem_status dem_set_pair_shape(dem_handle h, int32_t lanes_per_pair, int32_t grid_factor, int32_t waves_per_simd)
+dem_status dem_set_pair_shape(dem_handle h, int32_t lanes_per_pair, int32_t grid_factor, int32_t waves_per_simd,
+                              int32_t sep_lanes)
 {
     if (!h) return fail(nullptr, DEM_E_ARG, "null handle");
     if ((lanes_per_pair != 8 && lanes_per_pair != 16) || grid_factor < 1 || grid_factor > 4 ||
-        (waves_per_simd != 2 && waves_per_simd != 3))
-        return fail(h, DEM_E_ARG, "pair shape: %d lanes per pair (8 or 16), grid factor %d (1 to 4), %d waves per SIMD "
-                    "(2 or 3)", lanes_per_pair, grid_factor, waves_per_simd);
-    if (lanes_per_pair == h->pair_lanes && grid_factor == h->pair_grid && waves_per_simd == h->pair_waves) return DEM_OK;
+        (waves_per_simd != 2 && waves_per_simd != 3) || (sep_lanes != 4 && sep_lanes != 16) ||
+        (sep_lanes == 16 && lanes_per_pair != 16))
+        return fail(h, DEM_E_ARG,
+                    "pair shape: %d lanes per pair (8 or 16), grid factor %d (1 to 4), %d waves per SIMD (2 or 3), "
+                    "%d separation lanes (4, or 16 with 16 lanes per pair)",
+                    lanes_per_pair, grid_factor, waves_per_simd, sep_lanes);
+    if (lanes_per_pair == h->pair_lanes && grid_factor == h->pair_grid && waves_per_simd == h->pair_waves &&
+        sep_lanes == h->pair_sep)
+        return DEM_OK;
     h->pair_lanes = lanes_per_pair;
     h->pair_grid = grid_factor;
     h->pair_waves = waves_per_simd;
+    h->pair_sep = sep_lanes;
     refresh_batch(h);
     launch_lists(make_launch(h), LISTS_PLAN, h->stream);  // tiles of the new size
     HIPCHK(h, hipGetLastError());
@@ -1623,12 +1633,13 @@ dem_status dem_set_pair_shape(dem_handle h, int32_t lanes_per_pair, int32_t grid
 dem_status dem_tune_pairs(dem_handle h, int32_t reps, int32_t *shape, double *mean_ms)
 {
     if (!h || reps < 1) return fail(h, DEM_E_ARG, "bad argument");
-    static const int kShapes[DEM_PAIR_SHAPES][3] = {{16, 1, 2}, {8, 1, 2}, {16, 2, 2}, {8, 2, 2},
-                                                    {16, 1, 3}, {8, 1, 3}, {16, 2, 3}, {8, 2, 3}};
+    static const int kShapes[DEM_PAIR_SHAPES][4] = {{16, 1, 2, 4},  {8, 1, 2, 4},  {16, 2, 2, 4},  {8, 2, 2, 4},
+                                                    {16, 1, 3, 4},  {8, 1, 3, 4},  {16, 2, 3, 4},  {8, 2, 3, 4},
+                                                    {16, 1, 2, 16}, {16, 2, 2, 16}, {16, 1, 3, 16}, {16, 2, 3, 16}};
     double best = 0.0;
     int pick = 0;
     for (int k = 0; k < DEM_PAIR_SHAPES; ++k) {
-        dem_status st = dem_set_pair_shape(h, kShapes[k][0], kShapes[k][1], kShapes[k][2]);
+        dem_status st = dem_set_pair_shape(h, kShapes[k][0], kShapes[k][1], kShapes[k][2], kShapes[k][3]);
         double ms = 0.0;
         if (st == DEM_OK) st = dem_time_forces(h, reps, &ms);
         if (st != DEM_OK) return st;
@@ -1638,10 +1649,10 @@ dem_status dem_tune_pairs(dem_handle h, int32_t reps, int32_t *shape, double *me
             pick = k;
         }
     }
-    dem_status st = dem_set_pair_shape(h, kShapes[pick][0], kShapes[pick][1], kShapes[pick][2]);
+    dem_status st = dem_set_pair_shape(h, kShapes[pick][0], kShapes[pick][1], kShapes[pick][2], kShapes[pick][3]);
     if (st != DEM_OK) return st;
     if (shape)
-        for (int a = 0; a < 3; ++a) shape[a] = kShapes[pick][a];
+        for (int a = 0; a < 4; ++a) shape[a] = kShapes[pick][a];
     return DEM_OK;
 }
 

@@ -123,7 +123,7 @@ def lib():
         L.dem_set_counting.restype = st
         L.dem_time_forces.argtypes = [C.c_void_p, C.c_int32, _dp]
         L.dem_time_forces.restype = st
-        L.dem_set_pair_shape.argtypes = [C.c_void_p, C.c_int32, C.c_int32, C.c_int32]
+        L.dem_set_pair_shape.argtypes = [C.c_void_p, C.c_int32, C.c_int32, C.c_int32, C.c_int32]
         L.dem_set_pair_shape.restype = st
         L.dem_tune_pairs.argtypes = [C.c_void_p, C.c_int32, _ip, _dp]
         L.dem_tune_pairs.restype = st
@@ -275,16 +275,17 @@ def _lists_np(call, n, ncell, cap):
                 nbr=nb[: cap * n].reshape(cap, n) if n else nb[:0].reshape(cap, 0), n_nbr=nn[:n])
 
 
-# the tuner's candidates (lanes per pair, grid factor, waves per SIMD), in dem_tune_pairs order
-PAIR_SHAPES = ((16, 1, 2), (8, 1, 2), (16, 2, 2), (8, 2, 2), (16, 1, 3), (8, 1, 3), (16, 2, 3), (8, 2, 3))
+# the tuner's candidates (lanes per pair, grid factor, waves per SIMD, separation lanes), in dem_tune_pairs order
+PAIR_SHAPES = ((16, 1, 2, 4), (8, 1, 2, 4), (16, 2, 2, 4), (8, 2, 2, 4), (16, 1, 3, 4), (8, 1, 3, 4), (16, 2, 3, 4),
+               (8, 2, 3, 4), (16, 1, 2, 16), (16, 2, 2, 16), (16, 1, 3, 16), (16, 2, 3, 16))
 
 
 def _tune_pairs(check, h, reps):
-    shape = (C.c_int32 * 3)()
+    shape = (C.c_int32 * 4)()
     ms = (C.c_double * len(PAIR_SHAPES))()
     check(lib().dem_tune_pairs(h, int(reps), shape, ms), "dem_tune_pairs")
-    return dict(lanes=shape[0], grid=shape[1], waves=shape[2],
-                mean_ms={f"{a}x{b}x{c}": ms[k] for k, (a, b, c) in enumerate(PAIR_SHAPES)})
+    return dict(lanes=shape[0], grid=shape[1], waves=shape[2], sep=shape[3],
+                mean_ms={"x".join(map(str, sh)): ms[k] for k, sh in enumerate(PAIR_SHAPES)})
 
 
 class DemSystem:
@@ -392,10 +393,11 @@ class DemSystem:
         self._check(lib().dem_get_outputs(self.h, C.byref(v)), "dem_get_outputs")
         return {name: getattr(v, name) for name, _ in OutputView._fields_}
 
-    def set_pair_shape(self, lanes: int, grid: int = 1, waves: int = 2):
-        """Pair-kernel launch shape (8 or 16 lanes per pair, grid factor 1..4, 2 or 3 waves per SIMD);
-        results do not change."""
-        self._check(lib().dem_set_pair_shape(self.h, int(lanes), int(grid), int(waves)), "dem_set_pair_shape")
+    def set_pair_shape(self, lanes: int, grid: int = 1, waves: int = 2, sep: int = 4):
+        """Pair-kernel launch shape (8 or 16 lanes per pair, grid factor 1..4, 2 or 3 waves per SIMD, 4 or 16
+        separation lanes); results do not change."""
+        self._check(lib().dem_set_pair_shape(self.h, int(lanes), int(grid), int(waves), int(sep)),
+                    "dem_set_pair_shape")
 
     def tune_pairs(self, reps: int = 20) -> dict:
         """Times every pair-kernel shape on the current state and keeps the fastest."""
@@ -552,8 +554,9 @@ class DemBatch:
     def set_counting(self, on: bool):
         self._check(lib().dem_set_counting(self.h, 1 if on else 0), "dem_set_counting")
 
-    def set_pair_shape(self, lanes: int, grid: int = 1, waves: int = 2):
-        self._check(lib().dem_set_pair_shape(self.h, int(lanes), int(grid), int(waves)), "dem_set_pair_shape")
+    def set_pair_shape(self, lanes: int, grid: int = 1, waves: int = 2, sep: int = 4):
+        self._check(lib().dem_set_pair_shape(self.h, int(lanes), int(grid), int(waves), int(sep)),
+                    "dem_set_pair_shape")
 
     def tune_pairs(self, reps: int = 5) -> dict:
         return _tune_pairs(self._check, self.h, reps)

@@ -1,4 +1,4 @@
-"""Pair-kernel launch shapes (lanes per pair, grid factor, waves per SIMD): every shape the
+"""Pair-kernel launch shapes (lanes per pair, grid factor, waves per SIMD, separation lanes): every shape the
 tuner can choose gives the same forces and the same trajectories bit for
 bit, and tuning leaves the state alone.  The per-pair sums are formed in a
 canonical order (problem k of a solve round into partial sum k mod 16, one
@@ -10,7 +10,8 @@ from paper_1607_02427_amd import inputs as I
 
 pytestmark = pytest.mark.gpu
 
-SHAPES = [(16, 1, 2), (8, 1, 2), (16, 2, 2), (8, 2, 2), (16, 1, 3), (8, 1, 3), (16, 2, 3), (8, 2, 3)]
+SHAPES = [(16, 1, 2, 4), (8, 1, 2, 4), (16, 2, 2, 4), (8, 2, 2, 4), (16, 1, 3, 4), (8, 1, 3, 4), (16, 2, 3, 4),
+          (8, 2, 3, 4), (16, 1, 2, 16), (16, 2, 2, 16), (16, 1, 3, 16), (16, 2, 3, 16)]
 
 CASES = {
     "cubes_contact_512": lambda: I.cubes_3d_contact(n_side=8),
@@ -45,9 +46,9 @@ def test_shapes_give_identical_forces(name, prec):
     s = CASES[name]()
     print(f"[shapes] {name} n={s.n} {prec}", flush=True)
     outs = []
-    for lanes, grid, waves in SHAPES:
+    for lanes, grid, waves, sep in SHAPES:
         with dem.DemSystem(s, prec) as g:
-            g.set_pair_shape(lanes, grid, waves)
+            g.set_pair_shape(lanes, grid, waves, sep)
             g.compute_forces()
             outs.append(g.outputs())
     for o in outs[1:]:
@@ -63,13 +64,14 @@ def test_shapes_give_identical_trajectories():
     s = I.cubes_3d(n_side=10)
     print(f"[shapes] cubes_1000 NVT 300 steps", flush=True)
     ends = []
-    for lanes, grid, waves in [(16, 1, 2), (8, 2, 3)]:
+    for lanes, grid, waves, sep in [(16, 1, 2, 4), (8, 2, 3, 4), (16, 1, 3, 16)]:
         with dem.DemSystem(s, "fp32") as g:
-            g.set_pair_shape(lanes, grid, waves)
+            g.set_pair_shape(lanes, grid, waves, sep)
             g.step(300)
             ends.append((_state_arrays(g.state()), g.energy()))
-    _same(ends[0][0], ends[1][0])
-    assert ends[0][1]["H"] == ends[1][1]["H"]
+    for e in ends[1:]:
+        _same(ends[0][0], e[0])
+        assert ends[0][1]["H"] == e[1]["H"]
 
 
 def test_tuner_keeps_state_and_results():
@@ -84,7 +86,7 @@ def test_tuner_keeps_state_and_results():
         before = _state_arrays(g.state())
         r = g.tune_pairs(3)
         print("tuned", r, flush=True)
-        assert (r["lanes"], r["grid"], r["waves"]) in SHAPES
+        assert (r["lanes"], r["grid"], r["waves"], r["sep"]) in SHAPES
         assert all(v > 0 for v in r["mean_ms"].values())
         _same(_state_arrays(g.state()), before)
         g.step(50)
