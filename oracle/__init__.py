@@ -84,6 +84,9 @@ def lib():
                                        _dp, _dp, C.POINTER(Stats), _dp]
         L.or_run.argtypes = [C.POINTER(_OrSys), C.c_int, _dp, _dp, _dp, _dp, _ip, _ip, C.c_int, C.c_double,
                              C.c_int, C.c_double, C.c_double, _dp, C.c_int, _dp, _dp, _dp, _dp, _dp]
+        L.or_run_npt.argtypes = [C.POINTER(_OrSys), C.c_int, _dp, _dp, _dp, _dp, _ip, _ip, C.c_int, C.c_double,
+                                 C.c_double, C.c_double, C.c_double, C.c_double, _dp, _dp, _dp, C.c_int, _dp, _dp,
+                                 _dp, _dp, _dp]
         L.or_set_threads.argtypes = [C.c_int]
         L.or_get_threads.restype = C.c_int
         _lib = L
@@ -309,6 +312,35 @@ def run(sysobj, n_steps, *, mode=1, thermo=None, log=True, threads: Optional[int
                  float(s.dt), ens, float(s.kT), float(s.tau_T), _d(th), int(mode), _d(F), _d(T), _d(U), _d(W),
                  _d(lg) if lg is not None else None)
     return s, th, (lg[:n_steps] if lg is not None else None), dict(F=F, T=T, U=U, W=W)
+
+
+def run_npt(sysobj, n_steps, *, mode=1, thermo=None, veps=0.0, log=True, threads: Optional[int] = None):
+    """Integrates a copy of the system at fixed pressure sysobj.P (barostat
+    time constant sysobj.tau_P, Sec. IV.C); returns (final system with its
+    box, thermo, v_eps, log, forces).  log rows: U, K_trans, K_rot, xi, eta,
+    H, V, P_int, v_eps."""
+    if threads:
+        lib().or_set_threads(int(threads))
+    s = sysobj.copy()
+    osys = OracleSystem.of(s)
+    n = s.n
+    for name in ("x", "q", "v", "L"):
+        setattr(s, name, np.ascontiguousarray(getattr(s, name), dtype=np.float64))
+    s.image = np.ascontiguousarray(s.image, dtype=np.int32)
+    sid = np.ascontiguousarray(s.shape_id, dtype=np.int32)
+    th = np.zeros(2) if thermo is None else np.asarray(thermo, np.float64).copy()
+    baro = np.array([float(veps)])
+    box = np.ascontiguousarray(s.box, dtype=np.float64).copy()
+    F = np.zeros((n, 3))
+    T = np.zeros((n, 3))
+    U = np.zeros(n)
+    W = np.zeros((n, 9))
+    lg = np.zeros((max(n_steps, 1), 9)) if log else None
+    lib().or_run_npt(C.byref(osys.c), int(n), _d(s.x), _d(s.q), _d(s.v), _d(s.L), _i(s.image), _i(sid),
+                     int(n_steps), float(s.dt), float(s.kT), float(s.tau_T), float(s.P), float(s.tau_P), _d(box),
+                     _d(th), _d(baro), int(mode), _d(F), _d(T), _d(U), _d(W), _d(lg) if lg is not None else None)
+    s.box = box
+    return s, th, float(baro[0]), (lg[:n_steps] if lg is not None else None), dict(F=F, T=T, U=U, W=W)
 
 
 def kinetic(sysobj):

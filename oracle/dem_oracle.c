@@ -803,6 +803,160 @@ void or_run(const or_sys *S, int n, double *x, double *q, double *v, double *L, 
     thermo[1] = eta;
 }
 
+/* ------------------------------------------------- isothermal-isobaric */
+/* Sec. IV.C runs the assembly at fixed pressure with a barostat that takes
+ * the pressure from the virial tensor and cites the measure-preserving
+ * isothermal-isobaric integrator of Tuckerman et al. (2006).  The reading
+ * used here (isotropic box, one Nose-Hoover variable on translation,
+ * rotation and the barostat):
+ *   d = dimension, N_f = d (N - 1), alpha = 1 + d / N_f,
+ *   W = (N_f + d) kT tau_P^2 (barostat mass), g' = g + 1, Q = g' kT tau_T^2,
+ *   dx/dt = v + v_eps x,       dv/dt = F/m - (alpha v_eps + xi) v,
+ *   dL/dt = tau - xi L (plus the free rotation), dV/dt = d V v_eps,
+ *   dv_eps/dt = G_eps / W - xi v_eps,
+ *   G_eps = alpha 2 K_trans + tr W_vir - d V P_ext,
+ *   dxi/dt = (2 K_trans + 2 K_rot + W v_eps^2 - g' kT) / Q, deta/dt = xi.
+ * Conserved: K_trans + K_rot + U + W v_eps^2 / 2 + P_ext V + Q xi^2 / 2
+ * + g' kT eta.  One step of length h is the symmetric Trotter sequence
+ *   thermostat h/2, barostat h/2, kick h/2, drift h (with the box), free
+ *   rotation, forces, kick h/2, barostat h/2, thermostat h/2,
+ * where the kick and the drift are the exact flows of their linear parts:
+ *   v <- v e^{-alpha v_eps h/2} + (h/2)(F/m) e^{-alpha v_eps h/4} sinhc(alpha v_eps h/4),
+ *   x <- x e^{v_eps h} + h v e^{v_eps h/2} sinhc(v_eps h/2),  L_box <- L_box e^{v_eps h},
+ * with sinhc(u) = sinh(u) / u.  Positions are then wrapped into the new box. */
+static double sinhc(double u)
+{
+    if (fabs(u) < 1e-3) {
+        double u2 = u * u;
+        return 1.0 + u2 / 6.0 * (1.0 + u2 / 20.0 * (1.0 + u2 / 42.0));
+    }
+    return sinh(u) / u;
+}
+
+static double trace_virial(const or_sys *S, int n, const double *W)
+{
+    double tr = 0.0;
+    for (int i = 0; i < n; ++i)
+        for (int a = 0; a < S->dim; ++a) tr += W[9 * i + 4 * a];
+    return tr;
+}
+
+static double volume(const or_sys *S)
+{
+    return S->dim == 3 ? S->box[0] * S->box[1] * S->box[2] : S->box[0] * S->box[1];
+}
+
+/* Thermostat half step of length h (as nh_half, with the barostat's kinetic
+ * term W v_eps^2 in the drive and v_eps scaled with the velocities). */
+static void nh_half_npt(const or_sys *S, int n, double *v, double *L, const int *sid, double h, double g, double kT,
+                        double Qm, double Wm, double *veps, double *xi, double *eta)
+{
+    double Kt, Kr;
+    kinetic(S, n, v, L, sid, &Kt, &Kr);
+    double K2 = 2.0 * (Kt + Kr) + Wm * (*veps) * (*veps);
+    *xi += 0.5 * h * (K2 - g * kT) / Qm;
+    double s = exp(-(*xi) * h);
+    for (int i = 0; i < 3 * n; ++i) { v[i] *= s; L[i] *= s; }
+    *veps *= s;
+    K2 *= s * s;
+    *eta += (*xi) * h;
+    *xi += 0.5 * h * (K2 - g * kT) / Qm;
+}
+
+static void baro_half(const or_sys *S, int n, const double *v, const double *L, const int *sid, const double *W,
+                      double h, double alpha, double Pext, double Wm, double *veps)
+{
+    double Kt, Kr;
+    kinetic(S, n, v, L, sid, &Kt, &Kr);
+    double G = alpha * 2.0 * Kt + trace_virial(S, n, W) - S->dim * volume(S) * Pext;
+    *veps += h * G / Wm;
+}
+
+static void kick_npt(const or_sys *S, int n, double *v, double *L, const double *q, const int *sid, const double *F,
+                     const double *T, double h, double alpha, double veps)
+{
+    int d = S->dim;
+    double a = alpha * veps;
+    double damp = exp(-a * 0.5 * h), fk = 0.5 * h * exp(-a * 0.25 * h) * sinhc(a * 0.25 * h);
+    for (int i = 0; i < n; ++i) {
+        double m = S->mass[sid[i]];
+        double Rm[9], tb[3];
+        for (int c = 0; c < d; ++c) v[3 * i + c] = v[3 * i + c] * damp + fk * F[3 * i + c] / m;
+        quat_to_mat(q + 4 * i, Rm);
+        matT_vec(Rm, T + 3 * i, tb);
+        if (d == 2) L[3 * i + 2] += 0.5 * h * T[3 * i + 2];
+        else for (int c = 0; c < 3; ++c) L[3 * i + c] += 0.5 * h * tb[c];
+    }
+}
+
+/* Runs n_steps of the isothermal-isobaric integrator above.  box[3] is the
+ * box (updated), baro[1] = v_eps, thermo = {xi, eta}; log rows, if log is
+ * non-NULL: {U, K_trans, K_rot, xi, eta, H, V, P_int, v_eps} with
+ * P_int = (2 K_trans + tr W_vir) / (d V). */
+void or_run_npt(const or_sys *S0, int n, double *x, double *q, double *v, double *L, int *image, const int *sid,
+                int n_steps, double dt, double kT, double tau_T, double Pext, double tau_P, double *box,
+                double *thermo, double *baro, int mode, double *F, double *T, double *Ui, double *W, double *log)
+{
+    or_sys Sl = *S0;
+    or_sys *S = &Sl;
+    for (int a = 0; a < 3; ++a) S->box[a] = box[a];
+    int d = S->dim, drot = (d == 2) ? 1 : 3;
+    double g = (double)(d * n + drot * n - d) + 1.0;
+    double Nf = (double)(d * (n - 1));
+    double alpha = 1.0 + d / Nf;
+    double Qm = g * kT * tau_T * tau_T;
+    double Wm = (Nf + d) * kT * tau_P * tau_P;
+    double xi = thermo[0], eta = thermo[1], veps = baro[0];
+    or_forces(S, n, x, q, sid, mode, F, T, Ui, W, NULL, NULL);
+    for (int step = 0; step < n_steps; ++step) {
+        nh_half_npt(S, n, v, L, sid, 0.5 * dt, g, kT, Qm, Wm, &veps, &xi, &eta);
+        baro_half(S, n, v, L, sid, W, 0.5 * dt, alpha, Pext, Wm, &veps);
+        kick_npt(S, n, v, L, q, sid, F, T, dt, alpha, veps);
+        double grow = exp(veps * dt), vfac = dt * exp(veps * 0.5 * dt) * sinhc(veps * 0.5 * dt);
+        for (int a = 0; a < d; ++a) S->box[a] *= grow;
+        for (int i = 0; i < n; ++i) {
+            for (int a = 0; a < d; ++a) {
+                double xa = x[3 * i + a] * grow + vfac * v[3 * i + a];
+                double Lb = S->box[a];
+                if (xa >= Lb) { xa -= Lb; image[3 * i + a] += 1; }
+                else if (xa < 0.0) { xa += Lb; image[3 * i + a] -= 1; }
+                x[3 * i + a] = xa;
+            }
+            const double *I = S->inertia + 3 * sid[i];
+            double *qi = q + 4 * i, *Li = L + 3 * i;
+            if (d == 2) {
+                free_rot(qi, Li, I, 2, dt);
+            } else {
+                free_rot(qi, Li, I, 2, 0.5 * dt);
+                free_rot(qi, Li, I, 1, 0.5 * dt);
+                free_rot(qi, Li, I, 0, dt);
+                free_rot(qi, Li, I, 1, 0.5 * dt);
+                free_rot(qi, Li, I, 2, 0.5 * dt);
+            }
+            double qn = sqrt(qi[0] * qi[0] + qi[1] * qi[1] + qi[2] * qi[2] + qi[3] * qi[3]);
+            for (int a = 0; a < 4; ++a) qi[a] /= qn;
+        }
+        or_forces(S, n, x, q, sid, mode, F, T, Ui, W, NULL, NULL);
+        kick_npt(S, n, v, L, q, sid, F, T, dt, alpha, veps);
+        baro_half(S, n, v, L, sid, W, 0.5 * dt, alpha, Pext, Wm, &veps);
+        nh_half_npt(S, n, v, L, sid, 0.5 * dt, g, kT, Qm, Wm, &veps, &xi, &eta);
+        if (log) {
+            double Kt, Kr, U = 0.0;
+            kinetic(S, n, v, L, sid, &Kt, &Kr);
+            for (int i = 0; i < n; ++i) U += Ui[i];
+            double V = volume(S);
+            double H = Kt + Kr + U + 0.5 * Wm * veps * veps + Pext * V + 0.5 * Qm * xi * xi + g * kT * eta;
+            double *row = log + 9 * step;
+            row[0] = U; row[1] = Kt; row[2] = Kr; row[3] = xi; row[4] = eta; row[5] = H;
+            row[6] = V; row[7] = (2.0 * Kt + trace_virial(S, n, W)) / (d * V); row[8] = veps;
+        }
+    }
+    for (int a = 0; a < 3; ++a) box[a] = S->box[a];
+    thermo[0] = xi;
+    thermo[1] = eta;
+    baro[0] = veps;
+}
+
 void or_set_threads(int nt)
 {
 #ifdef _OPENMP

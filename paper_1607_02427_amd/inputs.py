@@ -508,6 +508,9 @@ class System:
     parallel_sin2: float = 1e-6
     name: str = ""
     thermo: Optional[tuple] = None  # Nose-Hoover (xi, eta) of a stored state; None: (0, 0)
+    P: float = 0.0                  # target pressure of the 'npt' ensemble
+    tau_P: float = 2.0              # its barostat time constant
+    veps: float = 0.0               # barostat velocity of a stored state
 
     @property
     def n(self) -> int:
