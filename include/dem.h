@@ -55,7 +55,7 @@ typedef enum {
 } dem_status;
 
 enum { DEM_FP64 = 0, DEM_FP32 = 1 };  /* pair-geometry precision */
-enum { DEM_NVE = 0, DEM_NVT = 1 };
+enum { DEM_NVE = 0, DEM_NVT = 1, DEM_NPT = 2 };
 /* List build selector.  Both values take the same device-wide build (cells,
  * then a neighbour scan of 16 lanes per particle, then the pair list), so
  * the lists are the same; the field is kept so parameter blocks stay
@@ -96,14 +96,16 @@ typedef struct {
     double skin;                  /* neighbour-list skin */
     double rebuild_frac;          /* rebuild when max displacement > rebuild_frac * skin */
     double dt;
-    int32_t ensemble;             /* DEM_NVE or DEM_NVT */
-    double kT;                    /* thermostat temperature (NVT) */
+    int32_t ensemble;             /* DEM_NVE, DEM_NVT or DEM_NPT */
+    double kT;                    /* thermostat temperature (NVT, NPT) */
     double tau_T;                 /* thermostat time constant: Q = g kT tau_T^2 */
     int32_t precision;            /* DEM_FP64 or DEM_FP32 */
     double parallel_sin2;         /* edges with |u x v|^2 < parallel_sin2 |u|^2 |v|^2
                                      use the overlap-midpoint rule (Sec. II) */
     int32_t nbr_capacity;         /* neighbour-row capacity; 0 = automatic */
     int32_t list_mode;            /* DEM_LISTS_AUTO or DEM_LISTS_MULTI */
+    double pressure;              /* DEM_NPT: target pressure P (>= 0) */
+    double tau_P;                 /* DEM_NPT: barostat time constant, W = (N_f + d) kT tau_P^2 */
 } dem_params;
 
 /* Caller-owned device arrays, FP64 structure-of-arrays, length n, borrowed
@@ -132,13 +134,17 @@ typedef struct {
 
 typedef struct {
     double U, K_trans, K_rot;
-    double H;                     /* K + U (NVE) or K + U + Q xi^2/2 + g kT eta (NVT) */
-    double T;                     /* 2K / g */
+    double H;                     /* K + U (NVE); K + U + Q xi^2/2 + g kT eta (NVT); NPT adds
+                                     W v_eps^2/2 + P V, with g and Q counting the barostat */
+    double T;                     /* 2K / g (g without the barostat's degree of freedom) */
     double P;                     /* (2 K_trans + tr W) / (d V) */
     double W[9];                  /* sum_i W_i */
     double xi, eta;               /* thermostat variables */
     int64_t step;
     int64_t n_rebuilds;
+    double V;                     /* box volume (area in 2D) */
+    double box[3];                /* current box (it changes under DEM_NPT) */
+    double veps;                  /* barostat velocity v_eps (DEM_NPT), d ln V / dt = d v_eps */
 } dem_energy_out;
 
 /* Creates a system on the current device and stream, validates and uploads
@@ -210,6 +216,11 @@ dem_status dem_sync(dem_handle h);
 /* Sets the Nose-Hoover variables (for checkpoint/restore); the next step
  * opens its half step from the current kinetic energy. */
 dem_status dem_set_thermostat(dem_handle h, double xi, double eta);
+
+/* Sets the barostat velocity v_eps of a DEM_NPT system (Sec. IV.C; a stored
+ * state's), after dem_set_thermostat if both are set; the next step opens
+ * its half steps from it.  DEM_E_ARG for other ensembles. */
+dem_status dem_set_barostat(dem_handle h, double veps);
 
 /* Copies the lists to host buffers (synchronises): cell_start[n_cells+1],
  * cell_particles[n], nbr[capacity * n] column-major (row i of particle i is

@@ -1288,7 +1288,8 @@ __global__ void __launch_bounds__(kGatherBlock) k_gather(BatchParams b, const Sy
         fl[FLAG_FILL] = (fl[FLAG_REBUILD] != 0 && budget[r] > 0) ? 1 : 0;
     }
     if (KICK && budget[r] <= 0) return;
-    const bool nvt = KICK && p.ensemble == DEM_NVT;
+    const bool npt = KICK && p.ensemble == DEM_NPT;
+    const bool nvt = KICK && (p.ensemble == DEM_NVT || npt);
     const size_t N = (size_t)b.N;
     const bool mine = i < p.off + p.n;
     double acc[16];
@@ -1322,7 +1323,7 @@ __global__ void __launch_bounds__(kGatherBlock) k_gather(BatchParams b, const Sy
     }
     for (int off = 1; off < kGatherLanes; off <<= 1)
         for (int c = 0; c < 16; ++c) acc[c] += __shfl_xor(acc[c], off, kGatherLanes);
-    double kt = 0.0, kr = 0.0;
+    double kt = 0.0, kr = 0.0, tw = 0.0;
     if (mine && sub == 0) {
         double *F = acc, *Tq = acc + 3;
         if (DIM == 2) {
@@ -1341,11 +1342,16 @@ __global__ void __launch_bounds__(kGatherBlock) k_gather(BatchParams b, const Sy
             const int sid = ssid;
             const double hm = 0.5 * p.dt / p.mass[sid];
             double v[3] = {sv[0] + hm * F[0], sv[1] + hm * F[1], 0.0};
+            if (npt) {  // the kick's exact flow with the barostat's friction
+                const double *th = thermo + r * TH_COUNT;
+                const double damp = th[TH_DAMP], fk = th[TH_FK] / p.mass[sid];
+                for (int a = 0; a < DIM; ++a) v[a] = sv[a] * damp + fk * F[a];
+            }
             s.vx[i] = v[0];
             s.vy[i] = v[1];
             double L[3] = {0.0, 0.0, 0.0};
             if (DIM == 3) {
-                v[2] = sv[2] + hm * F[2];
+                if (!npt) v[2] = sv[2] + hm * F[2];
                 s.vz[i] = v[2];
                 double tb[3];
                 body_torque(sq, Tq[0], Tq[1], Tq[2], tb);
@@ -1364,14 +1370,17 @@ __global__ void __launch_bounds__(kGatherBlock) k_gather(BatchParams b, const Sy
                 for (int a = 0; a < 3; ++a)
                     if (p.inertia[sid][a] > 0.0) kr += 0.5 * L[a] * L[a] / p.inertia[sid][a];
             }
+            if (npt) tw = acc[7] + acc[11] + (DIM == 3 ? acc[15] : 0.0);
         }
     }
     if (!nvt) return;
     kt = block_sum<kGatherBlock>(kt, sh);
     kr = block_sum<kGatherBlock>(kr, sh);
+    if (npt) tw = block_sum<kGatherBlock>(tw, sh);
     if (threadIdx.x == 0) {
-        ke_part[2 * cb] = kt;
-        ke_part[2 * cb + 1] = kr;
+        ke_part[kKePer * cb] = kt;
+        ke_part[kKePer * cb + 1] = kr;
+        ke_part[kKePer * cb + 2] = tw;
     }
 }
 
@@ -1387,7 +1396,7 @@ __global__ void __launch_bounds__(kGatherBlock) k_gather(BatchParams b, const Sy
 // first of them) and the pair entries of every chunk of a replica that
 // rebuilds (FLAG_FILL, which the tail workgroups do not touch), one chunk
 // per workgroup at a time; the cells are emptied for the next build.
-__global__ void __launch_bounds__(kGatherBlock) k_replica_tail(BatchParams b, const SysParams *reps, ListPtrs l,
+__global__ void __launch_bounds__(kGatherBlock) k_replica_tail(BatchParams b, SysParams *reps, ListPtrs l,
                                                                const double *ke_part, double *thermo, int64_t *budget,
                                                                int64_t *steps)
 {
@@ -1416,8 +1425,54 @@ __global__ void __launch_bounds__(kGatherBlock) k_replica_tail(BatchParams b, co
     const int64_t left = budget[r];
     const int32_t rebuilt = fl[FLAG_REBUILD], trigger = fl[FLAG_TRIGGER];
     const double xi0 = th[TH_XI], eta0 = th[TH_ETA];
-    const SysParams &p = reps[r];
+    SysParams &p = reps[r];
     if (!p.live || p.n == 0 || left <= 0) return;
+    if (p.ensemble == DEM_NPT) {
+        // closing of this step: barostat half step (K_trans after the
+        // closing kick, the virial of this step's forces, this step's box),
+        // thermostat half step; opening of the next: thermostat, barostat;
+        // then the next step's kick and drift factors and its box
+        const int nblk = (p.n + kChunk - 1) / kChunk;
+        const int c0 = p.off / kChunk;
+        double at = 0.0, ar = 0.0, aw = 0.0;
+#pragma unroll 8
+        for (int c = threadIdx.x; c < nblk; c += blockDim.x) {
+            at += ke_part[kKePer * (c0 + c)];
+            ar += ke_part[kKePer * (c0 + c) + 1];
+            aw += ke_part[kKePer * (c0 + c) + 2];
+        }
+        double Kt2 = 2.0 * block_sum<kGatherBlock>(at, sh);
+        const double Kr2 = 2.0 * block_sum<kGatherBlock>(ar, sh);
+        const double trW = block_sum<kGatherBlock>(aw, sh);
+        if (threadIdx.x == 0) {
+            double xi = xi0, eta = eta0, veps = th[TH_VEPS];
+            baro_half(p, Kt2, trW, veps);
+            double K2 = Kt2 + Kr2;
+            const double sb = nh_half_npt(p, xi, eta, K2, veps);
+            Kt2 *= sb * sb;
+            th[TH_XI_B] = xi;
+            th[TH_ETA_B] = eta;
+            th[TH_VEPS_B] = veps;
+            th[TH_SB] = sb;
+            const double sa = nh_half_npt(p, xi, eta, K2, veps);
+            Kt2 *= sa * sa;
+            baro_half(p, Kt2, trW, veps);
+            th[TH_XI] = xi;
+            th[TH_ETA] = eta;
+            th[TH_VEPS] = veps;
+            th[TH_SA] = sa;
+            th[TH_OPEN] = 1.0;
+            npt_factors(p, veps, th);
+            if (rebuilt != 0)  // this step's lists were built in this step's box
+                for (int a = 0; a < 3; ++a) p.box_build[a] = p.box[a];
+            double box[3];
+            for (int a = 0; a < 3; ++a) {
+                th[TH_BOXN + a] = p.box[a];
+                box[a] = p.box[a] * th[TH_GROW];
+            }
+            set_box(p, box, fl);
+        }
+    }
     if (p.ensemble == DEM_NVT) {
         const int nblk = (p.n + kChunk - 1) / kChunk;
         const int c0 = p.off / kChunk;
@@ -1425,7 +1480,8 @@ __global__ void __launch_bounds__(kGatherBlock) k_replica_tail(BatchParams b, co
         // unrolled so that many loads are in flight at once (large
         // replicas have thousands of chunks); the sums keep their order
 #pragma unroll 8
-        for (int c = threadIdx.x; c < nblk; c += blockDim.x) acc2 += ke_part[2 * (c0 + c)] + ke_part[2 * (c0 + c) + 1];
+        for (int c = threadIdx.x; c < nblk; c += blockDim.x)
+            acc2 += ke_part[kKePer * (c0 + c)] + ke_part[kKePer * (c0 + c) + 1];
         double K = block_sum<kGatherBlock>(acc2, sh);
         if (threadIdx.x == 0) {
             double xi = xi0, eta = eta0;
@@ -1517,7 +1573,7 @@ void gather_t(const Launch &L, bool kick, hipStream_t stream)
         k_gather<T, DIM, true><<<pad8(L.b.nchunk) + row_workgroups(L.b), kGatherBlock, 0, stream>>>(
             L.b, L.reps, L.s, L.o, L.l, rec, L.ke_part, L.thermo, L.budget, L.steps);
         k_replica_tail<<<L.b.nrep + std::min(L.b.nchunk, 1024), kGatherBlock, 0, stream>>>(
-            L.b, L.reps, L.l, L.ke_part, L.thermo, L.budget, L.steps);
+            L.b, const_cast<SysParams *>(L.reps), L.l, L.ke_part, L.thermo, L.budget, L.steps);
     }
     else
         k_gather<T, DIM, false><<<pad8(L.b.nchunk), kGatherBlock, 0, stream>>>(L.b, L.reps, L.s, L.o, L.l, rec, L.ke_part,

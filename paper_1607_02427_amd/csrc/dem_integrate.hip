@@ -122,10 +122,40 @@ __global__ void __launch_bounds__(kBlock) k_nh_begin(BatchParams b, const SysPar
     __shared__ double sh[kBlock];
     const SysParams &p = reps[blockIdx.x];
     double *th = thermo + blockIdx.x * TH_COUNT;
-    if (!p.live || p.n == 0 || p.ensemble != DEM_NVT || budget[blockIdx.x] <= 0 || th[TH_OPEN] != 0.0) return;
+    if (!p.live || p.n == 0 || (p.ensemble != DEM_NVT && p.ensemble != DEM_NPT) || budget[blockIdx.x] <= 0 ||
+        th[TH_OPEN] != 0.0)
+        return;
     const int c0 = p.off / kChunk, nc = (p.n + kChunk - 1) / kChunk;
+    if (p.ensemble == DEM_NPT) {
+        // thermostat half step, then barostat half step (from K_trans after
+        // it, the virial of the current forces and the current box)
+        double at = 0.0, ar = 0.0, aw = 0.0;
+        for (int c = threadIdx.x; c < nc; c += blockDim.x) {
+            at += ke_part[kKePer * (c0 + c)];
+            ar += ke_part[kKePer * (c0 + c) + 1];
+            aw += ke_part[kKePer * (c0 + c) + 2];
+        }
+        double Kt2 = 2.0 * block_sum<kBlock>(at, sh);
+        const double Kr2 = 2.0 * block_sum<kBlock>(ar, sh);
+        const double trW = block_sum<kBlock>(aw, sh);
+        if (threadIdx.x != 0) return;
+        double xi = th[TH_XI], eta = th[TH_ETA], veps = th[TH_VEPS];
+        double K2 = Kt2 + Kr2;
+        const double sa = nh_half_npt(p, xi, eta, K2, veps);
+        Kt2 *= sa * sa;
+        baro_half(p, Kt2, trW, veps);
+        th[TH_XI] = xi;
+        th[TH_ETA] = eta;
+        th[TH_VEPS] = veps;
+        th[TH_SB] = 1.0;
+        th[TH_SA] = sa;
+        th[TH_OPEN] = 1.0;
+        npt_factors(p, veps, th);
+        return;
+    }
     double acc = 0.0;
-    for (int c = threadIdx.x; c < nc; c += blockDim.x) acc += ke_part[2 * (c0 + c)] + ke_part[2 * (c0 + c) + 1];
+    for (int c = threadIdx.x; c < nc; c += blockDim.x)
+        acc += ke_part[kKePer * (c0 + c)] + ke_part[kKePer * (c0 + c) + 1];
     double K = block_sum<kBlock>(acc, sh);
     if (threadIdx.x != 0) return;
     double xi = th[TH_XI], eta = th[TH_ETA];
@@ -137,6 +167,29 @@ __global__ void __launch_bounds__(kBlock) k_nh_begin(BatchParams b, const SysPar
     th[TH_OPEN] = 1.0;
 }
 
+// Start of a call: an NPT replica's box moves on to the box of its next
+// step (TH_GROW times the box of the positions); end of a call: back to the
+// box of the positions, which the tail of every step keeps in TH_BOXN.
+__global__ void k_box_open(int nrep, SysParams *reps, ListPtrs l, const double *thermo, const int64_t *budget)
+{
+    const int r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= nrep) return;
+    SysParams &p = reps[r];
+    const double *th = thermo + r * TH_COUNT;
+    if (!p.live || p.ensemble != DEM_NPT || budget[r] <= 0) return;
+    const double box[3] = {th[TH_BOXN] * th[TH_GROW], th[TH_BOXN + 1] * th[TH_GROW], th[TH_BOXN + 2] * th[TH_GROW]};
+    set_box(p, box, l.flags + r * FLAG_COUNT);
+}
+
+__global__ void k_box_close(int nrep, SysParams *reps, ListPtrs l, const double *thermo)
+{
+    const int r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= nrep) return;
+    SysParams &p = reps[r];
+    if (!p.live || p.ensemble != DEM_NPT) return;
+    set_box(p, thermo + r * TH_COUNT + TH_BOXN, l.flags + r * FLAG_COUNT);
+}
+
 // End of a call: the velocities take the pending closing factor.
 __global__ void k_scale(BatchParams b, const SysParams *reps, StatePtrs s, ListPtrs l, const double *thermo)
 {
@@ -144,7 +197,7 @@ __global__ void k_scale(BatchParams b, const SysParams *reps, StatePtrs s, ListP
     const int r = wave_replica(b, l, i);
     if (r < 0 || i >= reps[r].off + reps[r].n) return;
     const double sc = thermo[r * TH_COUNT + TH_SB];
-    if (reps[r].ensemble != DEM_NVT || sc == 1.0) return;
+    if ((reps[r].ensemble != DEM_NVT && reps[r].ensemble != DEM_NPT) || sc == 1.0) return;
     s.vx[i] *= sc;
     s.vy[i] *= sc;
     s.vz[i] *= sc;
@@ -207,21 +260,33 @@ __global__ void __launch_bounds__(kChunk) k_kick_drift(BatchParams b, const SysP
     // parameters, not one round trip after another (this kernel writes
     // none of them; the thermostat slots exist for every replica)
     const int64_t left = budget[r];
-    const double th_sb = thermo[r * TH_COUNT + TH_SB], th_sa = thermo[r * TH_COUNT + TH_SA];
+    const double *thr = thermo + r * TH_COUNT;
+    const double th_sb = thr[TH_SB], th_sa = thr[TH_SA];
     const int32_t rebuild = l.flags[r * FLAG_COUNT + FLAG_REBUILD];
     const SysParams &p = reps[r];
     if (i >= p.off + p.n || left <= 0) return;
     // pending thermostat factors: the closing half step of the last step,
     // then the opening half step of this one (1 and 1 without a thermostat)
-    const bool nvt = p.ensemble == DEM_NVT;
+    const bool npt = p.ensemble == DEM_NPT;
+    const bool nvt = p.ensemble == DEM_NVT || npt;
     const double sb = nvt ? th_sb : 1.0;
     const double sa = nvt ? th_sa : 1.0;
     const double hm = 0.5 * p.dt / p.mass[sid];
     const double I[3] = {p.inertia[sid][0], p.inertia[sid][1], p.inertia[sid][2]};
     double v[3] = {(v0[0] * sb) * sa + hm * F0[0], (v0[1] * sb) * sa + hm * F0[1], 0.0};
+    double grow = 1.0, vfac = p.dt;
+    if (npt) {
+        // the exact flow of the kick with the barostat's friction, and of
+        // the drift with the box growing by `grow` this step
+        const double damp = thr[TH_DAMP], fk = thr[TH_FK] / p.mass[sid];
+        grow = thr[TH_GROW];
+        vfac = thr[TH_VFAC];
+        for (int a = 0; a < 3; ++a) v[a] = ((v0[a] * sb) * sa) * damp + fk * F0[a];
+        if (DIM == 2) v[2] = 0.0;
+    }
     double L[3];
     if (DIM == 3) {
-        v[2] = (v0[2] * sb) * sa + hm * F0[2];
+        if (!npt) v[2] = (v0[2] * sb) * sa + hm * F0[2];
         double tb[3];
         body_torque(q, T0[0], T0[1], T0[2], tb);
         L[0] = (L0[0] * sb) * sa + 0.5 * p.dt * tb[0];
@@ -233,7 +298,7 @@ __global__ void __launch_bounds__(kChunk) k_kick_drift(BatchParams b, const SysP
         L[2] = (L0[2] * sb) * sa + 0.5 * p.dt * T0[2];
     }
     for (int a = 0; a < DIM; ++a) {
-        double xa = x[a] + p.dt * v[a];
+        double xa = npt ? x[a] * grow + vfac * v[a] : x[a] + p.dt * v[a];
         if (xa >= p.box[a]) {
             xa -= p.box[a];
             img[a] += 1;
@@ -297,6 +362,22 @@ __global__ void __launch_bounds__(kChunk) k_kick_drift(BatchParams b, const SysP
         // build, plus one more step like this one, exceeds rebuild_frac * skin
         // (so no force is evaluated on a list older than that).
         double d2 = 0.0, v2 = 0.0;
+        if (npt) {
+            // under the barostat the lists were built in the box
+            // box_build: a particle's displacement is taken from its build
+            // position carried along with the box, and a shrinking box brings
+            // pairs beyond r_list closer by (1 - s) r_list (s = the box's
+            // scale since the build, one more step included)
+            const double lam = p.box[0] / p.box_build[0];
+            for (int a = 0; a < DIM; ++a) {
+                const double d = min_image(x[a] - lam * xl[a], p.box[a]);
+                d2 += d * d;
+                v2 += v[a] * v[a];
+            }
+            const double shrink = fmax(0.0, 1.0 - lam * grow) * 0.5 * sqrt(p.rl2);
+            const double reach = sqrt(d2) + p.dt * sqrt(v2) + shrink;
+            if (reach * reach > p.disp2) atomicOr(&l.flags[r * FLAG_COUNT + FLAG_TRIGGER], 1);
+        } else {
         for (int a = 0; a < DIM; ++a) {
             const double d = min_image(x[a] - xl[a], p.box[a]);
             d2 += d * d;
@@ -304,6 +385,7 @@ __global__ void __launch_bounds__(kChunk) k_kick_drift(BatchParams b, const SysP
         }
         const double reach = sqrt(d2) + p.dt * sqrt(v2);
         if (reach * reach > p.disp2) atomicOr(&l.flags[r * FLAG_COUNT + FLAG_TRIGGER], 1);
+        }
     }
     if (!(isfinite(x[0]) && isfinite(x[1]) && isfinite(x[2]) && isfinite(v[0]) && isfinite(v[1]) && isfinite(v[2])))
         atomicOr(&l.flags[r * FLAG_COUNT + FLAG_NONFINITE], 1);
@@ -311,15 +393,15 @@ __global__ void __launch_bounds__(kChunk) k_kick_drift(BatchParams b, const SysP
 
 // Per-chunk kinetic partials of the current state, with the particle-to-
 // block mapping of the gather (one chunk per block).
-__global__ void __launch_bounds__(kGatherBlock) k_kinetic(BatchParams b, const SysParams *reps, StatePtrs s, ListPtrs l,
-                                                       double *ke_part)
+__global__ void __launch_bounds__(kGatherBlock) k_kinetic(BatchParams b, const SysParams *reps, StatePtrs s, OutPtrs o,
+                                                       ListPtrs l, double *ke_part)
 {
     __shared__ double sh[kGatherBlock];
     const int r = l.chunk_rep[blockIdx.x];
     if (r < 0) return;
     const SysParams &p = reps[r];
     const int i = blockIdx.x * kGatherPer + threadIdx.x / kGatherLanes;
-    double kt = 0.0, kr = 0.0;
+    double kt = 0.0, kr = 0.0, tw = 0.0;
     if (i < p.off + p.n && (threadIdx.x % kGatherLanes) == 0) {
         const int sid = s.sid[i];
         const double m = p.mass[sid];
@@ -327,12 +409,16 @@ __global__ void __launch_bounds__(kGatherBlock) k_kinetic(BatchParams b, const S
         const double L[3] = {s.Lx[i], s.Ly[i], s.Lz[i]};
         for (int a = 0; a < 3; ++a)
             if (p.inertia[sid][a] > 0.0) kr += 0.5 * L[a] * L[a] / p.inertia[sid][a];
+        if (p.ensemble == DEM_NPT)
+            tw = o.W[i] + o.W[(size_t)4 * b.wstride + i] + (p.dim == 3 ? o.W[(size_t)8 * b.wstride + i] : 0.0);
     }
     kt = block_sum<kGatherBlock>(kt, sh);
     kr = block_sum<kGatherBlock>(kr, sh);
+    tw = block_sum<kGatherBlock>(tw, sh);
     if (threadIdx.x == 0) {
-        ke_part[2 * blockIdx.x] = kt;
-        ke_part[2 * blockIdx.x + 1] = kr;
+        ke_part[kKePer * blockIdx.x] = kt;
+        ke_part[kKePer * blockIdx.x + 1] = kr;
+        ke_part[kKePer * blockIdx.x + 2] = tw;
     }
 }
 
@@ -370,6 +456,8 @@ void launch_nh_begin(const Launch &L, hipStream_t stream)
 {
     if (L.b.nrep == 0) return;
     k_nh_begin<<<L.b.nrep, kBlock, 0, stream>>>(L.b, L.reps, L.ke_part, L.thermo, L.budget);
+    k_box_open<<<blocks_for(L.b.nrep), kBlock, 0, stream>>>(L.b.nrep, const_cast<SysParams *>(L.reps), L.l, L.thermo,
+                                                          L.budget);
 }
 
 void launch_nh_end(const Launch &L, hipStream_t stream)
@@ -378,6 +466,7 @@ void launch_nh_end(const Launch &L, hipStream_t stream)
     const int nr = (L.b.nrep + kBlock - 1) / kBlock;
     if (L.b.nchunk > 0) k_scale<<<blocks_for(L.b.nchunk * kChunk), kBlock, 0, stream>>>(L.b, L.reps, L.s, L.l, L.thermo);
     k_nh_close<<<nr, kBlock, 0, stream>>>(L.b.nrep, L.thermo);
+    k_box_close<<<nr, kBlock, 0, stream>>>(L.b.nrep, const_cast<SysParams *>(L.reps), L.l, L.thermo);
 }
 
 template <typename T>
@@ -404,7 +493,7 @@ void launch_kick_drift(const Launch &L, hipStream_t stream)
 void launch_kinetic(const Launch &L, hipStream_t stream)
 {
     if (L.b.nchunk == 0) return;
-    k_kinetic<<<L.b.nchunk, kGatherBlock, 0, stream>>>(L.b, L.reps, L.s, L.l, L.ke_part);
+    k_kinetic<<<L.b.nchunk, kGatherBlock, 0, stream>>>(L.b, L.reps, L.s, L.o, L.l, L.ke_part);
 }
 
 void launch_energy_partials(const Launch &L, double *part, hipStream_t stream)

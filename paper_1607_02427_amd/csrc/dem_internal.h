@@ -43,7 +43,7 @@ __host__ __device__ constexpr int pair_tile(int sep_lanes) { return kPairWaves *
 // tail, while the tail itself moves FLAG_REBUILD on to the next step).
 enum Flag {
     FLAG_REBUILD = 0, FLAG_NBUILDS = 1, FLAG_MAXROW = 2, FLAG_NONFINITE = 3, FLAG_NPAIRS = 4,
-    FLAG_TRIGGER = 6, FLAG_CELLOVF = 7, FLAG_NEWPAIRS = 9, FLAG_FILL = 10, FLAG_COUNT = 16
+    FLAG_TRIGGER = 6, FLAG_CELLOVF = 7, FLAG_NEWPAIRS = 9, FLAG_FILL = 10, FLAG_BOXSMALL = 11, FLAG_COUNT = 16
 };
 // Batch-wide words.  G_ANY: how many replicas rebuild their lists in the
 // current step (the list workgroups of the step kernels return at once
@@ -66,7 +66,22 @@ constexpr int lb_rows_per_group = 4;
 // the last completed step.  The next kick applies (v * SB) * SA, and the
 // end of a call applies SB alone, so a run split into calls and the same
 // run in one call give the same numbers.
-enum Thermo { TH_XI = 0, TH_ETA = 1, TH_SB = 2, TH_SA = 3, TH_XI_B = 4, TH_ETA_B = 5, TH_OPEN = 6, TH_COUNT = 8 };
+// DEM_NPT adds the barostat velocity after the opening half step of the
+// current step (TH_VEPS) and at the end of the last completed step
+// (TH_VEPS_B), and the step's factors of the exact kick and drift flows:
+// TH_DAMP = exp(-alpha v_eps h/2), TH_FK = (h/2) exp(-alpha v_eps h/4)
+// sinhc(alpha v_eps h/4), TH_GROW = exp(v_eps h), TH_VFAC = h exp(v_eps h/2)
+// sinhc(v_eps h/2) (sinhc(u) = sinh(u) / u).
+enum Thermo {
+    TH_XI = 0, TH_ETA = 1, TH_SB = 2, TH_SA = 3, TH_XI_B = 4, TH_ETA_B = 5, TH_OPEN = 6,
+    TH_VEPS = 8, TH_VEPS_B = 9, TH_DAMP = 10, TH_FK = 11, TH_GROW = 12, TH_VFAC = 13, TH_BOXN = 16, TH_COUNT = 24
+};
+// (TH_BOXN..TH_BOXN + 2: the box of the current positions.  Inside a call
+// the replica tail already moves SysParams::box on to the next step's box;
+// the end of a call puts the box of the positions back and the next call's
+// first step applies TH_GROW again.)
+// Per-chunk reduction partials of the step: K_trans, K_rot, tr W, (pad).
+constexpr int kKePer = 4;
 // Force work counters (unsigned long long).
 enum Stat {
     ST_PAIRS = 0, ST_FEATURES = 1, ST_INCUT = 2, ST_LAUNCHES = 3, ST_NEAR = 4, ST_REFINED = 5, ST_EENEAR = 6,
@@ -155,6 +170,15 @@ struct SysParams {
     double disp2;                // (rebuild_frac * skin)^2
     double eps, par_s2;
     double dt, kT, g, Qm;
+    // DEM_NPT (Sec. IV.C): target pressure, barostat mass W = (N_f + d) kT
+    // tau_P^2, alpha = 1 + d / N_f with N_f = d (n - 1); the box at the last
+    // list build; r_list and the cells per axis at creation.  box, cellw,
+    // nc, ncell and use_cells of an NPT replica change on the device every
+    // step (the replica tail), and the host reads them back before using them.
+    double pext, Wm, alpha;
+    double box_build[3];
+    double rlist;
+    int nc0[3], pad_npt;
     double mass[DEM_MAX_SHAPES];
     double inertia[DEM_MAX_SHAPES][3];
     double R[DEM_MAX_SHAPES];    // circumradius about the body origin
@@ -256,11 +280,86 @@ struct Launch {
     ListPtrs l;
     ForcePtrs f;
     int precision;
-    double *ke_part;             // [2 * nchunk]
+    double *ke_part;             // [kKePer * nchunk]
     double *thermo;              // [replica][TH_COUNT]
     int64_t *budget;             // [replica] steps left; a replica with none left is held still
     int64_t *steps;              // [replica] steps done
 };
+
+// ---- isothermal-isobaric steps (DEM_NPT, Sec. IV.C) ----------------------
+// The barostat follows the measure-preserving isotropic scheme the paper
+// cites: dx/dt = v + v_eps x, dv/dt = F/m - (alpha v_eps + xi) v, dV/dt =
+// d V v_eps, dv_eps/dt = (alpha 2 K_trans + tr W - d V P) / W - xi v_eps,
+// one Nose-Hoover xi for translation, rotation and the barostat.
+
+// sinh(u) / u; its series below |u| = 1e-2 (truncation below 1e-17).
+__device__ inline double sinhc(double u)
+{
+    if (fabs(u) < 1e-2) {
+        const double u2 = u * u;
+        return 1.0 + u2 * (1.0 / 6.0 + u2 * (1.0 / 120.0 + u2 * (1.0 / 5040.0)));
+    }
+    return sinh(u) / u;
+}
+
+__device__ inline double box_volume(const SysParams &p)
+{
+    return p.dim == 3 ? p.box[0] * p.box[1] * p.box[2] : p.box[0] * p.box[1];
+}
+
+// Thermostat half step of length dt/2 with the barostat's kinetic term in
+// its drive; K2 = 2 (K_trans + K_rot) and v_eps are scaled with the
+// velocities.  Returns the velocity scale.
+__device__ inline double nh_half_npt(const SysParams &p, double &xi, double &eta, double &K2, double &veps)
+{
+    const double h = 0.5 * p.dt;
+    xi += 0.5 * h * (K2 + p.Wm * veps * veps - p.g * p.kT) / p.Qm;
+    const double sc = exp(-xi * h);
+    K2 *= sc * sc;
+    veps *= sc;
+    eta += xi * h;
+    xi += 0.5 * h * (K2 + p.Wm * veps * veps - p.g * p.kT) / p.Qm;
+    return sc;
+}
+
+// Barostat half step of length dt/2 from 2 K_trans, tr W and the volume of
+// the box in p.
+__device__ inline void baro_half(const SysParams &p, double Kt2, double trW, double &veps)
+{
+    veps += 0.5 * p.dt * (p.alpha * Kt2 + trW - p.dim * box_volume(p) * p.pext) / p.Wm;
+}
+
+// The step's kick and drift factors for barostat velocity veps.
+__device__ inline void npt_factors(const SysParams &p, double veps, double *th)
+{
+    const double h = p.dt, a = p.alpha * veps;
+    th[TH_DAMP] = exp(-0.5 * h * a);
+    th[TH_FK] = 0.5 * h * exp(-0.25 * h * a) * sinhc(0.25 * h * a);
+    th[TH_GROW] = exp(h * veps);
+    th[TH_VFAC] = h * exp(0.5 * h * veps) * sinhc(0.5 * h * veps);
+}
+
+// Sets the box of an NPT replica and its cell geometry: as many cells per
+// axis as at creation while they stay at least r_list wide, fewer when the
+// box has shrunk; cells are used while every axis has three.  Flags a box
+// below twice r_list (the minimum image would no longer be unique).
+__device__ inline void set_box(SysParams &p, const double *box, int32_t *fl)
+{
+    int use = 1, ncell = 1;
+    for (int a = 0; a < 3; ++a) {
+        p.box[a] = box[a];
+        if (a < p.dim) {
+            if (box[a] < 2.0 * p.rlist) atomicOr(&fl[FLAG_BOXSMALL], 1);
+            const int fit = (int)floor(box[a] / p.rlist);
+            p.nc[a] = fit < p.nc0[a] ? (fit > 1 ? fit : 1) : p.nc0[a];
+            if (p.nc[a] < 3) use = 0;
+        }
+        p.cellw[a] = box[a] / (double)p.nc[a];
+        ncell *= p.nc[a];
+    }
+    p.ncell = ncell;
+    p.use_cells = use;
+}
 
 // Cell list, neighbour list, half pair list and the tile plan of the pair
 // kernel, outside a step.  mode LISTS_ALL or a replica index: from the

@@ -247,7 +247,10 @@ __device__ inline void fill_chunk(const BatchParams &b, const SysParams &p, cons
     }
     if (!mine) return;
     pair_fill(p, b, l, i);
-    if (clear_cells && p.use_cells) l.cell_count[p.coff + l.pcell[i]] = 0;  // every particle of the cell writes the same zero
+    // every particle of the cell writes the same zero (without cells the
+    // word is zero already; use_cells of a replica under the barostat may
+    // change while this runs)
+    if (clear_cells) l.cell_count[p.coff + l.pcell[i]] = 0;
 }
 
 // Tile plan (the first tile of each replica, b.tile pairs per tile) by one

@@ -65,6 +65,7 @@ struct SlotArena {
 
 struct Replica {
     bool live = false;
+    bool on_device = false;      // its SysParams have been uploaded (the device's box is current)
     SysParams sp{};
     dem_params prm{};            // copy; shapes not kept
     double r_list = 0.0;
@@ -100,7 +101,7 @@ struct dem_system {
     void *rot = nullptr;         // [N] PartRec in the force precision
     PartRec64 *rec64 = nullptr;  // [N] FP64 position and orientation (FP32 path)
     void *rec = nullptr;         // [cap][N] SlotRec in the force precision
-    double *ke_part = nullptr;   // [2 * chunks]
+    double *ke_part = nullptr;   // [kKePer * chunks]
     double *e_part = nullptr;    // [12 * chunks]
     double *scratch = nullptr;   // this device's copy of the static energy scratch (device address)
     double *thermo = nullptr;    // [replica][TH_COUNT]
@@ -194,6 +195,43 @@ __global__ void k_set_thermo(double *th, double xi, double eta)
     th[TH_ETA] = th[TH_ETA_B] = eta;
     th[TH_SB] = th[TH_SA] = 1.0;
     th[TH_OPEN] = 0.0;
+}
+
+// A new replica's barostat words (v_eps = 0) and the box of its positions.
+__global__ void k_set_baro(double *th, double bx, double by, double bz)
+{
+    th[TH_VEPS] = th[TH_VEPS_B] = 0.0;
+    th[TH_DAMP] = th[TH_GROW] = 1.0;
+    th[TH_FK] = th[TH_VFAC] = 0.0;
+    th[TH_BOXN] = bx;
+    th[TH_BOXN + 1] = by;
+    th[TH_BOXN + 2] = bz;
+}
+
+// The barostat velocity; the next step opens from it.
+__global__ void k_set_veps(double *th, double veps)
+{
+    th[TH_VEPS] = th[TH_VEPS_B] = veps;
+    th[TH_XI] = th[TH_XI_B];
+    th[TH_ETA] = th[TH_ETA_B];
+    th[TH_SB] = th[TH_SA] = 1.0;
+    th[TH_OPEN] = 0.0;
+}
+
+// Lists just built from the current positions: an NPT replica's build box.
+__global__ void k_box_built(SysParams *reps, int r)
+{
+    for (int a = 0; a < 3; ++a) reps[r].box_build[a] = reps[r].box[a];
+}
+
+// An NPT replica's box (and cells) from the box of its positions in its
+// thermostat words, after those were restored from a checkpoint.
+__global__ void k_box_restore(SysParams *reps, int r, ListPtrs l, const double *thermo)
+{
+    SysParams &p = reps[r];
+    if (p.ensemble != DEM_NPT) return;
+    set_box(p, thermo + r * TH_COUNT + TH_BOXN, l.flags + r * FLAG_COUNT);
+    for (int a = 0; a < 3; ++a) p.box_build[a] = p.box[a];
 }
 
 struct HostVec {
@@ -518,8 +556,35 @@ void place_pairs(dem_system *h)
     }
 }
 
+// The box and cell geometry of the NPT replicas, which the device moves on
+// every step, read back into the host copies (synchronises).
+dem_status sync_dynamic(dem_system *h)
+{
+    bool any = false;
+    for (const Replica &R : h->reps) any |= R.live && R.on_device && R.sp.ensemble == DEM_NPT;
+    if (!any) return DEM_OK;
+    std::vector<SysParams> dev(h->reps.size());
+    HIPCHK(h, hipMemcpyAsync(dev.data(), h->d_reps, sizeof(SysParams) * dev.size(), hipMemcpyDeviceToHost, h->stream));
+    HIPCHK(h, hipStreamSynchronize(h->stream));
+    for (size_t r = 0; r < h->reps.size(); ++r) {
+        SysParams &sp = h->reps[r].sp;
+        if (!h->reps[r].live || !h->reps[r].on_device || sp.ensemble != DEM_NPT) continue;
+        const SysParams &d = dev[r];
+        for (int a = 0; a < 3; ++a) {
+            sp.box[a] = d.box[a];
+            sp.cellw[a] = d.cellw[a];
+            sp.nc[a] = d.nc[a];
+            sp.box_build[a] = d.box_build[a];
+        }
+        sp.ncell = d.ncell;
+        sp.use_cells = d.use_cells;
+    }
+    return DEM_OK;
+}
+
 dem_status upload_tables(dem_system *h)
 {
+    if (dem_status st = sync_dynamic(h); st != DEM_OK) return st;
     std::vector<SysParams> sp(h->reps.size());
     for (size_t r = 0; r < h->reps.size(); ++r) {
         sp[r] = h->reps[r].sp;
@@ -539,6 +604,7 @@ dem_status upload_tables(dem_system *h)
         HIPCHK(h, hipMemcpyAsync(h->d_chunk_rep, h->h_chunk_rep.data(), sizeof(int32_t) * h->h_chunk_rep.size(),
                                  hipMemcpyHostToDevice, h->stream));
     HIPCHK(h, hipStreamSynchronize(h->stream));
+    for (Replica &R : h->reps) R.on_device = R.live;
     refresh_batch(h);
     drop_graph(h);
     return DEM_OK;
@@ -601,7 +667,7 @@ dem_status alloc_core(dem_system *h, int Ncap, int Ccap, int Scap, int Rcap)
               hipMalloc(&h->d_chunk_rep, sizeof(int32_t) * nch) == hipSuccess &&
               hipMalloc(&h->tab64, sizeof(ShapeTab<double>) * Scap) == hipSuccess &&
               hipMalloc(&h->tab32, sizeof(ShapeTab<float>) * Scap) == hipSuccess &&
-              hipMalloc(&h->ke_part, sizeof(double) * 2 * nch) == hipSuccess &&
+              hipMalloc(&h->ke_part, sizeof(double) * kKePer * nch) == hipSuccess &&
               hipMalloc(&h->e_part, sizeof(double) * 12 * nch) == hipSuccess &&
               hipMalloc(&h->thermo, sizeof(double) * TH_COUNT * Rcap) == hipSuccess &&
               hipMalloc(&h->budget, sizeof(int64_t) * Rcap) == hipSuccess &&
@@ -648,7 +714,7 @@ dem_status alloc_core(dem_system *h, int Ncap, int Ccap, int Scap, int Rcap)
     HIPCHK(h, hipMemsetAsync(h->lst.ptot, 0, sizeof(int32_t) * (N / lb_rows_per_group + 1), h->stream));
     HIPCHK(h, hipMemsetAsync(h->lst.pcell, 0, sizeof(int32_t) * N, h->stream));
     HIPCHK(h, hipMemsetAsync(h->stats, 0, sizeof(unsigned long long) * ST_COUNT, h->stream));
-    HIPCHK(h, hipMemsetAsync(h->ke_part, 0, sizeof(double) * 2 * nch, h->stream));
+    HIPCHK(h, hipMemsetAsync(h->ke_part, 0, sizeof(double) * kKePer * nch, h->stream));
     HIPCHK(h, hipMemsetAsync(h->budget, 0, sizeof(int64_t) * Rcap, h->stream));
     HIPCHK(h, hipMemsetAsync(h->steps, 0, sizeof(int64_t) * Rcap, h->stream));
     return DEM_OK;
@@ -686,6 +752,8 @@ dem_status latched(dem_system *h)
         if (f[FLAG_MAXROW] > h->bp.cap)
             return fail(h, DEM_E_CAPACITY, "replica %zu: neighbour row of %d exceeds capacity %d", r, f[FLAG_MAXROW],
                         h->bp.cap);
+        if (f[FLAG_BOXSMALL])
+            return fail(h, DEM_E_STATE, "replica %zu: the barostat shrank the box below twice the list radius", r);
     }
     return DEM_OK;
 }
@@ -750,8 +818,10 @@ dem_status build_lists_sync(dem_system *h, int only)
         }
         if (maxrow <= h->bp.cap) {
             for (size_t r = 0; r < h->reps.size(); ++r)
-                if (h->reps[r].live && (only < 0 || (int)r == only))
+                if (h->reps[r].live && (only < 0 || (int)r == only)) {
                     k_count_build<<<1, 1, 0, h->stream>>>(h->lst.flags + FLAG_COUNT * r);
+                    k_box_built<<<1, 1, 0, h->stream>>>(h->d_reps, (int)r);
+                }
             HIPCHK(h, hipGetLastError());
             return DEM_OK;
         }
@@ -774,12 +844,15 @@ dem_status describe_replica(dem_system *h, const dem_params &p, Replica &R, std:
     if (p.n < 0 || p.n > (int64_t)INT32_MAX / 64) return fail(h, DEM_E_ARG, "n out of range");
     if (p.n_shapes < 1 || p.n_shapes > DEM_MAX_SHAPES || !p.shapes)
         return fail(h, DEM_E_ARG, "n_shapes must be 1..%d", DEM_MAX_SHAPES);
-    if (p.ensemble != DEM_NVE && p.ensemble != DEM_NVT) return fail(h, DEM_E_ARG, "bad ensemble");
+    if (p.ensemble != DEM_NVE && p.ensemble != DEM_NVT && p.ensemble != DEM_NPT) return fail(h, DEM_E_ARG, "bad ensemble");
     if (p.list_mode != DEM_LISTS_AUTO && p.list_mode != DEM_LISTS_MULTI) return fail(h, DEM_E_ARG, "bad list_mode");
     if (!(p.dt > 0.0) || !(p.skin >= 0.0) || !(p.rebuild_frac > 0.0) || !(p.epsilon > 0.0) || !(p.parallel_sin2 >= 0.0))
         return fail(h, DEM_E_ARG, "dt, epsilon, rebuild_frac must be > 0; skin, parallel_sin2 >= 0");
     if (p.ensemble == DEM_NVT && (!(p.kT > 0.0) || !(p.tau_T > 0.0)))
         return fail(h, DEM_E_ARG, "NVT needs kT > 0 and tau_T > 0");
+    if (p.ensemble == DEM_NPT && (!(p.kT > 0.0) || !(p.tau_T > 0.0) || !(p.tau_P > 0.0) || !(p.pressure >= 0.0) ||
+                                  p.n < 2))
+        return fail(h, DEM_E_ARG, "NPT needs kT, tau_T, tau_P > 0, pressure >= 0 and at least 2 particles");
     for (int a = 0; a < p.dim; ++a)
         if (!(p.box[a] > 0.0)) return fail(h, DEM_E_ARG, "box must be positive");
     R = Replica{};
@@ -830,6 +903,21 @@ dem_status describe_replica(dem_system *h, const dem_params &p, Replica &R, std:
     sp.kT = p.kT;
     const int drot = p.dim == 2 ? 1 : 3;
     sp.g = (double)(p.dim * p.n + drot * p.n - p.dim);
+    sp.rlist = rl;
+    for (int a = 0; a < 3; ++a) {
+        sp.nc0[a] = sp.nc[a];
+        sp.box_build[a] = sp.box[a];
+    }
+    if (p.ensemble == DEM_NPT) {
+        // Sec. IV.C barostat: N_f = d (n - 1) translational degrees of
+        // freedom, alpha = 1 + d / N_f, W = (N_f + d) kT tau_P^2; the
+        // thermostat also takes the barostat's degree of freedom
+        const double Nf = (double)(p.dim * (p.n - 1));
+        sp.alpha = 1.0 + p.dim / Nf;
+        sp.Wm = (Nf + p.dim) * p.kT * p.tau_P * p.tau_P;
+        sp.pext = p.pressure;
+        sp.g += 1.0;
+    }
     sp.Qm = sp.g * p.kT * p.tau_T * p.tau_T;
     return DEM_OK;
 }
@@ -903,6 +991,7 @@ dem_status place_replica(dem_system *h, Replica &R, const std::vector<ShapeTab<d
         HIPCHK(h, hipMemsetAsync(h->lst.pcell + off, 0, sizeof(int32_t) * n, h->stream));
     }
     k_set_thermo<<<1, 1, 0, h->stream>>>(h->thermo + TH_COUNT * slot, 0.0, 0.0);
+    k_set_baro<<<1, 1, 0, h->stream>>>(h->thermo + TH_COUNT * slot, R.sp.box[0], R.sp.box[1], R.sp.box[2]);
     k_set_i64<<<1, 1, 0, h->stream>>>(h->budget + slot, kUnbounded);
     k_set_i64<<<1, 1, 0, h->stream>>>(h->steps + slot, 0);
     h->chunks.mark(R.chunk0, R.nchunks, 1);
@@ -970,20 +1059,26 @@ dem_status finish_energy(dem_system *h, int r, const double acc[12], const doubl
                          const int32_t flags[FLAG_COUNT], int64_t steps, dem_energy_out *o)
 {
     const SysParams &sp = h->reps[r].sp;
+    const bool npt = sp.ensemble == DEM_NPT;
     o->U = acc[0];
     o->K_trans = acc[1];
     o->K_rot = acc[2];
     for (int c = 0; c < 9; ++c) o->W[c] = acc[3 + c];
     const double K = o->K_trans + o->K_rot;
-    o->T = sp.g > 0 ? 2.0 * K / sp.g : 0.0;
+    const double g = npt ? sp.g - 1.0 : sp.g;  // the particles' degrees of freedom
+    o->T = g > 0 ? 2.0 * K / g : 0.0;
     const int d = sp.dim;
-    const double vol = d == 3 ? sp.box[0] * sp.box[1] * sp.box[2] : sp.box[0] * sp.box[1];
+    for (int a = 0; a < 3; ++a) o->box[a] = npt ? th[TH_BOXN + a] : sp.box[a];  // the box of the positions
+    const double vol = d == 3 ? o->box[0] * o->box[1] * o->box[2] : o->box[0] * o->box[1];
+    o->V = vol;
     const double trW = d == 3 ? o->W[0] + o->W[4] + o->W[8] : o->W[0] + o->W[4];
     o->P = (2.0 * o->K_trans + trW) / (d * vol);
     o->xi = th[TH_XI_B];
     o->eta = th[TH_ETA_B];
+    o->veps = npt ? th[TH_VEPS_B] : 0.0;
     o->H = K + o->U;
-    if (sp.ensemble == DEM_NVT) o->H += 0.5 * sp.Qm * o->xi * o->xi + sp.g * sp.kT * o->eta;
+    if (sp.ensemble == DEM_NVT || npt) o->H += 0.5 * sp.Qm * o->xi * o->xi + sp.g * sp.kT * o->eta;
+    if (npt) o->H += 0.5 * sp.Wm * o->veps * o->veps + sp.pext * vol;
     o->step = steps;
     o->n_rebuilds = flags[FLAG_NBUILDS];
     if (flags[FLAG_NONFINITE]) return fail(h, DEM_E_NONFINITE, "non-finite position or velocity");
@@ -991,6 +1086,8 @@ dem_status finish_energy(dem_system *h, int r, const double acc[12], const doubl
         return fail(h, DEM_E_CAPACITY, "a cell held more than %d particles in a list build", kCellCap);
     if (flags[FLAG_MAXROW] > h->bp.cap)
         return fail(h, DEM_E_CAPACITY, "neighbour row of %d exceeds capacity %d", flags[FLAG_MAXROW], h->bp.cap);
+    if (flags[FLAG_BOXSMALL])
+        return fail(h, DEM_E_STATE, "the barostat shrank the box below twice the list radius %g", sp.rlist);
     return DEM_OK;
 }
 
@@ -1029,6 +1126,7 @@ dem_status replica_energy_noalloc(dem_system *h, int r, dem_energy_out *o)
 dem_status copy_lists(dem_system *h, int r, int32_t *cell_start, int32_t *cell_particles, int32_t *nbr,
                       int32_t *n_nbr, int32_t *dims)
 {
+    if (dem_status st = sync_dynamic(h); st != DEM_OK) return st;  // an NPT replica's cells follow its box
     const Replica &R = h->reps[r];
     const size_t n = (size_t)R.sp.n, off = (size_t)R.sp.off, N = (size_t)h->bp.N;
     std::vector<int32_t> pcell(n);
@@ -1415,6 +1513,16 @@ dem_status dem_set_thermostat(dem_handle h, double xi, double eta)
     return DEM_OK;
 }
 
+dem_status dem_set_barostat(dem_handle h, double veps)
+{
+    if (!h) return fail(nullptr, DEM_E_ARG, "null handle");
+    if (!valid_replica(h, 0) || h->reps[0].sp.ensemble != DEM_NPT) return fail(h, DEM_E_ARG, "not an NPT system");
+    if (!std::isfinite(veps)) return fail(h, DEM_E_ARG, "non-finite v_eps");
+    k_set_veps<<<1, 1, 0, h->stream>>>(h->thermo, veps);
+    HIPCHK(h, hipGetLastError());
+    return DEM_OK;
+}
+
 dem_status dem_copy_lists(dem_handle h, int32_t *cell_start, int32_t *cell_particles, int32_t *nbr, int32_t *n_nbr,
                           int32_t *dims)
 {
@@ -1544,7 +1652,7 @@ dem_status dem_get_state(dem_handle h, void *host_buf, size_t bytes)
     unsigned char *b = static_cast<unsigned char *>(host_buf);
     CheckpointHeader hd{};
     std::memcpy(hd.magic, kCheckpointMagic, 8);
-    hd.version = 1;
+    hd.version = 2;
     hd.dim = h->dim;
     hd.n = (int64_t)n;
     int32_t nb = 0;
@@ -1577,7 +1685,7 @@ dem_status dem_set_state(dem_handle h, const void *host_buf, size_t bytes)
     if (bytes < sizeof(CheckpointHeader)) return fail(h, DEM_E_ARG, "checkpoint too short");
     CheckpointHeader hd;
     std::memcpy(&hd, host_buf, sizeof hd);
-    if (std::memcmp(hd.magic, kCheckpointMagic, 8) != 0 || hd.version != 1)
+    if (std::memcmp(hd.magic, kCheckpointMagic, 8) != 0 || hd.version != 2)
         return fail(h, DEM_E_ARG, "not a checkpoint of this library");
     if (hd.dim != h->dim || hd.n != (int64_t)n) return fail(h, DEM_E_ARG, "checkpoint of another system");
     if (bytes < dem_state_bytes(h)) return fail(h, DEM_E_ARG, "checkpoint too short");
@@ -1593,9 +1701,11 @@ dem_status dem_set_state(dem_handle h, const void *host_buf, size_t bytes)
         HIPCHK(h, hipMemcpyAsync(h->st.image, isrc + n, sizeof(int32_t) * 3 * n, hipMemcpyHostToDevice, h->stream));
     }
     HIPCHK(h, hipMemcpyAsync(h->thermo, hd.thermo, sizeof hd.thermo, hipMemcpyHostToDevice, h->stream));
+    k_box_restore<<<1, 1, 0, h->stream>>>(h->d_reps, 0, h->lst, h->thermo);  // the box of the restored positions
     k_set_i64<<<1, 1, 0, h->stream>>>(h->steps, hd.step);
     // latched device errors belong to the state being replaced
-    for (int w : {FLAG_NONFINITE, FLAG_MAXROW, FLAG_CELLOVF}) k_set_i32<<<1, 1, 0, h->stream>>>(h->lst.flags + w, 0);
+    for (int w : {FLAG_NONFINITE, FLAG_MAXROW, FLAG_CELLOVF, FLAG_BOXSMALL})
+        k_set_i32<<<1, 1, 0, h->stream>>>(h->lst.flags + w, 0);
     HIPCHK(h, hipStreamSynchronize(h->stream));  // the host buffer may be freed on return
     dem_status st = build_lists_sync(h, LISTS_ALL);
     if (st == DEM_OK) st = compute_forces(h);

@@ -18,7 +18,8 @@ LIB_PATH = os.path.join(HERE, "libdem.so")
 HEADER = os.path.join(os.path.dirname(HERE), "include", "dem.h")
 
 DEM_FP64, DEM_FP32 = 0, 1
-DEM_NVE, DEM_NVT = 0, 1
+DEM_NVE, DEM_NVT, DEM_NPT = 0, 1, 2
+ENSEMBLES = {"nve": DEM_NVE, "nvt": DEM_NVT, "npt": DEM_NPT}
 STATUS = {0: "DEM_OK", 1: "DEM_E_ARG", 2: "DEM_E_SHAPE", 3: "DEM_E_OOM", 4: "DEM_E_HIP", 5: "DEM_E_CAPACITY",
           6: "DEM_E_NONFINITE", 7: "DEM_E_STATE"}
 
@@ -37,7 +38,8 @@ class Params(C.Structure):
                 ("shapes", C.POINTER(ShapeDesc)), ("epsilon", C.c_double), ("skin", C.c_double),
                 ("rebuild_frac", C.c_double), ("dt", C.c_double), ("ensemble", C.c_int32), ("kT", C.c_double),
                 ("tau_T", C.c_double), ("precision", C.c_int32), ("parallel_sin2", C.c_double),
-                ("nbr_capacity", C.c_int32), ("list_mode", C.c_int32)]
+                ("nbr_capacity", C.c_int32), ("list_mode", C.c_int32), ("pressure", C.c_double),
+                ("tau_P", C.c_double)]
 
 
 class StatePtrs(C.Structure):
@@ -65,7 +67,8 @@ class OutputView(C.Structure):
 class EnergyOut(C.Structure):
     _fields_ = [("U", C.c_double), ("K_trans", C.c_double), ("K_rot", C.c_double), ("H", C.c_double),
                 ("T", C.c_double), ("P", C.c_double), ("W", C.c_double * 9), ("xi", C.c_double),
-                ("eta", C.c_double), ("step", C.c_int64), ("n_rebuilds", C.c_int64)]
+                ("eta", C.c_double), ("step", C.c_int64), ("n_rebuilds", C.c_int64), ("V", C.c_double),
+                ("box", C.c_double * 3), ("veps", C.c_double)]
 
 
 class DemError(RuntimeError):
@@ -113,6 +116,8 @@ def lib():
         L.dem_energy.restype = st
         L.dem_set_thermostat.argtypes = [C.c_void_p, C.c_double, C.c_double]
         L.dem_set_thermostat.restype = st
+        L.dem_set_barostat.argtypes = [C.c_void_p, C.c_double]
+        L.dem_set_barostat.restype = st
         L.dem_copy_lists.argtypes = [C.c_void_p, _ip, _ip, _ip, _ip, _ip]
         L.dem_copy_lists.restype = st
         L.dem_list_info.argtypes = [C.c_void_p, _dp, _ip, _ip]
@@ -195,9 +200,11 @@ def make_params(system, precision: str = "fp64", nbr_capacity: int = 0, list_mod
     p.skin = system.skin
     p.rebuild_frac = system.rebuild_frac
     p.dt = system.dt
-    p.ensemble = DEM_NVT if system.ensemble == "nvt" else DEM_NVE
+    p.ensemble = ENSEMBLES[system.ensemble]
     p.kT = system.kT
     p.tau_T = system.tau_T
+    p.pressure = float(getattr(system, "P", 0.0))
+    p.tau_P = float(getattr(system, "tau_P", 0.0))
     p.precision = DEM_FP32 if precision == "fp32" else DEM_FP64
     p.parallel_sin2 = system.parallel_sin2
     p.nbr_capacity = nbr_capacity
@@ -260,7 +267,7 @@ def _state_np(t, template):
 
 def _energy_dict(e):
     return dict(U=e.U, K_trans=e.K_trans, K_rot=e.K_rot, H=e.H, T=e.T, P=e.P, W=np.array(e.W[:]), xi=e.xi,
-                eta=e.eta, step=e.step, n_rebuilds=e.n_rebuilds)
+                eta=e.eta, step=e.step, n_rebuilds=e.n_rebuilds, V=e.V, box=np.array(e.box[:]), veps=e.veps)
 
 
 def _lists_np(call, n, ncell, cap):
@@ -320,6 +327,8 @@ class DemSystem:
         thermo = getattr(system, "thermo", None)  # a stored state's Nose-Hoover (xi, eta)
         if thermo is not None:
             self.set_thermostat(*thermo)
+        if system.ensemble == "npt" and getattr(system, "veps", 0.0):
+            self._check(lib().dem_set_barostat(self.h, float(system.veps)), "dem_set_barostat")
 
     # ---------------------------------------------------------------- calls
     def _check(self, st, where):
@@ -415,9 +424,14 @@ class DemSystem:
         return _outputs_np(self.o, self.system.n)
 
     def state(self):
-        """Synchronises and returns a numpy copy of the system at its current state."""
+        """Synchronises and returns a numpy copy of the system at its current state (under
+        the barostat with its current box, barostat velocity and thermostat)."""
         self.sync()
-        return _state_np(self.t, self.system)
+        s = _state_np(self.t, self.system)
+        if self.system.ensemble == "npt":
+            e = self.energy()
+            s.box, s.veps, s.thermo = e["box"].copy(), e["veps"], (e["xi"], e["eta"])
+        return s
 
     def close(self):
         if getattr(self, "h", None):
@@ -543,7 +557,11 @@ class DemBatch:
         self._check(lib().dem_batch_read(self.h, int(rid), C.byref(_state_ptrs(t)), C.byref(_out_ptrs(o))),
                     "dem_batch_read")
         self.sync()
-        return _state_np(t, system), _outputs_np(o, n)
+        s = _state_np(t, system)
+        if system.ensemble == "npt":
+            e = self.energy(rid)
+            s.box, s.veps, s.thermo = e["box"].copy(), e["veps"], (e["xi"], e["eta"])
+        return s, _outputs_np(o, n)
 
     def force_stats(self, reset: bool = False):
         out = (C.c_int64 * 9)()
