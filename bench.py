@@ -333,10 +333,14 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--replicas", type=int, default=96, help="replicas of the batched workload")
     ap.add_argument("--batched-steps", type=int, default=500)
-    ap.add_argument("--requests", type=int, default=32, help="requests of the served trace")
+    ap.add_argument("--requests", type=int, default=256, help="requests of the served trace")
+    ap.add_argument("--serve-budget-mb", type=int, default=512,
+                    help="admission budget of the served leg (device MiB for the live requests)")
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-served", action="store_true")
     ap.add_argument("--no-scale", action="store_true", help="skip the 262,144-octahedra run")
+    ap.add_argument("--no-npt", action="store_true", help="skip the isothermal-isobaric cube run")
+    ap.add_argument("--npt-steps", type=int, default=2000)
     ap.add_argument("--scale-steps", type=int, default=300)
     ap.add_argument("--copy-mb", type=int, default=0,
                     help="finish with device copies of this many MiB (scale for the HBM byte counters)")
@@ -351,6 +355,7 @@ def main():
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU layout is design-only.",
               file=sys.stderr)
         sys.exit(2)
+    import numpy as np
     import torch
     from paper_1607_02427_amd import inputs as I
     assert torch.cuda.is_available(), "bench.py needs a GPU"
@@ -397,6 +402,25 @@ def main():
         line["plain_fp64"] = {"value": n * args.steps / (r64["gpu_ms"] * 1e-3), "ms_per_step": r64["gpu_ms"] / args.steps}
         line["fp32_over_plain"] = ptps / line["plain_fp64"]["value"]
         g64.close()
+    if not args.no_npt:
+        # the same cubes at fixed pressure (Sec. IV.C): the target is the
+        # state's own virial pressure, so the box breathes about its size
+        g0 = __import__("paper_1607_02427_amd.dem", fromlist=["dem"]).DemSystem(system, "fp32")
+        p0 = g0.energy()["P"]
+        g0.close()
+        snpt = system.copy()
+        snpt.ensemble, snpt.P, snpt.tau_P = "npt", p0, 0.5
+        log(f"[bench] npt: {n} cubes at P = {p0:.4f}, {args.npt_steps} steps")
+        gn, rn = run_path(snpt, "fp32", args.npt_steps, 100)
+        en = gn.energy()
+        gn.close()
+        line["npt"] = {"workload": f"{n} rounded cubes from the same stored state, NPT at P = {p0:.4f} (the state's "
+                                   f"virial pressure), tau_P 0.5, kT 1, dt 5e-4, {args.npt_steps} steps after 100",
+                       "value": n * args.npt_steps / (rn["gpu_ms"] * 1e-3), "unit": "particle-timesteps/s",
+                       "ms_per_step": rn["gpu_ms"] / args.npt_steps, "dtype": "f32", "target_P": p0,
+                       "final_P": en["P"], "final_V": en["V"], "start_V": float(np.prod(system.box)),
+                       "rebuilds": en["n_rebuilds"]}
+        log(f"[bench] npt {line['npt']['value']:.3e} PTPS, V {line['npt']['start_V']:.1f} -> {en['V']:.1f}")
     if not args.no_scale:
         big = I.octahedra_compressed()
         log(f"[bench] at scale: {big.n} octahedra, {args.scale_steps} steps")
@@ -439,7 +463,7 @@ def main():
         work = sum(s.n * s.steps for s in trace)
         log(f"[bench] served: {len(trace)} requests, {work:.3e} particle-steps, arrivals over "
             f"{trace[-1].arrival:.2f} s")
-        srv = serve.Server(budget_bytes=64 << 30, precision="fp32", max_replicas=len(trace) + 8,
+        srv = serve.Server(budget_bytes=args.serve_budget_mb << 20, precision="fp32", max_replicas=len(trace) + 8,
                            max_particles={2: sum(s.n for s in trace if s.dim == 2) + 64 * len(trace),
                                           3: sum(s.n for s in trace if s.dim == 3) + 64 * len(trace)},
                            chunk=100)
@@ -453,8 +477,10 @@ def main():
         line["served"] = {
             "workload": f"{len(trace)} requests, Poisson arrivals at 40/s, sizes log-uniform 256-65536, 2D rounded "
                         f"pentagons or 3D rounded cubes / octahedra, 1000-5000 NVT steps, kT U[0.5, 2]; "
-                        f"64 GiB admission budget, continuous batching in chunks of 100 steps",
+                        f"{args.serve_budget_mb} MiB admission budget, continuous batching in chunks of 100 steps",
             "requests": len(trace), "p50_latency_s": srs["p50_latency_s"], "p99_latency_s": srs["p99_latency_s"],
+            "budget_bytes": args.serve_budget_mb << 20, "peak_bytes": srv.peak_used,
+            "waited_on_memory": srs["waited_on_memory"],
             "value": srs["value"], "unit": "particle-timesteps/s", "makespan_s": srs["makespan_s"],
             "offered_load": work / trace[-1].arrival, "dtype": "f32",
             "sequential_plain_fp64": None if sqs is None else {

@@ -315,6 +315,7 @@ typedef struct {
     int64_t max_cells;            /* cell slots (a replica takes its cell count + 1); 0 = particles + 2 per replica */
     int32_t max_shapes;           /* shape-table slots; 0 = DEM_MAX_SHAPES per replica */
     int32_t nbr_capacity;         /* neighbour-row capacity of every replica; 0 = grows as replicas need */
+    int64_t hbm_budget_bytes;     /* admission budget: device bytes the live replicas may take; 0 = no limit */
 } dem_batch_params;
 
 /* Creates an empty batch; allocates all its device memory.  Synchronises. */
@@ -324,9 +325,13 @@ dem_status dem_batch_create(const dem_batch_params *params, void *hip_stream, de
  * batch; n <= 65536), copies the state from the caller's device arrays
  * (dem_state_ptrs, borrowed for the call only), builds its lists and
  * computes its forces.  The replica then advances with every dem_step for
- * `steps` steps (0 = without limit) and is held still after that.  Returns
- * DEM_E_OOM when no run of free particle, cell or shape slots fits it, and
- * DEM_E_CAPACITY when rows overflow a fixed capacity.  Synchronises. */
+ * `steps` steps (0 = without limit) and is held still after that.  Admission
+ * by footprint: the replica is charged dem_footprint_bytes(params) plus its
+ * state and outputs in the batch (16 doubles and 4 ints per particle slot,
+ * slots in runs of 64); returns DEM_E_OOM, with nothing changed, when that
+ * would take the live replicas' charge over hbm_budget_bytes, or when no run
+ * of free particle, cell or shape slots fits it; DEM_E_CAPACITY when rows
+ * overflow a fixed capacity.  Synchronises. */
 dem_status dem_batch_add(dem_handle h, const dem_params *params, const dem_state_ptrs *state, int64_t steps,
                          int32_t *replica_id);
 
@@ -345,9 +350,10 @@ dem_status dem_batch_set_steps(dem_handle h, int32_t replica_id, int64_t steps);
  * either array may be NULL), and latched device errors.  Synchronises. */
 dem_status dem_batch_progress(dem_handle h, int64_t *steps_left, int64_t *steps_done, int32_t count);
 
-/* out[8]: live replicas, replica slots, free particle slots, largest run of
- * free particle slots, free cell slots, free shape slots, row capacity,
- * particle slots. */
+/* out[10]: live replicas, replica slots, free particle slots, largest run
+ * of free particle slots, free cell slots, free shape slots, row capacity,
+ * particle slots, bytes charged to the live replicas, admission budget
+ * (0 = no limit). */
 dem_status dem_batch_info(dem_handle h, int64_t *out);
 
 /* dem_energy and dem_copy_lists for one replica of a batch (replica 0 is

@@ -1218,19 +1218,25 @@ __device__ inline void add_slot(double acc[16], const SlotRec<T> &w)
 constexpr int kRowWorkgroups = 2048;
 inline int row_workgroups(const BatchParams &b) { return pad8(std::min(b.nchunk * (kChunk / lb::kNbrPer), kRowWorkgroups)); }
 
+// The replicas that rebuild are found 64 at a time (one lane each); the
+// groups of each are dealt over the role workgroups, starting at a
+// replica-dependent workgroup so that small replicas spread out too.
 template <int DIM>
 __device__ void step_rows(const BatchParams &b, const SysParams *reps, const StatePtrs &s, const ListPtrs &l,
                           const int64_t *budget, int *buf, int first)
 {
-    const int nbn = b.nchunk * (kChunk / lb::kNbrPer);
-    const int nrole = (int)gridDim.x - first;
-    for (int vb = (int)blockIdx.x - first; vb < nbn; vb += nrole) {
-        const int r = l.chunk_rep[vb * lb::kNbrPer / kChunk];
-        if (r < 0) continue;
-        const SysParams &p = reps[r];
-        int32_t *fl = l.flags + r * FLAG_COUNT;
-        if (!lb::building(LISTS_STEP, r, p, fl, budget)) continue;
-        lb::nbr_rows<DIM>(b, p, s, l, fl, vb, buf);
+    const int nrole = (int)gridDim.x - first, me = (int)blockIdx.x - first;
+    for (int r0 = 0; r0 < b.nrep; r0 += 64) {
+        const int rl = r0 + (int)__lane_id();
+        const bool bld = rl < b.nrep && lb::building(LISTS_STEP, rl, reps[rl], l.flags + rl * FLAG_COUNT, budget);
+        for (unsigned long long m = __ballot(bld); m != 0ull; m &= m - 1ull) {
+            const int r = r0 + __builtin_ctzll(m);
+            const SysParams &p = reps[r];
+            int32_t *fl = l.flags + r * FLAG_COUNT;
+            const int g0 = p.off / lb::kNbrPer, ng = (p.n + lb::kNbrPer - 1) / lb::kNbrPer;
+            for (int k = (me + nrole - (int)(((long long)r * 977) % nrole)) % nrole; k < ng; k += nrole)
+                lb::nbr_rows<DIM>(b, p, s, l, fl, g0 + k, buf);
+        }
     }
 }
 
@@ -1410,10 +1416,18 @@ __global__ void __launch_bounds__(kGatherBlock) k_replica_tail(BatchParams b, Sy
             lb::plan<kGatherBlock>(b, reps, l, part, [&](int r) {
                 return reps[r].n > 0 && l.flags[r * FLAG_COUNT + FLAG_FILL] != 0;
             });
-        for (int c = fb; c < b.nchunk; c += nfb) {
-            const int r = l.chunk_rep[c];
-            if (r < 0 || !reps[r].live || l.flags[r * FLAG_COUNT + FLAG_FILL] == 0) continue;
-            lb::fill_chunk(b, reps[r], l, c, false, true);
+        // the replicas that rebuild, 64 at a time; their chunks dealt over
+        // the fill workgroups from a replica-dependent start
+        for (int r0 = 0; r0 < b.nrep; r0 += 64) {
+            const int rl = r0 + (int)__lane_id();
+            const bool bld = rl < b.nrep && reps[rl].live && reps[rl].n > 0 && l.flags[rl * FLAG_COUNT + FLAG_FILL] != 0;
+            for (unsigned long long m = __ballot(bld); m != 0ull; m &= m - 1ull) {
+                const int r = r0 + __builtin_ctzll(m);
+                const SysParams &p = reps[r];
+                const int c0 = p.off / kChunk, nc = (p.n + kChunk - 1) / kChunk;
+                for (int k = (fb + nfb - (int)(((long long)r * 977) % nfb)) % nfb; k < nc; k += nfb)
+                    lb::fill_chunk(b, p, l, c0 + k, false, true);
+            }
         }
         return;
     }

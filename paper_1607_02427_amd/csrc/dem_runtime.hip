@@ -66,6 +66,7 @@ struct SlotArena {
 struct Replica {
     bool live = false;
     bool on_device = false;      // its SysParams have been uploaded (the device's box is current)
+    size_t bytes = 0;            // device bytes charged against the batch's admission budget
     SysParams sp{};
     dem_params prm{};            // copy; shapes not kept
     double r_list = 0.0;
@@ -78,6 +79,7 @@ struct Replica {
 
 struct dem_system {
     bool batch = false;
+    size_t hbm_budget = 0, hbm_used = 0;  // admission budget (0: none) and the live replicas' charge
     int dim = 0, precision = 0;
     bool auto_cap = true;
     bool counting = false;
@@ -1224,7 +1226,7 @@ size_t dem_footprint_bytes(const dem_params *p)
     const size_t nch = (n + kChunk - 1) / kChunk;
     const size_t maxp = n * (size_t)cap / 2;
     return sizeof(int32_t) * (n * (size_t)cap + 4 * n + ncell * (1 + kCellCap) + 4 * maxp + nch + 2 * FLAG_COUNT + G_COUNT + 2) +
-           sizeof(double) * (3 * n + 14 * nch + TH_COUNT + 2) + sizeof(unsigned long long) * ST_COUNT +
+           sizeof(double) * (3 * n + (kKePer + 12) * nch + TH_COUNT + 2) + sizeof(unsigned long long) * ST_COUNT +
            (partrec_bytes(p->precision) + (p->precision == DEM_FP32 ? sizeof(PartRec64) : 0)) * n +
            rec_bytes(p->precision) * (size_t)cap * n + sizeof(uint32_t) * (size_t)slot_words(cap) * n + sizeof(SysParams) + 2 * DEM_MAX_SHAPES * sizeof(ShapeTab<double>) + 256;
 }
@@ -1296,11 +1298,13 @@ dem_status dem_batch_create(const dem_batch_params *bpar, void *hip_stream, dem_
     if (b.max_replicas < 1 || b.max_replicas > 65536) return fail(nullptr, DEM_E_ARG, "max_replicas out of range");
     if (b.max_particles < 1 || b.max_particles > (int64_t)INT32_MAX / 128)
         return fail(nullptr, DEM_E_ARG, "max_particles out of range");
-    if (b.max_cells < 0 || b.max_cells > (int64_t)INT32_MAX / 2 || b.max_shapes < 0 || b.nbr_capacity < 0)
+    if (b.max_cells < 0 || b.max_cells > (int64_t)INT32_MAX / 2 || b.max_shapes < 0 || b.nbr_capacity < 0 ||
+        b.hbm_budget_bytes < 0)
         return fail(nullptr, DEM_E_ARG, "negative or oversized limit");
     dem_system *h = new (std::nothrow) dem_system();
     if (!h) return fail(nullptr, DEM_E_OOM, "host allocation");
     h->batch = true;
+    h->hbm_budget = (size_t)b.hbm_budget_bytes;
     h->dim = b.dim;
     h->precision = b.precision;
     h->stream = (hipStream_t)hip_stream;
@@ -1337,10 +1341,18 @@ dem_status dem_batch_add(dem_handle h, const dem_params *params, const dem_state
     std::vector<ShapeTab<float>> t32;
     dem_status st = describe_replica(h, *params, R, t64, t32);
     if (st != DEM_OK) return st;
-    if (R.nchunks * kChunk > h->Ncap) return fail(h, DEM_E_OOM, "replica larger than the batch");
+    const size_t slots = (size_t)((params->n + kChunk - 1) / kChunk) * kChunk;
+    if (slots > (size_t)h->Ncap) return fail(h, DEM_E_OOM, "replica larger than the batch");
+    // admission by footprint: its lists, cells and scratch, plus its state
+    // and outputs in the batch's arrays
+    R.bytes = dem_footprint_bytes(params) + slots * (16 * sizeof(double) + 4 * sizeof(int32_t));
+    if (h->hbm_budget > 0 && h->hbm_used + R.bytes > h->hbm_budget)
+        return fail(h, DEM_E_OOM, "replica of %zu bytes does not fit the admission budget (%zu of %zu bytes in use)",
+                    R.bytes, h->hbm_used, h->hbm_budget);
     const int want = h->auto_cap ? auto_capacity(*params, R.r_list) : h->bp.cap;
     int rid = -1;
     if ((st = place_replica(h, R, t64, t32, state, &rid)) != DEM_OK) return st;
+    h->hbm_used += R.bytes;
     if (want > h->bp.cap) {
         if ((st = alloc_nbr(h, want)) != DEM_OK) return st;
     }
@@ -1357,6 +1369,7 @@ dem_status dem_batch_remove(dem_handle h, int32_t rid)
     if (!h || !h->batch) return fail(h, DEM_E_ARG, "not a batch handle");
     if (!valid_replica(h, rid)) return fail(h, DEM_E_ARG, "no replica %d", rid);
     k_retire_flags<<<1, 1, 0, h->stream>>>(h->lst.flags + FLAG_COUNT * rid, h->lst.gflags);
+    h->hbm_used -= std::min(h->hbm_used, h->reps[rid].bytes);
     release_replica(h, rid);
     place_pairs(h);
     dem_status st = upload_tables(h);
@@ -1445,6 +1458,8 @@ dem_status dem_batch_info(dem_handle h, int64_t *out)
     out[5] = h->shapes.free_slots();
     out[6] = h->bp.cap;
     out[7] = h->Ncap;
+    out[8] = (int64_t)h->hbm_used;
+    out[9] = (int64_t)h->hbm_budget;
     return DEM_OK;
 }
 

@@ -54,7 +54,7 @@ class OutPtrs(C.Structure):
 class BatchParams(C.Structure):
     _fields_ = [("dim", C.c_int32), ("precision", C.c_int32), ("max_replicas", C.c_int32),
                 ("max_particles", C.c_int64), ("max_cells", C.c_int64), ("max_shapes", C.c_int32),
-                ("nbr_capacity", C.c_int32)]
+                ("nbr_capacity", C.c_int32), ("hbm_budget_bytes", C.c_int64)]
 
 
 class OutputView(C.Structure):
@@ -458,7 +458,7 @@ class DemBatch:
 
     def __init__(self, dim: int, precision: str = "fp32", max_replicas: int = 128, max_particles: int = 1 << 20,
                  max_cells: int = 0, max_shapes: int = 0, nbr_capacity: int = 0, device: str = "cuda:0",
-                 stream=None):
+                 stream=None, budget_bytes: int = 0):
         import torch
         self.torch = torch
         self.dim = dim
@@ -468,7 +468,7 @@ class DemBatch:
         self.systems = {}
         bp = BatchParams(dim=dim, precision=DEM_FP32 if precision == "fp32" else DEM_FP64, max_replicas=max_replicas,
                          max_particles=max_particles, max_cells=max_cells, max_shapes=max_shapes,
-                         nbr_capacity=nbr_capacity)
+                         nbr_capacity=nbr_capacity, hbm_budget_bytes=int(budget_bytes))
         h = C.c_void_p()
         torch.cuda.synchronize(self.device)
         with torch.cuda.device(self.device):
@@ -519,11 +519,11 @@ class DemBatch:
         return np.array(left[:count]), np.array(done[:count])
 
     def info(self):
-        out = (C.c_int64 * 8)()
+        out = (C.c_int64 * 10)()
         self._check(lib().dem_batch_info(self.h, out), "dem_batch_info")
         keys = ("live", "slots", "free_particles", "largest_free_run", "free_cells", "free_shapes", "capacity",
-                "particle_slots")
-        return dict(zip(keys, out[:8]))
+                "particle_slots", "bytes_charged", "budget_bytes")
+        return dict(zip(keys, out[:10]))
 
     def energy(self, rid: int):
         e = EnergyOut()

@@ -5,7 +5,10 @@ Requests (systems with an `arrival` time in seconds and a step count
 `steps`) wait in a FIFO queue until the device has room for them: a request
 is admitted when its device footprint (dem_footprint_bytes plus its state
 and outputs) fits in what is left of the memory budget and the batch of its
-dimension has a free run of particle slots.  Admitted requests join a
+dimension has a free run of particle slots.  The budget is enforced twice:
+here across both dimensions' batches, and by each batch itself
+(dem_batch_add returns DEM_E_OOM over the budget it was created with); a
+request that waits on memory is marked so in its record.  Admitted requests join a
 replica batch (one per dimension) whose every dem_step advances all live
 replicas at once; each replica carries its own step budget, so it stops
 exactly at its requested step count, and it is retired (its state copied
@@ -42,6 +45,7 @@ class Record:
     admitted: float = float("nan")
     finished: float = float("nan")
     result: Optional[tuple] = None
+    waited_on_memory: bool = False
 
     @property
     def latency(self) -> float:
@@ -68,11 +72,12 @@ class Server:
         self.batches: Dict[int, dem.DemBatch] = {}
         self.tuned_at: Dict[int, int] = {}  # live particles of each batch when its pair shape was last tuned
         self.used = 0
+        self.peak_used = 0
 
     def _batch(self, dim: int) -> dem.DemBatch:
         if dim not in self.batches:
             self.batches[dim] = dem.DemBatch(dim, self.precision, max_replicas=self.max_replicas,
-                                             max_particles=self.max_particles[dim])
+                                             max_particles=self.max_particles[dim], budget_bytes=self.budget)
         return self.batches[dim]
 
     def run(self, systems: List, log: Optional[Callable[[str], None]] = None) -> List[Record]:
@@ -95,17 +100,19 @@ class Server:
                 s = systems[k]
                 c = request_bytes(s, self.precision)
                 if self.used + c > self.budget:
+                    recs[k].waited_on_memory = True
                     continue
                 try:
                     rid = self._batch(s.dim).add(s, steps=int(s.steps))
                 except dem.DemError as e:
-                    if e.status == 3:  # no free slots of the right size yet
+                    if e.status == 3:  # over the batch's budget, or no free slots of the right size yet
                         continue
                     raise
                 queue.remove(k)
                 live[(s.dim, rid)] = k
                 cost[k] = c
                 self.used += c
+                self.peak_used = max(self.peak_used, self.used)
                 recs[k].admitted = self.clock() - t0
             if not live:
                 if pending:  # idle until the next arrival
@@ -155,7 +162,8 @@ def summarize(recs: List[Record]) -> dict:
     makespan = max(r.finished for r in recs) - min(r.arrival for r in recs)
     return dict(requests=len(recs), p50_latency_s=float(np.percentile(lat, 50)),
                 p99_latency_s=float(np.percentile(lat, 99)), mean_latency_s=float(lat.mean()),
-                makespan_s=float(makespan), particle_steps=int(work), value=work / makespan)
+                makespan_s=float(makespan), particle_steps=int(work), value=work / makespan,
+                waited_on_memory=int(sum(r.waited_on_memory for r in recs)))
 
 
 def run_sequential(systems: List, precision: str = "fp64", clock: Callable[[], float] = time.perf_counter,

@@ -193,3 +193,57 @@ def test_served_requests_equal_solo():
         st, out = r.result
         solo = _solo(dem, s, "fp32", s.steps)
         _same((st, out), solo[:2])
+
+
+def test_batch_admission_budget():
+    """dem_batch_add charges each replica its footprint (lists, cells,
+    scratch, state and outputs) against the batch's admission budget and
+    returns DEM_E_OOM, with nothing changed, when a replica does not fit;
+    removing a replica returns its charge."""
+    dem = _dem()
+    from paper_1607_02427_amd import serve
+    a, b = I.cubes_3d(n_side=5), I.cubes_3d_contact(n_side=6)
+    ca, cb = serve.request_bytes(a, "fp32"), serve.request_bytes(b, "fp32")
+    with dem.DemBatch(3, "fp32", max_replicas=4, max_particles=4096, budget_bytes=max(ca, cb) + min(ca, cb) // 2) as B:
+        ra = B.add(a)
+        assert B.info()["bytes_charged"] == ca
+        with pytest.raises(dem.DemError) as ex:
+            B.add(b)
+        assert ex.value.status == 3 and "admission budget" in str(ex.value)
+        assert B.info()["live"] == 1 and B.info()["bytes_charged"] == ca
+        B.remove(ra)
+        assert B.info()["bytes_charged"] == 0
+        rb = B.add(b)
+        assert B.info()["bytes_charged"] == cb
+        B.step(10)
+        _, out = B.read(rb)
+        assert np.isfinite(out["F"]).all()
+
+
+def test_served_requests_wait_on_memory():
+    """A budget that holds the largest request and little more:
+    later arrivals wait for memory (not for slots) until earlier requests
+    retire, and every result is still the request's solo result bit for bit."""
+    dem = _dem()
+    from paper_1607_02427_amd import serve
+    reqs = [I.replica_system(I.cube(r=0.15), 512, 0.4, 51, dt=5e-4),
+            I.replica_system(I.octahedron(r=0.2), 400, 0.3, 52, dt=2e-4, kT=0.7),
+            I.replica_system(I.tetrahedron(r=0.1), 450, 0.3, 53, dt=5e-4),
+            I.replica_system(I.cube(r=0.2), 300, 0.35, 54, dt=5e-4, kT=1.3)]
+    for k, (t, n) in enumerate([(0.0, 120), (0.0, 90), (0.01, 60), (0.02, 75)]):
+        reqs[k].arrival = t
+        reqs[k].steps = n
+    budget = int(1.05 * max(serve.request_bytes(s, "fp32") for s in reqs))
+    srv = serve.Server(budget_bytes=budget, precision="fp32", max_replicas=8, max_particles={3: 8192}, chunk=20,
+                       keep_results=True)
+    try:
+        recs = srv.run(reqs)
+    finally:
+        srv.close()
+    waited = [r for r in recs if r.waited_on_memory]
+    print(f"[serve] budget {budget} bytes, peak {srv.peak_used}, {len(waited)} requests waited on memory", flush=True)
+    assert waited and srv.peak_used <= budget
+    assert all(r.admitted > r.arrival for r in waited)
+    for r, s in zip(recs, reqs):
+        st, out = r.result
+        _same((st, out), _solo(dem, s, "fp32", s.steps)[:2])
