@@ -318,7 +318,7 @@ def table1_workloads(steps=(2000, 1000, 300), warmup=200):
             g.close()
             ptps = s.n * k / (r["gpu_ms"] * 1e-3)
             out.append(dict(shape=name, n=s.n, steps=k, value=ptps, ms_per_step=r["gpu_ms"] / k,
-                            pair_shape=[r["pair_shape"][a] for a in ("lanes", "grid", "waves", "sep")]))
+                            pair_shape=[r["pair_shape"][a] for a in ("lanes", "grid", "waves", "sep", "split")]))
             log(f"[table1] {name} N={s.n}: {ptps:.3e} PTPS ({r['gpu_ms'] / k * 1e3:.1f} us/step)")
     return out
 

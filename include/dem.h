@@ -267,23 +267,31 @@ dem_status dem_time_forces(dem_handle h, int32_t reps, double *mean_ms);
  * trips, 2 gives the compiler more registers); and sep_lanes (4, or 16 with
  * 16 lanes per pair) lanes take one pair in the separation stage, so a
  * wavefront settles 16 or 4 pairs at a time and a tile holds 64 or 16
- * pairs (16 spreads a small system over four times the wavefronts).  The
- * default is {16, 1, 2, 4}.  The next dem_step captures its graph again.
+ * pairs (16 spreads a small system over four times the wavefronts).
+ * split (0 or 1, the latter with sep_lanes 4) separates the contact search
+ * from the force evaluation, the two-step form Sec. V proposes: a search
+ * kernel runs the separation stage alone at 4 wavefronts per SIMD and
+ * compacts the pairs no supporting plane separates, per replica, into a
+ * buffer as large as the pair entries; a force kernel then gives each
+ * wavefront one feature round of those pairs (lanes_per_pair and
+ * waves_per_simd apply to it; grid_factor does not).  The default is
+ * {16, 1, 2, 4, 0}.  The next dem_step captures its graph again.
  * DEM_E_ARG for other values. */
-enum { DEM_PAIR_SHAPES = 12 };
+enum { DEM_PAIR_SHAPES = 16 };
 dem_status dem_set_pair_shape(dem_handle h, int32_t lanes_per_pair, int32_t grid_factor, int32_t waves_per_simd,
-                              int32_t sep_lanes);
+                              int32_t sep_lanes, int32_t split);
 
 /* Pair-shape autotuner: times `reps` launches of the pair kernel on the
  * current state for each of the DEM_PAIR_SHAPES shapes {lanes, factor,
- * waves, sep} = {16,1,2,4}, {8,1,2,4}, {16,2,2,4}, {8,2,2,4}, {16,1,3,4},
- * {8,1,3,4}, {16,2,3,4}, {8,2,3,4}, {16,1,2,16}, {16,2,2,16}, {16,1,3,16},
- * {16,2,3,16} (HIP events on the handle's stream) and keeps the fastest.
- * Outputs (each may be null): shape[4] receives the chosen {lanes, factor,
- * waves, sep}, mean_ms[DEM_PAIR_SHAPES] the mean launch time in ms of every
- * shape, in that order.  The state and lists are not changed; the records
- * of the pair kernel are overwritten by the next step as always.
- * Synchronises. */
+ * waves, sep, split} = {16,1,2,4,0}, {8,1,2,4,0}, {16,2,2,4,0}, {8,2,2,4,0},
+ * {16,1,3,4,0}, {8,1,3,4,0}, {16,2,3,4,0}, {8,2,3,4,0}, {16,1,2,16,0},
+ * {16,2,2,16,0}, {16,1,3,16,0}, {16,2,3,16,0}, {16,1,2,4,1}, {8,1,2,4,1},
+ * {16,1,3,4,1}, {8,1,3,4,1} (HIP events on the handle's stream) and keeps
+ * the fastest.  Outputs (each may be null): shape[5] receives the chosen
+ * {lanes, factor, waves, sep, split}, mean_ms[DEM_PAIR_SHAPES] the mean
+ * launch time in ms of every shape (both kernels of a split shape), in
+ * that order.  The state and lists are not changed; the records of the
+ * pair kernel are overwritten by the next step as always.  Synchronises. */
 dem_status dem_tune_pairs(dem_handle h, int32_t reps, int32_t *shape, double *mean_ms);
 
 /* Bytes of device memory the library would allocate for these parameters

@@ -504,12 +504,13 @@ struct alignas(16) RepLds {
     double box[3];
     double R[DEM_MAX_SHAPES], rad[DEM_MAX_SHAPES];
     double eps, par_s2;
-    int r, sbase, np, poff, first_tile, pad[3];
+    int r, sbase, np, poff, first_tile, ncmp, last, pad;
 };
 
 // Stages replica r: its shape tables and parameters.  Every thread of the
-// block calls it together.
-template <typename T>
+// block calls it together.  UNITS: the block walks force units of the
+// replica's compacted pairs (split form) instead of its pair tiles.
+template <typename T, bool UNITS = false>
 __device__ void stage_replica(const SysParams *reps, const ListPtrs &l, const ShapeTab<T> *gtab, ShapeTab<T> *tab,
                               RepLds &rl, int r)
 {
@@ -534,11 +535,11 @@ __device__ void stage_replica(const SysParams *reps, const ListPtrs &l, const Sh
             if (w < n16) dst[w] = v[u];
         }
     }
-    if (threadIdx.x < DEM_MAX_SHAPES) {
-        rl.R[threadIdx.x] = p.R[threadIdx.x];
-        rl.rad[threadIdx.x] = p.rad[threadIdx.x];
-    }
-    if (threadIdx.x == 0) {
+    if (threadIdx.x == 0) {  // (one thread: the LDS addresses stay scalar)
+        for (int k = 0; k < DEM_MAX_SHAPES; ++k) {
+            rl.R[k] = p.R[k];
+            rl.rad[k] = p.rad[k];
+        }
         for (int a = 0; a < 3; ++a) rl.box[a] = p.box[a];
         rl.eps = p.eps;
         rl.par_s2 = p.par_s2;
@@ -546,9 +547,21 @@ __device__ void stage_replica(const SysParams *reps, const ListPtrs &l, const Sh
         rl.sbase = p.sbase;
         rl.np = l.flags[r * FLAG_COUNT + FLAG_NPAIRS];
         rl.poff = p.poff;
-        rl.first_tile = l.tile_start[r];
+        rl.first_tile = UNITS ? l.cunit[r] : l.tile_start[r];
+        rl.ncmp = UNITS ? l.ccount[r] : 0;
     }
     __syncthreads();
+}
+
+// j's body frame in i's, R_i^T R_j (rows of R are body axes in space).
+template <typename T>
+__device__ inline M3<T> rel_rotation(const M3<T> &Ri, const M3<T> &Rj)
+{
+    M3<T> Rr;
+    for (int a = 0; a < 3; ++a)
+        for (int c = 0; c < 3; ++c)
+            Rr.m[3 * a + c] = Ri.m[a] * Rj.m[c] + Ri.m[3 + a] * Rj.m[3 + c] + Ri.m[6 + a] * Rj.m[6 + c];
+    return Rr;
 }
 
 // A live pair that no supporting plane separates, parked in its wave's LDS
@@ -606,7 +619,7 @@ struct Tally<false> {
 // the compiler must fit 168 registers and schedules with less freedom.  The
 // uncounted variants fit without spilling because the feature stage reads
 // the pair's transform from the LDS queue instead of holding it.
-template <typename T, int DIM, int GL, bool COUNT, int OCC, int SL>
+template <typename T, int DIM, int GL, bool COUNT, int OCC, int SL, int STAGE>
 __global__ void __launch_bounds__(64 * kWaves, OCC) k_pairs(BatchParams b, const SysParams *__restrict__ reps, StatePtrs s,
                                                           ListPtrs l, const PartRec<T> *__restrict__ prec,
                                                           const PartRec64 *__restrict__ rec64,
@@ -615,8 +628,11 @@ __global__ void __launch_bounds__(64 * kWaves, OCC) k_pairs(BatchParams b, const
                                                           unsigned long long *stats)
 {
     static_assert(GL == 8 || GL == 16, "8 or 16 lanes per pair");
-    static_assert(OCC == 2 || OCC == 3, "2 or 3 wavefronts per SIMD");
+    static_assert(OCC >= 2 && OCC <= 4, "2 to 4 wavefronts per SIMD");
     static_assert(SL == 4 || SL == 16, "4 or 16 lanes per pair in the separation stage");
+    static_assert(STAGE >= kFused && STAGE <= kForces, "fused, search or forces");
+    constexpr bool kSearch = STAGE == kSearchOnly;  // first stage only: compact the pairs it keeps
+    constexpr bool kForce = STAGE == kForces;       // second stage only, on the compacted pairs
     constexpr int kSepLanes = SL;
     constexpr int kPairsPerWave = 64 / SL;
     constexpr int kGL = GL;                                    // lanes per particle pair
@@ -647,7 +663,11 @@ __global__ void __launch_bounds__(64 * kWaves, OCC) k_pairs(BatchParams b, const
     const unsigned stamp = (unsigned)l.gflags[G_STAMP];
     const int G = gridDim.x, per = G >> 3;
     const int lb = (blockIdx.x & 7) * per + (blockIdx.x >> 3);
-    const int t0 = (int)((long long)ntiles * lb / G), t1 = (int)((long long)ntiles * (lb + 1) / G);
+    // the force kernel's units: kWaves * kGroups compacted pairs of one
+    // replica, so each wavefront takes one feature round
+    const int *first = kForce ? l.cunit : l.tile_start;
+    const int nunits = kForce ? l.cunit[b.nrep] : ntiles;
+    const int t0 = (int)((long long)nunits * lb / G), t1 = (int)((long long)nunits * (lb + 1) / G);
     const T grow = T(1.00001);
     Tally<COUNT> c_pairs, c_feat, c_in, c_near, c_ee, c_ref, c_sep, c_pv;
 
@@ -656,12 +676,12 @@ __global__ void __launch_bounds__(64 * kWaves, OCC) k_pairs(BatchParams b, const
         int lo = 0, hi = b.nrep;
         while (hi - lo > 1) {
             const int mid = (lo + hi) >> 1;
-            if (l.tile_start[mid] <= t0) lo = mid;
+            if (first[mid] <= t0) lo = mid;
             else hi = mid;
         }
         r = lo;
-        r_end = l.tile_start[r + 1];
-        stage_replica(reps, l, gtab, tab, rl, r);
+        r_end = first[r + 1];
+        stage_replica<T, kForce>(reps, l, gtab, tab, rl, r);
     }
     int head = 0, tail = 0;  // queue positions, the same in every lane of the wave
     int tt = t0;
@@ -669,7 +689,7 @@ __global__ void __launch_bounds__(64 * kWaves, OCC) k_pairs(BatchParams b, const
         const bool done = tt >= t1;
         const bool restage = !done && tt >= r_end;
         const int pending = tail - head;
-        if (pending >= kGroups || (pending > 0 && (done || restage))) {
+        if (!kSearch && (pending >= kGroups || (pending > 0 && (kForce || done || restage)))) {
             // ---- second stage: group g takes queue entry head + g ----
             const int take = pending < kGroups ? pending : kGroups;
             const bool live = grp < take;
@@ -996,9 +1016,50 @@ __global__ void __launch_bounds__(64 * kWaves, OCC) k_pairs(BatchParams b, const
         if (restage) {
             do {
                 ++r;
-                r_end = l.tile_start[r + 1];
+                r_end = first[r + 1];
             } while (tt >= r_end);
-            stage_replica(reps, l, gtab, tab, rl, r);
+            stage_replica<T, kForce>(reps, l, gtab, tab, rl, r);
+        }
+        if constexpr (kForce) {
+            // ---- unit tt: this wave's kGroups compacted pairs, one lane each ----
+            // (uniform over the wave: the queue positions stay scalar)
+            const int base = __builtin_amdgcn_readfirstlane((tt - rl.first_tile) * (kWaves * kGroups) + wid * kGroups);
+            const int left = __builtin_amdgcn_readfirstlane(rl.ncmp) - base;
+            const int n = left < 0 ? 0 : (left > kGroups ? kGroups : left);
+            head = tail = 0;  // the queue is empty between units
+            if (lane < n) {
+                const int4 ent = l.cpairs[rl.poff + base + lane];
+                const PartRec<T> ri = prec[ent.x];
+                const PartRec<T> rj = prec[ent.y];
+                M3<T> Ri, Rj;
+                for (int k = 0; k < 9; ++k) {
+                    Ri.m[k] = ri.R[k];
+                    Rj.m[k] = rj.R[k];
+                }
+                const double dx = min_image(rj.x - ri.x, rl.box[0]);
+                const double dy = min_image(rj.y - ri.y, rl.box[1]);
+                const double dz = (DIM == 3) ? min_image(rj.z - ri.z, rl.box[2]) : 0.0;
+                const M3<T> Rr = rel_rotation(Ri, Rj);
+                const V3<T> t = mulT(Ri, v3<T>((T)dx, (T)dy, (T)dz));
+                QEnt<T> &e = qb[lane];
+                e.ent = ent;
+                e.si = ri.sid;
+                e.sj = rj.sid;
+                for (int k = 0; k < 9; ++k) {
+                    e.Rr[k] = Rr.m[k];
+                    e.Ri[k] = Ri.m[k];
+                }
+                e.t[0] = t.x;
+                e.t[1] = t.y;
+                e.t[2] = t.z;
+                e.d[0] = (T)dx;
+                e.d[1] = (T)dy;
+                e.d[2] = (T)dz;
+            }
+            tail = n;
+            wave_sync_lds();
+            ++tt;
+            continue;
         }
         // ---- first stage on tile tt: 4 lanes per pair ----
         const int grp1 = lane / kSepLanes, sub1 = lane % kSepLanes;
@@ -1038,9 +1099,7 @@ __global__ void __launch_bounds__(64 * kWaves, OCC) k_pairs(BatchParams b, const
             T rc = T(0), Bi = T(0), Bj = T(0);
             for (int k = 0; k < 9; ++k) Rr.m[k] = T(0);
             if (live) {
-                for (int a = 0; a < 3; ++a)
-                    for (int c = 0; c < 3; ++c)
-                        Rr.m[3 * a + c] = Ri.m[a] * Rj.m[c] + Ri.m[3 + a] * Rj.m[3 + c] + Ri.m[6 + a] * Rj.m[6 + c];
+                Rr = rel_rotation(Ri, Rj);
                 t = mulT(Ri, v3<T>((T)dx, (T)dy, (T)dz));
                 rc = (T)(kWcaCut * (rl.rad[si] + rl.rad[sj]));
                 Bi = (T)rl.R[si] + rc;
@@ -1102,7 +1161,15 @@ __global__ void __launch_bounds__(64 * kWaves, OCC) k_pairs(BatchParams b, const
             }
             // queue the pairs that need the feature stage, one entry per group
             const unsigned long long m = __ballot(need && sub1 == 0);
-            if (need && sub1 == 0) {
+            if constexpr (kSearch) {
+                // or, in the split form, append them to the replica's compacted pairs
+                if (m != 0) {
+                    int at = 0;
+                    if (lane == 0) at = atomicAdd(&l.ccount[rl.r], (int)__popcll(m));
+                    at = __shfl(at, 0);
+                    if (need && sub1 == 0) l.cpairs[rl.poff + at + __popcll(m & below)] = ent;
+                }
+            } else if (need && sub1 == 0) {
                 QEnt<T> &e = qb[(tail + __popcll(m & below)) % kQCap];
                 e.ent = ent;
                 e.si = si;
@@ -1122,6 +1189,33 @@ __global__ void __launch_bounds__(64 * kWaves, OCC) k_pairs(BatchParams b, const
         }
         wave_sync_lds();  // the queue entries are visible to every lane
         ++tt;
+    }
+    if constexpr (kSearch || kForce) {
+        // the last workgroup to finish: after the search, the force units
+        // of each replica; after the forces, the counts back to zero for
+        // the next evaluation (every workgroup has read them by then)
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            __threadfence();
+            rl.last = atomicAdd(&l.ctick[kSearch ? 0 : 1], 1) == (int)gridDim.x - 1 ? 1 : 0;
+        }
+        __syncthreads();
+        if (rl.last) {
+            if constexpr (kSearch) {
+                const int per_unit = kWaves * (64 / b.pair_lanes);
+                for (int q = threadIdx.x; q < b.nrep; q += blockDim.x) {
+                    const int c = __hip_atomic_load(&l.ccount[q], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    l.cunit[q] = (c + per_unit - 1) / per_unit;
+                }
+                __syncthreads();
+                int *part = reinterpret_cast<int *>(pls);  // LDS the search does not use
+                const int total = lb::block_scan<64 * kWaves>(l.cunit, l.cunit, b.nrep, part);
+                if (threadIdx.x == 0) l.cunit[b.nrep] = total;
+            } else {
+                for (int q = threadIdx.x; q < b.nrep; q += blockDim.x) l.ccount[q] = 0;
+            }
+            if (threadIdx.x == 0) l.ctick[kSearch ? 0 : 1] = 0;
+        }
     }
     if (COUNT && stats) {
         const unsigned cnt[8] = {c_pairs.get(), c_feat.get(), c_in.get(), c_near.get(), c_ref.get(), c_ee.get(),
@@ -1547,36 +1641,43 @@ __global__ void k_rotations(BatchParams b, const SysParams *reps, StatePtrs s, L
     if (sizeof(T) == 4) rec64[i] = PartRec64{rc.x, rc.y, rc.z, s.qw[i], s.qx[i], s.qy[i], s.qz[i], 0.0};
 }
 
-template <typename T, int DIM, int GL, int OCC, int SL>
+template <typename T, int DIM, int GL, int OCC, int SL, int STAGE>
 void pairs_t(const Launch &L, unsigned long long *stats, hipStream_t stream);
 
 // The compiled shapes: {8, 16} lanes per pair x {2, 3} wavefronts per SIMD
 // with the 4-lane separation stage, and 16 lanes x {2, 3} with the 16-lane
-// one.
+// one; in the split form, the search kernel (4-lane separation stage,
+// kSearchOcc wavefronts per SIMD) and then the force kernel at {8, 16}
+// lanes x {2, 3} wavefronts.
 template <typename T, int DIM>
 void pairs_shape(const Launch &L, unsigned long long *stats, hipStream_t stream)
 {
     const bool g8 = L.b.pair_lanes == 8, o3 = L.b.pair_waves == 3;
-    if (L.b.pair_sep == 16) o3 ? pairs_t<T, DIM, 16, 3, 16>(L, stats, stream) : pairs_t<T, DIM, 16, 2, 16>(L, stats, stream);
-    else if (g8) o3 ? pairs_t<T, DIM, 8, 3, 4>(L, stats, stream) : pairs_t<T, DIM, 8, 2, 4>(L, stats, stream);
-    else o3 ? pairs_t<T, DIM, 16, 3, 4>(L, stats, stream) : pairs_t<T, DIM, 16, 2, 4>(L, stats, stream);
+    if (L.b.pair_split) {
+        pairs_t<T, DIM, 16, kSearchOcc, 4, kSearchOnly>(L, stats, stream);
+        if (g8) o3 ? pairs_t<T, DIM, 8, 3, 4, kForces>(L, stats, stream) : pairs_t<T, DIM, 8, 2, 4, kForces>(L, stats, stream);
+        else o3 ? pairs_t<T, DIM, 16, 3, 4, kForces>(L, stats, stream) : pairs_t<T, DIM, 16, 2, 4, kForces>(L, stats, stream);
+    } else if (L.b.pair_sep == 16)
+        o3 ? pairs_t<T, DIM, 16, 3, 16, kFused>(L, stats, stream) : pairs_t<T, DIM, 16, 2, 16, kFused>(L, stats, stream);
+    else if (g8) o3 ? pairs_t<T, DIM, 8, 3, 4, kFused>(L, stats, stream) : pairs_t<T, DIM, 8, 2, 4, kFused>(L, stats, stream);
+    else o3 ? pairs_t<T, DIM, 16, 3, 4, kFused>(L, stats, stream) : pairs_t<T, DIM, 16, 2, 4, kFused>(L, stats, stream);
 }
 
-template <typename T, int DIM, int GL, int OCC, int SL>
+template <typename T, int DIM, int GL, int OCC, int SL, int STAGE>
 void pairs_t(const Launch &L, unsigned long long *stats, hipStream_t stream)
 {
-    const size_t sh = pair_kernel_lds(sizeof(T) == 4 ? DEM_FP32 : DEM_FP64, L.b.tab_slots, GL, SL);
-    const int grid = L.b.pair_blocks;
+    const size_t sh = pair_kernel_lds(sizeof(T) == 4 ? DEM_FP32 : DEM_FP64, L.b.tab_slots, GL, SL, STAGE);
+    const int grid = STAGE == kSearchOnly ? L.b.search_blocks : L.b.pair_blocks;
     const auto rot = reinterpret_cast<const PartRec<T> *>(L.f.rot);
     const auto rec = reinterpret_cast<SlotRec<T> *>(L.f.rec);
     const auto tab = reinterpret_cast<const ShapeTab<T> *>(L.f.tab);
     const auto tab64 = reinterpret_cast<const ShapeTab<double> *>(L.f.tab64);
     if (stats)
-        k_pairs<T, DIM, GL, true, OCC, SL><<<grid, 64 * kWaves, sh, stream>>>(L.b, L.reps, L.s, L.l, rot, L.f.rec64, rec,
-                                                                           tab, tab64, stats);
+        k_pairs<T, DIM, GL, true, OCC, SL, STAGE><<<grid, 64 * kWaves, sh, stream>>>(L.b, L.reps, L.s, L.l, rot, L.f.rec64,
+                                                                                  rec, tab, tab64, stats);
     else
-        k_pairs<T, DIM, GL, false, OCC, SL><<<grid, 64 * kWaves, sh, stream>>>(L.b, L.reps, L.s, L.l, rot, L.f.rec64, rec,
-                                                                            tab, tab64, nullptr);
+        k_pairs<T, DIM, GL, false, OCC, SL, STAGE><<<grid, 64 * kWaves, sh, stream>>>(L.b, L.reps, L.s, L.l, rot, L.f.rec64,
+                                                                                   rec, tab, tab64, nullptr);
 }
 
 template <typename T, int DIM>
@@ -1632,43 +1733,56 @@ void launch_gather(const Launch &L, bool kick, hipStream_t stream)
     }
 }
 
-size_t pair_kernel_lds(int precision, int tab_slots, int lanes, int sep)
+size_t pair_kernel_lds(int precision, int tab_slots, int lanes, int sep, int stage)
 {
     const size_t w = precision == DEM_FP32 ? sizeof(ShapeTab<float>) : sizeof(ShapeTab<double>);
     const size_t pl = precision == DEM_FP32 ? sizeof(PairLds<float>) : sizeof(PairLds<double>);
     const size_t qe = precision == DEM_FP32 ? sizeof(QEnt<float>) : sizeof(QEnt<double>);
     const size_t acc = precision == DEM_FP32 ? sizeof(Acc<float>) : sizeof(Acc<double>);
+    if (stage == kSearchOnly)  // tables, replica, and the last workgroup's scan
+        return (size_t)tab_slots * w + sizeof(RepLds) + sizeof(int) * 64 * kWaves;
     return (size_t)tab_slots * w + sizeof(RepLds) + kWaves * (64 / lanes) * pl + kWaves * queue_slots(sep, lanes) * qe +
            (lanes == 16 ? kWaves * 64 * acc : 0);
 }
 
 namespace {
-template <typename T, int DIM>
+template <typename T, int DIM, int STAGE>
 hipError_t pair_occupancy(int *per_cu, size_t lds, int lanes, int waves, int sep)
 {
     const int t = 64 * kWaves;
-    if (sep == 16)
-        return waves == 3 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, k_pairs<T, DIM, 16, false, 3, 16>, t, lds)
-                          : hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, k_pairs<T, DIM, 16, false, 2, 16>, t, lds);
-    if (lanes == 8)
-        return waves == 3 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, k_pairs<T, DIM, 8, false, 3, 4>, t, lds)
-                          : hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, k_pairs<T, DIM, 8, false, 2, 4>, t, lds);
-    return waves == 3 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, k_pairs<T, DIM, 16, false, 3, 4>, t, lds)
-                      : hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, k_pairs<T, DIM, 16, false, 2, 4>, t, lds);
+    auto occ = [&](auto kernel) { return hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, kernel, t, lds); };
+    if constexpr (STAGE == kSearchOnly) {
+        return occ(k_pairs<T, DIM, 16, false, kSearchOcc, 4, kSearchOnly>);
+    } else {
+        if constexpr (STAGE == kFused)
+            if (sep == 16)
+                return waves == 3 ? occ(k_pairs<T, DIM, 16, false, 3, 16, STAGE>) : occ(k_pairs<T, DIM, 16, false, 2, 16, STAGE>);
+        if (lanes == 8)
+            return waves == 3 ? occ(k_pairs<T, DIM, 8, false, 3, 4, STAGE>) : occ(k_pairs<T, DIM, 8, false, 2, 4, STAGE>);
+        return waves == 3 ? occ(k_pairs<T, DIM, 16, false, 3, 4, STAGE>) : occ(k_pairs<T, DIM, 16, false, 2, 4, STAGE>);
+    }
+}
+
+template <typename T, int DIM>
+hipError_t pair_occupancy_stage(int *per_cu, size_t lds, int lanes, int waves, int sep, int stage)
+{
+    if (stage == kSearchOnly) return pair_occupancy<T, DIM, kSearchOnly>(per_cu, lds, lanes, waves, sep);
+    if (stage == kForces) return pair_occupancy<T, DIM, kForces>(per_cu, lds, lanes, waves, sep);
+    return pair_occupancy<T, DIM, kFused>(per_cu, lds, lanes, waves, sep);
 }
 }  // namespace
 
-int pair_blocks_resident(int precision, int dim, int tab_slots, int lanes, int waves, int sep)
+int pair_blocks_resident(int precision, int dim, int tab_slots, int lanes, int waves, int sep, int stage)
 {
-    const size_t lds = pair_kernel_lds(precision, tab_slots, lanes, sep);
+    const size_t lds = pair_kernel_lds(precision, tab_slots, lanes, sep, stage);
     int per_cu = 0, cus = 0, dev = 0;
     hipError_t e;
     if (precision == DEM_FP32)
-        e = dim == 3 ? pair_occupancy<float, 3>(&per_cu, lds, lanes, waves, sep)
-                     : pair_occupancy<float, 2>(&per_cu, lds, lanes, waves, sep);
+        e = dim == 3 ? pair_occupancy_stage<float, 3>(&per_cu, lds, lanes, waves, sep, stage)
+                     : pair_occupancy_stage<float, 2>(&per_cu, lds, lanes, waves, sep, stage);
     else
-        e = dim == 3 ? pair_occupancy<double, 3>(&per_cu, lds, lanes, waves, sep)
-                     : pair_occupancy<double, 2>(&per_cu, lds, lanes, waves, sep);
+        e = dim == 3 ? pair_occupancy_stage<double, 3>(&per_cu, lds, lanes, waves, sep, stage)
+                     : pair_occupancy_stage<double, 2>(&per_cu, lds, lanes, waves, sep, stage);
     if (e != hipSuccess || hipGetDevice(&dev) != hipSuccess ||
         hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
         return 512;

@@ -31,6 +31,11 @@ constexpr int kDefaultPairLanes = 16;
 constexpr int kDefaultPairWaves = 2;
 constexpr int kDefaultPairSep = 4;
 __host__ __device__ constexpr int pair_tile(int sep_lanes) { return kPairWaves * (64 / sep_lanes); }
+// What one launch of the pair kernel does: both stages (fused), or, in the
+// split form, the contact search (separation stage, compacting the pairs it
+// keeps) and then the contact forces (feature stage on those pairs).
+enum PairStage { kFused = 0, kSearchOnly = 1, kForces = 2 };
+constexpr int kSearchOcc = 4;  // wavefronts per SIMD of the search kernel
 
 // Per-replica device flag words (flags[r * FLAG_COUNT + w], one 64-byte
 // line per replica).  FLAG_TRIGGER: some particle has moved far enough
@@ -200,6 +205,8 @@ struct BatchParams {
     int pair_waves;              // its wavefronts per SIMD (2 or 3)
     int pair_sep;                // lanes per pair in its separation stage (4 or 16)
     int tile;                    // pairs per tile: pair_tile(pair_sep)
+    int pair_split;              // 1: two kernels, contact search then contact forces
+    int search_blocks;           // grid of the search kernel of the split form
     int dim;
 };
 
@@ -231,8 +238,20 @@ struct ListPtrs {
     // bit k % 32 of word k / 32, [slot_words(cap)][N]; the gather reads
     // only those records and clears the words
     uint32_t *smask;
+    // Split form of the pair kernel (contact search, then contact forces):
+    // the pairs no supporting plane separates, compacted per replica into
+    // its own range of pair slots ([pair slots], order not fixed); their
+    // count per replica, the force kernel's first unit of each replica
+    // ([nrep + 1]) and two tickets, laid out as split_ctl below.
+    int4 *cpairs;
+    int32_t *ccount;             // [replica slots] compacted pairs (zero between evaluations)
+    int32_t *cunit;              // [replica slots + 1] first force unit of each replica
+    int32_t *ctick;              // [2] blocks done: search kernel, force kernel
 };
 __host__ __device__ inline int slot_words(int cap) { return (cap + 31) / 32; }
+// ints of the split form's control words for `replicas` replica slots:
+// ccount [replicas], cunit [replicas + 1], ctick [2]
+inline size_t split_words(int replicas) { return 2 * (size_t)replicas + 3; }
 
 // Everything the pair kernel reads about one particle, in one cache line:
 // FP64 position, the body-to-space rotation in the force precision (row
@@ -396,8 +415,8 @@ __device__ inline void cell_insert(const SysParams &p, const ListPtrs &l, int i,
 
 // Dynamic LDS of the pair kernel, and how many of its blocks the device
 // holds at once.
-size_t pair_kernel_lds(int precision, int tab_slots, int lanes, int sep);
-int pair_blocks_resident(int precision, int dim, int tab_slots, int lanes, int waves, int sep);
+size_t pair_kernel_lds(int precision, int tab_slots, int lanes, int sep, int stage);
+int pair_blocks_resident(int precision, int dim, int tab_slots, int lanes, int waves, int sep, int stage);
 
 // Per-particle records (position, rotation, shape id) from the state arrays.
 void launch_rotations(const Launch &L, hipStream_t stream);

@@ -86,7 +86,8 @@ struct dem_system {
     int pair_lanes = kDefaultPairLanes;  // pair-kernel shape: lanes per pair,
     int pair_grid = 1;                   // blocks per resident block slot
     int pair_waves = kDefaultPairWaves;  // wavefronts per SIMD
-    int pair_sep = kDefaultPairSep;      // and lanes per pair of its separation stage
+    int pair_sep = kDefaultPairSep;      // and lanes per pair of its separation stage;
+    int pair_split = 0;                  // 1: search and force kernels instead of one
     BatchParams bp{};
     std::vector<Replica> reps;
     SlotArena chunks, cells, shapes;
@@ -528,6 +529,7 @@ void refresh_batch(dem_system *h)
     b.pair_lanes = h->pair_lanes;
     b.pair_waves = h->pair_waves;
     b.pair_sep = h->pair_sep;
+    b.pair_split = h->pair_split;
     b.tile = pair_tile(h->pair_sep);
     long long tiles = 0;
     for (size_t r = 0; r < h->reps.size(); ++r) {
@@ -542,11 +544,21 @@ void refresh_batch(dem_system *h)
     // by default one round of blocks, as many as the device holds at once
     // (a second round adds a whole block's latency but evens out the
     // tail), no more than the tiles use
+    const int stage = b.pair_split ? kForces : kFused;
     const long long resident =
-        (long long)pair_blocks_resident(h->precision, h->dim, b.tab_slots, b.pair_lanes, b.pair_waves, b.pair_sep) *
+        (long long)pair_blocks_resident(h->precision, h->dim, b.tab_slots, b.pair_lanes, b.pair_waves, b.pair_sep, stage) *
         h->pair_grid;
-    const long long want = std::max<long long>(8, std::min<long long>(tiles, resident));
+    // the split form's force kernel takes units of kPairWaves * 64 / lanes
+    // compacted pairs, at most one per that many pair slots
+    const long long units = tiles * b.tile / (kPairWaves * (64 / b.pair_lanes)) + b.nrep;
+    const long long want = std::max<long long>(8, std::min<long long>(b.pair_split ? units : tiles, resident));
     b.pair_blocks = (int)((want + 7) / 8 * 8);
+    b.search_blocks = 8;
+    if (b.pair_split) {
+        const long long rs = pair_blocks_resident(h->precision, h->dim, b.tab_slots, b.pair_lanes, b.pair_waves,
+                                                  b.pair_sep, kSearchOnly);
+        b.search_blocks = (int)((std::max<long long>(8, std::min(tiles, rs)) + 7) / 8 * 8);
+    }
 }
 
 // Pair slots of every replica follow its particle slots: cap / 2 per slot.
@@ -632,13 +644,16 @@ dem_status alloc_nbr(dem_system *h, int cap)
     HIPCHK(h, hipStreamSynchronize(h->stream));
     (void)hipFree(h->lst.nbr);
     (void)hipFree(h->lst.pairs);
+    (void)hipFree(h->lst.cpairs);
     (void)hipFree(h->rec);
     (void)hipFree(h->lst.smask);
     h->lst.nbr = nbr;
     h->lst.pairs = nullptr;
+    h->lst.cpairs = nullptr;
     h->rec = nullptr;
     h->lst.smask = nullptr;
     if (hipMalloc(&h->lst.pairs, sizeof(int4) * maxp) != hipSuccess ||
+        hipMalloc(&h->lst.cpairs, sizeof(int4) * maxp) != hipSuccess ||
         hipMalloc(&h->rec, rec_bytes(h->precision) * (size_t)cap * N) != hipSuccess ||
         hipMalloc(&h->lst.smask, sizeof(uint32_t) * (size_t)slot_words(cap) * N) != hipSuccess)
         return fail(h, DEM_E_OOM, "neighbour list of %d x %zu entries", cap, N);
@@ -678,6 +693,7 @@ dem_status alloc_core(dem_system *h, int Ncap, int Ccap, int Scap, int Rcap)
               hipMalloc(&h->lst.flags, sizeof(int32_t) * FLAG_COUNT * Rcap) == hipSuccess &&
               hipMalloc(&h->lst.gflags, sizeof(int32_t) * G_COUNT) == hipSuccess &&
               hipMalloc(&h->lst.tile_start, sizeof(int32_t) * (Rcap + 1)) == hipSuccess &&
+              hipMalloc(&h->lst.ccount, sizeof(int32_t) * split_words(Rcap)) == hipSuccess &&
               hipMalloc(&h->lst.cell_count, sizeof(int32_t) * std::max(Ccap, 1)) == hipSuccess &&
               hipMalloc(&h->lst.cell_slot, sizeof(int32_t) * kCellCap * (size_t)std::max(Ccap, 1)) == hipSuccess &&
               hipMalloc(&h->lst.pcell, sizeof(int32_t) * N) == hipSuccess &&
@@ -689,6 +705,8 @@ dem_status alloc_core(dem_system *h, int Ncap, int Ccap, int Scap, int Rcap)
               hipMalloc(&h->rot, partrec_bytes(h->precision) * N) == hipSuccess &&
               (h->precision != DEM_FP32 || hipMalloc(&h->rec64, sizeof(PartRec64) * N) == hipSuccess);
     if (!ok) return fail(h, DEM_E_OOM, "device allocation failed");
+    h->lst.cunit = h->lst.ccount + Rcap;
+    h->lst.ctick = h->lst.cunit + Rcap + 1;
     if (h->batch) {  // the batch's own state and output arrays
         double **d[] = {&h->st.x,  &h->st.y,  &h->st.z,  &h->st.qw, &h->st.qx, &h->st.qy, &h->st.qz,
                         &h->st.vx, &h->st.vy, &h->st.vz, &h->st.Lx, &h->st.Ly, &h->st.Lz, &h->out.Fx,
@@ -707,6 +725,9 @@ dem_status alloc_core(dem_system *h, int Ncap, int Ccap, int Scap, int Rcap)
     HIPCHK(h, hipMemsetAsync(h->lst.flags, 0, sizeof(int32_t) * FLAG_COUNT * Rcap, h->stream));
     HIPCHK(h, hipMemsetAsync(h->lst.gflags, 0, sizeof(int32_t) * G_COUNT, h->stream));
     HIPCHK(h, hipMemsetAsync(h->lst.tile_start, 0, sizeof(int32_t) * (Rcap + 1), h->stream));
+    // compacted-pair counts and tickets start at zero; the split form's
+    // last workgroups return them to zero after each evaluation
+    HIPCHK(h, hipMemsetAsync(h->lst.ccount, 0, sizeof(int32_t) * split_words(Rcap), h->stream));
     HIPCHK(h, hipMemsetAsync(h->lst.cell_count, 0, sizeof(int32_t) * std::max(Ccap, 1), h->stream));
     // rows, pair offsets and cells start empty, so a pass over a replica that
     // has no lists yet reads zeros
@@ -726,9 +747,10 @@ void free_all(dem_system *h)
 {
     drop_graph(h);
     void *ptrs[] = {h->d_reps, h->d_chunk_rep, h->tab64, h->tab32, h->ke_part, h->e_part, h->thermo, h->budget,
-                    h->steps, h->stats, h->lst.flags, h->lst.gflags, h->lst.tile_start, h->lst.cell_count,
+                    h->steps, h->stats, h->lst.flags, h->lst.gflags, h->lst.tile_start, h->lst.ccount, h->lst.cell_count,
                     h->lst.cell_slot, h->lst.pcell, h->lst.n_nbr, h->lst.xlast, h->lst.klo,
-                    h->lst.pstart, h->lst.ptot, h->lst.nbr, h->lst.pairs, h->lst.smask, h->rot, h->rec, h->rec64};
+                    h->lst.pstart, h->lst.ptot, h->lst.nbr, h->lst.pairs, h->lst.cpairs, h->lst.smask, h->rot, h->rec,
+                    h->rec64};
     for (void *p : ptrs) (void)hipFree(p);
     if (h->batch) {
         void *own[] = {h->st.x,  h->st.y,  h->st.z,  h->st.qw, h->st.qx,  h->st.qy,  h->st.qz,  h->st.vx,
@@ -1225,7 +1247,8 @@ size_t dem_footprint_bytes(const dem_params *p)
     for (int a = 0; a < p->dim && a < 3; ++a) ncell *= (size_t)std::max(1.0, std::floor(p->box[a] / rl));
     const size_t nch = (n + kChunk - 1) / kChunk;
     const size_t maxp = n * (size_t)cap / 2;
-    return sizeof(int32_t) * (n * (size_t)cap + 4 * n + ncell * (1 + kCellCap) + 4 * maxp + nch + 2 * FLAG_COUNT + G_COUNT + 2) +
+    return sizeof(int32_t) * (n * (size_t)cap + 4 * n + ncell * (1 + kCellCap) + 8 * maxp + nch + 2 * FLAG_COUNT + G_COUNT + 2 +
+                              split_words(1)) +
            sizeof(double) * (3 * n + (kKePer + 12) * nch + TH_COUNT + 2) + sizeof(unsigned long long) * ST_COUNT +
            (partrec_bytes(p->precision) + (p->precision == DEM_FP32 ? sizeof(PartRec64) : 0)) * n +
            rec_bytes(p->precision) * (size_t)cap * n + sizeof(uint32_t) * (size_t)slot_words(cap) * n + sizeof(SysParams) + 2 * DEM_MAX_SHAPES * sizeof(ShapeTab<double>) + 256;
@@ -1731,23 +1754,24 @@ dem_status dem_set_state(dem_handle h, const void *host_buf, size_t bytes)
 }
 
 dem_status dem_set_pair_shape(dem_handle h, int32_t lanes_per_pair, int32_t grid_factor, int32_t waves_per_simd,
-                              int32_t sep_lanes)
+                              int32_t sep_lanes, int32_t split)
 {
     if (!h) return fail(nullptr, DEM_E_ARG, "null handle");
     if ((lanes_per_pair != 8 && lanes_per_pair != 16) || grid_factor < 1 || grid_factor > 4 ||
         (waves_per_simd != 2 && waves_per_simd != 3) || (sep_lanes != 4 && sep_lanes != 16) ||
-        (sep_lanes == 16 && lanes_per_pair != 16))
+        (sep_lanes == 16 && lanes_per_pair != 16) || (split != 0 && split != 1) || (split == 1 && sep_lanes != 4))
         return fail(h, DEM_E_ARG,
                     "pair shape: %d lanes per pair (8 or 16), grid factor %d (1 to 4), %d waves per SIMD (2 or 3), "
-                    "%d separation lanes (4, or 16 with 16 lanes per pair)",
-                    lanes_per_pair, grid_factor, waves_per_simd, sep_lanes);
+                    "%d separation lanes (4, or 16 with 16 lanes per pair), split %d (0, or 1 with 4 separation lanes)",
+                    lanes_per_pair, grid_factor, waves_per_simd, sep_lanes, split);
     if (lanes_per_pair == h->pair_lanes && grid_factor == h->pair_grid && waves_per_simd == h->pair_waves &&
-        sep_lanes == h->pair_sep)
+        sep_lanes == h->pair_sep && split == h->pair_split)
         return DEM_OK;
     h->pair_lanes = lanes_per_pair;
     h->pair_grid = grid_factor;
     h->pair_waves = waves_per_simd;
     h->pair_sep = sep_lanes;
+    h->pair_split = split;
     refresh_batch(h);
     launch_lists(make_launch(h), LISTS_PLAN, h->stream);  // tiles of the new size
     HIPCHK(h, hipGetLastError());
@@ -1758,13 +1782,14 @@ dem_status dem_set_pair_shape(dem_handle h, int32_t lanes_per_pair, int32_t grid
 dem_status dem_tune_pairs(dem_handle h, int32_t reps, int32_t *shape, double *mean_ms)
 {
     if (!h || reps < 1) return fail(h, DEM_E_ARG, "bad argument");
-    static const int kShapes[DEM_PAIR_SHAPES][4] = {{16, 1, 2, 4},  {8, 1, 2, 4},  {16, 2, 2, 4},  {8, 2, 2, 4},
-                                                    {16, 1, 3, 4},  {8, 1, 3, 4},  {16, 2, 3, 4},  {8, 2, 3, 4},
-                                                    {16, 1, 2, 16}, {16, 2, 2, 16}, {16, 1, 3, 16}, {16, 2, 3, 16}};
+    static const int kShapes[DEM_PAIR_SHAPES][5] = {
+        {16, 1, 2, 4, 0},  {8, 1, 2, 4, 0},  {16, 2, 2, 4, 0},  {8, 2, 2, 4, 0},  {16, 1, 3, 4, 0},  {8, 1, 3, 4, 0},
+        {16, 2, 3, 4, 0},  {8, 2, 3, 4, 0},  {16, 1, 2, 16, 0}, {16, 2, 2, 16, 0}, {16, 1, 3, 16, 0}, {16, 2, 3, 16, 0},
+        {16, 1, 2, 4, 1},  {8, 1, 2, 4, 1},  {16, 1, 3, 4, 1},  {8, 1, 3, 4, 1}};
     double best = 0.0;
     int pick = 0;
     for (int k = 0; k < DEM_PAIR_SHAPES; ++k) {
-        dem_status st = dem_set_pair_shape(h, kShapes[k][0], kShapes[k][1], kShapes[k][2], kShapes[k][3]);
+        dem_status st = dem_set_pair_shape(h, kShapes[k][0], kShapes[k][1], kShapes[k][2], kShapes[k][3], kShapes[k][4]);
         double ms = 0.0;
         if (st == DEM_OK) st = dem_time_forces(h, reps, &ms);
         if (st != DEM_OK) return st;
@@ -1774,10 +1799,11 @@ dem_status dem_tune_pairs(dem_handle h, int32_t reps, int32_t *shape, double *me
             pick = k;
         }
     }
-    dem_status st = dem_set_pair_shape(h, kShapes[pick][0], kShapes[pick][1], kShapes[pick][2], kShapes[pick][3]);
+    dem_status st =
+        dem_set_pair_shape(h, kShapes[pick][0], kShapes[pick][1], kShapes[pick][2], kShapes[pick][3], kShapes[pick][4]);
     if (st != DEM_OK) return st;
     if (shape)
-        for (int a = 0; a < 4; ++a) shape[a] = kShapes[pick][a];
+        for (int a = 0; a < 5; ++a) shape[a] = kShapes[pick][a];
     return DEM_OK;
 }
 

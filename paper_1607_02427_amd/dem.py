@@ -128,7 +128,7 @@ def lib():
         L.dem_set_counting.restype = st
         L.dem_time_forces.argtypes = [C.c_void_p, C.c_int32, _dp]
         L.dem_time_forces.restype = st
-        L.dem_set_pair_shape.argtypes = [C.c_void_p, C.c_int32, C.c_int32, C.c_int32, C.c_int32]
+        L.dem_set_pair_shape.argtypes = [C.c_void_p, C.c_int32, C.c_int32, C.c_int32, C.c_int32, C.c_int32]
         L.dem_set_pair_shape.restype = st
         L.dem_tune_pairs.argtypes = [C.c_void_p, C.c_int32, _ip, _dp]
         L.dem_tune_pairs.restype = st
@@ -282,16 +282,18 @@ def _lists_np(call, n, ncell, cap):
                 nbr=nb[: cap * n].reshape(cap, n) if n else nb[:0].reshape(cap, 0), n_nbr=nn[:n])
 
 
-# the tuner's candidates (lanes per pair, grid factor, waves per SIMD, separation lanes), in dem_tune_pairs order
-PAIR_SHAPES = ((16, 1, 2, 4), (8, 1, 2, 4), (16, 2, 2, 4), (8, 2, 2, 4), (16, 1, 3, 4), (8, 1, 3, 4), (16, 2, 3, 4),
-               (8, 2, 3, 4), (16, 1, 2, 16), (16, 2, 2, 16), (16, 1, 3, 16), (16, 2, 3, 16))
+# the tuner's candidates (lanes per pair, grid factor, waves per SIMD, separation lanes, split), in
+# dem_tune_pairs order
+PAIR_SHAPES = ((16, 1, 2, 4, 0), (8, 1, 2, 4, 0), (16, 2, 2, 4, 0), (8, 2, 2, 4, 0), (16, 1, 3, 4, 0), (8, 1, 3, 4, 0),
+               (16, 2, 3, 4, 0), (8, 2, 3, 4, 0), (16, 1, 2, 16, 0), (16, 2, 2, 16, 0), (16, 1, 3, 16, 0),
+               (16, 2, 3, 16, 0), (16, 1, 2, 4, 1), (8, 1, 2, 4, 1), (16, 1, 3, 4, 1), (8, 1, 3, 4, 1))
 
 
 def _tune_pairs(check, h, reps):
-    shape = (C.c_int32 * 4)()
+    shape = (C.c_int32 * 5)()
     ms = (C.c_double * len(PAIR_SHAPES))()
     check(lib().dem_tune_pairs(h, int(reps), shape, ms), "dem_tune_pairs")
-    return dict(lanes=shape[0], grid=shape[1], waves=shape[2], sep=shape[3],
+    return dict(lanes=shape[0], grid=shape[1], waves=shape[2], sep=shape[3], split=shape[4],
                 mean_ms={"x".join(map(str, sh)): ms[k] for k, sh in enumerate(PAIR_SHAPES)})
 
 
@@ -402,10 +404,11 @@ class DemSystem:
         self._check(lib().dem_get_outputs(self.h, C.byref(v)), "dem_get_outputs")
         return {name: getattr(v, name) for name, _ in OutputView._fields_}
 
-    def set_pair_shape(self, lanes: int, grid: int = 1, waves: int = 2, sep: int = 4):
+    def set_pair_shape(self, lanes: int, grid: int = 1, waves: int = 2, sep: int = 4, split: int = 0):
         """Pair-kernel launch shape (8 or 16 lanes per pair, grid factor 1..4, 2 or 3 waves per SIMD, 4 or 16
-        separation lanes); results do not change."""
-        self._check(lib().dem_set_pair_shape(self.h, int(lanes), int(grid), int(waves), int(sep)),
+        separation lanes, split 0 or 1: one kernel, or a search kernel and a force kernel); results do not
+        change."""
+        self._check(lib().dem_set_pair_shape(self.h, int(lanes), int(grid), int(waves), int(sep), int(split)),
                     "dem_set_pair_shape")
 
     def tune_pairs(self, reps: int = 20) -> dict:
@@ -572,8 +575,8 @@ class DemBatch:
     def set_counting(self, on: bool):
         self._check(lib().dem_set_counting(self.h, 1 if on else 0), "dem_set_counting")
 
-    def set_pair_shape(self, lanes: int, grid: int = 1, waves: int = 2, sep: int = 4):
-        self._check(lib().dem_set_pair_shape(self.h, int(lanes), int(grid), int(waves), int(sep)),
+    def set_pair_shape(self, lanes: int, grid: int = 1, waves: int = 2, sep: int = 4, split: int = 0):
+        self._check(lib().dem_set_pair_shape(self.h, int(lanes), int(grid), int(waves), int(sep), int(split)),
                     "dem_set_pair_shape")
 
     def tune_pairs(self, reps: int = 5) -> dict:

@@ -40,7 +40,7 @@ def test_cubes_4096_equilibrated(prec):
         g.compute_forces()
         out = g.outputs()
         st = g.force_stats()
-    print(prec, shape["lanes"], shape["grid"], shape["waves"], shape["sep"], ref["stats"], st, flush=True)
+    print(prec, shape["lanes"], shape["grid"], shape["waves"], shape["sep"], shape["split"], ref["stats"], st, flush=True)
     check(f"{s.name}", prec, out, ref)
 
 
@@ -59,7 +59,7 @@ def _batch_against_oracle(dem, reps, prec, label):
         shape = B.tune_pairs(2)
         B.compute_forces()
         print(f"[full] {label} {prec} {len(reps)} replicas {total} particles, pair shape "
-              f"{shape['lanes']}x{shape['grid']}x{shape['waves']}x{shape['sep']}", flush=True)
+              f"{shape['lanes']}x{shape['grid']}x{shape['waves']}x{shape['sep']}x{shape['split']}", flush=True)
         worst = {}
         for s, r in zip(reps, rids):
             _, out = B.read(r)
@@ -103,6 +103,6 @@ def test_octahedra_262144_compressed(prec):
         g.compute_forces()
         out = g.outputs()
         st = g.force_stats()
-    print(prec, shape["lanes"], shape["grid"], shape["waves"], shape["sep"], ref["stats"], st, flush=True)
+    print(prec, shape["lanes"], shape["grid"], shape["waves"], shape["sep"], shape["split"], ref["stats"], st, flush=True)
     sub = {k: out[k][pick] for k in ("F", "T", "U", "W")}
     check(f"{s.name}[{len(pick)} of {s.n}]", prec, sub, ref)

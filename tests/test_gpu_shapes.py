@@ -1,8 +1,10 @@
-"""Pair-kernel launch shapes (lanes per pair, grid factor, waves per SIMD, separation lanes): every shape the
-tuner can choose gives the same forces and the same trajectories bit for
-bit, and tuning leaves the state alone.  The per-pair sums are formed in a
-canonical order (problem k of a solve round into partial sum k mod 16, one
-fixed combining tree), so the shape is a pure performance knob."""
+"""Pair-kernel launch shapes (lanes per pair, grid factor, waves per SIMD, separation lanes, split): every
+shape the tuner can choose gives the same forces and the same trajectories
+bit for bit, and tuning leaves the state alone.  The per-pair sums are
+formed in a canonical order (problem k of a solve round into partial sum
+k mod 16, one fixed combining tree), and a pair's result does not depend on
+which wavefront or kernel takes it, so the shape, the two-kernel split of
+contact search and forces included, is a pure performance knob."""
 import numpy as np
 import pytest
 
@@ -10,8 +12,9 @@ from paper_1607_02427_amd import inputs as I
 
 pytestmark = pytest.mark.gpu
 
-SHAPES = [(16, 1, 2, 4), (8, 1, 2, 4), (16, 2, 2, 4), (8, 2, 2, 4), (16, 1, 3, 4), (8, 1, 3, 4), (16, 2, 3, 4),
-          (8, 2, 3, 4), (16, 1, 2, 16), (16, 2, 2, 16), (16, 1, 3, 16), (16, 2, 3, 16)]
+SHAPES = [(16, 1, 2, 4, 0), (8, 1, 2, 4, 0), (16, 2, 2, 4, 0), (8, 2, 2, 4, 0), (16, 1, 3, 4, 0), (8, 1, 3, 4, 0),
+          (16, 2, 3, 4, 0), (8, 2, 3, 4, 0), (16, 1, 2, 16, 0), (16, 2, 2, 16, 0), (16, 1, 3, 16, 0),
+          (16, 2, 3, 16, 0), (16, 1, 2, 4, 1), (8, 1, 2, 4, 1), (16, 1, 3, 4, 1), (8, 1, 3, 4, 1)]
 
 CASES = {
     "cubes_contact_512": lambda: I.cubes_3d_contact(n_side=8),
@@ -46,9 +49,9 @@ def test_shapes_give_identical_forces(name, prec):
     s = CASES[name]()
     print(f"[shapes] {name} n={s.n} {prec}", flush=True)
     outs = []
-    for lanes, grid, waves, sep in SHAPES:
+    for shape in SHAPES:
         with dem.DemSystem(s, prec) as g:
-            g.set_pair_shape(lanes, grid, waves, sep)
+            g.set_pair_shape(*shape)
             g.compute_forces()
             outs.append(g.outputs())
     for o in outs[1:]:
@@ -64,9 +67,9 @@ def test_shapes_give_identical_trajectories():
     s = I.cubes_3d(n_side=10)
     print(f"[shapes] cubes_1000 NVT 300 steps", flush=True)
     ends = []
-    for lanes, grid, waves, sep in [(16, 1, 2, 4), (8, 2, 3, 4), (16, 1, 3, 16)]:
+    for shape in [(16, 1, 2, 4, 0), (8, 2, 3, 4, 0), (16, 1, 3, 16, 0), (8, 1, 3, 4, 1), (16, 1, 2, 4, 1)]:
         with dem.DemSystem(s, "fp32") as g:
-            g.set_pair_shape(lanes, grid, waves, sep)
+            g.set_pair_shape(*shape)
             g.step(300)
             ends.append((_state_arrays(g.state()), g.energy()))
     for e in ends[1:]:
@@ -86,7 +89,7 @@ def test_tuner_keeps_state_and_results():
         before = _state_arrays(g.state())
         r = g.tune_pairs(3)
         print("tuned", r, flush=True)
-        assert (r["lanes"], r["grid"], r["waves"], r["sep"]) in SHAPES
+        assert (r["lanes"], r["grid"], r["waves"], r["sep"], r["split"]) in SHAPES
         assert all(v > 0 for v in r["mean_ms"].values())
         _same(_state_arrays(g.state()), before)
         g.step(50)
@@ -107,3 +110,25 @@ def test_tuned_batch_equals_untuned():
             results.append([_state_arrays(b.read(r)[0]) for r in ids])
     for a, c in zip(results[0], results[1]):
         _same(a, c)
+
+
+def test_split_batch_equals_fused():
+    """The split form compacts each replica's pairs into its own range and
+    walks them replica by replica: a mixed 2D batch and a 3D batch step
+    the same with it as with the one-kernel form, list rebuilds included."""
+    dem = _dem()
+    for dim, reps in ((3, I.batched_replicas(6, seed=9, n_range=(300, 1500), steps=60)),
+                      (2, [I.squares_2d_contact(), I.dimer_gas("pentagon", 90, seed=21, dim=2),
+                           I.dimer_gas("square", 33, seed=22, dim=2)])):
+        print(f"[shapes] split vs fused, {dim}D batch of {len(reps)} replicas", flush=True)
+        results = []
+        for shape in ((16, 1, 2, 4, 0), (8, 1, 3, 4, 1), (16, 1, 2, 4, 1)):
+            with dem.DemBatch(dim, "fp32", max_replicas=8, max_particles=sum(-(-s.n // 64) * 64 for s in reps) + 512,
+                              max_cells=16384) as b:
+                ids = [b.add(s, steps=60) for s in reps]
+                b.set_pair_shape(*shape)
+                b.step(60)
+                results.append([_state_arrays(b.read(r)[0]) for r in ids])
+        for other in results[1:]:
+            for a, c in zip(results[0], other):
+                _same(a, c)
