@@ -81,10 +81,11 @@ def counters_now(g):
     return g.force_stats(reset=True)
 
 
-def run_path(system, precision, steps, warmup, counting=False, tune=True):
+def run_path(system, precision, steps, warmup, counting=False, tune=True, cells=False):
     import torch
     from paper_1607_02427_amd import dem
     g = dem.DemSystem(system, precision)
+    g.set_feature_cells(cells)
     stream = g.stream
     if counting:
         g.set_counting(True)
@@ -304,22 +305,32 @@ def table1_workloads(steps=(2000, 1000, 300), warmup=200):
     """The paper's Table I shapes and sizes on this engine: rounded cubes and
     rounded icosahedra (edge 1, r = 0.15 and 0.1) at N = 6^3, 16^3 and 40^3
     (its 256, 4096 and 65536 on cubic lattices), volume fraction 0.4, NVT
-    kT = 1 after `warmup` steps, FP32 pair geometry, tuned pair shape.  The
-    paper gives no densities; these are ours."""
+    kT = 1 after `warmup` steps, FP32 pair geometry, tuned pair shape; each
+    with the supporting-plane prefilter and with the shape-local feature
+    cells, with the work counters of one force evaluation at the start of
+    the timed window.  The paper gives no densities; these are ours."""
     from paper_1607_02427_amd import inputs as I
     out = []
     for name, shp, orient in (("cube", I.cube(1.0, 0.15), "small"), ("icosahedron", I.icosahedron(1.0, 0.1), "aligned")):
         for n_side, k in zip((6, 16, 40), steps):
-            s = I.lattice_system(shp, n_side, 0.4, 31 + n_side, orient=orient, max_deg=10.0,
-                                 name=f"{name}_{n_side ** 3}")
-            s.ensemble = "nvt"
-            s.dt = 5e-4
-            g, r = run_path(s, "fp32", k, warmup)
-            g.close()
-            ptps = s.n * k / (r["gpu_ms"] * 1e-3)
-            out.append(dict(shape=name, n=s.n, steps=k, value=ptps, ms_per_step=r["gpu_ms"] / k,
-                            pair_shape=[r["pair_shape"][a] for a in ("lanes", "grid", "waves", "sep", "split")]))
-            log(f"[table1] {name} N={s.n}: {ptps:.3e} PTPS ({r['gpu_ms'] / k * 1e3:.1f} us/step)")
+            for cells in (False, True):
+                s = I.lattice_system(shp, n_side, 0.4, 31 + n_side, orient=orient, max_deg=10.0,
+                                     name=f"{name}_{n_side ** 3}")
+                s.ensemble = "nvt"
+                s.dt = 5e-4
+                g, r = run_path(s, "fp32", k, warmup, cells=cells)
+                g.close()
+                ptps = s.n * k / (r["gpu_ms"] * 1e-3)
+                c = r["counters_start"]
+                out.append(dict(shape=name, n=s.n, feature_search="cells" if cells else "planes", steps=k, value=ptps,
+                                ms_per_step=r["gpu_ms"] / k,
+                                pair_shape=[r["pair_shape"][a] for a in ("lanes", "grid", "waves", "sep", "split")],
+                                pair_ms=min(r["pair_shape"]["mean_ms"].values()),
+                                counters={a: c[a] for a in ("pairs", "separated", "features", "vf_near", "ee_near",
+                                                            "in_cutoff")}))
+                log(f"[table1] {name} N={s.n} {'cells' if cells else 'planes'}: {ptps:.3e} PTPS "
+                    f"({r['gpu_ms'] / k * 1e3:.1f} us/step, pair kernel {out[-1]['pair_ms'] * 1e3:.1f} us, "
+                    f"{c['features']} problems to the cull, {c['in_cutoff']} in the cutoff)")
     return out
 
 

@@ -281,6 +281,27 @@ enum { DEM_PAIR_SHAPES = 16 };
 dem_status dem_set_pair_shape(dem_handle h, int32_t lanes_per_pair, int32_t grid_factor, int32_t waves_per_simd,
                               int32_t sep_lanes, int32_t split);
 
+/* Feature search (Sec. V: shape-local spatial structures for the contact
+ * point search).  on = 0 (default): the feature stage keeps the vertices,
+ * edges and faces that lie within reach of the other body's centre and not
+ * wholly beyond one of its supporting planes, and pairs every near vertex
+ * with every near face and every near edge with every near edge.  on = 1:
+ * each shape carries a grid of cells over its body frame (12 per axis in
+ * 3D, 40 in 2D, covering its circumradius plus its reach); a cell lists the
+ * shape's faces (2D: edges) within the cutoff of any point in it, and its
+ * edges within the cutoff plus the longest half edge of the replica's
+ * shapes.  After the prefilter above, a near vertex of the other body keeps
+ * only the near faces of the cell it lies in, and a near edge only the near
+ * edges of the cell that holds its midpoint.  Both forms keep every feature
+ * pair inside the
+ * cutoff and compute the same terms (within the FP32 path's rounding:
+ * the terms are summed in another order); results do not depend on the
+ * pair shape in either.  The cells are built on the host with the shape
+ * tables (14 KB per shape).  With cells the pair kernel is compiled for 2
+ * wavefronts per SIMD whatever the pair shape asks.  The next dem_step
+ * captures its graph again.  DEM_E_ARG for other values. */
+dem_status dem_set_feature_cells(dem_handle h, int32_t on);
+
 /* Pair-shape autotuner: times `reps` launches of the pair kernel on the
  * current state for each of the DEM_PAIR_SHAPES shapes {lanes, factor,
  * waves, sep, split} = {16,1,2,4,0}, {8,1,2,4,0}, {16,2,2,4,0}, {8,2,2,4,0},

@@ -182,10 +182,11 @@ __device__ inline V3<double> qrot(const double q[4], V3<double> v)
     return v + (2.0 * q[0]) * c + 2.0 * cross(u, c);
 }
 
-__device__ inline unsigned long long lanes_below()
+// Set bits of m in the lanes below this one (the hardware's masked bit
+// count: no lane mask is held in registers).
+__device__ inline int popc_below(unsigned long long m)
 {
-    const unsigned lane = __lane_id();
-    return lane == 0 ? 0ull : (~0ull >> (64 - lane));
+    return (int)__builtin_amdgcn_mbcnt_hi((unsigned)(m >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)m, 0u));
 }
 
 constexpr int kWaves = kPairWaves;  // waves per block
@@ -215,6 +216,35 @@ struct PairLds {
     // groups that solve its problems in the pooled solve (16 lanes per pair)
     int nA, nB, nfj, nfi, nej, cnt;
 };
+
+// Feature-cell form of the feature search (one per lane group, beside its
+// PairLds): the cell masks of i's edges (edges of j within reach of each,
+// 3D), and the prefix of the problem counts over the near entries (i's
+// vertices, j's vertices, i's edges), which numbers the pair's problems.
+struct PairFc {
+    unsigned eib[DEM_MAX_EDGES];
+    unsigned short pf[2 * DEM_MAX_VERTS + DEM_MAX_EDGES + 2];
+};
+
+// The masks of the shape-local feature cell of shape S (its cells at
+// `cells`) that holds point p, given in S's frame; zero outside the grid.
+template <typename T, int DIM>
+__device__ inline uint2 fc_lookup(const uint2 *__restrict__ cells, const ShapeTab<T> &S, V3<T> p)
+{
+    const int g = S.fc_g;
+    const int ix = (int)floor((p.x - S.fc_lo) * S.fc_ih);
+    const int iy = (int)floor((p.y - S.fc_lo) * S.fc_ih);
+    const int iz = DIM == 3 ? (int)floor((p.z - S.fc_lo) * S.fc_ih) : 0;
+    if (ix < 0 || ix >= g || iy < 0 || iy >= g || iz < 0 || iz >= (DIM == 3 ? g : 1)) return make_uint2(0u, 0u);
+    return cells[(iz * g + iy) * g + ix];
+}
+
+// Index of the r-th set bit of m (r < popcount(m)).
+__device__ inline int nth_bit(unsigned m, int r)
+{
+    for (int k = 0; k < r; ++k) m &= m - 1u;
+    return __builtin_ctz(m);
+}
 
 // Closest points of segments p1 + s d1 and p2 + t d2 (s, t in [0,1]) with
 // a = |d1|^2, e = |d2|^2 and their reciprocals ia, ie given.
@@ -261,7 +291,7 @@ __device__ inline T seg_seg(V3<T> p1, V3<T> d1, T a, T ia, V3<T> p2, V3<T> d2, T
 // with near faces (2D: edges) of j, family B near vertices of j with near
 // faces (edges) of i, family C near edges of i with near edges of j (3D).
 // Problem q decodes to list positions by an exact small division.
-template <typename T, int DIM>
+template <typename T, int DIM, bool FC = false>
 struct Problem {
     const ShapeTab<T> &Si, &Sj;
     const PairLds<T> &W;
@@ -270,9 +300,49 @@ struct Problem {
     int nA, nB;
     int nfj, nfi, nej;            // list lengths used as divisors
     float inv_fj, inv_fi, inv_ej;
+    // feature cells: nA, nB the near vertices of i and of j, nfj all near
+    // entries (with i's near edges); problem q belongs to the entry e with
+    // pf[e] <= q < pf[e + 1] and is the (q - pf[e])-th feature of its mask.
+    // The cull and the solves take its code fam << 10 | x << 5 | y instead.
+    const PairFc *F = nullptr;
+
+    __device__ int fc_code(int q) const
+    {
+        {
+            int lo = 0, hi = nfj;
+            while (hi - lo > 1) {
+                const int mid = (lo + hi) >> 1;
+                if ((int)F->pf[mid] <= q) lo = mid;
+                else hi = mid;
+            }
+            const int r = q - (int)F->pf[lo];
+            unsigned m;
+            int fam, x;
+            if (lo < nA) {
+                fam = 0;
+                x = W.vi_near[lo];
+                m = W.vib[x];
+            } else if (lo < nA + nB) {
+                fam = 1;
+                x = W.vj_near[lo - nA];
+                m = W.vjb[x];
+            } else {
+                fam = 2;
+                x = W.ei_near[lo - nA - nB];
+                m = F->eib[x];
+            }
+            return fam << 10 | x << 5 | nth_bit(m, r);
+        }
+    }
 
     __device__ void decode(int q, int &fam, int &x, int &y) const
     {
+        if constexpr (FC) {
+            fam = q >> 10;
+            x = (q >> 5) & 31;
+            y = q & 31;
+            return;
+        }
         if (q < nA) {
             const int ax = qdiv(q, inv_fj);
             fam = 0;
@@ -403,11 +473,10 @@ __device__ inline void wave_sync_lds()
 
 // Appends this lane's item to its group's list when keep is set; returns
 // the group's new length.  All 64 lanes must call it together.
-__device__ inline int group_append(bool keep, unsigned char *list, int len, int item, unsigned long long gmask,
-                                   unsigned long long below)
+__device__ inline int group_append(bool keep, unsigned char *list, int len, int item, unsigned long long gmask)
 {
     const unsigned long long m = __ballot(keep);
-    if (keep) list[len + __popcll(m & below & gmask)] = (unsigned char)item;
+    if (keep) list[len + popc_below(m & gmask)] = (unsigned char)item;
     return len + __popcll(m & gmask);
 }
 
@@ -522,7 +591,9 @@ __device__ void stage_replica(const SysParams *reps, const ListPtrs &l, const Sh
     const int n16 = p.n_shapes * (int)(sizeof(ShapeTab<T>) / 16);
     const uint4 *src = reinterpret_cast<const uint4 *>(gtab + p.sbase);
     uint4 *dst = reinterpret_cast<uint4 *>(tab);
-    for (int w0 = threadIdx.x; w0 < n16; w0 += kU * blockDim.x) {
+    int tid = threadIdx.x;  // (formed here, not held across the caller's loop)
+    asm volatile("" : "+v"(tid));
+    for (int w0 = tid; w0 < n16; w0 += kU * blockDim.x) {
         uint4 v[kU];
 #pragma unroll
         for (int u = 0; u < kU; ++u) {
@@ -619,7 +690,7 @@ struct Tally<false> {
 // the compiler must fit 168 registers and schedules with less freedom.  The
 // uncounted variants fit without spilling because the feature stage reads
 // the pair's transform from the LDS queue instead of holding it.
-template <typename T, int DIM, int GL, bool COUNT, int OCC, int SL, int STAGE>
+template <typename T, int DIM, int GL, bool COUNT, int OCC, int SL, int STAGE, bool FC>
 __global__ void __launch_bounds__(64 * kWaves, OCC) k_pairs(BatchParams b, const SysParams *__restrict__ reps, StatePtrs s,
                                                           ListPtrs l, const PartRec<T> *__restrict__ prec,
                                                           const PartRec64 *__restrict__ rec64,
@@ -650,14 +721,16 @@ __global__ void __launch_bounds__(64 * kWaves, OCC) k_pairs(BatchParams b, const
     // results of one pooled solve step, one per lane (16 lanes per pair only)
     constexpr bool kPool = kGL == 16;
     Acc<T> *pres = reinterpret_cast<Acc<T> *>(reinterpret_cast<unsigned char *>(qall) + kWaves * kQCap * sizeof(QEnt<T>));
+    // the feature-cell form's per-group prefix and edge masks
+    PairFc *pfc = reinterpret_cast<PairFc *>(reinterpret_cast<unsigned char *>(pres) +
+                                             (kPool ? kWaves * 64 * sizeof(Acc<T>) : 0));
 
     const int lane = __lane_id();
     const int wid = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int grp = lane / kGL, sub = lane % kGL;
+    const unsigned long long gmask = ((kGL == 64) ? ~0ull : ((1ull << kGL) - 1)) << (kGL * grp);
     PairLds<T> &W = pls[wid * kGroups + grp];
     QEnt<T> *qb = qall + wid * kQCap;
-    const unsigned long long gmask = ((kGL == 64) ? ~0ull : ((1ull << kGL) - 1)) << (kGL * grp);
-    const unsigned long long below = lanes_below();
     const size_t N = (size_t)b.N;
     const int ntiles = l.tile_start[b.nrep];
     const unsigned stamp = (unsigned)l.gflags[G_STAMP];
@@ -730,8 +803,10 @@ __global__ void __launch_bounds__(64 * kWaves, OCC) k_pairs(BatchParams b, const
             // the other body's supporting planes (for an edge or a face: all
             // its vertices beyond the same plane).  One lane per feature;
             // survivors are listed by index.
+            int cvj = 0, cvi = 0, cei = 0, cej = 0, cfi = 0, cfj = 0;
+            int fc_total = 0;
+            PairFc &Fc = pfc[FC ? wid * kGroups + grp : 0];
             const T thr = rcm + T(1e-5) * (Bi + Bj);
-            int cvj = 0, cvi = 0;
             for (int v0 = 0; v0 < DEM_MAX_VERTS; v0 += kGL) {
                 const int vk = v0 + sub;
                 bool nj = false, ni = false;
@@ -757,12 +832,11 @@ __global__ void __launch_bounds__(64 * kWaves, OCC) k_pairs(BatchParams b, const
                     W.vib[vk] = mb;
                     ni = mb == 0 && dot(v, v) < grow * Bj * Bj;
                 }
-                cvj = group_append(nj, W.vj_near, cvj, vk, gmask, below);
-                cvi = group_append(ni, W.vi_near, cvi, vk, gmask, below);
+                cvj = group_append(nj, W.vj_near, cvj, vk, gmask);
+                cvi = group_append(ni, W.vi_near, cvi, vk, gmask);
                 if (__ballot(live && (v0 + kGL < Si.nv || v0 + kGL < Sj.nv)) == 0) break;
             }
             wave_sync_lds();
-            int cei = 0, cej = 0;
             for (int e0 = 0; e0 < DEM_MAX_EDGES; e0 += kGL) {
                 const int e = e0 + sub;
                 bool ne = false, me = false;
@@ -776,11 +850,10 @@ __global__ void __launch_bounds__(64 * kWaves, OCC) k_pairs(BatchParams b, const
                     const T lim = Bi + Sj.eh[e];
                     me = (W.vjb[Sj.e[e][0]] & W.vjb[Sj.e[e][1]]) == 0 && dot(m, m) < grow * lim * lim;
                 }
-                cei = group_append(ne, W.ei_near, cei, e, gmask, below);
-                cej = group_append(me, W.ej_near, cej, e, gmask, below);
+                cei = group_append(ne, W.ei_near, cei, e, gmask);
+                cej = group_append(me, W.ej_near, cej, e, gmask);
                 if (__ballot(live && (e0 + kGL < Si.ne || e0 + kGL < Sj.ne)) == 0) break;
             }
-            int cfi = 0, cfj = 0;
             if (DIM == 3) {
                 const V3<T> ti = -(T)1 * mulT(Rr, t);  // i's centre in j's frame
                 for (int f0 = 0; f0 < DEM_MAX_FACES; f0 += kGL) {
@@ -802,16 +875,75 @@ __global__ void __launch_bounds__(64 * kWaves, OCC) k_pairs(BatchParams b, const
                         for (int k = Sj.foff[f]; k < Sj.foff[f + 1]; ++k) all &= W.vjb[Sj.floop[k]];
                         mf = all == 0 && dot(d, d) < grow * lim * lim;
                     }
-                    cfi = group_append(nf, W.fi_near, cfi, f, gmask, below);
-                    cfj = group_append(mf, W.fj_near, cfj, f, gmask, below);
+                    cfi = group_append(nf, W.fi_near, cfi, f, gmask);
+                    cfj = group_append(mf, W.fj_near, cfj, f, gmask);
                     if (__ballot(live && (f0 + kGL < Si.nf || f0 + kGL < Sj.nf)) == 0) break;
                 }
             }
             wave_sync_lds();
+            if constexpr (FC) {
+                // Shape-local feature cells narrow the near sets per feature:
+                // a near vertex keeps only the other body's near faces (2D:
+                // edges) listed by the cell it lies in, a near edge of i only
+                // j's near edges listed by the cell of its midpoint.
+                unsigned mfi = 0u, mfj = 0u, mei = 0u, mej = 0u;
+                for (int k = sub; k < cfi; k += kGL) mfi |= 1u << W.fi_near[k];
+                for (int k = sub; k < cfj; k += kGL) mfj |= 1u << W.fj_near[k];
+                for (int k = sub; k < cei; k += kGL) mei |= 1u << W.ei_near[k];
+                for (int k = sub; k < cej; k += kGL) mej |= 1u << W.ej_near[k];
+                for (int off = 1; off < kGL; off <<= 1) {
+                    mfi |= __shfl_xor(mfi, off, kGL);
+                    mfj |= __shfl_xor(mfj, off, kGL);
+                    mei |= __shfl_xor(mei, off, kGL);
+                    mej |= __shfl_xor(mej, off, kGL);
+                }
+                const unsigned tj = DIM == 3 ? mfj : mej, ti = DIM == 3 ? mfi : mei;
+                const uint2 *celli = l.fcells + (size_t)(rl.sbase + si) * kFcCells;
+                const uint2 *cellj = l.fcells + (size_t)(rl.sbase + sj) * kFcCells;
+                for (int k = sub; k < cvi; k += kGL) {
+                    const int x = W.vi_near[k];
+                    W.vib[x] = fc_lookup<T, DIM>(cellj, Sj, ld3(W.vi[x])).x & tj;
+                }
+                for (int k = sub; k < cvj; k += kGL) {
+                    const int x = W.vj_near[k];
+                    W.vjb[x] = fc_lookup<T, DIM>(celli, Si, ld3(W.vj[x])).x & ti;
+                }
+                if (DIM == 3)
+                    for (int k = sub; k < cei; k += kGL) {
+                        const int e = W.ei_near[k];
+                        const V3<T> m = T(0.5) * (ld3(W.vi[Si.e[e][0]]) + ld3(W.vi[Si.e[e][1]]));
+                        Fc.eib[e] = fc_lookup<T, DIM>(cellj, Sj, m).y & mej;
+                    }
+                wave_sync_lds();
+                // problem counts of the near entries (i's vertices, j's
+                // vertices, i's edges in 3D) and their prefix, GL at a time
+                const int nent = cvi + cvj + (DIM == 3 ? cei : 0);
+                if (sub == 0) Fc.pf[0] = 0;
+                for (int k0 = 0; k0 < nent; k0 += kGL) {
+                    const int k = k0 + sub;
+                    int c = 0;
+                    if (k < nent)
+                        c = __popc(k < cvi ? W.vib[W.vi_near[k]]
+                                           : (k < cvi + cvj ? W.vjb[W.vj_near[k - cvi]] : Fc.eib[W.ei_near[k - cvi - cvj]]));
+                    for (int off = 1; off < kGL; off <<= 1) {
+                        const int u = __shfl_up(c, off, kGL);
+                        if (sub >= off) c += u;
+                    }
+                    if (k < nent) Fc.pf[k + 1] = (unsigned short)(fc_total + c);
+                    fc_total += __shfl(c, kGL - 1, kGL);
+                }
+                wave_sync_lds();
+            }
 
-            Problem<T, DIM> P{Si, Sj, W, Rr, t, 0, 0, 1, 1, 1, 1.f, 1.f, 1.f};
+            Problem<T, DIM, FC> P{Si, Sj, W, Rr, t, 0, 0, 1, 1, 1, 1.f, 1.f, 1.f};
             int total;
-            if (DIM == 3) {
+            if (FC) {
+                P.nA = cvi;
+                P.nB = cvj;
+                P.nfj = cvi + cvj + (DIM == 3 ? cei : 0);
+                P.F = &Fc;
+                total = fc_total;
+            } else if (DIM == 3) {
                 P.nA = cvi * cfj;
                 P.nB = cvj * cfi;
                 total = P.nA + P.nB + cei * cej;
@@ -840,9 +972,10 @@ __global__ void __launch_bounds__(64 * kWaves, OCC) k_pairs(BatchParams b, const
                 const bool has = q < total;
                 const bool last = __ballot(has) == 0;
                 if (!last) {
-                    const bool keep = has && P.candidate(q, rcm);
+                    const int qc = (FC && has) ? P.fc_code(q) : q;
+                    const bool keep = has && P.candidate(qc, rcm);
                     const unsigned long long m = __ballot(keep);
-                    if (keep) W.queue[count + __popcll(m & below & gmask)] = (unsigned short)q;
+                    if (keep) W.queue[count + popc_below(m & gmask)] = (unsigned short)qc;
                     count += __popcll(m & gmask);
                 }
                 // rounds end at the same problems for any lane count and any
@@ -892,11 +1025,11 @@ __global__ void __launch_bounds__(64 * kWaves, OCC) k_pairs(BatchParams b, const
                                 const ShapeTab<T> &Sgi = tab[gi];
                                 const ShapeTab<T> &Sgj = tab[gj];
                                 const V3<T> tg = v3<T>(qg.t[0], qg.t[1], qg.t[2]);
-                                const Problem<T, DIM> Pg{Sgi, Sgj, Wg, *reinterpret_cast<const M3<T> *>(qg.Rr), tg,
-                                                         Wg.nA, Wg.nB, Wg.nfj, Wg.nfi, Wg.nej,
-                                                         1.0f / (float)(Wg.nfj > 0 ? Wg.nfj : 1),
-                                                         1.0f / (float)(Wg.nfi > 0 ? Wg.nfi : 1),
-                                                         1.0f / (float)(Wg.nej > 0 ? Wg.nej : 1)};
+                                const Problem<T, DIM, FC> Pg{Sgi, Sgj, Wg, *reinterpret_cast<const M3<T> *>(qg.Rr), tg,
+                                                             Wg.nA, Wg.nB, Wg.nfj, Wg.nfi, Wg.nej,
+                                                             1.0f / (float)(Wg.nfj > 0 ? Wg.nfj : 1),
+                                                             1.0f / (float)(Wg.nfi > 0 ? Wg.nfi : 1),
+                                                             1.0f / (float)(Wg.nej > 0 ? Wg.nej : 1)};
                                 const double sigd = rl.rad[gi] + rl.rad[gj];
                                 const T gsig2 = (T)(sigd * sigd);
                                 const T grc = (T)(kWcaCut * sigd);
@@ -1062,7 +1195,11 @@ __global__ void __launch_bounds__(64 * kWaves, OCC) k_pairs(BatchParams b, const
             continue;
         }
         // ---- first stage on tile tt: 4 lanes per pair ----
-        const int grp1 = lane / kSepLanes, sub1 = lane % kSepLanes;
+        // (lane indices formed here, not held across the feature stage: an
+        // empty asm keeps the compiler from hoisting them out of the loop)
+        int lane1 = lane;
+        asm volatile("" : "+v"(lane1));
+        const int grp1 = lane1 / kSepLanes, sub1 = lane1 % kSepLanes;
         const int q = (tt - rl.first_tile) * kTile + wid * kPairsPerWave + grp1;
         const bool active = q < rl.np;
         // two dependent round trips: the pair entry, then both particle
@@ -1167,10 +1304,10 @@ __global__ void __launch_bounds__(64 * kWaves, OCC) k_pairs(BatchParams b, const
                     int at = 0;
                     if (lane == 0) at = atomicAdd(&l.ccount[rl.r], (int)__popcll(m));
                     at = __shfl(at, 0);
-                    if (need && sub1 == 0) l.cpairs[rl.poff + at + __popcll(m & below)] = ent;
+                    if (need && sub1 == 0) l.cpairs[rl.poff + at + popc_below(m)] = ent;
                 }
             } else if (need && sub1 == 0) {
-                QEnt<T> &e = qb[(tail + __popcll(m & below)) % kQCap];
+                QEnt<T> &e = qb[(tail + popc_below(m)) % kQCap];
                 e.ent = ent;
                 e.si = si;
                 e.sj = sj;
@@ -1641,43 +1778,59 @@ __global__ void k_rotations(BatchParams b, const SysParams *reps, StatePtrs s, L
     if (sizeof(T) == 4) rec64[i] = PartRec64{rc.x, rc.y, rc.z, s.qw[i], s.qx[i], s.qy[i], s.qz[i], 0.0};
 }
 
-template <typename T, int DIM, int GL, int OCC, int SL, int STAGE>
+template <typename T, int DIM, int GL, int OCC, int SL, int STAGE, bool FC>
 void pairs_t(const Launch &L, unsigned long long *stats, hipStream_t stream);
 
 // The compiled shapes: {8, 16} lanes per pair x {2, 3} wavefronts per SIMD
 // with the 4-lane separation stage, and 16 lanes x {2, 3} with the 16-lane
 // one; in the split form, the search kernel (4-lane separation stage,
 // kSearchOcc wavefronts per SIMD) and then the force kernel at {8, 16}
-// lanes x {2, 3} wavefronts.
+// lanes x {2, 3} wavefronts.  Each feature stage with the supporting-plane
+// prefilter or with the shape-local feature cells (FC); the FC feature
+// stage does not fit the 168 registers of 3 wavefronts per SIMD, so it is
+// compiled for 2 whatever the shape asks.
+template <typename T, int DIM, bool FC>
+void pairs_form(const Launch &L, unsigned long long *stats, hipStream_t stream)
+{
+    const bool g8 = L.b.pair_lanes == 8, o3 = !FC && L.b.pair_waves == 3;
+    constexpr int O3 = FC ? 2 : 3;  // (FC: never taken, o3 is false)
+    if (L.b.pair_split) {
+        pairs_t<T, DIM, 16, kSearchOcc, 4, kSearchOnly, false>(L, stats, stream);
+        if (g8)
+            o3 ? pairs_t<T, DIM, 8, O3, 4, kForces, FC>(L, stats, stream) : pairs_t<T, DIM, 8, 2, 4, kForces, FC>(L, stats, stream);
+        else
+            o3 ? pairs_t<T, DIM, 16, O3, 4, kForces, FC>(L, stats, stream)
+               : pairs_t<T, DIM, 16, 2, 4, kForces, FC>(L, stats, stream);
+    } else if (L.b.pair_sep == 16)
+        o3 ? pairs_t<T, DIM, 16, O3, 16, kFused, FC>(L, stats, stream) : pairs_t<T, DIM, 16, 2, 16, kFused, FC>(L, stats, stream);
+    else if (g8)
+        o3 ? pairs_t<T, DIM, 8, O3, 4, kFused, FC>(L, stats, stream) : pairs_t<T, DIM, 8, 2, 4, kFused, FC>(L, stats, stream);
+    else
+        o3 ? pairs_t<T, DIM, 16, O3, 4, kFused, FC>(L, stats, stream) : pairs_t<T, DIM, 16, 2, 4, kFused, FC>(L, stats, stream);
+}
+
 template <typename T, int DIM>
 void pairs_shape(const Launch &L, unsigned long long *stats, hipStream_t stream)
 {
-    const bool g8 = L.b.pair_lanes == 8, o3 = L.b.pair_waves == 3;
-    if (L.b.pair_split) {
-        pairs_t<T, DIM, 16, kSearchOcc, 4, kSearchOnly>(L, stats, stream);
-        if (g8) o3 ? pairs_t<T, DIM, 8, 3, 4, kForces>(L, stats, stream) : pairs_t<T, DIM, 8, 2, 4, kForces>(L, stats, stream);
-        else o3 ? pairs_t<T, DIM, 16, 3, 4, kForces>(L, stats, stream) : pairs_t<T, DIM, 16, 2, 4, kForces>(L, stats, stream);
-    } else if (L.b.pair_sep == 16)
-        o3 ? pairs_t<T, DIM, 16, 3, 16, kFused>(L, stats, stream) : pairs_t<T, DIM, 16, 2, 16, kFused>(L, stats, stream);
-    else if (g8) o3 ? pairs_t<T, DIM, 8, 3, 4, kFused>(L, stats, stream) : pairs_t<T, DIM, 8, 2, 4, kFused>(L, stats, stream);
-    else o3 ? pairs_t<T, DIM, 16, 3, 4, kFused>(L, stats, stream) : pairs_t<T, DIM, 16, 2, 4, kFused>(L, stats, stream);
+    if (L.b.feature_cells) pairs_form<T, DIM, true>(L, stats, stream);
+    else pairs_form<T, DIM, false>(L, stats, stream);
 }
 
-template <typename T, int DIM, int GL, int OCC, int SL, int STAGE>
+template <typename T, int DIM, int GL, int OCC, int SL, int STAGE, bool FC>
 void pairs_t(const Launch &L, unsigned long long *stats, hipStream_t stream)
 {
-    const size_t sh = pair_kernel_lds(sizeof(T) == 4 ? DEM_FP32 : DEM_FP64, L.b.tab_slots, GL, SL, STAGE);
+    const size_t sh = pair_kernel_lds(sizeof(T) == 4 ? DEM_FP32 : DEM_FP64, L.b.tab_slots, GL, SL, STAGE, FC ? 1 : 0);
     const int grid = STAGE == kSearchOnly ? L.b.search_blocks : L.b.pair_blocks;
     const auto rot = reinterpret_cast<const PartRec<T> *>(L.f.rot);
     const auto rec = reinterpret_cast<SlotRec<T> *>(L.f.rec);
     const auto tab = reinterpret_cast<const ShapeTab<T> *>(L.f.tab);
     const auto tab64 = reinterpret_cast<const ShapeTab<double> *>(L.f.tab64);
     if (stats)
-        k_pairs<T, DIM, GL, true, OCC, SL, STAGE><<<grid, 64 * kWaves, sh, stream>>>(L.b, L.reps, L.s, L.l, rot, L.f.rec64,
-                                                                                  rec, tab, tab64, stats);
+        k_pairs<T, DIM, GL, true, OCC, SL, STAGE, FC><<<grid, 64 * kWaves, sh, stream>>>(L.b, L.reps, L.s, L.l, rot,
+                                                                                      L.f.rec64, rec, tab, tab64, stats);
     else
-        k_pairs<T, DIM, GL, false, OCC, SL, STAGE><<<grid, 64 * kWaves, sh, stream>>>(L.b, L.reps, L.s, L.l, rot, L.f.rec64,
-                                                                                   rec, tab, tab64, nullptr);
+        k_pairs<T, DIM, GL, false, OCC, SL, STAGE, FC><<<grid, 64 * kWaves, sh, stream>>>(L.b, L.reps, L.s, L.l, rot,
+                                                                                       L.f.rec64, rec, tab, tab64, nullptr);
 }
 
 template <typename T, int DIM>
@@ -1733,7 +1886,7 @@ void launch_gather(const Launch &L, bool kick, hipStream_t stream)
     }
 }
 
-size_t pair_kernel_lds(int precision, int tab_slots, int lanes, int sep, int stage)
+size_t pair_kernel_lds(int precision, int tab_slots, int lanes, int sep, int stage, int fc)
 {
     const size_t w = precision == DEM_FP32 ? sizeof(ShapeTab<float>) : sizeof(ShapeTab<double>);
     const size_t pl = precision == DEM_FP32 ? sizeof(PairLds<float>) : sizeof(PairLds<double>);
@@ -1742,47 +1895,52 @@ size_t pair_kernel_lds(int precision, int tab_slots, int lanes, int sep, int sta
     if (stage == kSearchOnly)  // tables, replica, and the last workgroup's scan
         return (size_t)tab_slots * w + sizeof(RepLds) + sizeof(int) * 64 * kWaves;
     return (size_t)tab_slots * w + sizeof(RepLds) + kWaves * (64 / lanes) * pl + kWaves * queue_slots(sep, lanes) * qe +
-           (lanes == 16 ? kWaves * 64 * acc : 0);
+           (lanes == 16 ? kWaves * 64 * acc : 0) + (fc ? kWaves * (64 / lanes) * sizeof(PairFc) : 0);
 }
 
 namespace {
-template <typename T, int DIM, int STAGE>
+template <typename T, int DIM, int STAGE, bool FC>
 hipError_t pair_occupancy(int *per_cu, size_t lds, int lanes, int waves, int sep)
 {
     const int t = 64 * kWaves;
     auto occ = [&](auto kernel) { return hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, kernel, t, lds); };
+    constexpr int O3 = FC ? 2 : 3;  // the FC feature stage is compiled for 2 wavefronts per SIMD only
     if constexpr (STAGE == kSearchOnly) {
-        return occ(k_pairs<T, DIM, 16, false, kSearchOcc, 4, kSearchOnly>);
+        return occ(k_pairs<T, DIM, 16, false, kSearchOcc, 4, kSearchOnly, false>);
     } else {
         if constexpr (STAGE == kFused)
             if (sep == 16)
-                return waves == 3 ? occ(k_pairs<T, DIM, 16, false, 3, 16, STAGE>) : occ(k_pairs<T, DIM, 16, false, 2, 16, STAGE>);
+                return waves == 3 ? occ(k_pairs<T, DIM, 16, false, O3, 16, STAGE, FC>)
+                                  : occ(k_pairs<T, DIM, 16, false, 2, 16, STAGE, FC>);
         if (lanes == 8)
-            return waves == 3 ? occ(k_pairs<T, DIM, 8, false, 3, 4, STAGE>) : occ(k_pairs<T, DIM, 8, false, 2, 4, STAGE>);
-        return waves == 3 ? occ(k_pairs<T, DIM, 16, false, 3, 4, STAGE>) : occ(k_pairs<T, DIM, 16, false, 2, 4, STAGE>);
+            return waves == 3 ? occ(k_pairs<T, DIM, 8, false, O3, 4, STAGE, FC>) : occ(k_pairs<T, DIM, 8, false, 2, 4, STAGE, FC>);
+        return waves == 3 ? occ(k_pairs<T, DIM, 16, false, O3, 4, STAGE, FC>) : occ(k_pairs<T, DIM, 16, false, 2, 4, STAGE, FC>);
     }
 }
 
 template <typename T, int DIM>
-hipError_t pair_occupancy_stage(int *per_cu, size_t lds, int lanes, int waves, int sep, int stage)
+hipError_t pair_occupancy_stage(int *per_cu, size_t lds, int lanes, int waves, int sep, int stage, int fc)
 {
-    if (stage == kSearchOnly) return pair_occupancy<T, DIM, kSearchOnly>(per_cu, lds, lanes, waves, sep);
-    if (stage == kForces) return pair_occupancy<T, DIM, kForces>(per_cu, lds, lanes, waves, sep);
-    return pair_occupancy<T, DIM, kFused>(per_cu, lds, lanes, waves, sep);
+    if (stage == kSearchOnly) return pair_occupancy<T, DIM, kSearchOnly, false>(per_cu, lds, lanes, waves, sep);
+    if (stage == kForces)
+        return fc ? pair_occupancy<T, DIM, kForces, true>(per_cu, lds, lanes, waves, sep)
+                  : pair_occupancy<T, DIM, kForces, false>(per_cu, lds, lanes, waves, sep);
+    return fc ? pair_occupancy<T, DIM, kFused, true>(per_cu, lds, lanes, waves, sep)
+              : pair_occupancy<T, DIM, kFused, false>(per_cu, lds, lanes, waves, sep);
 }
 }  // namespace
 
-int pair_blocks_resident(int precision, int dim, int tab_slots, int lanes, int waves, int sep, int stage)
+int pair_blocks_resident(int precision, int dim, int tab_slots, int lanes, int waves, int sep, int stage, int fc)
 {
-    const size_t lds = pair_kernel_lds(precision, tab_slots, lanes, sep, stage);
+    const size_t lds = pair_kernel_lds(precision, tab_slots, lanes, sep, stage, fc);
     int per_cu = 0, cus = 0, dev = 0;
     hipError_t e;
     if (precision == DEM_FP32)
-        e = dim == 3 ? pair_occupancy_stage<float, 3>(&per_cu, lds, lanes, waves, sep, stage)
-                     : pair_occupancy_stage<float, 2>(&per_cu, lds, lanes, waves, sep, stage);
+        e = dim == 3 ? pair_occupancy_stage<float, 3>(&per_cu, lds, lanes, waves, sep, stage, fc)
+                     : pair_occupancy_stage<float, 2>(&per_cu, lds, lanes, waves, sep, stage, fc);
     else
-        e = dim == 3 ? pair_occupancy_stage<double, 3>(&per_cu, lds, lanes, waves, sep, stage)
-                     : pair_occupancy_stage<double, 2>(&per_cu, lds, lanes, waves, sep, stage);
+        e = dim == 3 ? pair_occupancy_stage<double, 3>(&per_cu, lds, lanes, waves, sep, stage, fc)
+                     : pair_occupancy_stage<double, 2>(&per_cu, lds, lanes, waves, sep, stage, fc);
     if (e != hipSuccess || hipGetDevice(&dev) != hipSuccess ||
         hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
         return 512;

@@ -31,6 +31,16 @@ constexpr int kDefaultPairLanes = 16;
 constexpr int kDefaultPairWaves = 2;
 constexpr int kDefaultPairSep = 4;
 __host__ __device__ constexpr int pair_tile(int sep_lanes) { return kPairWaves * (64 / sep_lanes); }
+// Shape-local feature cells (Sec. V): a uniform grid over each shape's
+// body frame, kFcGrid3 cells per axis in 3D (kFcGrid2 in 2D), covering the
+// shape's circumradius plus its reach.  Cell c holds .x: the faces (3D) or
+// edges (2D) within reach of a vertex of another shape lying in c, and .y
+// (3D): the edges within reach of an edge of another shape whose midpoint
+// lies in c.  Built on the host, conservatively (the cell's centre
+// distance less its half diagonal).
+constexpr int kFcGrid3 = 12, kFcGrid2 = 40;
+constexpr int kFcCells = kFcGrid2 * kFcGrid2 > kFcGrid3 * kFcGrid3 * kFcGrid3 ? kFcGrid2 * kFcGrid2
+                                                                             : kFcGrid3 * kFcGrid3 * kFcGrid3;
 // What one launch of the pair kernel does: both stages (fused), or, in the
 // split form, the contact search (separation stage, compacting the pairs it
 // keeps) and then the contact forces (feature stage on those pairs).
@@ -126,8 +136,10 @@ __device__ inline void set_stamp(SlotRec<double> &w, unsigned s) { w.pad0 = __lo
 constexpr int kMaxSep = DEM_MAX_EDGES > DEM_MAX_FACES ? DEM_MAX_EDGES : DEM_MAX_FACES;
 template <typename T>
 struct alignas(16) ShapeTab {
-    int nv, ne, nf, pad0;
-    T r, R, pad1, pad2;
+    int nv, ne, nf;
+    int fc_g;                    // shape-local feature cells: fc_g cells per axis
+    T r, R;
+    T fc_lo, fc_ih;              // covering [fc_lo, -fc_lo] per axis, 1 / cell width
     T v[DEM_MAX_VERTS][3];
     int e[DEM_MAX_EDGES][2];
     T ed[DEM_MAX_EDGES][3];      // edge vector b - a
@@ -206,6 +218,7 @@ struct BatchParams {
     int pair_sep;                // lanes per pair in its separation stage (4 or 16)
     int tile;                    // pairs per tile: pair_tile(pair_sep)
     int pair_split;              // 1: two kernels, contact search then contact forces
+    int feature_cells;           // 1: the feature search reads the shape-local feature cells
     int search_blocks;           // grid of the search kernel of the split form
     int dim;
 };
@@ -244,6 +257,8 @@ struct ListPtrs {
     // count per replica, the force kernel's first unit of each replica
     // ([nrep + 1]) and two tickets, laid out as split_ctl below.
     int4 *cpairs;
+    // shape-local feature cells ([shape slots][kFcCells]; see fc_lookup)
+    const uint2 *fcells;
     int32_t *ccount;             // [replica slots] compacted pairs (zero between evaluations)
     int32_t *cunit;              // [replica slots + 1] first force unit of each replica
     int32_t *ctick;              // [2] blocks done: search kernel, force kernel
@@ -415,8 +430,8 @@ __device__ inline void cell_insert(const SysParams &p, const ListPtrs &l, int i,
 
 // Dynamic LDS of the pair kernel, and how many of its blocks the device
 // holds at once.
-size_t pair_kernel_lds(int precision, int tab_slots, int lanes, int sep, int stage);
-int pair_blocks_resident(int precision, int dim, int tab_slots, int lanes, int waves, int sep, int stage);
+size_t pair_kernel_lds(int precision, int tab_slots, int lanes, int sep, int stage, int fc);
+int pair_blocks_resident(int precision, int dim, int tab_slots, int lanes, int waves, int sep, int stage, int fc);
 
 // Per-particle records (position, rotation, shape id) from the state arrays.
 void launch_rotations(const Launch &L, hipStream_t stream);

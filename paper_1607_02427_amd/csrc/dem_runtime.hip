@@ -88,6 +88,7 @@ struct dem_system {
     int pair_waves = kDefaultPairWaves;  // wavefronts per SIMD
     int pair_sep = kDefaultPairSep;      // and lanes per pair of its separation stage;
     int pair_split = 0;                  // 1: search and force kernels instead of one
+    int feature_cells = 0;               // 1: the feature search reads the shape-local cells
     BatchParams bp{};
     std::vector<Replica> reps;
     SlotArena chunks, cells, shapes;
@@ -101,6 +102,7 @@ struct dem_system {
     hipStream_t stream = nullptr;
     hipStream_t cap_stream = nullptr;
     void *tab64 = nullptr, *tab32 = nullptr;
+    uint2 *fcells = nullptr;             // [shape slots][kFcCells] shape-local feature cells
     void *rot = nullptr;         // [N] PartRec in the force precision
     PartRec64 *rec64 = nullptr;  // [N] FP64 position and orientation (FP32 path)
     void *rec = nullptr;         // [cap][N] SlotRec in the force precision
@@ -423,6 +425,109 @@ dem_status build_table(dem_system *h, int idx, const dem_shape_desc &d, int dim,
     return DEM_OK;
 }
 
+// ---- shape-local feature cells ----------------------------------------
+
+HostVec hv(const double (&a)[3]) { return {a[0], a[1], a[2]}; }
+
+double seg_dist(HostVec p, HostVec a, HostVec b)
+{
+    const HostVec d = hsub(b, a), r = hsub(p, a);
+    const double dd = hdot(d, d);
+    const double s = dd > 0.0 ? std::clamp(hdot(r, d) / dd, 0.0, 1.0) : 0.0;
+    const HostVec q = hsub(r, HostVec{s * d.x, s * d.y, s * d.z});
+    return std::sqrt(hdot(q, q));
+}
+
+// Distance from p to face f, a planar polygon (convex or not): to its plane
+// when p projects inside the loop (crossing number in face coordinates),
+// else to its nearest loop edge.
+double face_dist(const ShapeTab<double> &T, int f, HostVec p)
+{
+    const int k0 = T.foff[f], k1 = T.foff[f + 1];
+    const HostVec n = hv(T.fn[f]), e1 = hv(T.fe1[f]), e2 = hcross(n, e1);
+    const double d = hdot(n, p) - T.fo[f];
+    const HostVec r = hsub(p, hv(T.v[T.floop[k0]]));
+    const double x = hdot(r, e1), y = hdot(r, e2);
+    bool in = false;
+    for (int k = k0; k < k1; ++k) {
+        const int kn = k + 1 < k1 ? k + 1 : k0;
+        const double ax = T.lxy[k][0], ay = T.lxy[k][1], bx = T.lxy[kn][0], by = T.lxy[kn][1];
+        if ((ay > y) != (by > y) && x < ax + (y - ay) * (bx - ax) / (by - ay)) in = !in;
+    }
+    if (in) return std::fabs(d);
+    double m = 1e300;
+    for (int k = k0; k < k1; ++k) {
+        const int kn = k + 1 < k1 ? k + 1 : k0;
+        m = std::min(m, seg_dist(p, hv(T.v[T.floop[k]]), hv(T.v[T.floop[kn]])));
+    }
+    return m;
+}
+
+// Reach of shape s's cells among the replica's shapes t: a vertex of any
+// shape within the cutoff of a feature of s (sigma = r_s + r_max), with room
+// for the rounding of FP32 positions; an edge, within that plus the longest
+// half edge (the edge is looked up by its midpoint).  L: half width of the
+// grid, beyond which no point is within reach of s.
+struct FcReach {
+    double v, e, L;
+};
+FcReach fc_reach(const std::vector<ShapeTab<double>> &t, int s)
+{
+    double rmax = 0.0, Rmax = 0.0, ehmax = 0.0;
+    for (const ShapeTab<double> &T : t) {
+        rmax = std::max(rmax, T.r);
+        Rmax = std::max(Rmax, T.R);
+        for (int k = 0; k < T.ne; ++k) ehmax = std::max(ehmax, T.eh[k]);
+    }
+    const ShapeTab<double> &S = t[s];
+    const double rc = kWcaCut * (S.r + rmax);
+    const double v = rc * 1.001 + 1e-4 * (S.R + Rmax + rc);
+    return {v, v + ehmax, S.R + v + ehmax};
+}
+
+// Grid geometry of every shape's cells, in both precisions' tables.
+void fc_geometry(std::vector<ShapeTab<double>> &t64, std::vector<ShapeTab<float>> &t32, int dim)
+{
+    for (size_t s = 0; s < t64.size(); ++s) {
+        const FcReach q = fc_reach(t64, (int)s);
+        const int g = dim == 3 ? kFcGrid3 : kFcGrid2;
+        t64[s].fc_g = t32[s].fc_g = g;
+        t64[s].fc_lo = -q.L;
+        t64[s].fc_ih = g / (2.0 * q.L);
+        t32[s].fc_lo = (float)t64[s].fc_lo;
+        t32[s].fc_ih = (float)t64[s].fc_ih;
+    }
+}
+
+// The cells of shape s (kFcCells entries; see kFcGrid3): each cell keeps
+// the features whose distance from its centre is within reach plus its half
+// diagonal, so every point of the cell is covered.
+void fc_build(const std::vector<ShapeTab<double>> &t, int s, int dim, uint2 *cells)
+{
+    const ShapeTab<double> &T = t[s];
+    const FcReach q = fc_reach(t, s);
+    const int g = T.fc_g;
+    const double w = 1.0 / T.fc_ih, hd = 0.5 * w * std::sqrt((double)dim);
+    for (int c = 0; c < kFcCells; ++c) cells[c] = make_uint2(0u, 0u);
+    for (int iz = 0; iz < (dim == 3 ? g : 1); ++iz)
+        for (int iy = 0; iy < g; ++iy)
+            for (int ix = 0; ix < g; ++ix) {
+                const HostVec c{T.fc_lo + (ix + 0.5) * w, T.fc_lo + (iy + 0.5) * w,
+                                dim == 3 ? T.fc_lo + (iz + 0.5) * w : 0.0};
+                unsigned fm = 0u, em = 0u;
+                if (dim == 3) {
+                    for (int f = 0; f < T.nf; ++f)
+                        if (face_dist(T, f, c) <= q.v + hd) fm |= 1u << f;
+                    for (int k = 0; k < T.ne; ++k)
+                        if (seg_dist(c, hv(T.v[T.e[k][0]]), hv(T.v[T.e[k][1]])) <= q.e + hd) em |= 1u << k;
+                } else {
+                    for (int k = 0; k < T.ne; ++k)
+                        if (seg_dist(c, hv(T.v[T.e[k][0]]), hv(T.v[T.e[k][1]])) <= q.v + hd) fm |= 1u << k;
+                }
+                cells[(iz * g + iy) * g + ix] = make_uint2(fm, em);
+            }
+}
+
 void to_float(const ShapeTab<double> &D, ShapeTab<float> &F)
 {
     std::memset(&F, 0, sizeof F);
@@ -530,6 +635,7 @@ void refresh_batch(dem_system *h)
     b.pair_waves = h->pair_waves;
     b.pair_sep = h->pair_sep;
     b.pair_split = h->pair_split;
+    b.feature_cells = h->feature_cells;
     b.tile = pair_tile(h->pair_sep);
     long long tiles = 0;
     for (size_t r = 0; r < h->reps.size(); ++r) {
@@ -545,9 +651,9 @@ void refresh_batch(dem_system *h)
     // (a second round adds a whole block's latency but evens out the
     // tail), no more than the tiles use
     const int stage = b.pair_split ? kForces : kFused;
-    const long long resident =
-        (long long)pair_blocks_resident(h->precision, h->dim, b.tab_slots, b.pair_lanes, b.pair_waves, b.pair_sep, stage) *
-        h->pair_grid;
+    const long long resident = (long long)pair_blocks_resident(h->precision, h->dim, b.tab_slots, b.pair_lanes,
+                                                               b.pair_waves, b.pair_sep, stage, b.feature_cells) *
+                               h->pair_grid;
     // the split form's force kernel takes units of kPairWaves * 64 / lanes
     // compacted pairs, at most one per that many pair slots
     const long long units = tiles * b.tile / (kPairWaves * (64 / b.pair_lanes)) + b.nrep;
@@ -556,7 +662,7 @@ void refresh_batch(dem_system *h)
     b.search_blocks = 8;
     if (b.pair_split) {
         const long long rs = pair_blocks_resident(h->precision, h->dim, b.tab_slots, b.pair_lanes, b.pair_waves,
-                                                  b.pair_sep, kSearchOnly);
+                                                  b.pair_sep, kSearchOnly, 0);
         b.search_blocks = (int)((std::max<long long>(8, std::min(tiles, rs)) + 7) / 8 * 8);
     }
 }
@@ -684,6 +790,7 @@ dem_status alloc_core(dem_system *h, int Ncap, int Ccap, int Scap, int Rcap)
               hipMalloc(&h->d_chunk_rep, sizeof(int32_t) * nch) == hipSuccess &&
               hipMalloc(&h->tab64, sizeof(ShapeTab<double>) * Scap) == hipSuccess &&
               hipMalloc(&h->tab32, sizeof(ShapeTab<float>) * Scap) == hipSuccess &&
+              hipMalloc(&h->fcells, sizeof(uint2) * kFcCells * Scap) == hipSuccess &&
               hipMalloc(&h->ke_part, sizeof(double) * kKePer * nch) == hipSuccess &&
               hipMalloc(&h->e_part, sizeof(double) * 12 * nch) == hipSuccess &&
               hipMalloc(&h->thermo, sizeof(double) * TH_COUNT * Rcap) == hipSuccess &&
@@ -705,6 +812,7 @@ dem_status alloc_core(dem_system *h, int Ncap, int Ccap, int Scap, int Rcap)
               hipMalloc(&h->rot, partrec_bytes(h->precision) * N) == hipSuccess &&
               (h->precision != DEM_FP32 || hipMalloc(&h->rec64, sizeof(PartRec64) * N) == hipSuccess);
     if (!ok) return fail(h, DEM_E_OOM, "device allocation failed");
+    h->lst.fcells = h->fcells;
     h->lst.cunit = h->lst.ccount + Rcap;
     h->lst.ctick = h->lst.cunit + Rcap + 1;
     if (h->batch) {  // the batch's own state and output arrays
@@ -746,7 +854,7 @@ dem_status alloc_core(dem_system *h, int Ncap, int Ccap, int Scap, int Rcap)
 void free_all(dem_system *h)
 {
     drop_graph(h);
-    void *ptrs[] = {h->d_reps, h->d_chunk_rep, h->tab64, h->tab32, h->ke_part, h->e_part, h->thermo, h->budget,
+    void *ptrs[] = {h->d_reps, h->d_chunk_rep, h->tab64, h->tab32, h->fcells, h->ke_part, h->e_part, h->thermo, h->budget,
                     h->steps, h->stats, h->lst.flags, h->lst.gflags, h->lst.tile_start, h->lst.ccount, h->lst.cell_count,
                     h->lst.cell_slot, h->lst.pcell, h->lst.n_nbr, h->lst.xlast, h->lst.klo,
                     h->lst.pstart, h->lst.ptot, h->lst.nbr, h->lst.pairs, h->lst.cpairs, h->lst.smask, h->rot, h->rec,
@@ -898,6 +1006,7 @@ dem_status describe_replica(dem_system *h, const dem_params &p, Replica &R, std:
         Rmax = std::max(Rmax, t64[s].R);
         rmax = std::max(rmax, p.shapes[s].rounding_radius);
     }
+    fc_geometry(t64, t32, p.dim);
     // r_list = 2 R_max + 2^(1/6) sigma_max + skin
     const double rl = 2.0 * Rmax + kWcaCut * (2.0 * rmax) + p.skin;
     R.r_list = rl;
@@ -1006,6 +1115,13 @@ dem_status place_replica(dem_system *h, Replica &R, const std::vector<ShapeTab<d
                              sizeof(ShapeTab<double>) * R.nshapes, hipMemcpyHostToDevice, h->stream));
     HIPCHK(h, hipMemcpyAsync(static_cast<ShapeTab<float> *>(h->tab32) + R.shape0, t32.data(),
                              sizeof(ShapeTab<float>) * R.nshapes, hipMemcpyHostToDevice, h->stream));
+    {
+        std::vector<uint2> cells((size_t)kFcCells * R.nshapes);
+        for (int s = 0; s < R.nshapes; ++s) fc_build(t64, s, R.sp.dim, cells.data() + (size_t)s * kFcCells);
+        HIPCHK(h, hipMemcpyAsync(h->fcells + (size_t)R.shape0 * kFcCells, cells.data(), sizeof(uint2) * cells.size(),
+                                 hipMemcpyHostToDevice, h->stream));
+        HIPCHK(h, hipStreamSynchronize(h->stream));  // the host cells go out of scope
+    }
     HIPCHK(h, hipMemsetAsync(h->lst.cell_count + R.cell0, 0, sizeof(int32_t) * R.ncells, h->stream));
     HIPCHK(h, hipMemsetAsync(h->lst.flags + FLAG_COUNT * slot, 0, sizeof(int32_t) * FLAG_COUNT, h->stream));
     if (n > 0) {  // the slots' previous owner left its lists there
@@ -1251,6 +1367,7 @@ size_t dem_footprint_bytes(const dem_params *p)
                               split_words(1)) +
            sizeof(double) * (3 * n + (kKePer + 12) * nch + TH_COUNT + 2) + sizeof(unsigned long long) * ST_COUNT +
            (partrec_bytes(p->precision) + (p->precision == DEM_FP32 ? sizeof(PartRec64) : 0)) * n +
+           sizeof(uint2) * kFcCells * DEM_MAX_SHAPES +
            rec_bytes(p->precision) * (size_t)cap * n + sizeof(uint32_t) * (size_t)slot_words(cap) * n + sizeof(SysParams) + 2 * DEM_MAX_SHAPES * sizeof(ShapeTab<double>) + 256;
 }
 
@@ -1775,6 +1892,17 @@ dem_status dem_set_pair_shape(dem_handle h, int32_t lanes_per_pair, int32_t grid
     refresh_batch(h);
     launch_lists(make_launch(h), LISTS_PLAN, h->stream);  // tiles of the new size
     HIPCHK(h, hipGetLastError());
+    drop_graph(h);
+    return DEM_OK;
+}
+
+dem_status dem_set_feature_cells(dem_handle h, int32_t on)
+{
+    if (!h) return fail(nullptr, DEM_E_ARG, "null handle");
+    if (on != 0 && on != 1) return fail(h, DEM_E_ARG, "feature cells: %d (0 or 1)", on);
+    if (on == h->feature_cells) return DEM_OK;
+    h->feature_cells = on;
+    refresh_batch(h);
     drop_graph(h);
     return DEM_OK;
 }

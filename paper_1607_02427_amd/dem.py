@@ -130,6 +130,8 @@ def lib():
         L.dem_time_forces.restype = st
         L.dem_set_pair_shape.argtypes = [C.c_void_p, C.c_int32, C.c_int32, C.c_int32, C.c_int32, C.c_int32]
         L.dem_set_pair_shape.restype = st
+        L.dem_set_feature_cells.argtypes = [C.c_void_p, C.c_int32]
+        L.dem_set_feature_cells.restype = st
         L.dem_tune_pairs.argtypes = [C.c_void_p, C.c_int32, _ip, _dp]
         L.dem_tune_pairs.restype = st
         L.dem_footprint_bytes.argtypes = [C.POINTER(Params)]
@@ -411,6 +413,10 @@ class DemSystem:
         self._check(lib().dem_set_pair_shape(self.h, int(lanes), int(grid), int(waves), int(sep), int(split)),
                     "dem_set_pair_shape")
 
+    def set_feature_cells(self, on: bool):
+        """Feature search through the shape-local feature cells (True) or the supporting-plane prefilter."""
+        self._check(lib().dem_set_feature_cells(self.h, 1 if on else 0), "dem_set_feature_cells")
+
     def tune_pairs(self, reps: int = 20) -> dict:
         """Times every pair-kernel shape on the current state and keeps the fastest."""
         return _tune_pairs(self._check, self.h, reps)
@@ -578,6 +584,9 @@ class DemBatch:
     def set_pair_shape(self, lanes: int, grid: int = 1, waves: int = 2, sep: int = 4, split: int = 0):
         self._check(lib().dem_set_pair_shape(self.h, int(lanes), int(grid), int(waves), int(sep), int(split)),
                     "dem_set_pair_shape")
+
+    def set_feature_cells(self, on: bool):
+        self._check(lib().dem_set_feature_cells(self.h, 1 if on else 0), "dem_set_feature_cells")
 
     def tune_pairs(self, reps: int = 5) -> dict:
         return _tune_pairs(self._check, self.h, reps)
