@@ -563,6 +563,7 @@ class DemBatch:
         with torch.cuda.device(self.device):
             t = _state_tensors(system, self.device)
             o = _output_tensors(n, self.device)
+        torch.cuda.current_stream(self.device).synchronize()  # the batch's stream may be another one
         self._check(lib().dem_batch_read(self.h, int(rid), C.byref(_state_ptrs(t)), C.byref(_out_ptrs(o))),
                     "dem_batch_read")
         self.sync()

@@ -15,7 +15,9 @@ exactly at its requested step count, and it is retired (its state copied
 out if asked, its slots freed) at the next poll.  The loop steps the
 batches in chunks of `chunk` steps and polls between chunks, which is when
 arrivals are admitted and finished requests retired: requests that arrive
-while others are on the device join them without waiting for them.  Each
+while others are on the device join them without waiting for them.  The
+two dimensions' batches run on streams of their own, so a chunk's 2D and
+3D steps overlap on the device.  Each
 batch retunes its pair-kernel shape whenever its live particle count has
 doubled since the last tuning (the shape never changes results).
 
@@ -76,8 +78,12 @@ class Server:
 
     def _batch(self, dim: int) -> dem.DemBatch:
         if dim not in self.batches:
+            import torch
+            # each dimension's batch on a stream of its own (default priority),
+            # so the 2D and 3D steps of a chunk run side by side on the device
             self.batches[dim] = dem.DemBatch(dim, self.precision, max_replicas=self.max_replicas,
-                                             max_particles=self.max_particles[dim], budget_bytes=self.budget)
+                                             max_particles=self.max_particles[dim], budget_bytes=self.budget,
+                                             stream=torch.cuda.Stream())
         return self.batches[dim]
 
     def run(self, systems: List, log: Optional[Callable[[str], None]] = None) -> List[Record]:
