@@ -81,17 +81,31 @@ def counters_now(g):
     return g.force_stats(reset=True)
 
 
-def run_path(system, precision, steps, warmup, counting=False, tune=True, cells=False):
+# --pair-shape and --feature-cells: a fixed pair-kernel shape instead of the
+# tuner's choice, and the shape-local feature cells, on every leg
+FORCED_SHAPE = None
+CELLS = False
+
+
+def pick_shape(g, reps):
+    """The tuner's shape, or the forced one (reported the same way)."""
+    if FORCED_SHAPE is None:
+        return g.tune_pairs(reps)
+    g.set_pair_shape(*FORCED_SHAPE)
+    return dict(zip(("lanes", "grid", "waves", "sep", "split"), FORCED_SHAPE), forced=True)
+
+
+def run_path(system, precision, steps, warmup, counting=False, tune=True, cells=None):
     import torch
     from paper_1607_02427_amd import dem
     g = dem.DemSystem(system, precision)
-    g.set_feature_cells(cells)
+    g.set_feature_cells(CELLS if cells is None else cells)
     stream = g.stream
     if counting:
         g.set_counting(True)
     g.step(warmup)
     g.sync()
-    shape = g.tune_pairs(20) if tune else None
+    shape = pick_shape(g, 20) if tune else None
     start = counters_now(g)  # the state the timed window starts from (forces are recomputed, unchanged)
     if counting:
         g.force_stats(reset=True)
@@ -191,11 +205,12 @@ def run_batched(replicas, steps, warmup, precision="fp32"):
     from paper_1607_02427_amd import dem
     total = sum(s.n for s in replicas)
     b = dem.DemBatch(3, precision, max_replicas=len(replicas) + 8, max_particles=total + 64 * len(replicas))
+    b.set_feature_cells(CELLS)
     for s in replicas:
         b.add(s)
     b.step(warmup)
     b.sync()
-    shape = b.tune_pairs(3)
+    shape = pick_shape(b, 3)
     e0 = torch.cuda.Event(enable_timing=True)
     e1 = torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
@@ -325,7 +340,7 @@ def table1_workloads(steps=(2000, 1000, 300), warmup=200):
                 out.append(dict(shape=name, n=s.n, feature_search="cells" if cells else "planes", steps=k, value=ptps,
                                 ms_per_step=r["gpu_ms"] / k,
                                 pair_shape=[r["pair_shape"][a] for a in ("lanes", "grid", "waves", "sep", "split")],
-                                pair_ms=min(r["pair_shape"]["mean_ms"].values()),
+                                pair_ms=min(r["pair_shape"].get("mean_ms", {"": float("nan")}).values()),
                                 counters={a: c[a] for a in ("pairs", "separated", "features", "vf_near", "ee_near",
                                                             "in_cutoff")}))
                 log(f"[table1] {name} N={s.n} {'cells' if cells else 'planes'}: {ptps:.3e} PTPS "
@@ -355,6 +370,10 @@ def main():
     ap.add_argument("--scale-steps", type=int, default=300)
     ap.add_argument("--copy-mb", type=int, default=0,
                     help="finish with device copies of this many MiB (scale for the HBM byte counters)")
+    ap.add_argument("--pair-shape", default=None,
+                    help="lanes,grid,waves,sep,split: this pair-kernel shape on every leg instead of the tuner's")
+    ap.add_argument("--feature-cells", action="store_true",
+                    help="the shape-local feature cells on every leg (the table1 runs take both)")
     ap.add_argument("--table1", action="store_true",
                     help="run only the cube and icosahedron workloads of the paper's Table I and print their JSON line")
     ap.add_argument("--energy-study", action="store_true",
@@ -362,6 +381,11 @@ def main():
     ap.add_argument("--no-sequential", action="store_true",
                     help="skip the one-at-a-time plain FP64 runs of the batched and served workloads")
     args = ap.parse_args()
+    global FORCED_SHAPE, CELLS
+    if args.pair_shape:
+        FORCED_SHAPE = tuple(int(v) for v in args.pair_shape.split(","))
+        assert len(FORCED_SHAPE) == 5, "--pair-shape lanes,grid,waves,sep,split"
+    CELLS = args.feature_cells
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU layout is design-only.",
               file=sys.stderr)
