@@ -316,19 +316,21 @@ def energy_fluctuations(dts_tau=(0.000625, 0.00125, 0.0025, 0.005, 0.01), durati
     return out
 
 
-def table1_workloads(steps=(2000, 1000, 300), warmup=200):
-    """The paper's Table I shapes and sizes on this engine: rounded cubes and
-    rounded icosahedra (edge 1, r = 0.15 and 0.1) at N = 6^3, 16^3 and 40^3
-    (its 256, 4096 and 65536 on cubic lattices), volume fraction 0.4, NVT
-    kT = 1 after `warmup` steps, FP32 pair geometry, tuned pair shape; each
-    with the supporting-plane prefilter and with the shape-local feature
-    cells, with the work counters of one force evaluation at the start of
+def table1_workloads(steps=(2000, 1000, 300), warmup=200, sides=(6, 16, 40), modes=(False, True)):
+    """The paper's Table I shapes and sizes on this engine: spheres (r = 0.5,
+    the central WCA baseline), rounded cubes and rounded icosahedra (edge 1,
+    r = 0.15 and 0.1) at N = 6^3, 16^3 and 40^3 (its 256, 4096 and 65536 on
+    cubic lattices), volume fraction 0.4, NVT kT = 1 after `warmup` steps,
+    FP32 pair geometry, tuned pair shape; the polytopes with the
+    supporting-plane prefilter and with the shape-local feature cells
+    (`modes`), with the work counters of one force evaluation at the start of
     the timed window.  The paper gives no densities; these are ours."""
     from paper_1607_02427_amd import inputs as I
     out = []
-    for name, shp, orient in (("cube", I.cube(1.0, 0.15), "small"), ("icosahedron", I.icosahedron(1.0, 0.1), "aligned")):
-        for n_side, k in zip((6, 16, 40), steps):
-            for cells in (False, True):
+    for name, shp, orient in (("sphere", I.sphere(0.5), "uniform"), ("cube", I.cube(1.0, 0.15), "small"),
+                              ("icosahedron", I.icosahedron(1.0, 0.1), "aligned")):
+        for n_side, k in zip(sides, steps):
+            for cells in (modes if name != "sphere" else (False,)):
                 s = I.lattice_system(shp, n_side, 0.4, 31 + n_side, orient=orient, max_deg=10.0,
                                      name=f"{name}_{n_side ** 3}")
                 s.ensemble = "nvt"
@@ -366,6 +368,8 @@ def main():
     ap.add_argument("--no-served", action="store_true")
     ap.add_argument("--no-scale", action="store_true", help="skip the 262,144-octahedra run")
     ap.add_argument("--no-npt", action="store_true", help="skip the isothermal-isobaric cube run")
+    ap.add_argument("--no-table1", action="store_true",
+                    help="skip the Table I shapes at N = 4096 (spheres, cubes, icosahedra) in the default line")
     ap.add_argument("--npt-steps", type=int, default=2000)
     ap.add_argument("--scale-steps", type=int, default=300)
     ap.add_argument("--copy-mb", type=int, default=0,
@@ -521,6 +525,14 @@ def main():
             "sequential_plain_fp64": None if sqs is None else {
                 "p50_latency_s": sqs["p50_latency_s"], "p99_latency_s": sqs["p99_latency_s"], "value": sqs["value"],
                 "makespan_s": sqs["makespan_s"]}}
+    if not args.no_table1:
+        log("[bench] Table I shapes at N = 4096")
+        line["table1_4096"] = {
+            "workload": "spheres (r 0.5, central WCA), rounded cubes (edge 1, r 0.15) and rounded icosahedra (edge 1, "
+                        "r 0.1), 16^3 on a cubic lattice at volume fraction 0.4, NVT kT 1, 1000 steps after 200, FP32 "
+                        "pair geometry, tuned pair shape",
+            "paper_table1_gpu_m6000": {"sphere": 4.6e7, "cube": 3.8e5, "icosahedron": 8.0e4},
+            "runs": table1_workloads(steps=(1000,), sides=(16,), modes=(False,))}
     if args.copy_mb > 0:
         copy_calibration(args.copy_mb)
     if not args.no_cpu:

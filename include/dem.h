@@ -71,7 +71,12 @@ enum { DEM_MAX_VERTS = 16, DEM_MAX_EDGES = 32, DEM_MAX_FACES = 20, DEM_MAX_LOOP 
  * 2D: vertices counter-clockwise with z = 0; edge k = (k, k+1 mod n) (Sec.
  * III: the edge beginning at a vertex, travelling counter-clockwise).
  * 3D: faces are planar vertex loops, counter-clockwise seen from outside,
- * convex or concave (Fig. 1a); every edge must appear in the edge table. */
+ * convex or concave (Fig. 1a); every edge must appear in the edge table.
+ * A single vertex at the origin with no edges and no faces is a sphere (2D:
+ * a disk) of radius rounding_radius (edges and face tables may then be
+ * null): two of them interact by the central WCA potential of Eq. 3/4 at
+ * the distance of their centres, the spheres of Sec. IV.B; against a
+ * polytope the point enters Eq. 1/2 as one vertex. */
 typedef struct {
     int32_t dim;                  /* 2 or 3, equal to the system's */
     int32_t n_vertices;

@@ -44,7 +44,7 @@ class Term(C.Structure):
                 ("r", C.c_double)]
 
 
-TERM_FAMILIES = {0: "EiEj", 1: "ViFj", 2: "VjFi", 3: "ViEj", 4: "VjEi"}
+TERM_FAMILIES = {0: "EiEj", 1: "ViFj", 2: "VjFi", 3: "ViEj", 4: "VjEi", 5: "ViVj"}
 
 
 class Stats(C.Structure):

@@ -289,7 +289,7 @@ static int point_polygon(const double *p, const double *loop, int k, double *q)
 /* One feature pair inside the cutoff, for diagnostics (or_pair_terms):
  * family 0 = E_i-E_j (a, b edges of i and j), 1 = V_i-F_j (a vertex of i, b
  * face of j), 2 = V_j-F_i (a vertex of j, b face of i), 3 = 2D V_i-E_j,
- * 4 = 2D V_j-E_i; inside = 1 when a vertex-face nearest point is the
+ * 4 = 2D V_j-E_i, 5 = point-point (spheres, disks); inside = 1 when a vertex-face nearest point is the
  * projection onto the face, 0 when it lies on the face's edges, -1 for the
  * other families; par = the parallel-edge rule applied; r = |P - Q|. */
 typedef struct {
@@ -347,7 +347,11 @@ static double accumulate(or_pair_out *o, const double *P, const double *Q, const
 /* Full evaluation of U_ij and its derivatives for particles of shapes si, sj
  * at positions xi, xj (xj already the image nearest to xi) and quaternions.
  * 3D: Eq. 1 (every E_i-E_j pair, every V_i-F_j pair, every V_j-F_i pair);
- * 2D: Eq. 2 (every V_i-E_j pair and every V_j-E_i pair). */
+ * 2D: Eq. 2 (every V_i-E_j pair and every V_j-E_i pair).  A shape that is a
+ * single point (no edges, no faces) is a sphere (2D: a disk) of radius r:
+ * against a polytope it enters Eq. 1/2 as one vertex; two of them interact
+ * by the central WCA potential of Eq. 3/4 at the distance of their points,
+ * the spheres of Sec. IV.B (family 5). */
 static void pair_eval(const or_sys *S, int si, int sj, const double *xi, const double *qi, const double *xj,
                       const double *qj, or_pair_out *o, or_terms *tl)
 {
@@ -371,6 +375,14 @@ static void pair_eval(const or_sys *S, int si, int sj, const double *xi, const d
     double eps = S->epsilon;
     const int *Ei = S->edges + 2 * S->e_off[si], *Ej = S->edges + 2 * S->e_off[sj];
     int nei = S->ne[si], nej = S->ne[sj];
+    if (nei == 0 && nej == 0 && S->nf[si] == 0 && S->nf[sj] == 0) {
+        for (int a = 0; a < nvi; ++a)
+            for (int b = 0; b < nvj; ++b) {
+                double r = accumulate(o, Vi[a], Vj[b], xi, xj, sigma, eps, 0, 0);
+                if (r >= 0.0) note(tl, 5, a, b, -1, 0, r);
+            }
+        return;
+    }
     if (S->dim == 2) {
         for (int a = 0; a < nvi; ++a)
             for (int e = 0; e < nej; ++e) {

@@ -1227,6 +1227,39 @@ __global__ void __launch_bounds__(64 * kWaves, OCC) k_pairs(BatchParams b, const
             const double bound = rl.R[si] + rl.R[sj] + kWcaCut * (rl.rad[si] + rl.rad[sj]);
             live = dx * dx + dy * dy + dz * dz < bound * bound;
         }
+        if (live && tab[si].ne == 0 && tab[sj].ne == 0 && tab[si].nf == 0 && tab[sj].nf == 0) {
+            // two points (spheres, disks): the central WCA term of their
+            // centres, in FP64, written here; no separation test, no
+            // feature stage
+            c_pairs.add(sub1 == 0 ? 1 : 0);
+            const double sig = rl.rad[si] + rl.rad[sj], rc = kWcaCut * sig;
+            const double r2 = dx * dx + dy * dy + dz * dz;
+            c_in.add(sub1 == 0 && r2 < rc * rc ? 1 : 0);
+            if (sub1 < 2 && r2 < rc * rc) {  // lane 0 writes i's slot, lane 1 j's
+                const double ir2 = 1.0 / r2, s2 = sig * sig * ir2, s6 = s2 * s2 * s2, h = 2.0 * s6 - 1.0;
+                const double fr = 24.0 * rl.eps * s6 * h * ir2;  // force on i along x_i - x_j
+                const bool js = sub1 == 1;
+                const double sg = js ? 1.0 : -1.0;
+                SlotRec<T> w;
+                w.F[0] = (T)(sg * fr * dx);
+                w.F[1] = (T)(sg * fr * dy);
+                w.F[2] = (T)(sg * fr * dz);
+                w.U = (T)(rl.eps * h * h);
+                w.tq[0] = w.tq[1] = w.tq[2] = T(0);
+                w.d[0] = (T)(-sg * dx);
+                w.d[1] = (T)(-sg * dy);
+                w.d[2] = (T)(-sg * dz);
+                w.pad1 = T(0);
+                set_stamp(w, stamp);
+                const int slot = js ? ent.w : ent.z;
+                const int pi = js ? ent.y : ent.x;
+                if (slot >= 0) {
+                    rec[(size_t)slot * N + pi] = w;
+                    atomicOr(&l.smask[(size_t)(slot >> 5) * N + pi], 1u << (slot & 31));
+                }
+            }
+            live = false;
+        }
         bool need = false;
         if (__ballot(live) != 0) {
             const ShapeTab<T> &Si = tab[si];

@@ -293,13 +293,17 @@ dem_status build_table(dem_system *h, int idx, const dem_shape_desc &d, int dim,
 {
     std::memset(&T, 0, sizeof T);
     if (d.dim != dim) return fail(h, DEM_E_SHAPE, "shape %d: dim %d differs from system dim %d", idx, d.dim, dim);
-    if (d.n_vertices < (dim == 3 ? 4 : 3) || d.n_vertices > DEM_MAX_VERTS)
-        return fail(h, DEM_E_SHAPE, "shape %d: %d vertices (limit %d)", idx, d.n_vertices, DEM_MAX_VERTS);
-    if (d.n_edges < 3 || d.n_edges > DEM_MAX_EDGES)
-        return fail(h, DEM_E_SHAPE, "shape %d: %d edges (limit %d)", idx, d.n_edges, DEM_MAX_EDGES);
-    if (dim == 3 && (d.n_faces < 4 || d.n_faces > DEM_MAX_FACES))
-        return fail(h, DEM_E_SHAPE, "shape %d: %d faces (limit %d)", idx, d.n_faces, DEM_MAX_FACES);
-    if (!d.vertices || !d.edges || (dim == 3 && (!d.face_offsets || !d.face_vertices)))
+    // a single point (no edges, no faces) is a sphere or disk of the rounding radius
+    const bool point = d.n_vertices == 1 && d.n_edges == 0 && (dim == 2 || d.n_faces == 0);
+    if (!point) {
+        if (d.n_vertices < (dim == 3 ? 4 : 3) || d.n_vertices > DEM_MAX_VERTS)
+            return fail(h, DEM_E_SHAPE, "shape %d: %d vertices (limit %d)", idx, d.n_vertices, DEM_MAX_VERTS);
+        if (d.n_edges < 3 || d.n_edges > DEM_MAX_EDGES)
+            return fail(h, DEM_E_SHAPE, "shape %d: %d edges (limit %d)", idx, d.n_edges, DEM_MAX_EDGES);
+        if (dim == 3 && (d.n_faces < 4 || d.n_faces > DEM_MAX_FACES))
+            return fail(h, DEM_E_SHAPE, "shape %d: %d faces (limit %d)", idx, d.n_faces, DEM_MAX_FACES);
+    }
+    if (!d.vertices || (!point && (!d.edges || (dim == 3 && (!d.face_offsets || !d.face_vertices)))))
         return fail(h, DEM_E_SHAPE, "shape %d: null table", idx);
     if (!(d.rounding_radius > 0.0) || !(d.mass > 0.0))
         return fail(h, DEM_E_SHAPE, "shape %d: rounding radius and mass must be positive", idx);
@@ -318,6 +322,7 @@ dem_status build_table(dem_system *h, int idx, const dem_shape_desc &d, int dim,
         if (rr > R) R = rr;
     }
     T.R = R;
+    if (point && R != 0.0) return fail(h, DEM_E_SHAPE, "shape %d: a point shape's vertex must be its centre", idx);
     for (int k = 0; k < T.ne; ++k) {
         int a = d.edges[2 * k], b = d.edges[2 * k + 1];
         if (a < 0 || b < 0 || a >= T.nv || b >= T.nv || a == b)
@@ -335,7 +340,7 @@ dem_status build_table(dem_system *h, int idx, const dem_shape_desc &d, int dim,
         T.eh[k] = 0.5 * std::sqrt(l2);
         for (int c = 0; c < 3; ++c) T.em[k][c] = 0.5 * (T.v[a][c] + T.v[b][c]);
     }
-    if (dim == 3) {
+    if (dim == 3 && !point) {
         if (d.face_offsets[0] != 0) return fail(h, DEM_E_SHAPE, "shape %d: face_offsets[0] != 0", idx);
         if (d.face_offsets[T.nf] > DEM_MAX_LOOP)
             return fail(h, DEM_E_SHAPE, "shape %d: %d face-loop entries (limit %d)", idx, d.face_offsets[T.nf], DEM_MAX_LOOP);

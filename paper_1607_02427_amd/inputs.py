@@ -362,6 +362,24 @@ def polygon(verts2: np.ndarray, r: float, name: str = "polygon", mass: float = 1
                  inertia=np.array([0.0, 0.0, Iz]), name=name, volume=float(A))
 
 
+def sphere(r: float = 0.5, mass: float = 1.0) -> Shape:
+    """A sphere of radius r: a single point rounded by r, no edges or faces.
+    Two spheres interact by the central WCA potential at the distance of
+    their centres (sigma = r_i + r_j), the baseline of Table I; a sphere and
+    a polytope through the sphere's point as a vertex of Eq. 1."""
+    I = 0.4 * mass * r * r
+    return Shape(dim=3, vertices=np.zeros((1, 3)), edges=np.zeros((0, 2), dtype=np.int32), faces=[], r=float(r),
+                 mass=float(mass), inertia=np.array([I, I, I]), name="sphere",
+                 volume=4.0 / 3.0 * math.pi * r ** 3)
+
+
+def disk(r: float = 0.5, mass: float = 1.0) -> Shape:
+    """A disk of radius r: the 2D counterpart of sphere()."""
+    return Shape(dim=2, vertices=np.zeros((1, 3)), edges=np.zeros((0, 2), dtype=np.int32), faces=[], r=float(r),
+                 mass=float(mass), inertia=np.array([0.0, 0.0, 0.5 * mass * r * r]), name="disk",
+                 volume=math.pi * r * r)
+
+
 def regular_polygon(n: int, edge: float = 1.0, r: float = 0.25, name: Optional[str] = None) -> Shape:
     R = edge / (2.0 * math.sin(math.pi / n))
     ang = -math.pi / 2 - math.pi / n + TWO_PI * np.arange(n) / n  # flat bottom edge
@@ -860,7 +878,7 @@ def _supporting_features(shp: Shape):
         loops = [list(f) for f in shp.faces]
         normals = [_newell(V, f) for f in loops]
     else:
-        loops = [[k, (k + 1) % shp.nv] for k in range(shp.nv)]
+        loops = [[k, (k + 1) % shp.nv] for k in range(shp.nv)] if shp.nv > 1 else []  # (a disk has no edges)
         normals = [_unit(np.array([V[b, 1] - V[a, 1], V[a, 0] - V[b, 0], 0.0])) for a, b in loops]
 
     def strict(idx, u):
