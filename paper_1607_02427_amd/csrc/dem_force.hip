@@ -1230,7 +1230,9 @@ __global__ void __launch_bounds__(64 * kWaves, OCC) k_pairs(BatchParams b, const
         if (live && tab[si].ne == 0 && tab[sj].ne == 0 && tab[si].nf == 0 && tab[sj].nf == 0) {
             // two points (spheres, disks): the central WCA term of their
             // centres, in FP64, written here; no separation test, no
-            // feature stage
+            // feature stage (no contraction: every kernel variant rounds the
+            // term alike)
+#pragma clang fp contract(off)
             c_pairs.add(sub1 == 0 ? 1 : 0);
             const double sig = rl.rad[si] + rl.rad[sj], rc = kWcaCut * sig;
             const double r2 = dx * dx + dy * dy + dz * dz;

@@ -247,3 +247,31 @@ def test_served_requests_wait_on_memory():
     for r, s in zip(recs, reqs):
         st, out = r.result
         _same((st, out), _solo(dem, s, "fp32", s.steps)[:2])
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_batch_with_spheres_and_cells_matches_oracle(prec):
+    """A batch holding sphere replicas (central WCA) beside polytope ones,
+    evaluated once with the supporting-plane prefilter and once with the
+    shape-local feature cells: every replica against the oracle, and in
+    FP64 the cells change no bit of the sphere replicas (their pairs never
+    reach the feature stage)."""
+    dem = _dem()
+    systems = [I.lattice_system(I.sphere(0.5), 8, 0.4, 7, orient="uniform", jitter=0.05),
+               I.contact_dimers(I.cube(1.0, 0.15), I.sphere(0.2), n_pairs=40),
+               I.contact_dimers(I.icosahedron(), n_pairs=32),
+               I.cubes_3d_contact(n_side=6)]
+    outs = {}
+    for cells in (False, True):
+        print(f"[batch-spheres] {prec} cells={cells} sizes={[s.n for s in systems]}", flush=True)
+        with dem.DemBatch(3, prec, max_replicas=8, max_particles=4096, max_cells=16384) as B:
+            B.set_feature_cells(cells)
+            rids = [B.add(s) for s in systems]
+            B.compute_forces()
+            for s, r in zip(systems, rids):
+                _, out = B.read(r)
+                check(f"batch_spheres_cells{int(cells)}_replica{r}_{s.name}", prec, out, O.forces(s))
+                outs[(cells, r)] = out
+    if prec == "fp64":
+        for k in ("F", "T", "U", "W"):
+            assert np.array_equal(outs[(False, rids[0])][k], outs[(True, rids[0])][k]), k
