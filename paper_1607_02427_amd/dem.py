@@ -92,6 +92,10 @@ def lib():
         if not os.path.exists(LIB_PATH):
             raise RuntimeError(f"libdem.so is not built at {LIB_PATH}; run __graft_entry__.build() "
                                f"or python -m paper_1607_02427_amd.build")
+        # torch first: the library then binds to the HIP runtime torch loads
+        # (the same soname); loaded first, it would pull in the system's copy
+        # and leave the process with a runtime torch cannot initialise on
+        import torch  # noqa: F401
         L = C.CDLL(LIB_PATH)
         st = C.c_int
         L.dem_create_system.argtypes = [C.POINTER(Params), C.POINTER(StatePtrs), C.POINTER(OutPtrs), C.c_void_p,

@@ -21,7 +21,7 @@ def test_header_declares_the_documented_entry_points():
 
 
 def test_library_exports_every_declared_function():
-    L = C.CDLL(dem.LIB_PATH)
+    L = dem.lib()
     missing = [n for n in dem.declared_functions() if not hasattr(L, n)]
     assert not missing, missing
 
