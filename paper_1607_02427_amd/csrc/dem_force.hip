@@ -735,12 +735,27 @@ __global__ void __launch_bounds__(64 * kWaves, OCC) k_pairs(BatchParams b, const
     const int ntiles = l.tile_start[b.nrep];
     const unsigned stamp = (unsigned)l.gflags[G_STAMP];
     const int G = gridDim.x, per = G >> 3;
-    const int lb = (blockIdx.x & 7) * per + (blockIdx.x >> 3);
     // the force kernel's units: kWaves * kGroups compacted pairs of one
     // replica, so each wavefront takes one feature round
     const int *first = kForce ? l.cunit : l.tile_start;
     const int nunits = kForce ? l.cunit[b.nrep] : ntiles;
-    const int t0 = (int)((long long)nunits * lb / G), t1 = (int)((long long)nunits * (lb + 1) / G);
+    // XCD x (block b runs on XCD b % 8) takes the x-th eighth of the units;
+    // its q-th block (q = b / 8) a contiguous share of them, or, when the
+    // eighth holds fewer units than the XCD has blocks, unit q: the blocks
+    // launched first take the work, and no unit waits for the grid's last
+    // blocks to be dispatched
+    const int xcd = blockIdx.x & 7, q = blockIdx.x >> 3;
+    const int us = (int)((long long)nunits * xcd / 8), un = (int)((long long)nunits * (xcd + 1) / 8) - us;
+    int t0, t1;
+    if (q >= per) {  // (grids are multiples of 8; none is left over)
+        t0 = t1 = 0;
+    } else if (un >= per) {
+        t0 = us + (int)((long long)un * q / per);
+        t1 = us + (int)((long long)un * (q + 1) / per);
+    } else {
+        t0 = us + (q < un ? q : un);
+        t1 = us + (q < un ? q + 1 : un);
+    }
     const T grow = T(1.00001);
     Tally<COUNT> c_pairs, c_feat, c_in, c_near, c_ee, c_ref, c_sep, c_pv;
 
