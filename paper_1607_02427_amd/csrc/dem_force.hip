@@ -303,7 +303,8 @@ struct Problem {
     // feature cells: nA, nB the near vertices of i and of j, nfj all near
     // entries (with i's near edges); problem q belongs to the entry e with
     // pf[e] <= q < pf[e + 1] and is the (q - pf[e])-th feature of its mask.
-    // The cull and the solves take its code fam << 10 | x << 5 | y instead.
+    // In both numberings the cull and the solves take the problem's code
+    // fam << 10 | x << 5 | y (fc_code, pack).
     const PairFc *F = nullptr;
 
     __device__ int fc_code(int q) const
@@ -335,14 +336,21 @@ struct Problem {
         }
     }
 
-    __device__ void decode(int q, int &fam, int &x, int &y) const
+    // the queue holds codes fam << 10 | x << 5 | y (the cull forms them: a
+    // solve step then decodes its problem without LDS loads)
+    __device__ static void decode(int code, int &fam, int &x, int &y)
     {
-        if constexpr (FC) {
-            fam = q >> 10;
-            x = (q >> 5) & 31;
-            y = q & 31;
-            return;
-        }
+        fam = code >> 10;
+        x = (code >> 5) & 31;
+        y = code & 31;
+    }
+
+    // code of problem q of the plane-prefilter numbering: vertex x of i
+    // against face (2D: edge) y of j for q < nA, vertex x of j against face
+    // y of i for q < nA + nB, edge x of i against edge y of j after that
+    __device__ int pack(int q) const
+    {
+        int fam, x, y;
         if (q < nA) {
             const int ax = qdiv(q, inv_fj);
             fam = 0;
@@ -359,6 +367,7 @@ struct Problem {
             x = W.ei_near[ex];
             y = W.ej_near[qq - ex * nej];
         }
+        return fam << 10 | x << 5 | y;
     }
 
     // conservative cull: false if no point of the two features can be within rc
@@ -987,7 +996,7 @@ __global__ void __launch_bounds__(64 * kWaves, OCC) k_pairs(BatchParams b, const
                 const bool has = q < total;
                 const bool last = __ballot(has) == 0;
                 if (!last) {
-                    const int qc = (FC && has) ? P.fc_code(q) : q;
+                    const int qc = has ? (FC ? P.fc_code(q) : P.pack(q)) : 0;
                     const bool keep = has && P.candidate(qc, rcm);
                     const unsigned long long m = __ballot(keep);
                     if (keep) W.queue[count + popc_below(m & gmask)] = (unsigned short)qc;
